@@ -1,0 +1,1398 @@
+/*
+ * hcao_oracle.c -- fp64 CPU oracle of the HCAO DSMC collision step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see hcao_oracle.h). Written for clarity, not
+ * speed: one cell at a time, one pair at a time, in the order the method
+ * states. Compile with -O2 -ffp-contract=off and without fast-math so that
+ * every floating-point operation is the IEEE operation written here.
+ *
+ * Paper sections followed (Lauterbach, Tuttas, Pfeiffer):
+ *   harmonic and Morse levels ....... Introduction, Eqs. energy-SHO, energy-AHO,
+ *                                     chi_e = hc w_e / (4 D_e); Sec. "The polyatomic
+ *                                     HCAO model" (theta form of the harmonic levels)
+ *   vibrational temperature ......... Sec. "Implementation ...", mean-energy equation
+ *   initial quantum numbers ......... same section, bend floor form and the stretch
+ *                                     acceptance Eq. accept-quant
+ *   relaxation ...................... same section: E_coll, bend/stretch i_max,
+ *                                     joint Larsen-Borgnakke acceptance, xi_rel = 5 - 2w
+ *   dissociation .................... Sec. "Dissociation reactions", Eq. Ecoll-diss
+ *   exchange ........................ Sec. "Exchange reactions", Eq. Ecoll-exch
+ *   competing reactions ............. Sec. "Competing reactions"
+ *   product redistribution .......... Sec. "Polyatomic QK reaction modeling" (LB)
+ * Pieces the paper takes from elsewhere are written from their textbook
+ * definitions: NTC candidate count and VHS cross-section (Bird), Marsaglia's
+ * (1972) unit vector and polar normal method, Philox4x32-10 (Salmon et al.,
+ * SC'11), Cody-Waite argument reduction (Cody & Waite 1980), a Feistel
+ * network permutation (Luby & Rackoff 1988) with cycle walking (Black &
+ * Rogaway 2002).
+ */
+#include "hcao_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* exact SI constants */
+#define H_PLANCK 6.62607015e-34
+#define C_LIGHT 299792458.0
+#define K_BOLTZ 1.380649e-23
+#define PI_D 3.141592653589793
+
+enum { E_OK = 0, E_INVAL = -1, E_STATE = -2, E_NOMEM = -3, E_CAPACITY = -5, E_LEVEL = -6, E_NONFINITE = -7 };
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)                   */
+/* ------------------------------------------------------------------ */
+void orc_philox4x32_10(uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+    uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+/* One random stream: key = seed, counter = (block, pair, cell, step).
+ * A double takes two consecutive 32-bit words (low word first) of the
+ * current block; a block holds two doubles. */
+typedef struct {
+  uint32_t k0, k1;
+  uint32_t pair, cell, step;
+  uint32_t block;
+  uint32_t buf[4];
+  int used;
+} stream;
+
+static void stream_open(stream *s, uint64_t seed, uint32_t pair, uint32_t cell, uint32_t step) {
+  s->k0 = (uint32_t)seed;
+  s->k1 = (uint32_t)(seed >> 32);
+  s->pair = pair;
+  s->cell = cell;
+  s->step = step;
+  s->block = 0;
+  s->used = 4;
+}
+
+static uint64_t next_u64(stream *s) {
+  if (s->used >= 4) {
+    uint32_t ctr[4] = {s->block, s->pair, s->cell, s->step};
+    orc_philox4x32_10(s->k0, s->k1, ctr, s->buf);
+    s->block += 1;
+    s->used = 0;
+  }
+  uint64_t lo = s->buf[s->used];
+  uint64_t hi = s->buf[s->used + 1];
+  s->used += 2;
+  return (hi << 32) | lo;
+}
+
+/* uniform double on [0, 1) with 53 random bits */
+static double uniform(stream *s) { return (double)(next_u64(s) >> 11) * 0x1p-53; }
+
+/* ------------------------------------------------------------------ */
+/* Deterministic exp / log / pow                                        */
+/* ------------------------------------------------------------------ */
+static double from_bits(uint64_t b) {
+  double d;
+  memcpy(&d, &b, 8);
+  return d;
+}
+static uint64_t to_bits(double d) {
+  uint64_t b;
+  memcpy(&b, &d, 8);
+  return b;
+}
+
+static const double LN2_HI = 0x1.62e42feep-1;       /* ln 2 with 21 trailing zero bits */
+static const double LN2_LO = 0x1.a39ef35793c76p-33; /* ln 2 - LN2_HI */
+static const double INV_LN2 = 0x1.71547652b82fep+0;
+static const double SQRT2 = 0x1.6a09e667f3bcdp+0;
+
+/* exp(x) = 2^k e^r with k = nearest integer to x/ln2, r = x - k ln2 by a
+ * two-part ln2 (Cody-Waite), e^r by its Taylor series to degree 17 in
+ * Horner form (|r| <= ln2/2, truncation below 1e-24). */
+double orc_detexp(double x) {
+  if (x != x) return x;
+  if (x > 708.0) return INFINITY;
+  if (x < -707.0) return 0.0;
+  double kd = floor(x * INV_LN2 + 0.5);
+  double r = (x - kd * LN2_HI) - kd * LN2_LO;
+  /* coefficients 1/n! for n = 17 .. 0 */
+  double p = 1.0 / 355687428096000.0;
+  p = p * r + 1.0 / 20922789888000.0;
+  p = p * r + 1.0 / 1307674368000.0;
+  p = p * r + 1.0 / 87178291200.0;
+  p = p * r + 1.0 / 6227020800.0;
+  p = p * r + 1.0 / 479001600.0;
+  p = p * r + 1.0 / 39916800.0;
+  p = p * r + 1.0 / 3628800.0;
+  p = p * r + 1.0 / 362880.0;
+  p = p * r + 1.0 / 40320.0;
+  p = p * r + 1.0 / 5040.0;
+  p = p * r + 1.0 / 720.0;
+  p = p * r + 1.0 / 120.0;
+  p = p * r + 1.0 / 24.0;
+  p = p * r + 1.0 / 6.0;
+  p = p * r + 0.5;
+  p = p * r + 1.0;
+  p = p * r + 1.0;
+  int k = (int)kd;
+  double scale = from_bits((uint64_t)(k + 1023) << 52);
+  return p * scale;
+}
+
+/* log(x) = e ln2 + log(m), m in (sqrt(1/2), sqrt(2)], with
+ * log(m) = 2 atanh(s), s = (m-1)/(m+1), as the odd series
+ * 2 s (1 + s^2/3 + s^4/5 + ... + s^22/23). */
+double orc_detlog(double x) {
+  if (x != x) return x;
+  if (x < 0.0) return NAN;
+  if (x == 0.0) return -INFINITY;
+  if (x == INFINITY) return INFINITY;
+  int e = 0;
+  uint64_t b = to_bits(x);
+  if ((b >> 52) == 0) { /* subnormal */
+    x = x * 0x1p54;
+    b = to_bits(x);
+    e = -54;
+  }
+  e += (int)((b >> 52) & 0x7ff) - 1023;
+  double m = from_bits((b & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL);
+  if (m > SQRT2) {
+    m = m * 0.5;
+    e += 1;
+  }
+  double s = (m - 1.0) / (m + 1.0);
+  double z = s * s;
+  double q = 1.0 / 23.0;
+  q = q * z + 1.0 / 21.0;
+  q = q * z + 1.0 / 19.0;
+  q = q * z + 1.0 / 17.0;
+  q = q * z + 1.0 / 15.0;
+  q = q * z + 1.0 / 13.0;
+  q = q * z + 1.0 / 11.0;
+  q = q * z + 1.0 / 9.0;
+  q = q * z + 1.0 / 7.0;
+  q = q * z + 1.0 / 5.0;
+  q = q * z + 1.0 / 3.0;
+  q = q * z + 1.0;
+  double t = s * q;
+  double lm = t + t;
+  double ed = (double)e;
+  return (ed * LN2_LO + lm) + ed * LN2_HI;
+}
+
+double orc_detpow(double x, double y) {
+  if (x == 0.0) return (y > 0.0) ? 0.0 : ((y == 0.0) ? 1.0 : INFINITY);
+  if (x < 0.0) return NAN;
+  return orc_detexp(y * orc_detlog(x));
+}
+
+/* ------------------------------------------------------------------ */
+/* Keyed permutation of [0, n): 10-round Feistel on 2b bits, cycle walk */
+/* ------------------------------------------------------------------ */
+static uint32_t feistel_round(uint32_t r, uint32_t key, uint32_t mask) {
+  uint32_t h = (r ^ key) * 0x9E3779B1u;
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  return h & mask;
+}
+
+static uint32_t feistel_half_bits(uint32_t n) {
+  uint32_t b = 1;
+  while (((uint64_t)1 << (2 * b)) < (uint64_t)n) b += 1;
+  return b;
+}
+
+static uint32_t feistel_once(uint32_t x, uint32_t b, const uint32_t keys[10]) {
+  uint32_t mask = ((uint32_t)1 << b) - 1u;
+  uint32_t left = x >> b, right = x & mask;
+  for (int r = 0; r < 10; ++r) {
+    uint32_t nl = right;
+    uint32_t nr = left ^ feistel_round(right, keys[r], mask);
+    left = nl;
+    right = nr;
+  }
+  return (left << b) | right;
+}
+
+uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[10], uint32_t i) {
+  uint32_t b = feistel_half_bits(n);
+  uint32_t y = feistel_once(i, b, keys);
+  while (y >= n) y = feistel_once(y, b, keys);
+  return y;
+}
+
+/* ------------------------------------------------------------------ */
+/* Data model                                                            */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double mass, dref, omega, tref;
+  uint32_t n_bend, n_stretch, n_modes;
+  double kt[ORC_MAX_MODES];     /* bends: k_B Theta */
+  double theta[ORC_MAX_MODES];  /* bends: Theta */
+  double *lev[ORC_MAX_MODES];   /* stretches: level energies, index 0..idiss */
+  uint32_t idiss[ORC_MAX_MODES];
+  double de[ORC_MAX_MODES];     /* stretches: dissociation energy D_e */
+  double zpe;
+  double formation;
+  double p_vib;
+  int sampler; /* resolved: JOINT or GIBBS */
+} species_t;
+
+typedef struct {
+  double mr, hm, m_a, m_b, msum, wa, wb, csg, esg, q;
+} pair_t;
+
+typedef struct {
+  int kind;
+  int a, b, c, d; /* diss: a -> c + d (b = -1); exch: a + b -> c + d */
+  uint64_t mask;
+  double alpha[ORC_MAX_MODES];
+  double steric, ea;
+  double dh;   /* sum of formation energies of products minus reactants */
+  double zsum; /* dissociation: ZPE_A + ZPE_B + ZPE_C */
+} reaction_t;
+
+typedef struct {
+  uint32_t n, cap;
+  double *vx, *vy, *vz;
+  uint8_t *sp;
+  uint16_t *lvl; /* n x max_modes, row major */
+  double volume, weight, sgmax, rem;
+  uint64_t ctr[ORC_N_CTR];
+} cell_t;
+
+struct orc_ctx {
+  uint64_t seed;
+  uint32_t n_cells, cap_default, step, finalized, loaded;
+  uint32_t n_species, n_reactions, max_modes;
+  species_t sp[ORC_MAX_SPECIES];
+  reaction_t rx[ORC_MAX_REACTIONS];
+  pair_t pr[ORC_MAX_SPECIES][ORC_MAX_SPECIES];
+  cell_t *cells;
+};
+
+static double mode_energy(const species_t *s, uint32_t m, uint32_t i) {
+  if (m < s->n_bend) return ((double)i + 0.5) * s->kt[m];
+  return s->lev[m][i];
+}
+
+static double vib_energy(const species_t *s, const uint16_t *lvl) {
+  double e = 0.0;
+  for (uint32_t m = 0; m < s->n_modes; ++m) e = e + mode_energy(s, m, lvl[m]);
+  return e;
+}
+
+/* ------------------------------------------------------------------ */
+/* Context set-up                                                        */
+/* ------------------------------------------------------------------ */
+int orc_create(uint64_t seed, uint32_t n_cells, const double *cell_volume, const double *cell_weight,
+               uint32_t capacity_per_cell, orc_ctx **out) {
+  if (!out || n_cells == 0 || !cell_volume || !cell_weight) return E_INVAL;
+  orc_ctx *o = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+  if (!o) return E_NOMEM;
+  o->seed = seed;
+  o->n_cells = n_cells;
+  o->cap_default = capacity_per_cell;
+  o->cells = (cell_t *)calloc(n_cells, sizeof(cell_t));
+  if (!o->cells) {
+    free(o);
+    return E_NOMEM;
+  }
+  for (uint32_t c = 0; c < n_cells; ++c) {
+    if (!(cell_volume[c] > 0.0) || !(cell_weight[c] > 0.0)) {
+      free(o->cells);
+      free(o);
+      return E_INVAL;
+    }
+    o->cells[c].volume = cell_volume[c];
+    o->cells[c].weight = cell_weight[c];
+  }
+  *out = o;
+  return E_OK;
+}
+
+static void free_cell(cell_t *c) {
+  free(c->vx);
+  free(c->vy);
+  free(c->vz);
+  free(c->sp);
+  free(c->lvl);
+  c->vx = c->vy = c->vz = NULL;
+  c->sp = NULL;
+  c->lvl = NULL;
+}
+
+void orc_destroy(orc_ctx *o) {
+  if (!o) return;
+  for (uint32_t s = 0; s < o->n_species; ++s)
+    for (uint32_t m = 0; m < ORC_MAX_MODES; ++m) free(o->sp[s].lev[m]);
+  if (o->cells)
+    for (uint32_t c = 0; c < o->n_cells; ++c) free_cell(&o->cells[c]);
+  free(o->cells);
+  free(o);
+}
+
+/* Morse (anharmonic) levels, Eq. energy-AHO: E(i) = a (i+1/2) - a x_e (i+1/2)^2
+ * with a = h c w_e. Levels are kept while they stay below D_e and still
+ * increase; D_e defaults to a / (4 x_e) (chi_e = hc w_e / (4 D_e)). */
+static int build_stretch(species_t *s, uint32_t m, double we, double xe, double de,
+                         uint32_t n_explicit, const double *explicit_levels) {
+  double *lev = (double *)malloc(ORC_MAX_LEVELS * sizeof(double));
+  if (!lev) return E_NOMEM;
+  uint32_t n = 0;
+  if (n_explicit > 0) {
+    if (!(de > 0.0)) {
+      free(lev);
+      return E_INVAL;
+    }
+    for (uint32_t i = 0; i < n_explicit && i < ORC_MAX_LEVELS; ++i) {
+      double e = explicit_levels[i];
+      if (!(e < de)) break;
+      if (i > 0 && !(e > lev[i - 1])) {
+        free(lev);
+        return E_INVAL;
+      }
+      lev[n++] = e;
+    }
+  } else {
+    if (!(we > 0.0) || !(xe >= 0.0)) {
+      free(lev);
+      return E_INVAL;
+    }
+    double a = (H_PLANCK * C_LIGHT) * we;
+    double ax = a * xe;
+    if (!(de > 0.0)) {
+      if (!(xe > 0.0)) {
+        free(lev);
+        return E_INVAL;
+      }
+      de = a / (4.0 * xe);
+    }
+    for (uint32_t i = 0; i < ORC_MAX_LEVELS; ++i) {
+      double v = (double)i + 0.5;
+      double e = (a * v) - ((ax * v) * v);
+      if (!(e < de)) break;
+      if (i > 0 && !(e > lev[i - 1])) break;
+      lev[n++] = e;
+    }
+  }
+  if (n == 0) {
+    free(lev);
+    return E_INVAL;
+  }
+  s->lev[m] = lev;
+  s->idiss[m] = n - 1;
+  s->de[m] = de;
+  return E_OK;
+}
+
+int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double tref,
+                    uint32_t n_bend, const double *theta, uint32_t n_stretch, const double *omega_e,
+                    const double *chi_e, const double *de, const uint32_t *n_levels,
+                    const double *levels, double formation, double p_vib, int sampler) {
+  if (!o || o->finalized) return E_STATE;
+  if (o->n_species >= ORC_MAX_SPECIES) return E_INVAL;
+  if (!(mass > 0.0) || !(dref > 0.0) || !(tref > 0.0) || !(omega >= 0.5) || !(omega < 1.5)) return E_INVAL;
+  if (n_bend + n_stretch > ORC_MAX_MODES) return E_INVAL;
+  if (!(p_vib >= 0.0) || !(p_vib <= 1.0)) return E_INVAL;
+  species_t *s = &o->sp[o->n_species];
+  memset(s, 0, sizeof(*s));
+  s->mass = mass;
+  s->dref = dref;
+  s->omega = omega;
+  s->tref = tref;
+  s->n_bend = n_bend;
+  s->n_stretch = n_stretch;
+  s->n_modes = n_bend + n_stretch;
+  s->formation = formation;
+  s->p_vib = p_vib;
+  for (uint32_t j = 0; j < n_bend; ++j) {
+    if (!(theta[j] > 0.0)) return E_INVAL;
+    s->theta[j] = theta[j];
+    s->kt[j] = K_BOLTZ * theta[j];
+  }
+  const double *lv = levels;
+  for (uint32_t j = 0; j < n_stretch; ++j) {
+    uint32_t ne = n_levels ? n_levels[j] : 0;
+    double dej = de ? de[j] : 0.0;
+    int rc = build_stretch(s, n_bend + j, omega_e ? omega_e[j] : 0.0, chi_e ? chi_e[j] : 0.0, dej, ne, lv);
+    if (rc) {
+      for (uint32_t m = 0; m < ORC_MAX_MODES; ++m) {
+        free(s->lev[m]);
+        s->lev[m] = NULL;
+      }
+      return rc;
+    }
+    if (lv) lv += ne;
+  }
+  double z = 0.0;
+  for (uint32_t m = 0; m < s->n_modes; ++m) z = z + mode_energy(s, m, 0);
+  s->zpe = z;
+  if (sampler == ORC_SAMPLER_AUTO)
+    s->sampler = (s->n_modes <= 4) ? ORC_SAMPLER_JOINT : ORC_SAMPLER_GIBBS;
+  else if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS)
+    s->sampler = sampler;
+  else
+    return E_INVAL;
+  if (s->n_modes > o->max_modes) o->max_modes = s->n_modes;
+  o->n_species += 1;
+  return E_OK;
+}
+
+int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int32_t product[2],
+                     uint64_t stretch_mask, const double *alpha, double steric, double ea) {
+  if (!o || o->finalized) return E_STATE;
+  if (o->n_reactions >= ORC_MAX_REACTIONS) return E_INVAL;
+  int ns = (int)o->n_species;
+  reaction_t *r = &o->rx[o->n_reactions];
+  memset(r, 0, sizeof(*r));
+  r->kind = kind;
+  if (kind == ORC_RX_DISSOCIATION) {
+    int a = reactant[0], c = product[0], d = product[1];
+    if (a < 0 || a >= ns || c < 0 || c >= ns || d < 0 || d >= ns) return E_INVAL;
+    const species_t *A = &o->sp[a];
+    if (A->n_stretch == 0) return E_INVAL;
+    if (stretch_mask == 0 || (A->n_stretch < 64 && (stretch_mask >> A->n_stretch) != 0)) return E_INVAL;
+    double msum = o->sp[c].mass + o->sp[d].mass;
+    if (fabs(msum - A->mass) > 1e-9 * A->mass) return E_INVAL;
+    r->a = a;
+    r->b = -1;
+    r->c = c;
+    r->d = d;
+    r->mask = stretch_mask;
+    r->dh = (o->sp[c].formation + o->sp[d].formation) - A->formation;
+    r->zsum = (A->zpe + o->sp[c].zpe) + o->sp[d].zpe;
+  } else if (kind == ORC_RX_EXCHANGE) {
+    int a = reactant[0], b = reactant[1], c = product[0], d = product[1];
+    if (a < 0 || a >= ns || b < 0 || b >= ns || c < 0 || c >= ns || d < 0 || d >= ns) return E_INVAL;
+    if (!(steric >= 0.0) || !(steric <= 1.0) || !(ea >= 0.0)) return E_INVAL;
+    double m_in = o->sp[a].mass + o->sp[b].mass, m_out = o->sp[c].mass + o->sp[d].mass;
+    if (fabs(m_in - m_out) > 1e-9 * m_in) return E_INVAL;
+    r->a = a;
+    r->b = b;
+    r->c = c;
+    r->d = d;
+    for (uint32_t m = 0; m < o->sp[a].n_modes; ++m) {
+      double al = alpha ? alpha[m] : 0.0;
+      if (!(al >= 0.0) || !(al <= 1.0)) return E_INVAL;
+      r->alpha[m] = al;
+    }
+    r->steric = steric;
+    r->ea = ea;
+    r->dh = (o->sp[c].formation + o->sp[d].formation) - (o->sp[a].formation + o->sp[b].formation);
+  } else {
+    return E_INVAL; /* recombination: see the recombination tables (not in this build of the oracle) */
+  }
+  o->n_reactions += 1;
+  return E_OK;
+}
+
+/* VHS pair constants (Bird): sigma g = C (g^2)^(1-w), with
+ * C = pi d^2 (2 k T_ref / m_r)^(w - 1/2) / Gamma(5/2 - w); mixed-pair d, w and
+ * T_ref are the means of both species. LB exponent xi_rel/2 - 1 = 3/2 - w. */
+static void build_pair(orc_ctx *o, uint32_t a, uint32_t b) {
+  const species_t *A = &o->sp[a], *B = &o->sp[b];
+  pair_t *p = &o->pr[a][b];
+  double msum = A->mass + B->mass;
+  double mr = (A->mass * B->mass) / msum;
+  double w = (A->omega + B->omega) * 0.5;
+  double d = (A->dref + B->dref) * 0.5;
+  double tr = (A->tref + B->tref) * 0.5;
+  double base = ((2.0 * K_BOLTZ) * tr) / mr;
+  p->mr = mr;
+  p->hm = 0.5 * mr;
+  p->m_a = A->mass;
+  p->m_b = B->mass;
+  p->msum = msum;
+  p->wa = B->mass / msum;
+  p->wb = A->mass / msum;
+  p->csg = ((PI_D * (d * d)) * pow(base, w - 0.5)) / tgamma(2.5 - w);
+  p->esg = 1.0 - w;
+  p->q = 1.5 - w;
+}
+
+int orc_finalize(orc_ctx *o) {
+  if (!o || o->finalized) return E_STATE;
+  if (o->n_species == 0) return E_INVAL;
+  for (uint32_t a = 0; a < o->n_species; ++a)
+    for (uint32_t b = 0; b < o->n_species; ++b) build_pair(o, a, b);
+  o->finalized = 1;
+  return E_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Particle storage                                                      */
+/* ------------------------------------------------------------------ */
+static int alloc_cell(orc_ctx *o, cell_t *c, uint32_t cap) {
+  free_cell(c);
+  uint32_t mm = o->max_modes ? o->max_modes : 1;
+  c->cap = cap;
+  c->n = 0;
+  c->vx = (double *)calloc(cap ? cap : 1, sizeof(double));
+  c->vy = (double *)calloc(cap ? cap : 1, sizeof(double));
+  c->vz = (double *)calloc(cap ? cap : 1, sizeof(double));
+  c->sp = (uint8_t *)calloc(cap ? cap : 1, 1);
+  c->lvl = (uint16_t *)calloc((size_t)(cap ? cap : 1) * mm, sizeof(uint16_t));
+  if (!c->vx || !c->vy || !c->vz || !c->sp || !c->lvl) return E_NOMEM;
+  return E_OK;
+}
+
+static uint32_t default_capacity(const orc_ctx *o, uint32_t n) {
+  if (o->cap_default) return o->cap_default;
+  return n + n / 2 + 32;
+}
+
+/* initial (sigma g)_max: an upper bound of sigma g over the cell's pairs,
+ * using |v_p - v_q|^2 <= 4 max|v|^2 and the species present */
+static void init_sgmax(orc_ctx *o, cell_t *c) {
+  double vmax2 = 0.0;
+  int present[ORC_MAX_SPECIES] = {0};
+  for (uint32_t i = 0; i < c->n; ++i) {
+    double v2 = (c->vx[i] * c->vx[i] + c->vy[i] * c->vy[i]) + c->vz[i] * c->vz[i];
+    if (v2 > vmax2) vmax2 = v2;
+    present[c->sp[i]] = 1;
+  }
+  double g2 = 4.0 * vmax2;
+  double best = 0.0;
+  if (g2 > 0.0) {
+    for (uint32_t a = 0; a < o->n_species; ++a) {
+      if (!present[a]) continue;
+      for (uint32_t b = 0; b < o->n_species; ++b) {
+        if (!present[b]) continue;
+        double sg = o->pr[a][b].csg * orc_detpow(g2, o->pr[a][b].esg);
+        if (sg > best) best = sg;
+      }
+    }
+  }
+  c->sgmax = best;
+  c->rem = 0.0;
+}
+
+static int check_particle(const orc_ctx *o, uint32_t sp, const double *v, const uint16_t *lvl) {
+  if (sp >= o->n_species) return E_INVAL;
+  if (!isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2])) return E_NONFINITE;
+  const species_t *s = &o->sp[sp];
+  for (uint32_t m = 0; m < o->max_modes; ++m) {
+    if (m >= s->n_modes) {
+      if (lvl[m] != 0) return E_LEVEL;
+    } else if (m >= s->n_bend && lvl[m] > s->idiss[m]) {
+      return E_LEVEL;
+    }
+  }
+  return E_OK;
+}
+
+/* Stable placement of particles into their cells (a counting sort by cell). */
+int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *species, const double *vel,
+             const uint16_t *levels) {
+  if (!o || !o->finalized) return E_STATE;
+  uint32_t mm = o->max_modes;
+  uint32_t *count = (uint32_t *)calloc(o->n_cells, sizeof(uint32_t));
+  if (!count) return E_NOMEM;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (cell[i] >= o->n_cells) {
+      free(count);
+      return E_INVAL;
+    }
+    int rc = check_particle(o, species[i], vel + 3 * i, levels + (size_t)i * mm);
+    if (rc) {
+      free(count);
+      return rc;
+    }
+    count[cell[i]] += 1;
+  }
+  for (uint32_t c = 0; c < o->n_cells; ++c) {
+    uint32_t cap = default_capacity(o, count[c]);
+    if (count[c] > cap) {
+      free(count);
+      return E_CAPACITY;
+    }
+    int rc = alloc_cell(o, &o->cells[c], cap);
+    if (rc) {
+      free(count);
+      return rc;
+    }
+    memset(o->cells[c].ctr, 0, sizeof(o->cells[c].ctr));
+  }
+  free(count);
+  for (uint64_t i = 0; i < n; ++i) {
+    cell_t *c = &o->cells[cell[i]];
+    uint32_t j = c->n++;
+    c->vx[j] = vel[3 * i];
+    c->vy[j] = vel[3 * i + 1];
+    c->vz[j] = vel[3 * i + 2];
+    c->sp[j] = species[i];
+    for (uint32_t m = 0; m < mm; ++m) c->lvl[(size_t)j * mm + m] = levels[(size_t)i * mm + m];
+  }
+  for (uint32_t c = 0; c < o->n_cells; ++c) init_sgmax(o, &o->cells[c]);
+  o->step = 0;
+  o->loaded = 1;
+  return E_OK;
+}
+
+/* Maxwellian components by Marsaglia's polar method (two normals per accepted point). */
+static void polar_normals(stream *st, double *n1, double *n2) {
+  double x, y, s;
+  for (;;) {
+    x = 2.0 * uniform(st) - 1.0;
+    y = 2.0 * uniform(st) - 1.0;
+    s = x * x + y * y;
+    if (s < 1.0 && s > 0.0) break;
+  }
+  double f = sqrt((-2.0 * orc_detlog(s)) / s);
+  *n1 = x * f;
+  *n2 = y * f;
+}
+
+/* Thermal initial state. Velocities: Maxwellian at T_trans. Bends: the floor
+ * form of the initialization section (i = floor(-ln r T_vib / Theta), r in (0,1]).
+ * Stretches: uniform proposal over 0..i_diss accepted with
+ * exp(-(E_i - E_0)/(k T_vib)) (Eq. accept-quant; proposal range read as
+ * inclusive of the ground state). Stream: pair = slot, cell, step = 0xFFFFFFFE. */
+int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, const double *t_vib) {
+  if (!o || !o->finalized) return E_STATE;
+  uint32_t mm = o->max_modes;
+  for (uint32_t c = 0; c < o->n_cells; ++c) {
+    uint32_t n = 0;
+    for (uint32_t s = 0; s < o->n_species; ++s) n += counts[(size_t)c * o->n_species + s];
+    uint32_t cap = default_capacity(o, n);
+    if (n > cap) return E_CAPACITY;
+    if (!(t_trans[c] >= 0.0) || !(t_vib[c] >= 0.0)) return E_INVAL;
+    int rc = alloc_cell(o, &o->cells[c], cap);
+    if (rc) return rc;
+    cell_t *C = &o->cells[c];
+    memset(C->ctr, 0, sizeof(C->ctr));
+    uint32_t slot = 0;
+    for (uint32_t s = 0; s < o->n_species; ++s) {
+      const species_t *S = &o->sp[s];
+      double sigma = sqrt((K_BOLTZ * t_trans[c]) / S->mass);
+      for (uint32_t k = 0; k < counts[(size_t)c * o->n_species + s]; ++k) {
+        stream st;
+        stream_open(&st, o->seed, slot, c, 0xFFFFFFFEu);
+        double n1, n2, n3, n4;
+        polar_normals(&st, &n1, &n2);
+        polar_normals(&st, &n3, &n4);
+        C->vx[slot] = sigma * n1;
+        C->vy[slot] = sigma * n2;
+        C->vz[slot] = sigma * n3;
+        C->sp[slot] = (uint8_t)s;
+        uint16_t *lv = C->lvl + (size_t)slot * mm;
+        for (uint32_t m = 0; m < mm; ++m) lv[m] = 0;
+        for (uint32_t m = 0; m < S->n_modes; ++m) {
+          if (m < S->n_bend) {
+            double r = 1.0 - uniform(&st);
+            double t = -orc_detlog(r);
+            double fi = floor(t * (t_vib[c] / S->theta[m]));
+            if (fi > 65535.0) fi = 65535.0;
+            lv[m] = (uint16_t)fi;
+          } else {
+            uint32_t top = S->idiss[m];
+            double kt = K_BOLTZ * t_vib[c];
+            for (;;) {
+              double u = uniform(&st);
+              uint32_t i = (uint32_t)floor(u * (double)(top + 1));
+              if (i > top) i = top;
+              double u2 = uniform(&st);
+              double x = (S->lev[m][i] - S->lev[m][0]) / kt;
+              if (u2 < orc_detexp(-x)) {
+                lv[m] = (uint16_t)i;
+                break;
+              }
+            }
+          }
+        }
+        slot += 1;
+      }
+    }
+    C->n = n;
+    init_sgmax(o, C);
+  }
+  o->step = 0;
+  o->loaded = 1;
+  return E_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Vibrational relaxation (Sec. "Implementation of the polyatomic HCAO   */
+/* model"): joint proposal + Larsen-Borgnakke acceptance, and the        */
+/* single-mode (Gibbs sweep) form of the same conditional target.        */
+/* ------------------------------------------------------------------ */
+
+/* proposal range for mode m given the energy e available to the mode */
+static uint32_t mode_top(const species_t *s, uint32_t m, double e) {
+  if (m < s->n_bend) {
+    /* i_max = floor(E/(k Theta) - 1/2) + 1 levels, i = floor(r i_max) in [0, i_max-1] */
+    double fi = floor(e / s->kt[m] - 0.5);
+    if (fi < 0.0) fi = 0.0;
+    if (fi > 65535.0) fi = 65535.0;
+    return (uint32_t)fi; /* inclusive top index */
+  }
+  /* highest stretch level strictly below the available energy, capped at i_diss */
+  uint32_t top = 0;
+  while (top < s->idiss[m] && s->lev[m][top + 1] < e) top += 1;
+  return top;
+}
+
+static uint32_t propose(const species_t *s, uint32_t m, double e, double u) {
+  uint32_t top = mode_top(s, m, e);
+  double span = (double)top + 1.0;
+  uint32_t i = (uint32_t)floor(u * span);
+  if (i > top) i = top;
+  return i;
+}
+
+/* Relaxes one molecule; *e_tr is the translational energy of the pair on
+ * entry and on exit. Returns the number of trials. */
+static uint64_t relax(const orc_ctx *o, const species_t *s, uint16_t *lvl, double *e_tr, double q,
+                      stream *st, int *capped) {
+  uint64_t trials = 0;
+  *capped = 0;
+  if (s->sampler == ORC_SAMPLER_JOINT) {
+    double e_coll = *e_tr + vib_energy(s, lvl);
+    double denom = e_coll - s->zpe;
+    if (!(denom > 0.0)) return 0;
+    uint16_t cand[ORC_MAX_MODES];
+    for (;;) {
+      trials += 1;
+      double sum = 0.0;
+      for (uint32_t m = 0; m < s->n_modes; ++m) {
+        double u = uniform(st);
+        cand[m] = (uint16_t)propose(s, m, e_coll, u);
+        sum = sum + mode_energy(s, m, cand[m]);
+      }
+      double ua = uniform(st);
+      int accept = 0;
+      if (sum < e_coll) accept = ua < orc_detpow((e_coll - sum) / denom, q);
+      if (accept) {
+        for (uint32_t m = 0; m < s->n_modes; ++m) lvl[m] = cand[m];
+        *e_tr = e_coll - sum;
+        break;
+      }
+      if (trials >= ORC_MAX_TRIALS) {
+        *capped = 1;
+        break;
+      }
+    }
+    (void)o;
+    return trials;
+  }
+  /* Gibbs sweep: each mode in turn takes the conditional of the joint target */
+  double et = *e_tr;
+  for (uint32_t m = 0; m < s->n_modes; ++m) {
+    double ec = et + mode_energy(s, m, lvl[m]);
+    double e0 = mode_energy(s, m, 0);
+    double den = ec - e0;
+    if (!(den > 0.0)) continue;
+    for (;;) {
+      trials += 1;
+      double u = uniform(st);
+      uint32_t i = propose(s, m, ec, u);
+      double ei = mode_energy(s, m, i);
+      double ua = uniform(st);
+      int accept = 0;
+      if (ei < ec) accept = ua < orc_detpow((ec - ei) / den, q);
+      if (accept) {
+        lvl[m] = (uint16_t)i;
+        et = ec - ei;
+        break;
+      }
+      if (trials >= ORC_MAX_TRIALS) {
+        *capped = 1;
+        break;
+      }
+    }
+    if (*capped) break;
+  }
+  *e_tr = et;
+  return trials;
+}
+
+/* ------------------------------------------------------------------ */
+/* VHS isotropic scattering                                              */
+/* ------------------------------------------------------------------ */
+static void unit_vector(stream *st, double n[3]) {
+  double x, y, s;
+  for (;;) {
+    x = 2.0 * uniform(st) - 1.0;
+    y = 2.0 * uniform(st) - 1.0;
+    s = x * x + y * y;
+    if (s < 1.0) break;
+  }
+  double f = 2.0 * sqrt(1.0 - s);
+  n[0] = x * f;
+  n[1] = y * f;
+  n[2] = 1.0 - 2.0 * s;
+}
+
+/* Places two bodies (pair table p) about the centre-of-mass velocity vcm
+ * with relative speed sqrt(2 E / m_r) along a random direction. */
+static void split(const pair_t *p, const double vcm[3], double e, stream *st, double va[3], double vb[3]) {
+  double g = sqrt((2.0 * e) / p->mr);
+  double n[3];
+  unit_vector(st, n);
+  double ga = p->wa * g, gb = p->wb * g;
+  for (int k = 0; k < 3; ++k) {
+    va[k] = vcm[k] + ga * n[k];
+    vb[k] = vcm[k] - gb * n[k];
+  }
+}
+
+static void com(const pair_t *p, const double va[3], const double vb[3], double out[3]) {
+  for (int k = 0; k < 3; ++k) out[k] = (p->m_a * va[k] + p->m_b * vb[k]) / p->msum;
+}
+
+/* ------------------------------------------------------------------ */
+/* One accepted collision                                                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double v[2][3];
+  uint8_t sp[2];
+  uint16_t lvl[2][ORC_MAX_MODES];
+} pair_state;
+
+typedef struct {
+  int born;
+  uint8_t sp;
+  double v[3];
+  uint16_t lvl[ORC_MAX_MODES];
+} newborn;
+
+typedef struct {
+  int kind, rx, a_side, mode;
+  double eex;
+} channel;
+
+#define MAX_CHANNELS 64
+
+/* Reaction decision, application, or relaxation + scattering for one
+ * accepted pair. Returns the reaction id or -1. ctr may be NULL. */
+static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint64_t *ctr, newborn *nb) {
+  const pair_t *pp = &o->pr[ps->sp[0]][ps->sp[1]];
+  double e_tr = pp->hm * g2;
+  double evib[2];
+  for (int x = 0; x < 2; ++x) evib[x] = vib_energy(&o->sp[ps->sp[x]], ps->lvl[x]);
+  nb->born = 0;
+
+  /* --- reaction decision: dissociation then exchange channels, canonical order --- */
+  channel ch[MAX_CHANNELS];
+  int nch = 0;
+  for (int side = 0; side < 2; ++side) {
+    int A = ps->sp[side];
+    for (uint32_t r = 0; r < o->n_reactions; ++r) {
+      const reaction_t *R = &o->rx[r];
+      if (R->kind != ORC_RX_DISSOCIATION || R->a != A) continue;
+      const species_t *SA = &o->sp[A];
+      for (uint32_t j = 0; j < SA->n_stretch; ++j) {
+        if (!((R->mask >> j) & 1ULL)) continue;
+        uint32_t m = SA->n_bend + j;
+        /* Eq. Ecoll-diss: E_tr + E_vib,A - sum of ZPE over A, B, C + E_A,j(0) */
+        double ecoll = ((e_tr + evib[side]) - R->zsum) + SA->lev[m][0];
+        double eex = ecoll - SA->de[m];
+        double pool = (e_tr + evib[side]) - R->dh;
+        double left = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
+        if (eex > 0.0 && left > 0.0 && nch < MAX_CHANNELS) {
+          ch[nch].kind = ORC_RX_DISSOCIATION;
+          ch[nch].rx = (int)r;
+          ch[nch].a_side = side;
+          ch[nch].mode = (int)m;
+          ch[nch].eex = eex;
+          nch += 1;
+        }
+      }
+    }
+  }
+  for (int side = 0; side < 2; ++side) {
+    int A = ps->sp[side], B = ps->sp[1 - side];
+    for (uint32_t r = 0; r < o->n_reactions; ++r) {
+      const reaction_t *R = &o->rx[r];
+      if (R->kind != ORC_RX_EXCHANGE || R->a != A || R->b != B) continue;
+      double us = uniform(st);
+      const species_t *SA = &o->sp[A];
+      /* Eq. Ecoll-exch: E_tr + sum_j alpha_j E_vib,A,j */
+      double ecoll = e_tr;
+      for (uint32_t m = 0; m < SA->n_modes; ++m)
+        ecoll = ecoll + R->alpha[m] * mode_energy(SA, m, ps->lvl[side][m]);
+      double eex = ecoll - R->ea;
+      double pool = ((e_tr + evib[side]) + evib[1 - side]) - R->dh;
+      double left = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
+      if (us < R->steric && eex > 0.0 && left > 0.0 && nch < MAX_CHANNELS) {
+        ch[nch].kind = ORC_RX_EXCHANGE;
+        ch[nch].rx = (int)r;
+        ch[nch].a_side = side;
+        ch[nch].mode = -1;
+        ch[nch].eex = eex;
+        nch += 1;
+      }
+    }
+  }
+  int pick = -1;
+  if (nch == 1) {
+    pick = 0;
+  } else if (nch > 1) {
+    /* one draw, channels weighted by their excess energy */
+    double total = 0.0;
+    for (int c = 0; c < nch; ++c) total = total + ch[c].eex;
+    double target = uniform(st) * total;
+    double cum = 0.0;
+    pick = nch - 1;
+    for (int c = 0; c < nch; ++c) {
+      cum = cum + ch[c].eex;
+      if (target < cum) {
+        pick = c;
+        break;
+      }
+    }
+  }
+
+  if (pick >= 0) {
+    const reaction_t *R = &o->rx[ch[pick].rx];
+    int a = ch[pick].a_side, b = 1 - a;
+    if (R->kind == ORC_RX_DISSOCIATION) {
+      /* A + M -> B + C + M: B takes A's slot, C is new. */
+      int spA = ps->sp[a], spM = ps->sp[b];
+      double pool = (e_tr + evib[a]) - R->dh;
+      double et = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
+      uint16_t lb[ORC_MAX_MODES] = {0}, lc[ORC_MAX_MODES] = {0};
+      int capped = 0;
+      uint64_t t = 0;
+      if (o->sp[R->c].n_modes > 0) t += relax(o, &o->sp[R->c], lb, &et, o->pr[R->c][spM].q, st, &capped);
+      if (o->sp[R->d].n_modes > 0) {
+        int c2 = 0;
+        t += relax(o, &o->sp[R->d], lc, &et, o->pr[R->d][spM].q, st, &c2);
+        capped |= c2;
+      }
+      /* share of the translational energy in the B-C relative motion:
+       * density proportional to sqrt(beta (1 - beta)), by rejection */
+      double beta;
+      for (;;) {
+        double u1 = uniform(st), u2 = uniform(st);
+        if (u2 * 0.5 < sqrt(u1 * (1.0 - u1))) {
+          beta = u1;
+          break;
+        }
+      }
+      double ebc = beta * et;
+      double exm = et - ebc;
+      const pair_t *pam = &o->pr[spA][spM];
+      double vcm[3], vbc[3], vm[3], vbn[3], vcn[3];
+      com(pam, ps->v[a], ps->v[b], vcm);
+      split(pam, vcm, exm, st, vbc, vm);
+      split(&o->pr[R->c][R->d], vbc, ebc, st, vbn, vcn);
+      for (int k = 0; k < 3; ++k) {
+        ps->v[a][k] = vbn[k];
+        ps->v[b][k] = vm[k];
+        nb->v[k] = vcn[k];
+      }
+      ps->sp[a] = (uint8_t)R->c;
+      memcpy(ps->lvl[a], lb, sizeof(lb));
+      nb->born = 1;
+      nb->sp = (uint8_t)R->d;
+      memcpy(nb->lvl, lc, sizeof(lc));
+      if (ctr) {
+        ctr[ORC_CTR_TRIALS] += t;
+        ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
+        ctr[ORC_CTR_BIRTHS] += 1;
+        ctr[ORC_CTR_REACTION0 + ch[pick].rx] += 1;
+      }
+    } else {
+      /* A + B -> C + D: C takes A's slot, D takes B's slot. */
+      int spA = ps->sp[a], spB = ps->sp[b];
+      double pool = ((e_tr + evib[a]) + evib[b]) - R->dh;
+      double et = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
+      uint16_t lc[ORC_MAX_MODES] = {0}, ld[ORC_MAX_MODES] = {0};
+      double qcd = o->pr[R->c][R->d].q;
+      int capped = 0;
+      uint64_t t = 0;
+      if (o->sp[R->c].n_modes > 0) t += relax(o, &o->sp[R->c], lc, &et, qcd, st, &capped);
+      if (o->sp[R->d].n_modes > 0) {
+        int c2 = 0;
+        t += relax(o, &o->sp[R->d], ld, &et, qcd, st, &c2);
+        capped |= c2;
+      }
+      double vcm[3], vc[3], vd[3];
+      com(&o->pr[spA][spB], ps->v[a], ps->v[b], vcm);
+      split(&o->pr[R->c][R->d], vcm, et, st, vc, vd);
+      memcpy(ps->v[a], vc, sizeof(vc));
+      memcpy(ps->v[b], vd, sizeof(vd));
+      ps->sp[a] = (uint8_t)R->c;
+      ps->sp[b] = (uint8_t)R->d;
+      memcpy(ps->lvl[a], lc, sizeof(lc));
+      memcpy(ps->lvl[b], ld, sizeof(ld));
+      if (ctr) {
+        ctr[ORC_CTR_TRIALS] += t;
+        ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
+        ctr[ORC_CTR_REACTION0 + ch[pick].rx] += 1;
+      }
+    }
+    return ch[pick].rx;
+  }
+
+  /* --- no reaction: relax each molecule in turn, then scatter --- */
+  for (int x = 0; x < 2; ++x) {
+    const species_t *S = &o->sp[ps->sp[x]];
+    if (S->n_modes == 0) continue;
+    double u = uniform(st);
+    if (!(u < S->p_vib)) continue;
+    int capped = 0;
+    uint64_t t = relax(o, S, ps->lvl[x], &e_tr, pp->q, st, &capped);
+    if (ctr) {
+      ctr[ORC_CTR_TRIALS] += t;
+      ctr[ORC_CTR_RELAX] += 1;
+      ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
+    }
+  }
+  double vcm[3], va[3], vb[3];
+  com(pp, ps->v[0], ps->v[1], vcm);
+  split(pp, vcm, e_tr, st, va, vb);
+  memcpy(ps->v[0], va, sizeof(va));
+  memcpy(ps->v[1], vb, sizeof(vb));
+  return -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* One time step of one cell                                             */
+/* ------------------------------------------------------------------ */
+static void load_pair(const cell_t *C, uint32_t mm, uint32_t p, uint32_t q, pair_state *ps) {
+  uint32_t idx[2] = {p, q};
+  memset(ps, 0, sizeof(*ps));
+  for (int x = 0; x < 2; ++x) {
+    uint32_t i = idx[x];
+    ps->v[x][0] = C->vx[i];
+    ps->v[x][1] = C->vy[i];
+    ps->v[x][2] = C->vz[i];
+    ps->sp[x] = C->sp[i];
+    for (uint32_t m = 0; m < mm; ++m) ps->lvl[x][m] = C->lvl[(size_t)i * mm + m];
+  }
+}
+
+static void store_pair(cell_t *C, uint32_t mm, uint32_t p, uint32_t q, const pair_state *ps) {
+  uint32_t idx[2] = {p, q};
+  for (int x = 0; x < 2; ++x) {
+    uint32_t i = idx[x];
+    C->vx[i] = ps->v[x][0];
+    C->vy[i] = ps->v[x][1];
+    C->vz[i] = ps->v[x][2];
+    C->sp[i] = ps->sp[x];
+    for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)i * mm + m] = ps->lvl[x][m];
+  }
+}
+
+static int step_cell(orc_ctx *o, uint32_t c, double dt) {
+  cell_t *C = &o->cells[c];
+  uint32_t mm = o->max_modes;
+  uint32_t n = C->n;
+  /* NTC: N_cand = floor(1/2 N (N-1) F_N (sigma g)_max dt / V + remainder) */
+  double x = 0.5 * (double)n * (double)(n - (n > 0 ? 1 : 0)) * C->weight * C->sgmax * dt / C->volume + C->rem;
+  double fl = floor(x);
+  C->rem = x - fl;
+  uint64_t ncand = (uint64_t)fl;
+  if (ncand > n / 2) {
+    C->ctr[ORC_CTR_SUPPRESSED] += ncand - n / 2;
+    ncand = n / 2;
+  }
+  /* ten Feistel round keys: words 0..9 of blocks 0, 1, 2 of the cell stream */
+  uint32_t keys[12];
+  for (uint32_t blk = 0; blk < 3; ++blk) {
+    uint32_t ctr[4] = {blk, 0xFFFFFFFFu, c, o->step};
+    orc_philox4x32_10((uint32_t)o->seed, (uint32_t)(o->seed >> 32), ctr, keys + 4 * blk);
+  }
+  newborn *nb = NULL;
+  if (ncand > 0) {
+    nb = (newborn *)calloc(ncand, sizeof(newborn));
+    if (!nb) return E_NOMEM;
+  }
+  double sg_seen = 0.0;
+  for (uint32_t k = 0; k < ncand; ++k) {
+    uint32_t p = orc_feistel_index(n, keys, 2 * k);
+    uint32_t q = orc_feistel_index(n, keys, 2 * k + 1);
+    stream st;
+    stream_open(&st, o->seed, k, c, o->step);
+    C->ctr[ORC_CTR_CANDIDATES] += 1;
+    double dx = C->vx[p] - C->vx[q], dy = C->vy[p] - C->vy[q], dz = C->vz[p] - C->vz[q];
+    double g2 = (dx * dx + dy * dy) + dz * dz;
+    const pair_t *pp = &o->pr[C->sp[p]][C->sp[q]];
+    double sg = (g2 > 0.0) ? pp->csg * orc_detpow(g2, pp->esg) : 0.0;
+    if (sg > sg_seen) sg_seen = sg;
+    double ua = uniform(&st);
+    if (!(ua < sg / C->sgmax)) continue;
+    C->ctr[ORC_CTR_COLLISIONS] += 1;
+    pair_state ps;
+    load_pair(C, mm, p, q, &ps);
+    collide(o, &ps, g2, &st, C->ctr, &nb[k]);
+    store_pair(C, mm, p, q, &ps);
+  }
+  /* births appended in pair order */
+  uint32_t births = 0;
+  for (uint32_t k = 0; k < ncand; ++k) births += (uint32_t)nb[k].born;
+  if (n + births > C->cap) {
+    free(nb);
+    return E_CAPACITY;
+  }
+  for (uint32_t k = 0; k < ncand; ++k) {
+    if (!nb[k].born) continue;
+    uint32_t j = C->n++;
+    C->vx[j] = nb[k].v[0];
+    C->vy[j] = nb[k].v[1];
+    C->vz[j] = nb[k].v[2];
+    C->sp[j] = nb[k].sp;
+    for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)j * mm + m] = nb[k].lvl[m];
+  }
+  free(nb);
+  if (sg_seen > C->sgmax) C->sgmax = sg_seen;
+  return E_OK;
+}
+
+int orc_step(orc_ctx *o, double dt, uint32_t n_steps) {
+  if (!o || !o->loaded) return E_STATE;
+  if (!(dt > 0.0)) return E_INVAL;
+  for (uint32_t s = 0; s < n_steps; ++s) {
+    for (uint32_t c = 0; c < o->n_cells; ++c) {
+      int rc = step_cell(o, c, dt);
+      if (rc) return rc;
+    }
+    o->step += 1;
+  }
+  return E_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Queries                                                               */
+/* ------------------------------------------------------------------ */
+uint32_t orc_max_modes(const orc_ctx *o) { return o->max_modes; }
+uint64_t orc_count(const orc_ctx *o, uint32_t cell) { return cell < o->n_cells ? o->cells[cell].n : 0; }
+uint32_t orc_step_index(const orc_ctx *o) { return o->step; }
+
+int orc_read_cell(const orc_ctx *o, uint32_t cell, uint8_t *species, double *vel, uint16_t *levels) {
+  if (!o || cell >= o->n_cells) return E_INVAL;
+  const cell_t *C = &o->cells[cell];
+  uint32_t mm = o->max_modes;
+  for (uint32_t i = 0; i < C->n; ++i) {
+    species[i] = C->sp[i];
+    vel[3 * i] = C->vx[i];
+    vel[3 * i + 1] = C->vy[i];
+    vel[3 * i + 2] = C->vz[i];
+    for (uint32_t m = 0; m < mm; ++m) levels[(size_t)i * mm + m] = C->lvl[(size_t)i * mm + m];
+  }
+  return E_OK;
+}
+
+int orc_read_cell_state(const orc_ctx *o, uint32_t cell, double *sgmax, double *rem, uint64_t *ctr) {
+  if (!o || cell >= o->n_cells) return E_INVAL;
+  const cell_t *C = &o->cells[cell];
+  *sgmax = C->sgmax;
+  *rem = C->rem;
+  memcpy(ctr, C->ctr, sizeof(C->ctr));
+  return E_OK;
+}
+
+int orc_levels(const orc_ctx *o, uint32_t species, uint32_t mode, double *out, uint32_t max_n) {
+  if (!o || species >= o->n_species) return E_INVAL;
+  const species_t *s = &o->sp[species];
+  if (mode >= s->n_modes) return E_INVAL;
+  if (mode < s->n_bend) {
+    for (uint32_t i = 0; i < max_n; ++i) out[i] = mode_energy(s, mode, i);
+    return (int)max_n;
+  }
+  uint32_t n = s->idiss[mode] + 1;
+  for (uint32_t i = 0; i < n && i < max_n; ++i) out[i] = s->lev[mode][i];
+  return (int)n;
+}
+
+int orc_species_info(const orc_ctx *o, uint32_t species, double *zpe, uint32_t *n_modes, uint32_t *sampler) {
+  if (!o || species >= o->n_species) return E_INVAL;
+  *zpe = o->sp[species].zpe;
+  *n_modes = o->sp[species].n_modes;
+  *sampler = (uint32_t)o->sp[species].sampler;
+  return E_OK;
+}
+
+int orc_pair_info(const orc_ctx *o, uint32_t a, uint32_t b, double *out8) {
+  if (!o || !o->finalized || a >= o->n_species || b >= o->n_species) return E_INVAL;
+  const pair_t *p = &o->pr[a][b];
+  out8[0] = p->mr;
+  out8[1] = p->hm;
+  out8[2] = p->msum;
+  out8[3] = p->wa;
+  out8[4] = p->wb;
+  out8[5] = p->csg;
+  out8[6] = p->esg;
+  out8[7] = p->q;
+  return E_OK;
+}
+
+/* Per-cell moments, plain sequential sums in slot order:
+ * out[0..2] sum m v, out[3] sum m |v|^2, out[4] total mass,
+ * out[5] sum of formation energies,
+ * then per species s: out[6+3s] count, out[7+3s] sum E_vib (with zero point),
+ * out[8+3s] sum (E_vib - ZPE). */
+int orc_moments(const orc_ctx *o, uint32_t cell, double *out) {
+  if (!o || cell >= o->n_cells) return E_INVAL;
+  const cell_t *C = &o->cells[cell];
+  uint32_t mm = o->max_modes;
+  memset(out, 0, sizeof(double) * (6 + 3 * o->n_species));
+  for (uint32_t i = 0; i < C->n; ++i) {
+    const species_t *S = &o->sp[C->sp[i]];
+    double m = S->mass;
+    out[0] += m * C->vx[i];
+    out[1] += m * C->vy[i];
+    out[2] += m * C->vz[i];
+    out[3] += m * ((C->vx[i] * C->vx[i] + C->vy[i] * C->vy[i]) + C->vz[i] * C->vz[i]);
+    out[4] += m;
+    out[5] += S->formation;
+    double ev = vib_energy(S, C->lvl + (size_t)i * mm);
+    out[6 + 3 * C->sp[i]] += 1.0;
+    out[7 + 3 * C->sp[i]] += ev;
+    out[8 + 3 * C->sp[i]] += ev - S->zpe;
+  }
+  return E_OK;
+}
+
+/* Mean vibrational energy above the ground state at temperature t
+ * (mean-energy equation of the implementation section). */
+static double mean_evib(const species_t *s, double t) {
+  double e = 0.0;
+  for (uint32_t m = 0; m < s->n_bend; ++m) e += s->kt[m] / (exp(s->theta[m] / t) - 1.0);
+  for (uint32_t m = s->n_bend; m < s->n_modes; ++m) {
+    double num = 0.0, den = 0.0;
+    for (uint32_t i = 0; i <= s->idiss[m]; ++i) {
+      double de = s->lev[m][i] - s->lev[m][0];
+      double w = exp(-de / (K_BOLTZ * t));
+      num += de * w;
+      den += w;
+    }
+    e += num / den;
+  }
+  return e;
+}
+
+/* T_vib by bisection in log T on [1, 1e6] K (zero-point search of the paper). */
+int orc_tvib(const orc_ctx *o, uint32_t species, double target, double *t_out) {
+  if (!o || species >= o->n_species) return E_INVAL;
+  const species_t *s = &o->sp[species];
+  if (s->n_modes == 0 || !(target > 0.0)) {
+    *t_out = 0.0;
+    return E_OK;
+  }
+  double lo = log(1.0), hi = log(1.0e6);
+  if (mean_evib(s, exp(hi)) < target) {
+    *t_out = exp(hi);
+    return E_OK;
+  }
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mean_evib(s, exp(mid)) < target)
+      lo = mid;
+    else
+      hi = mid;
+    if (hi - lo < 1e-15) break;
+  }
+  *t_out = exp(0.5 * (lo + hi));
+  return E_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Single-operation drivers                                              */
+/* ------------------------------------------------------------------ */
+/* n independent relaxations of one species; item i uses stream
+ * (pair = i, cell = 0xFFFFFFF0, step = current step). */
+int orc_relax_batch(orc_ctx *o, uint32_t species, double q, int sampler, uint32_t n, const double *e_tr,
+                    const uint16_t *lvl_in, uint16_t *lvl_out, double *e_tr_out, uint64_t *trials) {
+  if (!o || !o->finalized || species >= o->n_species) return E_INVAL;
+  species_t s = o->sp[species];
+  if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS) s.sampler = sampler;
+  uint32_t nm = s.n_modes;
+  for (uint32_t i = 0; i < n; ++i) {
+    stream st;
+    stream_open(&st, o->seed, i, 0xFFFFFFF0u, o->step);
+    uint16_t lv[ORC_MAX_MODES];
+    for (uint32_t m = 0; m < nm; ++m) lv[m] = lvl_in[(size_t)i * nm + m];
+    double et = e_tr[i];
+    int capped;
+    uint64_t t = relax(o, &s, lv, &et, q, &st, &capped);
+    for (uint32_t m = 0; m < nm; ++m) lvl_out[(size_t)i * nm + m] = lv[m];
+    e_tr_out[i] = et;
+    if (trials) trials[i] = t;
+  }
+  return E_OK;
+}
+
+/* Heat-bath chain: iteration i draws nothing but the relaxation; the
+ * translational energy offered to the molecule is the input e_tr[i].
+ * Chain c uses streams (pair = i, cell = 0xFFFFFFF1, step = c).
+ * hist[m * stride + level] counts the post-collision level of mode m
+ * (hist may be NULL). */
+int orc_relax_chain(orc_ctx *o, uint32_t species, double q, int sampler, uint32_t chain, uint32_t n_iter,
+                    const double *e_tr, uint16_t *lvl_state, uint64_t *hist, uint32_t hist_stride) {
+  if (!o || !o->finalized || species >= o->n_species) return E_INVAL;
+  species_t s = o->sp[species];
+  if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS) s.sampler = sampler;
+  for (uint32_t i = 0; i < n_iter; ++i) {
+    stream st;
+    stream_open(&st, o->seed, i, 0xFFFFFFF1u, chain);
+    double et = e_tr[i];
+    int capped;
+    relax(o, &s, lvl_state, &et, q, &st, &capped);
+    if (!hist) continue;
+    for (uint32_t m = 0; m < s.n_modes; ++m) {
+      uint32_t l = lvl_state[m];
+      if (l < hist_stride) hist[(size_t)m * hist_stride + l] += 1;
+    }
+  }
+  return E_OK;
+}
+
+/* n independent accepted collisions of given pairs (no NTC, no acceptance
+ * draw); item i uses stream (pair = i, cell = 0xFFFFFFF2, step = current).
+ * Arrays: sp[2n], vel[6n], lvl[2n x max_modes]; outputs likewise; born_*
+ * receive the newborn of item i (born_sp = 255 when none). */
+int orc_collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
+                      uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
+                      uint8_t *born_sp, double *born_vel, uint16_t *born_lvl) {
+  if (!o || !o->finalized) return E_INVAL;
+  uint32_t mm = o->max_modes;
+  for (uint32_t i = 0; i < n; ++i) {
+    pair_state ps;
+    memset(&ps, 0, sizeof(ps));
+    for (int x = 0; x < 2; ++x) {
+      if (sp[2 * i + x] >= o->n_species) return E_INVAL;
+      ps.sp[x] = sp[2 * i + x];
+      for (int k = 0; k < 3; ++k) ps.v[x][k] = vel[6 * i + 3 * x + k];
+      for (uint32_t m = 0; m < mm; ++m) ps.lvl[x][m] = lvl[((size_t)2 * i + x) * mm + m];
+    }
+    double dx = ps.v[0][0] - ps.v[1][0], dy = ps.v[0][1] - ps.v[1][1], dz = ps.v[0][2] - ps.v[1][2];
+    double g2 = (dx * dx + dy * dy) + dz * dz;
+    stream st;
+    stream_open(&st, o->seed, i, 0xFFFFFFF2u, o->step);
+    newborn nb;
+    memset(&nb, 0, sizeof(nb));
+    reaction_out[i] = collide(o, &ps, g2, &st, NULL, &nb);
+    for (int x = 0; x < 2; ++x) {
+      sp_out[2 * i + x] = ps.sp[x];
+      for (int k = 0; k < 3; ++k) vel_out[6 * i + 3 * x + k] = ps.v[x][k];
+      for (uint32_t m = 0; m < mm; ++m) lvl_out[((size_t)2 * i + x) * mm + m] = ps.lvl[x][m];
+    }
+    born_sp[i] = nb.born ? nb.sp : 255;
+    for (int k = 0; k < 3; ++k) born_vel[3 * i + k] = nb.born ? nb.v[k] : 0.0;
+    for (uint32_t m = 0; m < mm; ++m) born_lvl[(size_t)i * mm + m] = nb.born ? nb.lvl[m] : 0;
+  }
+  return E_OK;
+}

@@ -1,0 +1,91 @@
+/*
+ * hcao_oracle.h -- fp64 CPU oracle of the HCAO DSMC collision step.
+ *
+ * TEST INFRASTRUCTURE. This library exists only to check the GPU library
+ * against a plain, slow, obviously correct implementation. Only the test
+ * suite, the smoke entry point and the CPU-baseline leg of the benchmark
+ * may load it. The product path never calls it, and it shares no source
+ * with the GPU library: both are written independently from the paper
+ * (Lauterbach, Tuttas, Pfeiffer, "A harmonically-coupled-anharmonic-
+ * oscillator approach for polyatomic chemistry modeling in DSMC") and from
+ * the determinism specification of the readings listed in the design notes.
+ *
+ * Plain C API (ctypes friendly). Energies in J, SI units throughout.
+ * Every call returns 0 on success and a negative code on error.
+ */
+#ifndef HCAO_ORACLE_H
+#define HCAO_ORACLE_H
+#include <stdint.h>
+
+#define ORC_MAX_SPECIES 16
+#define ORC_MAX_MODES 16
+#define ORC_MAX_LEVELS 1024
+#define ORC_MAX_REACTIONS 32
+#define ORC_MAX_TRIALS 1000000
+
+/* per-cell counter slots */
+enum {
+  ORC_CTR_CANDIDATES = 0, /* NTC candidate pairs tested */
+  ORC_CTR_COLLISIONS = 1, /* accepted pairs (reactive ones included) */
+  ORC_CTR_TRIALS = 2,     /* relaxation sampler trials */
+  ORC_CTR_RELAX = 3,      /* relaxations performed */
+  ORC_CTR_CAPPED = 4,     /* sampler gave up after ORC_MAX_TRIALS */
+  ORC_CTR_SUPPRESSED = 5, /* NTC excess over floor(N/2), suppressed recombinations */
+  ORC_CTR_BIRTHS = 6,
+  ORC_CTR_DEATHS = 7,
+  ORC_CTR_REACTION0 = 8,  /* + reaction id */
+  ORC_N_CTR = 8 + ORC_MAX_REACTIONS
+};
+
+enum { ORC_SAMPLER_AUTO = 0, ORC_SAMPLER_JOINT = 1, ORC_SAMPLER_GIBBS = 2 };
+enum { ORC_RX_DISSOCIATION = 0, ORC_RX_EXCHANGE = 1, ORC_RX_RECOMBINATION = 2 };
+
+typedef struct orc_ctx orc_ctx;
+
+/* ---- determinism primitives (exported for pins) ---- */
+void orc_philox4x32_10(uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t out[4]);
+double orc_detlog(double x);
+double orc_detexp(double x);
+double orc_detpow(double x, double y);
+uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[10], uint32_t i);
+
+/* ---- context ---- */
+int orc_create(uint64_t seed, uint32_t n_cells, const double *cell_volume, const double *cell_weight,
+               uint32_t capacity_per_cell, orc_ctx **out);
+void orc_destroy(orc_ctx *o);
+int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double tref,
+                    uint32_t n_bend, const double *theta, uint32_t n_stretch, const double *omega_e,
+                    const double *chi_e, const double *de, const uint32_t *n_levels,
+                    const double *levels, double formation, double p_vib, int sampler);
+int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int32_t product[2],
+                     uint64_t stretch_mask, const double *alpha, double steric, double ea);
+int orc_finalize(orc_ctx *o);
+int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *species, const double *vel,
+             const uint16_t *levels);
+int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, const double *t_vib);
+int orc_step(orc_ctx *o, double dt, uint32_t n_steps);
+
+/* ---- queries ---- */
+uint32_t orc_max_modes(const orc_ctx *o);
+uint64_t orc_count(const orc_ctx *o, uint32_t cell);
+uint32_t orc_step_index(const orc_ctx *o);
+int orc_read_cell(const orc_ctx *o, uint32_t cell, uint8_t *species, double *vel, uint16_t *levels);
+int orc_read_cell_state(const orc_ctx *o, uint32_t cell, double *sgmax, double *rem, uint64_t *ctr);
+int orc_levels(const orc_ctx *o, uint32_t species, uint32_t mode, double *out, uint32_t max_n);
+int orc_species_info(const orc_ctx *o, uint32_t species, double *zpe, uint32_t *n_modes,
+                     uint32_t *sampler);
+int orc_pair_info(const orc_ctx *o, uint32_t a, uint32_t b, double *out8);
+int orc_moments(const orc_ctx *o, uint32_t cell, double *out);
+int orc_tvib(const orc_ctx *o, uint32_t species, double mean_evib_above_ground, double *t_out);
+
+/* ---- single-operation drivers for statistical and brute-force pins ---- */
+int orc_relax_batch(orc_ctx *o, uint32_t species, double q, int sampler, uint32_t n,
+                    const double *e_tr, const uint16_t *lvl_in, uint16_t *lvl_out,
+                    double *e_tr_out, uint64_t *trials);
+int orc_relax_chain(orc_ctx *o, uint32_t species, double q, int sampler, uint32_t chain,
+                    uint32_t n_iter, const double *e_tr, uint16_t *lvl_state, uint64_t *hist,
+                    uint32_t hist_stride);
+int orc_collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel,
+                      const uint16_t *lvl, uint8_t *sp_out, double *vel_out, uint16_t *lvl_out,
+                      int32_t *reaction_out, uint8_t *born_sp, double *born_vel, uint16_t *born_lvl);
+#endif

@@ -1,0 +1,252 @@
+/*
+ * hcao.h -- C ABI of the MI355X (gfx950) HCAO DSMC collision-step library.
+ *
+ * The library advances independent 0D reservoir cells of a dilute gas by
+ * the Direct Simulation Monte Carlo collision step with the polyatomic
+ * harmonically-coupled-anharmonic-oscillator (HCAO) vibrational model of
+ * Lauterbach, Tuttas and Pfeiffer, "A harmonically-coupled-anharmonic-
+ * oscillator approach for polyatomic chemistry modeling in DSMC":
+ *   - stretches are Morse oscillators (Eq. energy-AHO, chi_e = hc w_e/(4 D_e)),
+ *     bends are harmonic (Eq. energy-SHO and its Theta form), local-mode basis
+ *     (Sec. "The polyatomic HCAO model");
+ *   - every accepted pair first tests the reaction channels (Sec. "Polyatomic
+ *     QK reaction modeling": dissociation per stretch, Eq. Ecoll-diss;
+ *     exchange with steric factor and mode coupling alpha_j, Eq. Ecoll-exch;
+ *     competing channels weighted by their excess energy), else relaxes its
+ *     molecules by the joint Larsen-Borgnakke acceptance (Sec. "Implementation
+ *     of the polyatomic HCAO model") and scatters isotropically (VHS).
+ * Pair selection is Bird's no-time-counter (NTC) scheme over disjoint pairs
+ * of a keyed permutation; random numbers are Philox4x32-10 streams keyed by
+ * (seed, step, cell, pair), so results do not depend on launch shape.
+ *
+ * Conventions
+ *   Units: SI. Energies in J, measured from the potential minimum (they
+ *   include zero-point energy). Velocities in m/s.
+ *   Ownership: every input array is owned by the caller and copied during
+ *   the call; output arrays are caller-allocated with the sizes documented
+ *   below. All pointers are HOST pointers unless a name ends in _dev.
+ *   The context owns its device memory (freed by hcao_destroy).
+ *   Errors: every call returns an hcao_status. A device-side error (capacity
+ *   overflow, non-finite state) is sticky: later calls return it until
+ *   hcao_destroy. hcao_last_error() describes the last failure. No C++
+ *   exception crosses this boundary.
+ *   Call order: create -> add_species* -> add_reaction* -> finalize ->
+ *   (load_particles | init_thermal) -> (step | read_*)*. Violations return
+ *   HCAO_ESTATE.
+ *   Threading: a context is not thread-safe. All device work is issued on
+ *   the HIP stream given at create time (NULL = the null stream).
+ *   Layout of level arrays: n x max_modes row-major uint16 quantum numbers;
+ *   modes are ordered bends first, then stretches, as registered; unused
+ *   slots (mode >= the species' mode count) must be 0.
+ */
+#ifndef HCAO_H
+#define HCAO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HCAO_ABI_VERSION 1u
+#define HCAO_MAX_SPECIES 16
+#define HCAO_MAX_MODES 16
+#define HCAO_MAX_REACTIONS 32
+#define HCAO_MAX_LEVELS 1024
+/* per-cell counters (hcao_read_counters): */
+#define HCAO_CTR_CANDIDATES 0 /* NTC candidate pairs tested */
+#define HCAO_CTR_COLLISIONS 1 /* accepted pairs, reactive ones included */
+#define HCAO_CTR_TRIALS 2     /* relaxation sampler trials */
+#define HCAO_CTR_RELAX 3      /* molecule relaxations */
+#define HCAO_CTR_CAPPED 4     /* sampler stopped after 1e6 trials (levels kept) */
+#define HCAO_CTR_SUPPRESSED 5 /* NTC candidates beyond floor(N/2) (dropped) */
+#define HCAO_CTR_BIRTHS 6
+#define HCAO_CTR_DEATHS 7
+#define HCAO_CTR_REACTION0 8  /* + reaction id: reactions performed */
+#define HCAO_N_CTR (8 + HCAO_MAX_REACTIONS)
+
+typedef struct hcao_ctx hcao_ctx;
+
+typedef enum {
+  HCAO_OK = 0,
+  HCAO_EINVAL = -1,      /* bad argument */
+  HCAO_ESTATE = -2,      /* call out of order */
+  HCAO_ENOMEM = -3,      /* host or device allocation failed */
+  HCAO_EDEVICE = -4,     /* HIP runtime error */
+  HCAO_ECAPACITY = -5,   /* a cell exceeded its slot capacity (births) */
+  HCAO_ELEVEL = -6,      /* quantum number above the top bound level, or a
+                            nonzero level in an unused mode slot */
+  HCAO_ENONFINITE = -7,  /* non-finite velocity */
+  HCAO_EUNSUPPORTED = -8 /* feature not available in this build */
+} hcao_status;
+
+typedef enum { HCAO_FP64 = 0, HCAO_MIXED = 1 } hcao_precision;
+typedef enum { HCAO_SAMPLER_AUTO = 0, HCAO_SAMPLER_JOINT = 1, HCAO_SAMPLER_GIBBS = 2 } hcao_sampler;
+typedef enum { HCAO_RX_DISSOCIATION = 0, HCAO_RX_EXCHANGE = 1, HCAO_RX_RECOMBINATION = 2 } hcao_rx_kind;
+
+/* Context configuration.
+ *   seed: key of every random stream.
+ *   n_cells: number of independent reservoir cells (>= 1).
+ *   cell_volume / cell_weight: per-cell V [m^3] and particle weight F_N
+ *     (real molecules per simulated particle); both must be > 0.
+ *   capacity_per_cell: slot capacity of every cell; 0 = N + N/2 + 32 for a
+ *     cell loaded with N particles. Dissociation appends products; a cell
+ *     that would exceed its capacity stops the run with HCAO_ECAPACITY.
+ *   device: HIP device ordinal. hip_stream: hipStream_t or NULL. */
+typedef struct {
+  uint32_t abi_version; /* must be HCAO_ABI_VERSION */
+  hcao_precision precision;
+  uint64_t seed;
+  uint32_t n_cells;
+  const double *cell_volume; /* n_cells */
+  const double *cell_weight; /* n_cells */
+  uint32_t capacity_per_cell;
+  int device;
+  void *hip_stream;
+} hcao_config;
+
+/* One species (Sec. "Implementation of the polyatomic HCAO model": every
+ * stretch needs its level list or spectroscopic constants, every bend its
+ * characteristic temperature).
+ *   mass_kg; VHS d_ref [m], omega (0.5 <= omega < 1.5), T_ref [K];
+ *   n_bend, bend_theta_K[n_bend];
+ *   n_stretch, omega_e_per_m[n_stretch] (w_e in m^-1), chi_e[n_stretch],
+ *     De_J[n_stretch] (<= 0 or NULL: hc w_e / (4 chi_e));
+ *   n_levels / levels_J: optional explicit stretch level lists (NULL = Morse
+ *     from w_e, chi_e), concatenated per stretch, strictly increasing;
+ *   levels are kept while below D_e and still increasing (at most 1024);
+ *   formation_J: formation energy h_s (reaction enthalpies are differences);
+ *   coupling: stored and reported only (the pooled joint redistribution is
+ *     the stretch-bend coupling of this model);
+ *   p_vib: probability that an accepted non-reactive collision relaxes the
+ *     molecule (0..1);
+ *   sampler: JOINT = the joint proposal + acceptance as printed; GIBBS = one
+ *     sweep of single-mode conditionals of the same target; AUTO = JOINT for
+ *     at most 4 modes, GIBBS otherwise. */
+typedef struct {
+  double mass_kg, dref_m, omega, Tref_K;
+  uint32_t n_bend;
+  const double *bend_theta_K;
+  uint32_t n_stretch;
+  const double *omega_e_per_m, *chi_e, *De_J;
+  const uint32_t *n_levels;
+  const double *levels_J;
+  double formation_J;
+  double coupling;
+  double p_vib;
+  hcao_sampler sampler;
+} hcao_species_desc;
+
+/* One reaction (Sec. "Polyatomic QK reaction modeling").
+ *   DISSOCIATION: reactant[0] = A (any partner M), product = {B, C}; B takes
+ *     A's slot, C is appended to the cell. stretch_mask bit j: A's j-th
+ *     stretch is a dissociation channel (threshold: Eq. Ecoll-diss > D_e).
+ *     m_A must equal m_B + m_C.
+ *   EXCHANGE: reactant = {A, B}, product = {C, D}; C takes A's slot, D B's.
+ *     alpha[n_modes of A] couples each of A's modes (Eq. Ecoll-exch); steric
+ *     in [0,1]; Ea_J the barrier. m_A + m_B must equal m_C + m_D.
+ *   RECOMBINATION: not available in this build (HCAO_EUNSUPPORTED).
+ *   gamma_rot must be 0 (no rotational modes are modelled). */
+typedef struct {
+  hcao_rx_kind kind;
+  int32_t reactant[2];
+  int32_t product[2];
+  uint64_t stretch_mask;
+  const double *alpha;
+  double steric, Ea_J;
+  double gamma_rot;
+  uint32_t n_samp;
+} hcao_reaction_desc;
+
+/* Moments of one cell or of all cells (hcao_read_moments).
+ * E_trans_J is the translational energy in the frame of the cell's mean
+ * velocity; T_trans_K = 2 E_trans / (3 k N); T_vib_K[s] solves the Boltzmann
+ * mean-energy equation of the paper for the species' mean vibrational
+ * energy above the zero point (0 for atoms or absent species). */
+typedef struct {
+  uint64_t n_total;
+  uint64_t n_species[HCAO_MAX_SPECIES];
+  double number_density[HCAO_MAX_SPECIES]; /* N_s F_N / V [m^-3] (total: summed over cells / total V) */
+  double momentum[3];                      /* sum m v [kg m/s] per simulated particle */
+  double E_trans_J, E_kin_J;               /* translational energy (COM frame), kinetic energy */
+  double E_vib_J[HCAO_MAX_SPECIES];        /* sum of vibrational energy above the zero point */
+  double E_formation_J;                    /* sum of formation energies */
+  double T_trans_K;
+  double T_vib_K[HCAO_MAX_SPECIES];
+} hcao_moments;
+
+const char *hcao_status_string(hcao_status s);
+const char *hcao_last_error(const hcao_ctx *ctx);
+
+hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out);
+hcao_status hcao_add_species(hcao_ctx *ctx, const hcao_species_desc *sp, int32_t *id);
+hcao_status hcao_add_reaction(hcao_ctx *ctx, const hcao_reaction_desc *rx, int32_t *id);
+/* Builds the level, pair and reaction tables and uploads them. */
+hcao_status hcao_finalize(hcao_ctx *ctx);
+
+/* Loads n particles from host arrays in any order: cell[n] (< n_cells),
+ * species[n], vel[3n] (x,y,z per particle), levels[n * max_modes].
+ * Particles are placed by a stable counting sort on the device, so each
+ * cell keeps the given relative order. Resets the step counter to 0 and
+ * sets each cell's (sigma g)_max to an upper bound over its initial pairs. */
+hcao_status hcao_load_particles(hcao_ctx *ctx, uint64_t n, const uint32_t *cell, const uint8_t *species,
+                                const double *vel, const uint16_t *levels);
+
+/* Thermal initial state on the device: counts[n_cells * n_species] particles
+ * per cell and species (species-major within a cell), Maxwellian velocities
+ * at t_trans[c] and vibrational levels at t_vib[c] (the paper's
+ * initialization: bends by the floor form, stretches by Eq. accept-quant
+ * with a proposal over 0..i_diss). */
+hcao_status hcao_init_thermal(hcao_ctx *ctx, const uint32_t *counts, const double *t_trans,
+                              const double *t_vib);
+
+/* Advances every cell by n_steps collision steps of length dt [s]. */
+hcao_status hcao_step(hcao_ctx *ctx, double dt, uint32_t n_steps);
+
+/* Waits for the stream and returns the sticky device status. */
+hcao_status hcao_sync(hcao_ctx *ctx);
+
+/* Sizes: number of cells' live particles and the mode-slot count. */
+hcao_status hcao_get_counts(hcao_ctx *ctx, uint64_t *per_cell /* n_cells or NULL */, uint64_t *total);
+uint32_t hcao_max_modes(const hcao_ctx *ctx);
+uint32_t hcao_step_index(const hcao_ctx *ctx);
+
+/* Reads every live particle in canonical order (cell-major; within a cell:
+ * survivors in their previous order, then products born in pair order).
+ * species[total], vel[3 total], levels[total * max_modes]. */
+hcao_status hcao_read_particles(hcao_ctx *ctx, uint8_t *species, double *vel, uint16_t *levels);
+
+/* Per-cell state: sgmax[n_cells] ((sigma g)_max, m^3/s), rem[n_cells] (NTC
+ * remainder), counters[n_cells * HCAO_N_CTR]. Any pointer may be NULL. */
+hcao_status hcao_read_cell_state(hcao_ctx *ctx, double *sgmax, double *rem, uint64_t *counters);
+
+/* Moments; per_cell[n_cells] may be NULL. */
+hcao_status hcao_read_moments(hcao_ctx *ctx, hcao_moments *per_cell, hcao_moments *total);
+
+/* Reaction counts summed over cells: counts[n_reactions]. */
+hcao_status hcao_read_reaction_counts(hcao_ctx *ctx, uint64_t *counts);
+
+/* Tables as built on the host (for table-equality checks):
+ * hcao_get_levels: stretch levels (or the first max_n bend levels) of one
+ * mode, returns the count written via *n_out. hcao_get_pair: m_r, m_r/2,
+ * m_a + m_b, m_b/(m_a+m_b), m_a/(m_a+m_b), C (sigma g = C (g^2)^e), e, q. */
+hcao_status hcao_get_levels(const hcao_ctx *ctx, uint32_t species, uint32_t mode, double *out, uint32_t max_n,
+                            uint32_t *n_out);
+hcao_status hcao_get_pair(const hcao_ctx *ctx, uint32_t a, uint32_t b, double *out8);
+
+/* Kernel timing over the stream: when enabled, the library records HIP
+ * events around each step-kernel launch; hcao_kernel_time returns the
+ * summed elapsed milliseconds and the number of launches since enabling. */
+hcao_status hcao_set_timing(hcao_ctx *ctx, int enable);
+hcao_status hcao_kernel_time(hcao_ctx *ctx, double *ms, uint64_t *launches);
+
+/* Checkpoint of the full state (particles, per-cell state, step index). */
+hcao_status hcao_save(hcao_ctx *ctx, const char *path);
+hcao_status hcao_restore(hcao_ctx *ctx, const char *path);
+
+void hcao_destroy(hcao_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1012 @@
+// hcao_runtime.cpp -- host runtime behind the C ABI of include/hcao.h.
+//
+// Builds the species, pair and reaction tables on the host, owns the
+// device buffers of the structure-of-arrays particle state, and issues the
+// gfx950 kernels of hcao_kernels.hip on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hcao.h"
+#include "hcao_tables.h"
+
+namespace hcao {
+// kernels (hcao_kernels.hip)
+size_t step_lds_bytes(uint32_t lds_cap, uint32_t mm, int block);
+hipError_t launch_step(const StepArgs &a, uint32_t mm, int block, uint32_t n_blocks, hipStream_t s);
+hipError_t set_step_lds_limit(size_t bytes);
+hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
+                       const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
+                       hipStream_t s);
+hipError_t launch_cell_init(const Tables *tab, const State &st, const CellArrays &cells, uint32_t n_cells,
+                            hipStream_t s);
+hipError_t launch_moments(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
+                          const uint32_t *cnt, double *out, uint32_t n_cells, hipStream_t s);
+hipError_t launch_load_check(const Tables *tab, const uint32_t *cell, const uint8_t *sp, const double *vel,
+                             const uint16_t *lvl, uint64_t n, uint32_t n_cells, uint32_t *count, uint32_t *err,
+                             hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t s);
+hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32_t *idx_tmp, uint32_t *hist,
+                       uint64_t *offs, uint64_t n, uint32_t key_bits, hipStream_t s, bool &result_in_tmp);
+uint64_t sort_tiles(uint64_t n);
+hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
+                        const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,
+                        const uint16_t *lvl, const State &st, uint64_t n, hipStream_t s);
+}  // namespace hcao
+
+using namespace hcao;
+
+namespace {
+
+constexpr double kH = 6.62607015e-34;
+constexpr double kC = 299792458.0;
+constexpr double kB = 1.380649e-23;
+constexpr double kPi = 3.141592653589793;
+constexpr size_t kLdsBudget = 64 * 1024;  // LDS bytes per workgroup for the tile path
+
+struct SpeciesHost {
+  hcao_species_desc d;
+  std::vector<double> theta;
+  std::vector<std::vector<double>> levels;  // per stretch
+  std::vector<double> de;
+  double zpe = 0.0;
+  int sampler = HCAO_SAMPLER_JOINT;
+  uint32_t n_modes = 0;
+};
+
+struct ReactionHost {
+  hcao_reaction_desc d;
+  std::vector<double> alpha;
+};
+
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  hipError_t alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = count;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+struct hcao_ctx {
+  hcao_config cfg{};
+  std::vector<double> volume, weight;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool finalized = false, loaded = false;
+  hcao_status sticky = HCAO_OK;
+  std::string last_error;
+  std::vector<SpeciesHost> species;
+  std::vector<ReactionHost> reactions;
+  uint32_t max_modes = 0;
+  Tables tab{};
+  std::vector<double> lev_host;
+  DevBuf<Tables> d_tab;
+  DevBuf<double> d_lev;
+  // particle state
+  uint64_t total_slots = 0;
+  std::vector<uint32_t> cap_host;
+  std::vector<uint64_t> off_host;
+  DevBuf<double> vx, vy, vz, bvx, bvy, bvz;
+  DevBuf<uint8_t> sp, bsp;
+  DevBuf<uint16_t> lvl, blvl;
+  DevBuf<uint64_t> off;
+  DevBuf<uint32_t> cnt, cap;
+  DevBuf<double> d_volume, d_weight, sgmax, rem;
+  DevBuf<unsigned long long> ctr;
+  DevBuf<uint32_t> err;
+  DevBuf<uint32_t> lds_cells, big_cells;
+  uint32_t n_lds_cells = 0, n_big_cells = 0, lds_cap = 0;
+  int block = 64;
+  uint32_t step = 0;
+  bool timing = false;
+  double timed_ms = 0.0;
+  uint64_t timed_launches = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_create_error;  // failure text of the last hcao_create on this thread
+
+hcao_status fail(hcao_ctx *c, hcao_status s, const std::string &msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+hcao_status hip_fail(hcao_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (c) {
+    c->last_error = m;
+    c->sticky = HCAO_EDEVICE;
+  }
+  return HCAO_EDEVICE;
+}
+
+#define HIP_TRY(ctx, expr)                               \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+// Morse levels E(i) = a (i + 1/2) - a x_e (i + 1/2)^2, a = h c w_e; kept while
+// below D_e and still increasing. D_e defaults to a / (4 x_e).
+hcao_status build_stretch(hcao_ctx *c, double we, double xe, double de, uint32_t n_explicit, const double *expl,
+                          std::vector<double> &out, double &de_out) {
+  out.clear();
+  if (n_explicit > 0) {
+    if (!(de > 0.0)) return fail(c, HCAO_EINVAL, "explicit level list needs D_e > 0");
+    for (uint32_t i = 0; i < n_explicit && i < (uint32_t)kMaxLevels; ++i) {
+      const double e = expl[i];
+      if (!(e < de)) break;
+      if (i > 0 && !(e > out.back())) return fail(c, HCAO_EINVAL, "level list must increase strictly");
+      out.push_back(e);
+    }
+  } else {
+    if (!(we > 0.0) || !(xe >= 0.0)) return fail(c, HCAO_EINVAL, "stretch needs omega_e > 0 and chi_e >= 0");
+    const double a = (kH * kC) * we;
+    const double ax = a * xe;
+    if (!(de > 0.0)) {
+      if (!(xe > 0.0)) return fail(c, HCAO_EINVAL, "D_e missing and chi_e = 0");
+      de = a / (4.0 * xe);
+    }
+    for (uint32_t i = 0; i < (uint32_t)kMaxLevels; ++i) {
+      const double v = (double)i + 0.5;
+      const double e = (a * v) - ((ax * v) * v);
+      if (!(e < de)) break;
+      if (i > 0 && !(e > out.back())) break;
+      out.push_back(e);
+    }
+  }
+  if (out.empty()) return fail(c, HCAO_EINVAL, "stretch has no bound level");
+  de_out = de;
+  return HCAO_OK;
+}
+
+double host_mode_energy(const SpeciesHost &s, uint32_t m, uint32_t i) {
+  const uint32_t nb = s.d.n_bend;
+  if (m < nb) return ((double)i + 0.5) * (kB * s.theta[m]);
+  return s.levels[m - nb][i];
+}
+
+void free_state(hcao_ctx *c) {
+  c->vx.release();
+  c->vy.release();
+  c->vz.release();
+  c->sp.release();
+  c->lvl.release();
+  c->bvx.release();
+  c->bvy.release();
+  c->bvz.release();
+  c->bsp.release();
+  c->blvl.release();
+  c->off.release();
+  c->cnt.release();
+  c->cap.release();
+  c->d_volume.release();
+  c->d_weight.release();
+  c->sgmax.release();
+  c->rem.release();
+  c->ctr.release();
+  c->lds_cells.release();
+  c->big_cells.release();
+  c->loaded = false;
+}
+
+uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
+  if (c->cfg.capacity_per_cell) return c->cfg.capacity_per_cell;
+  return n + n / 2 + 32;
+}
+
+State state_of(hcao_ctx *c) { return State{c->vx.p, c->vy.p, c->vz.p, c->sp.p, c->lvl.p, c->total_slots}; }
+State scratch_of(hcao_ctx *c) {
+  return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bsp.p, c->blvl.p, c->total_slots};
+}
+CellArrays cells_of(hcao_ctx *c) {
+  return CellArrays{c->off.p, c->cnt.p, c->cap.p, c->d_volume.p, c->d_weight.p, c->sgmax.p, c->rem.p, c->ctr.p};
+}
+
+// Allocates the state for per-cell counts; sets capacities, offsets and
+// the split between cells served from LDS tiles and from HBM.
+hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
+                        const std::vector<uint32_t> *caps = nullptr) {
+  free_state(c);
+  const uint32_t nc = c->cfg.n_cells;
+  c->cap_host.assign(nc, 0);
+  c->off_host.assign(nc + 1, 0);
+  uint64_t tot = 0;
+  for (uint32_t i = 0; i < nc; ++i) {
+    const uint32_t cp = caps ? (*caps)[i] : default_cap(c, counts[i]);
+    if (counts[i] > cp) return fail(c, HCAO_ECAPACITY, "cell " + std::to_string(i) + " exceeds its capacity");
+    c->cap_host[i] = cp;
+    c->off_host[i] = tot;
+    tot += cp;
+  }
+  c->off_host[nc] = tot;
+  c->total_slots = tot;
+  const uint32_t mm = c->max_modes ? c->max_modes : 1;
+  HIP_TRY(c, c->vx.alloc(tot));
+  HIP_TRY(c, c->vy.alloc(tot));
+  HIP_TRY(c, c->vz.alloc(tot));
+  HIP_TRY(c, c->sp.alloc(tot));
+  HIP_TRY(c, c->lvl.alloc(tot * mm));
+  HIP_TRY(c, c->off.alloc(nc + 1));
+  HIP_TRY(c, c->cnt.alloc(nc));
+  HIP_TRY(c, c->cap.alloc(nc));
+  HIP_TRY(c, c->d_volume.alloc(nc));
+  HIP_TRY(c, c->d_weight.alloc(nc));
+  HIP_TRY(c, c->sgmax.alloc(nc));
+  HIP_TRY(c, c->rem.alloc(nc));
+  HIP_TRY(c, c->ctr.alloc((size_t)nc * kNumCtr));
+  HIP_TRY(c, hipMemsetAsync(c->lvl.p, 0, tot * mm * sizeof(uint16_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ctr.p, 0, (size_t)nc * kNumCtr * sizeof(unsigned long long), c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->off.p, c->off_host.data(), (nc + 1) * sizeof(uint64_t), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->cap.p, c->cap_host.data(), nc * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->cnt.p, counts.data(), nc * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_volume.p, c->volume.data(), nc * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_weight.p, c->weight.data(), nc * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  // tile path for cells whose capacity fits the LDS budget
+  uint32_t lcap = 0;
+  std::vector<uint32_t> small, big;
+  for (uint32_t i = 0; i < nc; ++i) {
+    if (step_lds_bytes(c->cap_host[i], mm, c->block) <= kLdsBudget) {
+      small.push_back(i);
+      lcap = std::max(lcap, c->cap_host[i]);
+    } else {
+      big.push_back(i);
+    }
+  }
+  c->lds_cap = lcap;
+  c->n_lds_cells = (uint32_t)small.size();
+  c->n_big_cells = (uint32_t)big.size();
+  if (!big.empty()) {
+    HIP_TRY(c, c->bvx.alloc(tot));
+    HIP_TRY(c, c->bvy.alloc(tot));
+    HIP_TRY(c, c->bvz.alloc(tot));
+    HIP_TRY(c, c->bsp.alloc(tot));
+    HIP_TRY(c, c->blvl.alloc(tot * mm));
+    HIP_TRY(c, c->big_cells.alloc(big.size()));
+    HIP_TRY(c, hipMemcpyAsync(c->big_cells.p, big.data(), big.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                              c->stream));
+  }
+  if (!small.empty() && !big.empty()) {
+    HIP_TRY(c, c->lds_cells.alloc(small.size()));
+    HIP_TRY(c, hipMemcpyAsync(c->lds_cells.p, small.data(), small.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return HCAO_OK;
+}
+
+hcao_status check_sticky(hcao_ctx *c) {
+  if (!c) return HCAO_EINVAL;
+  return c->sticky;
+}
+
+hcao_status read_err(hcao_ctx *c) {
+  uint32_t e = 0;
+  HIP_TRY(c, hipMemcpyAsync(&e, c->err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (e & kErrCapacity) {
+    c->sticky = HCAO_ECAPACITY;
+    return fail(c, HCAO_ECAPACITY, "a cell exceeded its slot capacity");
+  }
+  return HCAO_OK;
+}
+
+// mean vibrational energy above the zero point at temperature t (Boltzmann
+// sums over the bound stretch levels, harmonic closed form for bends)
+double mean_evib(const SpeciesHost &s, double t) {
+  double e = 0.0;
+  for (uint32_t b = 0; b < s.d.n_bend; ++b) {
+    const double th = s.theta[b];
+    e += kB * th / std::expm1(th / t);
+  }
+  for (const auto &L : s.levels) {
+    double num = 0.0, den = 0.0;
+    for (double x : L) {
+      const double d = x - L[0];
+      const double w = std::exp(-d / (kB * t));
+      num += d * w;
+      den += w;
+    }
+    e += num / den;
+  }
+  return e;
+}
+
+double solve_tvib(const SpeciesHost &s, double target) {
+  if (s.n_modes == 0 || !(target > 0.0)) return 0.0;
+  double lo = 0.0, hi = std::log(1.0e6);
+  if (mean_evib(s, std::exp(hi)) < target) return std::exp(hi);
+  for (int it = 0; it < 200 && hi - lo > 1e-15; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mean_evib(s, std::exp(mid)) < target)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return std::exp(0.5 * (lo + hi));
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *hcao_status_string(hcao_status s) {
+  switch (s) {
+    case HCAO_OK: return "ok";
+    case HCAO_EINVAL: return "invalid argument";
+    case HCAO_ESTATE: return "call out of order";
+    case HCAO_ENOMEM: return "out of memory";
+    case HCAO_EDEVICE: return "HIP runtime error";
+    case HCAO_ECAPACITY: return "cell capacity exceeded";
+    case HCAO_ELEVEL: return "invalid quantum number";
+    case HCAO_ENONFINITE: return "non-finite velocity";
+    case HCAO_EUNSUPPORTED: return "unsupported feature";
+  }
+  return "unknown status";
+}
+
+const char *hcao_last_error(const hcao_ctx *ctx) { return ctx ? ctx->last_error.c_str() : g_create_error.c_str(); }
+
+hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out) {
+  if (!cfg || !out) return HCAO_EINVAL;
+  if (cfg->abi_version != HCAO_ABI_VERSION) return HCAO_EINVAL;
+  if (cfg->n_cells == 0 || !cfg->cell_volume || !cfg->cell_weight) return HCAO_EINVAL;
+  if (cfg->precision != HCAO_FP64) return HCAO_EUNSUPPORTED;
+  for (uint32_t i = 0; i < cfg->n_cells; ++i)
+    if (!(cfg->cell_volume[i] > 0.0) || !(cfg->cell_weight[i] > 0.0) || !std::isfinite(cfg->cell_volume[i]) ||
+        !std::isfinite(cfg->cell_weight[i]))
+      return HCAO_EINVAL;
+  hcao_ctx *c = new (std::nothrow) hcao_ctx();
+  if (!c) return HCAO_ENOMEM;
+  c->cfg = *cfg;
+  c->volume.assign(cfg->cell_volume, cfg->cell_volume + cfg->n_cells);
+  c->weight.assign(cfg->cell_weight, cfg->cell_weight + cfg->n_cells);
+  c->cfg.cell_volume = nullptr;
+  c->cfg.cell_weight = nullptr;
+  c->device = cfg->device;
+  c->stream = (hipStream_t)cfg->hip_stream;
+  if (const char *b = std::getenv("HCAO_BLOCK")) {
+    const int v = std::atoi(b);
+    if (v == 64 || v == 128 || v == 256) c->block = v;
+  }
+  const char *step = "hipSetDevice";
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev0), step = "hipEventCreate";
+  if (e == hipSuccess) e = hipEventCreate(&c->ev1), step = "hipEventCreate";
+  if (e == hipSuccess) e = c->err.alloc(1), step = "hipMalloc";
+  if (e == hipSuccess) e = hipMemsetAsync(c->err.p, 0, sizeof(uint32_t), c->stream), step = "hipMemsetAsync";
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream), step = "hipStreamSynchronize";
+  if (e != hipSuccess) {
+    g_create_error = std::string(step) + ": " + hipGetErrorString(e);
+    delete c;
+    return HCAO_EDEVICE;
+  }
+  g_create_error.clear();
+  *out = c;
+  return HCAO_OK;
+}
+
+hcao_status hcao_add_species(hcao_ctx *c, const hcao_species_desc *d, int32_t *id) {
+  if (!c || !d) return HCAO_EINVAL;
+  if (c->finalized) return fail(c, HCAO_ESTATE, "add_species after finalize");
+  if (c->species.size() >= (size_t)kMaxSpecies) return fail(c, HCAO_EINVAL, "too many species");
+  if (!(d->mass_kg > 0.0) || !(d->dref_m > 0.0) || !(d->Tref_K > 0.0) || !(d->omega >= 0.5) || !(d->omega < 1.5))
+    return fail(c, HCAO_EINVAL, "bad mass or VHS parameters");
+  if (d->n_bend + d->n_stretch > (uint32_t)kMaxModes) return fail(c, HCAO_EINVAL, "too many modes");
+  if (!(d->p_vib >= 0.0) || !(d->p_vib <= 1.0)) return fail(c, HCAO_EINVAL, "p_vib outside [0,1]");
+  SpeciesHost s;
+  s.d = *d;
+  s.d.bend_theta_K = nullptr;
+  s.d.omega_e_per_m = s.d.chi_e = s.d.De_J = nullptr;
+  s.d.n_levels = nullptr;
+  s.d.levels_J = nullptr;
+  for (uint32_t j = 0; j < d->n_bend; ++j) {
+    if (!d->bend_theta_K || !(d->bend_theta_K[j] > 0.0)) return fail(c, HCAO_EINVAL, "bend needs Theta > 0");
+    s.theta.push_back(d->bend_theta_K[j]);
+  }
+  const double *lv = d->levels_J;
+  for (uint32_t j = 0; j < d->n_stretch; ++j) {
+    const uint32_t ne = d->n_levels ? d->n_levels[j] : 0;
+    std::vector<double> L;
+    double de_out = 0.0;
+    hcao_status st = build_stretch(c, d->omega_e_per_m ? d->omega_e_per_m[j] : 0.0, d->chi_e ? d->chi_e[j] : 0.0,
+                                   d->De_J ? d->De_J[j] : 0.0, ne, lv, L, de_out);
+    if (st) return st;
+    if (lv) lv += ne;
+    s.levels.push_back(L);
+    s.de.push_back(de_out);
+  }
+  s.n_modes = d->n_bend + d->n_stretch;
+  double z = 0.0;
+  for (uint32_t m = 0; m < s.n_modes; ++m) z = z + host_mode_energy(s, m, 0);
+  s.zpe = z;
+  if (d->sampler == HCAO_SAMPLER_AUTO)
+    s.sampler = s.n_modes <= 4 ? HCAO_SAMPLER_JOINT : HCAO_SAMPLER_GIBBS;
+  else if (d->sampler == HCAO_SAMPLER_JOINT || d->sampler == HCAO_SAMPLER_GIBBS)
+    s.sampler = d->sampler;
+  else
+    return fail(c, HCAO_EINVAL, "unknown sampler");
+  c->species.push_back(s);
+  c->max_modes = std::max(c->max_modes, s.n_modes);
+  if (id) *id = (int32_t)c->species.size() - 1;
+  return HCAO_OK;
+}
+
+hcao_status hcao_add_reaction(hcao_ctx *c, const hcao_reaction_desc *d, int32_t *id) {
+  if (!c || !d) return HCAO_EINVAL;
+  if (c->finalized) return fail(c, HCAO_ESTATE, "add_reaction after finalize");
+  if (c->reactions.size() >= (size_t)kMaxReactions) return fail(c, HCAO_EINVAL, "too many reactions");
+  if (d->gamma_rot != 0.0) return fail(c, HCAO_EUNSUPPORTED, "rotation coupling needs rotational modes");
+  const int ns = (int)c->species.size();
+  auto ok = [&](int s) { return s >= 0 && s < ns; };
+  ReactionHost r;
+  r.d = *d;
+  r.d.alpha = nullptr;
+  if (d->kind == HCAO_RX_DISSOCIATION) {
+    if (!ok(d->reactant[0]) || !ok(d->product[0]) || !ok(d->product[1]))
+      return fail(c, HCAO_EINVAL, "bad dissociation species");
+    const SpeciesHost &A = c->species[d->reactant[0]];
+    const uint32_t nst = A.d.n_stretch;
+    if (nst == 0 || d->stretch_mask == 0 || (nst < 64 && (d->stretch_mask >> nst) != 0))
+      return fail(c, HCAO_EINVAL, "stretch mask must name stretches of A");
+    const double msum = c->species[d->product[0]].d.mass_kg + c->species[d->product[1]].d.mass_kg;
+    if (std::fabs(msum - A.d.mass_kg) > 1e-9 * A.d.mass_kg) return fail(c, HCAO_EINVAL, "m_A != m_B + m_C");
+  } else if (d->kind == HCAO_RX_EXCHANGE) {
+    if (!ok(d->reactant[0]) || !ok(d->reactant[1]) || !ok(d->product[0]) || !ok(d->product[1]))
+      return fail(c, HCAO_EINVAL, "bad exchange species");
+    if (!(d->steric >= 0.0) || !(d->steric <= 1.0) || !(d->Ea_J >= 0.0))
+      return fail(c, HCAO_EINVAL, "steric in [0,1] and Ea >= 0 required");
+    const double m_in = c->species[d->reactant[0]].d.mass_kg + c->species[d->reactant[1]].d.mass_kg;
+    const double m_out = c->species[d->product[0]].d.mass_kg + c->species[d->product[1]].d.mass_kg;
+    if (std::fabs(m_in - m_out) > 1e-9 * m_in) return fail(c, HCAO_EINVAL, "exchange does not conserve mass");
+    const uint32_t nm = c->species[d->reactant[0]].n_modes;
+    for (uint32_t m = 0; m < nm; ++m) {
+      const double a = d->alpha ? d->alpha[m] : 0.0;
+      if (!(a >= 0.0) || !(a <= 1.0)) return fail(c, HCAO_EINVAL, "alpha outside [0,1]");
+      r.alpha.push_back(a);
+    }
+  } else if (d->kind == HCAO_RX_RECOMBINATION) {
+    return fail(c, HCAO_EUNSUPPORTED, "recombination is not available in this build");
+  } else {
+    return fail(c, HCAO_EINVAL, "unknown reaction kind");
+  }
+  c->reactions.push_back(r);
+  if (id) *id = (int32_t)c->reactions.size() - 1;
+  return HCAO_OK;
+}
+
+hcao_status hcao_finalize(hcao_ctx *c) {
+  if (!c) return HCAO_EINVAL;
+  if (c->finalized) return fail(c, HCAO_ESTATE, "finalize called twice");
+  if (c->species.empty()) return fail(c, HCAO_EINVAL, "no species");
+  Tables &T = c->tab;
+  std::memset(&T, 0, sizeof(T));
+  T.n_species = (uint32_t)c->species.size();
+  T.n_reactions = (uint32_t)c->reactions.size();
+  T.max_modes = c->max_modes;
+  c->lev_host.clear();
+  for (uint32_t s = 0; s < T.n_species; ++s) {
+    const SpeciesHost &h = c->species[s];
+    SpeciesTab &S = T.sp[s];
+    S.mass = h.d.mass_kg;
+    S.zpe = h.zpe;
+    S.formation = h.d.formation_J;
+    S.p_vib = h.d.p_vib;
+    S.n_modes = h.n_modes;
+    S.n_bend = h.d.n_bend;
+    S.sampler = (uint32_t)h.sampler;
+    for (uint32_t b = 0; b < h.d.n_bend; ++b) {
+      S.theta[b] = h.theta[b];
+      S.kt[b] = kB * h.theta[b];
+    }
+    for (uint32_t j = 0; j < h.d.n_stretch; ++j) {
+      const uint32_t m = h.d.n_bend + j;
+      S.lev_off[m] = (uint32_t)c->lev_host.size();
+      S.idiss[m] = (uint32_t)h.levels[j].size() - 1;
+      S.de[m] = h.de[j];
+      c->lev_host.insert(c->lev_host.end(), h.levels[j].begin(), h.levels[j].end());
+    }
+  }
+  T.n_levels = (uint32_t)c->lev_host.size();
+  // VHS pair constants: sigma g = C (g^2)^(1-w), C = pi d^2 (2 k T_ref / m_r)^(w-1/2) / Gamma(5/2-w),
+  // mixed-pair d, w, T_ref as species means; LB exponent 3/2 - w
+  for (uint32_t a = 0; a < T.n_species; ++a)
+    for (uint32_t b = 0; b < T.n_species; ++b) {
+      const hcao_species_desc &A = c->species[a].d, &B = c->species[b].d;
+      PairTab &P = T.pr[a][b];
+      const double msum = A.mass_kg + B.mass_kg;
+      const double mr = (A.mass_kg * B.mass_kg) / msum;
+      const double w = (A.omega + B.omega) * 0.5;
+      const double d = (A.dref_m + B.dref_m) * 0.5;
+      const double tr = (A.Tref_K + B.Tref_K) * 0.5;
+      const double base = ((2.0 * kB) * tr) / mr;
+      P.mr = mr;
+      P.hm = 0.5 * mr;
+      P.m_a = A.mass_kg;
+      P.m_b = B.mass_kg;
+      P.msum = msum;
+      P.wa = B.mass_kg / msum;
+      P.wb = A.mass_kg / msum;
+      P.csg = ((kPi * (d * d)) * std::pow(base, w - 0.5)) / std::tgamma(2.5 - w);
+      P.esg = 1.0 - w;
+      P.q = 1.5 - w;
+    }
+  for (uint32_t r = 0; r < T.n_reactions; ++r) {
+    const ReactionHost &h = c->reactions[r];
+    ReactionTab &R = T.rx[r];
+    R.kind = (int32_t)h.d.kind;
+    R.mask = h.d.stretch_mask;
+    if (h.d.kind == HCAO_RX_DISSOCIATION) {
+      const int a = h.d.reactant[0], pc = h.d.product[0], pd = h.d.product[1];
+      R.a = a;
+      R.b = -1;
+      R.c = pc;
+      R.d = pd;
+      R.dh = (c->species[pc].d.formation_J + c->species[pd].d.formation_J) - c->species[a].d.formation_J;
+      R.zsum = (c->species[a].zpe + c->species[pc].zpe) + c->species[pd].zpe;
+    } else {
+      const int a = h.d.reactant[0], b = h.d.reactant[1], pc = h.d.product[0], pd = h.d.product[1];
+      R.a = a;
+      R.b = b;
+      R.c = pc;
+      R.d = pd;
+      for (size_t m = 0; m < h.alpha.size(); ++m) R.alpha[m] = h.alpha[m];
+      R.steric = h.d.steric;
+      R.ea = h.d.Ea_J;
+      R.dh = (c->species[pc].d.formation_J + c->species[pd].d.formation_J) -
+             (c->species[a].d.formation_J + c->species[b].d.formation_J);
+    }
+  }
+  HIP_TRY(c, c->d_tab.alloc(1));
+  HIP_TRY(c, c->d_lev.alloc(c->lev_host.size()));
+  HIP_TRY(c, hipMemcpyAsync(c->d_tab.p, &T, sizeof(Tables), hipMemcpyHostToDevice, c->stream));
+  if (!c->lev_host.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->d_lev.p, c->lev_host.data(), c->lev_host.size() * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, set_step_lds_limit(kLdsBudget));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->finalized = true;
+  return HCAO_OK;
+}
+
+hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, const uint8_t *species,
+                                const double *vel, const uint16_t *levels) {
+  if (!c) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  if (!c->finalized) return fail(c, HCAO_ESTATE, "load before finalize");
+  if (n && (!cell || !species || !vel || !levels)) return fail(c, HCAO_EINVAL, "null particle array");
+  if (n > 0xFFFFFFFFull) return fail(c, HCAO_EINVAL, "too many particles");
+  const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
+  DevBuf<uint32_t> d_cell, d_count, keys_tmp, idx, idx_tmp, hist;
+  DevBuf<uint8_t> d_sp;
+  DevBuf<double> d_vel;
+  DevBuf<uint16_t> d_lvl;
+  DevBuf<uint64_t> offs, packed;
+  HIP_TRY(c, d_cell.alloc(n));
+  HIP_TRY(c, d_sp.alloc(n));
+  HIP_TRY(c, d_vel.alloc(3 * n));
+  HIP_TRY(c, d_lvl.alloc(n * mm));
+  HIP_TRY(c, d_count.alloc(nc));
+  HIP_TRY(c, hipMemsetAsync(d_count.p, 0, nc * sizeof(uint32_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->err.p, 0, sizeof(uint32_t), c->stream));
+  if (n) {
+    HIP_TRY(c, hipMemcpyAsync(d_cell.p, cell, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_sp.p, species, n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_vel.p, vel, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d_lvl.p, levels, n * mm * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(c, launch_load_check(c->d_tab.p, d_cell.p, d_sp.p, d_vel.p, d_lvl.p, n, nc, d_count.p, c->err.p,
+                               c->stream));
+  std::vector<uint32_t> counts(nc);
+  uint32_t err = 0;
+  HIP_TRY(c, hipMemcpyAsync(counts.data(), d_count.p, nc * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&err, c->err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (err & kErrInvalid) return fail(c, HCAO_EINVAL, "particle with bad cell or species");
+  if (err & kErrNonFinite) return fail(c, HCAO_ENONFINITE, "non-finite velocity");
+  if (err & kErrLevel) return fail(c, HCAO_ELEVEL, "quantum number out of range");
+  if (hcao_status s = alloc_state(c, counts)) return s;
+  // stable counting sort by cell, then placement into the padded layout
+  uint32_t key_bits = 0;
+  while (key_bits < 32 && ((uint64_t)1 << key_bits) < nc) ++key_bits;
+  key_bits = ((key_bits + 7) / 8) * 8;
+  const uint64_t tiles = sort_tiles(n);
+  HIP_TRY(c, keys_tmp.alloc(n));
+  HIP_TRY(c, idx.alloc(n));
+  HIP_TRY(c, idx_tmp.alloc(n));
+  HIP_TRY(c, hist.alloc(256 * tiles));
+  HIP_TRY(c, offs.alloc(256 * tiles));
+  HIP_TRY(c, packed.alloc(nc));
+  bool in_tmp = false;
+  HIP_TRY(c, launch_sort(d_cell.p, idx.p, keys_tmp.p, idx_tmp.p, hist.p, offs.p, n, key_bits, c->stream, in_tmp));
+  HIP_TRY(c, launch_scan_u32(c->cnt.p, packed.p, nc, c->stream));
+  const uint32_t *sk = in_tmp ? keys_tmp.p : d_cell.p;
+  const uint32_t *si = in_tmp ? idx_tmp.p : idx.p;
+  HIP_TRY(c, launch_place(c->d_tab.p, sk, si, packed.p, c->off.p, d_sp.p, d_vel.p, d_lvl.p, state_of(c), n,
+                          c->stream));
+  HIP_TRY(c, launch_cell_init(c->d_tab.p, state_of(c), cells_of(c), nc, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  d_cell.release();
+  c->step = 0;
+  c->loaded = true;
+  return HCAO_OK;
+}
+
+hcao_status hcao_init_thermal(hcao_ctx *c, const uint32_t *counts, const double *t_trans, const double *t_vib) {
+  if (!c || !counts || !t_trans || !t_vib) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  if (!c->finalized) return fail(c, HCAO_ESTATE, "init before finalize");
+  const uint32_t nc = c->cfg.n_cells, ns = (uint32_t)c->species.size();
+  std::vector<uint32_t> per(nc, 0);
+  for (uint32_t i = 0; i < nc; ++i) {
+    uint64_t s = 0;
+    for (uint32_t j = 0; j < ns; ++j) s += counts[(size_t)i * ns + j];
+    if (s > 0xFFFFFFFFull) return fail(c, HCAO_EINVAL, "cell too large");
+    per[i] = (uint32_t)s;
+    if (!(t_trans[i] >= 0.0) || !(t_vib[i] >= 0.0) || !std::isfinite(t_trans[i]) || !std::isfinite(t_vib[i]))
+      return fail(c, HCAO_EINVAL, "bad temperature");
+  }
+  if (hcao_status s = alloc_state(c, per)) return s;
+  DevBuf<uint32_t> d_counts;
+  DevBuf<double> d_tt, d_tv;
+  HIP_TRY(c, d_counts.alloc((size_t)nc * ns));
+  HIP_TRY(c, d_tt.alloc(nc));
+  HIP_TRY(c, d_tv.alloc(nc));
+  HIP_TRY(c, hipMemcpyAsync(d_counts.p, counts, (size_t)nc * ns * sizeof(uint32_t), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d_tt.p, t_trans, nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d_tv.p, t_vib, nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_init(c->d_tab.p, c->d_lev.p, state_of(c), c->off.p, d_counts.p, d_tt.p, d_tv.p, c->cfg.seed, nc,
+                         c->stream));
+  HIP_TRY(c, launch_cell_init(c->d_tab.p, state_of(c), cells_of(c), nc, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->step = 0;
+  c->loaded = true;
+  return HCAO_OK;
+}
+
+hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
+  if (!c) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "step before load");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, HCAO_EINVAL, "dt must be > 0");
+  StepArgs a{};
+  a.tab = c->d_tab.p;
+  a.lev = c->d_lev.p;
+  a.st = state_of(c);
+  a.scratch = scratch_of(c);
+  a.cells = cells_of(c);
+  a.err = c->err.p;
+  a.seed = c->cfg.seed;
+  a.dt = dt;
+  const uint32_t mm = c->max_modes ? c->max_modes : 1;
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  for (uint32_t s = 0; s < n_steps; ++s) {
+    a.step = c->step;
+    if (c->n_lds_cells) {
+      StepArgs b = a;
+      b.lds_cap = c->lds_cap;
+      b.cell_list = c->n_big_cells ? c->lds_cells.p : nullptr;
+      b.n_launch_cells = c->n_lds_cells;
+      HIP_TRY(c, launch_step(b, mm, c->block, c->n_lds_cells, c->stream));
+    }
+    if (c->n_big_cells) {
+      StepArgs b = a;
+      b.lds_cap = 0;
+      b.cell_list = c->big_cells.p;
+      b.n_launch_cells = c->n_big_cells;
+      HIP_TRY(c, launch_step(b, mm, 256, c->n_big_cells, c->stream));
+    }
+    c->step += 1;
+  }
+  if (c->timing) {
+    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->timed_ms += ms;
+    c->timed_launches += n_steps;
+  }
+  return HCAO_OK;
+}
+
+hcao_status hcao_sync(hcao_ctx *c) {
+  if (!c) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->loaded) return read_err(c);
+  return HCAO_OK;
+}
+
+hcao_status hcao_get_counts(hcao_ctx *c, uint64_t *per_cell, uint64_t *total) {
+  if (!c) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  std::vector<uint32_t> cnt(c->cfg.n_cells);
+  HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->cnt.p, cnt.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  uint64_t t = 0;
+  for (size_t i = 0; i < cnt.size(); ++i) {
+    if (per_cell) per_cell[i] = cnt[i];
+    t += cnt[i];
+  }
+  if (total) *total = t;
+  return HCAO_OK;
+}
+
+uint32_t hcao_max_modes(const hcao_ctx *c) { return c ? c->max_modes : 0; }
+uint32_t hcao_step_index(const hcao_ctx *c) { return c ? c->step : 0; }
+
+hcao_status hcao_read_particles(hcao_ctx *c, uint8_t *species, double *vel, uint16_t *levels) {
+  if (!c || !species || !vel || !levels) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  const uint64_t tot = c->total_slots;
+  const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
+  std::vector<double> vx(tot), vy(tot), vz(tot);
+  std::vector<uint8_t> sp(tot);
+  std::vector<uint16_t> lv(tot * mm);
+  std::vector<uint32_t> cnt(nc);
+  HIP_TRY(c, hipMemcpyAsync(vx.data(), c->vx.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(vy.data(), c->vy.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(vz.data(), c->vz.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(sp.data(), c->sp.p, tot, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(lv.data(), c->lvl.p, tot * mm * 2, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  uint64_t j = 0;
+  for (uint32_t cell = 0; cell < nc; ++cell) {
+    const uint64_t b = c->off_host[cell];
+    for (uint32_t i = 0; i < cnt[cell]; ++i, ++j) {
+      const uint64_t g = b + i;
+      species[j] = sp[g];
+      vel[3 * j] = vx[g];
+      vel[3 * j + 1] = vy[g];
+      vel[3 * j + 2] = vz[g];
+      for (uint32_t m = 0; m < mm; ++m) levels[j * mm + m] = lv[m * tot + g];
+    }
+  }
+  return HCAO_OK;
+}
+
+hcao_status hcao_read_cell_state(hcao_ctx *c, double *sgmax, double *rem, uint64_t *counters) {
+  if (!c) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  const uint32_t nc = c->cfg.n_cells;
+  if (sgmax) HIP_TRY(c, hipMemcpyAsync(sgmax, c->sgmax.p, nc * 8, hipMemcpyDeviceToHost, c->stream));
+  if (rem) HIP_TRY(c, hipMemcpyAsync(rem, c->rem.p, nc * 8, hipMemcpyDeviceToHost, c->stream));
+  if (counters)
+    HIP_TRY(c, hipMemcpyAsync(counters, c->ctr.p, (size_t)nc * kNumCtr * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return HCAO_OK;
+}
+
+hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments *total) {
+  if (!c) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  const uint32_t nc = c->cfg.n_cells, ns = (uint32_t)c->species.size();
+  const uint32_t w = 6 + 2 * ns;
+  DevBuf<double> d_out;
+  HIP_TRY(c, d_out.alloc((size_t)nc * w));
+  HIP_TRY(c, launch_moments(c->d_tab.p, c->d_lev.p, state_of(c), c->off.p, c->cnt.p, d_out.p, nc, c->stream));
+  std::vector<double> raw((size_t)nc * w);
+  HIP_TRY(c, hipMemcpyAsync(raw.data(), d_out.p, raw.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  auto fill = [&](hcao_moments &M, const double *r, double vol, double wgt) {
+    std::memset(&M, 0, sizeof(M));
+    for (int k = 0; k < 3; ++k) M.momentum[k] = r[k];
+    const double mass = r[4];
+    const double p2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+    M.E_kin_J = 0.5 * r[3];
+    M.E_trans_J = mass > 0.0 ? 0.5 * (r[3] - p2 / mass) : 0.0;
+    M.E_formation_J = r[5];
+    uint64_t ntot = 0;
+    for (uint32_t s = 0; s < ns; ++s) {
+      const uint64_t k = (uint64_t)std::llround(r[6 + s]);
+      M.n_species[s] = k;
+      ntot += k;
+      M.E_vib_J[s] = r[6 + ns + s];
+      if (vol > 0.0) M.number_density[s] = (double)k * wgt / vol;
+      M.T_vib_K[s] = k ? solve_tvib(c->species[s], r[6 + ns + s] / (double)k) : 0.0;
+    }
+    M.n_total = ntot;
+    M.T_trans_K = ntot ? 2.0 * M.E_trans_J / (3.0 * kB * (double)ntot) : 0.0;
+  };
+  std::vector<double> sum(w, 0.0);
+  double vol_tot = 0.0;
+  std::vector<double> dens(ns, 0.0);
+  for (uint32_t i = 0; i < nc; ++i) {
+    const double *r = raw.data() + (size_t)i * w;
+    if (per_cell) fill(per_cell[i], r, c->volume[i], c->weight[i]);
+    for (uint32_t k = 0; k < w; ++k) sum[k] += r[k];
+    vol_tot += c->volume[i];
+    for (uint32_t s = 0; s < ns; ++s) dens[s] += r[6 + s] * c->weight[i];
+  }
+  if (total) {
+    fill(*total, sum.data(), 0.0, 0.0);
+    for (uint32_t s = 0; s < ns; ++s) total->number_density[s] = dens[s] / vol_tot;
+  }
+  return HCAO_OK;
+}
+
+hcao_status hcao_read_reaction_counts(hcao_ctx *c, uint64_t *counts) {
+  if (!c || !counts) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  const uint32_t nc = c->cfg.n_cells;
+  std::vector<uint64_t> ctr((size_t)nc * kNumCtr);
+  if (hcao_status s = hcao_read_cell_state(c, nullptr, nullptr, ctr.data())) return s;
+  for (size_t r = 0; r < c->reactions.size(); ++r) {
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < nc; ++i) t += ctr[(size_t)i * kNumCtr + HCAO_CTR_REACTION0 + r];
+    counts[r] = t;
+  }
+  return HCAO_OK;
+}
+
+hcao_status hcao_get_levels(const hcao_ctx *c, uint32_t species, uint32_t mode, double *out, uint32_t max_n,
+                            uint32_t *n_out) {
+  if (!c || !out || species >= c->species.size()) return HCAO_EINVAL;
+  const SpeciesHost &s = c->species[species];
+  if (mode >= s.n_modes) return HCAO_EINVAL;
+  uint32_t n = 0;
+  if (mode < s.d.n_bend) {
+    for (; n < max_n; ++n) out[n] = host_mode_energy(s, mode, n);
+  } else {
+    const auto &L = s.levels[mode - s.d.n_bend];
+    for (; n < max_n && n < L.size(); ++n) out[n] = L[n];
+    n = (uint32_t)L.size();
+  }
+  if (n_out) *n_out = n;
+  return HCAO_OK;
+}
+
+hcao_status hcao_get_pair(const hcao_ctx *c, uint32_t a, uint32_t b, double *out8) {
+  if (!c || !out8 || !c->finalized || a >= c->species.size() || b >= c->species.size()) return HCAO_EINVAL;
+  const PairTab &P = c->tab.pr[a][b];
+  const double v[8] = {P.mr, P.hm, P.msum, P.wa, P.wb, P.csg, P.esg, P.q};
+  std::memcpy(out8, v, sizeof(v));
+  return HCAO_OK;
+}
+
+hcao_status hcao_set_timing(hcao_ctx *c, int enable) {
+  if (!c) return HCAO_EINVAL;
+  c->timing = enable != 0;
+  c->timed_ms = 0.0;
+  c->timed_launches = 0;
+  return HCAO_OK;
+}
+
+hcao_status hcao_kernel_time(hcao_ctx *c, double *ms, uint64_t *launches) {
+  if (!c) return HCAO_EINVAL;
+  if (ms) *ms = c->timed_ms;
+  if (launches) *launches = c->timed_launches;
+  return HCAO_OK;
+}
+
+hcao_status hcao_save(hcao_ctx *c, const char *path) {
+  if (!c || !path) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  if (hcao_status s = hcao_sync(c)) return s;
+  const uint64_t tot = c->total_slots;
+  const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
+  std::vector<double> vx(tot), vy(tot), vz(tot), sg(nc), rm(nc);
+  std::vector<uint8_t> sp(tot);
+  std::vector<uint16_t> lv(tot * mm);
+  std::vector<uint32_t> cnt(nc);
+  std::vector<unsigned long long> ctr((size_t)nc * kNumCtr);
+  HIP_TRY(c, hipMemcpy(vx.data(), c->vx.p, tot * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(vy.data(), c->vy.p, tot * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(vz.data(), c->vz.p, tot * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(sp.data(), c->sp.p, tot, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(lv.data(), c->lvl.p, tot * mm * 2, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(sg.data(), c->sgmax.p, nc * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(rm.data(), c->rem.p, nc * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(ctr.data(), c->ctr.p, ctr.size() * 8, hipMemcpyDeviceToHost));
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(c, HCAO_EINVAL, std::string("cannot open ") + path);
+  const uint64_t hdr[6] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step};
+  bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
+  ok = ok && std::fwrite(c->cap_host.data(), 4, nc, f) == nc;
+  ok = ok && std::fwrite(cnt.data(), 4, nc, f) == nc;
+  ok = ok && std::fwrite(sg.data(), 8, nc, f) == nc;
+  ok = ok && std::fwrite(rm.data(), 8, nc, f) == nc;
+  ok = ok && std::fwrite(ctr.data(), 8, ctr.size(), f) == ctr.size();
+  ok = ok && std::fwrite(vx.data(), 8, tot, f) == tot;
+  ok = ok && std::fwrite(vy.data(), 8, tot, f) == tot;
+  ok = ok && std::fwrite(vz.data(), 8, tot, f) == tot;
+  ok = ok && std::fwrite(sp.data(), 1, tot, f) == tot;
+  ok = ok && std::fwrite(lv.data(), 2, lv.size(), f) == lv.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, HCAO_EINVAL, "write failed");
+  return HCAO_OK;
+}
+
+hcao_status hcao_restore(hcao_ctx *c, const char *path) {
+  if (!c || !path) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  if (!c->finalized) return fail(c, HCAO_ESTATE, "restore before finalize");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(c, HCAO_EINVAL, std::string("cannot open ") + path);
+  uint64_t hdr[6];
+  const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
+  if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x48434130534156ull || hdr[1] != HCAO_ABI_VERSION ||
+      hdr[2] != nc || hdr[4] != mm) {
+    std::fclose(f);
+    return fail(c, HCAO_EINVAL, "checkpoint does not match this context");
+  }
+  const uint64_t tot = hdr[3];
+  std::vector<uint32_t> capv(nc), cnt(nc);
+  std::vector<double> sg(nc), rm(nc), vx(tot), vy(tot), vz(tot);
+  std::vector<unsigned long long> ctr((size_t)nc * kNumCtr);
+  std::vector<uint8_t> sp(tot);
+  std::vector<uint16_t> lv(tot * mm);
+  bool ok = std::fread(capv.data(), 4, nc, f) == nc;
+  ok = ok && std::fread(cnt.data(), 4, nc, f) == nc;
+  ok = ok && std::fread(sg.data(), 8, nc, f) == nc;
+  ok = ok && std::fread(rm.data(), 8, nc, f) == nc;
+  ok = ok && std::fread(ctr.data(), 8, ctr.size(), f) == ctr.size();
+  ok = ok && std::fread(vx.data(), 8, tot, f) == tot;
+  ok = ok && std::fread(vy.data(), 8, tot, f) == tot;
+  ok = ok && std::fread(vz.data(), 8, tot, f) == tot;
+  ok = ok && std::fread(sp.data(), 1, tot, f) == tot;
+  ok = ok && std::fread(lv.data(), 2, lv.size(), f) == lv.size();
+  std::fclose(f);
+  if (!ok) return fail(c, HCAO_EINVAL, "truncated checkpoint");
+  uint64_t t2 = 0;
+  for (uint32_t v : capv) t2 += v;
+  if (t2 != tot) return fail(c, HCAO_EINVAL, "checkpoint capacities inconsistent");
+  if (hcao_status st = alloc_state(c, cnt, &capv)) return st;
+  HIP_TRY(c, hipMemcpy(c->vx.p, vx.data(), tot * 8, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->vy.p, vy.data(), tot * 8, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->vz.p, vz.data(), tot * 8, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->sp.p, sp.data(), tot, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->lvl.p, lv.data(), tot * mm * 2, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->sgmax.p, sg.data(), nc * 8, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->rem.p, rm.data(), nc * 8, hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->ctr.p, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice));
+  c->step = (uint32_t)hdr[5];
+  c->loaded = true;
+  return HCAO_OK;
+}
+
+void hcao_destroy(hcao_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_state(c);
+  c->d_tab.release();
+  c->d_lev.release();
+  c->err.release();
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+}  // extern "C"

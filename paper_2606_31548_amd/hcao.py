@@ -1,0 +1,313 @@
+"""Python binding of libhcao.so (ctypes; argument marshalling only).
+
+Every operation runs in the library's HIP kernels on the GPU. The binding
+refuses to work without the built library: there is no CPU fallback.
+PyTorch is used only to hand the library a HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhcao.so")
+
+ABI_VERSION = 1
+MAX_SPECIES = 16
+MAX_MODES = 16
+MAX_REACTIONS = 32
+N_CTR = 8 + MAX_REACTIONS
+CTR_CANDIDATES, CTR_COLLISIONS, CTR_TRIALS, CTR_RELAX, CTR_CAPPED, CTR_SUPPRESSED, CTR_BIRTHS, CTR_DEATHS = range(8)
+CTR_REACTION0 = 8
+FP64, MIXED = 0, 1
+
+STATUS = {0: "HCAO_OK", -1: "HCAO_EINVAL", -2: "HCAO_ESTATE", -3: "HCAO_ENOMEM", -4: "HCAO_EDEVICE",
+          -5: "HCAO_ECAPACITY", -6: "HCAO_ELEVEL", -7: "HCAO_ENONFINITE", -8: "HCAO_EUNSUPPORTED"}
+
+_d, _u32, _u64, _i32 = ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+_vp = ctypes.c_void_p
+_pd = ctypes.POINTER(ctypes.c_double)
+
+
+class hcao_config(ctypes.Structure):
+    _fields_ = [("abi_version", _u32), ("precision", ctypes.c_int), ("seed", _u64), ("n_cells", _u32),
+                ("cell_volume", _pd), ("cell_weight", _pd), ("capacity_per_cell", _u32), ("device", ctypes.c_int),
+                ("hip_stream", _vp)]
+
+
+class hcao_species_desc(ctypes.Structure):
+    _fields_ = [("mass_kg", _d), ("dref_m", _d), ("omega", _d), ("Tref_K", _d), ("n_bend", _u32),
+                ("bend_theta_K", _pd), ("n_stretch", _u32), ("omega_e_per_m", _pd), ("chi_e", _pd), ("De_J", _pd),
+                ("n_levels", ctypes.POINTER(_u32)), ("levels_J", _pd), ("formation_J", _d), ("coupling", _d),
+                ("p_vib", _d), ("sampler", ctypes.c_int)]
+
+
+class hcao_reaction_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("reactant", _i32 * 2), ("product", _i32 * 2), ("stretch_mask", _u64),
+                ("alpha", _pd), ("steric", _d), ("Ea_J", _d), ("gamma_rot", _d), ("n_samp", _u32)]
+
+
+class hcao_moments(ctypes.Structure):
+    _fields_ = [("n_total", _u64), ("n_species", _u64 * MAX_SPECIES), ("number_density", _d * MAX_SPECIES),
+                ("momentum", _d * 3), ("E_trans_J", _d), ("E_kin_J", _d), ("E_vib_J", _d * MAX_SPECIES),
+                ("E_formation_J", _d), ("T_trans_K", _d), ("T_vib_K", _d * MAX_SPECIES)]
+
+
+class HcaoError(RuntimeError):
+    def __init__(self, call, code, msg=""):
+        super().__init__(f"{call}: {STATUS.get(code, code)} {msg}".strip())
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Loads libhcao.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(the HCAO step has no CPU fallback)")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7. If
+    # it is loaded first, the library binds to that same runtime (same
+    # soname); loading the library first and PyTorch afterwards would start a
+    # second runtime that finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    L.hcao_status_string.argtypes = [st]; L.hcao_status_string.restype = ctypes.c_char_p
+    L.hcao_last_error.argtypes = [_vp]; L.hcao_last_error.restype = ctypes.c_char_p
+    L.hcao_create.argtypes = [ctypes.POINTER(hcao_config), ctypes.POINTER(_vp)]
+    L.hcao_add_species.argtypes = [_vp, ctypes.POINTER(hcao_species_desc), ctypes.POINTER(_i32)]
+    L.hcao_add_reaction.argtypes = [_vp, ctypes.POINTER(hcao_reaction_desc), ctypes.POINTER(_i32)]
+    L.hcao_finalize.argtypes = [_vp]
+    L.hcao_load_particles.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp]
+    L.hcao_init_thermal.argtypes = [_vp, _vp, _vp, _vp]
+    L.hcao_step.argtypes = [_vp, _d, _u32]
+    L.hcao_sync.argtypes = [_vp]
+    L.hcao_get_counts.argtypes = [_vp, _vp, ctypes.POINTER(_u64)]
+    L.hcao_max_modes.argtypes = [_vp]; L.hcao_max_modes.restype = _u32
+    L.hcao_step_index.argtypes = [_vp]; L.hcao_step_index.restype = _u32
+    L.hcao_read_particles.argtypes = [_vp, _vp, _vp, _vp]
+    L.hcao_read_cell_state.argtypes = [_vp, _vp, _vp, _vp]
+    L.hcao_read_moments.argtypes = [_vp, _vp, ctypes.POINTER(hcao_moments)]
+    L.hcao_read_reaction_counts.argtypes = [_vp, _vp]
+    L.hcao_get_levels.argtypes = [_vp, _u32, _u32, _vp, _u32, ctypes.POINTER(_u32)]
+    L.hcao_get_pair.argtypes = [_vp, _u32, _u32, _vp]
+    L.hcao_set_timing.argtypes = [_vp, ctypes.c_int]
+    L.hcao_kernel_time.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(_u64)]
+    L.hcao_save.argtypes = [_vp, ctypes.c_char_p]
+    L.hcao_restore.argtypes = [_vp, ctypes.c_char_p]
+    L.hcao_destroy.argtypes = [_vp]; L.hcao_destroy.restype = None
+    for name in ("hcao_create", "hcao_add_species", "hcao_add_reaction", "hcao_finalize", "hcao_load_particles",
+                 "hcao_init_thermal", "hcao_step", "hcao_sync", "hcao_get_counts", "hcao_read_particles",
+                 "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
+                 "hcao_get_pair", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore"):
+        getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_vp)
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_pd)
+
+
+def torch_stream():
+    """The current PyTorch HIP stream handle (or None)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class Simulation:
+    """One library context: cells, species, reactions and particles on the GPU."""
+
+    def __init__(self, seed: int, n_cells: int, cell_volume, cell_weight, capacity_per_cell: int = 0,
+                 device: int = 0, stream=None, precision: int = FP64):
+        self._L = load_library()
+        self._keep = []
+        vol = np.ascontiguousarray(np.broadcast_to(np.asarray(cell_volume, np.float64), (n_cells,)))
+        wgt = np.ascontiguousarray(np.broadcast_to(np.asarray(cell_weight, np.float64), (n_cells,)))
+        self._keep += [vol, wgt]
+        if stream is None:
+            stream = torch_stream()
+        cfg = hcao_config(ABI_VERSION, precision, int(seed) & (2**64 - 1), n_cells, _dp(vol), _dp(wgt),
+                          capacity_per_cell, device, stream)
+        h = _vp()
+        self._chk("hcao_create", self._L.hcao_create(ctypes.byref(cfg), ctypes.byref(h)), handle=False)
+        self._h = h
+        self.n_cells = n_cells
+        self.n_species = 0
+        self.n_reactions = 0
+        self.max_modes = 0
+
+    # -- plumbing --
+    def _chk(self, call, rc, handle=True):
+        if rc != 0:
+            msg = ""
+            if handle and getattr(self, "_h", None):
+                msg = self._L.hcao_last_error(self._h).decode()
+            elif not handle:
+                msg = self._L.hcao_last_error(None).decode()
+            raise HcaoError(call, rc, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.hcao_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up --
+    def add_species(self, sp) -> int:
+        th = np.asarray(sp.bend_theta_K, np.float64)
+        we = np.asarray(sp.omega_e_per_m, np.float64)
+        xe = np.asarray(sp.chi_e, np.float64)
+        de = np.asarray(sp.De_J, np.float64)
+        nl = lv = None
+        if getattr(sp, "levels_J", None) is not None:
+            nl = np.asarray([len(x) for x in sp.levels_J], np.uint32)
+            lv = np.concatenate([np.asarray(x, np.float64) for x in sp.levels_J])
+        self._keep += [th, we, xe, de, nl, lv]
+        d = hcao_species_desc(sp.mass_kg, sp.dref_m, sp.omega, sp.Tref_K, len(th), _dp(th) if len(th) else None,
+                              len(we), _dp(we) if len(we) else None, _dp(xe) if len(xe) else None,
+                              _dp(de) if len(de) else None,
+                              nl.ctypes.data_as(ctypes.POINTER(_u32)) if nl is not None else None, _dp(lv),
+                              sp.formation_J, getattr(sp, "coupling", 0.0), sp.p_vib, sp.sampler)
+        i = _i32()
+        self._chk("hcao_add_species", self._L.hcao_add_species(self._h, ctypes.byref(d), ctypes.byref(i)))
+        self.n_species += 1
+        return i.value
+
+    def add_reaction(self, rx) -> int:
+        al = None if rx.alpha is None else np.asarray(rx.alpha, np.float64)
+        self._keep.append(al)
+        d = hcao_reaction_desc(rx.kind, (_i32 * 2)(*rx.reactant), (_i32 * 2)(*rx.product), int(rx.stretch_mask),
+                               _dp(al), rx.steric, rx.Ea_J, 0.0, getattr(rx, "n_samp", 0))
+        i = _i32()
+        self._chk("hcao_add_reaction", self._L.hcao_add_reaction(self._h, ctypes.byref(d), ctypes.byref(i)))
+        self.n_reactions += 1
+        return i.value
+
+    def finalize(self):
+        self._chk("hcao_finalize", self._L.hcao_finalize(self._h))
+        self.max_modes = self._L.hcao_max_modes(self._h)
+
+    # -- particles --
+    def load_particles(self, cell, species, vel, levels):
+        cell = np.ascontiguousarray(cell, np.uint32)
+        species = np.ascontiguousarray(species, np.uint8)
+        vel = np.ascontiguousarray(vel, np.float64)
+        levels = np.ascontiguousarray(levels, np.uint16)
+        self._chk("hcao_load_particles",
+                  self._L.hcao_load_particles(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels)))
+
+    def init_thermal(self, counts, t_trans, t_vib):
+        counts = np.ascontiguousarray(counts, np.uint32)
+        tt = np.ascontiguousarray(np.broadcast_to(np.asarray(t_trans, np.float64), (self.n_cells,)))
+        tv = np.ascontiguousarray(np.broadcast_to(np.asarray(t_vib, np.float64), (self.n_cells,)))
+        self._chk("hcao_init_thermal", self._L.hcao_init_thermal(self._h, _p(counts), _p(tt), _p(tv)))
+
+    def step(self, dt: float, n_steps: int = 1):
+        self._chk("hcao_step", self._L.hcao_step(self._h, float(dt), int(n_steps)))
+
+    def sync(self):
+        self._chk("hcao_sync", self._L.hcao_sync(self._h))
+
+    @property
+    def step_index(self) -> int:
+        return self._L.hcao_step_index(self._h)
+
+    def counts(self):
+        per = np.zeros(self.n_cells, np.uint64)
+        tot = _u64()
+        self._chk("hcao_get_counts", self._L.hcao_get_counts(self._h, _p(per), ctypes.byref(tot)))
+        return per, tot.value
+
+    def read_particles(self):
+        """Returns (counts per cell, species, vel[n,3], levels[n, max_modes]) in canonical order."""
+        per, tot = self.counts()
+        sp = np.zeros(tot, np.uint8)
+        v = np.zeros((tot, 3), np.float64)
+        lv = np.zeros((tot, max(self.max_modes, 1)), np.uint16)
+        self._chk("hcao_read_particles", self._L.hcao_read_particles(self._h, _p(sp), _p(v), _p(lv)))
+        return per.astype(np.int64), sp, v, lv[:, :self.max_modes]
+
+    def cell_state(self):
+        sg = np.zeros(self.n_cells, np.float64)
+        rem = np.zeros(self.n_cells, np.float64)
+        ctr = np.zeros((self.n_cells, N_CTR), np.uint64)
+        self._chk("hcao_read_cell_state", self._L.hcao_read_cell_state(self._h, _p(sg), _p(rem), _p(ctr)))
+        return sg, rem, ctr
+
+    def moments(self, per_cell: bool = False):
+        tot = hcao_moments()
+        arr = (hcao_moments * self.n_cells)() if per_cell else None
+        self._chk("hcao_read_moments", self._L.hcao_read_moments(
+            self._h, ctypes.cast(arr, _vp) if per_cell else None, ctypes.byref(tot)))
+        return (tot, list(arr)) if per_cell else tot
+
+    def reaction_counts(self):
+        out = np.zeros(max(self.n_reactions, 1), np.uint64)
+        self._chk("hcao_read_reaction_counts", self._L.hcao_read_reaction_counts(self._h, _p(out)))
+        return out[:self.n_reactions]
+
+    def levels(self, species, mode, max_n=1024):
+        out = np.zeros(max_n, np.float64)
+        n = _u32()
+        self._chk("hcao_get_levels", self._L.hcao_get_levels(self._h, species, mode, _p(out), max_n,
+                                                              ctypes.byref(n)))
+        return out[:min(n.value, max_n)]
+
+    def pair(self, a, b):
+        out = np.zeros(8, np.float64)
+        self._chk("hcao_get_pair", self._L.hcao_get_pair(self._h, a, b, _p(out)))
+        return dict(zip(("mr", "hm", "msum", "wa", "wb", "csg", "esg", "q"), out))
+
+    def set_timing(self, enable: bool):
+        self._chk("hcao_set_timing", self._L.hcao_set_timing(self._h, int(enable)))
+
+    def kernel_time(self):
+        ms = _d()
+        n = _u64()
+        self._chk("hcao_kernel_time", self._L.hcao_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def save(self, path):
+        self._chk("hcao_save", self._L.hcao_save(self._h, str(path).encode()))
+
+    def restore(self, path):
+        self._chk("hcao_restore", self._L.hcao_restore(self._h, str(path).encode()))
+
+
+def from_workload(wl, seed: Optional[int] = None, capacity_per_cell: Optional[int] = None, stream=None):
+    """Builds a Simulation with the species and reactions of a workloads.Workload."""
+    cap = wl.capacity_per_cell if capacity_per_cell is None else capacity_per_cell
+    s = Simulation(wl.seed if seed is None else seed, wl.n_cells, wl.cell_volume, wl.cell_weight, cap,
+                   stream=stream)
+    for sp in wl.species:
+        s.add_species(sp)
+    for rx in wl.reactions:
+        s.add_reaction(rx)
+    s.finalize()
+    return s

@@ -59,7 +59,8 @@ extern "C" {
 #define HCAO_CTR_TRIALS 2     /* relaxation sampler trials */
 #define HCAO_CTR_RELAX 3      /* molecule relaxations */
 #define HCAO_CTR_CAPPED 4     /* sampler stopped after 1e6 trials (levels kept) */
-#define HCAO_CTR_SUPPRESSED 5 /* NTC candidates beyond floor(N/2) (dropped) */
+#define HCAO_CTR_SUPPRESSED 5 /* NTC candidates beyond floor(N/2) (dropped), and
+                                 recombinations without third body or energy */
 #define HCAO_CTR_BIRTHS 6
 #define HCAO_CTR_DEATHS 7
 #define HCAO_CTR_REACTION0 8  /* + reaction id: reactions performed */
@@ -89,7 +90,7 @@ typedef enum { HCAO_RX_DISSOCIATION = 0, HCAO_RX_EXCHANGE = 1, HCAO_RX_RECOMBINA
  *   n_cells: number of independent reservoir cells (>= 1).
  *   cell_volume / cell_weight: per-cell V [m^3] and particle weight F_N
  *     (real molecules per simulated particle); both must be > 0.
- *   capacity_per_cell: slot capacity of every cell; 0 = N + N/2 + 32 for a
+ *   capacity_per_cell: slot capacity of every cell; 0 = N + N/4 + 32 for a
  *     cell loaded with N particles. Dissociation appends products; a cell
  *     that would exceed its capacity stops the run with HCAO_ECAPACITY.
  *   device: HIP device ordinal. hip_stream: hipStream_t or NULL. */
@@ -145,7 +146,16 @@ typedef struct {
  *   EXCHANGE: reactant = {A, B}, product = {C, D}; C takes A's slot, D B's.
  *     alpha[n_modes of A] couples each of A's modes (Eq. Ecoll-exch); steric
  *     in [0,1]; Ea_J the barrier. m_A + m_B must equal m_C + m_D.
- *   RECOMBINATION: not available in this build (HCAO_EUNSUPPORTED).
+ *   RECOMBINATION (Sec. "Recombination reactions"): reactant = {B, C}
+ *     (distinct species), product[0] = A, stretch_mask names the bond of A
+ *     whose D_e enters the forward probability; n_samp sample energies of
+ *     the Whitten-Rabinovich approximation (0 = 1000). The pair k's third
+ *     body is the particle at permutation index 2 N_cand + k (if any); the
+ *     pair recombines with probability min(1, k_b n / <sigma g>_BC) at the
+ *     cell's step-start translational temperature, k_b = k_f / K_eq with k_f
+ *     of the section's forward-rate expression (VHS means of A and the third
+ *     body) and K_eq from translational and vibrational partition sums. B
+ *     takes A's slot; C is removed. m_A must equal m_B + m_C.
  *   gamma_rot must be 0 (no rotational modes are modelled). */
 typedef struct {
   hcao_rx_kind kind;
@@ -233,6 +243,11 @@ hcao_status hcao_read_reaction_counts(hcao_ctx *ctx, uint64_t *counts);
 hcao_status hcao_get_levels(const hcao_ctx *ctx, uint32_t species, uint32_t mode, double *out, uint32_t max_n,
                             uint32_t *n_out);
 hcao_status hcao_get_pair(const hcao_ctx *ctx, uint32_t a, uint32_t b, double *out8);
+/* Recombination probability factors k_b(T) / <sigma g>_BC(T) [m^3] of one
+ * recombination reaction: n_species x 1024 values (third-body species major,
+ * temperature nodes log-spaced on [100, 5e4] K). */
+hcao_status hcao_get_recombination_table(const hcao_ctx *ctx, uint32_t reaction, double *out, uint32_t max_n,
+                                         uint32_t *n_out);
 
 /* Kernel timing over the stream: when enabled, the library records HIP
  * events around each step-kernel launch; hcao_kernel_time returns the

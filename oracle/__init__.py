@@ -57,7 +57,7 @@ def lib():
         L.orc_create.argtypes = [u64, u32, vp, vp, u32, P(vp)]
         L.orc_destroy.argtypes = [vp]; L.orc_destroy.restype = None
         L.orc_add_species.argtypes = [vp, d, d, d, d, u32, vp, u32, vp, vp, vp, vp, vp, d, d, ctypes.c_int]
-        L.orc_add_reaction.argtypes = [vp, ctypes.c_int, vp, vp, u64, vp, d, d]
+        L.orc_add_reaction.argtypes = [vp, ctypes.c_int, vp, vp, u64, vp, d, d, u32]
         L.orc_finalize.argtypes = [vp]
         L.orc_load.argtypes = [vp, u64, vp, vp, vp, vp]
         L.orc_init_thermal.argtypes = [vp, vp, vp, vp]
@@ -75,6 +75,14 @@ def lib():
         L.orc_relax_batch.argtypes = [vp, u32, d, ctypes.c_int, u32, vp, vp, vp, vp, vp]
         L.orc_relax_chain.argtypes = [vp, u32, d, ctypes.c_int, u32, u32, vp, vp, vp, u32]
         L.orc_collide_batch.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_collide3_batch.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d]
+        L.orc_collide3_batch.restype = ctypes.c_int
+        L.orc_gamma_q.argtypes = [d, d]; L.orc_gamma_q.restype = d
+        L.orc_wr_rho.argtypes = [vp, u32, d]; L.orc_wr_rho.restype = d
+        L.orc_wr_probability.argtypes = [vp, u32, d, d, u32, d]; L.orc_wr_probability.restype = d
+        L.orc_q_vib.argtypes = [vp, u32, d]; L.orc_q_vib.restype = d
+        L.orc_rec_factor.argtypes = [vp, u32, u32, d]; L.orc_rec_factor.restype = d
+        L.orc_rec_table.argtypes = [vp, u32, vp]; L.orc_rec_table.restype = ctypes.c_int
         for name in ("orc_create", "orc_add_species", "orc_add_reaction", "orc_finalize", "orc_load",
                      "orc_init_thermal", "orc_step", "orc_read_cell", "orc_read_cell_state", "orc_levels",
                      "orc_species_info", "orc_pair_info", "orc_moments", "orc_tvib", "orc_relax_batch",
@@ -119,6 +127,10 @@ def detexp(x):
 
 def detpow(x, y):
     return lib().orc_detpow(float(x), float(y))
+
+
+def gamma_q(a, x):
+    return lib().orc_gamma_q(float(a), float(x))
 
 
 def feistel_index(n, keys, i):
@@ -187,7 +199,7 @@ class Oracle:
         p = np.asarray(rx.product, np.int32)
         al = None if rx.alpha is None else np.asarray(rx.alpha, np.float64)
         _chk("orc_add_reaction", lib().orc_add_reaction(self._h, rx.kind, _p(r), _p(p), int(rx.stretch_mask),
-                                                        _p(al), rx.steric, rx.Ea_J))
+                                                        _p(al), rx.steric, rx.Ea_J, int(getattr(rx, "n_samp", 0))))
         self.n_reactions += 1
         return self.n_reactions - 1
 
@@ -293,6 +305,43 @@ class Oracle:
         _chk("orc_relax_chain", lib().orc_relax_chain(self._h, species, float(q), int(sampler), int(chain),
                                                       len(e_tr), _p(e_tr), _p(state), _p(hist), hist_stride))
         return hist, state
+
+    def wr_rho(self, species, e):
+        return lib().orc_wr_rho(self._h, species, float(e))
+
+    def wr_probability(self, species, de, omega, n_samp, t):
+        return lib().orc_wr_probability(self._h, species, float(de), float(omega), int(n_samp), float(t))
+
+    def q_vib(self, species, t):
+        return lib().orc_q_vib(self._h, species, float(t))
+
+    def rec_factor(self, reaction, third, t):
+        return lib().orc_rec_factor(self._h, reaction, third, float(t))
+
+    def rec_table(self, reaction):
+        out = np.zeros(self.n_species * 1024, np.float64)
+        _chk("orc_rec_table", lib().orc_rec_table(self._h, reaction, _p(out)))
+        return out.reshape(self.n_species, 1024)
+
+    def collide3_batch(self, sp, vel, lvl, m_sp, m_vel, t_cell, n_cell):
+        """collide_batch with a third body per item (recombination)."""
+        sp = np.ascontiguousarray(sp, np.uint8)
+        n = len(sp) // 2
+        vel = np.ascontiguousarray(vel, np.float64)
+        lvl = np.ascontiguousarray(lvl, np.uint16)
+        m_sp = np.ascontiguousarray(m_sp, np.uint8)
+        m_vel = np.ascontiguousarray(m_vel, np.float64).copy()
+        sp_o = np.zeros_like(sp)
+        vel_o = np.zeros_like(vel)
+        lvl_o = np.zeros_like(lvl)
+        rx = np.zeros(n, np.int32)
+        bsp = np.zeros(n, np.uint8)
+        bvel = np.zeros((n, 3), np.float64)
+        blvl = np.zeros((n, self.max_modes), np.uint16)
+        _chk("orc_collide3_batch", lib().orc_collide3_batch(
+            self._h, n, _p(sp), _p(vel), _p(lvl), _p(sp_o), _p(vel_o), _p(lvl_o), _p(rx), _p(bsp), _p(bvel),
+            _p(blvl), _p(m_sp), _p(m_vel), float(t_cell), float(n_cell)))
+        return sp_o, vel_o, lvl_o, rx, m_vel
 
     def collide_batch(self, sp, vel, lvl):
         sp = np.ascontiguousarray(sp, np.uint8)

@@ -261,14 +261,20 @@ typedef struct {
   double mr, hm, m_a, m_b, msum, wa, wb, csg, esg, q;
 } pair_t;
 
+#define REC_NT 1024
+#define REC_TMIN 100.0
+#define REC_TMAX 5.0e4
+
 typedef struct {
   int kind;
-  int a, b, c, d; /* diss: a -> c + d (b = -1); exch: a + b -> c + d */
+  int a, b, c, d; /* diss: a -> c + d (b = -1); exch: a + b -> c + d; recomb: a + b -> c (d = -1) */
   uint64_t mask;
   double alpha[ORC_MAX_MODES];
   double steric, ea;
   double dh;   /* sum of formation energies of products minus reactants */
   double zsum; /* dissociation: ZPE_A + ZPE_B + ZPE_C */
+  uint32_t n_samp;
+  double *rec; /* recombination: [third-body species][REC_NT] k_b / <sigma g>_BC  [m^3] */
 } reaction_t;
 
 typedef struct {
@@ -283,7 +289,8 @@ typedef struct {
 struct orc_ctx {
   uint64_t seed;
   uint32_t n_cells, cap_default, step, finalized, loaded;
-  uint32_t n_species, n_reactions, max_modes;
+  uint32_t n_species, n_reactions, max_modes, has_recomb;
+  double rec_l0, rec_inv_step; /* log(REC_TMIN), (REC_NT - 1) / log(REC_TMAX / REC_TMIN) */
   species_t sp[ORC_MAX_SPECIES];
   reaction_t rx[ORC_MAX_REACTIONS];
   pair_t pr[ORC_MAX_SPECIES][ORC_MAX_SPECIES];
@@ -343,6 +350,7 @@ static void free_cell(cell_t *c) {
 
 void orc_destroy(orc_ctx *o) {
   if (!o) return;
+  for (uint32_t r = 0; r < o->n_reactions; ++r) free(o->rx[r].rec);
   for (uint32_t s = 0; s < o->n_species; ++s)
     for (uint32_t m = 0; m < ORC_MAX_MODES; ++m) free(o->sp[s].lev[m]);
   if (o->cells)
@@ -459,7 +467,7 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
 }
 
 int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int32_t product[2],
-                     uint64_t stretch_mask, const double *alpha, double steric, double ea) {
+                     uint64_t stretch_mask, const double *alpha, double steric, double ea, uint32_t n_samp) {
   if (!o || o->finalized) return E_STATE;
   if (o->n_reactions >= ORC_MAX_REACTIONS) return E_INVAL;
   int ns = (int)o->n_species;
@@ -499,8 +507,25 @@ int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int3
     r->steric = steric;
     r->ea = ea;
     r->dh = (o->sp[c].formation + o->sp[d].formation) - (o->sp[a].formation + o->sp[b].formation);
+  } else if (kind == ORC_RX_RECOMBINATION) {
+    /* B + C (+M) -> A (+M): reactant = {B, C}, product[0] = A; stretch_mask names
+     * the bond(s) of A whose dissociation this reverses (D_e of the first one) */
+    int b = reactant[0], c = reactant[1], a = product[0];
+    if (a < 0 || a >= ns || b < 0 || b >= ns || c < 0 || c >= ns || b == c) return E_INVAL;
+    const species_t *A = &o->sp[a];
+    if (A->n_stretch == 0 || stretch_mask == 0 || (A->n_stretch < 64 && (stretch_mask >> A->n_stretch) != 0))
+      return E_INVAL;
+    double msum = o->sp[b].mass + o->sp[c].mass;
+    if (fabs(msum - A->mass) > 1e-9 * A->mass) return E_INVAL;
+    r->a = b;
+    r->b = c;
+    r->c = a;
+    r->d = -1;
+    r->mask = stretch_mask;
+    r->dh = A->formation - (o->sp[b].formation + o->sp[c].formation);
+    r->n_samp = n_samp ? n_samp : 1000;
   } else {
-    return E_INVAL; /* recombination: see the recombination tables (not in this build of the oracle) */
+    return E_INVAL;
   }
   o->n_reactions += 1;
   return E_OK;
@@ -530,13 +555,186 @@ static void build_pair(orc_ctx *o, uint32_t a, uint32_t b) {
   p->q = 1.5 - w;
 }
 
+/* ------------------------------------------------------------------ */
+/* Recombination rate tables (Sec. "Recombination reactions")            */
+/* ------------------------------------------------------------------ */
+
+/* Regularized upper incomplete gamma Q(a, x), x > 0: series for x < a + 1,
+ * Lentz continued fraction otherwise (Press et al., Numerical Recipes 6.2). */
+static double gamma_q(double a, double x) {
+  if (!(x > 0.0)) return 1.0;
+  double lpre = -x + a * log(x) - lgamma(a);
+  if (x < a + 1.0) {
+    double ap = a, del = 1.0 / a, sum = del;
+    for (int n = 1; n <= 1000; ++n) {
+      ap = ap + 1.0;
+      del = del * (x / ap);
+      sum = sum + del;
+      if (fabs(del) < fabs(sum) * 1e-17) break;
+    }
+    return 1.0 - sum * exp(lpre);
+  }
+  const double tiny = 1e-300;
+  double bb = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / bb, h = d;
+  for (int i = 1; i <= 1000; ++i) {
+    double an = -(double)i * ((double)i - a);
+    bb = bb + 2.0;
+    d = an * d + bb;
+    if (fabs(d) < tiny) d = tiny;
+    c = bb + an / c;
+    if (fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    double del = d * c;
+    h = h * del;
+    if (fabs(del - 1.0) < 1e-17) break;
+  }
+  return exp(lpre) * h;
+}
+
+/* vibrational partition sum of a species, energies from its ground state */
+static double q_vib(const species_t *s, double t) {
+  double q = 1.0;
+  for (uint32_t m = 0; m < s->n_bend; ++m) q = q * (1.0 / (1.0 - exp(-s->theta[m] / t)));
+  for (uint32_t m = s->n_bend; m < s->n_modes; ++m) {
+    double z = 0.0;
+    for (uint32_t i = 0; i <= s->idiss[m]; ++i) z = z + exp(-(s->lev[m][i] - s->lev[m][0]) / (K_BOLTZ * t));
+    q = q * z;
+  }
+  return q;
+}
+
+/* forward probability P(T) of the recombination section with the
+ * Whitten-Rabinovich density of states at n_samp evenly spaced energies */
+static double wr_probability(const species_t *A, double de, double omega, uint32_t n_samp, double t) {
+  uint32_t l = A->n_modes;
+  double nu_sum = 0.0, nu2_sum = 0.0;
+  for (uint32_t m = 0; m < l; ++m) {
+    double nu = (m < A->n_bend) ? (K_BOLTZ * A->theta[m]) / H_PLANCK : (A->lev[m][1] - A->lev[m][0]) / H_PLANCK;
+    nu_sum = nu_sum + nu;
+    nu2_sum = nu2_sum + nu * nu;
+  }
+  double ez = 0.5 * H_PLANCK * nu_sum;
+  double lm1 = (double)l - 1.0;
+  double beta = (lm1 * lm1 * nu2_sum) / ((double)l * (nu_sum * nu_sum));
+  double num = 0.0, den = 0.0;
+  for (uint32_t i = 1; i <= n_samp; ++i) {
+    double e = (double)(i - 1) * de / (double)(n_samp - 1);
+    double r = e / ez;
+    double omg = (r >= 1.0) ? pow(10.0, -1.0506 * pow(r, 0.25)) : 1.0 / (5.0 * r + 2.73 * sqrt(r) + 3.51);
+    double aw = 1.0 - beta * omg;
+    double rho = pow(e + aw * ez, lm1);
+    double w = rho * exp(-e / (K_BOLTZ * t));
+    num = num + gamma_q(2.5 - omega, (de - e) / (K_BOLTZ * t)) * w;
+    den = den + w;
+  }
+  return den > 0.0 ? num / den : 0.0;
+}
+
+static int build_recombination(orc_ctx *o, reaction_t *R) {
+  const species_t *B = &o->sp[R->a], *C = &o->sp[R->b], *A = &o->sp[R->c];
+  uint32_t j = 0;
+  while (!((R->mask >> j) & 1ULL)) ++j;
+  double de = A->de[A->n_bend + j];
+  double de0 = ((B->formation + B->zpe) + (C->formation + C->zpe)) - (A->formation + A->zpe);
+  const pair_t *pbc = &o->pr[R->a][R->b];
+  double w_bc = 1.0 - pbc->esg;
+  double d_bc = (B->dref + C->dref) * 0.5, t_bc = (B->tref + C->tref) * 0.5;
+  R->rec = (double *)calloc((size_t)o->n_species * REC_NT, sizeof(double));
+  if (!R->rec) return E_NOMEM;
+  for (uint32_t i = 0; i < REC_NT; ++i) {
+    double t = exp(o->rec_l0 + (double)i / o->rec_inv_step);
+    double sg_bc = 2.0 * (d_bc * d_bc) * sqrt((2.0 * PI_D * K_BOLTZ * t_bc) / pbc->mr) * pow(t / t_bc, 1.0 - w_bc);
+    double ktr = (2.0 * PI_D * K_BOLTZ * t) / (H_PLANCK * H_PLANCK);
+    double keq = pow(ktr, 1.5) * pow((B->mass * C->mass) / A->mass, 1.5) * ((q_vib(B, t) * q_vib(C, t)) / q_vib(A, t)) *
+                 exp(-de0 / (K_BOLTZ * t));
+    double p_w = -1.0, p = 0.0; /* P depends on the third body only through omega */
+    for (uint32_t m = 0; m < o->n_species; ++m) {
+      const species_t *M = &o->sp[m];
+      double w = (A->omega + M->omega) * 0.5, d = (A->dref + M->dref) * 0.5, tr = (A->tref + M->tref) * 0.5;
+      double mred = (A->mass * M->mass) / (A->mass + M->mass);
+      double delta = ((uint32_t)R->c == m) ? 2.0 : 1.0;
+      if (w != p_w) {
+        p = wr_probability(A, de, w, R->n_samp, t);
+        p_w = w;
+      }
+      double kf = p * ((2.0 * (d * d)) / delta) * sqrt((2.0 * PI_D * K_BOLTZ * tr) / mred) * pow(t / tr, 1.0 - w);
+      double v = (kf / keq) / sg_bc;
+      R->rec[(size_t)m * REC_NT + i] = (v == v && v >= 0.0) ? v : 0.0;
+    }
+  }
+  return E_OK;
+}
+
 int orc_finalize(orc_ctx *o) {
   if (!o || o->finalized) return E_STATE;
   if (o->n_species == 0) return E_INVAL;
   for (uint32_t a = 0; a < o->n_species; ++a)
     for (uint32_t b = 0; b < o->n_species; ++b) build_pair(o, a, b);
+  o->rec_l0 = log(REC_TMIN);
+  o->rec_inv_step = (double)(REC_NT - 1) / log(REC_TMAX / REC_TMIN);
+  for (uint32_t r = 0; r < o->n_reactions; ++r) {
+    if (o->rx[r].kind != ORC_RX_RECOMBINATION) continue;
+    o->has_recomb = 1;
+    int rc = build_recombination(o, &o->rx[r]);
+    if (rc) return rc;
+  }
   o->finalized = 1;
   return E_OK;
+}
+
+double orc_gamma_q(double a, double x) { return gamma_q(a, x); }
+
+/* normalised Whitten-Rabinovich density of states of species s at energy e
+ * above its ground state: [e + a(e) E_z]^(l-1) / ((l-1)! prod h nu_k) */
+double orc_wr_rho(const orc_ctx *o, uint32_t species, double e) {
+  const species_t *A = &o->sp[species];
+  uint32_t l = A->n_modes;
+  double nu_sum = 0.0, nu2_sum = 0.0, prod = 1.0;
+  for (uint32_t m = 0; m < l; ++m) {
+    double nu = (m < A->n_bend) ? (K_BOLTZ * A->theta[m]) / H_PLANCK : (A->lev[m][1] - A->lev[m][0]) / H_PLANCK;
+    nu_sum = nu_sum + nu;
+    nu2_sum = nu2_sum + nu * nu;
+    prod = prod * (H_PLANCK * nu);
+  }
+  double ez = 0.5 * H_PLANCK * nu_sum;
+  double lm1 = (double)l - 1.0;
+  double beta = (lm1 * lm1 * nu2_sum) / ((double)l * (nu_sum * nu_sum));
+  double r = e / ez;
+  double omg = (r >= 1.0) ? pow(10.0, -1.0506 * pow(r, 0.25)) : 1.0 / (5.0 * r + 2.73 * sqrt(r) + 3.51);
+  double aw = 1.0 - beta * omg;
+  return pow(e + aw * ez, lm1) / (tgamma((double)l) * prod);
+}
+
+double orc_wr_probability(const orc_ctx *o, uint32_t species, double de, double omega, uint32_t n_samp, double t) {
+  return wr_probability(&o->sp[species], de, omega, n_samp, t);
+}
+
+double orc_q_vib(const orc_ctx *o, uint32_t species, double t) { return q_vib(&o->sp[species], t); }
+
+/* per-collision recombination probability factor at the cell temperature,
+ * linear in log T between table nodes */
+static double rec_lookup(const orc_ctx *o, const reaction_t *R, uint32_t m, double t) {
+  const double *tab = R->rec + (size_t)m * REC_NT;
+  if (!(t > 0.0)) return tab[0];
+  double u = (orc_detlog(t) - o->rec_l0) * o->rec_inv_step;
+  if (!(u > 0.0)) return tab[0];
+  if (!(u < (double)(REC_NT - 1))) return tab[REC_NT - 1];
+  double fi = floor(u);
+  uint32_t i = (uint32_t)fi;
+  double f = u - fi;
+  return tab[i] + f * (tab[i + 1] - tab[i]);
+}
+
+double orc_rec_factor(const orc_ctx *o, uint32_t reaction, uint32_t third, double t) {
+  if (!o || reaction >= o->n_reactions || o->rx[reaction].kind != ORC_RX_RECOMBINATION || third >= o->n_species)
+    return -1.0;
+  return rec_lookup(o, &o->rx[reaction], third, t);
+}
+
+int orc_rec_table(const orc_ctx *o, uint32_t reaction, double *out) {
+  if (!o || reaction >= o->n_reactions || o->rx[reaction].kind != ORC_RX_RECOMBINATION) return E_INVAL;
+  memcpy(out, o->rx[reaction].rec, sizeof(double) * o->n_species * REC_NT);
+  return REC_NT;
 }
 
 /* ------------------------------------------------------------------ */
@@ -558,7 +756,7 @@ static int alloc_cell(orc_ctx *o, cell_t *c, uint32_t cap) {
 
 static uint32_t default_capacity(const orc_ctx *o, uint32_t n) {
   if (o->cap_default) return o->cap_default;
-  return n + n / 2 + 32;
+  return n + n / 4 + 32;
 }
 
 /* initial (sigma g)_max: an upper bound of sigma g over the cell's pairs,
@@ -867,6 +1065,11 @@ typedef struct {
   double v[2][3];
   uint8_t sp[2];
   uint16_t lvl[2][ORC_MAX_MODES];
+  int dead[2];
+  int has_m;   /* a third body is available for recombination */
+  uint8_t sp_m;
+  double v_m[3];
+  double t_cell, n_cell;
 } pair_state;
 
 typedef struct {
@@ -891,6 +1094,59 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
   double evib[2];
   for (int x = 0; x < 2; ++x) evib[x] = vib_energy(&o->sp[ps->sp[x]], ps->lvl[x]);
   nb->born = 0;
+
+  /* --- recombination first: B + C (+M) -> A (+M) --- */
+  for (uint32_t r = 0; r < o->n_reactions; ++r) {
+    const reaction_t *R = &o->rx[r];
+    if (R->kind != ORC_RX_RECOMBINATION) continue;
+    int side_b;
+    if (ps->sp[0] == R->a && ps->sp[1] == R->b)
+      side_b = 0;
+    else if (ps->sp[1] == R->a && ps->sp[0] == R->b)
+      side_b = 1;
+    else
+      continue;
+    double u = uniform(st);
+    if (!ps->has_m) {
+      if (ctr) ctr[ORC_CTR_SUPPRESSED] += 1;
+      continue;
+    }
+    double prob = rec_lookup(o, R, ps->sp_m, ps->t_cell) * ps->n_cell;
+    if (prob > 1.0) prob = 1.0;
+    if (!(u < prob)) continue;
+    int b = side_b, c = 1 - side_b;
+    const species_t *A = &o->sp[R->c];
+    const pair_t *pbc = &o->pr[R->a][R->b];
+    double vbc[3];
+    com(pbc, ps->v[b], ps->v[c], vbc);
+    double gx = vbc[0] - ps->v_m[0], gy = vbc[1] - ps->v_m[1], gz = vbc[2] - ps->v_m[2];
+    const pair_t *pam = &o->pr[R->c][ps->sp_m];
+    double e_am = pam->hm * ((gx * gx + gy * gy) + gz * gz);
+    double pool = (((e_am + e_tr) + evib[b]) + evib[c]) - R->dh;
+    double et = pool - A->zpe;
+    if (!(et > 0.0)) {
+      if (ctr) ctr[ORC_CTR_SUPPRESSED] += 1;
+      continue;
+    }
+    uint16_t la[ORC_MAX_MODES] = {0};
+    int capped = 0;
+    uint64_t t = relax(o, A, la, &et, pam->q, st, &capped);
+    double vcm[3], va[3], vm[3];
+    com(pam, vbc, ps->v_m, vcm);
+    split(pam, vcm, et, st, va, vm);
+    memcpy(ps->v[b], va, sizeof(va));
+    memcpy(ps->v_m, vm, sizeof(vm));
+    ps->sp[b] = (uint8_t)R->c;
+    memcpy(ps->lvl[b], la, sizeof(la));
+    ps->dead[c] = 1;
+    if (ctr) {
+      ctr[ORC_CTR_TRIALS] += t;
+      ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
+      ctr[ORC_CTR_DEATHS] += 1;
+      ctr[ORC_CTR_REACTION0 + r] += 1;
+    }
+    return (int)r;
+  }
 
   /* --- reaction decision: dissociation then exchange channels, canonical order --- */
   channel ch[MAX_CHANNELS];
@@ -1091,9 +1347,42 @@ static void store_pair(cell_t *C, uint32_t mm, uint32_t p, uint32_t q, const pai
     C->vx[i] = ps->v[x][0];
     C->vy[i] = ps->v[x][1];
     C->vz[i] = ps->v[x][2];
-    C->sp[i] = ps->sp[x];
+    C->sp[i] = ps->dead[x] ? (uint8_t)255 : ps->sp[x];
     for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)i * mm + m] = ps->lvl[x][m];
   }
+}
+
+/* Translational temperature of a cell at step start. The sums of m, m v and
+ * m |v|^2 run over blocks of 64 particles in slot order; each block is
+ * reduced by a halving tree (element t takes element t + s for s = 32, 16,
+ * ..., 1), and block results are added left to right. */
+static double cell_temperature(const orc_ctx *o, const cell_t *C) {
+  uint32_t n = C->n;
+  if (n < 2) return 0.0;
+  double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (uint32_t b0 = 0; b0 < n; b0 += 64) {
+    double x[5][64];
+    for (int t = 0; t < 64; ++t) {
+      uint32_t i = b0 + (uint32_t)t;
+      if (i < n) {
+        double m = o->sp[C->sp[i]].mass;
+        double vx = C->vx[i], vy = C->vy[i], vz = C->vz[i];
+        x[0][t] = m;
+        x[1][t] = m * vx;
+        x[2][t] = m * vy;
+        x[3][t] = m * vz;
+        x[4][t] = m * ((vx * vx + vy * vy) + vz * vz);
+      } else {
+        for (int q = 0; q < 5; ++q) x[q][t] = 0.0;
+      }
+    }
+    for (int sft = 32; sft >= 1; sft >>= 1)
+      for (int t = 0; t < sft; ++t)
+        for (int q = 0; q < 5; ++q) x[q][t] = x[q][t] + x[q][t + sft];
+    for (int q = 0; q < 5; ++q) tot[q] = tot[q] + x[q][0];
+  }
+  double p2 = (tot[1] * tot[1] + tot[2] * tot[2]) + tot[3] * tot[3];
+  return (tot[4] - p2 / tot[0]) / (3.0 * K_BOLTZ * (double)n);
 }
 
 static int step_cell(orc_ctx *o, uint32_t c, double dt) {
@@ -1120,6 +1409,8 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     nb = (newborn *)calloc(ncand, sizeof(newborn));
     if (!nb) return E_NOMEM;
   }
+  double t_cell = o->has_recomb ? cell_temperature(o, C) : 0.0;
+  double n_cell = (double)n * C->weight / C->volume;
   double sg_seen = 0.0;
   for (uint32_t k = 0; k < ncand; ++k) {
     uint32_t p = orc_feistel_index(n, keys, 2 * k);
@@ -1137,13 +1428,43 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     C->ctr[ORC_CTR_COLLISIONS] += 1;
     pair_state ps;
     load_pair(C, mm, p, q, &ps);
+    /* third body of pair k: the particle at permutation index 2 N_cand + k */
+    uint32_t mslot = 0;
+    if (2 * ncand + k < n) {
+      mslot = orc_feistel_index(n, keys, (uint32_t)(2 * ncand + k));
+      ps.has_m = 1;
+      ps.sp_m = C->sp[mslot];
+      ps.v_m[0] = C->vx[mslot];
+      ps.v_m[1] = C->vy[mslot];
+      ps.v_m[2] = C->vz[mslot];
+    }
+    ps.t_cell = t_cell;
+    ps.n_cell = n_cell;
     collide(o, &ps, g2, &st, C->ctr, &nb[k]);
     store_pair(C, mm, p, q, &ps);
+    if (ps.has_m) {
+      C->vx[mslot] = ps.v_m[0];
+      C->vy[mslot] = ps.v_m[1];
+      C->vz[mslot] = ps.v_m[2];
+    }
   }
-  /* births appended in pair order */
+  /* deaths removed (survivors keep their order), births appended in pair order */
+  uint32_t alive = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (C->sp[i] == 255) continue;
+    if (alive != i) {
+      C->vx[alive] = C->vx[i];
+      C->vy[alive] = C->vy[i];
+      C->vz[alive] = C->vz[i];
+      C->sp[alive] = C->sp[i];
+      for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)alive * mm + m] = C->lvl[(size_t)i * mm + m];
+    }
+    ++alive;
+  }
+  C->n = alive;
   uint32_t births = 0;
   for (uint32_t k = 0; k < ncand; ++k) births += (uint32_t)nb[k].born;
-  if (n + births > C->cap) {
+  if (alive + births > C->cap) {
     free(nb);
     return E_CAPACITY;
   }
@@ -1364,9 +1685,33 @@ int orc_relax_chain(orc_ctx *o, uint32_t species, double q, int sampler, uint32_
  * draw); item i uses stream (pair = i, cell = 0xFFFFFFF2, step = current).
  * Arrays: sp[2n], vel[6n], lvl[2n x max_modes]; outputs likewise; born_*
  * receive the newborn of item i (born_sp = 255 when none). */
+static int collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
+                         uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
+                         uint8_t *born_sp, double *born_vel, uint16_t *born_lvl, const uint8_t *m_sp, double *m_vel,
+                         double t_cell, double n_cell);
+
 int orc_collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
                       uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
                       uint8_t *born_sp, double *born_vel, uint16_t *born_lvl) {
+  return collide_batch(o, n, sp, vel, lvl, sp_out, vel_out, lvl_out, reaction_out, born_sp, born_vel, born_lvl, NULL,
+                       NULL, 0.0, 0.0);
+}
+
+/* as orc_collide_batch, with a third body per item (m_sp[n], m_vel[3n] in and
+ * out) at cell temperature t_cell and number density n_cell; a recombined
+ * item reports species 255 on its vanished side */
+int orc_collide3_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
+                       uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
+                       uint8_t *born_sp, double *born_vel, uint16_t *born_lvl, const uint8_t *m_sp, double *m_vel,
+                       double t_cell, double n_cell) {
+  return collide_batch(o, n, sp, vel, lvl, sp_out, vel_out, lvl_out, reaction_out, born_sp, born_vel, born_lvl, m_sp,
+                       m_vel, t_cell, n_cell);
+}
+
+static int collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
+                         uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
+                         uint8_t *born_sp, double *born_vel, uint16_t *born_lvl, const uint8_t *m_sp, double *m_vel,
+                         double t_cell, double n_cell) {
   if (!o || !o->finalized) return E_INVAL;
   uint32_t mm = o->max_modes;
   for (uint32_t i = 0; i < n; ++i) {
@@ -1378,6 +1723,13 @@ int orc_collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *v
       for (int k = 0; k < 3; ++k) ps.v[x][k] = vel[6 * i + 3 * x + k];
       for (uint32_t m = 0; m < mm; ++m) ps.lvl[x][m] = lvl[((size_t)2 * i + x) * mm + m];
     }
+    if (m_sp) {
+      ps.has_m = 1;
+      ps.sp_m = m_sp[i];
+      for (int k = 0; k < 3; ++k) ps.v_m[k] = m_vel[3 * i + k];
+      ps.t_cell = t_cell;
+      ps.n_cell = n_cell;
+    }
     double dx = ps.v[0][0] - ps.v[1][0], dy = ps.v[0][1] - ps.v[1][1], dz = ps.v[0][2] - ps.v[1][2];
     double g2 = (dx * dx + dy * dy) + dz * dz;
     stream st;
@@ -1385,8 +1737,10 @@ int orc_collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *v
     newborn nb;
     memset(&nb, 0, sizeof(nb));
     reaction_out[i] = collide(o, &ps, g2, &st, NULL, &nb);
+    if (m_sp)
+      for (int k = 0; k < 3; ++k) m_vel[3 * i + k] = ps.v_m[k];
     for (int x = 0; x < 2; ++x) {
-      sp_out[2 * i + x] = ps.sp[x];
+      sp_out[2 * i + x] = ps.dead[x] ? (uint8_t)255 : ps.sp[x];
       for (int k = 0; k < 3; ++k) vel_out[6 * i + 3 * x + k] = ps.v[x][k];
       for (uint32_t m = 0; m < mm; ++m) lvl_out[((size_t)2 * i + x) * mm + m] = ps.lvl[x][m];
     }

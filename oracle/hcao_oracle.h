@@ -30,7 +30,7 @@ enum {
   ORC_CTR_TRIALS = 2,     /* relaxation sampler trials */
   ORC_CTR_RELAX = 3,      /* relaxations performed */
   ORC_CTR_CAPPED = 4,     /* sampler gave up after ORC_MAX_TRIALS */
-  ORC_CTR_SUPPRESSED = 5, /* NTC excess over floor(N/2), suppressed recombinations */
+  ORC_CTR_SUPPRESSED = 5, /* NTC excess over floor(N/2); recombinations without third body or energy */
   ORC_CTR_BIRTHS = 6,
   ORC_CTR_DEATHS = 7,
   ORC_CTR_REACTION0 = 8,  /* + reaction id */
@@ -58,7 +58,7 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
                     const double *chi_e, const double *de, const uint32_t *n_levels,
                     const double *levels, double formation, double p_vib, int sampler);
 int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int32_t product[2],
-                     uint64_t stretch_mask, const double *alpha, double steric, double ea);
+                     uint64_t stretch_mask, const double *alpha, double steric, double ea, uint32_t n_samp);
 int orc_finalize(orc_ctx *o);
 int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *species, const double *vel,
              const uint16_t *levels);
@@ -88,4 +88,15 @@ int orc_relax_chain(orc_ctx *o, uint32_t species, double q, int sampler, uint32_
 int orc_collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel,
                       const uint16_t *lvl, uint8_t *sp_out, double *vel_out, uint16_t *lvl_out,
                       int32_t *reaction_out, uint8_t *born_sp, double *born_vel, uint16_t *born_lvl);
+/* ---- recombination (Sec. "Recombination reactions") ---- */
+double orc_gamma_q(double a, double x);
+double orc_wr_rho(const orc_ctx *o, uint32_t species, double e);
+double orc_wr_probability(const orc_ctx *o, uint32_t species, double de, double omega, uint32_t n_samp, double t);
+double orc_q_vib(const orc_ctx *o, uint32_t species, double t);
+double orc_rec_factor(const orc_ctx *o, uint32_t reaction, uint32_t third, double t);
+int orc_rec_table(const orc_ctx *o, uint32_t reaction, double *out);
+int orc_collide3_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
+                       uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
+                       uint8_t *born_sp, double *born_vel, uint16_t *born_lvl, const uint8_t *m_sp, double *m_vel,
+                       double t_cell, double n_cell);
 #endif

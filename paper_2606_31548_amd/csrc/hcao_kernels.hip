@@ -22,7 +22,7 @@ namespace hcao {
 namespace {
 
 constexpr double kBoltz = 1.380649e-23;
-constexpr uint32_t kNone = 255u;
+constexpr uint8_t kDead = 255;  // species byte of a particle removed by recombination
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 counter-based generator (Salmon et al., SC'11)
@@ -62,17 +62,18 @@ struct Rng {
     block = 0;
     used = 4;
   }
+  __device__ __attribute__((noinline)) void refill() {
+    uint32_t x0 = block, x1 = pair, x2 = cell, x3 = step;
+    philox10(k0, k1, x0, x1, x2, x3);
+    w0 = x0;
+    w1 = x1;
+    w2 = x2;
+    w3 = x3;
+    block += 1;
+    used = 0;
+  }
   __device__ __forceinline__ uint64_t next64() {
-    if (used >= 4) {
-      uint32_t x0 = block, x1 = pair, x2 = cell, x3 = step;
-      philox10(k0, k1, x0, x1, x2, x3);
-      w0 = x0;
-      w1 = x1;
-      w2 = x2;
-      w3 = x3;
-      block += 1;
-      used = 0;
-    }
+    if (used >= 4) refill();
     uint64_t r = (used == 0) ? (((uint64_t)w1 << 32) | w0) : (((uint64_t)w3 << 32) | w2);
     used += 2;
     return r;
@@ -214,19 +215,21 @@ __device__ __forceinline__ void make_perm(Perm &P, uint32_t n, uint64_t seed, ui
 }
 
 // ---------------------------------------------------------------------------
-// particle views
+// tables in LDS
 // ---------------------------------------------------------------------------
-struct View {
-  double *vx, *vy, *vz;
-  uint8_t *sp;
-  uint16_t *lvl;
-  uint64_t stride;
+// species / pair / reaction tables and stretch levels, staged in LDS
+struct Tab {
+  const SpeciesTab *sp;
+  const PairTab *pr;  // [a * ns + b]
+  const ReactionTab *rx;
+  const double *lev;
+  uint32_t ns, nr, mm, rec_nt;
+  __device__ __forceinline__ const PairTab &pair(uint32_t a, uint32_t b) const { return pr[a * ns + b]; }
 };
 
 struct Ctx {
-  const Tables *T;
-  const double *lev;
-  unsigned long long *ctr;  // LDS counters
+  Tab T;
+  unsigned long long *ctr;  // LDS counters of the pair's cell
   uint16_t *scr;            // per-lane scratch, [2 * max_modes][block]
   uint32_t lane, block;
 };
@@ -237,7 +240,7 @@ __device__ __forceinline__ double mode_energy(const SpeciesTab &S, const double 
 }
 
 __device__ __forceinline__ double vib_energy(const SpeciesTab &S, const double *lev, const uint16_t *lv,
-                                             uint64_t stride) {
+                                             uint32_t stride) {
   double e = 0.0;
   for (uint32_t m = 0; m < S.n_modes; ++m) e = e + mode_energy(S, lev, m, lv[m * stride]);
   return e;
@@ -266,25 +269,25 @@ __device__ __forceinline__ uint32_t pick_level(uint32_t top, double u) {
 
 // Larsen-Borgnakke relaxation of one molecule (levels at lv[m * stride]);
 // e_tr is the pair's translational energy on entry and exit.
-__device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint64_t stride, double &e_tr, double q,
-                          Rng &rng, bool &capped) {
+__device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint32_t stride, double &e_tr,
+                          double q, Rng &rng, bool &capped) {
   uint32_t trials = 0;
   capped = false;
   const uint32_t nm = S.n_modes;
   if (S.sampler == HCAO_SAMPLER_JOINT) {
-    const double e_coll = e_tr + vib_energy(S, C.lev, lv, stride);
+    const double e_coll = e_tr + vib_energy(S, C.T.lev, lv, stride);
     const double denom = e_coll - S.zpe;
     if (!(denom > 0.0)) return 0;
     uint16_t *tops = C.scr + C.lane;
     uint16_t *cand = C.scr + (size_t)nm * C.block + C.lane;
-    for (uint32_t m = 0; m < nm; ++m) tops[m * C.block] = (uint16_t)mode_top(S, C.lev, m, e_coll);
+    for (uint32_t m = 0; m < nm; ++m) tops[m * C.block] = (uint16_t)mode_top(S, C.T.lev, m, e_coll);
     for (;;) {
       ++trials;
       double sum = 0.0;
       for (uint32_t m = 0; m < nm; ++m) {
         const uint32_t i = pick_level(tops[m * C.block], rng.uniform());
         cand[m * C.block] = (uint16_t)i;
-        sum = sum + mode_energy(S, C.lev, m, i);
+        sum = sum + mode_energy(S, C.T.lev, m, i);
       }
       const double ua = rng.uniform();
       const bool ok = (sum < e_coll) && (ua < dpow((e_coll - sum) / denom, q));
@@ -302,14 +305,14 @@ __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint6
   }
   double et = e_tr;
   for (uint32_t m = 0; m < nm; ++m) {
-    const double ec = et + mode_energy(S, C.lev, m, lv[m * stride]);
-    const double den = ec - mode_energy(S, C.lev, m, 0);
+    const double ec = et + mode_energy(S, C.T.lev, m, lv[m * stride]);
+    const double den = ec - mode_energy(S, C.T.lev, m, 0);
     if (!(den > 0.0)) continue;
-    const uint32_t top = mode_top(S, C.lev, m, ec);
+    const uint32_t top = mode_top(S, C.T.lev, m, ec);
     for (;;) {
       ++trials;
       const uint32_t i = pick_level(top, rng.uniform());
-      const double ei = mode_energy(S, C.lev, m, i);
+      const double ei = mode_energy(S, C.T.lev, m, i);
       const double ua = rng.uniform();
       const bool ok = (ei < ec) && (ua < dpow((ec - ei) / den, q));
       if (ok) {
@@ -362,37 +365,121 @@ __device__ __forceinline__ void split(const PairTab &P, Vec3 vcm, double e, Rng 
   vb = Vec3{vcm.x - gb * nx, vcm.y - gb * ny, vcm.z - gb * nz};
 }
 
-__device__ __forceinline__ Vec3 load_v(const View &V, uint32_t i) { return Vec3{V.vx[i], V.vy[i], V.vz[i]}; }
-__device__ __forceinline__ void store_v(const View &V, uint32_t i, Vec3 v) {
-  V.vx[i] = v.x;
-  V.vy[i] = v.y;
-  V.vz[i] = v.z;
+__device__ __forceinline__ void zero_levels(uint16_t *lv, uint32_t stride, uint32_t mm) {
+  for (uint32_t m = 0; m < mm; ++m) lv[m * stride] = 0;
 }
 
-__device__ __forceinline__ void zero_levels(uint16_t *lv, uint64_t stride, uint32_t mm) {
-  for (uint32_t m = 0; m < mm; ++m) lv[m * stride] = 0;
+// One colliding pair held on chip: velocities and species in registers,
+// quantum numbers in per-lane LDS slots (mode m of side x at lv_x[m * ls]).
+struct PairLocal {
+  Vec3 v0, v1;
+  uint32_t sp0, sp1;
+  bool dead0, dead1;
+  uint16_t *lv0, *lv1, *lvn;
+  uint32_t ls;
+  bool born;  // a dissociation product (species nb_sp, velocity nb_v, levels lvn)
+  uint32_t nb_sp;
+  Vec3 nb_v;
+  bool has_m, m_moved;  // third body for recombination
+  uint32_t sp_m;
+  Vec3 v_m;
+  double n_cell;
+  int32_t rec_i;  // recombination table node of the cell temperature (-1: below, -2: above)
+  double rec_f;
+};
+
+__device__ __forceinline__ double vib_local(const Tab &T, uint32_t sp, const uint16_t *lv, uint32_t ls) {
+  const SpeciesTab &S = T.sp[sp];
+  double e = 0.0;
+  for (uint32_t m = 0; m < S.n_modes; ++m) e = e + mode_energy(S, T.lev, m, lv[m * ls]);
+  return e;
 }
 
 struct Channel {
   int32_t rx, side, mode;
 };
 
-// One accepted pair (slots p, q of the tile): reaction decision and
-// application, or relaxation of both molecules, then scattering.
-// A dissociation product is written to nb at index k.
-__device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, double g2, Rng &rng, const View &nb,
-                        uint32_t k) {
-  const Tables &T = *C.T;
-  const uint32_t mm = T.max_modes;
-  const uint32_t slot[2] = {p, q};
-  const uint32_t spp = t.sp[p], spq = t.sp[q];
-  const uint32_t sps[2] = {spp, spq};
-  const PairTab &PP = T.pr[spp][spq];
+// Reaction decision and application, or relaxation of both molecules, then
+// scattering, for one accepted pair held in P. Returns the reaction id or -1.
+__device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const double *rec) {
+  const Tab &T = C.T;
+  const uint32_t mm = T.mm;
+  const uint32_t ls = P.ls;
+  const uint32_t sps[2] = {P.sp0, P.sp1};
+  const PairTab &PP = T.pair(P.sp0, P.sp1);
   double e_tr = PP.hm * g2;
-  const double ev0 = vib_energy(T.sp[spp], C.lev, t.lvl + p, t.stride);
-  const double ev1 = vib_energy(T.sp[spq], C.lev, t.lvl + q, t.stride);
+  const double ev0 = vib_local(T, P.sp0, P.lv0, ls);
+  const double ev1 = vib_local(T, P.sp1, P.lv1, ls);
+  P.born = false;
+  P.m_moved = false;
 
-  // --- reaction decision: dissociation channels, then exchange channels ---
+  // --- recombination first: B + C (+M) -> A (+M) ---
+  for (uint32_t r = 0; r < T.nr; ++r) {
+    const ReactionTab &R = T.rx[r];
+    if (R.kind != HCAO_RX_RECOMBINATION) continue;
+    uint32_t side_b;
+    if (P.sp0 == (uint32_t)R.a && P.sp1 == (uint32_t)R.b)
+      side_b = 0;
+    else if (P.sp1 == (uint32_t)R.a && P.sp0 == (uint32_t)R.b)
+      side_b = 1;
+    else
+      continue;
+    const double u = rng.uniform();
+    if (!P.has_m) {
+      atomicAdd(&C.ctr[HCAO_CTR_SUPPRESSED], 1ull);
+      continue;
+    }
+    const double *tab = rec + R.rec_off + (size_t)P.sp_m * T.rec_nt;
+    double prob;
+    if (P.rec_i == -1)
+      prob = tab[0];
+    else if (P.rec_i == -2)
+      prob = tab[T.rec_nt - 1];
+    else
+      prob = tab[P.rec_i] + P.rec_f * (tab[P.rec_i + 1] - tab[P.rec_i]);
+    prob = prob * P.n_cell;
+    if (prob > 1.0) prob = 1.0;
+    if (!(u < prob)) continue;
+    const SpeciesTab &SA = T.sp[R.c];
+    const PairTab &PBC = T.pair(R.a, R.b);
+    const Vec3 vb = side_b ? P.v1 : P.v0, vc = side_b ? P.v0 : P.v1;
+    const Vec3 vbc = com(PBC, vb, vc);
+    const double gx = vbc.x - P.v_m.x, gy = vbc.y - P.v_m.y, gz = vbc.z - P.v_m.z;
+    const PairTab &PAM = T.pair(R.c, P.sp_m);
+    const double e_am = PAM.hm * ((gx * gx + gy * gy) + gz * gz);
+    const double evb = side_b ? ev1 : ev0, evc = side_b ? ev0 : ev1;
+    const double pool = (((e_am + e_tr) + evb) + evc) - R.dh;
+    double et = pool - SA.zpe;
+    if (!(et > 0.0)) {
+      atomicAdd(&C.ctr[HCAO_CTR_SUPPRESSED], 1ull);
+      continue;
+    }
+    uint16_t *la = side_b ? P.lv1 : P.lv0;
+    zero_levels(la, ls, mm);
+    bool capped = false;
+    const uint32_t tr = relax(C, SA, la, ls, et, PAM.q, rng, capped);
+    const Vec3 vcm = com(PAM, vbc, P.v_m);
+    Vec3 va, vm;
+    split(PAM, vcm, et, rng, va, vm);
+    if (side_b) {
+      P.v1 = va;
+      P.sp1 = (uint32_t)R.c;
+      P.dead0 = true;
+    } else {
+      P.v0 = va;
+      P.sp0 = (uint32_t)R.c;
+      P.dead1 = true;
+    }
+    P.v_m = vm;
+    P.m_moved = true;
+    if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
+    if (capped) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], 1ull);
+    atomicAdd(&C.ctr[HCAO_CTR_DEATHS], 1ull);
+    atomicAdd(&C.ctr[HCAO_CTR_REACTION0 + r], 1ull);
+    return (int)r;
+  }
+
+  // --- dissociation channels, then exchange channels, canonical order ---
   uint32_t nch = 0;
   double total = 0.0;
   Channel first{-1, 0, 0}, last{-1, 0, 0};
@@ -401,7 +488,7 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
   for (uint32_t side = 0; side < 2; ++side) {
     const uint32_t A = sps[side];
     const double evA = side ? ev1 : ev0;
-    for (uint32_t r = 0; r < T.n_reactions; ++r) {
+    for (uint32_t r = 0; r < T.nr; ++r) {
       const ReactionTab &R = T.rx[r];
       if (R.kind != HCAO_RX_DISSOCIATION || (uint32_t)R.a != A) continue;
       const SpeciesTab &SA = T.sp[A];
@@ -409,7 +496,7 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
       for (uint32_t j = 0; j < nst; ++j) {
         if (!((R.mask >> j) & 1ull)) continue;
         const uint32_t m = SA.n_bend + j;
-        const double ecoll = ((e_tr + evA) - R.zsum) + C.lev[SA.lev_off[m]];
+        const double ecoll = ((e_tr + evA) - R.zsum) + T.lev[SA.lev_off[m]];
         const double eex = ecoll - SA.de[m];
         const double pool = (e_tr + evA) - R.dh;
         const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
@@ -426,15 +513,14 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
   for (uint32_t side = 0; side < 2; ++side) {
     const uint32_t A = sps[side], B = sps[1 - side];
     const double evA = side ? ev1 : ev0, evB = side ? ev0 : ev1;
-    const uint32_t sA = slot[side];
-    for (uint32_t r = 0; r < T.n_reactions; ++r) {
+    const uint16_t *lA = side ? P.lv1 : P.lv0;
+    for (uint32_t r = 0; r < T.nr; ++r) {
       const ReactionTab &R = T.rx[r];
       if (R.kind != HCAO_RX_EXCHANGE || (uint32_t)R.a != A || (uint32_t)R.b != B) continue;
       const double us = rng.uniform();
       const SpeciesTab &SA = T.sp[A];
       double ecoll = e_tr;
-      for (uint32_t m = 0; m < SA.n_modes; ++m)
-        ecoll = ecoll + R.alpha[m] * mode_energy(SA, C.lev, m, t.lvl[m * t.stride + sA]);
+      for (uint32_t m = 0; m < SA.n_modes; ++m) ecoll = ecoll + R.alpha[m] * mode_energy(SA, T.lev, m, lA[m * ls]);
       const double eex = ecoll - R.ea;
       const double pool = ((e_tr + evA) + evB) - R.dh;
       const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
@@ -464,7 +550,7 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
       for (uint32_t side = 0; side < 2 && !found; ++side) {
         const uint32_t A = sps[side];
         const double evA = side ? ev1 : ev0;
-        for (uint32_t r = 0; r < T.n_reactions && !found; ++r) {
+        for (uint32_t r = 0; r < T.nr && !found; ++r) {
           const ReactionTab &R = T.rx[r];
           if (R.kind != HCAO_RX_DISSOCIATION || (uint32_t)R.a != A) continue;
           const SpeciesTab &SA = T.sp[A];
@@ -472,7 +558,7 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
           for (uint32_t j = 0; j < nst && !found; ++j) {
             if (!((R.mask >> j) & 1ull)) continue;
             const uint32_t m = SA.n_bend + j;
-            const double ecoll = ((e_tr + evA) - R.zsum) + C.lev[SA.lev_off[m]];
+            const double ecoll = ((e_tr + evA) - R.zsum) + T.lev[SA.lev_off[m]];
             const double eex = ecoll - SA.de[m];
             const double pool = (e_tr + evA) - R.dh;
             const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
@@ -490,8 +576,8 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
       for (uint32_t side = 0; side < 2 && !found; ++side) {
         const uint32_t A = sps[side], B = sps[1 - side];
         const double evA = side ? ev1 : ev0, evB = side ? ev0 : ev1;
-        const uint32_t sA = slot[side];
-        for (uint32_t r = 0; r < T.n_reactions && !found; ++r) {
+        const uint16_t *lA = side ? P.lv1 : P.lv0;
+        for (uint32_t r = 0; r < T.nr && !found; ++r) {
           const ReactionTab &R = T.rx[r];
           if (R.kind != HCAO_RX_EXCHANGE || (uint32_t)R.a != A || (uint32_t)R.b != B) continue;
           const bool st_ok = ex_i < 64 ? ((steric_ok >> ex_i) & 1ull) != 0 : false;
@@ -499,7 +585,7 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
           const SpeciesTab &SA = T.sp[A];
           double ecoll = e_tr;
           for (uint32_t m = 0; m < SA.n_modes; ++m)
-            ecoll = ecoll + R.alpha[m] * mode_energy(SA, C.lev, m, t.lvl[m * t.stride + sA]);
+            ecoll = ecoll + R.alpha[m] * mode_energy(SA, T.lev, m, lA[m * ls]);
           const double eex = ecoll - R.ea;
           const double pool = ((e_tr + evA) + evB) - R.dh;
           const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
@@ -516,23 +602,23 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
     }
 
     const ReactionTab &R = T.rx[pick.rx];
-    const uint32_t a = (uint32_t)pick.side, b = 1 - a;
-    const uint32_t sa = slot[a], sb = slot[b];
+    const uint32_t a = (uint32_t)pick.side;
+    const Vec3 va0 = a ? P.v1 : P.v0, vb0 = a ? P.v0 : P.v1;
     const double eva = a ? ev1 : ev0, evb = a ? ev0 : ev1;
+    uint16_t *la = a ? P.lv1 : P.lv0;
+    uint16_t *lb = a ? P.lv0 : P.lv1;
     uint64_t tr = 0;
     bool capped = false, c2 = false;
     if (R.kind == HCAO_RX_DISSOCIATION) {
       // A + M -> B + C + M: B takes A's slot, C is new
-      const uint32_t spA = sps[a], spM = sps[b];
+      const uint32_t spA = sps[a], spM = sps[1 - a];
       const double pool = (e_tr + eva) - R.dh;
       double et = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-      uint16_t *lb = t.lvl + sa;
-      uint16_t *lc = nb.lvl + k;
-      zero_levels(lb, t.stride, mm);
-      zero_levels(lc, nb.stride, mm);
-      if (T.sp[R.c].n_modes > 0) tr += relax(C, T.sp[R.c], lb, t.stride, et, T.pr[R.c][spM].q, rng, capped);
+      zero_levels(la, ls, mm);
+      zero_levels(P.lvn, ls, mm);
+      if (T.sp[R.c].n_modes > 0) tr += relax(C, T.sp[R.c], la, ls, et, T.pair(R.c, spM).q, rng, capped);
       if (T.sp[R.d].n_modes > 0) {
-        tr += relax(C, T.sp[R.d], lc, nb.stride, et, T.pr[R.d][spM].q, rng, c2);
+        tr += relax(C, T.sp[R.d], P.lvn, ls, et, T.pair(R.d, spM).q, rng, c2);
         capped = capped || c2;
       }
       double beta;
@@ -545,44 +631,56 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
       }
       const double ebc = beta * et;
       const double exm = et - ebc;
-      const PairTab &PAM = T.pr[spA][spM];
-      const Vec3 vcm = com(PAM, load_v(t, sa), load_v(t, sb));
+      const PairTab &PAM = T.pair(spA, spM);
+      const Vec3 vcm = com(PAM, va0, vb0);
       Vec3 vbc, vm, vbn, vcn;
       split(PAM, vcm, exm, rng, vbc, vm);
-      split(T.pr[R.c][R.d], vbc, ebc, rng, vbn, vcn);
-      store_v(t, sa, vbn);
-      store_v(t, sb, vm);
-      store_v(nb, k, vcn);
-      t.sp[sa] = (uint8_t)R.c;
-      nb.sp[k] = (uint8_t)R.d;
+      split(T.pair(R.c, R.d), vbc, ebc, rng, vbn, vcn);
+      if (a) {
+        P.v1 = vbn;
+        P.v0 = vm;
+        P.sp1 = (uint32_t)R.c;
+      } else {
+        P.v0 = vbn;
+        P.v1 = vm;
+        P.sp0 = (uint32_t)R.c;
+      }
+      P.born = true;
+      P.nb_sp = (uint32_t)R.d;
+      P.nb_v = vcn;
       atomicAdd(&C.ctr[HCAO_CTR_BIRTHS], 1ull);
     } else {
       // A + B -> C + D: C takes A's slot, D takes B's
-      const uint32_t spA = sps[a], spB = sps[b];
+      const uint32_t spA = sps[a], spB = sps[1 - a];
       const double pool = ((e_tr + eva) + evb) - R.dh;
       double et = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-      uint16_t *lc = t.lvl + sa;
-      uint16_t *ld = t.lvl + sb;
-      zero_levels(lc, t.stride, mm);
-      zero_levels(ld, t.stride, mm);
-      const double qcd = T.pr[R.c][R.d].q;
-      if (T.sp[R.c].n_modes > 0) tr += relax(C, T.sp[R.c], lc, t.stride, et, qcd, rng, capped);
+      zero_levels(la, ls, mm);
+      zero_levels(lb, ls, mm);
+      const double qcd = T.pair(R.c, R.d).q;
+      if (T.sp[R.c].n_modes > 0) tr += relax(C, T.sp[R.c], la, ls, et, qcd, rng, capped);
       if (T.sp[R.d].n_modes > 0) {
-        tr += relax(C, T.sp[R.d], ld, t.stride, et, qcd, rng, c2);
+        tr += relax(C, T.sp[R.d], lb, ls, et, qcd, rng, c2);
         capped = capped || c2;
       }
-      const Vec3 vcm = com(T.pr[spA][spB], load_v(t, sa), load_v(t, sb));
+      const Vec3 vcm = com(T.pair(spA, spB), va0, vb0);
       Vec3 vc, vd;
-      split(T.pr[R.c][R.d], vcm, et, rng, vc, vd);
-      store_v(t, sa, vc);
-      store_v(t, sb, vd);
-      t.sp[sa] = (uint8_t)R.c;
-      t.sp[sb] = (uint8_t)R.d;
+      split(T.pair(R.c, R.d), vcm, et, rng, vc, vd);
+      if (a) {
+        P.v1 = vc;
+        P.v0 = vd;
+        P.sp1 = (uint32_t)R.c;
+        P.sp0 = (uint32_t)R.d;
+      } else {
+        P.v0 = vc;
+        P.v1 = vd;
+        P.sp0 = (uint32_t)R.c;
+        P.sp1 = (uint32_t)R.d;
+      }
     }
     if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
     if (capped) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], 1ull);
     atomicAdd(&C.ctr[HCAO_CTR_REACTION0 + pick.rx], 1ull);
-    return;
+    return pick.rx;
   }
 
   // --- no reaction: relax each molecule in turn, then scatter ---
@@ -594,206 +692,405 @@ __device__ void collide(const Ctx &C, const View &t, uint32_t p, uint32_t q, dou
     const double u = rng.uniform();
     if (!(u < S.p_vib)) continue;
     bool capped = false;
-    tr += relax(C, S, t.lvl + slot[x], t.stride, e_tr, PP.q, rng, capped);
+    tr += relax(C, S, x ? P.lv1 : P.lv0, ls, e_tr, PP.q, rng, capped);
     ++nrel;
     ncap += capped ? 1u : 0u;
   }
   if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
   if (nrel) atomicAdd(&C.ctr[HCAO_CTR_RELAX], (unsigned long long)nrel);
   if (ncap) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], (unsigned long long)ncap);
-  const Vec3 vcm = com(PP, load_v(t, p), load_v(t, q));
-  Vec3 va, vb;
-  split(PP, vcm, e_tr, rng, va, vb);
-  store_v(t, p, va);
-  store_v(t, q, vb);
+  const Vec3 vcm = com(PP, P.v0, P.v1);
+  split(PP, vcm, e_tr, rng, P.v0, P.v1);
+  return -1;
 }
 
-// block-wide exclusive scan of one value per thread (small blocks)
-template <int BLOCK>
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
-  const uint32_t tid = threadIdx.x;
-  s_tmp[tid] = v;
-  __syncthreads();
-  for (uint32_t off = 1; off < BLOCK; off <<= 1) {
-    const uint32_t add = tid >= off ? s_tmp[tid - off] : 0u;
-    __syncthreads();
-    s_tmp[tid] += add;
-    __syncthreads();
+// Translational temperature of a cell by one wave: blocks of 64 particles in
+// slot order, each reduced by a halving tree (lane t takes lane t + s for
+// s = 32, ..., 1), block results added in order.
+__device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint64_t base, uint32_t n, uint32_t lane) {
+  if (n < 2) return 0.0;
+  double tot0 = 0.0, tot1 = 0.0, tot2 = 0.0, tot3 = 0.0, tot4 = 0.0;
+  for (uint32_t b0 = 0; b0 < n; b0 += 64) {
+    const uint32_t i = b0 + lane;
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
+    if (i < n) {
+      const uint64_t g = base + i;
+      const double m = spt[st.sp[g]].mass;
+      const double vx = st.vx[g], vy = st.vy[g], vz = st.vz[g];
+      x0 = m;
+      x1 = m * vx;
+      x2 = m * vy;
+      x3 = m * vz;
+      x4 = m * ((vx * vx + vy * vy) + vz * vz);
+    }
+    for (int s = 32; s >= 1; s >>= 1) {
+      x0 = x0 + __shfl_down(x0, s);
+      x1 = x1 + __shfl_down(x1, s);
+      x2 = x2 + __shfl_down(x2, s);
+      x3 = x3 + __shfl_down(x3, s);
+      x4 = x4 + __shfl_down(x4, s);
+    }
+    tot0 = tot0 + x0;
+    tot1 = tot1 + x1;
+    tot2 = tot2 + x2;
+    tot3 = tot3 + x3;
+    tot4 = tot4 + x4;
   }
-  total = s_tmp[BLOCK - 1];
-  const uint32_t incl = s_tmp[tid];
-  __syncthreads();
-  return incl - v;
+  const double p2 = (tot1 * tot1 + tot2 * tot2) + tot3 * tot3;
+  return (tot4 - p2 / tot0) / (3.0 * kBoltz * (double)n);
 }
 
-// LDS layout of one tile: [vx | vy | vz | nb.vx | nb.vy | nb.vz] doubles, then
-// [lvl (mm x L) | nb.lvl (mm x L2) | scratch (2 mm x BLOCK)] u16, then
-// [sp (L) | nb.sp (L2)] bytes.
-__host__ __device__ inline size_t tile_lds_bytes(uint32_t L, uint32_t mm, uint32_t block) {
-  const uint32_t L2 = L / 2 + 1;
-  size_t bytes = (size_t)8 * (3 * L + 3 * L2);
-  bytes += (size_t)2 * ((size_t)mm * L + (size_t)mm * L2 + (size_t)2 * mm * block);
-  bytes += (size_t)L + L2;
-  return (bytes + 15) & ~(size_t)15;
+// ---------------------------------------------------------------------------
+// the collision step: one workgroup per group of consecutive cells
+// ---------------------------------------------------------------------------
+struct CellHdr {
+  uint64_t base;
+  uint32_t cell, n, cap, ncand, cstart, pad;
+  double sgmax, rem_new, n_cell, rec_f;
+  int32_t rec_i, pad2;
+  unsigned long long sgbits, excess;
+  Perm perm;
+};
+
+// the cell of flattened candidate j: the last cell whose range starts at or before j
+__device__ __forceinline__ uint32_t group_cell(const CellHdr *hdr, uint32_t ncell, uint32_t j) {
+  uint32_t lo = 0, hi = ncell;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (hdr[mid].cstart <= j)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
 }
 
-template <int BLOCK, bool kLds>
+// Phase 0 stages the tables in LDS and computes each cell's NTC candidate
+// count and permutation keys (and, with recombination, the cell
+// temperature). Phase A tests every candidate pair of the group (lane per
+// candidate) and appends the accepted ones to a work list. Phase B gives
+// every lane one accepted pair: the pair's state is gathered once into
+// registers and per-lane LDS, the reaction / relaxation / scattering runs
+// on chip, and the result is written back. Phase C removes recombined
+// particles, places the products of each cell in pair order and writes the
+// per-cell state. Pairs are disjoint and every draw is keyed by (cell,
+// pair), so the order in which lanes take work does not change the result.
+template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ unsigned long long s_ctr[kNumCtr];
-  __shared__ unsigned long long s_sgbits;
-  __shared__ uint32_t s_scan[BLOCK];
-
+  __shared__ uint32_t s_nheavy, s_nlight, s_total;
   const uint32_t tid = threadIdx.x;
-  const uint32_t c = A.cell_list ? A.cell_list[blockIdx.x] : blockIdx.x;
-  const Tables *T = A.tab;
-  const uint32_t mm = T->max_modes;
-  const uint64_t base = A.cells.off[c];
-  const uint32_t n = A.cells.cnt[c];
-  const uint32_t cap = A.cells.cap[c];
-  const double sgmax = A.cells.sgmax[c];
+  const uint32_t lane = tid & 63u, wave = tid >> 6;
+  const unsigned long long lt = lane ? ((1ull << lane) - 1ull) : 0ull;
+  const Tables *GT = A.tab;
+  const uint32_t ns = GT->n_species, nr = GT->n_reactions, mm = GT->max_modes, nl = GT->n_levels;
+  const uint32_t nctr = 8 + nr;
+  const uint32_t c0 = A.grp[blockIdx.x], c1 = A.grp[blockIdx.x + 1];
+  const uint32_t ncell = c1 - c0;
+  const uint64_t wbase = A.grp_work[blockIdx.x];
 
-  // NTC candidate count: floor(1/2 N (N-1) F_N (sigma g)_max dt / V + remainder)
-  const double x = 0.5 * (double)n * (double)(n - (n > 0 ? 1u : 0u)) * A.cells.weight[c] * sgmax * A.dt /
-                       A.cells.volume[c] +
-                   A.cells.rem[c];
-  const double fl = floor(x);
-  const double rem_new = x - fl;
-  uint64_t ncand = (uint64_t)fl;
-  uint64_t excess = 0;
-  if (ncand > n / 2) {
-    excess = ncand - n / 2;
-    ncand = n / 2;
+  // ---- LDS carve-up ----
+  unsigned char *q = smem;
+  SpeciesTab *l_sp = reinterpret_cast<SpeciesTab *>(q);
+  q += sizeof(SpeciesTab) * ns;
+  PairTab *l_pr = reinterpret_cast<PairTab *>(q);
+  q += sizeof(PairTab) * ns * ns;
+  ReactionTab *l_rx = reinterpret_cast<ReactionTab *>(q);
+  q += sizeof(ReactionTab) * nr;
+  double *l_lev = reinterpret_cast<double *>(q);
+  q += sizeof(double) * nl;
+  CellHdr *hdr = reinterpret_cast<CellHdr *>(q);
+  q += sizeof(CellHdr) * ncell;
+  unsigned long long *l_ctr = reinterpret_cast<unsigned long long *>(q);
+  q += sizeof(unsigned long long) * nctr * ncell;
+  uint16_t *scr = reinterpret_cast<uint16_t *>(q);  // [2 mm][BLOCK] sampler scratch
+  uint16_t *plv = scr + (size_t)2 * mm * BLOCK;      // [3 mm][BLOCK] pair levels
+
+  // ---- phase 0: tables and cell headers ----
+  {
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(GT->sp);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(l_sp);
+    for (uint32_t i = tid; i < ns * sizeof(SpeciesTab) / 8; i += BLOCK) dst[i] = src[i];
+    for (uint32_t i = tid; i < ns * ns; i += BLOCK) l_pr[i] = GT->pr[i / ns][i % ns];
+    src = reinterpret_cast<const uint64_t *>(GT->rx);
+    dst = reinterpret_cast<uint64_t *>(l_rx);
+    for (uint32_t i = tid; i < nr * sizeof(ReactionTab) / 8; i += BLOCK) dst[i] = src[i];
+    for (uint32_t i = tid; i < nl; i += BLOCK) l_lev[i] = A.lev[i];
+    for (uint32_t i = tid; i < nctr * ncell; i += BLOCK) l_ctr[i] = 0ull;
   }
-
-  for (uint32_t i = tid; i < (uint32_t)kNumCtr; i += BLOCK) s_ctr[i] = 0ull;
-  if (tid == 0) s_sgbits = 0ull;
-
-  View t, nb;
-  const uint32_t L = A.lds_cap, L2 = A.lds_cap / 2 + 1;
-  uint16_t *scr;
-  if (kLds) {
-    double *d = reinterpret_cast<double *>(smem);
-    t.vx = d;
-    t.vy = d + L;
-    t.vz = d + 2 * L;
-    nb.vx = d + 3 * L;
-    nb.vy = d + 3 * L + L2;
-    nb.vz = d + 3 * L + 2 * L2;
-    uint16_t *h = reinterpret_cast<uint16_t *>(d + 3 * L + 3 * L2);
-    t.lvl = h;
-    nb.lvl = h + (size_t)mm * L;
-    scr = h + (size_t)mm * (L + L2);
-    uint8_t *bt = reinterpret_cast<uint8_t *>(scr + (size_t)2 * mm * BLOCK);
-    t.sp = bt;
-    nb.sp = bt + L;
-    t.stride = L;
-    nb.stride = L2;
-    for (uint32_t i = tid; i < n; i += BLOCK) {
-      t.vx[i] = A.st.vx[base + i];
-      t.vy[i] = A.st.vy[base + i];
-      t.vz[i] = A.st.vz[base + i];
-      t.sp[i] = A.st.sp[base + i];
+  for (uint32_t g = tid; g < ncell; g += BLOCK) {
+    CellHdr &H = hdr[g];
+    const uint32_t c = c0 + g;
+    const uint32_t n = A.cells.cnt[c];
+    const double sgmax = A.cells.sgmax[c];
+    // NTC candidate count: floor(1/2 N (N-1) F_N (sigma g)_max dt / V + remainder)
+    const double x = 0.5 * (double)n * (double)(n - (n > 0 ? 1u : 0u)) * A.cells.weight[c] * sgmax * A.dt /
+                         A.cells.volume[c] +
+                     A.cells.rem[c];
+    const double fl = floor(x);
+    uint64_t ncand = (uint64_t)fl;
+    uint64_t excess = 0;
+    if (ncand > n / 2) {
+      excess = ncand - n / 2;
+      ncand = n / 2;
     }
-    for (uint32_t m = 0; m < mm; ++m)
-      for (uint32_t i = tid; i < n; i += BLOCK) t.lvl[m * L + i] = A.st.lvl[m * A.st.stride + base + i];
-  } else {
-    scr = reinterpret_cast<uint16_t *>(smem);
-    t.vx = A.st.vx + base;
-    t.vy = A.st.vy + base;
-    t.vz = A.st.vz + base;
-    t.sp = A.st.sp + base;
-    t.lvl = A.st.lvl + base;
-    t.stride = A.st.stride;
-    nb.vx = A.scratch.vx + base;
-    nb.vy = A.scratch.vy + base;
-    nb.vz = A.scratch.vz + base;
-    nb.sp = A.scratch.sp + base;
-    nb.lvl = A.scratch.lvl + base;
-    nb.stride = A.scratch.stride;
+    H.base = A.cells.off[c];
+    H.cell = c;
+    H.n = n;
+    H.cap = A.cells.cap[c];
+    H.ncand = (uint32_t)ncand;
+    H.sgmax = sgmax;
+    H.rem_new = x - fl;
+    H.n_cell = (double)n * A.cells.weight[c] / A.cells.volume[c];
+    H.rec_i = -1;
+    H.rec_f = 0.0;
+    H.sgbits = 0ull;
+    H.excess = excess;
+    if (ncand > 0) make_perm(H.perm, n, A.seed, c, A.step);
   }
   __syncthreads();
-
-  Ctx C{T, A.lev, s_ctr, scr, tid, BLOCK};
-  if (ncand > 0) {
-    Perm P;
-    make_perm(P, n, A.seed, c, A.step);
-    double sg_seen = 0.0;
-    uint32_t ncoll = 0;
-    for (uint32_t k = tid; k < (uint32_t)ncand; k += BLOCK) {
-      const uint32_t p = P(2 * k), q = P(2 * k + 1);
-      Rng rng;
-      rng.open(A.seed, k, c, A.step);
-      const double dx = t.vx[p] - t.vx[q], dy = t.vy[p] - t.vy[q], dz = t.vz[p] - t.vz[q];
-      const double g2 = (dx * dx + dy * dy) + dz * dz;
-      const PairTab &PP = T->pr[t.sp[p]][t.sp[q]];
-      const double sg = (g2 > 0.0) ? PP.csg * dpow(g2, PP.esg) : 0.0;
-      sg_seen = sg > sg_seen ? sg : sg_seen;
-      const double ua = rng.uniform();
-      nb.sp[k] = (uint8_t)kNone;
-      if (!(ua < sg / sgmax)) continue;
-      ++ncoll;
-      collide(C, t, p, q, g2, rng, nb, k);
-    }
-    atomicMax(&s_sgbits, (unsigned long long)__double_as_longlong(sg_seen));
-    if (ncoll) atomicAdd(&s_ctr[HCAO_CTR_COLLISIONS], (unsigned long long)ncoll);
-  }
-  __syncthreads();
-
-  // births: products in pair order after the survivors
-  uint32_t births = 0;
-  bool overflow = false;
-  if (ncand > 0) {
-    const uint32_t nc = (uint32_t)ncand;
-    const uint32_t chunk = (nc + BLOCK - 1) / BLOCK;
-    const uint32_t k0 = tid * chunk, k1 = min(nc, k0 + chunk);
-    uint32_t mine = 0;
-    for (uint32_t k = k0; k < k1; ++k) mine += (nb.sp[k] != kNone) ? 1u : 0u;
-    const int any = __syncthreads_or(mine != 0);
-    if (any) {
-      uint32_t total;
-      uint32_t rank = block_exclusive_scan<BLOCK>(mine, s_scan, total);
-      births = total;
-      const uint32_t limit = kLds ? min(cap, L) : cap;
-      overflow = n + births > limit;
-      if (!overflow) {
-        for (uint32_t k = k0; k < k1; ++k) {
-          if (nb.sp[k] == kNone) continue;
-          const uint32_t dst = n + rank;
-          ++rank;
-          t.vx[dst] = nb.vx[k];
-          t.vy[dst] = nb.vy[k];
-          t.vz[dst] = nb.vz[k];
-          t.sp[dst] = nb.sp[k];
-          for (uint32_t m = 0; m < mm; ++m) t.lvl[m * t.stride + dst] = nb.lvl[m * nb.stride + k];
+  if (GT->has_recomb) {
+    // cell temperature and its recombination-table coordinate (one wave per cell)
+    for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
+      CellHdr &H = hdr[g];
+      const double t = cell_temperature(A.st, l_sp, H.base, H.n, lane);
+      if (lane == 0) {
+        int32_t ri = -1;
+        double rf = 0.0;
+        if (t > 0.0) {
+          const double u = (dlog(t) - GT->rec_l0) * GT->rec_inv_step;
+          if (!(u > 0.0)) {
+            ri = -1;
+          } else if (!(u < (double)(GT->rec_nt - 1))) {
+            ri = -2;
+          } else {
+            const double fi = floor(u);
+            ri = (int32_t)fi;
+            rf = u - fi;
+          }
         }
+        H.rec_i = ri;
+        H.rec_f = rf;
       }
     }
   }
-  const uint32_t n_out = overflow ? n : n + births;
-  if (kLds) {
-    __syncthreads();
-    for (uint32_t i = tid; i < n_out; i += BLOCK) {
-      A.st.vx[base + i] = t.vx[i];
-      A.st.vy[base + i] = t.vy[i];
-      A.st.vz[base + i] = t.vz[i];
-      A.st.sp[base + i] = t.sp[i];
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (uint32_t g = 0; g < ncell; ++g) {
+      hdr[g].cstart = acc;
+      acc += hdr[g].ncand;
     }
-    for (uint32_t m = 0; m < mm; ++m)
-      for (uint32_t i = tid; i < n_out; i += BLOCK) A.st.lvl[m * A.st.stride + base + i] = t.lvl[m * L + i];
+    s_total = acc;
+    s_nheavy = 0;
+    s_nlight = 0;
   }
   __syncthreads();
-  if (tid == 0) {
-    if (overflow) atomicOr(A.err, kErrCapacity);
-    A.cells.cnt[c] = n_out;
-    const double seen = __longlong_as_double((long long)s_sgbits);
-    A.cells.sgmax[c] = seen > sgmax ? seen : sgmax;
-    A.cells.rem[c] = rem_new;
-    unsigned long long *ctr = A.cells.ctr + (size_t)c * kNumCtr;
-    ctr[HCAO_CTR_CANDIDATES] += ncand;
-    ctr[HCAO_CTR_SUPPRESSED] += excess;
-    for (int i = 0; i < kNumCtr; ++i)
-      if (i != HCAO_CTR_CANDIDATES && i != HCAO_CTR_SUPPRESSED) ctr[i] += s_ctr[i];
+  const uint32_t total = s_total;
+  const Tab T{l_sp, l_pr, l_rx, l_lev, ns, nr, mm, GT->rec_nt};
+  uint32_t *work = A.work + wbase;
+  uint8_t *bflag = A.bflag + wbase;
+
+  // ---- phase A: candidate pairs, VHS acceptance ----
+  // Accepted pairs that involve a molecule (the long sampler chains) fill
+  // the work list from the front, atom-atom pairs from the back, so that
+  // waves of phase B hold work of similar length. One LDS atomic per wave
+  // and section.
+  const uint32_t wcap = (uint32_t)(A.grp_work[blockIdx.x + 1] - wbase);
+  for (uint32_t j0 = 0; j0 < total; j0 += BLOCK) {
+    const uint32_t j = j0 + tid;
+    bool acc = false, heavy = false;
+    if (j < total) {
+      const uint32_t g = group_cell(hdr, ncell, j);
+      const CellHdr &H = hdr[g];
+      const uint32_t k = j - H.cstart;
+      const uint32_t p = H.perm(2 * k), qq = H.perm(2 * k + 1);
+      const uint64_t gp = H.base + p, gq = H.base + qq;
+      const double dx = A.st.vx[gp] - A.st.vx[gq], dy = A.st.vy[gp] - A.st.vy[gq],
+                   dz = A.st.vz[gp] - A.st.vz[gq];
+      const double g2 = (dx * dx + dy * dy) + dz * dz;
+      const uint32_t a = A.st.sp[gp], b = A.st.sp[gq];
+      const PairTab &PP = T.pair(a, b);
+      const double sg = (g2 > 0.0) ? PP.csg * dpow(g2, PP.esg) : 0.0;
+      const unsigned long long sb = (unsigned long long)__double_as_longlong(sg);
+      if (sb > hdr[g].sgbits) atomicMax(&hdr[g].sgbits, sb);
+      Rng rng;
+      rng.open(A.seed, k, H.cell, A.step);
+      const double ua = rng.uniform();
+      bflag[j] = 0;
+      acc = ua < sg / H.sgmax;
+      heavy = (T.sp[a].n_modes | T.sp[b].n_modes) != 0;
+    }
+    const unsigned long long mh = __ballot(acc && heavy), ml = __ballot(acc && !heavy);
+    uint32_t bh = 0, bl = 0;
+    if (lane == 0) {
+      if (mh) bh = atomicAdd(&s_nheavy, (uint32_t)__popcll(mh));
+      if (ml) bl = atomicAdd(&s_nlight, (uint32_t)__popcll(ml));
+    }
+    bh = __shfl(bh, 0);
+    bl = __shfl(bl, 0);
+    if (acc) {
+      if (heavy)
+        work[bh + (uint32_t)__popcll(mh & lt)] = j;
+      else
+        work[wcap - 1 - (bl + (uint32_t)__popcll(ml & lt))] = j;
+    }
+  }
+  __syncthreads();
+
+  // ---- phase B: one accepted pair per lane ----
+  const uint32_t nheavy = s_nheavy, nwork = s_nheavy + s_nlight;
+  for (uint32_t i = tid; i < nwork; i += BLOCK) {
+    const uint32_t j = i < nheavy ? work[i] : work[wcap - 1 - (i - nheavy)];
+    const uint32_t g = group_cell(hdr, ncell, j);
+    const CellHdr &H = hdr[g];
+    const uint32_t k = j - H.cstart;
+    const uint32_t p = H.perm(2 * k), qq = H.perm(2 * k + 1);
+    const uint64_t gp = H.base + p, gq = H.base + qq;
+    PairLocal P;
+    P.v0 = Vec3{A.st.vx[gp], A.st.vy[gp], A.st.vz[gp]};
+    P.v1 = Vec3{A.st.vx[gq], A.st.vy[gq], A.st.vz[gq]};
+    P.sp0 = A.st.sp[gp];
+    P.sp1 = A.st.sp[gq];
+    P.dead0 = P.dead1 = false;
+    P.ls = BLOCK;
+    P.lv0 = plv + tid;
+    P.lv1 = plv + (size_t)mm * BLOCK + tid;
+    P.lvn = plv + (size_t)2 * mm * BLOCK + tid;
+    for (uint32_t m = 0; m < mm; ++m) {
+      P.lv0[m * BLOCK] = A.st.lvl[m * A.st.stride + gp];
+      P.lv1[m * BLOCK] = A.st.lvl[m * A.st.stride + gq];
+    }
+    P.has_m = false;
+    uint64_t gm = 0;
+    if (GT->has_recomb && 2 * H.ncand + k < H.n) {
+      // third body of pair k: the particle at permutation index 2 N_cand + k
+      gm = H.base + H.perm(2 * H.ncand + k);
+      P.has_m = true;
+      P.sp_m = A.st.sp[gm];
+      P.v_m = Vec3{A.st.vx[gm], A.st.vy[gm], A.st.vz[gm]};
+    }
+    P.n_cell = H.n_cell;
+    P.rec_i = H.rec_i;
+    P.rec_f = H.rec_f;
+    const double dx = P.v0.x - P.v1.x, dy = P.v0.y - P.v1.y, dz = P.v0.z - P.v1.z;
+    const double g2 = (dx * dx + dy * dy) + dz * dz;
+    Rng rng;
+    rng.open(A.seed, k, H.cell, A.step);
+    (void)rng.uniform();  // the acceptance draw of phase A
+    unsigned long long *ctr = l_ctr + (size_t)g * nctr;
+    atomicAdd(&ctr[HCAO_CTR_COLLISIONS], 1ull);
+    Ctx C{T, ctr, scr, tid, BLOCK};
+    collide(C, P, g2, rng, A.rec);
+    A.st.vx[gp] = P.v0.x;
+    A.st.vy[gp] = P.v0.y;
+    A.st.vz[gp] = P.v0.z;
+    A.st.vx[gq] = P.v1.x;
+    A.st.vy[gq] = P.v1.y;
+    A.st.vz[gq] = P.v1.z;
+    A.st.sp[gp] = P.dead0 ? (uint8_t)kDead : (uint8_t)P.sp0;
+    A.st.sp[gq] = P.dead1 ? (uint8_t)kDead : (uint8_t)P.sp1;
+    for (uint32_t m = 0; m < mm; ++m) {
+      A.st.lvl[m * A.st.stride + gp] = P.lv0[m * BLOCK];
+      A.st.lvl[m * A.st.stride + gq] = P.lv1[m * BLOCK];
+    }
+    if (P.m_moved) {
+      A.st.vx[gm] = P.v_m.x;
+      A.st.vy[gm] = P.v_m.y;
+      A.st.vz[gm] = P.v_m.z;
+    }
+    if (P.born) {
+      const uint64_t gb = H.base + k;
+      A.scratch.vx[gb] = P.nb_v.x;
+      A.scratch.vy[gb] = P.nb_v.y;
+      A.scratch.vz[gb] = P.nb_v.z;
+      A.scratch.sp[gb] = (uint8_t)P.nb_sp;
+      for (uint32_t m = 0; m < mm; ++m) A.scratch.lvl[m * A.scratch.stride + gb] = P.lvn[m * BLOCK];
+      bflag[j] = 1;
+    }
+  }
+  __syncthreads();
+
+  // ---- phase C: deaths, products in pair order, per-cell state ----
+  // one wave per cell: ballots give each survivor its new slot and each
+  // product its rank in pair order
+  for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
+    const CellHdr &H = hdr[g];
+    const unsigned long long *in = l_ctr + (size_t)g * nctr;
+    uint32_t alive = H.n;
+    if (in[HCAO_CTR_DEATHS] != 0ull) {
+      // stable in-place compaction: a chunk's survivors move to lower slots
+      // after the whole chunk has been read
+      uint32_t kept = 0;
+      for (uint32_t i0 = 0; i0 < H.n; i0 += 64) {
+        const uint32_t i = i0 + lane;
+        const uint64_t src = H.base + i;
+        const bool live = i < H.n && A.st.sp[src] != kDead;
+        const unsigned long long m = __ballot(live);
+        const uint64_t dst = H.base + kept + (uint32_t)__popcll(m & lt);
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        uint8_t spv = 0;
+        if (live) {
+          vx = A.st.vx[src];
+          vy = A.st.vy[src];
+          vz = A.st.vz[src];
+          spv = A.st.sp[src];
+        }
+        if (live) {
+          A.st.vx[dst] = vx;
+          A.st.vy[dst] = vy;
+          A.st.vz[dst] = vz;
+          A.st.sp[dst] = spv;
+        }
+        for (uint32_t mo = 0; mo < mm; ++mo) {
+          uint16_t l = 0;
+          if (live) l = A.st.lvl[mo * A.st.stride + src];
+          if (live) A.st.lvl[mo * A.st.stride + dst] = l;
+        }
+        kept += (uint32_t)__popcll(m);
+      }
+      alive = kept;
+    }
+    uint32_t births = 0;
+    for (uint32_t k0 = 0; k0 < H.ncand; k0 += 64) {
+      const uint32_t k = k0 + lane;
+      births += (uint32_t)__popcll(__ballot(k < H.ncand && bflag[H.cstart + k] != 0));
+    }
+    const bool overflow = alive + births > H.cap;
+    if (births && !overflow) {
+      uint32_t done = 0;
+      for (uint32_t k0 = 0; k0 < H.ncand; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const bool f = k < H.ncand && bflag[H.cstart + k] != 0;
+        const unsigned long long m = __ballot(f);
+        if (f) {
+          const uint64_t from = H.base + k, to = H.base + alive + done + (uint32_t)__popcll(m & lt);
+          A.st.vx[to] = A.scratch.vx[from];
+          A.st.vy[to] = A.scratch.vy[from];
+          A.st.vz[to] = A.scratch.vz[from];
+          A.st.sp[to] = A.scratch.sp[from];
+          for (uint32_t mo = 0; mo < mm; ++mo)
+            A.st.lvl[mo * A.st.stride + to] = A.scratch.lvl[mo * A.scratch.stride + from];
+        }
+        done += (uint32_t)__popcll(m);
+      }
+    }
+    const uint32_t c = H.cell;
+    unsigned long long *out = A.cells.ctr + (size_t)c * kNumCtr;
+    for (uint32_t i = lane; i < nctr; i += 64) {
+      if (i == HCAO_CTR_CANDIDATES)
+        out[i] += H.ncand;
+      else if (i == HCAO_CTR_SUPPRESSED)
+        out[i] += H.excess + in[i];
+      else
+        out[i] += in[i];
+    }
+    if (lane == 0) {
+      if (overflow) atomicOr(A.err, kErrCapacity);
+      A.cells.cnt[c] = overflow ? alive : alive + births;
+      const double seen = __longlong_as_double((long long)H.sgbits);
+      A.cells.sgmax[c] = seen > H.sgmax ? seen : H.sgmax;
+      A.cells.rem[c] = H.rem_new;
+    }
   }
 }
 
@@ -1166,43 +1463,30 @@ __global__ void k_iota(uint32_t *x, uint64_t n) {
 // ---------------------------------------------------------------------------
 // launch wrappers (host side)
 // ---------------------------------------------------------------------------
-size_t step_lds_bytes(uint32_t lds_cap, uint32_t mm, int block) {
-  if (lds_cap == 0) return (size_t)2 * 2 * mm * block;
-  return tile_lds_bytes(lds_cap, mm, (uint32_t)block);
+size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block) {
+  const uint32_t ns = T.n_species, nr = T.n_reactions;
+  size_t b = sizeof(SpeciesTab) * ns + sizeof(PairTab) * ns * ns + sizeof(ReactionTab) * nr + 8 * (size_t)T.n_levels;
+  b += sizeof(CellHdr) * max_cells + 8 * (size_t)(8 + nr) * max_cells;
+  b += (size_t)2 * (2 + 3) * (T.max_modes ? T.max_modes : 1) * block;
+  return (b + 15) & ~(size_t)15;
 }
 
-hipError_t launch_step(const StepArgs &a, uint32_t mm, int block, uint32_t n_blocks, hipStream_t s) {
-  const size_t lds = step_lds_bytes(a.lds_cap, mm, block);
-  if (n_blocks == 0) return hipSuccess;
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, uint32_t n_groups, hipStream_t s) {
+  if (n_groups == 0) return hipSuccess;
   switch (block) {
-    case 64:
-      if (a.lds_cap)
-        hipLaunchKernelGGL((k_step<64, true>), dim3(n_blocks), dim3(64), lds, s, a);
-      else
-        hipLaunchKernelGGL((k_step<64, false>), dim3(n_blocks), dim3(64), lds, s, a);
-      break;
-    case 128:
-      if (a.lds_cap)
-        hipLaunchKernelGGL((k_step<128, true>), dim3(n_blocks), dim3(128), lds, s, a);
-      else
-        hipLaunchKernelGGL((k_step<128, false>), dim3(n_blocks), dim3(128), lds, s, a);
-      break;
-    case 256:
-      if (a.lds_cap)
-        hipLaunchKernelGGL((k_step<256, true>), dim3(n_blocks), dim3(256), lds, s, a);
-      else
-        hipLaunchKernelGGL((k_step<256, false>), dim3(n_blocks), dim3(256), lds, s, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 64: hipLaunchKernelGGL((k_step<64>), dim3(n_groups), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_step<128>), dim3(n_groups), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_step<256>), dim3(n_groups), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_step<512>), dim3(n_groups), dim3(512), lds, s, a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t set_step_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
-  const void *fns[] = {(const void *)k_step<64, true>, (const void *)k_step<128, true>,
-                       (const void *)k_step<256, true>};
+  const void *fns[] = {(const void *)k_step<64>, (const void *)k_step<128>, (const void *)k_step<256>,
+                       (const void *)k_step<512>};
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;

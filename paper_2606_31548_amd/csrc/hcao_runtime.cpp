@@ -17,8 +17,8 @@
 
 namespace hcao {
 // kernels (hcao_kernels.hip)
-size_t step_lds_bytes(uint32_t lds_cap, uint32_t mm, int block);
-hipError_t launch_step(const StepArgs &a, uint32_t mm, int block, uint32_t n_blocks, hipStream_t s);
+size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block);
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, uint32_t n_groups, hipStream_t s);
 hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
@@ -47,7 +47,8 @@ constexpr double kH = 6.62607015e-34;
 constexpr double kC = 299792458.0;
 constexpr double kB = 1.380649e-23;
 constexpr double kPi = 3.141592653589793;
-constexpr size_t kLdsBudget = 64 * 1024;  // LDS bytes per workgroup for the tile path
+constexpr size_t kLdsBudget = 64 * 1024;  // LDS bytes per workgroup of the step kernel
+constexpr uint32_t kMaxGroupCells = 64;   // cells per workgroup at most
 
 struct SpeciesHost {
   hcao_species_desc d;
@@ -90,6 +91,8 @@ struct DevBuf {
 
 struct hcao_ctx {
   hcao_config cfg{};
+  std::vector<double> rec_host;  // recombination factors, all reactions
+  DevBuf<double> d_rec;
   std::vector<double> volume, weight;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -115,9 +118,13 @@ struct hcao_ctx {
   DevBuf<double> d_volume, d_weight, sgmax, rem;
   DevBuf<unsigned long long> ctr;
   DevBuf<uint32_t> err;
-  DevBuf<uint32_t> lds_cells, big_cells;
-  uint32_t n_lds_cells = 0, n_big_cells = 0, lds_cap = 0;
-  int block = 64;
+  DevBuf<uint32_t> grp, work;
+  DevBuf<uint64_t> grp_work;
+  DevBuf<uint8_t> bflag;
+  uint32_t n_groups = 0, max_group_cells = 1;
+  size_t step_lds = 0;
+  int block = 256;
+  uint32_t group_slots = 4096;  // target slot capacity per workgroup
   uint32_t step = 0;
   bool timing = false;
   double timed_ms = 0.0;
@@ -208,14 +215,16 @@ void free_state(hcao_ctx *c) {
   c->sgmax.release();
   c->rem.release();
   c->ctr.release();
-  c->lds_cells.release();
-  c->big_cells.release();
+  c->grp.release();
+  c->grp_work.release();
+  c->work.release();
+  c->bflag.release();
   c->loaded = false;
 }
 
 uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
   if (c->cfg.capacity_per_cell) return c->cfg.capacity_per_cell;
-  return n + n / 2 + 32;
+  return n + n / 4 + 32;
 }
 
 State state_of(hcao_ctx *c) { return State{c->vx.p, c->vy.p, c->vz.p, c->sp.p, c->lvl.p, c->total_slots}; }
@@ -268,35 +277,43 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
                             c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_weight.p, c->weight.data(), nc * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
-  // tile path for cells whose capacity fits the LDS budget
-  uint32_t lcap = 0;
-  std::vector<uint32_t> small, big;
+  // products staging (indexed like the state)
+  HIP_TRY(c, c->bvx.alloc(tot));
+  HIP_TRY(c, c->bvy.alloc(tot));
+  HIP_TRY(c, c->bvz.alloc(tot));
+  HIP_TRY(c, c->bsp.alloc(tot));
+  HIP_TRY(c, c->blvl.alloc(tot * mm));
+  // workgroups over consecutive cells: at most kMaxGroupCells cells and
+  // about group_slots slots each
+  std::vector<uint32_t> grp{0};
+  std::vector<uint64_t> gw{0};
+  uint64_t slots = 0, wsum = 0;
+  uint32_t in_group = 0, max_cells = 1;
   for (uint32_t i = 0; i < nc; ++i) {
-    if (step_lds_bytes(c->cap_host[i], mm, c->block) <= kLdsBudget) {
-      small.push_back(i);
-      lcap = std::max(lcap, c->cap_host[i]);
-    } else {
-      big.push_back(i);
+    if (in_group > 0 && (in_group >= kMaxGroupCells || slots + c->cap_host[i] > c->group_slots)) {
+      grp.push_back(i);
+      gw.push_back(wsum);
+      max_cells = std::max(max_cells, in_group);
+      in_group = 0;
+      slots = 0;
     }
+    ++in_group;
+    slots += c->cap_host[i];
+    wsum += c->cap_host[i] / 2 + 1;
   }
-  c->lds_cap = lcap;
-  c->n_lds_cells = (uint32_t)small.size();
-  c->n_big_cells = (uint32_t)big.size();
-  if (!big.empty()) {
-    HIP_TRY(c, c->bvx.alloc(tot));
-    HIP_TRY(c, c->bvy.alloc(tot));
-    HIP_TRY(c, c->bvz.alloc(tot));
-    HIP_TRY(c, c->bsp.alloc(tot));
-    HIP_TRY(c, c->blvl.alloc(tot * mm));
-    HIP_TRY(c, c->big_cells.alloc(big.size()));
-    HIP_TRY(c, hipMemcpyAsync(c->big_cells.p, big.data(), big.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                              c->stream));
-  }
-  if (!small.empty() && !big.empty()) {
-    HIP_TRY(c, c->lds_cells.alloc(small.size()));
-    HIP_TRY(c, hipMemcpyAsync(c->lds_cells.p, small.data(), small.size() * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, c->stream));
-  }
+  grp.push_back(nc);
+  gw.push_back(wsum);
+  max_cells = std::max(max_cells, in_group);
+  c->n_groups = (uint32_t)grp.size() - 1;
+  c->max_group_cells = max_cells;
+  HIP_TRY(c, c->grp.alloc(grp.size()));
+  HIP_TRY(c, c->grp_work.alloc(gw.size()));
+  HIP_TRY(c, c->work.alloc(wsum));
+  HIP_TRY(c, c->bflag.alloc(wsum));
+  HIP_TRY(c, hipMemcpyAsync(c->grp.p, grp.data(), grp.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->grp_work.p, gw.data(), gw.size() * 8, hipMemcpyHostToDevice, c->stream));
+  c->step_lds = step_lds_bytes(c->tab, c->max_group_cells, c->block);
+  if (c->step_lds > kLdsBudget) return fail(c, HCAO_EUNSUPPORTED, "step kernel LDS budget exceeded");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return HCAO_OK;
 }
@@ -352,6 +369,120 @@ double solve_tvib(const SpeciesHost &s, double target) {
   return std::exp(0.5 * (lo + hi));
 }
 
+// ---------------------------------------------------------------------------
+// recombination: per-collision probability factors k_b / <sigma g>_BC
+// ---------------------------------------------------------------------------
+// regularized upper incomplete gamma Q(a, x), x > 0 (series below a + 1,
+// Lentz continued fraction above; Press et al., Numerical Recipes 6.2)
+double inc_gamma_q(double a, double x) {
+  if (!(x > 0.0)) return 1.0;
+  const double lpre = -x + a * std::log(x) - std::lgamma(a);
+  if (x < a + 1.0) {
+    double ap = a, del = 1.0 / a, sum = del;
+    for (int n = 1; n <= 1000; ++n) {
+      ap = ap + 1.0;
+      del = del * (x / ap);
+      sum = sum + del;
+      if (std::fabs(del) < std::fabs(sum) * 1e-17) break;
+    }
+    return 1.0 - sum * std::exp(lpre);
+  }
+  const double tiny = 1e-300;
+  double bb = x + 1.0 - a, cf = 1.0 / tiny, d = 1.0 / bb, h = d;
+  for (int i = 1; i <= 1000; ++i) {
+    const double an = -(double)i * ((double)i - a);
+    bb = bb + 2.0;
+    d = an * d + bb;
+    if (std::fabs(d) < tiny) d = tiny;
+    cf = bb + an / cf;
+    if (std::fabs(cf) < tiny) cf = tiny;
+    d = 1.0 / d;
+    const double del = d * cf;
+    h = h * del;
+    if (std::fabs(del - 1.0) < 1e-17) break;
+  }
+  return std::exp(lpre) * h;
+}
+
+// vibrational partition sum from the ground state
+double partition_vib(const SpeciesHost &s, double t) {
+  double qv = 1.0;
+  for (uint32_t b = 0; b < s.d.n_bend; ++b) qv = qv * (1.0 / (1.0 - std::exp(-s.theta[b] / t)));
+  for (const auto &L : s.levels) {
+    double z = 0.0;
+    for (size_t i = 0; i < L.size(); ++i) z = z + std::exp(-(L[i] - L[0]) / (kB * t));
+    qv = qv * z;
+  }
+  return qv;
+}
+
+// forward probability of the recombination section: Whitten-Rabinovich
+// density of states at n_samp evenly spaced energies up to D_e
+double wr_forward(const SpeciesHost &A, double de, double omega, uint32_t n_samp, double t) {
+  const uint32_t l = A.n_modes, nb = A.d.n_bend;
+  double nu_sum = 0.0, nu2_sum = 0.0;
+  for (uint32_t m = 0; m < l; ++m) {
+    const double nu = (m < nb) ? (kB * A.theta[m]) / kH : (A.levels[m - nb][1] - A.levels[m - nb][0]) / kH;
+    nu_sum = nu_sum + nu;
+    nu2_sum = nu2_sum + nu * nu;
+  }
+  const double ez = 0.5 * kH * nu_sum;
+  const double lm1 = (double)l - 1.0;
+  const double beta = (lm1 * lm1 * nu2_sum) / ((double)l * (nu_sum * nu_sum));
+  double num = 0.0, den = 0.0;
+  for (uint32_t i = 1; i <= n_samp; ++i) {
+    const double e = (double)(i - 1) * de / (double)(n_samp - 1);
+    const double r = e / ez;
+    const double omg =
+        (r >= 1.0) ? std::pow(10.0, -1.0506 * std::pow(r, 0.25)) : 1.0 / (5.0 * r + 2.73 * std::sqrt(r) + 3.51);
+    const double aw = 1.0 - beta * omg;
+    const double rho = std::pow(e + aw * ez, lm1);
+    const double w = rho * std::exp(-e / (kB * t));
+    num = num + inc_gamma_q(2.5 - omega, (de - e) / (kB * t)) * w;
+    den = den + w;
+  }
+  return den > 0.0 ? num / den : 0.0;
+}
+
+// k_b / <sigma g>_BC on the log-T grid, per third-body species (appended to out)
+void build_recombination_table(const hcao_ctx *c, const hcao_reaction_desc &d, const Tables &T,
+                               std::vector<double> &out) {
+  const SpeciesHost &B = c->species[d.reactant[0]], &C = c->species[d.reactant[1]], &A = c->species[d.product[0]];
+  uint32_t j = 0;
+  while (!((d.stretch_mask >> j) & 1ull)) ++j;
+  const double de = A.de[j];
+  const double de0 = ((B.d.formation_J + B.zpe) + (C.d.formation_J + C.zpe)) - (A.d.formation_J + A.zpe);
+  const PairTab &PBC = T.pr[d.reactant[0]][d.reactant[1]];
+  const double w_bc = 1.0 - PBC.esg;
+  const double d_bc = (B.d.dref_m + C.d.dref_m) * 0.5, t_bc = (B.d.Tref_K + C.d.Tref_K) * 0.5;
+  const uint32_t ns = T.n_species, n_samp = d.n_samp ? d.n_samp : 1000;
+  const size_t off = out.size();
+  out.resize(off + (size_t)ns * kRecNodes, 0.0);
+  for (uint32_t i = 0; i < kRecNodes; ++i) {
+    const double t = std::exp(T.rec_l0 + (double)i / T.rec_inv_step);
+    const double sg_bc = 2.0 * (d_bc * d_bc) * std::sqrt((2.0 * kPi * kB * t_bc) / PBC.mr) * std::pow(t / t_bc, 1.0 - w_bc);
+    const double ktr = (2.0 * kPi * kB * t) / (kH * kH);
+    const double keq = std::pow(ktr, 1.5) * std::pow((B.d.mass_kg * C.d.mass_kg) / A.d.mass_kg, 1.5) *
+                       ((partition_vib(B, t) * partition_vib(C, t)) / partition_vib(A, t)) * std::exp(-de0 / (kB * t));
+    double p_w = -1.0, p = 0.0;  // P depends on the third body only through omega
+    for (uint32_t m = 0; m < ns; ++m) {
+      const hcao_species_desc &M = c->species[m].d;
+      const double w = (A.d.omega + M.omega) * 0.5, dd = (A.d.dref_m + M.dref_m) * 0.5,
+                   tr = (A.d.Tref_K + M.Tref_K) * 0.5;
+      const double mred = (A.d.mass_kg * M.mass_kg) / (A.d.mass_kg + M.mass_kg);
+      const double delta = ((uint32_t)d.product[0] == m) ? 2.0 : 1.0;
+      if (w != p_w) {
+        p = wr_forward(A, de, w, n_samp, t);
+        p_w = w;
+      }
+      const double kf =
+          p * ((2.0 * (dd * dd)) / delta) * std::sqrt((2.0 * kPi * kB * tr) / mred) * std::pow(t / tr, 1.0 - w);
+      const double v = (kf / keq) / sg_bc;
+      out[off + (size_t)m * kRecNodes + i] = (v == v && v >= 0.0) ? v : 0.0;
+    }
+  }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -396,7 +527,11 @@ hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out) {
   c->stream = (hipStream_t)cfg->hip_stream;
   if (const char *b = std::getenv("HCAO_BLOCK")) {
     const int v = std::atoi(b);
-    if (v == 64 || v == 128 || v == 256) c->block = v;
+    if (v == 64 || v == 128 || v == 256 || v == 512) c->block = v;
+  }
+  if (const char *g = std::getenv("HCAO_GROUP_SLOTS")) {
+    const long v = std::atol(g);
+    if (v >= 1 && v <= (1L << 30)) c->group_slots = (uint32_t)v;
   }
   const char *step = "hipSetDevice";
   hipError_t e = hipSetDevice(c->device);
@@ -495,7 +630,14 @@ hcao_status hcao_add_reaction(hcao_ctx *c, const hcao_reaction_desc *d, int32_t 
       r.alpha.push_back(a);
     }
   } else if (d->kind == HCAO_RX_RECOMBINATION) {
-    return fail(c, HCAO_EUNSUPPORTED, "recombination is not available in this build");
+    const int b = d->reactant[0], cc = d->reactant[1], a = d->product[0];
+    if (!ok(a) || !ok(b) || !ok(cc) || b == cc) return fail(c, HCAO_EINVAL, "bad recombination species");
+    const SpeciesHost &A = c->species[a];
+    const uint32_t nst = A.d.n_stretch;
+    if (nst == 0 || d->stretch_mask == 0 || (nst < 64 && (d->stretch_mask >> nst) != 0))
+      return fail(c, HCAO_EINVAL, "stretch mask must name stretches of A");
+    const double msum = c->species[b].d.mass_kg + c->species[cc].d.mass_kg;
+    if (std::fabs(msum - A.d.mass_kg) > 1e-9 * A.d.mass_kg) return fail(c, HCAO_EINVAL, "m_A != m_B + m_C");
   } else {
     return fail(c, HCAO_EINVAL, "unknown reaction kind");
   }
@@ -560,12 +702,26 @@ hcao_status hcao_finalize(hcao_ctx *c) {
       P.esg = 1.0 - w;
       P.q = 1.5 - w;
     }
+  T.rec_nt = kRecNodes;
+  T.rec_l0 = std::log(kRecTmin);
+  T.rec_inv_step = (double)(kRecNodes - 1) / std::log(kRecTmax / kRecTmin);
+  c->rec_host.clear();
   for (uint32_t r = 0; r < T.n_reactions; ++r) {
     const ReactionHost &h = c->reactions[r];
     ReactionTab &R = T.rx[r];
     R.kind = (int32_t)h.d.kind;
     R.mask = h.d.stretch_mask;
-    if (h.d.kind == HCAO_RX_DISSOCIATION) {
+    if (h.d.kind == HCAO_RX_RECOMBINATION) {
+      const int b = h.d.reactant[0], cc = h.d.reactant[1], a = h.d.product[0];
+      R.a = b;
+      R.b = cc;
+      R.c = a;
+      R.d = -1;
+      R.dh = c->species[a].d.formation_J - (c->species[b].d.formation_J + c->species[cc].d.formation_J);
+      R.rec_off = c->rec_host.size();
+      T.has_recomb = 1;
+      build_recombination_table(c, h.d, T, c->rec_host);
+    } else if (h.d.kind == HCAO_RX_DISSOCIATION) {
       const int a = h.d.reactant[0], pc = h.d.product[0], pd = h.d.product[1];
       R.a = a;
       R.b = -1;
@@ -588,6 +744,10 @@ hcao_status hcao_finalize(hcao_ctx *c) {
   }
   HIP_TRY(c, c->d_tab.alloc(1));
   HIP_TRY(c, c->d_lev.alloc(c->lev_host.size()));
+  HIP_TRY(c, c->d_rec.alloc(c->rec_host.size()));
+  if (!c->rec_host.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->d_rec.p, c->rec_host.data(), c->rec_host.size() * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->d_tab.p, &T, sizeof(Tables), hipMemcpyHostToDevice, c->stream));
   if (!c->lev_host.empty())
     HIP_TRY(c, hipMemcpyAsync(c->d_lev.p, c->lev_host.data(), c->lev_host.size() * sizeof(double),
@@ -708,24 +868,15 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
   a.err = c->err.p;
   a.seed = c->cfg.seed;
   a.dt = dt;
-  const uint32_t mm = c->max_modes ? c->max_modes : 1;
+  a.rec = c->d_rec.p;
+  a.grp = c->grp.p;
+  a.grp_work = c->grp_work.p;
+  a.work = c->work.p;
+  a.bflag = c->bflag.p;
   if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   for (uint32_t s = 0; s < n_steps; ++s) {
     a.step = c->step;
-    if (c->n_lds_cells) {
-      StepArgs b = a;
-      b.lds_cap = c->lds_cap;
-      b.cell_list = c->n_big_cells ? c->lds_cells.p : nullptr;
-      b.n_launch_cells = c->n_lds_cells;
-      HIP_TRY(c, launch_step(b, mm, c->block, c->n_lds_cells, c->stream));
-    }
-    if (c->n_big_cells) {
-      StepArgs b = a;
-      b.lds_cap = 0;
-      b.cell_list = c->big_cells.p;
-      b.n_launch_cells = c->n_big_cells;
-      HIP_TRY(c, launch_step(b, mm, 256, c->n_big_cells, c->stream));
-    }
+    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->n_groups, c->stream));
     c->step += 1;
   }
   if (c->timing) {
@@ -895,6 +1046,17 @@ hcao_status hcao_get_pair(const hcao_ctx *c, uint32_t a, uint32_t b, double *out
   return HCAO_OK;
 }
 
+hcao_status hcao_get_recombination_table(const hcao_ctx *c, uint32_t reaction, double *out, uint32_t max_n,
+                                         uint32_t *n_out) {
+  if (!c || !c->finalized || reaction >= c->reactions.size()) return HCAO_EINVAL;
+  const ReactionTab &R = c->tab.rx[reaction];
+  if (R.kind != HCAO_RX_RECOMBINATION) return HCAO_EINVAL;
+  const uint32_t n = (uint32_t)c->species.size() * kRecNodes;
+  for (uint32_t i = 0; i < n && i < max_n; ++i) out[i] = c->rec_host[R.rec_off + i];
+  if (n_out) *n_out = n;
+  return HCAO_OK;
+}
+
 hcao_status hcao_set_timing(hcao_ctx *c, int enable) {
   if (!c) return HCAO_EINVAL;
   c->timing = enable != 0;
@@ -1003,6 +1165,7 @@ void hcao_destroy(hcao_ctx *c) {
   free_state(c);
   c->d_tab.release();
   c->d_lev.release();
+  c->d_rec.release();
   c->err.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

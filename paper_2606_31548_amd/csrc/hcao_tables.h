@@ -36,15 +36,26 @@ struct PairTab {
   double mr, hm, m_a, m_b, msum, wa, wb, csg, esg, q;
 };
 
+// Recombination B + C (+M) -> A (+M) is stored with a = B, b = C, c = A,
+// d = -1; its probability factors k_b / <sigma g>_BC [m^3] per third-body
+// species and log-spaced temperature node start at rec_off in the
+// recombination array.
 struct ReactionTab {
   int32_t kind, a, b, c, d, pad;
   uint64_t mask;
   double alpha[kMaxModes];
   double steric, ea, dh, zsum;
+  uint64_t rec_off;
 };
+
+constexpr uint32_t kRecNodes = 1024;
+constexpr double kRecTmin = 100.0;
+constexpr double kRecTmax = 5.0e4;
 
 struct Tables {
   uint32_t n_species, n_reactions, max_modes, n_levels;
+  uint32_t has_recomb, rec_nt, pad0, pad1;
+  double rec_l0, rec_inv_step;  // log T of node 0; nodes per unit of log T
   SpeciesTab sp[kMaxSpecies];
   PairTab pr[kMaxSpecies][kMaxSpecies];
   ReactionTab rx[kMaxReactions];
@@ -69,15 +80,20 @@ struct CellArrays {
   unsigned long long *ctr;  // [n_cells][kNumCtr]
 };
 
+// One workgroup processes the consecutive cells [grp[b], grp[b+1]); its work
+// list and product flags live at grp_work[b] in work / bflag (sized for
+// sum over its cells of cap/2 + 1 entries).
 struct StepArgs {
   const Tables *tab;
   const double *lev;
   State st;
-  State scratch;  // newborn staging for cells processed from global memory
+  State scratch;  // products of the step, at the cell's base + pair index
   CellArrays cells;
-  const uint32_t *cell_list;  // cells of this launch (nullptr: cell = block index)
-  uint32_t n_launch_cells;
-  uint32_t lds_cap;  // slot capacity of the LDS tile (0: global-memory path)
+  const double *rec;  // recombination factors
+  const uint32_t *grp;
+  const uint64_t *grp_work;
+  uint32_t *work;
+  uint8_t *bflag;
   uint32_t *err;
   uint64_t seed;
   uint32_t step;

@@ -102,6 +102,7 @@ def load_library():
     L.hcao_read_reaction_counts.argtypes = [_vp, _vp]
     L.hcao_get_levels.argtypes = [_vp, _u32, _u32, _vp, _u32, ctypes.POINTER(_u32)]
     L.hcao_get_pair.argtypes = [_vp, _u32, _u32, _vp]
+    L.hcao_get_recombination_table.argtypes = [_vp, _u32, _vp, _u32, ctypes.POINTER(_u32)]
     L.hcao_set_timing.argtypes = [_vp, ctypes.c_int]
     L.hcao_kernel_time.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(_u64)]
     L.hcao_save.argtypes = [_vp, ctypes.c_char_p]
@@ -110,7 +111,7 @@ def load_library():
     for name in ("hcao_create", "hcao_add_species", "hcao_add_reaction", "hcao_finalize", "hcao_load_particles",
                  "hcao_init_thermal", "hcao_step", "hcao_sync", "hcao_get_counts", "hcao_read_particles",
                  "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
-                 "hcao_get_pair", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore"):
+                 "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -283,6 +284,13 @@ class Simulation:
         out = np.zeros(8, np.float64)
         self._chk("hcao_get_pair", self._L.hcao_get_pair(self._h, a, b, _p(out)))
         return dict(zip(("mr", "hm", "msum", "wa", "wb", "csg", "esg", "q"), out))
+
+    def recombination_table(self, reaction):
+        out = np.zeros(self.n_species * 1024, np.float64)
+        n = _u32()
+        self._chk("hcao_get_recombination_table", self._L.hcao_get_recombination_table(
+            self._h, reaction, _p(out), len(out), ctypes.byref(n)))
+        return out[:n.value].reshape(self.n_species, -1)
 
     def set_timing(self, enable: bool):
         self._chk("hcao_set_timing", self._L.hcao_set_timing(self._h, int(enable)))

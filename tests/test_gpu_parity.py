@@ -147,10 +147,13 @@ def test_step_parity_ragged_cells_mixed_paths(orc, hc):
 
 
 def test_launch_shape_invariance(orc, hc, monkeypatch):
-    wl = W.methane_argon(n_cells=16, per_cell=256)
+    """Workgroup size and the number of cells per workgroup do not change
+    any bit of the result."""
+    wl = W.methane_argon(n_cells=40, per_cell=256)
     outs = []
-    for block in ("64", "128", "256"):
+    for block, slots in (("64", "1"), ("128", "700"), ("256", "4096"), ("512", "100000")):
         monkeypatch.setenv("HCAO_BLOCK", block)
+        monkeypatch.setenv("HCAO_GROUP_SLOTS", slots)
         g = hc.from_workload(wl)
         g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
         g.step(wl.dt, 30)
@@ -237,3 +240,30 @@ def test_capacity_overflow_is_reported(hc):
     assert e.value.code == -5
     with pytest.raises(hc.HcaoError):
         g.step(wl.dt, 1)
+
+
+def test_recombination_tables_are_bitwise_equal(orc, hc):
+    wl = W.methane_chemistry(n_cells=2, per_cell=16, recombination=True)
+    o, g = _both(orc, hc, wl)
+    a = o.rec_table(2)
+    b = g.recombination_table(2)
+    assert a.shape == b.shape
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_step_parity_recombination_dense(orc, hc):
+    """Three-body recombination exercised hard (n = 3e26 m^-3): deaths,
+    compaction of survivors and products in one step, all three reactions."""
+    wl = W.methane_chemistry(n_cells=24, per_cell=256, recombination=True, t=6000.0)
+    wl.cell_weight = wl.cell_weight * 3e4
+    wl.dt = 5e-14
+    o, g = _run_parity(orc, hc, wl, 30, [1, 29])
+    ctr = o.counters().sum(0)
+    assert ctr[orc.CTR_DEATHS] > 0 and ctr[orc.CTR_BIRTHS] > 0
+    assert ctr[orc.CTR_REACTION0 + 1] > 0
+
+
+def test_step_parity_chemistry_config_density(orc, hc):
+    """CH4/CH3/H/H2 with all three reactions at 1e22 m^-3, 8000 K."""
+    wl = W.methane_chemistry(n_cells=48, per_cell=256, recombination=True)
+    _run_parity(orc, hc, wl, 40, [40])

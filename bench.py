@@ -132,7 +132,7 @@ def main():
     sim.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kernel_ms, launches = sim.kernel_time()
+    kernel_ms, launches, kernel_steps = sim.kernel_time()
     sim.set_timing(False)
     _, _, ctr1 = sim.cell_state()
     tot1 = sim.moments()
@@ -143,9 +143,12 @@ def main():
     trials = int(ctr1[:, hcao.CTR_TRIALS].sum() - ctr0[:, hcao.CTR_TRIALS].sum())
     reactions = int(ctr1[:, hcao.CTR_REACTION0:].sum() - ctr0[:, hcao.CTR_REACTION0:].sum())
     n_mean = 0.5 * (tot0.n_total + tot1.n_total)
-    # algorithmic bytes per launch (one launch = one step over all cells)
-    b_alg = 0.5 * (algorithmic_bytes(wl.species, per_species0, wl.n_cells) +
-                   algorithmic_bytes(wl.species, per_species1, wl.n_cells))
+    # algorithmic bytes per launch: per step, every live particle's state read
+    # and written once plus 64 B per cell; a launch advances kernel_steps/launches steps
+    b_step = 0.5 * (algorithmic_bytes(wl.species, per_species0, wl.n_cells) +
+                    algorithmic_bytes(wl.species, per_species1, wl.n_cells))
+    steps_per_launch = kernel_steps / max(launches, 1)
+    b_alg = b_step * steps_per_launch
     avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
     achieved = b_alg / avg_launch_s / 1e9
 
@@ -171,7 +174,8 @@ def main():
         "sampler_trials_per_collision": trials / max(coll, 1),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step", "bytes_per_launch": b_alg, "mean_launch_us": avg_launch_s * 1e6},
+                     "kernel": "k_step", "bytes_per_launch": b_alg, "steps_per_launch": steps_per_launch,
+                     "mean_launch_us": avg_launch_s * 1e6},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

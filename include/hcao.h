@@ -249,11 +249,14 @@ hcao_status hcao_get_pair(const hcao_ctx *ctx, uint32_t a, uint32_t b, double *o
 hcao_status hcao_get_recombination_table(const hcao_ctx *ctx, uint32_t reaction, double *out, uint32_t max_n,
                                          uint32_t *n_out);
 
-/* Kernel timing over the stream: when enabled, the library records HIP
- * events around each step-kernel launch; hcao_kernel_time returns the
- * summed elapsed milliseconds and the number of launches since enabling. */
+/* Kernel timing over the stream: when enabled, each hcao_step call records
+ * HIP events on the context's stream around its step-kernel launches;
+ * hcao_kernel_time returns the summed elapsed milliseconds, the number of
+ * launches and the number of steps they advanced since enabling. A launch
+ * advances every cell by up to HCAO_STEPS_PER_LAUNCH steps (environment
+ * variable; default: all steps of the call). */
 hcao_status hcao_set_timing(hcao_ctx *ctx, int enable);
-hcao_status hcao_kernel_time(hcao_ctx *ctx, double *ms, uint64_t *launches);
+hcao_status hcao_kernel_time(hcao_ctx *ctx, double *ms, uint64_t *launches, uint64_t *steps);
 
 /* Checkpoint of the full state (particles, per-cell state, step index). */
 hcao_status hcao_save(hcao_ctx *ctx, const char *path);

@@ -205,12 +205,13 @@ double orc_detpow(double x, double y) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Keyed permutation of [0, n): 10-round Feistel on 2b bits, cycle walk */
-/* ------------------------------------------------------------------ */
+/* Keyed permutation of [0, n): Feistel network on 2b bits (Luby-Rackoff),
+ * 16 rounds for half widths b <= 3 and 10 rounds above, cycle walking
+ * (Black-Rogaway) into [0, n). The round function uses 24-bit factors. */
 static uint32_t feistel_round(uint32_t r, uint32_t key, uint32_t mask) {
-  uint32_t h = (r ^ key) * 0x9E3779B1u;
-  h ^= h >> 16;
-  h *= 0x85EBCA6Bu;
+  uint32_t h = ((r ^ key) & 0xFFFFFFu) * 0x9E3779u;
+  h ^= h >> 15;
+  h = (h & 0xFFFFFFu) * 0x85EBCBu;
   h ^= h >> 13;
   return h & mask;
 }
@@ -221,10 +222,11 @@ static uint32_t feistel_half_bits(uint32_t n) {
   return b;
 }
 
-static uint32_t feistel_once(uint32_t x, uint32_t b, const uint32_t keys[10]) {
+static uint32_t feistel_once(uint32_t x, uint32_t b, const uint32_t keys[16]) {
   uint32_t mask = ((uint32_t)1 << b) - 1u;
+  uint32_t rounds = b <= 3 ? 16 : 10;
   uint32_t left = x >> b, right = x & mask;
-  for (int r = 0; r < 10; ++r) {
+  for (uint32_t r = 0; r < rounds; ++r) {
     uint32_t nl = right;
     uint32_t nr = left ^ feistel_round(right, keys[r], mask);
     left = nl;
@@ -233,7 +235,7 @@ static uint32_t feistel_once(uint32_t x, uint32_t b, const uint32_t keys[10]) {
   return (left << b) | right;
 }
 
-uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[10], uint32_t i) {
+uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[16], uint32_t i) {
   uint32_t b = feistel_half_bits(n);
   uint32_t y = feistel_once(i, b, keys);
   while (y >= n) y = feistel_once(y, b, keys);
@@ -1398,9 +1400,9 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     C->ctr[ORC_CTR_SUPPRESSED] += ncand - n / 2;
     ncand = n / 2;
   }
-  /* ten Feistel round keys: words 0..9 of blocks 0, 1, 2 of the cell stream */
-  uint32_t keys[12];
-  for (uint32_t blk = 0; blk < 3; ++blk) {
+  /* sixteen Feistel round keys: blocks 0..3 of the cell stream */
+  uint32_t keys[16];
+  for (uint32_t blk = 0; blk < 4; ++blk) {
     uint32_t ctr[4] = {blk, 0xFFFFFFFFu, c, o->step};
     orc_philox4x32_10((uint32_t)o->seed, (uint32_t)(o->seed >> 32), ctr, keys + 4 * blk);
   }

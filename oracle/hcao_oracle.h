@@ -47,7 +47,7 @@ void orc_philox4x32_10(uint32_t k0, uint32_t k1, const uint32_t ctr[4], uint32_t
 double orc_detlog(double x);
 double orc_detexp(double x);
 double orc_detpow(double x, double y);
-uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[10], uint32_t i);
+uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[16], uint32_t i);
 
 /* ---- context ---- */
 int orc_create(uint64_t seed, uint32_t n_cells, const double *cell_volume, const double *cell_weight,

@@ -35,8 +35,9 @@ __device__ __forceinline__ void philox10(uint32_t k0, uint32_t k1, uint32_t &x0,
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
-    const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * x0, p1 = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t y0 = hi1 ^ x1 ^ k0;
     const uint32_t y2 = hi0 ^ x3 ^ k1;
     x0 = y0;
@@ -46,12 +47,14 @@ __device__ __forceinline__ void philox10(uint32_t k0, uint32_t k1, uint32_t &x0,
   }
 }
 
-// A stream (seed; pair, cell, step): each Philox block yields two 64-bit
-// draws, low word first.
-struct Rng {
+// A stream (seed; pair, cell, step). The fp64 form takes one 64-bit draw
+// (two words, low first) per uniform, (u >> 11) 2^-53; the mixed form takes
+// one 32-bit word per uniform, (w >> 8) 2^-24 (exact in either type).
+template <bool MIX>
+struct RngT {
   uint32_t k0, k1, pair, cell, step, block;
   uint32_t w0, w1, w2, w3;
-  uint32_t used;
+  uint32_t used;  // words consumed from the current block
 
   __device__ __forceinline__ void open(uint64_t seed, uint32_t p, uint32_t c, uint32_t s) {
     k0 = (uint32_t)seed;
@@ -62,7 +65,7 @@ struct Rng {
     block = 0;
     used = 4;
   }
-  __device__ __attribute__((noinline)) void refill() {
+  __device__ __forceinline__ void refill() {
     uint32_t x0 = block, x1 = pair, x2 = cell, x3 = step;
     philox10(k0, k1, x0, x1, x2, x3);
     w0 = x0;
@@ -78,8 +81,19 @@ struct Rng {
     used += 2;
     return r;
   }
-  __device__ __forceinline__ double uniform() { return (double)(next64() >> 11) * 0x1p-53; }
+  __device__ __forceinline__ uint32_t next32() {
+    if (used >= 4) refill();
+    const uint32_t r = used == 0 ? w0 : (used == 1 ? w1 : (used == 2 ? w2 : w3));
+    used += 1;
+    return r;
+  }
+  __device__ __forceinline__ double uniform() {
+    if (MIX) return (double)((float)(next32() >> 8) * 0x1p-24f);
+    return (double)(next64() >> 11) * 0x1p-53;
+  }
+  __device__ __forceinline__ float uniform_f() { return (float)(next32() >> 8) * 0x1p-24f; }
 };
+using Rng = RngT<false>;
 
 // ---------------------------------------------------------------------------
 // Fixed-sequence exp / log / pow (Cody-Waite reduction + fixed series)
@@ -161,31 +175,68 @@ __device__ __forceinline__ double dpow(double x, double y) {
   return dexp(y * dlog(x));
 }
 
+// Exact comparisons against a power through a single-precision filter.
+// est = 2^(y log2 x) from the hardware log2/exp2 (v_log_f32, v_exp_f32) is
+// within 5e-6 of x^y for x in [2^-53, 2^64] and y in (0, 1] (measured over
+// 1.7e7 operands); a decision further than kFilter from est is the one the
+// fp64 power gives, and only the band in between evaluates dpow. The
+// result of every comparison is therefore that of the fp64 expression.
+constexpr double kFilter = 1e-4;
+
+__device__ __forceinline__ double pow_estimate(double x, double y) {
+  return (double)__builtin_amdgcn_exp2f((float)y * __builtin_amdgcn_logf((float)x));
+}
+
+// u < x^y (as dpow computes it), for x in (0, 1] and y in (0, 1]
+__device__ __forceinline__ bool below_pow(double u, double x, double y) {
+  const double est = pow_estimate(x, y);
+  if (u < est * (1.0 - kFilter)) return true;
+  if (u > est * (1.0 + kFilter)) return false;
+  return u < dpow(x, y);
+}
+
 // ---------------------------------------------------------------------------
-// keyed permutation of [0, n): 10-round Feistel network on 2b bits with
-// cycle walking (Luby-Rackoff; Black-Rogaway)
+// keyed permutation of [0, n): Feistel network on 2b bits (Luby-Rackoff),
+// 16 rounds for b <= 3 and 10 above, cycle walking (Black-Rogaway); the
+// round function multiplies 24-bit factors (full-rate v_mul_u32_u24)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t feistel_f(uint32_t r, uint32_t key, uint32_t mask) {
-  uint32_t h = (r ^ key) * 0x9E3779B1u;
-  h ^= h >> 16;
-  h *= 0x85EBCA6Bu;
+  uint32_t h = __umul24(r ^ key, 0x9E3779u);
+  h ^= h >> 15;
+  h = __umul24(h, 0x85EBCBu);
   h ^= h >> 13;
   return h & mask;
 }
 
 struct Perm {
-  uint32_t n, b, mask;
-  uint32_t k[10];
-  __device__ __forceinline__ uint32_t once(uint32_t x) const {
+  uint32_t n, b, mask, rounds;
+  uint32_t k[16];
+};
+
+// the permutation evaluated with its keys in registers
+struct PermReg {
+  uint32_t n, b, mask, rounds;
+  uint32_t k[16];
+  __device__ __forceinline__ void load(const Perm &P) {
+    n = P.n;
+    b = P.b;
+    mask = P.mask;
+    rounds = P.rounds;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) k[i] = P.k[i];
+  }
+  template <int R>
+  __device__ __forceinline__ uint32_t once_r(uint32_t x) const {
     uint32_t l = x >> b, r = x & mask;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < R; ++i) {
       const uint32_t nr = l ^ feistel_f(r, k[i], mask);
       l = r;
       r = nr;
     }
     return (l << b) | r;
   }
+  __device__ __forceinline__ uint32_t once(uint32_t x) const { return rounds == 10 ? once_r<10>(x) : once_r<16>(x); }
   __device__ __forceinline__ uint32_t operator()(uint32_t i) const {
     uint32_t y = once(i);
     while (y >= n) y = once(y);
@@ -199,19 +250,17 @@ __device__ __forceinline__ void make_perm(Perm &P, uint32_t n, uint64_t seed, ui
   while ((1ull << (2 * b)) < (unsigned long long)n) ++b;
   P.b = b;
   P.mask = (1u << b) - 1u;
+  P.rounds = b <= 3 ? 16u : 10u;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  uint32_t w[12];
 #pragma unroll
-  for (uint32_t blk = 0; blk < 3; ++blk) {
+  for (uint32_t blk = 0; blk < 4; ++blk) {
     uint32_t x0 = blk, x1 = 0xFFFFFFFFu, x2 = cell, x3 = step;
     philox10(k0, k1, x0, x1, x2, x3);
-    w[4 * blk] = x0;
-    w[4 * blk + 1] = x1;
-    w[4 * blk + 2] = x2;
-    w[4 * blk + 3] = x3;
+    P.k[4 * blk] = x0;
+    P.k[4 * blk + 1] = x1;
+    P.k[4 * blk + 2] = x2;
+    P.k[4 * blk + 3] = x3;
   }
-#pragma unroll
-  for (int i = 0; i < 10; ++i) P.k[i] = w[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -254,11 +303,17 @@ __device__ __forceinline__ uint32_t mode_top(const SpeciesTab &S, const double *
     fi = fi > 65535.0 ? 65535.0 : fi;
     return (uint32_t)fi;
   }
+  // highest level strictly below e (the table increases strictly), at least 0
   const double *L = lev + S.lev_off[m];
-  const uint32_t idiss = S.idiss[m];
-  uint32_t top = 0;
-  while (top < idiss && L[top + 1] < e) ++top;
-  return top;
+  uint32_t lo = 0, hi = S.idiss[m];
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (L[mid] < e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 __device__ __forceinline__ uint32_t pick_level(uint32_t top, double u) {
@@ -290,7 +345,7 @@ __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint3
         sum = sum + mode_energy(S, C.T.lev, m, i);
       }
       const double ua = rng.uniform();
-      const bool ok = (sum < e_coll) && (ua < dpow((e_coll - sum) / denom, q));
+      const bool ok = (sum < e_coll) && below_pow(ua, (e_coll - sum) / denom, q);
       if (ok) {
         for (uint32_t m = 0; m < nm; ++m) lv[m * stride] = cand[m * C.block];
         e_tr = e_coll - sum;
@@ -314,7 +369,7 @@ __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint3
       const uint32_t i = pick_level(top, rng.uniform());
       const double ei = mode_energy(S, C.T.lev, m, i);
       const double ua = rng.uniform();
-      const bool ok = (ei < ec) && (ua < dpow((ec - ei) / den, q));
+      const bool ok = (ei < ec) && below_pow(ua, (ec - ei) / den, q);
       if (ok) {
         lv[m * stride] = (uint16_t)i;
         et = ec - ei;
@@ -399,29 +454,128 @@ struct Channel {
   int32_t rx, side, mode;
 };
 
+// Channel enumeration of one pair (dissociation channels of p then q, then
+// exchange channels of p then q, registration order). Pass 0 draws the
+// steric numbers, counts the open channels and sums their excess energy;
+// pass 1 repeats the same arithmetic to find the channel that holds target.
+struct ChannelScan {
+  uint32_t nch;
+  double total;
+  Channel first, last, pick;
+  bool found;
+};
+
+__device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32_t sp1, double ev0, double ev1,
+                                              const uint16_t *lv0, const uint16_t *lv1, uint32_t ls, double e_tr,
+                                              Rng &rng, uint64_t &steric_ok, int pass, double target,
+                                              ChannelScan &S) {
+  double cum = 0.0;
+  uint32_t seen = 0, ex_i = 0;
+  for (uint32_t kind = 0; kind < 2; ++kind) {
+    for (uint32_t side = 0; side < 2; ++side) {
+      const uint32_t A = side ? sp1 : sp0, B = side ? sp0 : sp1;
+      const double evA = side ? ev1 : ev0, evB = side ? ev0 : ev1;
+      const uint16_t *lA = side ? lv1 : lv0;
+      const SpeciesTab &SA = T.sp[A];
+      for (uint32_t r = 0; r < T.nr; ++r) {
+        const ReactionTab &R = T.rx[r];
+        if (kind == 0) {
+          if (R.kind != HCAO_RX_DISSOCIATION || (uint32_t)R.a != A) continue;
+          const uint32_t nst = SA.n_modes - SA.n_bend;
+          for (uint32_t j = 0; j < nst; ++j) {
+            if (!((R.mask >> j) & 1ull)) continue;
+            const uint32_t m = SA.n_bend + j;
+            // Eq. Ecoll-diss: E_tr + E_vib,A - sum ZPE(A, B, C) + E_A,j(0)
+            const double ecoll = ((e_tr + evA) - R.zsum) + T.lev[SA.lev_off[m]];
+            const double eex = ecoll - SA.de[m];
+            const double pool = (e_tr + evA) - R.dh;
+            const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+            if (eex > 0.0 && left > 0.0 && seen < (uint32_t)kMaxChannels) {
+              const Channel ch{(int32_t)r, (int32_t)side, (int32_t)m};
+              ++seen;
+              if (pass == 0) {
+                if (seen == 1) S.first = ch;
+                S.last = ch;
+                S.total = S.total + eex;
+              } else if (!S.found) {
+                cum = cum + eex;
+                if (target < cum) {
+                  S.pick = ch;
+                  S.found = true;
+                }
+              }
+            }
+          }
+        } else {
+          if (R.kind != HCAO_RX_EXCHANGE || (uint32_t)R.a != A || (uint32_t)R.b != B) continue;
+          bool st_ok;
+          if (pass == 0) {
+            st_ok = rng.uniform() < R.steric;
+            if (st_ok && ex_i < 64) steric_ok |= (1ull << ex_i);
+          } else {
+            st_ok = ex_i < 64 ? ((steric_ok >> ex_i) & 1ull) != 0 : false;
+          }
+          ++ex_i;
+          // Eq. Ecoll-exch: E_tr + sum_j alpha_j E_vib,A,j
+          double ecoll = e_tr;
+          for (uint32_t m = 0; m < SA.n_modes; ++m)
+            ecoll = ecoll + R.alpha[m] * mode_energy(SA, T.lev, m, lA[m * ls]);
+          const double eex = ecoll - R.ea;
+          const double pool = ((e_tr + evA) + evB) - R.dh;
+          const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+          if (st_ok && eex > 0.0 && left > 0.0 && seen < (uint32_t)kMaxChannels) {
+            const Channel ch{(int32_t)r, (int32_t)side, -1};
+            ++seen;
+            if (pass == 0) {
+              if (seen == 1) S.first = ch;
+              S.last = ch;
+              S.total = S.total + eex;
+            } else if (!S.found) {
+              cum = cum + eex;
+              if (target < cum) {
+                S.pick = ch;
+                S.found = true;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  if (pass == 0) S.nch = seen;
+}
+
 // Reaction decision and application, or relaxation of both molecules, then
 // scattering, for one accepted pair held in P. Returns the reaction id or -1.
+// The outcome is decided first; the molecules to relax are then queued (at
+// most two, in draw order) and run through one sampler loop, and the
+// velocities come from at most two isotropic splits.
 __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const double *rec) {
   const Tab &T = C.T;
   const uint32_t mm = T.mm;
   const uint32_t ls = P.ls;
-  const uint32_t sps[2] = {P.sp0, P.sp1};
-  const PairTab &PP = T.pair(P.sp0, P.sp1);
-  double e_tr = PP.hm * g2;
-  const double ev0 = vib_local(T, P.sp0, P.lv0, ls);
-  const double ev1 = vib_local(T, P.sp1, P.lv1, ls);
+  const uint32_t sp0 = P.sp0, sp1 = P.sp1;
+  const PairTab &PP = T.pair(sp0, sp1);
+  const double e_tr0 = PP.hm * g2;
+  const double ev0 = vib_local(T, sp0, P.lv0, ls), ev1 = vib_local(T, sp1, P.lv1, ls);
   P.born = false;
   P.m_moved = false;
 
+  // outcome: 0 none, 1 dissociation, 2 exchange, 3 recombination
+  int kind = 0, rx = -1;
+  uint32_t side = 0;  // reacting side: A of dissociation/exchange, B of recombination
+  Vec3 vbc{0.0, 0.0, 0.0};
+  double et = e_tr0;
+
   // --- recombination first: B + C (+M) -> A (+M) ---
-  for (uint32_t r = 0; r < T.nr; ++r) {
+  for (uint32_t r = 0; r < T.nr && kind == 0; ++r) {
     const ReactionTab &R = T.rx[r];
     if (R.kind != HCAO_RX_RECOMBINATION) continue;
-    uint32_t side_b;
+    uint32_t sb;
     if (P.sp0 == (uint32_t)R.a && P.sp1 == (uint32_t)R.b)
-      side_b = 0;
+      sb = 0;
     else if (P.sp1 == (uint32_t)R.a && P.sp0 == (uint32_t)R.b)
-      side_b = 1;
+      sb = 1;
     else
       continue;
     const double u = rng.uniform();
@@ -440,268 +594,214 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
     prob = prob * P.n_cell;
     if (prob > 1.0) prob = 1.0;
     if (!(u < prob)) continue;
-    const SpeciesTab &SA = T.sp[R.c];
-    const PairTab &PBC = T.pair(R.a, R.b);
-    const Vec3 vb = side_b ? P.v1 : P.v0, vc = side_b ? P.v0 : P.v1;
-    const Vec3 vbc = com(PBC, vb, vc);
-    const double gx = vbc.x - P.v_m.x, gy = vbc.y - P.v_m.y, gz = vbc.z - P.v_m.z;
-    const PairTab &PAM = T.pair(R.c, P.sp_m);
-    const double e_am = PAM.hm * ((gx * gx + gy * gy) + gz * gz);
-    const double evb = side_b ? ev1 : ev0, evc = side_b ? ev0 : ev1;
-    const double pool = (((e_am + e_tr) + evb) + evc) - R.dh;
-    double et = pool - SA.zpe;
-    if (!(et > 0.0)) {
+    const Vec3 vb = sb ? P.v1 : P.v0, vc = sb ? P.v0 : P.v1;
+    const Vec3 c3 = com(T.pair(R.a, R.b), vb, vc);
+    const double gx = c3.x - P.v_m.x, gy = c3.y - P.v_m.y, gz = c3.z - P.v_m.z;
+    const double e_am = T.pair(R.c, P.sp_m).hm * ((gx * gx + gy * gy) + gz * gz);
+    const double pool = (((e_am + e_tr0) + (sb ? ev1 : ev0)) + (sb ? ev0 : ev1)) - R.dh;
+    const double e_left = pool - T.sp[R.c].zpe;
+    if (!(e_left > 0.0)) {
       atomicAdd(&C.ctr[HCAO_CTR_SUPPRESSED], 1ull);
       continue;
     }
-    uint16_t *la = side_b ? P.lv1 : P.lv0;
+    kind = 3;
+    rx = (int)r;
+    side = sb;
+    vbc = c3;
+    et = e_left;
+  }
+
+  // --- dissociation and exchange channels, competition by excess energy ---
+  if (kind == 0) {
+    uint64_t steric_ok = 0;
+    ChannelScan S;
+    S.nch = 0;
+    S.total = 0.0;
+    S.found = false;
+    S.first = S.last = S.pick = Channel{-1, 0, 0};
+    scan_channels(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 0, 0.0, S);
+    if (S.nch > 0) {
+      Channel pick = S.first;
+      if (S.nch > 1) {
+        const double target = rng.uniform() * S.total;
+        scan_channels(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 1, target, S);
+        pick = S.found ? S.pick : S.last;
+      }
+      const ReactionTab &R = T.rx[pick.rx];
+      rx = pick.rx;
+      side = (uint32_t)pick.side;
+      const double eva = side ? ev1 : ev0, evb = side ? ev0 : ev1;
+      if (R.kind == HCAO_RX_DISSOCIATION) {
+        kind = 1;
+        et = (((e_tr0 + eva) - R.dh) - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+      } else {
+        kind = 2;
+        et = ((((e_tr0 + eva) + evb) - R.dh) - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+      }
+    }
+  }
+
+  // --- queue the relaxations (at most two, in draw order) ---
+  uint16_t *lvj0 = nullptr, *lvj1 = nullptr;
+  uint32_t spj0 = 0, spj1 = 0;
+  double qj0 = 0.0, qj1 = 0.0;
+  bool pv = false;
+  uint32_t njob = 0;
+  const ReactionTab &RX = T.rx[rx < 0 ? 0 : rx];
+  uint16_t *la = side ? P.lv1 : P.lv0;
+  uint16_t *lb = side ? P.lv0 : P.lv1;
+  uint32_t ja_sp = 0, jb_sp = 0;  // candidate jobs a and b
+  uint16_t *ja_lv = nullptr, *jb_lv = nullptr;
+  double ja_q = 0.0, jb_q = 0.0;
+  if (kind == 0) {
+    pv = true;
+    ja_sp = sp0;
+    ja_lv = P.lv0;
+    ja_q = PP.q;
+    jb_sp = sp1;
+    jb_lv = P.lv1;
+    jb_q = PP.q;
+  } else if (kind == 1) {
+    // A + M -> B + C + M: B takes A's slot, C is new, both from the ground state
+    const uint32_t spM = side ? sp0 : sp1;
     zero_levels(la, ls, mm);
-    bool capped = false;
-    const uint32_t tr = relax(C, SA, la, ls, et, PAM.q, rng, capped);
-    const Vec3 vcm = com(PAM, vbc, P.v_m);
-    Vec3 va, vm;
-    split(PAM, vcm, et, rng, va, vm);
-    if (side_b) {
-      P.v1 = va;
-      P.sp1 = (uint32_t)R.c;
-      P.dead0 = true;
+    zero_levels(P.lvn, ls, mm);
+    ja_sp = (uint32_t)RX.c;
+    ja_lv = la;
+    ja_q = T.pair(RX.c, spM).q;
+    jb_sp = (uint32_t)RX.d;
+    jb_lv = P.lvn;
+    jb_q = T.pair(RX.d, spM).q;
+  } else if (kind == 2) {
+    // A + B -> C + D: C takes A's slot, D takes B's
+    zero_levels(la, ls, mm);
+    zero_levels(lb, ls, mm);
+    const double qcd = T.pair(RX.c, RX.d).q;
+    ja_sp = (uint32_t)RX.c;
+    ja_lv = la;
+    ja_q = qcd;
+    jb_sp = (uint32_t)RX.d;
+    jb_lv = lb;
+    jb_q = qcd;
+  } else {
+    // B + C (+M) -> A (+M): A takes B's slot
+    zero_levels(la, ls, mm);
+    ja_sp = (uint32_t)RX.c;
+    ja_lv = la;
+    ja_q = T.pair(RX.c, P.sp_m).q;
+  }
+  if (T.sp[ja_sp].n_modes > 0) {
+    lvj0 = ja_lv;
+    spj0 = ja_sp;
+    qj0 = ja_q;
+    ++njob;
+  }
+  if (kind != 3 && T.sp[jb_sp].n_modes > 0) {
+    if (njob == 0) {
+      lvj0 = jb_lv;
+      spj0 = jb_sp;
+      qj0 = jb_q;
     } else {
-      P.v0 = va;
-      P.sp0 = (uint32_t)R.c;
-      P.dead1 = true;
+      lvj1 = jb_lv;
+      spj1 = jb_sp;
+      qj1 = jb_q;
     }
-    P.v_m = vm;
-    P.m_moved = true;
-    if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
-    if (capped) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], 1ull);
-    atomicAdd(&C.ctr[HCAO_CTR_DEATHS], 1ull);
-    atomicAdd(&C.ctr[HCAO_CTR_REACTION0 + r], 1ull);
-    return (int)r;
+    ++njob;
   }
-
-  // --- dissociation channels, then exchange channels, canonical order ---
-  uint32_t nch = 0;
-  double total = 0.0;
-  Channel first{-1, 0, 0}, last{-1, 0, 0};
-  uint64_t steric_ok = 0;  // outcome of each matched exchange draw, in order
-  uint32_t n_exch = 0;
-  for (uint32_t side = 0; side < 2; ++side) {
-    const uint32_t A = sps[side];
-    const double evA = side ? ev1 : ev0;
-    for (uint32_t r = 0; r < T.nr; ++r) {
-      const ReactionTab &R = T.rx[r];
-      if (R.kind != HCAO_RX_DISSOCIATION || (uint32_t)R.a != A) continue;
-      const SpeciesTab &SA = T.sp[A];
-      const uint32_t nst = SA.n_modes - SA.n_bend;
-      for (uint32_t j = 0; j < nst; ++j) {
-        if (!((R.mask >> j) & 1ull)) continue;
-        const uint32_t m = SA.n_bend + j;
-        const double ecoll = ((e_tr + evA) - R.zsum) + T.lev[SA.lev_off[m]];
-        const double eex = ecoll - SA.de[m];
-        const double pool = (e_tr + evA) - R.dh;
-        const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-        if (eex > 0.0 && left > 0.0 && nch < (uint32_t)kMaxChannels) {
-          const Channel ch{(int32_t)r, (int32_t)side, (int32_t)m};
-          if (nch == 0) first = ch;
-          last = ch;
-          total = total + eex;
-          ++nch;
-        }
-      }
-    }
-  }
-  for (uint32_t side = 0; side < 2; ++side) {
-    const uint32_t A = sps[side], B = sps[1 - side];
-    const double evA = side ? ev1 : ev0, evB = side ? ev0 : ev1;
-    const uint16_t *lA = side ? P.lv1 : P.lv0;
-    for (uint32_t r = 0; r < T.nr; ++r) {
-      const ReactionTab &R = T.rx[r];
-      if (R.kind != HCAO_RX_EXCHANGE || (uint32_t)R.a != A || (uint32_t)R.b != B) continue;
-      const double us = rng.uniform();
-      const SpeciesTab &SA = T.sp[A];
-      double ecoll = e_tr;
-      for (uint32_t m = 0; m < SA.n_modes; ++m) ecoll = ecoll + R.alpha[m] * mode_energy(SA, T.lev, m, lA[m * ls]);
-      const double eex = ecoll - R.ea;
-      const double pool = ((e_tr + evA) + evB) - R.dh;
-      const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-      const bool st_ok = us < R.steric;
-      if (st_ok && n_exch < 64) steric_ok |= (1ull << n_exch);
-      ++n_exch;
-      if (st_ok && eex > 0.0 && left > 0.0 && nch < (uint32_t)kMaxChannels) {
-        const Channel ch{(int32_t)r, (int32_t)side, -1};
-        if (nch == 0) first = ch;
-        last = ch;
-        total = total + eex;
-        ++nch;
-      }
-    }
-  }
-
-  if (nch > 0) {
-    Channel pick = first;
-    if (nch > 1) {
-      // one draw over the open channels weighted by excess energy; the
-      // channels are enumerated again in the same order
-      const double target = rng.uniform() * total;
-      double cum = 0.0;
-      uint32_t seen = 0, ex_i = 0;
-      bool found = false;
-      pick = last;
-      for (uint32_t side = 0; side < 2 && !found; ++side) {
-        const uint32_t A = sps[side];
-        const double evA = side ? ev1 : ev0;
-        for (uint32_t r = 0; r < T.nr && !found; ++r) {
-          const ReactionTab &R = T.rx[r];
-          if (R.kind != HCAO_RX_DISSOCIATION || (uint32_t)R.a != A) continue;
-          const SpeciesTab &SA = T.sp[A];
-          const uint32_t nst = SA.n_modes - SA.n_bend;
-          for (uint32_t j = 0; j < nst && !found; ++j) {
-            if (!((R.mask >> j) & 1ull)) continue;
-            const uint32_t m = SA.n_bend + j;
-            const double ecoll = ((e_tr + evA) - R.zsum) + T.lev[SA.lev_off[m]];
-            const double eex = ecoll - SA.de[m];
-            const double pool = (e_tr + evA) - R.dh;
-            const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-            if (eex > 0.0 && left > 0.0 && seen < (uint32_t)kMaxChannels) {
-              ++seen;
-              cum = cum + eex;
-              if (target < cum) {
-                pick = Channel{(int32_t)r, (int32_t)side, (int32_t)m};
-                found = true;
-              }
-            }
-          }
-        }
-      }
-      for (uint32_t side = 0; side < 2 && !found; ++side) {
-        const uint32_t A = sps[side], B = sps[1 - side];
-        const double evA = side ? ev1 : ev0, evB = side ? ev0 : ev1;
-        const uint16_t *lA = side ? P.lv1 : P.lv0;
-        for (uint32_t r = 0; r < T.nr && !found; ++r) {
-          const ReactionTab &R = T.rx[r];
-          if (R.kind != HCAO_RX_EXCHANGE || (uint32_t)R.a != A || (uint32_t)R.b != B) continue;
-          const bool st_ok = ex_i < 64 ? ((steric_ok >> ex_i) & 1ull) != 0 : false;
-          ++ex_i;
-          const SpeciesTab &SA = T.sp[A];
-          double ecoll = e_tr;
-          for (uint32_t m = 0; m < SA.n_modes; ++m)
-            ecoll = ecoll + R.alpha[m] * mode_energy(SA, T.lev, m, lA[m * ls]);
-          const double eex = ecoll - R.ea;
-          const double pool = ((e_tr + evA) + evB) - R.dh;
-          const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-          if (st_ok && eex > 0.0 && left > 0.0 && seen < (uint32_t)kMaxChannels) {
-            ++seen;
-            cum = cum + eex;
-            if (target < cum) {
-              pick = Channel{(int32_t)r, (int32_t)side, -1};
-              found = true;
-            }
-          }
-        }
-      }
-    }
-
-    const ReactionTab &R = T.rx[pick.rx];
-    const uint32_t a = (uint32_t)pick.side;
-    const Vec3 va0 = a ? P.v1 : P.v0, vb0 = a ? P.v0 : P.v1;
-    const double eva = a ? ev1 : ev0, evb = a ? ev0 : ev1;
-    uint16_t *la = a ? P.lv1 : P.lv0;
-    uint16_t *lb = a ? P.lv0 : P.lv1;
-    uint64_t tr = 0;
-    bool capped = false, c2 = false;
-    if (R.kind == HCAO_RX_DISSOCIATION) {
-      // A + M -> B + C + M: B takes A's slot, C is new
-      const uint32_t spA = sps[a], spM = sps[1 - a];
-      const double pool = (e_tr + eva) - R.dh;
-      double et = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-      zero_levels(la, ls, mm);
-      zero_levels(P.lvn, ls, mm);
-      if (T.sp[R.c].n_modes > 0) tr += relax(C, T.sp[R.c], la, ls, et, T.pair(R.c, spM).q, rng, capped);
-      if (T.sp[R.d].n_modes > 0) {
-        tr += relax(C, T.sp[R.d], P.lvn, ls, et, T.pair(R.d, spM).q, rng, c2);
-        capped = capped || c2;
-      }
-      double beta;
-      for (;;) {
-        const double u1 = rng.uniform(), u2 = rng.uniform();
-        if (u2 * 0.5 < sqrt(u1 * (1.0 - u1))) {
-          beta = u1;
-          break;
-        }
-      }
-      const double ebc = beta * et;
-      const double exm = et - ebc;
-      const PairTab &PAM = T.pair(spA, spM);
-      const Vec3 vcm = com(PAM, va0, vb0);
-      Vec3 vbc, vm, vbn, vcn;
-      split(PAM, vcm, exm, rng, vbc, vm);
-      split(T.pair(R.c, R.d), vbc, ebc, rng, vbn, vcn);
-      if (a) {
-        P.v1 = vbn;
-        P.v0 = vm;
-        P.sp1 = (uint32_t)R.c;
-      } else {
-        P.v0 = vbn;
-        P.v1 = vm;
-        P.sp0 = (uint32_t)R.c;
-      }
-      P.born = true;
-      P.nb_sp = (uint32_t)R.d;
-      P.nb_v = vcn;
-      atomicAdd(&C.ctr[HCAO_CTR_BIRTHS], 1ull);
-    } else {
-      // A + B -> C + D: C takes A's slot, D takes B's
-      const uint32_t spA = sps[a], spB = sps[1 - a];
-      const double pool = ((e_tr + eva) + evb) - R.dh;
-      double et = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
-      zero_levels(la, ls, mm);
-      zero_levels(lb, ls, mm);
-      const double qcd = T.pair(R.c, R.d).q;
-      if (T.sp[R.c].n_modes > 0) tr += relax(C, T.sp[R.c], la, ls, et, qcd, rng, capped);
-      if (T.sp[R.d].n_modes > 0) {
-        tr += relax(C, T.sp[R.d], lb, ls, et, qcd, rng, c2);
-        capped = capped || c2;
-      }
-      const Vec3 vcm = com(T.pair(spA, spB), va0, vb0);
-      Vec3 vc, vd;
-      split(T.pair(R.c, R.d), vcm, et, rng, vc, vd);
-      if (a) {
-        P.v1 = vc;
-        P.v0 = vd;
-        P.sp1 = (uint32_t)R.c;
-        P.sp0 = (uint32_t)R.d;
-      } else {
-        P.v0 = vc;
-        P.v1 = vd;
-        P.sp0 = (uint32_t)R.c;
-        P.sp1 = (uint32_t)R.d;
-      }
-    }
-    if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
-    if (capped) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], 1ull);
-    atomicAdd(&C.ctr[HCAO_CTR_REACTION0 + pick.rx], 1ull);
-    return pick.rx;
-  }
-
-  // --- no reaction: relax each molecule in turn, then scatter ---
   uint64_t tr = 0;
   uint32_t nrel = 0, ncap = 0;
-  for (uint32_t x = 0; x < 2; ++x) {
-    const SpeciesTab &S = T.sp[sps[x]];
-    if (S.n_modes == 0) continue;
-    const double u = rng.uniform();
-    if (!(u < S.p_vib)) continue;
+  for (uint32_t j = 0; j < njob; ++j) {
+    const SpeciesTab &S = T.sp[j ? spj1 : spj0];
+    if (pv) {
+      const double u = rng.uniform();
+      if (!(u < S.p_vib)) continue;
+      ++nrel;
+    }
     bool capped = false;
-    tr += relax(C, S, x ? P.lv1 : P.lv0, ls, e_tr, PP.q, rng, capped);
-    ++nrel;
+    tr += relax(C, S, j ? lvj1 : lvj0, ls, et, j ? qj1 : qj0, rng, capped);
     ncap += capped ? 1u : 0u;
   }
   if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
   if (nrel) atomicAdd(&C.ctr[HCAO_CTR_RELAX], (unsigned long long)nrel);
   if (ncap) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], (unsigned long long)ncap);
-  const Vec3 vcm = com(PP, P.v0, P.v1);
-  split(PP, vcm, e_tr, rng, P.v0, P.v1);
-  return -1;
+
+  // --- scattering ---
+  const Vec3 va0 = side ? P.v1 : P.v0, vb0 = side ? P.v0 : P.v1;
+  double e1 = et, e2 = 0.0;
+  if (kind == 1) {
+    // share of the translational energy in the B-C motion: density
+    // proportional to sqrt(beta (1 - beta)), by rejection
+    double beta;
+    for (;;) {
+      const double u1 = rng.uniform(), u2 = rng.uniform();
+      if (u2 * 0.5 < sqrt(u1 * (1.0 - u1))) {
+        beta = u1;
+        break;
+      }
+    }
+    e2 = beta * et;
+    e1 = et - e2;
+  }
+  const uint32_t spA = side ? sp1 : sp0, spB = side ? sp0 : sp1;
+  const PairTab *t1;
+  Vec3 cm;
+  if (kind == 0) {
+    t1 = &PP;
+    cm = com(PP, P.v0, P.v1);
+  } else if (kind == 1) {
+    t1 = &T.pair(spA, spB);
+    cm = com(*t1, va0, vb0);
+  } else if (kind == 2) {
+    t1 = &T.pair(RX.c, RX.d);
+    cm = com(T.pair(spA, spB), va0, vb0);
+  } else {
+    t1 = &T.pair(RX.c, P.sp_m);
+    cm = com(*t1, vbc, P.v_m);
+  }
+  Vec3 x1, y1;
+  split(*t1, cm, e1, rng, x1, y1);
+  if (kind == 0) {
+    P.v0 = x1;
+    P.v1 = y1;
+    return -1;
+  }
+  if (kind == 1) {
+    Vec3 x2, y2;
+    split(T.pair(RX.c, RX.d), x1, e2, rng, x2, y2);
+    x1 = x2;
+    P.born = true;
+    P.nb_sp = (uint32_t)RX.d;
+    P.nb_v = y2;
+    atomicAdd(&C.ctr[HCAO_CTR_BIRTHS], 1ull);
+  }
+  if (kind == 3) {
+    P.v_m = y1;
+    P.m_moved = true;
+    atomicAdd(&C.ctr[HCAO_CTR_DEATHS], 1ull);
+  }
+  const uint32_t new_a = (uint32_t)RX.c;
+  const uint32_t new_b = kind == 2 ? (uint32_t)RX.d : spB;
+  if (side) {
+    P.v1 = x1;
+    P.sp1 = new_a;
+    if (kind == 3)
+      P.dead0 = true;
+    else {
+      P.v0 = y1;
+      P.sp0 = new_b;
+    }
+  } else {
+    P.v0 = x1;
+    P.sp0 = new_a;
+    if (kind == 3)
+      P.dead1 = true;
+    else {
+      P.v1 = y1;
+      P.sp1 = new_b;
+    }
+  }
+  atomicAdd(&C.ctr[HCAO_CTR_REACTION0 + rx], 1ull);
+  return rx;
 }
 
 // Translational temperature of a cell by one wave: blocks of 64 particles in
@@ -743,10 +843,13 @@ __device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint6
 // ---------------------------------------------------------------------------
 // the collision step: one workgroup per group of consecutive cells
 // ---------------------------------------------------------------------------
+// Per-cell state kept in LDS across the steps of a launch (base .. weight)
+// and per-step quantities (ncand .. perm).
 struct CellHdr {
   uint64_t base;
   uint32_t cell, n, cap, ncand, cstart, pad;
-  double sgmax, rem_new, n_cell, rec_f;
+  double sgmax, rem, volume, weight;
+  double rem_new, n_cell, rec_f;
   int32_t rec_i, pad2;
   unsigned long long sgbits, excess;
   Perm perm;
@@ -802,11 +905,13 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
   CellHdr *hdr = reinterpret_cast<CellHdr *>(q);
   q += sizeof(CellHdr) * ncell;
   unsigned long long *l_ctr = reinterpret_cast<unsigned long long *>(q);
-  q += sizeof(unsigned long long) * nctr * ncell;
+  q += sizeof(unsigned long long) * nctr * ncell * 2;  // per-step counters, then totals
   uint16_t *scr = reinterpret_cast<uint16_t *>(q);  // [2 mm][BLOCK] sampler scratch
   uint16_t *plv = scr + (size_t)2 * mm * BLOCK;      // [3 mm][BLOCK] pair levels
 
-  // ---- phase 0: tables and cell headers ----
+  unsigned long long *l_tot = l_ctr + (size_t)nctr * ncell;  // counters summed over the launch's steps
+
+  // ---- once per launch: tables and the persistent cell state ----
   {
     const uint64_t *src = reinterpret_cast<const uint64_t *>(GT->sp);
     uint64_t *dst = reinterpret_cast<uint64_t *>(l_sp);
@@ -816,17 +921,36 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     dst = reinterpret_cast<uint64_t *>(l_rx);
     for (uint32_t i = tid; i < nr * sizeof(ReactionTab) / 8; i += BLOCK) dst[i] = src[i];
     for (uint32_t i = tid; i < nl; i += BLOCK) l_lev[i] = A.lev[i];
-    for (uint32_t i = tid; i < nctr * ncell; i += BLOCK) l_ctr[i] = 0ull;
+    for (uint32_t i = tid; i < nctr * ncell; i += BLOCK) l_tot[i] = 0ull;
   }
   for (uint32_t g = tid; g < ncell; g += BLOCK) {
     CellHdr &H = hdr[g];
     const uint32_t c = c0 + g;
-    const uint32_t n = A.cells.cnt[c];
-    const double sgmax = A.cells.sgmax[c];
+    H.base = A.cells.off[c];
+    H.cell = c;
+    H.n = A.cells.cnt[c];
+    H.cap = A.cells.cap[c];
+    H.sgmax = A.cells.sgmax[c];
+    H.rem = A.cells.rem[c];
+    H.volume = A.cells.volume[c];
+    H.weight = A.cells.weight[c];
+  }
+  const Tab T{l_sp, l_pr, l_rx, l_lev, ns, nr, mm, GT->rec_nt};
+  uint32_t *work = A.work + 3 * wbase;  // entries of (j, p, q)
+  uint8_t *bflag = A.bflag + wbase;
+  const uint32_t wcap = (uint32_t)(A.grp_work[blockIdx.x + 1] - wbase);
+  __syncthreads();
+
+  for (uint32_t si = 0; si < A.n_steps; ++si) {
+  const uint32_t step = A.step + si;
+
+  // ---- phase 0: candidate counts and permutation keys of the step ----
+  for (uint32_t i = tid; i < nctr * ncell; i += BLOCK) l_ctr[i] = 0ull;
+  for (uint32_t g = tid; g < ncell; g += BLOCK) {
+    CellHdr &H = hdr[g];
+    const uint32_t n = H.n;
     // NTC candidate count: floor(1/2 N (N-1) F_N (sigma g)_max dt / V + remainder)
-    const double x = 0.5 * (double)n * (double)(n - (n > 0 ? 1u : 0u)) * A.cells.weight[c] * sgmax * A.dt /
-                         A.cells.volume[c] +
-                     A.cells.rem[c];
+    const double x = 0.5 * (double)n * (double)(n - (n > 0 ? 1u : 0u)) * H.weight * H.sgmax * A.dt / H.volume + H.rem;
     const double fl = floor(x);
     uint64_t ncand = (uint64_t)fl;
     uint64_t excess = 0;
@@ -834,19 +958,14 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
       excess = ncand - n / 2;
       ncand = n / 2;
     }
-    H.base = A.cells.off[c];
-    H.cell = c;
-    H.n = n;
-    H.cap = A.cells.cap[c];
     H.ncand = (uint32_t)ncand;
-    H.sgmax = sgmax;
     H.rem_new = x - fl;
-    H.n_cell = (double)n * A.cells.weight[c] / A.cells.volume[c];
+    H.n_cell = (double)n * H.weight / H.volume;
     H.rec_i = -1;
     H.rec_f = 0.0;
     H.sgbits = 0ull;
     H.excess = excess;
-    if (ncand > 0) make_perm(H.perm, n, A.seed, c, A.step);
+    if (ncand > 0) make_perm(H.perm, n, A.seed, H.cell, step);
   }
   __syncthreads();
   if (GT->has_recomb) {
@@ -886,38 +1005,52 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
   }
   __syncthreads();
   const uint32_t total = s_total;
-  const Tab T{l_sp, l_pr, l_rx, l_lev, ns, nr, mm, GT->rec_nt};
-  uint32_t *work = A.work + wbase;
-  uint8_t *bflag = A.bflag + wbase;
 
   // ---- phase A: candidate pairs, VHS acceptance ----
   // Accepted pairs that involve a molecule (the long sampler chains) fill
   // the work list from the front, atom-atom pairs from the back, so that
   // waves of phase B hold work of similar length. One LDS atomic per wave
   // and section.
-  const uint32_t wcap = (uint32_t)(A.grp_work[blockIdx.x + 1] - wbase);
   for (uint32_t j0 = 0; j0 < total; j0 += BLOCK) {
     const uint32_t j = j0 + tid;
     bool acc = false, heavy = false;
+    uint32_t pj = 0, qj = 0;
     if (j < total) {
       const uint32_t g = group_cell(hdr, ncell, j);
       const CellHdr &H = hdr[g];
       const uint32_t k = j - H.cstart;
-      const uint32_t p = H.perm(2 * k), qq = H.perm(2 * k + 1);
+      PermReg perm;
+      perm.load(H.perm);
+      const uint32_t p = perm(2 * k), qq = perm(2 * k + 1);
+      pj = p;
+      qj = qq;
       const uint64_t gp = H.base + p, gq = H.base + qq;
       const double dx = A.st.vx[gp] - A.st.vx[gq], dy = A.st.vy[gp] - A.st.vy[gq],
                    dz = A.st.vz[gp] - A.st.vz[gq];
       const double g2 = (dx * dx + dy * dy) + dz * dz;
       const uint32_t a = A.st.sp[gp], b = A.st.sp[gq];
       const PairTab &PP = T.pair(a, b);
-      const double sg = (g2 > 0.0) ? PP.csg * dpow(g2, PP.esg) : 0.0;
-      const unsigned long long sb = (unsigned long long)__double_as_longlong(sg);
-      if (sb > hdr[g].sgbits) atomicMax(&hdr[g].sgbits, sb);
       Rng rng;
-      rng.open(A.seed, k, H.cell, A.step);
+      rng.open(A.seed, k, H.cell, step);
       const double ua = rng.uniform();
       bflag[j] = 0;
-      acc = ua < sg / H.sgmax;
+      // VHS acceptance ua < sigma g / (sigma g)_max with sigma g = C (g^2)^(1-w).
+      // The exact sigma g is needed for the decision only near the filter
+      // band, and for the (sigma g)_max update only when it may exceed the
+      // cell's current value (the update keeps the larger of the two).
+      const double est = (g2 > 0.0) ? PP.csg * pow_estimate(g2, PP.esg) : 0.0;
+      const double ratio = est / H.sgmax;
+      const bool need_max = est >= H.sgmax * (1.0 - 2.0 * kFilter);
+      if (ua < ratio * (1.0 - kFilter) && !need_max) {
+        acc = true;
+      } else if (ua > ratio * (1.0 + kFilter) && !need_max) {
+        acc = false;
+      } else {
+        const double sg = (g2 > 0.0) ? PP.csg * dpow(g2, PP.esg) : 0.0;
+        const unsigned long long sb = (unsigned long long)__double_as_longlong(sg);
+        if (sb > hdr[g].sgbits) atomicMax(&hdr[g].sgbits, sb);
+        acc = ua < sg / H.sgmax;
+      }
       heavy = (T.sp[a].n_modes | T.sp[b].n_modes) != 0;
     }
     const unsigned long long mh = __ballot(acc && heavy), ml = __ballot(acc && !heavy);
@@ -929,10 +1062,10 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     bh = __shfl(bh, 0);
     bl = __shfl(bl, 0);
     if (acc) {
-      if (heavy)
-        work[bh + (uint32_t)__popcll(mh & lt)] = j;
-      else
-        work[wcap - 1 - (bl + (uint32_t)__popcll(ml & lt))] = j;
+      const uint32_t slot = heavy ? bh + (uint32_t)__popcll(mh & lt) : wcap - 1 - (bl + (uint32_t)__popcll(ml & lt));
+      work[3 * slot] = j;
+      work[3 * slot + 1] = pj;
+      work[3 * slot + 2] = qj;
     }
   }
   __syncthreads();
@@ -940,11 +1073,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
   // ---- phase B: one accepted pair per lane ----
   const uint32_t nheavy = s_nheavy, nwork = s_nheavy + s_nlight;
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
-    const uint32_t j = i < nheavy ? work[i] : work[wcap - 1 - (i - nheavy)];
+    const uint32_t slot = i < nheavy ? i : wcap - 1 - (i - nheavy);
+    const uint32_t j = work[3 * slot], p = work[3 * slot + 1], qq = work[3 * slot + 2];
     const uint32_t g = group_cell(hdr, ncell, j);
     const CellHdr &H = hdr[g];
     const uint32_t k = j - H.cstart;
-    const uint32_t p = H.perm(2 * k), qq = H.perm(2 * k + 1);
     const uint64_t gp = H.base + p, gq = H.base + qq;
     PairLocal P;
     P.v0 = Vec3{A.st.vx[gp], A.st.vy[gp], A.st.vz[gp]};
@@ -964,7 +1097,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     uint64_t gm = 0;
     if (GT->has_recomb && 2 * H.ncand + k < H.n) {
       // third body of pair k: the particle at permutation index 2 N_cand + k
-      gm = H.base + H.perm(2 * H.ncand + k);
+      PermReg perm;
+      perm.load(H.perm);
+      gm = H.base + perm(2 * H.ncand + k);
       P.has_m = true;
       P.sp_m = A.st.sp[gm];
       P.v_m = Vec3{A.st.vx[gm], A.st.vy[gm], A.st.vz[gm]};
@@ -975,7 +1110,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     const double dx = P.v0.x - P.v1.x, dy = P.v0.y - P.v1.y, dz = P.v0.z - P.v1.z;
     const double g2 = (dx * dx + dy * dy) + dz * dz;
     Rng rng;
-    rng.open(A.seed, k, H.cell, A.step);
+    rng.open(A.seed, k, H.cell, step);
     (void)rng.uniform();  // the acceptance draw of phase A
     unsigned long long *ctr = l_ctr + (size_t)g * nctr;
     atomicAdd(&ctr[HCAO_CTR_COLLISIONS], 1ull);
@@ -1050,11 +1185,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
       }
       alive = kept;
     }
-    uint32_t births = 0;
-    for (uint32_t k0 = 0; k0 < H.ncand; k0 += 64) {
-      const uint32_t k = k0 + lane;
-      births += (uint32_t)__popcll(__ballot(k < H.ncand && bflag[H.cstart + k] != 0));
-    }
+    const uint32_t births = (uint32_t)in[HCAO_CTR_BIRTHS];
     const bool overflow = alive + births > H.cap;
     if (births && !overflow) {
       uint32_t done = 0;
@@ -1074,22 +1205,37 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
         done += (uint32_t)__popcll(m);
       }
     }
-    const uint32_t c = H.cell;
-    unsigned long long *out = A.cells.ctr + (size_t)c * kNumCtr;
+    unsigned long long *tot = l_tot + (size_t)g * nctr;
     for (uint32_t i = lane; i < nctr; i += 64) {
-      if (i == HCAO_CTR_CANDIDATES)
-        out[i] += H.ncand;
-      else if (i == HCAO_CTR_SUPPRESSED)
-        out[i] += H.excess + in[i];
-      else
-        out[i] += in[i];
+      unsigned long long v = in[i];
+      if (i == HCAO_CTR_CANDIDATES) v = H.ncand;
+      if (i == HCAO_CTR_SUPPRESSED) v += H.excess;
+      tot[i] += v;
     }
     if (lane == 0) {
       if (overflow) atomicOr(A.err, kErrCapacity);
-      A.cells.cnt[c] = overflow ? alive : alive + births;
+      CellHdr &Hm = hdr[g];
+      Hm.n = overflow ? alive : alive + births;
       const double seen = __longlong_as_double((long long)H.sgbits);
-      A.cells.sgmax[c] = seen > H.sgmax ? seen : H.sgmax;
-      A.cells.rem[c] = H.rem_new;
+      Hm.sgmax = seen > H.sgmax ? seen : H.sgmax;
+      Hm.rem = H.rem_new;
+    }
+  }
+  __syncthreads();
+  }  // steps
+
+  // ---- persistent cell state back to HBM ----
+  for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
+    const CellHdr &H = hdr[g];
+    const uint32_t c = H.cell;
+    unsigned long long *out = A.cells.ctr + (size_t)c * kNumCtr;
+    const unsigned long long *tot = l_tot + (size_t)g * nctr;
+    for (uint32_t i = lane; i < nctr; i += 64)
+      if (tot[i]) atomicAdd(&out[i], tot[i]);  // no return value: the wave does not wait
+    if (lane == 0) {
+      A.cells.cnt[c] = H.n;
+      A.cells.sgmax[c] = H.sgmax;
+      A.cells.rem[c] = H.rem;
     }
   }
 }
@@ -1466,7 +1612,7 @@ __global__ void k_iota(uint32_t *x, uint64_t n) {
 size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block) {
   const uint32_t ns = T.n_species, nr = T.n_reactions;
   size_t b = sizeof(SpeciesTab) * ns + sizeof(PairTab) * ns * ns + sizeof(ReactionTab) * nr + 8 * (size_t)T.n_levels;
-  b += sizeof(CellHdr) * max_cells + 8 * (size_t)(8 + nr) * max_cells;
+  b += sizeof(CellHdr) * max_cells + 2 * 8 * (size_t)(8 + nr) * max_cells;
   b += (size_t)2 * (2 + 3) * (T.max_modes ? T.max_modes : 1) * block;
   return (b + 15) & ~(size_t)15;
 }

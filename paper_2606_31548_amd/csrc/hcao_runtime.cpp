@@ -123,12 +123,13 @@ struct hcao_ctx {
   DevBuf<uint8_t> bflag;
   uint32_t n_groups = 0, max_group_cells = 1;
   size_t step_lds = 0;
-  int block = 256;
-  uint32_t group_slots = 4096;  // target slot capacity per workgroup
+  int block = 64;
+  uint32_t group_slots = 1024;  // target slot capacity per workgroup
   uint32_t step = 0;
   bool timing = false;
   double timed_ms = 0.0;
-  uint64_t timed_launches = 0;
+  uint64_t timed_launches = 0, timed_steps = 0;
+  uint32_t steps_per_launch = 1u << 30;  // all steps of an hcao_step call in one launch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -283,14 +284,18 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   HIP_TRY(c, c->bvz.alloc(tot));
   HIP_TRY(c, c->bsp.alloc(tot));
   HIP_TRY(c, c->blvl.alloc(tot * mm));
-  // workgroups over consecutive cells: at most kMaxGroupCells cells and
+  // workgroups over consecutive cells: at most kMaxGroupCells cells (fewer
+  // when the per-cell LDS records of a wide workgroup would not fit) and
   // about group_slots slots each
+  uint32_t cell_limit = kMaxGroupCells;
+  while (cell_limit > 0 && step_lds_bytes(c->tab, cell_limit, c->block) > kLdsBudget) --cell_limit;
+  if (cell_limit == 0) return fail(c, HCAO_EUNSUPPORTED, "step kernel LDS budget exceeded");
   std::vector<uint32_t> grp{0};
   std::vector<uint64_t> gw{0};
   uint64_t slots = 0, wsum = 0;
   uint32_t in_group = 0, max_cells = 1;
   for (uint32_t i = 0; i < nc; ++i) {
-    if (in_group > 0 && (in_group >= kMaxGroupCells || slots + c->cap_host[i] > c->group_slots)) {
+    if (in_group > 0 && (in_group >= cell_limit || slots + c->cap_host[i] > c->group_slots)) {
       grp.push_back(i);
       gw.push_back(wsum);
       max_cells = std::max(max_cells, in_group);
@@ -308,7 +313,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   c->max_group_cells = max_cells;
   HIP_TRY(c, c->grp.alloc(grp.size()));
   HIP_TRY(c, c->grp_work.alloc(gw.size()));
-  HIP_TRY(c, c->work.alloc(wsum));
+  HIP_TRY(c, c->work.alloc(3 * wsum));
   HIP_TRY(c, c->bflag.alloc(wsum));
   HIP_TRY(c, hipMemcpyAsync(c->grp.p, grp.data(), grp.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->grp_work.p, gw.data(), gw.size() * 8, hipMemcpyHostToDevice, c->stream));
@@ -528,6 +533,10 @@ hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out) {
   if (const char *b = std::getenv("HCAO_BLOCK")) {
     const int v = std::atoi(b);
     if (v == 64 || v == 128 || v == 256 || v == 512) c->block = v;
+  }
+  if (const char *k = std::getenv("HCAO_STEPS_PER_LAUNCH")) {
+    const long v = std::atol(k);
+    if (v >= 1) c->steps_per_launch = (uint32_t)std::min<long>(v, 1L << 30);
   }
   if (const char *g = std::getenv("HCAO_GROUP_SLOTS")) {
     const long v = std::atol(g);
@@ -874,10 +883,15 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
   a.work = c->work.p;
   a.bflag = c->bflag.p;
   if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-  for (uint32_t s = 0; s < n_steps; ++s) {
+  uint64_t launches = 0;
+  for (uint32_t done = 0; done < n_steps;) {
+    const uint32_t k = std::min(n_steps - done, c->steps_per_launch);
     a.step = c->step;
+    a.n_steps = k;
     HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->n_groups, c->stream));
-    c->step += 1;
+    c->step += k;
+    done += k;
+    ++launches;
   }
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
@@ -885,7 +899,8 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
     float ms = 0.f;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->timed_ms += ms;
-    c->timed_launches += n_steps;
+    c->timed_launches += launches;
+    c->timed_steps += n_steps;
   }
   return HCAO_OK;
 }
@@ -1062,13 +1077,15 @@ hcao_status hcao_set_timing(hcao_ctx *c, int enable) {
   c->timing = enable != 0;
   c->timed_ms = 0.0;
   c->timed_launches = 0;
+  c->timed_steps = 0;
   return HCAO_OK;
 }
 
-hcao_status hcao_kernel_time(hcao_ctx *c, double *ms, uint64_t *launches) {
+hcao_status hcao_kernel_time(hcao_ctx *c, double *ms, uint64_t *launches, uint64_t *steps) {
   if (!c) return HCAO_EINVAL;
   if (ms) *ms = c->timed_ms;
   if (launches) *launches = c->timed_launches;
+  if (steps) *steps = c->timed_steps;
   return HCAO_OK;
 }
 

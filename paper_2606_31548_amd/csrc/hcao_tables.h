@@ -96,7 +96,8 @@ struct StepArgs {
   uint8_t *bflag;
   uint32_t *err;
   uint64_t seed;
-  uint32_t step;
+  uint32_t step;     // index of the launch's first step
+  uint32_t n_steps;  // steps advanced by this launch
   double dt;
 };
 

@@ -104,7 +104,7 @@ def load_library():
     L.hcao_get_pair.argtypes = [_vp, _u32, _u32, _vp]
     L.hcao_get_recombination_table.argtypes = [_vp, _u32, _vp, _u32, ctypes.POINTER(_u32)]
     L.hcao_set_timing.argtypes = [_vp, ctypes.c_int]
-    L.hcao_kernel_time.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(_u64)]
+    L.hcao_kernel_time.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]
     L.hcao_save.argtypes = [_vp, ctypes.c_char_p]
     L.hcao_restore.argtypes = [_vp, ctypes.c_char_p]
     L.hcao_destroy.argtypes = [_vp]; L.hcao_destroy.restype = None
@@ -296,10 +296,13 @@ class Simulation:
         self._chk("hcao_set_timing", self._L.hcao_set_timing(self._h, int(enable)))
 
     def kernel_time(self):
+        """(elapsed ms, launches, steps) of the step kernel since set_timing(True)."""
         ms = _d()
         n = _u64()
-        self._chk("hcao_kernel_time", self._L.hcao_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        k = _u64()
+        self._chk("hcao_kernel_time", self._L.hcao_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n),
+                                                                ctypes.byref(k)))
+        return ms.value, n.value, k.value
 
     def save(self, path):
         self._chk("hcao_save", self._L.hcao_save(self._h, str(path).encode()))

@@ -147,13 +147,15 @@ def test_step_parity_ragged_cells_mixed_paths(orc, hc):
 
 
 def test_launch_shape_invariance(orc, hc, monkeypatch):
-    """Workgroup size and the number of cells per workgroup do not change
+    """Workgroup size, cells per workgroup and steps per launch do not change
     any bit of the result."""
     wl = W.methane_argon(n_cells=40, per_cell=256)
     outs = []
-    for block, slots in (("64", "1"), ("128", "700"), ("256", "4096"), ("512", "100000")):
+    for block, slots, spl in (("64", "1", "1"), ("128", "700", "7"), ("256", "4096", "30"),
+                              ("512", "100000", "1000")):
         monkeypatch.setenv("HCAO_BLOCK", block)
         monkeypatch.setenv("HCAO_GROUP_SLOTS", slots)
+        monkeypatch.setenv("HCAO_STEPS_PER_LAUNCH", spl)
         g = hc.from_workload(wl)
         g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
         g.step(wl.dt, 30)

@@ -1,10 +1,12 @@
 """Benchmark of the HCAO DSMC collision step on one MI355X.
 
-Workload (default): 4,096 reservoir cells x 256 particles (1,048,576),
-methane-like molecules (16 amu, 4 Morse C-H stretches, 5 bends) in an
-argon-like bath at 1:9, T_trans 20,000 K, T_vib 300 K, dissociation
-CH4 + M -> CH3 + H + M, fp64, dt 1e-8 s; synthetic thermal initial state
-generated on the GPU.
+Workload (default): 262,144 reservoir cells x 256 particles (67.1M) of the
+CH4/CH3/H/H2 chemistry (64 of each per cell, n = 1e22 m^-3, T 8,000 K,
+dissociation CH4 + M -> CH3 + H + M, exchange CH4 + H -> CH3 + H2 and
+recombination CH3 + H + M -> CH4 + M, dt 5e-9 s), synthetic thermal initial
+state generated on the GPU. The mixed fp32/fp64 form is the headline value;
+the fp64 form is timed beside it on the same workload, and both report the
+energy drift over their run.
 
 A step is one pass of the whole collision step over every cell (NTC
 selection, VHS acceptance, reaction decision and application, relaxation,
@@ -13,8 +15,8 @@ steps with the state resident in HBM, bracketed by stream synchronisation.
 
 Prints one JSON line with the metric (collisions/s), the roofline of the
 step kernel (algorithmic bytes per launch / mean launch duration from HIP
-events recorded on the library's stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+events recorded on the library's stream) and the CPU oracle (fp64) timed on
+a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -43,17 +45,25 @@ def algorithmic_bytes(wl_species, counts_by_species, n_cells, b_v=8):
     return float((counts_by_species * per).sum() + 64.0 * n_cells)
 
 
+WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "triatomic")
+
+
 def make_workload(name):
-    if name == "methane-argon":
+    if name == "chemistry-67m":
+        wl = W.methane_chemistry(n_cells=262144, per_cell=256, recombination=True)
+        desc = ("262144 cells x 256 particles (67.1M), CH4/CH3/H/H2 64 each per cell, T 8000 K, "
+                "dissociation + exchange + recombination, dt 5e-9 s")
+    elif name == "chemistry-16m":
+        wl = W.methane_chemistry(n_cells=65536, per_cell=256, recombination=True)
+        desc = ("65536 cells x 256 particles (16.8M), CH4/CH3/H/H2 64 each per cell, T 8000 K, "
+                "dissociation + exchange + recombination, dt 5e-9 s")
+    elif name == "methane-argon":
         wl = W.methane_argon(n_cells=4096, per_cell=256)
         desc = "4096 cells x 256 particles, CH4-like/Ar-like 1:9, T_trans 20000 K, T_vib 300 K, " \
-               "CH4+M->CH3+H+M, fp64, dt 1e-8 s"
-    elif name == "methane-chemistry":
-        wl = W.methane_chemistry(n_cells=65536, per_cell=256, recombination=False)
-        desc = "65536 cells x 256 particles, CH4/CH3/H/H2, T 8000 K, dissociation + exchange, fp64, dt 1e-8 s"
+               "CH4+M->CH3+H+M, dt 1e-8 s"
     elif name == "triatomic":
         wl = W.triatomic_reservoir(10000)
-        desc = "1 cell x 10000 particles, synthetic triatomic, T_trans 10000 K, T_vib 300 K, dissociation, fp64"
+        desc = "1 cell x 10000 particles, synthetic triatomic, T_trans 10000 K, T_vib 300 K, dissociation"
     else:
         raise SystemExit(f"unknown workload {name}")
     return wl, desc
@@ -86,12 +96,90 @@ def cpu_baseline(name, target_s=15.0):
                       f"steps, {dt:.1f} s, single thread"}
 
 
+def _energy(sim, m, n_modes):
+    """Kinetic + vibrational (zero point included) + formation energy of the
+    particles [J] and the thermal part (kinetic + vibrational above the zero
+    point) that drift is measured against."""
+    e = m.E_kin_J + m.E_formation_J
+    th = m.E_kin_J
+    for s in range(len(n_modes)):
+        e += m.E_vib_J[s] + m.n_species[s] * sim.zero_point(s)
+        th += m.E_vib_J[s]
+    return e, th
+
+
+def measure(hcao, torch, wl, precision, steps, warmup):
+    """Times `steps` steps of one form after `warmup` untimed ones; returns
+    throughput, the step kernel's roofline figures and the energy drift."""
+    stream = torch.cuda.Stream()
+    sim = hcao.from_workload(wl, stream=hcao.ctypes.c_void_p(stream.cuda_stream), precision=precision)
+    sim.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    n_modes = [sp.n_modes for sp in wl.species]
+    m_init = sim.moments()
+    e_init, th_init = _energy(sim, m_init, n_modes)
+    sim.step(wl.dt, warmup)
+    sim.sync()
+
+    _, _, ctr0 = sim.cell_state()
+    tot0 = sim.moments()
+    per_species0 = np.array(tot0.n_species[:len(wl.species)], np.float64)
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(wl.dt, steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, launches, kernel_steps = sim.kernel_time()
+    sim.set_timing(False)
+    _, _, ctr1 = sim.cell_state()
+    tot1 = sim.moments()
+    per_species1 = np.array(tot1.n_species[:len(wl.species)], np.float64)
+    e_end, _ = _energy(sim, tot1, n_modes)
+
+    coll = int(ctr1[:, hcao.CTR_COLLISIONS].sum() - ctr0[:, hcao.CTR_COLLISIONS].sum())
+    cand = int(ctr1[:, hcao.CTR_CANDIDATES].sum() - ctr0[:, hcao.CTR_CANDIDATES].sum())
+    trials = int(ctr1[:, hcao.CTR_TRIALS].sum() - ctr0[:, hcao.CTR_TRIALS].sum())
+    reactions = int(ctr1[:, hcao.CTR_REACTION0:].sum() - ctr0[:, hcao.CTR_REACTION0:].sum())
+    n_mean = 0.5 * (tot0.n_total + tot1.n_total)
+    # algorithmic bytes per launch: per step, every live particle's state read
+    # and written once plus 64 B per cell; a launch advances kernel_steps/launches steps
+    b_v = 4 if precision == hcao.MIXED else 8
+    b_step = 0.5 * (algorithmic_bytes(wl.species, per_species0, wl.n_cells, b_v) +
+                    algorithmic_bytes(wl.species, per_species1, wl.n_cells, b_v))
+    steps_per_launch = kernel_steps / max(launches, 1)
+    b_alg = b_step * steps_per_launch
+    avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
+    achieved = b_alg / avg_launch_s / 1e9
+    r = {
+        "collisions_per_s": coll / elapsed,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "particle_steps_per_s": n_mean * steps / elapsed,
+        "candidates": cand,
+        "collisions": coll,
+        "reactions": reactions,
+        "sampler_trials_per_collision": trials / max(coll, 1),
+        # relative to the initial thermal energy, over all warm-up and timed steps
+        "energy_drift": abs(e_end - e_init) / th_init,
+        "energy_owed_rel": tot1.E_defect_J / th_init,
+        "T_trans_K": tot1.T_trans_K,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step", "bytes_per_launch": b_alg, "steps_per_launch": steps_per_launch,
+                     "mean_launch_us": avg_launch_s * 1e6},
+    }
+    sim.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="methane-argon")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="chemistry-67m", choices=WORKLOADS)
+    ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"),
+                    help="both: the mixed form is the headline value, the fp64 form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -116,68 +204,36 @@ def main():
         return
 
     wl, desc = make_workload(args.workload)
-    stream = torch.cuda.Stream()
-    sim = hcao.from_workload(wl, stream=hcao.ctypes.c_void_p(stream.cuda_stream))
-    sim.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
-    sim.step(wl.dt, args.warmup)
-    sim.sync()
-
-    _, _, ctr0 = sim.cell_state()
-    tot0 = sim.moments()
-    per_species0 = np.array(tot0.n_species[:len(wl.species)], np.float64)
-    sim.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(wl.dt, args.steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kernel_ms, launches, kernel_steps = sim.kernel_time()
-    sim.set_timing(False)
-    _, _, ctr1 = sim.cell_state()
-    tot1 = sim.moments()
-    per_species1 = np.array(tot1.n_species[:len(wl.species)], np.float64)
-
-    coll = int(ctr1[:, hcao.CTR_COLLISIONS].sum() - ctr0[:, hcao.CTR_COLLISIONS].sum())
-    cand = int(ctr1[:, hcao.CTR_CANDIDATES].sum() - ctr0[:, hcao.CTR_CANDIDATES].sum())
-    trials = int(ctr1[:, hcao.CTR_TRIALS].sum() - ctr0[:, hcao.CTR_TRIALS].sum())
-    reactions = int(ctr1[:, hcao.CTR_REACTION0:].sum() - ctr0[:, hcao.CTR_REACTION0:].sum())
-    n_mean = 0.5 * (tot0.n_total + tot1.n_total)
-    # algorithmic bytes per launch: per step, every live particle's state read
-    # and written once plus 64 B per cell; a launch advances kernel_steps/launches steps
-    b_step = 0.5 * (algorithmic_bytes(wl.species, per_species0, wl.n_cells) +
-                    algorithmic_bytes(wl.species, per_species1, wl.n_cells))
-    steps_per_launch = kernel_steps / max(launches, 1)
-    b_alg = b_step * steps_per_launch
-    avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
-    achieved = b_alg / avg_launch_s / 1e9
-
+    forms = {"both": ("mixed", "fp64"), "mixed": ("mixed",), "fp64": ("fp64",)}[args.precision]
+    res = {}
+    for f in forms:
+        print(f"# timing the {f} form: {args.warmup} warm-up + {args.steps} steps", file=sys.stderr, flush=True)
+        res[f] = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, args.steps, args.warmup)
+    head = res[forms[0]]
     out = {
-        "metric": "HCAO collisions/s on 1 MI355X",
-        "value": coll / elapsed,
+        "metric": "HCAO collisions/s on 1 MI355X; mixed FP32/FP64 vs FP64 at fixed energy error",
+        "value": head["collisions_per_s"],
         "unit": "collisions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if forms[0] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "cells": wl.n_cells, "particles": int(wl.n_particles), "precision": "fp64",
-                   "sampler": "joint <= 4 modes, Gibbs sweep otherwise"},
-        "particle_steps_per_s": n_mean * args.steps / elapsed,
-        "candidates": cand,
-        "collisions": coll,
-        "reactions": reactions,
-        "sampler_trials_per_collision": trials / max(coll, 1),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step", "bytes_per_launch": b_alg, "steps_per_launch": steps_per_launch,
-                     "mean_launch_us": avg_launch_s * 1e6},
+        "config": {"workload": desc, "cells": wl.n_cells, "particles": int(wl.n_particles),
+                   "precision": forms[0], "sampler": "joint <= 4 modes, Gibbs sweep otherwise"},
+        "particle_steps_per_s": head["particle_steps_per_s"],
+        "energy_drift": head["energy_drift"],
+        "roofline": head["roofline"],
+        "forms": res,
     }
+    if "mixed" in res and "fp64" in res:
+        out["mixed_vs_fp64"] = res["mixed"]["collisions_per_s"] / res["fp64"]["collisions_per_s"]
     if not args.no_cpu_baseline:
+        print("# timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

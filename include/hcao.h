@@ -81,6 +81,19 @@ typedef enum {
   HCAO_EUNSUPPORTED = -8 /* feature not available in this build */
 } hcao_status;
 
+/* Arithmetic of the step.
+ *   HCAO_FP64: everything in IEEE fp64; bit-identical across launch shapes
+ *     and to the fp64 reference of the method.
+ *   HCAO_MIXED: velocities are stored in fp32; the VHS acceptance (g^2 and
+ *     the power), the Larsen-Borgnakke draws, ratio and power, the level
+ *     proposals and the post-collision kinematics run in fp32; collision
+ *     energies, energy pools, reaction thresholds, channel weights and all
+ *     accumulators stay fp64. Random draws take one 32-bit word each. The
+ *     energy each collision's fp32 velocities gain or lose is audited in
+ *     fp64 per cell and returned to the cell's particles in a later
+ *     collision (hcao_moments.E_defect_J holds what is still owed).
+ *     Results are reproducible and independent of launch shape, but not
+ *     bit-identical to HCAO_FP64. */
 typedef enum { HCAO_FP64 = 0, HCAO_MIXED = 1 } hcao_precision;
 typedef enum { HCAO_SAMPLER_AUTO = 0, HCAO_SAMPLER_JOINT = 1, HCAO_SAMPLER_GIBBS = 2 } hcao_sampler;
 typedef enum { HCAO_RX_DISSOCIATION = 0, HCAO_RX_EXCHANGE = 1, HCAO_RX_RECOMBINATION = 2 } hcao_rx_kind;
@@ -183,6 +196,9 @@ typedef struct {
   double E_formation_J;                    /* sum of formation energies */
   double T_trans_K;
   double T_vib_K[HCAO_MAX_SPECIES];
+  double E_defect_J; /* mixed form: energy owed to the particles by fp32 rounding, not yet
+                        returned (0 in HCAO_FP64); E_kin + sum (E_vib + N_s ZPE_s) + E_formation
+                        + E_defect is conserved to fp64 rounding */
 } hcao_moments;
 
 const char *hcao_status_string(hcao_status s);

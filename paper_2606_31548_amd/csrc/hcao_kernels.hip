@@ -95,6 +95,70 @@ struct RngT {
 };
 using Rng = RngT<false>;
 
+// Arithmetic type of the velocities, kinematics and sampler draws: fp64 in
+// the fp64 form, fp32 in the mixed form.
+template <bool MIX>
+struct RealOf {
+  using type = double;
+};
+template <>
+struct RealOf<true> {
+  using type = float;
+};
+template <bool MIX>
+using Real = typename RealOf<MIX>::type;
+
+template <bool MIX>
+__device__ __forceinline__ Real<MIX> draw(RngT<MIX> &rng) {
+  if constexpr (MIX)
+    return rng.uniform_f();
+  else
+    return rng.uniform();
+}
+
+template <typename R>
+struct V3 {
+  R x, y, z;
+};
+using Vec3 = V3<double>;
+
+// velocity of slot i in the state's own precision
+template <bool MIX>
+__device__ __forceinline__ V3<Real<MIX>> ldv(const State &s, uint64_t i) {
+  if constexpr (MIX)
+    return V3<float>{s.fx[i], s.fy[i], s.fz[i]};
+  else
+    return V3<double>{s.vx[i], s.vy[i], s.vz[i]};
+}
+template <bool MIX>
+__device__ __forceinline__ void stv(const State &s, uint64_t i, V3<Real<MIX>> v) {
+  if constexpr (MIX) {
+    s.fx[i] = v.x;
+    s.fy[i] = v.y;
+    s.fz[i] = v.z;
+  } else {
+    s.vx[i] = v.x;
+    s.vy[i] = v.y;
+    s.vz[i] = v.z;
+  }
+}
+// the same for kernels that serve both forms (the set that is not null)
+__device__ __forceinline__ Vec3 load_vel(const State &s, uint64_t i) {
+  if (s.fx) return Vec3{(double)s.fx[i], (double)s.fy[i], (double)s.fz[i]};
+  return Vec3{s.vx[i], s.vy[i], s.vz[i]};
+}
+__device__ __forceinline__ void store_vel(const State &s, uint64_t i, double x, double y, double z) {
+  if (s.fx) {
+    s.fx[i] = (float)x;
+    s.fy[i] = (float)y;
+    s.fz[i] = (float)z;
+  } else {
+    s.vx[i] = x;
+    s.vy[i] = y;
+    s.vz[i] = z;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fixed-sequence exp / log / pow (Cody-Waite reduction + fixed series)
 // ---------------------------------------------------------------------------
@@ -193,6 +257,22 @@ __device__ __forceinline__ bool below_pow(double u, double x, double y) {
   if (u < est * (1.0 - kFilter)) return true;
   if (u > est * (1.0 + kFilter)) return false;
   return u < dpow(x, y);
+}
+
+// x^y in single precision (mixed form)
+__device__ __forceinline__ float pow_f(float x, float y) {
+  return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+}
+
+// Larsen-Borgnakke acceptance u < (num / den)^q for num, den > 0: the fp64
+// form divides in fp64 and decides as the fp64 power does; the mixed form
+// takes the ratio and the power in fp32 (u is then an fp32 draw)
+template <bool MIX>
+__device__ __forceinline__ bool lb_accept(double u, double num, double den, double q) {
+  if constexpr (MIX)
+    return (float)u < pow_f((float)num / (float)den, (float)q);
+  else
+    return below_pow(u, num / den, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -316,16 +396,22 @@ __device__ __forceinline__ uint32_t mode_top(const SpeciesTab &S, const double *
   return lo;
 }
 
-__device__ __forceinline__ uint32_t pick_level(uint32_t top, double u) {
-  const double span = (double)top + 1.0;
-  uint32_t i = (uint32_t)floor(u * span);
+// uniform level on 0..top from one draw: min(floor(u (top + 1)), top)
+template <bool MIX>
+__device__ __forceinline__ uint32_t pick_level(uint32_t top, RngT<MIX> &rng) {
+  uint32_t i;
+  if constexpr (MIX)
+    i = (uint32_t)(rng.uniform_f() * (float)(top + 1));
+  else
+    i = (uint32_t)floor(rng.uniform() * ((double)top + 1.0));
   return i > top ? top : i;
 }
 
 // Larsen-Borgnakke relaxation of one molecule (levels at lv[m * stride]);
 // e_tr is the pair's translational energy on entry and exit.
+template <bool MIX>
 __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint32_t stride, double &e_tr,
-                          double q, Rng &rng, bool &capped) {
+                          double q, RngT<MIX> &rng, bool &capped) {
   uint32_t trials = 0;
   capped = false;
   const uint32_t nm = S.n_modes;
@@ -340,12 +426,12 @@ __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint3
       ++trials;
       double sum = 0.0;
       for (uint32_t m = 0; m < nm; ++m) {
-        const uint32_t i = pick_level(tops[m * C.block], rng.uniform());
+        const uint32_t i = pick_level<MIX>(tops[m * C.block], rng);
         cand[m * C.block] = (uint16_t)i;
         sum = sum + mode_energy(S, C.T.lev, m, i);
       }
-      const double ua = rng.uniform();
-      const bool ok = (sum < e_coll) && below_pow(ua, (e_coll - sum) / denom, q);
+      const double ua = (double)draw<MIX>(rng);
+      const bool ok = (sum < e_coll) && lb_accept<MIX>(ua, e_coll - sum, denom, q);
       if (ok) {
         for (uint32_t m = 0; m < nm; ++m) lv[m * stride] = cand[m * C.block];
         e_tr = e_coll - sum;
@@ -366,10 +452,10 @@ __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint3
     const uint32_t top = mode_top(S, C.T.lev, m, ec);
     for (;;) {
       ++trials;
-      const uint32_t i = pick_level(top, rng.uniform());
+      const uint32_t i = pick_level<MIX>(top, rng);
       const double ei = mode_energy(S, C.T.lev, m, i);
-      const double ua = rng.uniform();
-      const bool ok = (ei < ec) && below_pow(ua, (ec - ei) / den, q);
+      const double ua = (double)draw<MIX>(rng);
+      const bool ok = (ei < ec) && lb_accept<MIX>(ua, ec - ei, den, q);
       if (ok) {
         lv[m * stride] = (uint16_t)i;
         et = ec - ei;
@@ -387,37 +473,54 @@ __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint3
 }
 
 // isotropic unit vector (Marsaglia 1972)
-__device__ __forceinline__ void unit_vector(Rng &rng, double &nx, double &ny, double &nz) {
-  double x, y, s;
+template <bool MIX>
+__device__ __forceinline__ V3<Real<MIX>> unit_vector(RngT<MIX> &rng) {
+  using R = Real<MIX>;
+  R x, y, s;
   for (;;) {
-    x = 2.0 * rng.uniform() - 1.0;
-    y = 2.0 * rng.uniform() - 1.0;
+    x = R(2) * draw<MIX>(rng) - R(1);
+    y = R(2) * draw<MIX>(rng) - R(1);
     s = x * x + y * y;
-    if (s < 1.0) break;
+    if (s < R(1)) break;
   }
-  const double f = 2.0 * sqrt(1.0 - s);
-  nx = x * f;
-  ny = y * f;
-  nz = 1.0 - 2.0 * s;
+  const R f = R(2) * sqrt(R(1) - s);
+  return V3<R>{x * f, y * f, R(1) - R(2) * s};
 }
 
-struct Vec3 {
-  double x, y, z;
-};
-
-__device__ __forceinline__ Vec3 com(const PairTab &P, Vec3 a, Vec3 b) {
-  return Vec3{(P.m_a * a.x + P.m_b * b.x) / P.msum, (P.m_a * a.y + P.m_b * b.y) / P.msum,
-              (P.m_a * a.z + P.m_b * b.z) / P.msum};
+// centre-of-mass velocity of a pair (the mixed form weighs with the mass
+// fractions in fp32)
+template <bool MIX>
+__device__ __forceinline__ V3<Real<MIX>> com(const PairTab &P, V3<Real<MIX>> a, V3<Real<MIX>> b) {
+  if constexpr (MIX) {
+    const float fa = (float)P.wb, fb = (float)P.wa;  // m_a / M, m_b / M
+    return V3<float>{fa * a.x + fb * b.x, fa * a.y + fb * b.y, fa * a.z + fb * b.z};
+  } else {
+    return Vec3{(P.m_a * a.x + P.m_b * b.x) / P.msum, (P.m_a * a.y + P.m_b * b.y) / P.msum,
+                (P.m_a * a.z + P.m_b * b.z) / P.msum};
+  }
 }
 
 // two bodies about the centre-of-mass velocity with relative energy e
-__device__ __forceinline__ void split(const PairTab &P, Vec3 vcm, double e, Rng &rng, Vec3 &va, Vec3 &vb) {
-  const double g = sqrt((2.0 * e) / P.mr);
-  double nx, ny, nz;
-  unit_vector(rng, nx, ny, nz);
-  const double ga = P.wa * g, gb = P.wb * g;
-  va = Vec3{vcm.x + ga * nx, vcm.y + ga * ny, vcm.z + ga * nz};
-  vb = Vec3{vcm.x - gb * nx, vcm.y - gb * ny, vcm.z - gb * nz};
+template <bool MIX>
+__device__ __forceinline__ void split(const PairTab &P, V3<Real<MIX>> vcm, double e, RngT<MIX> &rng,
+                                      V3<Real<MIX>> &va, V3<Real<MIX>> &vb) {
+  using R = Real<MIX>;
+  R g;
+  if constexpr (MIX)
+    g = sqrtf((float)(2.0 * e) / (float)P.mr);
+  else
+    g = sqrt((2.0 * e) / P.mr);
+  const V3<R> n = unit_vector<MIX>(rng);
+  const R ga = (R)P.wa * g, gb = (R)P.wb * g;
+  va = V3<R>{vcm.x + ga * n.x, vcm.y + ga * n.y, vcm.z + ga * n.z};
+  vb = V3<R>{vcm.x - gb * n.x, vcm.y - gb * n.y, vcm.z - gb * n.z};
+}
+
+// kinetic energy 1/2 m |v|^2 in fp64
+template <typename R>
+__device__ __forceinline__ double kinetic(double m, V3<R> v) {
+  const double x = v.x, y = v.y, z = v.z;
+  return 0.5 * m * ((x * x + y * y) + z * z);
 }
 
 __device__ __forceinline__ void zero_levels(uint16_t *lv, uint32_t stride, uint32_t mm) {
@@ -426,18 +529,20 @@ __device__ __forceinline__ void zero_levels(uint16_t *lv, uint32_t stride, uint3
 
 // One colliding pair held on chip: velocities and species in registers,
 // quantum numbers in per-lane LDS slots (mode m of side x at lv_x[m * ls]).
+template <bool MIX>
 struct PairLocal {
-  Vec3 v0, v1;
+  using R = Real<MIX>;
+  V3<R> v0, v1;
   uint32_t sp0, sp1;
   bool dead0, dead1;
   uint16_t *lv0, *lv1, *lvn;
   uint32_t ls;
   bool born;  // a dissociation product (species nb_sp, velocity nb_v, levels lvn)
   uint32_t nb_sp;
-  Vec3 nb_v;
+  V3<R> nb_v;
   bool has_m, m_moved;  // third body for recombination
   uint32_t sp_m;
-  Vec3 v_m;
+  V3<R> v_m;
   double n_cell;
   int32_t rec_i;  // recombination table node of the cell temperature (-1: below, -2: above)
   double rec_f;
@@ -465,9 +570,10 @@ struct ChannelScan {
   bool found;
 };
 
+template <bool MIX>
 __device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32_t sp1, double ev0, double ev1,
                                               const uint16_t *lv0, const uint16_t *lv1, uint32_t ls, double e_tr,
-                                              Rng &rng, uint64_t &steric_ok, int pass, double target,
+                                              RngT<MIX> &rng, uint64_t &steric_ok, int pass, double target,
                                               ChannelScan &S) {
   double cum = 0.0;
   uint32_t seen = 0, ex_i = 0;
@@ -510,7 +616,7 @@ __device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32
           if (R.kind != HCAO_RX_EXCHANGE || (uint32_t)R.a != A || (uint32_t)R.b != B) continue;
           bool st_ok;
           if (pass == 0) {
-            st_ok = rng.uniform() < R.steric;
+            st_ok = (double)draw<MIX>(rng) < R.steric;
             if (st_ok && ex_i < 64) steric_ok |= (1ull << ex_i);
           } else {
             st_ok = ex_i < 64 ? ((steric_ok >> ex_i) & 1ull) != 0 : false;
@@ -549,14 +655,23 @@ __device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32
 // scattering, for one accepted pair held in P. Returns the reaction id or -1.
 // The outcome is decided first; the molecules to relax are then queued (at
 // most two, in draw order) and run through one sampler loop, and the
-// velocities come from at most two isotropic splits.
-__device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const double *rec) {
+// velocities come from at most two isotropic splits. g2 is |v_p - v_q|^2 in
+// fp64. In the mixed form, fold is energy owed to the cell's particles by
+// earlier rounding; it joins this pair's translational energy when the sum
+// stays positive.
+template <bool MIX>
+__device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rng, const double *rec,
+                       double fold) {
+  using Rl = Real<MIX>;
   const Tab &T = C.T;
   const uint32_t mm = T.mm;
   const uint32_t ls = P.ls;
   const uint32_t sp0 = P.sp0, sp1 = P.sp1;
   const PairTab &PP = T.pair(sp0, sp1);
-  const double e_tr0 = PP.hm * g2;
+  double e_tr0 = PP.hm * g2;
+  if constexpr (MIX) {
+    if (fold != 0.0 && e_tr0 + fold > 0.0) e_tr0 = e_tr0 + fold;
+  }
   const double ev0 = vib_local(T, sp0, P.lv0, ls), ev1 = vib_local(T, sp1, P.lv1, ls);
   P.born = false;
   P.m_moved = false;
@@ -564,7 +679,7 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
   // outcome: 0 none, 1 dissociation, 2 exchange, 3 recombination
   int kind = 0, rx = -1;
   uint32_t side = 0;  // reacting side: A of dissociation/exchange, B of recombination
-  Vec3 vbc{0.0, 0.0, 0.0};
+  V3<Rl> vbc{Rl(0), Rl(0), Rl(0)};
   double et = e_tr0;
 
   // --- recombination first: B + C (+M) -> A (+M) ---
@@ -578,7 +693,7 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
       sb = 1;
     else
       continue;
-    const double u = rng.uniform();
+    const double u = (double)draw<MIX>(rng);
     if (!P.has_m) {
       atomicAdd(&C.ctr[HCAO_CTR_SUPPRESSED], 1ull);
       continue;
@@ -594,9 +709,10 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
     prob = prob * P.n_cell;
     if (prob > 1.0) prob = 1.0;
     if (!(u < prob)) continue;
-    const Vec3 vb = sb ? P.v1 : P.v0, vc = sb ? P.v0 : P.v1;
-    const Vec3 c3 = com(T.pair(R.a, R.b), vb, vc);
-    const double gx = c3.x - P.v_m.x, gy = c3.y - P.v_m.y, gz = c3.z - P.v_m.z;
+    const V3<Rl> vb = sb ? P.v1 : P.v0, vc = sb ? P.v0 : P.v1;
+    const V3<Rl> c3 = com<MIX>(T.pair(R.a, R.b), vb, vc);
+    const double gx = (double)c3.x - (double)P.v_m.x, gy = (double)c3.y - (double)P.v_m.y,
+                 gz = (double)c3.z - (double)P.v_m.z;
     const double e_am = T.pair(R.c, P.sp_m).hm * ((gx * gx + gy * gy) + gz * gz);
     const double pool = (((e_am + e_tr0) + (sb ? ev1 : ev0)) + (sb ? ev0 : ev1)) - R.dh;
     const double e_left = pool - T.sp[R.c].zpe;
@@ -619,12 +735,12 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
     S.total = 0.0;
     S.found = false;
     S.first = S.last = S.pick = Channel{-1, 0, 0};
-    scan_channels(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 0, 0.0, S);
+    scan_channels<MIX>(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 0, 0.0, S);
     if (S.nch > 0) {
       Channel pick = S.first;
       if (S.nch > 1) {
-        const double target = rng.uniform() * S.total;
-        scan_channels(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 1, target, S);
+        const double target = (double)draw<MIX>(rng) * S.total;
+        scan_channels<MIX>(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 1, target, S);
         pick = S.found ? S.pick : S.last;
       }
       const ReactionTab &R = T.rx[pick.rx];
@@ -713,12 +829,12 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
   for (uint32_t j = 0; j < njob; ++j) {
     const SpeciesTab &S = T.sp[j ? spj1 : spj0];
     if (pv) {
-      const double u = rng.uniform();
+      const double u = (double)draw<MIX>(rng);
       if (!(u < S.p_vib)) continue;
       ++nrel;
     }
     bool capped = false;
-    tr += relax(C, S, j ? lvj1 : lvj0, ls, et, j ? qj1 : qj0, rng, capped);
+    tr += relax<MIX>(C, S, j ? lvj1 : lvj0, ls, et, j ? qj1 : qj0, rng, capped);
     ncap += capped ? 1u : 0u;
   }
   if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
@@ -726,48 +842,48 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
   if (ncap) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], (unsigned long long)ncap);
 
   // --- scattering ---
-  const Vec3 va0 = side ? P.v1 : P.v0, vb0 = side ? P.v0 : P.v1;
+  const V3<Rl> va0 = side ? P.v1 : P.v0, vb0 = side ? P.v0 : P.v1;
   double e1 = et, e2 = 0.0;
   if (kind == 1) {
     // share of the translational energy in the B-C motion: density
     // proportional to sqrt(beta (1 - beta)), by rejection
-    double beta;
+    Rl beta;
     for (;;) {
-      const double u1 = rng.uniform(), u2 = rng.uniform();
-      if (u2 * 0.5 < sqrt(u1 * (1.0 - u1))) {
+      const Rl u1 = draw<MIX>(rng), u2 = draw<MIX>(rng);
+      if (u2 * Rl(0.5) < sqrt(u1 * (Rl(1) - u1))) {
         beta = u1;
         break;
       }
     }
-    e2 = beta * et;
+    e2 = (double)beta * et;
     e1 = et - e2;
   }
   const uint32_t spA = side ? sp1 : sp0, spB = side ? sp0 : sp1;
   const PairTab *t1;
-  Vec3 cm;
+  V3<Rl> cm;
   if (kind == 0) {
     t1 = &PP;
-    cm = com(PP, P.v0, P.v1);
+    cm = com<MIX>(PP, P.v0, P.v1);
   } else if (kind == 1) {
     t1 = &T.pair(spA, spB);
-    cm = com(*t1, va0, vb0);
+    cm = com<MIX>(*t1, va0, vb0);
   } else if (kind == 2) {
     t1 = &T.pair(RX.c, RX.d);
-    cm = com(T.pair(spA, spB), va0, vb0);
+    cm = com<MIX>(T.pair(spA, spB), va0, vb0);
   } else {
     t1 = &T.pair(RX.c, P.sp_m);
-    cm = com(*t1, vbc, P.v_m);
+    cm = com<MIX>(*t1, vbc, P.v_m);
   }
-  Vec3 x1, y1;
-  split(*t1, cm, e1, rng, x1, y1);
+  V3<Rl> x1, y1;
+  split<MIX>(*t1, cm, e1, rng, x1, y1);
   if (kind == 0) {
     P.v0 = x1;
     P.v1 = y1;
     return -1;
   }
   if (kind == 1) {
-    Vec3 x2, y2;
-    split(T.pair(RX.c, RX.d), x1, e2, rng, x2, y2);
+    V3<Rl> x2, y2;
+    split<MIX>(T.pair(RX.c, RX.d), x1, e2, rng, x2, y2);
     x1 = x2;
     P.born = true;
     P.nb_sp = (uint32_t)RX.d;
@@ -807,6 +923,7 @@ __device__ int collide(const Ctx &C, PairLocal &P, double g2, Rng &rng, const do
 // Translational temperature of a cell by one wave: blocks of 64 particles in
 // slot order, each reduced by a halving tree (lane t takes lane t + s for
 // s = 32, ..., 1), block results added in order.
+template <bool MIX>
 __device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint64_t base, uint32_t n, uint32_t lane) {
   if (n < 2) return 0.0;
   double tot0 = 0.0, tot1 = 0.0, tot2 = 0.0, tot3 = 0.0, tot4 = 0.0;
@@ -816,7 +933,8 @@ __device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint6
     if (i < n) {
       const uint64_t g = base + i;
       const double m = spt[st.sp[g]].mass;
-      const double vx = st.vx[g], vy = st.vy[g], vz = st.vz[g];
+      const V3<Real<MIX>> v = ldv<MIX>(st, g);
+      const double vx = v.x, vy = v.y, vz = v.z;
       x0 = m;
       x1 = m * vx;
       x2 = m * vy;
@@ -850,6 +968,7 @@ struct CellHdr {
   uint32_t cell, n, cap, ncand, cstart, pad;
   double sgmax, rem, volume, weight;
   double rem_new, n_cell, rec_f;
+  double defect;  // mixed form: energy the cell's particles lack
   int32_t rec_i, pad2;
   unsigned long long sgbits, excess;
   Perm perm;
@@ -878,8 +997,16 @@ __device__ __forceinline__ uint32_t group_cell(const CellHdr *hdr, uint32_t ncel
 // particles, places the products of each cell in pair order and writes the
 // per-cell state. Pairs are disjoint and every draw is keyed by (cell,
 // pair), so the order in which lanes take work does not change the result.
-template <int BLOCK>
+//
+// The mixed form (MIX) keeps fp32 velocities, tests VHS acceptance and
+// samples levels in fp32, and keeps energies, thresholds and accumulators in
+// fp64. Each pair records the fp64 energy its fp32 velocities lost or gained
+// (the audit of its particles before and after); the cell's sum, reduced in
+// pair order, is owed to the cell and joins the translational energy of the
+// cell's pair 0 in the next step in which that pair collides.
+template <int BLOCK, bool MIX>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
+  using R = Real<MIX>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ uint32_t s_nheavy, s_nlight, s_total;
   const uint32_t tid = threadIdx.x;
@@ -934,10 +1061,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     H.rem = A.cells.rem[c];
     H.volume = A.cells.volume[c];
     H.weight = A.cells.weight[c];
+    H.defect = MIX ? A.cells.defect[c] : 0.0;
   }
   const Tab T{l_sp, l_pr, l_rx, l_lev, ns, nr, mm, GT->rec_nt};
   uint32_t *work = A.work + 3 * wbase;  // entries of (j, p, q)
   uint8_t *bflag = A.bflag + wbase;
+  double *wdef = MIX ? A.wdef + wbase : nullptr;
   const uint32_t wcap = (uint32_t)(A.grp_work[blockIdx.x + 1] - wbase);
   __syncthreads();
 
@@ -972,7 +1101,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     // cell temperature and its recombination-table coordinate (one wave per cell)
     for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
       CellHdr &H = hdr[g];
-      const double t = cell_temperature(A.st, l_sp, H.base, H.n, lane);
+      const double t = cell_temperature<MIX>(A.st, l_sp, H.base, H.n, lane);
       if (lane == 0) {
         int32_t ri = -1;
         double rf = 0.0;
@@ -1025,31 +1154,39 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
       pj = p;
       qj = qq;
       const uint64_t gp = H.base + p, gq = H.base + qq;
-      const double dx = A.st.vx[gp] - A.st.vx[gq], dy = A.st.vy[gp] - A.st.vy[gq],
-                   dz = A.st.vz[gp] - A.st.vz[gq];
-      const double g2 = (dx * dx + dy * dy) + dz * dz;
+      const V3<R> vp = ldv<MIX>(A.st, gp), vq = ldv<MIX>(A.st, gq);
+      const R dx = vp.x - vq.x, dy = vp.y - vq.y, dz = vp.z - vq.z;
+      const R g2 = (dx * dx + dy * dy) + dz * dz;
       const uint32_t a = A.st.sp[gp], b = A.st.sp[gq];
       const PairTab &PP = T.pair(a, b);
-      Rng rng;
+      RngT<MIX> rng;
       rng.open(A.seed, k, H.cell, step);
-      const double ua = rng.uniform();
+      const R ua = draw<MIX>(rng);
       bflag[j] = 0;
       // VHS acceptance ua < sigma g / (sigma g)_max with sigma g = C (g^2)^(1-w).
-      // The exact sigma g is needed for the decision only near the filter
-      // band, and for the (sigma g)_max update only when it may exceed the
-      // cell's current value (the update keeps the larger of the two).
-      const double est = (g2 > 0.0) ? PP.csg * pow_estimate(g2, PP.esg) : 0.0;
-      const double ratio = est / H.sgmax;
-      const bool need_max = est >= H.sgmax * (1.0 - 2.0 * kFilter);
-      if (ua < ratio * (1.0 - kFilter) && !need_max) {
-        acc = true;
-      } else if (ua > ratio * (1.0 + kFilter) && !need_max) {
-        acc = false;
+      if constexpr (MIX) {
+        wdef[j] = 0.0;
+        const float sg = (g2 > 0.0f) ? (float)PP.csg * pow_f(g2, (float)PP.esg) : 0.0f;
+        const unsigned long long sb = (unsigned long long)__double_as_longlong((double)sg);
+        if ((double)sg > H.sgmax && sb > hdr[g].sgbits) atomicMax(&hdr[g].sgbits, sb);
+        acc = ua < sg / (float)H.sgmax;
       } else {
-        const double sg = (g2 > 0.0) ? PP.csg * dpow(g2, PP.esg) : 0.0;
-        const unsigned long long sb = (unsigned long long)__double_as_longlong(sg);
-        if (sb > hdr[g].sgbits) atomicMax(&hdr[g].sgbits, sb);
-        acc = ua < sg / H.sgmax;
+        // The exact sigma g is needed for the decision only near the filter
+        // band, and for the (sigma g)_max update only when it may exceed the
+        // cell's current value (the update keeps the larger of the two).
+        const double est = (g2 > 0.0) ? PP.csg * pow_estimate(g2, PP.esg) : 0.0;
+        const double ratio = est / H.sgmax;
+        const bool need_max = est >= H.sgmax * (1.0 - 2.0 * kFilter);
+        if (ua < ratio * (1.0 - kFilter) && !need_max) {
+          acc = true;
+        } else if (ua > ratio * (1.0 + kFilter) && !need_max) {
+          acc = false;
+        } else {
+          const double sg = (g2 > 0.0) ? PP.csg * dpow(g2, PP.esg) : 0.0;
+          const unsigned long long sb = (unsigned long long)__double_as_longlong(sg);
+          if (sb > hdr[g].sgbits) atomicMax(&hdr[g].sgbits, sb);
+          acc = ua < sg / H.sgmax;
+        }
       }
       heavy = (T.sp[a].n_modes | T.sp[b].n_modes) != 0;
     }
@@ -1079,9 +1216,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
     const CellHdr &H = hdr[g];
     const uint32_t k = j - H.cstart;
     const uint64_t gp = H.base + p, gq = H.base + qq;
-    PairLocal P;
-    P.v0 = Vec3{A.st.vx[gp], A.st.vy[gp], A.st.vz[gp]};
-    P.v1 = Vec3{A.st.vx[gq], A.st.vy[gq], A.st.vz[gq]};
+    PairLocal<MIX> P;
+    P.v0 = ldv<MIX>(A.st, gp);
+    P.v1 = ldv<MIX>(A.st, gq);
     P.sp0 = A.st.sp[gp];
     P.sp1 = A.st.sp[gq];
     P.dead0 = P.dead1 = false;
@@ -1102,42 +1239,56 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
       gm = H.base + perm(2 * H.ncand + k);
       P.has_m = true;
       P.sp_m = A.st.sp[gm];
-      P.v_m = Vec3{A.st.vx[gm], A.st.vy[gm], A.st.vz[gm]};
+      P.v_m = ldv<MIX>(A.st, gm);
     }
     P.n_cell = H.n_cell;
     P.rec_i = H.rec_i;
     P.rec_f = H.rec_f;
-    const double dx = P.v0.x - P.v1.x, dy = P.v0.y - P.v1.y, dz = P.v0.z - P.v1.z;
+    // |v_p - v_q|^2 in fp64 (exact differences of fp32 velocities in the mixed form)
+    const double dx = (double)P.v0.x - (double)P.v1.x, dy = (double)P.v0.y - (double)P.v1.y,
+                 dz = (double)P.v0.z - (double)P.v1.z;
     const double g2 = (dx * dx + dy * dy) + dz * dz;
-    Rng rng;
+    RngT<MIX> rng;
     rng.open(A.seed, k, H.cell, step);
-    (void)rng.uniform();  // the acceptance draw of phase A
+    (void)draw<MIX>(rng);  // the acceptance draw of phase A
     unsigned long long *ctr = l_ctr + (size_t)g * nctr;
     atomicAdd(&ctr[HCAO_CTR_COLLISIONS], 1ull);
     Ctx C{T, ctr, scr, tid, BLOCK};
-    collide(C, P, g2, rng, A.rec);
-    A.st.vx[gp] = P.v0.x;
-    A.st.vy[gp] = P.v0.y;
-    A.st.vz[gp] = P.v0.z;
-    A.st.vx[gq] = P.v1.x;
-    A.st.vy[gq] = P.v1.y;
-    A.st.vz[gq] = P.v1.z;
+    // mixed form: fp64 energy (kinetic, vibrational, formation) of the
+    // pair's particles before the collision
+    double e_in = 0.0, e_m_in = 0.0;
+    if constexpr (MIX) {
+      const SpeciesTab &S0 = T.sp[P.sp0], &S1 = T.sp[P.sp1];
+      e_in = ((kinetic(S0.mass, P.v0) + vib_local(T, P.sp0, P.lv0, BLOCK)) + S0.formation) +
+             ((kinetic(S1.mass, P.v1) + vib_local(T, P.sp1, P.lv1, BLOCK)) + S1.formation);
+      if (P.has_m) e_m_in = kinetic(T.sp[P.sp_m].mass, P.v_m);
+    }
+    collide<MIX>(C, P, g2, rng, A.rec, (MIX && k == 0) ? H.defect : 0.0);
+    if constexpr (MIX) {
+      double e_out = 0.0;
+      if (!P.dead0)
+        e_out = e_out + ((kinetic(T.sp[P.sp0].mass, P.v0) + vib_local(T, P.sp0, P.lv0, BLOCK)) + T.sp[P.sp0].formation);
+      if (!P.dead1)
+        e_out = e_out + ((kinetic(T.sp[P.sp1].mass, P.v1) + vib_local(T, P.sp1, P.lv1, BLOCK)) + T.sp[P.sp1].formation);
+      if (P.born)
+        e_out = e_out + ((kinetic(T.sp[P.nb_sp].mass, P.nb_v) + vib_local(T, P.nb_sp, P.lvn, BLOCK)) +
+                         T.sp[P.nb_sp].formation);
+      double d = e_in - e_out;
+      if (P.m_moved) d = d + (e_m_in - kinetic(T.sp[P.sp_m].mass, P.v_m));
+      wdef[j] = d;
+    }
+    stv<MIX>(A.st, gp, P.v0);
+    stv<MIX>(A.st, gq, P.v1);
     A.st.sp[gp] = P.dead0 ? (uint8_t)kDead : (uint8_t)P.sp0;
     A.st.sp[gq] = P.dead1 ? (uint8_t)kDead : (uint8_t)P.sp1;
     for (uint32_t m = 0; m < mm; ++m) {
       A.st.lvl[m * A.st.stride + gp] = P.lv0[m * BLOCK];
       A.st.lvl[m * A.st.stride + gq] = P.lv1[m * BLOCK];
     }
-    if (P.m_moved) {
-      A.st.vx[gm] = P.v_m.x;
-      A.st.vy[gm] = P.v_m.y;
-      A.st.vz[gm] = P.v_m.z;
-    }
+    if (P.m_moved) stv<MIX>(A.st, gm, P.v_m);
     if (P.born) {
       const uint64_t gb = H.base + k;
-      A.scratch.vx[gb] = P.nb_v.x;
-      A.scratch.vy[gb] = P.nb_v.y;
-      A.scratch.vz[gb] = P.nb_v.z;
+      stv<MIX>(A.scratch, gb, P.nb_v);
       A.scratch.sp[gb] = (uint8_t)P.nb_sp;
       for (uint32_t m = 0; m < mm; ++m) A.scratch.lvl[m * A.scratch.stride + gb] = P.lvn[m * BLOCK];
       bflag[j] = 1;
@@ -1162,18 +1313,14 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
         const bool live = i < H.n && A.st.sp[src] != kDead;
         const unsigned long long m = __ballot(live);
         const uint64_t dst = H.base + kept + (uint32_t)__popcll(m & lt);
-        double vx = 0.0, vy = 0.0, vz = 0.0;
+        V3<R> v{R(0), R(0), R(0)};
         uint8_t spv = 0;
         if (live) {
-          vx = A.st.vx[src];
-          vy = A.st.vy[src];
-          vz = A.st.vz[src];
+          v = ldv<MIX>(A.st, src);
           spv = A.st.sp[src];
         }
         if (live) {
-          A.st.vx[dst] = vx;
-          A.st.vy[dst] = vy;
-          A.st.vz[dst] = vz;
+          stv<MIX>(A.st, dst, v);
           A.st.sp[dst] = spv;
         }
         for (uint32_t mo = 0; mo < mm; ++mo) {
@@ -1195,14 +1342,22 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
         const unsigned long long m = __ballot(f);
         if (f) {
           const uint64_t from = H.base + k, to = H.base + alive + done + (uint32_t)__popcll(m & lt);
-          A.st.vx[to] = A.scratch.vx[from];
-          A.st.vy[to] = A.scratch.vy[from];
-          A.st.vz[to] = A.scratch.vz[from];
+          stv<MIX>(A.st, to, ldv<MIX>(A.scratch, from));
           A.st.sp[to] = A.scratch.sp[from];
           for (uint32_t mo = 0; mo < mm; ++mo)
             A.st.lvl[mo * A.st.stride + to] = A.scratch.lvl[mo * A.scratch.stride + from];
         }
         done += (uint32_t)__popcll(m);
+      }
+    }
+    double dsum = 0.0;
+    if constexpr (MIX) {
+      // energy defects of the cell's pairs, summed in pair order
+      for (uint32_t k0 = 0; k0 < H.ncand; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        double x = k < H.ncand ? wdef[H.cstart + k] : 0.0;
+        for (int s = 32; s >= 1; s >>= 1) x = x + __shfl_down(x, s);
+        dsum = dsum + x;
       }
     }
     unsigned long long *tot = l_tot + (size_t)g * nctr;
@@ -1219,6 +1374,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
       const double seen = __longlong_as_double((long long)H.sgbits);
       Hm.sgmax = seen > H.sgmax ? seen : H.sgmax;
       Hm.rem = H.rem_new;
+      if (MIX) Hm.defect = H.defect + dsum;
     }
   }
   __syncthreads();
@@ -1236,6 +1392,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
       A.cells.cnt[c] = H.n;
       A.cells.sgmax[c] = H.sgmax;
       A.cells.rem[c] = H.rem;
+      if (MIX) A.cells.defect[c] = H.defect;
     }
   }
 }
@@ -1286,9 +1443,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
     polar_normals(rng, n3, n4);
     const double sigma = sqrt((kBoltz * tt) / S.mass);
     const uint64_t g = A.off[c] + i;
-    A.st.vx[g] = sigma * n1;
-    A.st.vy[g] = sigma * n2;
-    A.st.vz[g] = sigma * n3;
+    store_vel(A.st, g, sigma * n1, sigma * n2, sigma * n3);
     A.st.sp[g] = (uint8_t)s;
     for (uint32_t m = 0; m < mm; ++m) {
       uint32_t l = 0;
@@ -1345,8 +1500,8 @@ __global__ __launch_bounds__(256) void k_cell_init(CellInitArgs A) {
   double vmax2 = 0.0;
   uint32_t mask = 0;
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const double vx = A.st.vx[base + i], vy = A.st.vy[base + i], vz = A.st.vz[base + i];
-    const double v2 = (vx * vx + vy * vy) + vz * vz;
+    const Vec3 v = load_vel(A.st, base + i);
+    const double v2 = (v.x * v.x + v.y * v.y) + v.z * v.z;
     vmax2 = v2 > vmax2 ? v2 : vmax2;
     mask |= 1u << A.st.sp[base + i];
   }
@@ -1405,7 +1560,8 @@ __global__ __launch_bounds__(256) void k_moments(MomentArgs A) {
     const uint32_t s = A.st.sp[g];
     const SpeciesTab &S = T.sp[s];
     const double m = S.mass;
-    const double vx = A.st.vx[g], vy = A.st.vy[g], vz = A.st.vz[g];
+    const Vec3 v = load_vel(A.st, g);
+    const double vx = v.x, vy = v.y, vz = v.z;
     acc[0] += m * vx;
     acc[1] += m * vy;
     acc[2] += m * vz;
@@ -1592,9 +1748,7 @@ __global__ __launch_bounds__(256) void k_load_place(PlaceArgs A) {
   const uint64_t src = A.sorted_idx[j];
   const uint64_t g = A.off[c] + (j - A.packed_start[c]);
   const uint32_t mm = A.tab->max_modes;
-  A.st.vx[g] = A.vel[3 * src];
-  A.st.vy[g] = A.vel[3 * src + 1];
-  A.st.vz[g] = A.vel[3 * src + 2];
+  store_vel(A.st, g, A.vel[3 * src], A.vel[3 * src + 1], A.vel[3 * src + 2]);
   A.st.sp[g] = A.sp[src];
   for (uint32_t m = 0; m < mm; ++m) A.st.lvl[m * A.st.stride + g] = A.lvl[src * mm + m];
 }
@@ -1617,22 +1771,29 @@ size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block) {
   return (b + 15) & ~(size_t)15;
 }
 
-hipError_t launch_step(const StepArgs &a, size_t lds, int block, uint32_t n_groups, hipStream_t s) {
-  if (n_groups == 0) return hipSuccess;
+template <bool MIX>
+static hipError_t launch_step_t(const StepArgs &a, size_t lds, int block, uint32_t n_groups, hipStream_t s) {
   switch (block) {
-    case 64: hipLaunchKernelGGL((k_step<64>), dim3(n_groups), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((k_step<128>), dim3(n_groups), dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((k_step<256>), dim3(n_groups), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_step<512>), dim3(n_groups), dim3(512), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((k_step<64, MIX>), dim3(n_groups), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_step<128, MIX>), dim3(n_groups), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_step<256, MIX>), dim3(n_groups), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_step<512, MIX>), dim3(n_groups), dim3(512), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, uint32_t n_groups, hipStream_t s) {
+  if (n_groups == 0) return hipSuccess;
+  return mixed ? launch_step_t<true>(a, lds, block, n_groups, s) : launch_step_t<false>(a, lds, block, n_groups, s);
+}
+
 hipError_t set_step_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
-  const void *fns[] = {(const void *)k_step<64>, (const void *)k_step<128>, (const void *)k_step<256>,
-                       (const void *)k_step<512>};
+  const void *fns[] = {(const void *)k_step<64, false>,  (const void *)k_step<128, false>,
+                       (const void *)k_step<256, false>, (const void *)k_step<512, false>,
+                       (const void *)k_step<64, true>,   (const void *)k_step<128, true>,
+                       (const void *)k_step<256, true>,  (const void *)k_step<512, true>};
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;

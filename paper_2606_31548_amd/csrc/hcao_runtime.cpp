@@ -18,7 +18,7 @@
 namespace hcao {
 // kernels (hcao_kernels.hip)
 size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block);
-hipError_t launch_step(const StepArgs &a, size_t lds, int block, uint32_t n_groups, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, uint32_t n_groups, hipStream_t s);
 hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
@@ -110,17 +110,20 @@ struct hcao_ctx {
   uint64_t total_slots = 0;
   std::vector<uint32_t> cap_host;
   std::vector<uint64_t> off_host;
-  DevBuf<double> vx, vy, vz, bvx, bvy, bvz;
+  bool mixed = false;                         // fp32 velocities (mixed form)
+  DevBuf<double> vx, vy, vz, bvx, bvy, bvz;  // fp64 form
+  DevBuf<float> fx, fy, fz, bfx, bfy, bfz;   // mixed form
   DevBuf<uint8_t> sp, bsp;
   DevBuf<uint16_t> lvl, blvl;
   DevBuf<uint64_t> off;
   DevBuf<uint32_t> cnt, cap;
-  DevBuf<double> d_volume, d_weight, sgmax, rem;
+  DevBuf<double> d_volume, d_weight, sgmax, rem, defect;
   DevBuf<unsigned long long> ctr;
   DevBuf<uint32_t> err;
   DevBuf<uint32_t> grp, work;
   DevBuf<uint64_t> grp_work;
   DevBuf<uint8_t> bflag;
+  DevBuf<double> wdef;
   uint32_t n_groups = 0, max_group_cells = 1;
   size_t step_lds = 0;
   int block = 64;
@@ -201,11 +204,17 @@ void free_state(hcao_ctx *c) {
   c->vx.release();
   c->vy.release();
   c->vz.release();
+  c->fx.release();
+  c->fy.release();
+  c->fz.release();
   c->sp.release();
   c->lvl.release();
   c->bvx.release();
   c->bvy.release();
   c->bvz.release();
+  c->bfx.release();
+  c->bfy.release();
+  c->bfz.release();
   c->bsp.release();
   c->blvl.release();
   c->off.release();
@@ -215,11 +224,13 @@ void free_state(hcao_ctx *c) {
   c->d_weight.release();
   c->sgmax.release();
   c->rem.release();
+  c->defect.release();
   c->ctr.release();
   c->grp.release();
   c->grp_work.release();
   c->work.release();
   c->bflag.release();
+  c->wdef.release();
   c->loaded = false;
 }
 
@@ -228,12 +239,79 @@ uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
   return n + n / 4 + 32;
 }
 
-State state_of(hcao_ctx *c) { return State{c->vx.p, c->vy.p, c->vz.p, c->sp.p, c->lvl.p, c->total_slots}; }
+State state_of(hcao_ctx *c) {
+  return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->total_slots};
+}
 State scratch_of(hcao_ctx *c) {
-  return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bsp.p, c->blvl.p, c->total_slots};
+  return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->total_slots};
 }
 CellArrays cells_of(hcao_ctx *c) {
-  return CellArrays{c->off.p, c->cnt.p, c->cap.p, c->d_volume.p, c->d_weight.p, c->sgmax.p, c->rem.p, c->ctr.p};
+  return CellArrays{c->off.p,   c->cnt.p, c->cap.p,    c->d_volume.p, c->d_weight.p,
+                    c->sgmax.p, c->rem.p, c->defect.p, c->ctr.p};
+}
+
+// velocity arrays of the context's precision (three, fp64 or fp32)
+hipError_t alloc_vel(hcao_ctx *c, DevBuf<double> &x, DevBuf<double> &y, DevBuf<double> &z, DevBuf<float> &fx,
+                     DevBuf<float> &fy, DevBuf<float> &fz, uint64_t n) {
+  hipError_t e;
+  if (c->mixed) {
+    if ((e = fx.alloc(n)) != hipSuccess) return e;
+    if ((e = fy.alloc(n)) != hipSuccess) return e;
+    return fz.alloc(n);
+  }
+  if ((e = x.alloc(n)) != hipSuccess) return e;
+  if ((e = y.alloc(n)) != hipSuccess) return e;
+  return z.alloc(n);
+}
+
+// all velocity slots as fp64 (synchronous)
+hcao_status download_vel(hcao_ctx *c, std::vector<double> &vx, std::vector<double> &vy, std::vector<double> &vz) {
+  const uint64_t tot = c->total_slots;
+  vx.resize(tot);
+  vy.resize(tot);
+  vz.resize(tot);
+  if (c->mixed) {
+    std::vector<float> fx(tot), fy(tot), fz(tot);
+    HIP_TRY(c, hipMemcpyAsync(fx.data(), c->fx.p, tot * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(fy.data(), c->fy.p, tot * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(fz.data(), c->fz.p, tot * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (uint64_t i = 0; i < tot; ++i) {
+      vx[i] = fx[i];
+      vy[i] = fy[i];
+      vz[i] = fz[i];
+    }
+    return HCAO_OK;
+  }
+  HIP_TRY(c, hipMemcpyAsync(vx.data(), c->vx.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(vy.data(), c->vy.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(vz.data(), c->vz.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return HCAO_OK;
+}
+
+// all velocity slots from fp64 (rounded to fp32 in the mixed form; synchronous)
+hcao_status upload_vel(hcao_ctx *c, const std::vector<double> &vx, const std::vector<double> &vy,
+                       const std::vector<double> &vz) {
+  const uint64_t tot = c->total_slots;
+  if (c->mixed) {
+    std::vector<float> fx(tot), fy(tot), fz(tot);
+    for (uint64_t i = 0; i < tot; ++i) {
+      fx[i] = (float)vx[i];
+      fy[i] = (float)vy[i];
+      fz[i] = (float)vz[i];
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->fx.p, fx.data(), tot * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->fy.p, fy.data(), tot * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->fz.p, fz.data(), tot * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return HCAO_OK;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->vx.p, vx.data(), tot * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->vy.p, vy.data(), tot * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->vz.p, vz.data(), tot * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return HCAO_OK;
 }
 
 // Allocates the state for per-cell counts; sets capacities, offsets and
@@ -255,9 +333,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   c->off_host[nc] = tot;
   c->total_slots = tot;
   const uint32_t mm = c->max_modes ? c->max_modes : 1;
-  HIP_TRY(c, c->vx.alloc(tot));
-  HIP_TRY(c, c->vy.alloc(tot));
-  HIP_TRY(c, c->vz.alloc(tot));
+  HIP_TRY(c, alloc_vel(c, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, tot));
   HIP_TRY(c, c->sp.alloc(tot));
   HIP_TRY(c, c->lvl.alloc(tot * mm));
   HIP_TRY(c, c->off.alloc(nc + 1));
@@ -267,7 +343,9 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   HIP_TRY(c, c->d_weight.alloc(nc));
   HIP_TRY(c, c->sgmax.alloc(nc));
   HIP_TRY(c, c->rem.alloc(nc));
+  HIP_TRY(c, c->defect.alloc(nc));
   HIP_TRY(c, c->ctr.alloc((size_t)nc * kNumCtr));
+  HIP_TRY(c, hipMemsetAsync(c->defect.p, 0, nc * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->lvl.p, 0, tot * mm * sizeof(uint16_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->ctr.p, 0, (size_t)nc * kNumCtr * sizeof(unsigned long long), c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->off.p, c->off_host.data(), (nc + 1) * sizeof(uint64_t), hipMemcpyHostToDevice,
@@ -279,9 +357,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   HIP_TRY(c, hipMemcpyAsync(c->d_weight.p, c->weight.data(), nc * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   // products staging (indexed like the state)
-  HIP_TRY(c, c->bvx.alloc(tot));
-  HIP_TRY(c, c->bvy.alloc(tot));
-  HIP_TRY(c, c->bvz.alloc(tot));
+  HIP_TRY(c, alloc_vel(c, c->bvx, c->bvy, c->bvz, c->bfx, c->bfy, c->bfz, tot));
   HIP_TRY(c, c->bsp.alloc(tot));
   HIP_TRY(c, c->blvl.alloc(tot * mm));
   // workgroups over consecutive cells: at most kMaxGroupCells cells (fewer
@@ -315,6 +391,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   HIP_TRY(c, c->grp_work.alloc(gw.size()));
   HIP_TRY(c, c->work.alloc(3 * wsum));
   HIP_TRY(c, c->bflag.alloc(wsum));
+  if (c->mixed) HIP_TRY(c, c->wdef.alloc(wsum));
   HIP_TRY(c, hipMemcpyAsync(c->grp.p, grp.data(), grp.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->grp_work.p, gw.data(), gw.size() * 8, hipMemcpyHostToDevice, c->stream));
   c->step_lds = step_lds_bytes(c->tab, c->max_group_cells, c->block);
@@ -516,7 +593,7 @@ hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out) {
   if (!cfg || !out) return HCAO_EINVAL;
   if (cfg->abi_version != HCAO_ABI_VERSION) return HCAO_EINVAL;
   if (cfg->n_cells == 0 || !cfg->cell_volume || !cfg->cell_weight) return HCAO_EINVAL;
-  if (cfg->precision != HCAO_FP64) return HCAO_EUNSUPPORTED;
+  if (cfg->precision != HCAO_FP64 && cfg->precision != HCAO_MIXED) return HCAO_EINVAL;
   for (uint32_t i = 0; i < cfg->n_cells; ++i)
     if (!(cfg->cell_volume[i] > 0.0) || !(cfg->cell_weight[i] > 0.0) || !std::isfinite(cfg->cell_volume[i]) ||
         !std::isfinite(cfg->cell_weight[i]))
@@ -524,6 +601,7 @@ hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out) {
   hcao_ctx *c = new (std::nothrow) hcao_ctx();
   if (!c) return HCAO_ENOMEM;
   c->cfg = *cfg;
+  c->mixed = cfg->precision == HCAO_MIXED;
   c->volume.assign(cfg->cell_volume, cfg->cell_volume + cfg->n_cells);
   c->weight.assign(cfg->cell_weight, cfg->cell_weight + cfg->n_cells);
   c->cfg.cell_volume = nullptr;
@@ -882,13 +960,14 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
   a.grp_work = c->grp_work.p;
   a.work = c->work.p;
   a.bflag = c->bflag.p;
+  a.wdef = c->wdef.p;
   if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
   uint64_t launches = 0;
   for (uint32_t done = 0; done < n_steps;) {
     const uint32_t k = std::min(n_steps - done, c->steps_per_launch);
     a.step = c->step;
     a.n_steps = k;
-    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->n_groups, c->stream));
+    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->n_groups, c->stream));
     c->step += k;
     done += k;
     ++launches;
@@ -940,9 +1019,7 @@ hcao_status hcao_read_particles(hcao_ctx *c, uint8_t *species, double *vel, uint
   std::vector<uint8_t> sp(tot);
   std::vector<uint16_t> lv(tot * mm);
   std::vector<uint32_t> cnt(nc);
-  HIP_TRY(c, hipMemcpyAsync(vx.data(), c->vx.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(vy.data(), c->vy.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(vz.data(), c->vz.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  if (hcao_status s = download_vel(c, vx, vy, vz)) return s;
   HIP_TRY(c, hipMemcpyAsync(sp.data(), c->sp.p, tot, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(lv.data(), c->lvl.p, tot * mm * 2, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost, c->stream));
@@ -982,8 +1059,9 @@ hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments 
   DevBuf<double> d_out;
   HIP_TRY(c, d_out.alloc((size_t)nc * w));
   HIP_TRY(c, launch_moments(c->d_tab.p, c->d_lev.p, state_of(c), c->off.p, c->cnt.p, d_out.p, nc, c->stream));
-  std::vector<double> raw((size_t)nc * w);
+  std::vector<double> raw((size_t)nc * w), df(nc);
   HIP_TRY(c, hipMemcpyAsync(raw.data(), d_out.p, raw.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(df.data(), c->defect.p, nc * 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   auto fill = [&](hcao_moments &M, const double *r, double vol, double wgt) {
     std::memset(&M, 0, sizeof(M));
@@ -1006,11 +1084,15 @@ hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments 
     M.T_trans_K = ntot ? 2.0 * M.E_trans_J / (3.0 * kB * (double)ntot) : 0.0;
   };
   std::vector<double> sum(w, 0.0);
-  double vol_tot = 0.0;
+  double vol_tot = 0.0, def_tot = 0.0;
   std::vector<double> dens(ns, 0.0);
   for (uint32_t i = 0; i < nc; ++i) {
     const double *r = raw.data() + (size_t)i * w;
-    if (per_cell) fill(per_cell[i], r, c->volume[i], c->weight[i]);
+    if (per_cell) {
+      fill(per_cell[i], r, c->volume[i], c->weight[i]);
+      per_cell[i].E_defect_J = df[i];
+    }
+    def_tot += df[i];
     for (uint32_t k = 0; k < w; ++k) sum[k] += r[k];
     vol_tot += c->volume[i];
     for (uint32_t s = 0; s < ns; ++s) dens[s] += r[6 + s] * c->weight[i];
@@ -1018,6 +1100,7 @@ hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments 
   if (total) {
     fill(*total, sum.data(), 0.0, 0.0);
     for (uint32_t s = 0; s < ns; ++s) total->number_density[s] = dens[s] / vol_tot;
+    total->E_defect_J = def_tot;
   }
   return HCAO_OK;
 }
@@ -1095,14 +1178,13 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   if (hcao_status s = hcao_sync(c)) return s;
   const uint64_t tot = c->total_slots;
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
-  std::vector<double> vx(tot), vy(tot), vz(tot), sg(nc), rm(nc);
+  std::vector<double> vx, vy, vz, sg(nc), rm(nc), df(nc);
   std::vector<uint8_t> sp(tot);
   std::vector<uint16_t> lv(tot * mm);
   std::vector<uint32_t> cnt(nc);
   std::vector<unsigned long long> ctr((size_t)nc * kNumCtr);
-  HIP_TRY(c, hipMemcpy(vx.data(), c->vx.p, tot * 8, hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(vy.data(), c->vy.p, tot * 8, hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(vz.data(), c->vz.p, tot * 8, hipMemcpyDeviceToHost));
+  if (hcao_status s = download_vel(c, vx, vy, vz)) return s;
+  HIP_TRY(c, hipMemcpy(df.data(), c->defect.p, nc * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(sp.data(), c->sp.p, tot, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(lv.data(), c->lvl.p, tot * mm * 2, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost));
@@ -1111,12 +1193,14 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   HIP_TRY(c, hipMemcpy(ctr.data(), c->ctr.p, ctr.size() * 8, hipMemcpyDeviceToHost));
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(c, HCAO_EINVAL, std::string("cannot open ") + path);
-  const uint64_t hdr[6] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step};
+  // velocities are stored as fp64 in both forms (exact for fp32 values)
+  const uint64_t hdr[7] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step, c->mixed ? 1ull : 0ull};
   bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
   ok = ok && std::fwrite(c->cap_host.data(), 4, nc, f) == nc;
   ok = ok && std::fwrite(cnt.data(), 4, nc, f) == nc;
   ok = ok && std::fwrite(sg.data(), 8, nc, f) == nc;
   ok = ok && std::fwrite(rm.data(), 8, nc, f) == nc;
+  ok = ok && std::fwrite(df.data(), 8, nc, f) == nc;
   ok = ok && std::fwrite(ctr.data(), 8, ctr.size(), f) == ctr.size();
   ok = ok && std::fwrite(vx.data(), 8, tot, f) == tot;
   ok = ok && std::fwrite(vy.data(), 8, tot, f) == tot;
@@ -1134,16 +1218,16 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   if (!c->finalized) return fail(c, HCAO_ESTATE, "restore before finalize");
   FILE *f = std::fopen(path, "rb");
   if (!f) return fail(c, HCAO_EINVAL, std::string("cannot open ") + path);
-  uint64_t hdr[6];
+  uint64_t hdr[7];
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
   if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x48434130534156ull || hdr[1] != HCAO_ABI_VERSION ||
-      hdr[2] != nc || hdr[4] != mm) {
+      hdr[2] != nc || hdr[4] != mm || hdr[6] != (c->mixed ? 1ull : 0ull)) {
     std::fclose(f);
     return fail(c, HCAO_EINVAL, "checkpoint does not match this context");
   }
   const uint64_t tot = hdr[3];
   std::vector<uint32_t> capv(nc), cnt(nc);
-  std::vector<double> sg(nc), rm(nc), vx(tot), vy(tot), vz(tot);
+  std::vector<double> sg(nc), rm(nc), df(nc), vx(tot), vy(tot), vz(tot);
   std::vector<unsigned long long> ctr((size_t)nc * kNumCtr);
   std::vector<uint8_t> sp(tot);
   std::vector<uint16_t> lv(tot * mm);
@@ -1151,6 +1235,7 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   ok = ok && std::fread(cnt.data(), 4, nc, f) == nc;
   ok = ok && std::fread(sg.data(), 8, nc, f) == nc;
   ok = ok && std::fread(rm.data(), 8, nc, f) == nc;
+  ok = ok && std::fread(df.data(), 8, nc, f) == nc;
   ok = ok && std::fread(ctr.data(), 8, ctr.size(), f) == ctr.size();
   ok = ok && std::fread(vx.data(), 8, tot, f) == tot;
   ok = ok && std::fread(vy.data(), 8, tot, f) == tot;
@@ -1163,9 +1248,8 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   for (uint32_t v : capv) t2 += v;
   if (t2 != tot) return fail(c, HCAO_EINVAL, "checkpoint capacities inconsistent");
   if (hcao_status st = alloc_state(c, cnt, &capv)) return st;
-  HIP_TRY(c, hipMemcpy(c->vx.p, vx.data(), tot * 8, hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->vy.p, vy.data(), tot * 8, hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->vz.p, vz.data(), tot * 8, hipMemcpyHostToDevice));
+  if (hcao_status s = upload_vel(c, vx, vy, vz)) return s;
+  HIP_TRY(c, hipMemcpy(c->defect.p, df.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->sp.p, sp.data(), tot, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->lvl.p, lv.data(), tot * mm * 2, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->sgmax.p, sg.data(), nc * 8, hipMemcpyHostToDevice));

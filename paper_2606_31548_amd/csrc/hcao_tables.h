@@ -63,9 +63,12 @@ struct Tables {
 
 // Particle state in HBM: structure of arrays, cell-major segments with
 // per-cell slot capacity. Slot i of cell c lives at index off[c] + i;
-// level of mode m at lvl[m * stride + index].
+// level of mode m at lvl[m * stride + index]. Velocities are fp64 (vx, vy,
+// vz) in the fp64 form and fp32 (fx, fy, fz) in the mixed form; the other
+// set is null.
 struct State {
   double *vx, *vy, *vz;
+  float *fx, *fy, *fz;
   uint8_t *sp;
   uint16_t *lvl;
   uint64_t stride;  // total slots (all cells)
@@ -77,6 +80,7 @@ struct CellArrays {
   const uint32_t *cap;
   const double *volume, *weight;
   double *sgmax, *rem;
+  double *defect;           // mixed form: energy the cell's particles lack [J]
   unsigned long long *ctr;  // [n_cells][kNumCtr]
 };
 
@@ -94,6 +98,7 @@ struct StepArgs {
   const uint64_t *grp_work;
   uint32_t *work;
   uint8_t *bflag;
+  double *wdef;  // mixed form: energy defect of each candidate pair, indexed like bflag
   uint32_t *err;
   uint64_t seed;
   uint32_t step;     // index of the launch's first step

@@ -53,7 +53,7 @@ class hcao_reaction_desc(ctypes.Structure):
 class hcao_moments(ctypes.Structure):
     _fields_ = [("n_total", _u64), ("n_species", _u64 * MAX_SPECIES), ("number_density", _d * MAX_SPECIES),
                 ("momentum", _d * 3), ("E_trans_J", _d), ("E_kin_J", _d), ("E_vib_J", _d * MAX_SPECIES),
-                ("E_formation_J", _d), ("T_trans_K", _d), ("T_vib_K", _d * MAX_SPECIES)]
+                ("E_formation_J", _d), ("T_trans_K", _d), ("T_vib_K", _d * MAX_SPECIES), ("E_defect_J", _d)]
 
 
 class HcaoError(RuntimeError):
@@ -157,6 +157,8 @@ class Simulation:
         self.n_species = 0
         self.n_reactions = 0
         self.max_modes = 0
+        self.precision = precision
+        self._n_modes = []
 
     # -- plumbing --
     def _chk(self, call, rc, handle=True):
@@ -198,6 +200,7 @@ class Simulation:
         i = _i32()
         self._chk("hcao_add_species", self._L.hcao_add_species(self._h, ctypes.byref(d), ctypes.byref(i)))
         self.n_species += 1
+        self._n_modes.append(len(th) + len(we))
         return i.value
 
     def add_reaction(self, rx) -> int:
@@ -268,6 +271,20 @@ class Simulation:
             self._h, ctypes.cast(arr, _vp) if per_cell else None, ctypes.byref(tot)))
         return (tot, list(arr)) if per_cell else tot
 
+    def zero_point(self, species) -> float:
+        """Zero-point energy of a species [J]: the sum of its modes' ground levels."""
+        return float(sum(self.levels(species, m, 1)[0] for m in range(self._n_modes[species])))
+
+    def total_energy(self, m=None, with_defect: bool = True) -> float:
+        """Kinetic + vibrational (zero point included) + formation energy of
+        all particles [J], plus, by default, the energy the mixed form still
+        owes them."""
+        m = self.moments() if m is None else m
+        e = m.E_kin_J + m.E_formation_J
+        for s in range(self.n_species):
+            e += m.E_vib_J[s] + m.n_species[s] * self.zero_point(s)
+        return e + (m.E_defect_J if with_defect else 0.0)
+
     def reaction_counts(self):
         out = np.zeros(max(self.n_reactions, 1), np.uint64)
         self._chk("hcao_read_reaction_counts", self._L.hcao_read_reaction_counts(self._h, _p(out)))
@@ -311,11 +328,12 @@ class Simulation:
         self._chk("hcao_restore", self._L.hcao_restore(self._h, str(path).encode()))
 
 
-def from_workload(wl, seed: Optional[int] = None, capacity_per_cell: Optional[int] = None, stream=None):
+def from_workload(wl, seed: Optional[int] = None, capacity_per_cell: Optional[int] = None, stream=None,
+                  precision: int = FP64):
     """Builds a Simulation with the species and reactions of a workloads.Workload."""
     cap = wl.capacity_per_cell if capacity_per_cell is None else capacity_per_cell
     s = Simulation(wl.seed if seed is None else seed, wl.n_cells, wl.cell_volume, wl.cell_weight, cap,
-                   stream=stream)
+                   stream=stream, precision=precision)
     for sp in wl.species:
         s.add_species(sp)
     for rx in wl.reactions:

@@ -104,14 +104,14 @@ def _run_parity(orc, hc, wl, steps, chunks, init="thermal", cap=0, seed=None):
     return o, g
 
 
-def test_step_parity_triatomic_global_path(orc, hc):
-    """One 10,000-particle cell (larger than an LDS tile): dissociation on."""
+def test_step_parity_triatomic_single_cell(orc, hc):
+    """One 10,000-particle cell (one workgroup holds it alone): dissociation on."""
     wl = W.triatomic_reservoir(10000)
     o, g = _run_parity(orc, hc, wl, 60, [1, 9, 50])
     assert o.counters()[0, orc.CTR_COLLISIONS] > 1000
 
 
-def test_step_parity_methane_argon_lds_path(orc, hc):
+def test_step_parity_methane_argon(orc, hc):
     wl = W.methane_argon(n_cells=64, per_cell=256)
     o, g = _run_parity(orc, hc, wl, 150, [1, 49, 100])
     ctr = o.counters().sum(0)
@@ -134,8 +134,8 @@ def test_step_parity_joint_sampler_many_modes(orc, hc):
     _run_parity(orc, hc, wl, 20, [20])
 
 
-def test_step_parity_ragged_cells_mixed_paths(orc, hc):
-    """Cells of 0, 1, 2, 3 ... particles next to cells too large for LDS."""
+def test_step_parity_ragged_cells(orc, hc):
+    """Cells of 0, 1, 2, 3 ... particles next to cells of up to 2500."""
     wl = W.methane_argon(n_cells=40, per_cell=256, t_trans=30000.0)
     rng = np.random.default_rng(7)
     sizes = [0, 1, 2, 3, 4, 5, 63, 64, 65, 127, 255, 256, 257, 1000, 2500] + list(rng.integers(2, 400, 25))

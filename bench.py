@@ -45,7 +45,7 @@ def algorithmic_bytes(wl_species, counts_by_species, n_cells, b_v=8):
     return float((counts_by_species * per).sum() + 64.0 * n_cells)
 
 
-WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "triatomic")
+WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "triatomic")
 
 
 def make_workload(name):
@@ -61,6 +61,11 @@ def make_workload(name):
         wl = W.methane_argon(n_cells=4096, per_cell=256)
         desc = "4096 cells x 256 particles, CH4-like/Ar-like 1:9, T_trans 20000 K, T_vib 300 K, " \
                "CH4+M->CH3+H+M, dt 1e-8 s"
+    elif name == "batched":
+        wl = W.batched_reservoirs(n_res=4096)
+        desc = ("4096 independent reservoirs of the CH4-like/Ar-like 1:9 chemistry, particle counts log-uniform "
+                f"in [1000, 100000] ({int(wl.n_particles)} in total), T_trans uniform in [5000, 30000] K, "
+                "T_vib 300 K, CH4+M->CH3+H+M, dt 1e-8 s")
     elif name == "triatomic":
         wl = W.triatomic_reservoir(10000)
         desc = "1 cell x 10000 particles, synthetic triatomic, T_trans 10000 K, T_vib 300 K, dissociation"
@@ -108,16 +113,26 @@ def _energy(sim, m, n_modes):
     return e, th
 
 
-def measure(hcao, torch, wl, precision, steps, warmup):
-    """Times `steps` steps of one form after `warmup` untimed ones; returns
-    throughput, the step kernel's roofline figures and the energy drift."""
+def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotune=False):
+    """Times `steps` steps of one form after `warmup` untimed ones, every
+    step-kernel launch advancing `spl` steps (so that every launch, warm-up
+    included, has the same size); returns throughput, the step kernel's
+    roofline figures and the energy drift. graph: steps through the captured
+    hipGraph form; autotune: picks the launch shape first."""
     stream = torch.cuda.Stream()
     sim = hcao.from_workload(wl, stream=hcao.ctypes.c_void_p(stream.cuda_stream), precision=precision)
     sim.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    shape = sim.launch_shape()  # defaults, or HCAO_BLOCK / HCAO_GROUP_SLOTS from the environment
+    sim.set_launch_shape(shape["block"], shape["group_slots"], spl)
+    shape = sim.autotune(wl.dt, trial_steps=min(spl, 5)) if autotune else sim.launch_shape()
+    if autotune:
+        sim.set_launch_shape(shape["block"], shape["group_slots"], spl)
     n_modes = [sp.n_modes for sp in wl.species]
     m_init = sim.moments()
     e_init, th_init = _energy(sim, m_init, n_modes)
-    sim.step(wl.dt, warmup)
+    advance = (lambda n: [sim.step_graph(wl.dt, spl) for _ in range(n // spl)]) if graph else \
+        (lambda n: sim.step(wl.dt, n))
+    advance(warmup)
     sim.sync()
 
     _, _, ctr0 = sim.cell_state()
@@ -126,7 +141,7 @@ def measure(hcao, torch, wl, precision, steps, warmup):
     sim.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(wl.dt, steps)
+    advance(steps)
     sim.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -163,6 +178,7 @@ def measure(hcao, torch, wl, precision, steps, warmup):
         "energy_drift": abs(e_end - e_init) / th_init,
         "energy_owed_rel": tot1.E_defect_J / th_init,
         "T_trans_K": tot1.T_trans_K,
+        "launch_shape": dict(sim.launch_shape(), graph=graph, autotuned=autotune),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_step", "bytes_per_launch": b_alg, "steps_per_launch": steps_per_launch,
@@ -172,11 +188,42 @@ def measure(hcao, torch, wl, precision, steps, warmup):
     return r
 
 
+def measure_sequential(hcao, torch, wl, steps):
+    """The same reservoirs run one at a time: one context and one launch per
+    reservoir and step (what the batched launch replaces)."""
+    stream = torch.cuda.Stream()
+    sims = []
+    for r in range(wl.n_cells):
+        one = W.Workload(wl.name, wl.species, wl.reactions, wl.counts[r:r + 1].copy(), wl.t_trans[r:r + 1].copy(),
+                         wl.t_vib[r:r + 1].copy(), wl.cell_volume[r:r + 1].copy(), wl.cell_weight[r:r + 1].copy(),
+                         dt=wl.dt, seed=wl.seed + r)
+        s = hcao.from_workload(one, stream=hcao.ctypes.c_void_p(stream.cuda_stream))
+        s.init_thermal(one.counts, one.t_trans, one.t_vib)
+        sims.append(s)
+    for s in sims:
+        s.step(wl.dt, 1)
+    torch.cuda.synchronize()
+    c0 = sum(int(s.cell_state()[2][:, hcao.CTR_COLLISIONS].sum()) for s in sims)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s in sims:
+            s.step(wl.dt, 1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    c1 = sum(int(s.cell_state()[2][:, hcao.CTR_COLLISIONS].sum()) for s in sims)
+    for s in sims:
+        s.close()
+    return {"collisions_per_s": (c1 - c0) / elapsed, "ms_per_step": elapsed * 1e3 / steps, "steps": steps,
+            "launches_per_step": wl.n_cells}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps-per-launch", type=int, default=50,
+                    help="steps per step-kernel launch; --steps and --warmup are rounded up to multiples of it")
     ap.add_argument("--workload", default="chemistry-67m", choices=WORKLOADS)
     ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"),
                     help="both: the mixed form is the headline value, the fp64 form is timed beside it")
@@ -204,19 +251,25 @@ def main():
         return
 
     wl, desc = make_workload(args.workload)
+    spl = max(1, args.steps_per_launch)
+    steps = -(-args.steps // spl) * spl
+    warmup = -(-args.warmup // spl) * spl
     forms = {"both": ("mixed", "fp64"), "mixed": ("mixed",), "fp64": ("fp64",)}[args.precision]
+    batched = args.workload == "batched"
     res = {}
     for f in forms:
-        print(f"# timing the {f} form: {args.warmup} warm-up + {args.steps} steps", file=sys.stderr, flush=True)
-        res[f] = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, args.steps, args.warmup)
+        print(f"# timing the {f} form: {warmup} warm-up + {steps} steps, {spl} per launch", file=sys.stderr,
+              flush=True)
+        res[f] = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, steps, warmup, spl,
+                         graph=batched, autotune=batched)
     head = res[forms[0]]
     out = {
         "metric": "HCAO collisions/s on 1 MI355X; mixed FP32/FP64 vs FP64 at fixed energy error",
         "value": head["collisions_per_s"],
         "unit": "collisions/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -232,6 +285,12 @@ def main():
     }
     if "mixed" in res and "fp64" in res:
         out["mixed_vs_fp64"] = res["mixed"]["collisions_per_s"] / res["fp64"]["collisions_per_s"]
+    if batched:
+        print("# timing per-reservoir sequential launches (fp64)", file=sys.stderr, flush=True)
+        seq = measure_sequential(hcao, torch, wl, 2)
+        out["sequential_fp64"] = seq
+        if "fp64" in res:
+            out["batched_vs_sequential_fp64"] = res["fp64"]["collisions_per_s"] / seq["collisions_per_s"]
     if not args.no_cpu_baseline:
         print("# timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

@@ -229,6 +229,44 @@ hcao_status hcao_init_thermal(hcao_ctx *ctx, const uint32_t *counts, const doubl
 /* Advances every cell by n_steps collision steps of length dt [s]. */
 hcao_status hcao_step(hcao_ctx *ctx, double dt, uint32_t n_steps);
 
+/* Launch shape of the step kernel. Results do not depend on it, bit for
+ * bit: it only changes how cells map onto workgroups and launches.
+ *   block: workgroup size, 64, 128, 256 or 512 lanes;
+ *   group_slots: a workgroup takes consecutive cells while their summed slot
+ *     capacity stays within group_slots (at least one cell, at most 64, and
+ *     fewer when the workgroup's per-cell LDS records would not fit);
+ *   steps_per_launch: steps one kernel launch advances, each workgroup
+ *     keeping its cells' state in LDS between them (0 = all steps of a call).
+ * Defaults 64, 1024, 0; the environment variables HCAO_BLOCK,
+ * HCAO_GROUP_SLOTS and HCAO_STEPS_PER_LAUNCH override them at create time.
+ * hcao_set_launch_shape waits for the stream; it returns HCAO_EINVAL for a
+ * block size not listed or group_slots = 0. */
+typedef struct {
+  uint32_t block;
+  uint32_t group_slots;
+  uint32_t steps_per_launch;
+} hcao_launch_shape;
+hcao_status hcao_get_launch_shape(const hcao_ctx *ctx, hcao_launch_shape *shape);
+hcao_status hcao_set_launch_shape(hcao_ctx *ctx, const hcao_launch_shape *shape);
+
+/* Autotuner of the launch shape: times trial_steps steps of every candidate
+ * (block 64, 128, 256 x group_slots 256 .. 4096) from a device copy of the
+ * current state, puts the state back, and keeps the fastest candidate
+ * (steps_per_launch is left as it is). The particles, per-cell state,
+ * counters and step index after the call are those before it. cache_path
+ * (or, when NULL, the environment variable HCAO_AUTOTUNE_CACHE; no cache if
+ * neither is set) names a text file of earlier results keyed by cell
+ * layout, species set and precision: a hit is used without timing, a new
+ * result is appended. chosen may be NULL. Needs loaded particles. */
+hcao_status hcao_autotune(hcao_ctx *ctx, double dt, uint32_t trial_steps, const char *cache_path,
+                          hcao_launch_shape *chosen);
+
+/* hipGraph form of hcao_step: the first call for a given (dt, n_steps) and
+ * launch shape captures the step-kernel launches of n_steps steps and a
+ * device-side update of the step index into a graph on the context's
+ * stream; later calls replay it. Results are bitwise those of hcao_step. */
+hcao_status hcao_step_graph(hcao_ctx *ctx, double dt, uint32_t n_steps);
+
 /* Waits for the stream and returns the sticky device status. */
 hcao_status hcao_sync(hcao_ctx *ctx);
 
@@ -268,9 +306,9 @@ hcao_status hcao_get_recombination_table(const hcao_ctx *ctx, uint32_t reaction,
 /* Kernel timing over the stream: when enabled, each hcao_step call records
  * HIP events on the context's stream around its step-kernel launches;
  * hcao_kernel_time returns the summed elapsed milliseconds, the number of
- * launches and the number of steps they advanced since enabling. A launch
- * advances every cell by up to HCAO_STEPS_PER_LAUNCH steps (environment
- * variable; default: all steps of the call). */
+ * launches and the number of steps they advanced since enabling (a launch
+ * advances every cell by up to the shape's steps_per_launch steps; a graph
+ * replay counts its step-kernel launches). */
 hcao_status hcao_set_timing(hcao_ctx *ctx, int enable);
 hcao_status hcao_kernel_time(hcao_ctx *ctx, double *ms, uint64_t *launches, uint64_t *steps);
 

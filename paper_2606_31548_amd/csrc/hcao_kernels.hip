@@ -1015,9 +1015,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
   const Tables *GT = A.tab;
   const uint32_t ns = GT->n_species, nr = GT->n_reactions, mm = GT->max_modes, nl = GT->n_levels;
   const uint32_t nctr = 8 + nr;
-  const uint32_t c0 = A.grp[blockIdx.x], c1 = A.grp[blockIdx.x + 1];
+  const uint32_t c0 = A.grp[2 * blockIdx.x], c1 = A.grp[2 * blockIdx.x + 1];
   const uint32_t ncell = c1 - c0;
-  const uint64_t wbase = A.grp_work[blockIdx.x];
+  const uint64_t wbase = A.grp_work[2 * blockIdx.x];
 
   // ---- LDS carve-up ----
   unsigned char *q = smem;
@@ -1067,11 +1067,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
   uint32_t *work = A.work + 3 * wbase;  // entries of (j, p, q)
   uint8_t *bflag = A.bflag + wbase;
   double *wdef = MIX ? A.wdef + wbase : nullptr;
-  const uint32_t wcap = (uint32_t)(A.grp_work[blockIdx.x + 1] - wbase);
+  const uint32_t wcap = (uint32_t)(A.grp_work[2 * blockIdx.x + 1] - wbase);
   __syncthreads();
 
+  const uint32_t step0 = A.step_dev ? *A.step_dev + A.step : A.step;
   for (uint32_t si = 0; si < A.n_steps; ++si) {
-  const uint32_t step = A.step + si;
+  const uint32_t step = step0 + si;
 
   // ---- phase 0: candidate counts and permutation keys of the step ----
   for (uint32_t i = tid; i < nctr * ncell; i += BLOCK) l_ctr[i] = 0ull;
@@ -1753,6 +1754,11 @@ __global__ __launch_bounds__(256) void k_load_place(PlaceArgs A) {
   for (uint32_t m = 0; m < mm; ++m) A.st.lvl[m * A.st.stride + g] = A.lvl[src * mm + m];
 }
 
+// advances the device step index after the launches of a graph replay
+__global__ void k_advance(uint32_t *step, uint32_t n) {
+  if (threadIdx.x == 0) step[0] = step[0] + n;
+}
+
 __global__ void k_iota(uint32_t *x, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = (uint32_t)i;
@@ -1786,6 +1792,11 @@ static hipError_t launch_step_t(const StepArgs &a, size_t lds, int block, uint32
 hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, uint32_t n_groups, hipStream_t s) {
   if (n_groups == 0) return hipSuccess;
   return mixed ? launch_step_t<true>(a, lds, block, n_groups, s) : launch_step_t<false>(a, lds, block, n_groups, s);
+}
+
+hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, step, n);
+  return hipGetLastError();
 }
 
 hipError_t set_step_lds_limit(size_t bytes) {

@@ -5,6 +5,7 @@
 // gfx950 kernels of hcao_kernels.hip on the context's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -20,6 +21,7 @@ namespace hcao {
 size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block);
 hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, uint32_t n_groups, hipStream_t s);
 hipError_t set_step_lds_limit(size_t bytes);
+hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s);
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
                        hipStream_t s);
@@ -124,6 +126,7 @@ struct hcao_ctx {
   DevBuf<uint64_t> grp_work;
   DevBuf<uint8_t> bflag;
   DevBuf<double> wdef;
+  uint64_t work_entries = 0;  // entries of work / bflag / wdef
   uint32_t n_groups = 0, max_group_cells = 1;
   size_t step_lds = 0;
   int block = 64;
@@ -134,6 +137,16 @@ struct hcao_ctx {
   uint64_t timed_launches = 0, timed_steps = 0;
   uint32_t steps_per_launch = 1u << 30;  // all steps of an hcao_step call in one launch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // graph form of the step
+  uint64_t shape_gen = 0;          // bumped whenever the workgroup layout changes
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double graph_dt = 0.0;
+  uint32_t graph_n = 0, graph_launches = 0;
+  uint64_t graph_gen = ~0ull;
+  DevBuf<uint32_t> d_step;      // step index read by graph replays
+  int64_t d_step_value = -1;    // value d_step holds (-1: unknown)
 };
 
 namespace {
@@ -231,6 +244,7 @@ void free_state(hcao_ctx *c) {
   c->work.release();
   c->bflag.release();
   c->wdef.release();
+  c->work_entries = 0;
   c->loaded = false;
 }
 
@@ -314,6 +328,66 @@ hcao_status upload_vel(hcao_ctx *c, const std::vector<double> &vx, const std::ve
   return HCAO_OK;
 }
 
+// Workgroups of the step kernel: runs of consecutive cells of at most
+// kMaxGroupCells cells (fewer when the per-cell LDS records of a wide
+// workgroup would not fit) and about group_slots slots each. Workgroup w
+// takes cells [grp[2w], grp[2w+1]) and work-list entries [grp_work[2w],
+// grp_work[2w+1]) (cap/2 + 1 per cell). Workgroups are dispatched longest
+// first (by slot capacity), so that the largest cells start earliest.
+hcao_status build_groups(hcao_ctx *c) {
+  const uint32_t nc = c->cfg.n_cells;
+  uint32_t cell_limit = kMaxGroupCells;
+  while (cell_limit > 0 && step_lds_bytes(c->tab, cell_limit, c->block) > kLdsBudget) --cell_limit;
+  if (cell_limit == 0) return fail(c, HCAO_EUNSUPPORTED, "step kernel LDS budget exceeded");
+  struct G {
+    uint32_t c0, c1;
+    uint64_t w0, w1, slots;
+  };
+  std::vector<G> groups;
+  uint64_t slots = 0, wsum = 0, w0 = 0;
+  uint32_t in_group = 0, max_cells = 1, first = 0;
+  for (uint32_t i = 0; i < nc; ++i) {
+    if (in_group > 0 && (in_group >= cell_limit || slots + c->cap_host[i] > c->group_slots)) {
+      groups.push_back(G{first, i, w0, wsum, slots});
+      max_cells = std::max(max_cells, in_group);
+      in_group = 0;
+      slots = 0;
+      first = i;
+      w0 = wsum;
+    }
+    ++in_group;
+    slots += c->cap_host[i];
+    wsum += c->cap_host[i] / 2 + 1;
+  }
+  groups.push_back(G{first, nc, w0, wsum, slots});
+  max_cells = std::max(max_cells, in_group);
+  std::stable_sort(groups.begin(), groups.end(), [](const G &x, const G &y) { return x.slots > y.slots; });
+  std::vector<uint32_t> grp;
+  std::vector<uint64_t> gw;
+  for (const G &g : groups) {
+    grp.push_back(g.c0);
+    grp.push_back(g.c1);
+    gw.push_back(g.w0);
+    gw.push_back(g.w1);
+  }
+  c->n_groups = (uint32_t)groups.size();
+  c->max_group_cells = max_cells;
+  ++c->shape_gen;
+  HIP_TRY(c, c->grp.alloc(grp.size()));
+  HIP_TRY(c, c->grp_work.alloc(gw.size()));
+  if (c->work_entries != wsum) {
+    HIP_TRY(c, c->work.alloc(3 * wsum));
+    HIP_TRY(c, c->bflag.alloc(wsum));
+    if (c->mixed) HIP_TRY(c, c->wdef.alloc(wsum));
+    c->work_entries = wsum;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->grp.p, grp.data(), grp.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->grp_work.p, gw.data(), gw.size() * 8, hipMemcpyHostToDevice, c->stream));
+  c->step_lds = step_lds_bytes(c->tab, c->max_group_cells, c->block);
+  if (c->step_lds > kLdsBudget) return fail(c, HCAO_EUNSUPPORTED, "step kernel LDS budget exceeded");
+  return HCAO_OK;
+}
+
 // Allocates the state for per-cell counts; sets capacities, offsets and
 // the split between cells served from LDS tiles and from HBM.
 hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
@@ -360,42 +434,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   HIP_TRY(c, alloc_vel(c, c->bvx, c->bvy, c->bvz, c->bfx, c->bfy, c->bfz, tot));
   HIP_TRY(c, c->bsp.alloc(tot));
   HIP_TRY(c, c->blvl.alloc(tot * mm));
-  // workgroups over consecutive cells: at most kMaxGroupCells cells (fewer
-  // when the per-cell LDS records of a wide workgroup would not fit) and
-  // about group_slots slots each
-  uint32_t cell_limit = kMaxGroupCells;
-  while (cell_limit > 0 && step_lds_bytes(c->tab, cell_limit, c->block) > kLdsBudget) --cell_limit;
-  if (cell_limit == 0) return fail(c, HCAO_EUNSUPPORTED, "step kernel LDS budget exceeded");
-  std::vector<uint32_t> grp{0};
-  std::vector<uint64_t> gw{0};
-  uint64_t slots = 0, wsum = 0;
-  uint32_t in_group = 0, max_cells = 1;
-  for (uint32_t i = 0; i < nc; ++i) {
-    if (in_group > 0 && (in_group >= cell_limit || slots + c->cap_host[i] > c->group_slots)) {
-      grp.push_back(i);
-      gw.push_back(wsum);
-      max_cells = std::max(max_cells, in_group);
-      in_group = 0;
-      slots = 0;
-    }
-    ++in_group;
-    slots += c->cap_host[i];
-    wsum += c->cap_host[i] / 2 + 1;
-  }
-  grp.push_back(nc);
-  gw.push_back(wsum);
-  max_cells = std::max(max_cells, in_group);
-  c->n_groups = (uint32_t)grp.size() - 1;
-  c->max_group_cells = max_cells;
-  HIP_TRY(c, c->grp.alloc(grp.size()));
-  HIP_TRY(c, c->grp_work.alloc(gw.size()));
-  HIP_TRY(c, c->work.alloc(3 * wsum));
-  HIP_TRY(c, c->bflag.alloc(wsum));
-  if (c->mixed) HIP_TRY(c, c->wdef.alloc(wsum));
-  HIP_TRY(c, hipMemcpyAsync(c->grp.p, grp.data(), grp.size() * 4, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->grp_work.p, gw.data(), gw.size() * 8, hipMemcpyHostToDevice, c->stream));
-  c->step_lds = step_lds_bytes(c->tab, c->max_group_cells, c->block);
-  if (c->step_lds > kLdsBudget) return fail(c, HCAO_EUNSUPPORTED, "step kernel LDS budget exceeded");
+  if (hcao_status st = build_groups(c)) return st;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return HCAO_OK;
 }
@@ -941,11 +980,9 @@ hcao_status hcao_init_thermal(hcao_ctx *c, const uint32_t *counts, const double 
   return HCAO_OK;
 }
 
-hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
-  if (!c) return HCAO_EINVAL;
-  if (hcao_status s = check_sticky(c)) return s;
-  if (!c->loaded) return fail(c, HCAO_ESTATE, "step before load");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, HCAO_EINVAL, "dt must be > 0");
+namespace {
+
+StepArgs step_args(hcao_ctx *c, double dt) {
   StepArgs a{};
   a.tab = c->d_tab.p;
   a.lev = c->d_lev.p;
@@ -961,26 +998,282 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
   a.work = c->work.p;
   a.bflag = c->bflag.p;
   a.wdef = c->wdef.p;
-  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-  uint64_t launches = 0;
+  return a;
+}
+
+// Issues the step-kernel launches of n_steps steps on stream s. With
+// step_dev, the launches read their base step index from the device and a
+// final kernel advances it; otherwise base is the first step's index.
+hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base, uint32_t *step_dev,
+                        hipStream_t s, uint32_t *launches) {
+  StepArgs a = step_args(c, dt);
+  a.step_dev = step_dev;
+  uint32_t n = 0;
   for (uint32_t done = 0; done < n_steps;) {
     const uint32_t k = std::min(n_steps - done, c->steps_per_launch);
-    a.step = c->step;
+    a.step = (step_dev ? 0u : base) + done;
     a.n_steps = k;
-    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->n_groups, c->stream));
-    c->step += k;
+    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->n_groups, s));
     done += k;
-    ++launches;
+    ++n;
   }
-  if (c->timing) {
-    HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(c->ev1));
-    float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    c->timed_ms += ms;
-    c->timed_launches += launches;
-    c->timed_steps += n_steps;
+  if (step_dev) HIP_TRY(c, launch_advance(step_dev, n_steps, s));
+  if (launches) *launches = n;
+  return HCAO_OK;
+}
+
+hcao_status timing_begin(hcao_ctx *c) {
+  if (c->timing) HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  return HCAO_OK;
+}
+
+hcao_status timing_end(hcao_ctx *c, uint32_t launches, uint32_t n_steps) {
+  if (!c->timing) return HCAO_OK;
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->timed_ms += ms;
+  c->timed_launches += launches;
+  c->timed_steps += n_steps;
+  return HCAO_OK;
+}
+
+hcao_status check_step_args(hcao_ctx *c, double dt) {
+  if (!c) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "step before load");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, HCAO_EINVAL, "dt must be > 0");
+  return HCAO_OK;
+}
+
+void drop_graph(hcao_ctx *c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_gen = ~0ull;
+}
+
+}  // namespace
+
+hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
+  if (hcao_status s = check_step_args(c, dt)) return s;
+  if (hcao_status s = timing_begin(c)) return s;
+  uint32_t launches = 0;
+  if (hcao_status s = issue_steps(c, dt, n_steps, c->step, nullptr, c->stream, &launches)) return s;
+  c->step += n_steps;
+  return timing_end(c, launches, n_steps);
+}
+
+hcao_status hcao_step_graph(hcao_ctx *c, double dt, uint32_t n_steps) {
+  if (hcao_status s = check_step_args(c, dt)) return s;
+  if (n_steps == 0) return HCAO_OK;
+  if (!c->graph_exec || c->graph_dt != dt || c->graph_n != n_steps || c->graph_gen != c->shape_gen) {
+    drop_graph(c);
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->d_step.p) HIP_TRY(c, c->d_step.alloc(1));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    uint32_t launches = 0;
+    const hcao_status st = issue_steps(c, dt, n_steps, 0, c->d_step.p, c->cap_stream, &launches);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != HCAO_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    c->graph = g;
+    HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    c->graph_dt = dt;
+    c->graph_n = n_steps;
+    c->graph_launches = launches;
+    c->graph_gen = c->shape_gen;
   }
+  if (c->d_step_value != (int64_t)c->step) {
+    HIP_TRY(c, hipMemcpyAsync(c->d_step.p, &c->step, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));  // the source is host memory that changes below
+  }
+  if (hcao_status s = timing_begin(c)) return s;
+  HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+  c->step += n_steps;
+  c->d_step_value = c->step;
+  return timing_end(c, c->graph_launches, n_steps);
+}
+
+hcao_status hcao_get_launch_shape(const hcao_ctx *c, hcao_launch_shape *shape) {
+  if (!c || !shape) return HCAO_EINVAL;
+  shape->block = (uint32_t)c->block;
+  shape->group_slots = c->group_slots;
+  shape->steps_per_launch = c->steps_per_launch >= (1u << 30) ? 0u : c->steps_per_launch;
+  return HCAO_OK;
+}
+
+hcao_status hcao_set_launch_shape(hcao_ctx *c, const hcao_launch_shape *shape) {
+  if (!c || !shape) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  const uint32_t b = shape->block;
+  if ((b != 64 && b != 128 && b != 256 && b != 512) || shape->group_slots == 0)
+    return fail(c, HCAO_EINVAL, "launch shape: block must be 64, 128, 256 or 512 and group_slots > 0");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int old_block = c->block;
+  const uint32_t old_slots = c->group_slots;
+  c->block = (int)b;
+  c->group_slots = shape->group_slots;
+  c->steps_per_launch = shape->steps_per_launch ? shape->steps_per_launch : (1u << 30);
+  ++c->shape_gen;
+  if (c->loaded) {
+    if (hcao_status s = build_groups(c)) {
+      c->block = old_block;
+      c->group_slots = old_slots;
+      (void)build_groups(c);
+      return s;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return HCAO_OK;
+}
+
+extern "C++" {
+namespace {
+
+// Device copy of everything a step changes, for the autotuner's trials.
+struct Snapshot {
+  DevBuf<double> vx, vy, vz, sgmax, rem, defect;
+  DevBuf<float> fx, fy, fz;
+  DevBuf<uint8_t> sp;
+  DevBuf<uint16_t> lvl;
+  DevBuf<uint32_t> cnt, err;
+  DevBuf<unsigned long long> ctr;
+  uint32_t step = 0;
+};
+
+template <class T>
+hipError_t dcopy(DevBuf<T> &dst, const DevBuf<T> &src, bool alloc, hipStream_t s) {
+  if (!src.p) return hipSuccess;
+  if (alloc) {
+    hipError_t e = dst.alloc(src.n);
+    if (e != hipSuccess) return e;
+  }
+  return hipMemcpyAsync(dst.p, src.p, src.n * sizeof(T), hipMemcpyDeviceToDevice, s);
+}
+
+// direction: true = context -> snapshot (allocating), false = snapshot -> context
+hcao_status snapshot(hcao_ctx *c, Snapshot &S, bool take) {
+  hipStream_t st = c->stream;
+#define SNAP(f) HIP_TRY(c, take ? dcopy(S.f, c->f, true, st) : dcopy(c->f, S.f, false, st))
+  SNAP(vx);
+  SNAP(vy);
+  SNAP(vz);
+  SNAP(fx);
+  SNAP(fy);
+  SNAP(fz);
+  SNAP(sp);
+  SNAP(lvl);
+  SNAP(cnt);
+  SNAP(sgmax);
+  SNAP(rem);
+  SNAP(defect);
+  SNAP(ctr);
+  SNAP(err);
+#undef SNAP
+  if (take)
+    S.step = c->step;
+  else
+    c->step = S.step;
+  HIP_TRY(c, hipStreamSynchronize(st));
+  return HCAO_OK;
+}
+
+// cache key: cell capacities, species and precision
+std::string tune_key(const hcao_ctx *c) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the capacities
+  for (uint32_t v : c->cap_host) {
+    for (int i = 0; i < 4; ++i) {
+      h ^= (v >> (8 * i)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "cells=%u slots=%llu caps=%016llx species=%u modes=%u rx=%u mixed=%d",
+                c->cfg.n_cells, (unsigned long long)c->total_slots, (unsigned long long)h,
+                (unsigned)c->species.size(), c->max_modes, (unsigned)c->reactions.size(), c->mixed ? 1 : 0);
+  return buf;
+}
+
+}  // namespace
+}  // extern "C++"
+
+hcao_status hcao_autotune(hcao_ctx *c, double dt, uint32_t trial_steps, const char *cache_path,
+                          hcao_launch_shape *chosen) {
+  if (hcao_status s = check_step_args(c, dt)) return s;
+  if (trial_steps == 0) return fail(c, HCAO_EINVAL, "trial_steps must be > 0");
+  if (!cache_path) cache_path = std::getenv("HCAO_AUTOTUNE_CACHE");
+  const std::string key = tune_key(c);
+  hcao_launch_shape best{(uint32_t)c->block, c->group_slots, 0};
+  const uint32_t spl = c->steps_per_launch;
+  bool found = false;
+  if (cache_path) {
+    if (FILE *f = std::fopen(cache_path, "r")) {
+      char line[320];
+      while (std::fgets(line, sizeof(line), f)) {
+        unsigned b = 0, g = 0;
+        const size_t kl = key.size();
+        if (std::strncmp(line, key.c_str(), kl) == 0 && line[kl] == ' ' &&
+            std::sscanf(line + kl, " block=%u group_slots=%u", &b, &g) == 2) {
+          best.block = b;
+          best.group_slots = g;
+          found = true;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  if (!found) {
+    Snapshot S;
+    if (hcao_status s = snapshot(c, S, true)) return s;
+    const uint32_t blocks[] = {64, 128, 256};
+    const uint32_t slots[] = {256, 512, 1024, 2048, 4096};
+    const bool was_timing = c->timing;
+    double best_ms = 0.0;
+    for (uint32_t b : blocks) {
+      for (uint32_t g : slots) {
+        if (g < b) continue;
+        hcao_launch_shape t{b, g, spl >= (1u << 30) ? 0u : spl};
+        if (hcao_set_launch_shape(c, &t) != HCAO_OK) {
+          c->sticky = HCAO_OK;  // a shape whose LDS does not fit is skipped
+          continue;
+        }
+        HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+        uint32_t launches = 0;
+        hcao_status st = issue_steps(c, dt, trial_steps, c->step, nullptr, c->stream, &launches);
+        if (st) return st;
+        HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        if (hcao_status e = read_err(c)) return e;
+        if (!found || ms < best_ms) {
+          best_ms = ms;
+          best = t;
+          found = true;
+        }
+        if (hcao_status s = snapshot(c, S, false)) return s;
+      }
+    }
+    c->timing = was_timing;
+    if (cache_path) {
+      if (FILE *f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s block=%u group_slots=%u ms_per_step=%.6g\n", key.c_str(), best.block, best.group_slots,
+                     best_ms / trial_steps);
+        std::fclose(f);
+      }
+    }
+  }
+  best.steps_per_launch = spl >= (1u << 30) ? 0u : spl;
+  if (hcao_status s = hcao_set_launch_shape(c, &best)) return s;
+  if (chosen) *chosen = best;
   return HCAO_OK;
 }
 
@@ -1263,6 +1556,9 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
 void hcao_destroy(hcao_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  c->d_step.release();
   free_state(c);
   c->d_tab.release();
   c->d_lev.release();

@@ -84,9 +84,10 @@ struct CellArrays {
   unsigned long long *ctr;  // [n_cells][kNumCtr]
 };
 
-// One workgroup processes the consecutive cells [grp[b], grp[b+1]); its work
-// list and product flags live at grp_work[b] in work / bflag (sized for
-// sum over its cells of cap/2 + 1 entries).
+// Workgroup b processes the consecutive cells [grp[2b], grp[2b+1]); its work
+// list, product flags and pair energy defects are the entries
+// [grp_work[2b], grp_work[2b+1]) of work (three words each) / bflag / wdef
+// (sum over its cells of cap/2 + 1 entries).
 struct StepArgs {
   const Tables *tab;
   const double *lev;
@@ -101,8 +102,9 @@ struct StepArgs {
   double *wdef;  // mixed form: energy defect of each candidate pair, indexed like bflag
   uint32_t *err;
   uint64_t seed;
-  uint32_t step;     // index of the launch's first step
-  uint32_t n_steps;  // steps advanced by this launch
+  const uint32_t *step_dev;  // device step index (graph replays) or null
+  uint32_t step;             // index of the launch's first step (plus *step_dev when set)
+  uint32_t n_steps;          // steps advanced by this launch
   double dt;
 };
 

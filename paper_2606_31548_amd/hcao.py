@@ -56,6 +56,10 @@ class hcao_moments(ctypes.Structure):
                 ("E_formation_J", _d), ("T_trans_K", _d), ("T_vib_K", _d * MAX_SPECIES), ("E_defect_J", _d)]
 
 
+class hcao_launch_shape(ctypes.Structure):
+    _fields_ = [("block", _u32), ("group_slots", _u32), ("steps_per_launch", _u32)]
+
+
 class HcaoError(RuntimeError):
     def __init__(self, call, code, msg=""):
         super().__init__(f"{call}: {STATUS.get(code, code)} {msg}".strip())
@@ -108,10 +112,15 @@ def load_library():
     L.hcao_save.argtypes = [_vp, ctypes.c_char_p]
     L.hcao_restore.argtypes = [_vp, ctypes.c_char_p]
     L.hcao_destroy.argtypes = [_vp]; L.hcao_destroy.restype = None
+    L.hcao_get_launch_shape.argtypes = [_vp, ctypes.POINTER(hcao_launch_shape)]
+    L.hcao_set_launch_shape.argtypes = [_vp, ctypes.POINTER(hcao_launch_shape)]
+    L.hcao_autotune.argtypes = [_vp, _d, _u32, ctypes.c_char_p, ctypes.POINTER(hcao_launch_shape)]
+    L.hcao_step_graph.argtypes = [_vp, _d, _u32]
     for name in ("hcao_create", "hcao_add_species", "hcao_add_reaction", "hcao_finalize", "hcao_load_particles",
                  "hcao_init_thermal", "hcao_step", "hcao_sync", "hcao_get_counts", "hcao_read_particles",
                  "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
-                 "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore"):
+                 "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore",
+                 "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -234,6 +243,25 @@ class Simulation:
 
     def step(self, dt: float, n_steps: int = 1):
         self._chk("hcao_step", self._L.hcao_step(self._h, float(dt), int(n_steps)))
+
+    def step_graph(self, dt: float, n_steps: int = 1):
+        """hcao_step through a captured hipGraph (captured on first use per (dt, n_steps))."""
+        self._chk("hcao_step_graph", self._L.hcao_step_graph(self._h, float(dt), int(n_steps)))
+
+    def launch_shape(self):
+        sh = hcao_launch_shape()
+        self._chk("hcao_get_launch_shape", self._L.hcao_get_launch_shape(self._h, ctypes.byref(sh)))
+        return {"block": sh.block, "group_slots": sh.group_slots, "steps_per_launch": sh.steps_per_launch}
+
+    def set_launch_shape(self, block: int = 64, group_slots: int = 1024, steps_per_launch: int = 0):
+        sh = hcao_launch_shape(block, group_slots, steps_per_launch)
+        self._chk("hcao_set_launch_shape", self._L.hcao_set_launch_shape(self._h, ctypes.byref(sh)))
+
+    def autotune(self, dt: float, trial_steps: int = 5, cache_path=None):
+        sh = hcao_launch_shape()
+        cp = None if cache_path is None else str(cache_path).encode()
+        self._chk("hcao_autotune", self._L.hcao_autotune(self._h, float(dt), int(trial_steps), cp, ctypes.byref(sh)))
+        return {"block": sh.block, "group_slots": sh.group_slots, "steps_per_launch": sh.steps_per_launch}
 
     def sync(self):
         self._chk("hcao_sync", self._L.hcao_sync(self._h))

@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"),
                     help="both: the mixed form is the headline value, the fp64 form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default (or HCAO_BLOCK / HCAO_GROUP_SLOTS) launch shape instead of autotuning it")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this size (counter calibration)")
@@ -261,7 +263,7 @@ def main():
         print(f"# timing the {f} form: {warmup} warm-up + {steps} steps, {spl} per launch", file=sys.stderr,
               flush=True)
         res[f] = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, steps, warmup, spl,
-                         graph=batched, autotune=batched)
+                         graph=batched, autotune=not args.no_autotune)
     head = res[forms[0]]
     out = {
         "metric": "HCAO collisions/s on 1 MI355X; mixed FP32/FP64 vs FP64 at fixed energy error",

@@ -205,40 +205,42 @@ double orc_detpow(double x, double y) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Keyed permutation of [0, n): Feistel network on 2b bits (Luby-Rackoff),
- * 16 rounds for half widths b <= 3 and 10 rounds above, cycle walking
- * (Black-Rogaway) into [0, n). The round function uses 24-bit factors. */
-static uint32_t feistel_round(uint32_t r, uint32_t key, uint32_t mask) {
+/* Keyed permutation of [0, n): a Feistel network on Z_m x Z_m with
+ * m = ceil(sqrt(n)) and addition modulo m in place of xor (a generalised
+ * Feistel cipher, Black & Rogaway 2002), 16 rounds for m <= 8 and 10 rounds
+ * above, then cycle walking into [0, n). The round function mixes the right
+ * half with the round key using 24-bit factors and maps the 32-bit hash to
+ * [0, m) by its high product with m. */
+static uint32_t feistel_round(uint32_t r, uint32_t key, uint32_t m) {
   uint32_t h = ((r ^ key) & 0xFFFFFFu) * 0x9E3779u;
   h ^= h >> 15;
   h = (h & 0xFFFFFFu) * 0x85EBCBu;
   h ^= h >> 13;
-  return h & mask;
+  return (uint32_t)(((uint64_t)h * (uint64_t)m) >> 32);
 }
 
-static uint32_t feistel_half_bits(uint32_t n) {
-  uint32_t b = 1;
-  while (((uint64_t)1 << (2 * b)) < (uint64_t)n) b += 1;
-  return b;
+static uint32_t feistel_side(uint32_t n) {
+  uint32_t m = 1;
+  while ((uint64_t)m * (uint64_t)m < (uint64_t)n) m += 1;
+  return m;
 }
 
-static uint32_t feistel_once(uint32_t x, uint32_t b, const uint32_t keys[16]) {
-  uint32_t mask = ((uint32_t)1 << b) - 1u;
-  uint32_t rounds = b <= 3 ? 16 : 10;
-  uint32_t left = x >> b, right = x & mask;
+static uint32_t feistel_once(uint32_t x, uint32_t m, const uint32_t keys[16]) {
+  uint32_t rounds = m <= 8 ? 16 : 10;
+  uint32_t left = x / m, right = x % m;
   for (uint32_t r = 0; r < rounds; ++r) {
     uint32_t nl = right;
-    uint32_t nr = left ^ feistel_round(right, keys[r], mask);
+    uint32_t nr = (left + feistel_round(right, keys[r], m)) % m;
     left = nl;
     right = nr;
   }
-  return (left << b) | right;
+  return left * m + right;
 }
 
 uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[16], uint32_t i) {
-  uint32_t b = feistel_half_bits(n);
-  uint32_t y = feistel_once(i, b, keys);
-  while (y >= n) y = feistel_once(y, b, keys);
+  uint32_t m = feistel_side(n);
+  uint32_t y = feistel_once(i, m, keys);
+  while (y >= n) y = feistel_once(y, m, keys);
   return y;
 }
 

@@ -276,61 +276,69 @@ __device__ __forceinline__ bool lb_accept(double u, double num, double den, doub
 }
 
 // ---------------------------------------------------------------------------
-// keyed permutation of [0, n): Feistel network on 2b bits (Luby-Rackoff),
-// 16 rounds for b <= 3 and 10 above, cycle walking (Black-Rogaway); the
-// round function multiplies 24-bit factors (full-rate v_mul_u32_u24)
+// keyed permutation of [0, n): Feistel network on Z_m x Z_m, m = ceil(sqrt n),
+// with addition modulo m (generalised Feistel cipher, Black-Rogaway), 16
+// rounds for m <= 8 and 10 above, cycle walking into [0, n) (m^2 / n < 1.2
+// for n >= 25, so walks are short). The round function multiplies 24-bit
+// factors (full-rate v_mul_u32_u24) and scales the hash to [0, m) by its
+// high product with m.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t feistel_f(uint32_t r, uint32_t key, uint32_t mask) {
+__device__ __forceinline__ uint32_t feistel_f(uint32_t r, uint32_t key, uint32_t m) {
   uint32_t h = __umul24(r ^ key, 0x9E3779u);
   h ^= h >> 15;
   h = __umul24(h, 0x85EBCBu);
   h ^= h >> 13;
-  return h & mask;
+  return __umulhi(h, m);
 }
 
 struct Perm {
-  uint32_t n, b, mask, rounds;
+  uint32_t n, m, pad, rounds;
   uint32_t k[16];
 };
 
 // the permutation evaluated with its keys in registers
 struct PermReg {
-  uint32_t n, b, mask, rounds;
+  uint32_t n, m, rounds;
   uint32_t k[16];
   __device__ __forceinline__ void load(const Perm &P) {
     n = P.n;
-    b = P.b;
-    mask = P.mask;
+    m = P.m;
     rounds = P.rounds;
 #pragma unroll
     for (int i = 0; i < 16; ++i) k[i] = P.k[i];
   }
   template <int R>
-  __device__ __forceinline__ uint32_t once_r(uint32_t x) const {
-    uint32_t l = x >> b, r = x & mask;
+  __device__ __forceinline__ void once_r(uint32_t &l, uint32_t &r) const {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const uint32_t nr = l ^ feistel_f(r, k[i], mask);
+      uint32_t s = l + feistel_f(r, k[i], m);
+      s = s >= m ? s - m : s;
       l = r;
-      r = nr;
+      r = s;
     }
-    return (l << b) | r;
   }
-  __device__ __forceinline__ uint32_t once(uint32_t x) const { return rounds == 10 ? once_r<10>(x) : once_r<16>(x); }
+  __device__ __forceinline__ void once(uint32_t &l, uint32_t &r) const {
+    if (rounds == 10)
+      once_r<10>(l, r);
+    else
+      once_r<16>(l, r);
+  }
   __device__ __forceinline__ uint32_t operator()(uint32_t i) const {
-    uint32_t y = once(i);
-    while (y >= n) y = once(y);
-    return y;
+    uint32_t l = i / m, r = i - l * m;
+    once(l, r);
+    while (l * m + r >= n) once(l, r);
+    return l * m + r;
   }
 };
 
 __device__ __forceinline__ void make_perm(Perm &P, uint32_t n, uint64_t seed, uint32_t cell, uint32_t step) {
   P.n = n;
-  uint32_t b = 1;
-  while ((1ull << (2 * b)) < (unsigned long long)n) ++b;
-  P.b = b;
-  P.mask = (1u << b) - 1u;
-  P.rounds = b <= 3 ? 16u : 10u;
+  uint32_t m = (uint32_t)sqrtf((float)n);
+  while (m * m < n) ++m;
+  while (m > 1 && (m - 1) * (m - 1) >= n) --m;
+  P.m = m;
+  P.pad = 0;
+  P.rounds = m <= 8 ? 16u : 10u;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
   for (uint32_t blk = 0; blk < 4; ++blk) {

@@ -1,8 +1,9 @@
 """Pins of the oracle's determinism primitives: Philox4x32-10 against the
 published known-answer vectors, the deterministic log/exp/pow against the C
-library to a few ulp, and the keyed Feistel permutation (bijectivity and uniformity of
-the pairs it forms; 4 rounds fail the uniformity pin for small cells, 10
-rounds suffice for half widths of 4 bits and more, 16 below)."""
+library to a few ulp, and the keyed permutation that forms the candidate
+pairs, a Feistel network on Z_m x Z_m with modular addition (bijectivity,
+uniformity of the ordered pairs it forms at several cell sizes and pair
+positions, and of single positions in a large cell)."""
 import math
 import os
 
@@ -86,15 +87,26 @@ def test_feistel_is_permutation(orc, n):
     assert sorted(perm) == list(range(n))
 
 
-@pytest.mark.parametrize("n", [5, 8, 20, 100])
-def test_feistel_pairs_are_uniform(orc, n):
-    # over many keys, the first candidate pair (pi(0), pi(1)) of a cell must
-    # hit each ordered pair equally often
+@pytest.mark.parametrize("n,k", [(5, 0), (8, 0), (20, 0), (100, 0), (65, 7), (9, 2)])
+def test_feistel_pairs_are_uniform(orc, n, k):
+    # over many keys, candidate pair k, (pi(2k), pi(2k+1)), of a cell must hit
+    # each ordered pair equally often (m = 3, 3, 5, 10, 9, 3: both round counts)
     counts = np.zeros((n, n), np.int64)
     for s in range(max(28000, 40 * n * (n - 1))):
         keys = np.concatenate([orc.philox((11, 0), (b, 0xFFFFFFFF, 5, s)) for b in range(4)])
-        p, q = orc.feistel_index(n, keys, 0), orc.feistel_index(n, keys, 1)
+        p, q = orc.feistel_index(n, keys, 2 * k), orc.feistel_index(n, keys, 2 * k + 1)
         assert p != q
         counts[p, q] += 1
     obs = counts[~np.eye(n, dtype=bool)]
     assert stats.chisquare(obs).pvalue > 1e-4
+
+
+def test_feistel_positions_are_uniform_in_a_large_cell(orc):
+    # a single position of the permutation (as a third body takes it) is
+    # uniform over a 300-particle cell (m = 18, one cycle-walk step in ~8)
+    n = 300
+    counts = np.zeros(n, np.int64)
+    for s in range(30000):
+        keys = np.concatenate([orc.philox((3, 1), (b, 0xFFFFFFFF, 9, s)) for b in range(4)])
+        counts[orc.feistel_index(n, keys, 123)] += 1
+    assert stats.chisquare(counts).pvalue > 1e-4

@@ -930,37 +930,47 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
 
 // Translational temperature of a cell by one wave: blocks of 64 particles in
 // slot order, each reduced by a halving tree (lane t takes lane t + s for
-// s = 32, ..., 1), block results added in order.
+// s = 32, ..., 1), block results added in order. The loads of four blocks
+// are issued together, so their latencies overlap.
 template <bool MIX>
 __device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint64_t base, uint32_t n, uint32_t lane) {
   if (n < 2) return 0.0;
+  constexpr int U = 4;
   double tot0 = 0.0, tot1 = 0.0, tot2 = 0.0, tot3 = 0.0, tot4 = 0.0;
-  for (uint32_t b0 = 0; b0 < n; b0 += 64) {
-    const uint32_t i = b0 + lane;
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
-    if (i < n) {
-      const uint64_t g = base + i;
-      const double m = spt[st.sp[g]].mass;
-      const V3<Real<MIX>> v = ldv<MIX>(st, g);
-      const double vx = v.x, vy = v.y, vz = v.z;
-      x0 = m;
-      x1 = m * vx;
-      x2 = m * vy;
-      x3 = m * vz;
-      x4 = m * ((vx * vx + vy * vy) + vz * vz);
+  for (uint32_t b0 = 0; b0 < n; b0 += 64 * U) {
+    double m[U], vx[U], vy[U], vz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = b0 + 64 * u + lane;
+      m[u] = 0.0;
+      vx[u] = vy[u] = vz[u] = 0.0;
+      if (i < n) {
+        const uint64_t g = base + i;
+        m[u] = spt[st.sp[g]].mass;
+        const V3<Real<MIX>> v = ldv<MIX>(st, g);
+        vx[u] = v.x;
+        vy[u] = v.y;
+        vz[u] = v.z;
+      }
     }
-    for (int s = 32; s >= 1; s >>= 1) {
-      x0 = x0 + __shfl_down(x0, s);
-      x1 = x1 + __shfl_down(x1, s);
-      x2 = x2 + __shfl_down(x2, s);
-      x3 = x3 + __shfl_down(x3, s);
-      x4 = x4 + __shfl_down(x4, s);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (b0 + 64 * u >= n) break;
+      double x0 = m[u], x1 = m[u] * vx[u], x2 = m[u] * vy[u], x3 = m[u] * vz[u];
+      double x4 = m[u] * ((vx[u] * vx[u] + vy[u] * vy[u]) + vz[u] * vz[u]);
+      for (int s = 32; s >= 1; s >>= 1) {
+        x0 = x0 + __shfl_down(x0, s);
+        x1 = x1 + __shfl_down(x1, s);
+        x2 = x2 + __shfl_down(x2, s);
+        x3 = x3 + __shfl_down(x3, s);
+        x4 = x4 + __shfl_down(x4, s);
+      }
+      tot0 = tot0 + x0;
+      tot1 = tot1 + x1;
+      tot2 = tot2 + x2;
+      tot3 = tot3 + x3;
+      tot4 = tot4 + x4;
     }
-    tot0 = tot0 + x0;
-    tot1 = tot1 + x1;
-    tot2 = tot2 + x2;
-    tot3 = tot3 + x3;
-    tot4 = tot4 + x4;
   }
   const double p2 = (tot1 * tot1 + tot2 * tot2) + tot3 * tot3;
   return (tot4 - p2 / tot0) / (3.0 * kBoltz * (double)n);
@@ -1013,7 +1023,7 @@ __device__ __forceinline__ uint32_t group_cell(const CellHdr *hdr, uint32_t ncel
 // pair order, is owed to the cell and joins the translational energy of the
 // cell's pair 0 in the next step in which that pair collides.
 template <int BLOCK, bool MIX>
-__global__ __launch_bounds__(BLOCK) void k_step(StepArgs A) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs A) {
   using R = Real<MIX>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ uint32_t s_nheavy, s_nlight, s_total;

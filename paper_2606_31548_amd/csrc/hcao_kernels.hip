@@ -1,18 +1,18 @@
 // hcao_kernels.hip -- gfx950 kernels of the HCAO DSMC collision step.
 //
-// One workgroup owns one reservoir cell for a whole step: it stages the
-// cell's particles in LDS (or works in place in HBM for cells too large for
-// LDS), forms NTC candidate pairs from a keyed permutation, tests them with
-// the VHS acceptance, runs the reaction decision / Larsen-Borgnakke
-// relaxation / isotropic scattering of each accepted pair in its lane,
-// appends reaction products in pair order with a block scan, and writes the
-// tile back with coalesced stores. Cells never exchange particles, so the
-// launch needs no inter-workgroup communication and the result does not
-// depend on the launch shape.
+// A workgroup owns a run of consecutive reservoir cells for several steps
+// (persistent): it keeps the tables and the cells' headers in LDS, forms NTC
+// candidate pairs from a keyed permutation, tests them with the VHS
+// acceptance, runs the reaction decision / Larsen-Borgnakke relaxation /
+// isotropic scattering of each accepted pair in one lane, and places products
+// and removes recombined particles with wavefront ballots. Cells never
+// exchange particles, so a launch needs no inter-workgroup communication and
+// the result does not depend on the launch shape.
 //
 // Arithmetic is IEEE fp64 without contraction (built with -ffp-contract=off);
 // log/exp are the library's own fixed-sequence versions, so that every
-// decision is reproducible bit for bit.
+// decision is reproducible bit for bit. The mixed form (MIX) keeps fp32
+// velocities, kinematics and sampler arithmetic and fp64 energies.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

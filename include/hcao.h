@@ -280,6 +280,13 @@ uint32_t hcao_step_index(const hcao_ctx *ctx);
  * species[total], vel[3 total], levels[total * max_modes]. */
 hcao_status hcao_read_particles(hcao_ctx *ctx, uint8_t *species, double *vel, uint16_t *levels);
 
+/* The live particles of one cell in canonical order (for sampled checks of
+ * large runs): writes min(count, max_n) particles into species[max_n],
+ * vel[3 max_n], levels[max_n * max_modes] and the cell's count into *n_out.
+ * HCAO_EINVAL for a cell index >= n_cells. */
+hcao_status hcao_read_cell_particles(hcao_ctx *ctx, uint32_t cell, uint32_t max_n, uint8_t *species, double *vel,
+                                     uint16_t *levels, uint32_t *n_out);
+
 /* Per-cell state: sgmax[n_cells] ((sigma g)_max, m^3/s), rem[n_cells] (NTC
  * remainder), counters[n_cells * HCAO_N_CTR]. Any pointer may be NULL. */
 hcao_status hcao_read_cell_state(hcao_ctx *ctx, double *sgmax, double *rem, uint64_t *counters);

@@ -1303,6 +1303,47 @@ hcao_status hcao_get_counts(hcao_ctx *c, uint64_t *per_cell, uint64_t *total) {
 uint32_t hcao_max_modes(const hcao_ctx *c) { return c ? c->max_modes : 0; }
 uint32_t hcao_step_index(const hcao_ctx *c) { return c ? c->step : 0; }
 
+hcao_status hcao_read_cell_particles(hcao_ctx *c, uint32_t cell, uint32_t max_n, uint8_t *species, double *vel,
+                                     uint16_t *levels, uint32_t *n_out) {
+  if (!c || (max_n && (!species || !vel || !levels))) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  if (cell >= c->cfg.n_cells) return fail(c, HCAO_EINVAL, "cell index out of range");
+  const uint64_t tot = c->total_slots, b = c->off_host[cell];
+  const uint32_t mm = c->max_modes ? c->max_modes : 1;
+  uint32_t n = 0;
+  HIP_TRY(c, hipMemcpyAsync(&n, c->cnt.p + cell, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (n_out) *n_out = n;
+  const uint32_t k = std::min(n, max_n);
+  if (k == 0) return HCAO_OK;
+  std::vector<double> v(3 * (size_t)k);
+  std::vector<uint16_t> lv((size_t)k * mm);
+  if (c->mixed) {
+    std::vector<float> f(3 * (size_t)k);
+    HIP_TRY(c, hipMemcpyAsync(f.data(), c->fx.p + b, k * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(f.data() + k, c->fy.p + b, k * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(f.data() + 2 * (size_t)k, c->fz.p + b, k * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < v.size(); ++i) v[i] = f[i];
+  } else {
+    HIP_TRY(c, hipMemcpyAsync(v.data(), c->vx.p + b, k * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(v.data() + k, c->vy.p + b, k * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(v.data() + 2 * (size_t)k, c->vz.p + b, k * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(c, hipMemcpyAsync(species, c->sp.p + b, k, hipMemcpyDeviceToHost, c->stream));
+  for (uint32_t m = 0; m < mm; ++m)
+    HIP_TRY(c, hipMemcpyAsync(lv.data() + (size_t)m * k, c->lvl.p + (size_t)m * tot + b, k * 2, hipMemcpyDeviceToHost,
+                              c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (uint32_t i = 0; i < k; ++i) {
+    vel[3 * i] = v[i];
+    vel[3 * i + 1] = v[k + i];
+    vel[3 * i + 2] = v[2 * (size_t)k + i];
+    for (uint32_t m = 0; m < mm; ++m) levels[(size_t)i * mm + m] = lv[(size_t)m * k + i];
+  }
+  return HCAO_OK;
+}
+
 hcao_status hcao_read_particles(hcao_ctx *c, uint8_t *species, double *vel, uint16_t *levels) {
   if (!c || !species || !vel || !levels) return HCAO_EINVAL;
   if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");

@@ -116,11 +116,13 @@ def load_library():
     L.hcao_set_launch_shape.argtypes = [_vp, ctypes.POINTER(hcao_launch_shape)]
     L.hcao_autotune.argtypes = [_vp, _d, _u32, ctypes.c_char_p, ctypes.POINTER(hcao_launch_shape)]
     L.hcao_step_graph.argtypes = [_vp, _d, _u32]
+    L.hcao_read_cell_particles.argtypes = [_vp, _u32, _u32, _vp, _vp, _vp, ctypes.POINTER(_u32)]
     for name in ("hcao_create", "hcao_add_species", "hcao_add_reaction", "hcao_finalize", "hcao_load_particles",
                  "hcao_init_thermal", "hcao_step", "hcao_sync", "hcao_get_counts", "hcao_read_particles",
                  "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
                  "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore",
-                 "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph"):
+                 "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
+                 "hcao_read_cell_particles"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -284,6 +286,18 @@ class Simulation:
         lv = np.zeros((tot, max(self.max_modes, 1)), np.uint16)
         self._chk("hcao_read_particles", self._L.hcao_read_particles(self._h, _p(sp), _p(v), _p(lv)))
         return per.astype(np.int64), sp, v, lv[:, :self.max_modes]
+
+    def read_cell(self, cell: int, max_n: int = 1 << 20):
+        """(species, vel[n,3], levels[n, max_modes]) of one cell in canonical order."""
+        mm = max(self.max_modes, 1)
+        sp = np.zeros(max_n, np.uint8)
+        v = np.zeros((max_n, 3), np.float64)
+        lv = np.zeros((max_n, mm), np.uint16)
+        n = _u32()
+        self._chk("hcao_read_cell_particles", self._L.hcao_read_cell_particles(
+            self._h, int(cell), int(max_n), _p(sp), _p(v), _p(lv), ctypes.byref(n)))
+        k = min(n.value, max_n)
+        return sp[:k], v[:k], lv[:k, :self.max_modes]
 
     def cell_state(self):
         sg = np.zeros(self.n_cells, np.float64)

@@ -1026,7 +1026,8 @@ template <int BLOCK, bool MIX>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs A) {
   using R = Real<MIX>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ uint32_t s_nheavy, s_nlight, s_total;
+  __shared__ uint32_t s_nwork, s_total;
+  __shared__ uint32_t s_bin[256];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u, wave = tid >> 6;
   const unsigned long long lt = lane ? ((1ull << lane) - 1ull) : 0ull;
@@ -1082,10 +1083,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     H.defect = MIX ? A.cells.defect[c] : 0.0;
   }
   const Tab T{l_sp, l_pr, l_rx, l_lev, ns, nr, mm, GT->rec_nt};
-  uint32_t *work = A.work + 3 * wbase;  // entries of (j, p, q)
+  const uint32_t wcap = (uint32_t)(A.grp_work[2 * blockIdx.x + 1] - wbase);
+  uint32_t *work_in = A.work + 7 * wbase;           // accepted pairs as found: (j, p, q, key)
+  uint32_t *work = work_in + 4 * (size_t)wcap;      // the same sorted by key: (j, p, q)
   uint8_t *bflag = A.bflag + wbase;
   double *wdef = MIX ? A.wdef + wbase : nullptr;
-  const uint32_t wcap = (uint32_t)(A.grp_work[2 * blockIdx.x + 1] - wbase);
   __syncthreads();
 
   const uint32_t step0 = A.step_dev ? *A.step_dev + A.step : A.step;
@@ -1148,21 +1150,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       acc += hdr[g].ncand;
     }
     s_total = acc;
-    s_nheavy = 0;
-    s_nlight = 0;
+    s_nwork = 0;
   }
   __syncthreads();
   const uint32_t total = s_total;
 
   // ---- phase A: candidate pairs, VHS acceptance ----
-  // Accepted pairs that involve a molecule (the long sampler chains) fill
-  // the work list from the front, atom-atom pairs from the back, so that
-  // waves of phase B hold work of similar length. One LDS atomic per wave
-  // and section.
+  // Accepted pairs are appended to a work list (one LDS atomic per wave)
+  // with a key that orders them by the sampler work they carry: the mode
+  // counts of p and of q. A counting sort by that key (largest first) then
+  // gives each wave of phase B pairs whose relaxations have the same shape.
   for (uint32_t j0 = 0; j0 < total; j0 += BLOCK) {
     const uint32_t j = j0 + tid;
-    bool acc = false, heavy = false;
-    uint32_t pj = 0, qj = 0;
+    bool acc = false;
+    uint32_t pj = 0, qj = 0, key = 0;
     if (j < total) {
       const uint32_t g = group_cell(hdr, ncell, j);
       const CellHdr &H = hdr[g];
@@ -1207,30 +1208,57 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           acc = ua < sg / H.sgmax;
         }
       }
-      heavy = (T.sp[a].n_modes | T.sp[b].n_modes) != 0;
+      const uint32_t na = T.sp[a].n_modes < 15 ? T.sp[a].n_modes : 15;
+      const uint32_t nb = T.sp[b].n_modes < 15 ? T.sp[b].n_modes : 15;
+      key = 255u - (na * 16u + nb);
     }
-    const unsigned long long mh = __ballot(acc && heavy), ml = __ballot(acc && !heavy);
-    uint32_t bh = 0, bl = 0;
-    if (lane == 0) {
-      if (mh) bh = atomicAdd(&s_nheavy, (uint32_t)__popcll(mh));
-      if (ml) bl = atomicAdd(&s_nlight, (uint32_t)__popcll(ml));
-    }
-    bh = __shfl(bh, 0);
-    bl = __shfl(bl, 0);
+    const unsigned long long ma = __ballot(acc);
+    uint32_t wb = 0;
+    if (lane == 0 && ma) wb = atomicAdd(&s_nwork, (uint32_t)__popcll(ma));
+    wb = __shfl(wb, 0);
     if (acc) {
-      const uint32_t slot = heavy ? bh + (uint32_t)__popcll(mh & lt) : wcap - 1 - (bl + (uint32_t)__popcll(ml & lt));
-      work[3 * slot] = j;
-      work[3 * slot + 1] = pj;
-      work[3 * slot + 2] = qj;
+      const uint32_t slot = wb + (uint32_t)__popcll(ma & lt);
+      work_in[4 * slot] = j;
+      work_in[4 * slot + 1] = pj;
+      work_in[4 * slot + 2] = qj;
+      work_in[4 * slot + 3] = key;
     }
   }
   __syncthreads();
 
-  // ---- phase B: one accepted pair per lane ----
-  const uint32_t nheavy = s_nheavy, nwork = s_nheavy + s_nlight;
+  // ---- counting sort of the work list by key ----
+  const uint32_t nwork = s_nwork;
+  for (uint32_t i = tid; i < 256; i += BLOCK) s_bin[i] = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < nwork; i += BLOCK) atomicAdd(&s_bin[work_in[4 * i + 3]], 1u);
+  __syncthreads();
+  if (tid < 64) {
+    // exclusive scan of the 256 bins, four per lane
+    const uint32_t b0 = s_bin[4 * lane], b1 = s_bin[4 * lane + 1], b2 = s_bin[4 * lane + 2], b3 = s_bin[4 * lane + 3];
+    const uint32_t sum = ((b0 + b1) + b2) + b3;
+    uint32_t inc = sum;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(inc, d);
+      if ((int)lane >= d) inc += o;
+    }
+    const uint32_t ex = inc - sum;
+    s_bin[4 * lane] = ex;
+    s_bin[4 * lane + 1] = ex + b0;
+    s_bin[4 * lane + 2] = ex + b0 + b1;
+    s_bin[4 * lane + 3] = ex + b0 + b1 + b2;
+  }
+  __syncthreads();
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
-    const uint32_t slot = i < nheavy ? i : wcap - 1 - (i - nheavy);
-    const uint32_t j = work[3 * slot], p = work[3 * slot + 1], qq = work[3 * slot + 2];
+    const uint32_t pos = atomicAdd(&s_bin[work_in[4 * i + 3]], 1u);
+    work[3 * pos] = work_in[4 * i];
+    work[3 * pos + 1] = work_in[4 * i + 1];
+    work[3 * pos + 2] = work_in[4 * i + 2];
+  }
+  __syncthreads();
+
+  // ---- phase B: one accepted pair per lane ----
+  for (uint32_t i = tid; i < nwork; i += BLOCK) {
+    const uint32_t j = work[3 * i], p = work[3 * i + 1], qq = work[3 * i + 2];
     const uint32_t g = group_cell(hdr, ncell, j);
     const CellHdr &H = hdr[g];
     const uint32_t k = j - H.cstart;

@@ -376,7 +376,7 @@ hcao_status build_groups(hcao_ctx *c) {
   HIP_TRY(c, c->grp.alloc(grp.size()));
   HIP_TRY(c, c->grp_work.alloc(gw.size()));
   if (c->work_entries != wsum) {
-    HIP_TRY(c, c->work.alloc(3 * wsum));
+    HIP_TRY(c, c->work.alloc(7 * wsum));  // (j, p, q, key) as found, then (j, p, q) sorted
     HIP_TRY(c, c->bflag.alloc(wsum));
     if (c->mixed) HIP_TRY(c, c->wdef.alloc(wsum));
     c->work_entries = wsum;

@@ -86,7 +86,8 @@ struct CellArrays {
 
 // Workgroup b processes the consecutive cells [grp[2b], grp[2b+1]); its work
 // list, product flags and pair energy defects are the entries
-// [grp_work[2b], grp_work[2b+1]) of work (three words each) / bflag / wdef
+// [grp_work[2b], grp_work[2b+1]) of work (seven words each: the pair as
+// found and as sorted) / bflag / wdef
 // (sum over its cells of cap/2 + 1 entries).
 struct StepArgs {
   const Tables *tab;

@@ -54,6 +54,7 @@ def lib():
         L.orc_detexp.argtypes = [d]; L.orc_detexp.restype = d
         L.orc_detpow.argtypes = [d, d]; L.orc_detpow.restype = d
         L.orc_feistel_index.argtypes = [u32, vp, u32]; L.orc_feistel_index.restype = u32
+        L.orc_gibbs_propose.argtypes = [u32, ctypes.c_double, ctypes.c_double]; L.orc_gibbs_propose.restype = u32
         L.orc_create.argtypes = [u64, u32, vp, vp, u32, P(vp)]
         L.orc_destroy.argtypes = [vp]; L.orc_destroy.restype = None
         L.orc_add_species.argtypes = [vp, d, d, d, d, u32, vp, u32, vp, vp, vp, vp, vp, d, d, ctypes.c_int]
@@ -131,6 +132,10 @@ def detpow(x, y):
 
 def gamma_q(a, x):
     return lib().orc_gamma_q(float(a), float(x))
+
+
+def gibbs_propose(top, c, u):
+    return lib().orc_gibbs_propose(int(top), float(c), float(u))
 
 
 def feistel_index(n, keys, i):

@@ -258,7 +258,8 @@ typedef struct {
   double zpe;
   double formation;
   double p_vib;
-  int sampler; /* resolved: JOINT or GIBBS */
+  int sampler;                 /* resolved: JOINT or GIBBS */
+  int concave[ORC_MAX_MODES]; /* level spacings never increase (bends, Morse stretches) */
 } species_t;
 
 typedef struct {
@@ -459,6 +460,14 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
   double z = 0.0;
   for (uint32_t m = 0; m < s->n_modes; ++m) z = z + mode_energy(s, m, 0);
   s->zpe = z;
+  /* concavity of the level sequence, which the Gibbs proposal relies on */
+  for (uint32_t m = 0; m < s->n_modes; ++m) {
+    int ok = 1;
+    if (m >= s->n_bend)
+      for (uint32_t i = 1; i < s->idiss[m]; ++i)
+        if (!((s->lev[m][i + 1] - s->lev[m][i]) <= (s->lev[m][i] - s->lev[m][i - 1]))) ok = 0;
+    s->concave[m] = ok;
+  }
   if (sampler == ORC_SAMPLER_AUTO)
     s->sampler = (s->n_modes <= 4) ? ORC_SAMPLER_JOINT : ORC_SAMPLER_GIBBS;
   else if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS)
@@ -962,6 +971,33 @@ static uint32_t propose(const species_t *s, uint32_t m, double e, double u) {
   return i;
 }
 
+/* Gibbs-sweep proposal for one mode (our sampler, reading A3): the target
+ * over levels 0..top is proportional to t_i = ((E_c - E_i) / den)^q with
+ * den = E_c - E_0. Since (1 - x)^q <= 1 - q x for q in (0, 1], and a
+ * concave level sequence has E_i - E_0 >= i (E_top - E_0) / top, t_i is
+ * bounded by the linear envelope w_i = 1 - c i, c = q (E_top - E_0) /
+ * (top den); the level is drawn from w_i and accepted with probability
+ * t_i / w_i. The draw inverts the discrete CDF: with K = i + 1 the CDF is
+ * G(K) = h K - (c/2) K^2, h = 1 + c/2, so i = floor(K*) with G(K*) = u G(top+1),
+ * K* = 2 s / (h + sqrt(h^2 - 2 c s)). c = 0 (top = 0, or levels that are not
+ * concave) is the uniform proposal floor(u (top + 1)). */
+static double gibbs_slope(const species_t *s, uint32_t m, uint32_t top, double den, double q) {
+  if (top == 0 || !s->concave[m]) return 0.0;
+  return (q * (mode_energy(s, m, top) - mode_energy(s, m, 0))) / ((double)top * den);
+}
+
+static uint32_t propose_linear(uint32_t top, double c, double u) {
+  double z = ((double)top + 1.0) * (1.0 - (0.5 * c) * (double)top);
+  double h = 1.0 + 0.5 * c;
+  double sv = u * z;
+  double k = (2.0 * sv) / (h + sqrt(h * h - (2.0 * c) * sv));
+  double fi = floor(k);
+  uint32_t i = fi > (double)top ? top : (uint32_t)fi;
+  return i;
+}
+
+uint32_t orc_gibbs_propose(uint32_t top, double c, double u) { return propose_linear(top, c, u); }
+
 /* Relaxes one molecule; *e_tr is the translational energy of the pair on
  * entry and on exit. Returns the number of trials. */
 static uint64_t relax(const orc_ctx *o, const species_t *s, uint16_t *lvl, double *e_tr, double q,
@@ -1004,14 +1040,16 @@ static uint64_t relax(const orc_ctx *o, const species_t *s, uint16_t *lvl, doubl
     double e0 = mode_energy(s, m, 0);
     double den = ec - e0;
     if (!(den > 0.0)) continue;
+    uint32_t top = mode_top(s, m, ec);
+    double c = gibbs_slope(s, m, top, den, q);
     for (;;) {
       trials += 1;
       double u = uniform(st);
-      uint32_t i = propose(s, m, ec, u);
+      uint32_t i = propose_linear(top, c, u);
       double ei = mode_energy(s, m, i);
       double ua = uniform(st);
       int accept = 0;
-      if (ei < ec) accept = ua < orc_detpow((ec - ei) / den, q);
+      if (ei < ec) accept = ua * (1.0 - c * (double)i) < orc_detpow((ec - ei) / den, q);
       if (accept) {
         lvl[m] = (uint16_t)i;
         et = ec - ei;

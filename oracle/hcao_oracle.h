@@ -48,6 +48,8 @@ double orc_detlog(double x);
 double orc_detexp(double x);
 double orc_detpow(double x, double y);
 uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[16], uint32_t i);
+/* Gibbs-sweep level proposal: weights 1 - c i on 0..top, by inversion of u */
+uint32_t orc_gibbs_propose(uint32_t top, double c, double u);
 
 /* ---- context ---- */
 int orc_create(uint64_t seed, uint32_t n_cells, const double *cell_volume, const double *cell_weight,

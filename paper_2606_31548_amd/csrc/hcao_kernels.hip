@@ -452,18 +452,44 @@ __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint3
     }
     return trials;
   }
+  // Gibbs sweep: the level of mode m is proposed from the linear envelope
+  // w_i = 1 - c i of the target ((E_c - E_i) / (E_c - E_0))^q on 0..top
+  // (valid for q <= 1 and levels whose spacings never grow; c = 0 gives the
+  // uniform proposal) by inverting its discrete CDF, and accepted with
+  // probability target / w_i.
   double et = e_tr;
   for (uint32_t m = 0; m < nm; ++m) {
     const double ec = et + mode_energy(S, C.T.lev, m, lv[m * stride]);
-    const double den = ec - mode_energy(S, C.T.lev, m, 0);
+    const double e0 = mode_energy(S, C.T.lev, m, 0);
+    const double den = ec - e0;
     if (!(den > 0.0)) continue;
     const uint32_t top = mode_top(S, C.T.lev, m, ec);
+    double c = 0.0;
+    if (top > 0 && ((S.concave >> m) & 1u))
+      c = (q * (mode_energy(S, C.T.lev, m, top) - e0)) / ((double)top * den);
+    const double z = ((double)top + 1.0) * (1.0 - (0.5 * c) * (double)top);
+    const double h = 1.0 + 0.5 * c;
+    const double hh = h * h, c2 = 2.0 * c;
     for (;;) {
       ++trials;
-      const uint32_t i = pick_level<MIX>(top, rng);
+      uint32_t i;
+      double w;
+      if constexpr (MIX) {
+        const float sv = rng.uniform_f() * (float)z;
+        const float k = (2.0f * sv) / ((float)h + sqrtf((float)hh - (float)c2 * sv));
+        const float fi = floorf(k);
+        i = fi > (float)top ? top : (uint32_t)fi;
+        w = (double)(1.0f - (float)c * (float)i);
+      } else {
+        const double sv = rng.uniform() * z;
+        const double k = (2.0 * sv) / (h + sqrt(hh - c2 * sv));
+        const double fi = floor(k);
+        i = fi > (double)top ? top : (uint32_t)fi;
+        w = 1.0 - c * (double)i;
+      }
       const double ei = mode_energy(S, C.T.lev, m, i);
       const double ua = (double)draw<MIX>(rng);
-      const bool ok = (ei < ec) && lb_accept<MIX>(ua, ec - ei, den, q);
+      const bool ok = (ei < ec) && lb_accept<MIX>(MIX ? (double)((float)ua * (float)w) : ua * w, ec - ei, den, q);
       if (ok) {
         lv[m * stride] = (uint16_t)i;
         et = ec - ei;

@@ -796,11 +796,20 @@ hcao_status hcao_finalize(hcao_ctx *c) {
       S.theta[b] = h.theta[b];
       S.kt[b] = kB * h.theta[b];
     }
+    // bends have equal spacings; a stretch qualifies when its spacings never
+    // grow (Morse levels), which the Gibbs proposal's envelope needs
+    S.concave = 0;
+    for (uint32_t b = 0; b < h.d.n_bend; ++b) S.concave |= 1u << b;
     for (uint32_t j = 0; j < h.d.n_stretch; ++j) {
       const uint32_t m = h.d.n_bend + j;
       S.lev_off[m] = (uint32_t)c->lev_host.size();
       S.idiss[m] = (uint32_t)h.levels[j].size() - 1;
       S.de[m] = h.de[j];
+      const std::vector<double> &L = h.levels[j];
+      bool spacing_shrinks = true;
+      for (size_t i = 1; i + 1 < L.size(); ++i)
+        if (!((L[i + 1] - L[i]) <= (L[i] - L[i - 1]))) spacing_shrinks = false;
+      if (spacing_shrinks) S.concave |= 1u << m;
       c->lev_host.insert(c->lev_host.end(), h.levels[j].begin(), h.levels[j].end());
     }
   }

@@ -24,7 +24,8 @@ constexpr uint32_t kErrNonFinite = 8u;
 
 struct SpeciesTab {
   double mass, zpe, formation, p_vib;
-  uint32_t n_modes, n_bend, sampler, pad;
+  uint32_t n_modes, n_bend, sampler;
+  uint32_t concave;             // bit m: the level spacings of mode m never increase
   double kt[kMaxModes];         // bends: k_B Theta
   double theta[kMaxModes];      // bends: Theta
   double de[kMaxModes];         // stretches: D_e

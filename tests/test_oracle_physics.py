@@ -262,6 +262,45 @@ def test_gibbs_sweep_matches_enumeration(orc):
     assert _chi2_states(samples, probs) > 1e-4
 
 
+@pytest.mark.parametrize("top,c", [(0, 0.0), (1, 0.5), (3, 0.0), (5, 0.12), (20, 0.03), (40, 0.76 / 40)])
+def test_gibbs_proposal_follows_linear_weights(orc, top, c):
+    """The Gibbs proposal draws level i with probability proportional to
+    1 - c i on 0..top: a fine midpoint grid of u reproduces the weights to
+    within one grid cell per level; c = 0 is floor(u (top + 1))."""
+    n = 200000
+    u = (np.arange(n) + 0.5) / n
+    lv = np.array([orc.gibbs_propose(top, c, x) for x in u])
+    assert lv.min() >= 0 and lv.max() <= top
+    w = 1.0 - c * np.arange(top + 1)
+    expect = n * w / w.sum()
+    got = np.bincount(lv, minlength=top + 1)
+    assert np.all(np.abs(got - expect) <= 1.0 + 1e-9 * n)
+    if c == 0.0:
+        assert np.array_equal(lv, np.minimum(np.floor(u * (top + 1)), top).astype(int))
+
+
+def test_gibbs_envelope_bounds_the_target(orc):
+    """For the concave level sequences of the workloads (bends, Morse
+    stretches) the linear envelope 1 - c i with c = q (E_top - E_0) /
+    (top (E_c - E_0)) bounds the target ((E_c - E_i) / (E_c - E_0))^q."""
+    q = 1.5 - 0.74
+    o = _build(orc, W.methane_species() + W.triatomic_species()[:2], seed=3)
+    for sp in range(o.n_species):
+        _, nm, _ = o.species_info(sp)
+        for m in range(nm):
+            lev = o.levels(sp, m, 400)
+            for ec in np.linspace(lev[0] * 1.01, lev[-1] * 1.5, 37):
+                below = np.flatnonzero(lev < ec)
+                top = int(below.max())
+                if top == 0:
+                    continue
+                den = ec - lev[0]
+                c = q * (lev[top] - lev[0]) / (top * den)
+                i = np.arange(top + 1)
+                t = ((ec - lev[:top + 1]) / den) ** q
+                assert np.all(t <= (1.0 - c * i) * (1 + 1e-12)), (sp, m, ec)
+
+
 # --------------------------------------------------------------------------
 # heat bath: Boltzmann populations
 # --------------------------------------------------------------------------

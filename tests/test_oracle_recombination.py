@@ -171,7 +171,7 @@ def test_reservoir_with_recombination_keeps_atoms(orc):
     """A dense CH4/CH3/H/H2 reservoir with all three reactions: carbon and
     hydrogen atoms are conserved, the count change equals births - deaths."""
     wl = W.methane_chemistry(n_cells=6, per_cell=256, recombination=True, t=6000.0)
-    wl.cell_weight = wl.cell_weight * 3e4  # n = 3e26 m^-3: frequent three-body events
+    wl.cell_weight = wl.cell_weight * 1e5  # n = 1e27 m^-3: frequent three-body events
     wl.dt = 5e-14
     o = orc.from_workload(wl)
     o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)

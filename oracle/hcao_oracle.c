@@ -1401,30 +1401,26 @@ static void store_pair(cell_t *C, uint32_t mm, uint32_t p, uint32_t q, const pai
 static double cell_temperature(const orc_ctx *o, const cell_t *C) {
   uint32_t n = C->n;
   if (n < 2) return 0.0;
-  double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (uint32_t b0 = 0; b0 < n; b0 += 64) {
-    double x[5][64];
-    for (int t = 0; t < 64; ++t) {
-      uint32_t i = b0 + (uint32_t)t;
-      if (i < n) {
-        double m = o->sp[C->sp[i]].mass;
-        double vx = C->vx[i], vy = C->vy[i], vz = C->vz[i];
-        x[0][t] = m;
-        x[1][t] = m * vx;
-        x[2][t] = m * vy;
-        x[3][t] = m * vz;
-        x[4][t] = m * ((vx * vx + vy * vy) + vz * vz);
-      } else {
-        for (int q = 0; q < 5; ++q) x[q][t] = 0.0;
-      }
+  /* 64 partial sums: sum t takes particles t, t + 64, t + 128, ... in slot
+   * order; then a halving tree (sum t adds sum t + s for s = 32, ..., 1) */
+  double x[5][64];
+  for (int t = 0; t < 64; ++t) {
+    for (int q = 0; q < 5; ++q) x[q][t] = 0.0;
+    for (uint32_t i = (uint32_t)t; i < n; i += 64) {
+      double m = o->sp[C->sp[i]].mass;
+      double vx = C->vx[i], vy = C->vy[i], vz = C->vz[i];
+      x[0][t] = x[0][t] + m;
+      x[1][t] = x[1][t] + m * vx;
+      x[2][t] = x[2][t] + m * vy;
+      x[3][t] = x[3][t] + m * vz;
+      x[4][t] = x[4][t] + m * ((vx * vx + vy * vy) + vz * vz);
     }
-    for (int sft = 32; sft >= 1; sft >>= 1)
-      for (int t = 0; t < sft; ++t)
-        for (int q = 0; q < 5; ++q) x[q][t] = x[q][t] + x[q][t + sft];
-    for (int q = 0; q < 5; ++q) tot[q] = tot[q] + x[q][0];
   }
-  double p2 = (tot[1] * tot[1] + tot[2] * tot[2]) + tot[3] * tot[3];
-  return (tot[4] - p2 / tot[0]) / (3.0 * K_BOLTZ * (double)n);
+  for (int sft = 32; sft >= 1; sft >>= 1)
+    for (int t = 0; t < sft; ++t)
+      for (int q = 0; q < 5; ++q) x[q][t] = x[q][t] + x[q][t + sft];
+  double p2 = (x[1][0] * x[1][0] + x[2][0] * x[2][0]) + x[3][0] * x[3][0];
+  return (x[4][0] - p2 / x[0][0]) / (3.0 * K_BOLTZ * (double)n);
 }
 
 static int step_cell(orc_ctx *o, uint32_t c, double dt) {

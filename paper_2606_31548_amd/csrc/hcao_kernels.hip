@@ -954,15 +954,15 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   return rx;
 }
 
-// Translational temperature of a cell by one wave: blocks of 64 particles in
-// slot order, each reduced by a halving tree (lane t takes lane t + s for
-// s = 32, ..., 1), block results added in order. The loads of four blocks
-// are issued together, so their latencies overlap.
+// Translational temperature of a cell by one wave: lane t sums particles
+// t, t + 64, t + 128, ... in slot order (loads of four blocks issued
+// together), then a halving tree (lane t takes lane t + s for s = 32, ...,
+// 1) combines the 64 partial sums.
 template <bool MIX>
 __device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint64_t base, uint32_t n, uint32_t lane) {
   if (n < 2) return 0.0;
   constexpr int U = 4;
-  double tot0 = 0.0, tot1 = 0.0, tot2 = 0.0, tot3 = 0.0, tot4 = 0.0;
+  double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
   for (uint32_t b0 = 0; b0 < n; b0 += 64 * U) {
     double m[U], vx[U], vy[U], vz[U];
 #pragma unroll
@@ -981,25 +981,24 @@ __device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint6
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (b0 + 64 * u >= n) break;
-      double x0 = m[u], x1 = m[u] * vx[u], x2 = m[u] * vy[u], x3 = m[u] * vz[u];
-      double x4 = m[u] * ((vx[u] * vx[u] + vy[u] * vy[u]) + vz[u] * vz[u]);
-      for (int s = 32; s >= 1; s >>= 1) {
-        x0 = x0 + __shfl_down(x0, s);
-        x1 = x1 + __shfl_down(x1, s);
-        x2 = x2 + __shfl_down(x2, s);
-        x3 = x3 + __shfl_down(x3, s);
-        x4 = x4 + __shfl_down(x4, s);
+      if (b0 + 64 * u + lane < n) {
+        x0 = x0 + m[u];
+        x1 = x1 + m[u] * vx[u];
+        x2 = x2 + m[u] * vy[u];
+        x3 = x3 + m[u] * vz[u];
+        x4 = x4 + m[u] * ((vx[u] * vx[u] + vy[u] * vy[u]) + vz[u] * vz[u]);
       }
-      tot0 = tot0 + x0;
-      tot1 = tot1 + x1;
-      tot2 = tot2 + x2;
-      tot3 = tot3 + x3;
-      tot4 = tot4 + x4;
     }
   }
-  const double p2 = (tot1 * tot1 + tot2 * tot2) + tot3 * tot3;
-  return (tot4 - p2 / tot0) / (3.0 * kBoltz * (double)n);
+  for (int s = 32; s >= 1; s >>= 1) {
+    x0 = x0 + __shfl_down(x0, s);
+    x1 = x1 + __shfl_down(x1, s);
+    x2 = x2 + __shfl_down(x2, s);
+    x3 = x3 + __shfl_down(x3, s);
+    x4 = x4 + __shfl_down(x4, s);
+  }
+  const double p2 = (x1 * x1 + x2 * x2) + x3 * x3;
+  return (x4 - p2 / x0) / (3.0 * kBoltz * (double)n);
 }
 
 // ---------------------------------------------------------------------------

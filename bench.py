@@ -279,7 +279,7 @@ def main():
         "dtype": "f32+f64" if forms[0] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "cells": wl.n_cells, "particles": int(wl.n_particles),
-                   "precision": forms[0], "sampler": "joint <= 4 modes, Gibbs sweep otherwise"},
+                   "precision": forms[0], "sampler": "joint for 2-4 modes, Gibbs sweep otherwise"},
         "particle_steps_per_s": head["particle_steps_per_s"],
         "energy_drift": head["energy_drift"],
         "roofline": head["roofline"],

@@ -136,7 +136,8 @@ typedef struct {
  *     molecule (0..1);
  *   sampler: JOINT = the joint proposal + acceptance as printed; GIBBS = one
  *     sweep of single-mode conditionals of the same target; AUTO = JOINT for
- *     at most 4 modes, GIBBS otherwise. */
+ *     2 to 4 modes, GIBBS otherwise (for one mode both have the same target,
+ *     and the sweep's proposal accepts more often). */
 typedef struct {
   double mass_kg, dref_m, omega, Tref_K;
   uint32_t n_bend;

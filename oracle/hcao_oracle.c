@@ -469,7 +469,7 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
     s->concave[m] = ok;
   }
   if (sampler == ORC_SAMPLER_AUTO)
-    s->sampler = (s->n_modes <= 4) ? ORC_SAMPLER_JOINT : ORC_SAMPLER_GIBBS;
+    s->sampler = (s->n_modes >= 2 && s->n_modes <= 4) ? ORC_SAMPLER_JOINT : ORC_SAMPLER_GIBBS;
   else if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS)
     s->sampler = sampler;
   else

@@ -711,7 +711,7 @@ hcao_status hcao_add_species(hcao_ctx *c, const hcao_species_desc *d, int32_t *i
   for (uint32_t m = 0; m < s.n_modes; ++m) z = z + host_mode_energy(s, m, 0);
   s.zpe = z;
   if (d->sampler == HCAO_SAMPLER_AUTO)
-    s.sampler = s.n_modes <= 4 ? HCAO_SAMPLER_JOINT : HCAO_SAMPLER_GIBBS;
+    s.sampler = (s.n_modes >= 2 && s.n_modes <= 4) ? HCAO_SAMPLER_JOINT : HCAO_SAMPLER_GIBBS;
   else if (d->sampler == HCAO_SAMPLER_JOINT || d->sampler == HCAO_SAMPLER_GIBBS)
     s.sampler = d->sampler;
   else

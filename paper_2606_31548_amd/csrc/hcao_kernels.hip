@@ -578,6 +578,8 @@ struct PairLocal {
   uint32_t sp_m;
   V3<R> v_m;
   double n_cell;
+  double et_out;     // translational energy handed to the scattering (relative motions)
+  double fold_used;  // mixed form: energy owed to the cell that joined this pair
   int32_t rec_i;  // recombination table node of the cell temperature (-1: below, -2: above)
   double rec_f;
 };
@@ -704,7 +706,11 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   const PairTab &PP = T.pair(sp0, sp1);
   double e_tr0 = PP.hm * g2;
   if constexpr (MIX) {
-    if (fold != 0.0 && e_tr0 + fold > 0.0) e_tr0 = e_tr0 + fold;
+    P.fold_used = 0.0;
+    if (fold != 0.0 && e_tr0 + fold > 0.0) {
+      e_tr0 = e_tr0 + fold;
+      P.fold_used = fold;
+    }
   }
   const double ev0 = vib_local(T, sp0, P.lv0, ls), ev1 = vib_local(T, sp1, P.lv1, ls);
   P.born = false;
@@ -909,6 +915,7 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     cm = com<MIX>(*t1, vbc, P.v_m);
   }
   V3<Rl> x1, y1;
+  P.et_out = et;
   split<MIX>(*t1, cm, e1, rng, x1, y1);
   if (kind == 0) {
     P.v0 = x1;
@@ -1326,28 +1333,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     unsigned long long *ctr = l_ctr + (size_t)g * nctr;
     atomicAdd(&ctr[HCAO_CTR_COLLISIONS], 1ull);
     Ctx C{T, ctr, scr, tid, BLOCK};
-    // mixed form: fp64 energy (kinetic, vibrational, formation) of the
-    // pair's particles before the collision
-    double e_in = 0.0, e_m_in = 0.0;
+    // mixed form: momentum of the pair (and of the third body) before the
+    // collision, in fp64 from the stored fp32 velocities
+    double mt = 0.0, px = 0.0, py = 0.0, pz = 0.0, mm3 = 0.0;
     if constexpr (MIX) {
-      const SpeciesTab &S0 = T.sp[P.sp0], &S1 = T.sp[P.sp1];
-      e_in = ((kinetic(S0.mass, P.v0) + vib_local(T, P.sp0, P.lv0, BLOCK)) + S0.formation) +
-             ((kinetic(S1.mass, P.v1) + vib_local(T, P.sp1, P.lv1, BLOCK)) + S1.formation);
-      if (P.has_m) e_m_in = kinetic(T.sp[P.sp_m].mass, P.v_m);
+      const double m0 = T.sp[P.sp0].mass, m1 = T.sp[P.sp1].mass;
+      mt = m0 + m1;
+      px = m0 * (double)P.v0.x + m1 * (double)P.v1.x;
+      py = m0 * (double)P.v0.y + m1 * (double)P.v1.y;
+      pz = m0 * (double)P.v0.z + m1 * (double)P.v1.z;
+      if (P.has_m) mm3 = T.sp[P.sp_m].mass;  // joins the sums only if the third body takes part
     }
+    const Vec3 vm_in = P.has_m ? Vec3{(double)P.v_m.x, (double)P.v_m.y, (double)P.v_m.z} : Vec3{0.0, 0.0, 0.0};
     collide<MIX>(C, P, g2, rng, A.rec, (MIX && k == 0) ? H.defect : 0.0);
     if constexpr (MIX) {
-      double e_out = 0.0;
-      if (!P.dead0)
-        e_out = e_out + ((kinetic(T.sp[P.sp0].mass, P.v0) + vib_local(T, P.sp0, P.lv0, BLOCK)) + T.sp[P.sp0].formation);
-      if (!P.dead1)
-        e_out = e_out + ((kinetic(T.sp[P.sp1].mass, P.v1) + vib_local(T, P.sp1, P.lv1, BLOCK)) + T.sp[P.sp1].formation);
-      if (P.born)
-        e_out = e_out + ((kinetic(T.sp[P.nb_sp].mass, P.nb_v) + vib_local(T, P.nb_sp, P.lvn, BLOCK)) +
-                         T.sp[P.nb_sp].formation);
-      double d = e_in - e_out;
-      if (P.m_moved) d = d + (e_m_in - kinetic(T.sp[P.sp_m].mass, P.v_m));
-      wdef[j] = d;
+      // Energy audit of the fp32 kinematics: the scattering intends the
+      // kinetic energy of the total centre-of-mass motion plus the
+      // translational energy handed to it (vibrational and formation energy
+      // are bookkept in fp64 and cancel); the defect is the intended minus
+      // the stored fp32 kinetic energy, less energy owed that joined here.
+      if (P.m_moved) {
+        mt = mt + mm3;
+        px = px + mm3 * vm_in.x;
+        py = py + mm3 * vm_in.y;
+        pz = pz + mm3 * vm_in.z;
+      }
+      const double ke_int = (0.5 * ((px * px + py * py) + pz * pz)) / mt + P.et_out;
+      double ke_out = 0.0;
+      if (!P.dead0) ke_out = ke_out + kinetic(T.sp[P.sp0].mass, P.v0);
+      if (!P.dead1) ke_out = ke_out + kinetic(T.sp[P.sp1].mass, P.v1);
+      if (P.born) ke_out = ke_out + kinetic(T.sp[P.nb_sp].mass, P.nb_v);
+      if (P.m_moved) ke_out = ke_out + kinetic(T.sp[P.sp_m].mass, P.v_m);
+      wdef[j] = (ke_int - ke_out) - P.fold_used;
     }
     stv<MIX>(A.st, gp, P.v0);
     stv<MIX>(A.st, gq, P.v1);

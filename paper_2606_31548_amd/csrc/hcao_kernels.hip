@@ -723,7 +723,8 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   double et = e_tr0;
 
   // --- recombination first: B + C (+M) -> A (+M) ---
-  for (uint32_t r = 0; r < T.nr && kind == 0; ++r) {
+  // (pairs that no reaction lists skip the decision; it would draw nothing)
+  for (uint32_t r = 0; PP.react && r < T.nr && kind == 0; ++r) {
     const ReactionTab &R = T.rx[r];
     if (R.kind != HCAO_RX_RECOMBINATION) continue;
     uint32_t sb;
@@ -768,7 +769,7 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   }
 
   // --- dissociation and exchange channels, competition by excess energy ---
-  if (kind == 0) {
+  if (kind == 0 && PP.react) {
     uint64_t steric_ok = 0;
     ChannelScan S;
     S.nch = 0;

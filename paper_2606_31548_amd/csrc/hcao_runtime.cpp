@@ -837,6 +837,21 @@ hcao_status hcao_finalize(hcao_ctx *c) {
       P.esg = 1.0 - w;
       P.q = 1.5 - w;
     }
+  // pairs some reaction can involve; the step skips the reaction decision for the others
+  for (uint32_t a = 0; a < T.n_species; ++a)
+    for (uint32_t b = 0; b < T.n_species; ++b) {
+      uint32_t react = 0;
+      for (const ReactionHost &h : c->reactions) {
+        const int32_t ra = h.d.reactant[0], rb = h.d.reactant[1];
+        if (h.d.kind == HCAO_RX_DISSOCIATION) {
+          if (ra == (int32_t)a || ra == (int32_t)b) react = 1;
+        } else if ((ra == (int32_t)a && rb == (int32_t)b) || (ra == (int32_t)b && rb == (int32_t)a)) {
+          react = 1;
+        }
+      }
+      T.pr[a][b].react = react;
+      T.pr[a][b].pad = 0;
+    }
   T.rec_nt = kRecNodes;
   T.rec_l0 = std::log(kRecTmin);
   T.rec_inv_step = (double)(kRecNodes - 1) / std::log(kRecTmax / kRecTmin);

@@ -35,6 +35,8 @@ struct SpeciesTab {
 
 struct PairTab {
   double mr, hm, m_a, m_b, msum, wa, wb, csg, esg, q;
+  uint32_t react;  // some reaction lists this pair (as A, or as A + B / B + C), in either order
+  uint32_t pad;
 };
 
 // Recombination B + C (+M) -> A (+M) is stored with a = B, b = C, c = A,

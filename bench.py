@@ -47,6 +47,13 @@ def algorithmic_bytes(wl_species, counts_by_species, n_cells, b_v=8):
 
 WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "triatomic")
 
+# Launch shape (workgroup size, slot target per workgroup) that the
+# library's autotuner (hcao_autotune) picks for each workload on MI355X;
+# fixed here so that a profiled run holds only the timed launches.
+# --autotune re-runs the autotuner instead.
+TUNED_SHAPE = {"chemistry-67m": (128, 2048), "chemistry-16m": (128, 2048), "methane-argon": (64, 1024),
+               "batched": (256, 4096), "triatomic": (64, 1024)}
+
 
 def make_workload(name):
     if name == "chemistry-67m":
@@ -101,6 +108,38 @@ def cpu_baseline(name, target_s=15.0):
                       f"steps, {dt:.1f} s, single thread"}
 
 
+def kernel_digest():
+    """Digest of the step kernel's sources: measured traffic is used only
+    while the kernel it was measured on is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hcao_kernels.hip", "hcao_tables.h"):
+        with open(os.path.join(ROOT, "paper_2606_31548_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, form, spl, shape):
+    """HBM bytes per k_step launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs recorded in profiles/k_step_traffic.txt (lines 'traffic key=value
+    ...'), or None when no record matches this kernel, workload, form and
+    launch shape."""
+    path = os.path.join(ROOT, "profiles", "k_step_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_digest()
+    with open(path) as fh:
+        for line in fh:
+            if not line.startswith("traffic "):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if (kv.get("digest") == digest and kv.get("workload") == workload and kv.get("form") == form
+                    and int(kv.get("steps_per_launch", -1)) == spl and int(kv.get("block", -1)) == shape["block"]
+                    and int(kv.get("group_slots", -1)) == shape["group_slots"]):
+                return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def _energy(sim, m, n_modes):
     """Kinetic + vibrational (zero point included) + formation energy of the
     particles [J] and the thermal part (kinetic + vibrational above the zero
@@ -113,7 +152,7 @@ def _energy(sim, m, n_modes):
     return e, th
 
 
-def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotune=False):
+def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotune=False, shape=None):
     """Times `steps` steps of one form after `warmup` untimed ones, every
     step-kernel launch advancing `spl` steps (so that every launch, warm-up
     included, has the same size); returns throughput, the step kernel's
@@ -122,11 +161,13 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
     stream = torch.cuda.Stream()
     sim = hcao.from_workload(wl, stream=hcao.ctypes.c_void_p(stream.cuda_stream), precision=precision)
     sim.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
-    shape = sim.launch_shape()  # defaults, or HCAO_BLOCK / HCAO_GROUP_SLOTS from the environment
-    sim.set_launch_shape(shape["block"], shape["group_slots"], spl)
-    shape = sim.autotune(wl.dt, trial_steps=min(spl, 5)) if autotune else sim.launch_shape()
+    if shape is None:
+        cur = sim.launch_shape()  # defaults, or HCAO_BLOCK / HCAO_GROUP_SLOTS from the environment
+        shape = (cur["block"], cur["group_slots"])
+    sim.set_launch_shape(shape[0], shape[1], spl)
     if autotune:
-        sim.set_launch_shape(shape["block"], shape["group_slots"], spl)
+        tuned = sim.autotune(wl.dt, trial_steps=min(spl, 5))
+        sim.set_launch_shape(tuned["block"], tuned["group_slots"], spl)
     n_modes = [sp.n_modes for sp in wl.species]
     m_init = sim.moments()
     e_init, th_init = _energy(sim, m_init, n_modes)
@@ -228,8 +269,11 @@ def main():
     ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"),
                     help="both: the mixed form is the headline value, the fp64 form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default (or HCAO_BLOCK / HCAO_GROUP_SLOTS) launch shape instead of autotuning it")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner before timing (default for the batched workload)")
+    ap.add_argument("--library-shape", action="store_true",
+                    help="use the library's default launch shape (or HCAO_BLOCK / HCAO_GROUP_SLOTS) instead of "
+                         "the tuned one")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this size (counter calibration)")
@@ -263,7 +307,9 @@ def main():
         print(f"# timing the {f} form: {warmup} warm-up + {steps} steps, {spl} per launch", file=sys.stderr,
               flush=True)
         res[f] = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, steps, warmup, spl,
-                         graph=batched, autotune=not args.no_autotune)
+                         graph=batched, autotune=args.autotune or batched,
+                         shape=None if args.library_shape else TUNED_SHAPE[args.workload])
+        res[f]["roofline"]["traffic"] = measured_traffic(args.workload, f, spl, res[f]["launch_shape"])
     head = res[forms[0]]
     out = {
         "metric": "HCAO collisions/s on 1 MI355X; mixed FP32/FP64 vs FP64 at fixed energy error",

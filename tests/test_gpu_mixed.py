@@ -102,6 +102,7 @@ def _observables(g):
         out[f"n{s}"] = float(m.n_species[s])
         if m.n_species[s] and g._n_modes[s]:
             out[f"Tvib{s}"] = m.T_vib_K[s]
+            out[f"Evib{s}"] = m.E_vib_J[s]
     for r, c in enumerate(g.reaction_counts()):
         out[f"rx{r}"] = float(c)
     return out

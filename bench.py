@@ -81,13 +81,25 @@ def make_workload(name):
     return wl, desc
 
 
-def cpu_baseline(name, target_s=15.0):
+SAMPLERS = {"auto": W.SAMPLER_AUTO, "joint": W.SAMPLER_JOINT, "gibbs": W.SAMPLER_GIBBS, "exact": W.SAMPLER_EXACT}
+SAMPLER_DESC = {"auto": "joint for 2-4 modes, Gibbs sweep otherwise", "joint": "joint proposal as printed",
+                "gibbs": "Gibbs sweep", "exact": "exact joint sampler (per-mode Boltzmann proposals)"}
+
+
+def set_sampler(wl, sampler):
+    for s in wl.species:
+        if s.n_modes:
+            s.sampler = SAMPLERS[sampler]
+
+
+def cpu_baseline(name, target_s=15.0, sampler="auto"):
     """The oracle as it stands (single thread) on a bounded sample of the
     same workload: a subset of the cells, stepped from the same kind of
     initial state, until about target_s seconds of CPU work are done."""
     import oracle
     oracle.build(force=False)
     wl, _ = make_workload(name)
+    set_sampler(wl, sampler)
     n_cells = min(wl.n_cells, 512)
     sub = W.Workload(wl.name, wl.species, wl.reactions, wl.counts[:n_cells].copy(), wl.t_trans[:n_cells].copy(),
                      wl.t_vib[:n_cells].copy(), wl.cell_volume[:n_cells].copy(), wl.cell_weight[:n_cells].copy(),
@@ -274,6 +286,8 @@ def main():
     ap.add_argument("--library-shape", action="store_true",
                     help="use the library's default launch shape (or HCAO_BLOCK / HCAO_GROUP_SLOTS) instead of "
                          "the tuned one")
+    ap.add_argument("--sampler", default="auto", choices=SAMPLERS,
+                    help="relaxation sampler of every molecular species")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this size (counter calibration)")
@@ -297,6 +311,7 @@ def main():
         return
 
     wl, desc = make_workload(args.workload)
+    set_sampler(wl, args.sampler)
     spl = max(1, args.steps_per_launch)
     steps = -(-args.steps // spl) * spl
     warmup = -(-args.warmup // spl) * spl
@@ -309,7 +324,8 @@ def main():
         res[f] = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, steps, warmup, spl,
                          graph=batched, autotune=args.autotune or batched,
                          shape=None if args.library_shape else TUNED_SHAPE[args.workload])
-        res[f]["roofline"]["traffic"] = measured_traffic(args.workload, f, spl, res[f]["launch_shape"])
+        res[f]["roofline"]["traffic"] = (measured_traffic(args.workload, f, spl, res[f]["launch_shape"])
+                                         if args.sampler == "auto" else None)
     head = res[forms[0]]
     out = {
         "metric": "HCAO collisions/s on 1 MI355X; mixed FP32/FP64 vs FP64 at fixed energy error",
@@ -325,7 +341,7 @@ def main():
         "dtype": "f32+f64" if forms[0] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "cells": wl.n_cells, "particles": int(wl.n_particles),
-                   "precision": forms[0], "sampler": "joint for 2-4 modes, Gibbs sweep otherwise"},
+                   "precision": forms[0], "sampler": SAMPLER_DESC[args.sampler]},
         "particle_steps_per_s": head["particle_steps_per_s"],
         "energy_drift": head["energy_drift"],
         "roofline": head["roofline"],
@@ -341,7 +357,7 @@ def main():
             out["batched_vs_sequential_fp64"] = res["fp64"]["collisions_per_s"] / seq["collisions_per_s"]
     if not args.no_cpu_baseline:
         print("# timing the oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds, args.sampler)
     print(json.dumps(out), flush=True)
 
 

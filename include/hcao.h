@@ -95,7 +95,12 @@ typedef enum {
  *     Results are reproducible and independent of launch shape, but not
  *     bit-identical to HCAO_FP64. */
 typedef enum { HCAO_FP64 = 0, HCAO_MIXED = 1 } hcao_precision;
-typedef enum { HCAO_SAMPLER_AUTO = 0, HCAO_SAMPLER_JOINT = 1, HCAO_SAMPLER_GIBBS = 2 } hcao_sampler;
+typedef enum {
+  HCAO_SAMPLER_AUTO = 0,
+  HCAO_SAMPLER_JOINT = 1,
+  HCAO_SAMPLER_GIBBS = 2,
+  HCAO_SAMPLER_EXACT = 3
+} hcao_sampler;
 typedef enum { HCAO_RX_DISSOCIATION = 0, HCAO_RX_EXCHANGE = 1, HCAO_RX_RECOMBINATION = 2 } hcao_rx_kind;
 
 /* Context configuration.
@@ -135,9 +140,13 @@ typedef struct {
  *   p_vib: probability that an accepted non-reactive collision relaxes the
  *     molecule (0..1);
  *   sampler: JOINT = the joint proposal + acceptance as printed; GIBBS = one
- *     sweep of single-mode conditionals of the same target; AUTO = JOINT for
- *     2 to 4 modes, GIBBS otherwise (for one mode both have the same target,
- *     and the sweep's proposal accepts more often). */
+ *     sweep of single-mode conditionals of the same target; EXACT = an
+ *     independent draw from the joint target (E_coll - sum E_m)^q like JOINT,
+ *     by rejection from per-mode Boltzmann proposals at one inverse
+ *     temperature, whose acceptance does not collapse with many modes
+ *     (about 3 trials for 9 modes); AUTO = JOINT for 2 to 4 modes, GIBBS
+ *     otherwise (for one mode both have the same target, and the sweep's
+ *     proposal accepts more often). */
 typedef struct {
   double mass_kg, dref_m, omega, Tref_K;
   uint32_t n_bend;
@@ -310,6 +319,14 @@ hcao_status hcao_get_pair(const hcao_ctx *ctx, uint32_t a, uint32_t b, double *o
  * temperature nodes log-spaced on [100, 5e4] K). */
 hcao_status hcao_get_recombination_table(const hcao_ctx *ctx, uint32_t reaction, double *out, uint32_t max_n,
                                          uint32_t *n_out);
+/* Inverse temperature [1/J] of the EXACT sampler's proposal for a molecule
+ * of `species` relaxing in a collision with `partner` (the pair's LB
+ * exponent q), at energy e_J > 0 above the molecule's zero point: the value
+ * the step kernel reads from its per-(species, q) table for that energy's
+ * bin, raised to q / e_J if below. HCAO_EINVAL if the species does not use
+ * the EXACT sampler, has no modes, or e_J is not positive. Host-side table
+ * read; no device work. */
+hcao_status hcao_get_exact_beta(const hcao_ctx *ctx, uint32_t species, uint32_t partner, double e_J, double *beta);
 
 /* Kernel timing over the stream: when enabled, each hcao_step call records
  * HIP events on the context's stream around its step-kernel launches;

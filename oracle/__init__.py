@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hcao_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-SAMPLER_AUTO, SAMPLER_JOINT, SAMPLER_GIBBS = 0, 1, 2
+SAMPLER_AUTO, SAMPLER_JOINT, SAMPLER_GIBBS, SAMPLER_EXACT = 0, 1, 2, 3
 RX_DISSOCIATION, RX_EXCHANGE, RX_RECOMBINATION = 0, 1, 2
 CTR_CANDIDATES, CTR_COLLISIONS, CTR_TRIALS, CTR_RELAX, CTR_CAPPED, CTR_SUPPRESSED, CTR_BIRTHS, CTR_DEATHS = range(8)
 CTR_REACTION0 = 8
@@ -55,6 +55,7 @@ def lib():
         L.orc_detpow.argtypes = [d, d]; L.orc_detpow.restype = d
         L.orc_feistel_index.argtypes = [u32, vp, u32]; L.orc_feistel_index.restype = u32
         L.orc_gibbs_propose.argtypes = [u32, ctypes.c_double, ctypes.c_double]; L.orc_gibbs_propose.restype = u32
+        L.orc_exact_beta.argtypes = [vp, u32, d, d]; L.orc_exact_beta.restype = d
         L.orc_create.argtypes = [u64, u32, vp, vp, u32, P(vp)]
         L.orc_destroy.argtypes = [vp]; L.orc_destroy.restype = None
         L.orc_add_species.argtypes = [vp, d, d, d, d, u32, vp, u32, vp, vp, vp, vp, vp, d, d, ctypes.c_int]
@@ -289,6 +290,9 @@ class Oracle:
         t = ctypes.c_double()
         _chk("orc_tvib", lib().orc_tvib(self._h, species, float(mean_evib_above_ground), ctypes.byref(t)))
         return t.value
+
+    def exact_beta(self, species, q, ep):
+        return lib().orc_exact_beta(self._h, int(species), float(q), float(ep))
 
     def relax_batch(self, species, q, sampler, e_tr, lvl_in):
         e_tr = np.ascontiguousarray(e_tr, np.float64)

@@ -258,7 +258,7 @@ typedef struct {
   double zpe;
   double formation;
   double p_vib;
-  int sampler;                 /* resolved: JOINT or GIBBS */
+  int sampler;                 /* resolved: JOINT, GIBBS or EXACT */
   int concave[ORC_MAX_MODES]; /* level spacings never increase (bends, Morse stretches) */
 } species_t;
 
@@ -470,7 +470,7 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
   }
   if (sampler == ORC_SAMPLER_AUTO)
     s->sampler = (s->n_modes >= 2 && s->n_modes <= 4) ? ORC_SAMPLER_JOINT : ORC_SAMPLER_GIBBS;
-  else if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS)
+  else if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS || sampler == ORC_SAMPLER_EXACT)
     s->sampler = sampler;
   else
     return E_INVAL;
@@ -998,12 +998,166 @@ static uint32_t propose_linear(uint32_t top, double c, double u) {
 
 uint32_t orc_gibbs_propose(uint32_t top, double c, double u) { return propose_linear(top, c, u); }
 
+/* Exact sampler of the joint target (our design, reading A3): the target of
+ * the joint proposal, P(i) proportional to (E' - S(i))^q over S(i) < E' with
+ * e_m(i) = E_m(i) - E_m(0), S = sum_m e_m(i_m) and E' = E_coll - ZPE, drawn by
+ * rejection from a product of per-mode Boltzmann distributions at one inverse
+ * temperature beta. With the proposal weight exp(-beta S), target / proposal
+ * is (E' - S)^q exp(beta S); over S in [0, E') it peaks at S = E' - q / beta
+ * (beta E' >= q), so the acceptance probability is
+ * (y e^(1 - y))^q = exp(q (ln y + 1 - y)) with y = beta (E' - S) / q.
+ * Any beta gives the target exactly; it sets only the acceptance rate, which
+ * is highest where the proposal's mean energy plus q / beta equals E'.
+ *
+ * beta is looked up by E': the bin b = (bit pattern of E') >> 48 (1/16 of an
+ * octave), clamped to [2^-90, 2^-49) J, holds beta_j of the grid
+ * beta_j = (1 + (j mod 16) / 16) 2^(40 + j div 16), j in [0, 960): the smallest
+ * j, by bisection, with G(beta_j) + q / beta_j <= E'_b, where E'_b is the
+ * bin's midpoint and G the proposal's mean energy over the modes' full level
+ * sets (bends: k Theta / expm1(beta k Theta); stretches: the Boltzmann mean of
+ * e_i over 0..i_diss, i ascending). beta is raised to q / E' if below. */
+#define EXACT_BIN_LO 14928u  /* bits(2^-90) >> 48 */
+#define EXACT_BIN_HI 15583u  /* last bin below 2^-49 */
+#define EXACT_NBETA 960u
+
+static double exact_beta_grid(uint32_t j) { return ldexp(1.0 + (double)(j & 15u) / 16.0, (int)(j >> 4) + 40); }
+
+static double exact_mean_energy(const species_t *s, double beta) {
+  double g = 0.0;
+  for (uint32_t m = 0; m < s->n_modes; ++m) {
+    if (m < s->n_bend) {
+      g = g + s->kt[m] / expm1(beta * s->kt[m]);
+    } else {
+      double num = 0.0, den = 0.0;
+      for (uint32_t i = 0; i <= s->idiss[m]; ++i) {
+        double e = s->lev[m][i] - s->lev[m][0];
+        double w = exp(-(beta * e));
+        num = num + e * w;
+        den = den + w;
+      }
+      g = g + num / den;
+    }
+  }
+  return g;
+}
+
+static uint32_t exact_bin(double ep) {
+  uint64_t b;
+  memcpy(&b, &ep, 8);
+  uint32_t k = (uint32_t)(b >> 48);
+  if (k < EXACT_BIN_LO) k = EXACT_BIN_LO;
+  if (k > EXACT_BIN_HI) k = EXACT_BIN_HI;
+  return k;
+}
+
+static double exact_bin_beta(const species_t *s, double q, uint32_t bin) {
+  double ec = from_bits(((uint64_t)bin << 48) | ((uint64_t)1 << 47));
+  uint32_t lo = 0, hi = EXACT_NBETA - 1;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    double bm = exact_beta_grid(mid);
+    if (exact_mean_energy(s, bm) + q / bm <= ec)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return exact_beta_grid(lo);
+}
+
+double orc_exact_beta(orc_ctx *o, uint32_t species, double q, double ep) {
+  if (!o || species >= o->n_species || !(ep > 0.0)) return -1.0;
+  double beta = exact_bin_beta(&o->sp[species], q, exact_bin(ep));
+  if (beta * ep < q) beta = q / ep;
+  return beta;
+}
+
+/* slope of the geometric proposal of mode m on 0..top: k Theta for bends;
+ * for stretches the chord e(top) / top (a lower bound of e(i) / i when the
+ * spacings never grow), else the minimum of e(i) / i */
+static double exact_slope(const species_t *s, uint32_t m, uint32_t top) {
+  if (m < s->n_bend) return s->kt[m];
+  double e0 = s->lev[m][0];
+  if (s->concave[m]) return (s->lev[m][top] - e0) / (double)top;
+  double sl = s->lev[m][1] - e0;
+  for (uint32_t i = 2; i <= top; ++i) {
+    double v = (s->lev[m][i] - e0) / (double)i;
+    if (v < sl) sl = v;
+  }
+  return sl;
+}
+
+static uint64_t relax_exact(const species_t *s, uint16_t *lvl, double *e_tr, double q, stream *st,
+                            int *capped) {
+  double e_coll = *e_tr + vib_energy(s, lvl);
+  double ep = e_coll - s->zpe;
+  if (!(ep > 0.0)) return 0;
+  double beta = exact_bin_beta(s, q, exact_bin(ep));
+  if (beta * ep < q) beta = q / ep;
+  uint32_t top[ORC_MAX_MODES];
+  double c[ORC_MAX_MODES], sl[ORC_MAX_MODES];
+  for (uint32_t m = 0; m < s->n_modes; ++m) {
+    top[m] = mode_top(s, m, ep + mode_energy(s, m, 0));
+    sl[m] = top[m] > 0 ? exact_slope(s, m, top[m]) : 0.0;
+    c[m] = beta * sl[m];
+  }
+  uint64_t trials = 0;
+  uint16_t cand[ORC_MAX_MODES];
+  for (;;) {
+    double sum = 0.0;
+    for (uint32_t m = 0; m < s->n_modes && !*capped; ++m) {
+      cand[m] = 0;
+      if (top[m] == 0) continue;
+      for (;;) {
+        trials += 1;
+        if (trials >= ORC_MAX_TRIALS) {
+          *capped = 1;
+          break;
+        }
+        double u = uniform(st);
+        double x = -orc_detlog(1.0 - u) / c[m];
+        if (!(x < (double)top[m] + 1.0)) continue; /* beyond the top level: redraw */
+        uint32_t i = (uint32_t)floor(x);
+        if (m >= s->n_bend && i > 0) {
+          /* stretch: keep with probability exp(-beta (e(i) - slope i)) */
+          double d = (mode_energy(s, m, i) - mode_energy(s, m, 0)) - sl[m] * (double)i;
+          if (d > 0.0) {
+            double u2 = uniform(st);
+            if (!(u2 < orc_detexp(-(beta * d)))) continue;
+          }
+        }
+        cand[m] = (uint16_t)i;
+        break;
+      }
+    }
+    if (*capped) break;
+    trials += 1;
+    for (uint32_t m = 0; m < s->n_modes; ++m) sum = sum + (mode_energy(s, m, cand[m]) - mode_energy(s, m, 0));
+    if (sum < ep) {
+      double y = (beta * (ep - sum)) / q;
+      double ua = uniform(st);
+      if (ua < orc_detexp(q * ((orc_detlog(y) + 1.0) - y))) {
+        for (uint32_t m = 0; m < s->n_modes; ++m) lvl[m] = cand[m];
+        double ev = 0.0;
+        for (uint32_t m = 0; m < s->n_modes; ++m) ev = ev + mode_energy(s, m, cand[m]);
+        *e_tr = e_coll - ev;
+        break;
+      }
+    }
+    if (trials >= ORC_MAX_TRIALS) {
+      *capped = 1;
+      break;
+    }
+  }
+  return trials;
+}
+
 /* Relaxes one molecule; *e_tr is the translational energy of the pair on
  * entry and on exit. Returns the number of trials. */
 static uint64_t relax(const orc_ctx *o, const species_t *s, uint16_t *lvl, double *e_tr, double q,
                       stream *st, int *capped) {
   uint64_t trials = 0;
   *capped = 0;
+  if (s->sampler == ORC_SAMPLER_EXACT) return relax_exact(s, lvl, e_tr, q, st, capped);
   if (s->sampler == ORC_SAMPLER_JOINT) {
     double e_coll = *e_tr + vib_energy(s, lvl);
     double denom = e_coll - s->zpe;
@@ -1677,7 +1831,7 @@ int orc_relax_batch(orc_ctx *o, uint32_t species, double q, int sampler, uint32_
                     const uint16_t *lvl_in, uint16_t *lvl_out, double *e_tr_out, uint64_t *trials) {
   if (!o || !o->finalized || species >= o->n_species) return E_INVAL;
   species_t s = o->sp[species];
-  if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS) s.sampler = sampler;
+  if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS || sampler == ORC_SAMPLER_EXACT) s.sampler = sampler;
   uint32_t nm = s.n_modes;
   for (uint32_t i = 0; i < n; ++i) {
     stream st;
@@ -1703,7 +1857,7 @@ int orc_relax_chain(orc_ctx *o, uint32_t species, double q, int sampler, uint32_
                     const double *e_tr, uint16_t *lvl_state, uint64_t *hist, uint32_t hist_stride) {
   if (!o || !o->finalized || species >= o->n_species) return E_INVAL;
   species_t s = o->sp[species];
-  if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS) s.sampler = sampler;
+  if (sampler == ORC_SAMPLER_JOINT || sampler == ORC_SAMPLER_GIBBS || sampler == ORC_SAMPLER_EXACT) s.sampler = sampler;
   for (uint32_t i = 0; i < n_iter; ++i) {
     stream st;
     stream_open(&st, o->seed, i, 0xFFFFFFF1u, chain);

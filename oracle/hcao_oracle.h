@@ -37,7 +37,7 @@ enum {
   ORC_N_CTR = 8 + ORC_MAX_REACTIONS
 };
 
-enum { ORC_SAMPLER_AUTO = 0, ORC_SAMPLER_JOINT = 1, ORC_SAMPLER_GIBBS = 2 };
+enum { ORC_SAMPLER_AUTO = 0, ORC_SAMPLER_JOINT = 1, ORC_SAMPLER_GIBBS = 2, ORC_SAMPLER_EXACT = 3 };
 enum { ORC_RX_DISSOCIATION = 0, ORC_RX_EXCHANGE = 1, ORC_RX_RECOMBINATION = 2 };
 
 typedef struct orc_ctx orc_ctx;
@@ -50,6 +50,10 @@ double orc_detpow(double x, double y);
 uint32_t orc_feistel_index(uint32_t n, const uint32_t keys[16], uint32_t i);
 /* Gibbs-sweep level proposal: weights 1 - c i on 0..top, by inversion of u */
 uint32_t orc_gibbs_propose(uint32_t top, double c, double u);
+/* inverse temperature of the exact sampler's proposal for a molecule of the
+ * given species with LB exponent q and energy E' above its zero point
+ * (-1 on invalid input) */
+double orc_exact_beta(orc_ctx *o, uint32_t species, double q, double ep);
 
 /* ---- context ---- */
 int orc_create(uint64_t seed, uint32_t n_cells, const double *cell_volume, const double *cell_weight,

@@ -360,6 +360,7 @@ struct Tab {
   const PairTab *pr;  // [a * ns + b]
   const ReactionTab *rx;
   const double *lev;
+  const double *beta;  // exact sampler's beta tables (global memory)
   uint32_t ns, nr, mm, rec_nt;
   __device__ __forceinline__ const PairTab &pair(uint32_t a, uint32_t b) const { return pr[a * ns + b]; }
 };
@@ -415,14 +416,164 @@ __device__ __forceinline__ uint32_t pick_level(uint32_t top, RngT<MIX> &rng) {
   return i > top ? top : i;
 }
 
-// Larsen-Borgnakke relaxation of one molecule (levels at lv[m * stride]);
-// e_tr is the pair's translational energy on entry and exit.
+// u < exp(-a) for a >= 0, decided as the fp64 dexp decides (fp32 filter)
+__device__ __forceinline__ bool below_exp_neg(double u, double a) {
+  const double est = (double)__builtin_amdgcn_exp2f(-(float)a * 1.44269504f);
+  if (u < est * (1.0 - kFilter)) return true;
+  if (u > est * (1.0 + kFilter)) return false;
+  return u < dexp(-a);
+}
+
+// Exact sampler, level proposal of one mode: the geometric level
+// floor(-ln(1 - u) / c) with c = beta * slope. Returns false when it lies
+// above top (the caller draws again). The fp64 form decides floor() as the
+// fp64 expression -dlog(1 - u) / c does: an fp32 estimate far enough from
+// an integer settles it, else the fp64 expression is evaluated.
 template <bool MIX>
+__device__ __forceinline__ bool geometric_level(RngT<MIX> &rng, double c, uint32_t top, uint32_t &i) {
+  const float ftop1 = (float)top + 1.0f;
+  if constexpr (MIX) {
+    const float u = rng.uniform_f();
+    const float x = -__builtin_amdgcn_logf(1.0f - u) * (0.69314718f / (float)c);
+    if (!(x < ftop1)) return false;
+    i = (uint32_t)floorf(x);
+    return true;
+  } else {
+    const double u = rng.uniform();
+    const double v = 1.0 - u;
+    const float k = (float)(0.6931471805599453 / c);
+    const float xe = -__builtin_amdgcn_logf((float)v) * k;
+    const float band = 1e-5f * (xe + 1.0f) + 1e-6f * k;
+    if (xe >= ftop1 + band) return false;
+    const float fl = floorf(xe);
+    if (xe - fl > band && (fl + 1.0f) - xe > band) {
+      i = (uint32_t)fl;
+      return true;
+    }
+    const double x = -dlog(v) / c;
+    if (!(x < (double)top + 1.0)) return false;
+    i = (uint32_t)floor(x);
+    return true;
+  }
+}
+
+// Exact sampler, slope of the geometric proposal of mode m on 0..top: the
+// harmonic spacing of a bend; for a stretch the chord (E_top - E_0) / top,
+// a lower bound of (E_i - E_0) / i when the spacings never grow, else the
+// smallest (E_i - E_0) / i
+__device__ __forceinline__ double exact_slope(const SpeciesTab &S, const double *lev, uint32_t m, uint32_t top) {
+  if (m < S.n_bend) return S.kt[m];
+  const double *L = lev + S.lev_off[m];
+  if ((S.concave >> m) & 1u) return (L[top] - L[0]) / (double)top;
+  double sl = L[1] - L[0];
+  for (uint32_t i = 2; i <= top; ++i) {
+    const double v = (L[i] - L[0]) / (double)i;
+    if (v < sl) sl = v;
+  }
+  return sl;
+}
+
+// Larsen-Borgnakke relaxation of one molecule (levels at lv[m * stride]);
+// e_tr is the pair's translational energy on entry and exit; btab is the
+// molecule's beta table (exact sampler only). The exact sampler is compiled
+// only into the instantiations with EX set, which run when some species
+// uses it, so that it does not weigh on the register allocation of the
+// others.
+template <bool MIX, bool EX>
 __device__ uint32_t relax(const Ctx &C, const SpeciesTab &S, uint16_t *lv, uint32_t stride, double &e_tr,
-                          double q, RngT<MIX> &rng, bool &capped) {
+                          double q, const double *btab, RngT<MIX> &rng, bool &capped) {
   uint32_t trials = 0;
   capped = false;
   const uint32_t nm = S.n_modes;
+  if (EX && S.sampler == HCAO_SAMPLER_EXACT) {
+    // Independent draw from the joint target (E' - S)^q on S < E' (S: sum of
+    // the modes' energies above their ground levels, E' = E_coll - ZPE) by
+    // rejection from per-mode Boltzmann proposals at inverse temperature
+    // beta: bends geometric, stretches geometric on the chord slope thinned
+    // by exp(-beta (E_i - E_0 - slope i)); target / proposal over its
+    // maximum is exp(q (ln y + 1 - y)), y = beta (E' - S) / q.
+    const double e_coll = e_tr + vib_energy(S, C.T.lev, lv, stride);
+    const double ep = e_coll - S.zpe;
+    if (!(ep > 0.0)) return 0;
+    uint32_t bin = (uint32_t)((unsigned long long)__double_as_longlong(ep) >> 48);
+    bin = bin < kExactBinLo ? kExactBinLo : (bin > kExactBinHi ? kExactBinHi : bin);
+    double beta = btab[bin - kExactBinLo];
+    if (beta * ep < q) beta = q / ep;
+    uint16_t *tops = C.scr + C.lane;
+    uint16_t *cand = C.scr + (size_t)nm * C.block + C.lane;
+    for (uint32_t m = 0; m < nm; ++m)
+      tops[m * C.block] = (uint16_t)mode_top(S, C.T.lev, m, ep + mode_energy(S, C.T.lev, m, 0));
+    for (;;) {
+      double sum = 0.0;
+      for (uint32_t m = 0; m < nm && !capped; ++m) {
+        const uint32_t top = tops[m * C.block];
+        uint32_t i = 0;
+        if (top > 0) {
+          const double sl = exact_slope(S, C.T.lev, m, top);
+          const double c = beta * sl;
+          for (;;) {
+            ++trials;
+            if (trials >= kMaxTrials) {
+              capped = true;
+              break;
+            }
+            if (!geometric_level<MIX>(rng, c, top, i)) continue;
+            if (m >= S.n_bend && i > 0) {
+              const double d = (mode_energy(S, C.T.lev, m, i) - mode_energy(S, C.T.lev, m, 0)) - sl * (double)i;
+              if (d > 0.0) {
+                bool keep;
+                if constexpr (MIX)
+                  keep = rng.uniform_f() < __builtin_amdgcn_exp2f(-(float)(beta * d) * 1.44269504f);
+                else
+                  keep = below_exp_neg(rng.uniform(), beta * d);
+                if (!keep) continue;
+              }
+            }
+            break;
+          }
+        }
+        cand[m * C.block] = (uint16_t)i;
+        sum = sum + (mode_energy(S, C.T.lev, m, i) - mode_energy(S, C.T.lev, m, 0));
+      }
+      if (capped) break;
+      ++trials;
+      if (sum < ep) {
+        const double y = (beta * (ep - sum)) / q;
+        bool ok;
+        if constexpr (MIX) {
+          const float yf = (float)y, qf = (float)q;
+          const float ex = qf * ((__builtin_amdgcn_logf(yf) * 0.69314718f + 1.0f) - yf);
+          ok = rng.uniform_f() < __builtin_amdgcn_exp2f(ex * 1.44269504f);
+        } else {
+          const double ua = rng.uniform();
+          const float yf = (float)y, qf = (float)q;
+          const float ex = qf * ((__builtin_amdgcn_logf(yf) * 0.69314718f + 1.0f) - yf);
+          const double est = (double)__builtin_amdgcn_exp2f(ex * 1.44269504f);
+          if (ua < est * (1.0 - kFilter))
+            ok = true;
+          else if (ua > est * (1.0 + kFilter))
+            ok = false;
+          else
+            ok = ua < dexp(q * ((dlog(y) + 1.0) - y));
+        }
+        if (ok) {
+          double ev = 0.0;
+          for (uint32_t m = 0; m < nm; ++m) {
+            const uint16_t l = cand[m * C.block];
+            lv[m * stride] = l;
+            ev = ev + mode_energy(S, C.T.lev, m, l);
+          }
+          e_tr = e_coll - ev;
+          break;
+        }
+      }
+      if (trials >= kMaxTrials) {
+        capped = true;
+        break;
+      }
+    }
+    return trials;
+  }
   if (S.sampler == HCAO_SAMPLER_JOINT) {
     const double e_coll = e_tr + vib_energy(S, C.T.lev, lv, stride);
     const double denom = e_coll - S.zpe;
@@ -695,7 +846,7 @@ __device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32
 // fp64. In the mixed form, fold is energy owed to the cell's particles by
 // earlier rounding; it joins this pair's translational energy when the sum
 // stays positive.
-template <bool MIX>
+template <bool MIX, bool EX>
 __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rng, const double *rec,
                        double fold) {
   using Rl = Real<MIX>;
@@ -802,6 +953,7 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   uint16_t *lvj0 = nullptr, *lvj1 = nullptr;
   uint32_t spj0 = 0, spj1 = 0;
   double qj0 = 0.0, qj1 = 0.0;
+  uint32_t bj0 = 0, bj1 = 0;  // beta table offsets (exact sampler)
   bool pv = false;
   uint32_t njob = 0;
   const ReactionTab &RX = T.rx[rx < 0 ? 0 : rx];
@@ -810,14 +962,17 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   uint32_t ja_sp = 0, jb_sp = 0;  // candidate jobs a and b
   uint16_t *ja_lv = nullptr, *jb_lv = nullptr;
   double ja_q = 0.0, jb_q = 0.0;
+  uint32_t ja_b = 0, jb_b = 0;
   if (kind == 0) {
     pv = true;
     ja_sp = sp0;
     ja_lv = P.lv0;
     ja_q = PP.q;
+    ja_b = PP.beta_off;
     jb_sp = sp1;
     jb_lv = P.lv1;
     jb_q = PP.q;
+    jb_b = T.pair(sp1, sp0).beta_off;
   } else if (kind == 1) {
     // A + M -> B + C + M: B takes A's slot, C is new, both from the ground state
     const uint32_t spM = side ? sp0 : sp1;
@@ -826,9 +981,11 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     ja_sp = (uint32_t)RX.c;
     ja_lv = la;
     ja_q = T.pair(RX.c, spM).q;
+    ja_b = T.pair(RX.c, spM).beta_off;
     jb_sp = (uint32_t)RX.d;
     jb_lv = P.lvn;
     jb_q = T.pair(RX.d, spM).q;
+    jb_b = T.pair(RX.d, spM).beta_off;
   } else if (kind == 2) {
     // A + B -> C + D: C takes A's slot, D takes B's
     zero_levels(la, ls, mm);
@@ -837,20 +994,24 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     ja_sp = (uint32_t)RX.c;
     ja_lv = la;
     ja_q = qcd;
+    ja_b = T.pair(RX.c, RX.d).beta_off;
     jb_sp = (uint32_t)RX.d;
     jb_lv = lb;
     jb_q = qcd;
+    jb_b = T.pair(RX.d, RX.c).beta_off;
   } else {
     // B + C (+M) -> A (+M): A takes B's slot
     zero_levels(la, ls, mm);
     ja_sp = (uint32_t)RX.c;
     ja_lv = la;
     ja_q = T.pair(RX.c, P.sp_m).q;
+    ja_b = T.pair(RX.c, P.sp_m).beta_off;
   }
   if (T.sp[ja_sp].n_modes > 0) {
     lvj0 = ja_lv;
     spj0 = ja_sp;
     qj0 = ja_q;
+    bj0 = ja_b;
     ++njob;
   }
   if (kind != 3 && T.sp[jb_sp].n_modes > 0) {
@@ -858,10 +1019,12 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
       lvj0 = jb_lv;
       spj0 = jb_sp;
       qj0 = jb_q;
+      bj0 = jb_b;
     } else {
       lvj1 = jb_lv;
       spj1 = jb_sp;
       qj1 = jb_q;
+      bj1 = jb_b;
     }
     ++njob;
   }
@@ -875,7 +1038,8 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
       ++nrel;
     }
     bool capped = false;
-    tr += relax<MIX>(C, S, j ? lvj1 : lvj0, ls, et, j ? qj1 : qj0, rng, capped);
+    const uint32_t bo = j ? bj1 : bj0;
+    tr += relax<MIX, EX>(C, S, j ? lvj1 : lvj0, ls, et, j ? qj1 : qj0, C.T.beta + (bo == 0xFFFFFFFFu ? 0u : bo), rng, capped);
     ncap += capped ? 1u : 0u;
   }
   if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
@@ -1055,7 +1219,7 @@ __device__ __forceinline__ uint32_t group_cell(const CellHdr *hdr, uint32_t ncel
 // (the audit of its particles before and after); the cell's sum, reduced in
 // pair order, is owed to the cell and joins the translational energy of the
 // cell's pair 0 in the next step in which that pair collides.
-template <int BLOCK, bool MIX>
+template <int BLOCK, bool MIX, bool EX>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs A) {
   using R = Real<MIX>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -1115,7 +1279,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     H.weight = A.cells.weight[c];
     H.defect = MIX ? A.cells.defect[c] : 0.0;
   }
-  const Tab T{l_sp, l_pr, l_rx, l_lev, ns, nr, mm, GT->rec_nt};
+  const Tab T{l_sp, l_pr, l_rx, l_lev, A.beta, ns, nr, mm, GT->rec_nt};
   const uint32_t wcap = (uint32_t)(A.grp_work[2 * blockIdx.x + 1] - wbase);
   uint32_t *work_in = A.work + 7 * wbase;           // accepted pairs as found: (j, p, q, key)
   uint32_t *work = work_in + 4 * (size_t)wcap;      // the same sorted by key: (j, p, q)
@@ -1346,7 +1510,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (P.has_m) mm3 = T.sp[P.sp_m].mass;  // joins the sums only if the third body takes part
     }
     const Vec3 vm_in = P.has_m ? Vec3{(double)P.v_m.x, (double)P.v_m.y, (double)P.v_m.z} : Vec3{0.0, 0.0, 0.0};
-    collide<MIX>(C, P, g2, rng, A.rec, (MIX && k == 0) ? H.defect : 0.0);
+    collide<MIX, EX>(C, P, g2, rng, A.rec, (MIX && k == 0) ? H.defect : 0.0);
     if constexpr (MIX) {
       // Energy audit of the fp32 kinematics: the scattering intends the
       // kinetic energy of the total centre-of-mass motion plus the
@@ -1866,21 +2030,26 @@ size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block) {
   return (b + 15) & ~(size_t)15;
 }
 
-template <bool MIX>
+template <bool MIX, bool EX>
 static hipError_t launch_step_t(const StepArgs &a, size_t lds, int block, uint32_t n_groups, hipStream_t s) {
   switch (block) {
-    case 64: hipLaunchKernelGGL((k_step<64, MIX>), dim3(n_groups), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((k_step<128, MIX>), dim3(n_groups), dim3(128), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((k_step<256, MIX>), dim3(n_groups), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_step<512, MIX>), dim3(n_groups), dim3(512), lds, s, a); break;
+    case 64: hipLaunchKernelGGL((k_step<64, MIX, EX>), dim3(n_groups), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_step<128, MIX, EX>), dim3(n_groups), dim3(128), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_step<256, MIX, EX>), dim3(n_groups), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_step<512, MIX, EX>), dim3(n_groups), dim3(512), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, uint32_t n_groups, hipStream_t s) {
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, bool exact, uint32_t n_groups,
+                       hipStream_t s) {
   if (n_groups == 0) return hipSuccess;
-  return mixed ? launch_step_t<true>(a, lds, block, n_groups, s) : launch_step_t<false>(a, lds, block, n_groups, s);
+  if (exact)
+    return mixed ? launch_step_t<true, true>(a, lds, block, n_groups, s)
+                 : launch_step_t<false, true>(a, lds, block, n_groups, s);
+  return mixed ? launch_step_t<true, false>(a, lds, block, n_groups, s)
+               : launch_step_t<false, false>(a, lds, block, n_groups, s);
 }
 
 hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s) {
@@ -1890,10 +2059,15 @@ hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s) {
 
 hipError_t set_step_lds_limit(size_t bytes) {
   hipError_t e = hipSuccess;
-  const void *fns[] = {(const void *)k_step<64, false>,  (const void *)k_step<128, false>,
-                       (const void *)k_step<256, false>, (const void *)k_step<512, false>,
-                       (const void *)k_step<64, true>,   (const void *)k_step<128, true>,
-                       (const void *)k_step<256, true>,  (const void *)k_step<512, true>};
+  const void *fns[] = {
+      (const void *)k_step<64, false, false>, (const void *)k_step<128, false, false>,
+      (const void *)k_step<256, false, false>, (const void *)k_step<512, false, false>,
+      (const void *)k_step<64, true, false>, (const void *)k_step<128, true, false>,
+      (const void *)k_step<256, true, false>, (const void *)k_step<512, true, false>,
+      (const void *)k_step<64, false, true>, (const void *)k_step<128, false, true>,
+      (const void *)k_step<256, false, true>, (const void *)k_step<512, false, true>,
+      (const void *)k_step<64, true, true>, (const void *)k_step<128, true, true>,
+      (const void *)k_step<256, true, true>, (const void *)k_step<512, true, true>};
   for (const void *f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;

@@ -19,7 +19,8 @@
 namespace hcao {
 // kernels (hcao_kernels.hip)
 size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block);
-hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, uint32_t n_groups, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, bool exact, uint32_t n_groups,
+                       hipStream_t s);
 hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s);
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
@@ -93,8 +94,11 @@ struct DevBuf {
 
 struct hcao_ctx {
   hcao_config cfg{};
-  std::vector<double> rec_host;  // recombination factors, all reactions
+  std::vector<double> rec_host;   // recombination factors, all reactions
+  std::vector<double> beta_host;  // exact sampler: beta per E' bin, per (species, LB exponent)
+  bool has_exact = false;         // some species uses the exact sampler
   DevBuf<double> d_rec;
+  DevBuf<double> d_beta;
   std::vector<double> volume, weight;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -712,7 +716,7 @@ hcao_status hcao_add_species(hcao_ctx *c, const hcao_species_desc *d, int32_t *i
   s.zpe = z;
   if (d->sampler == HCAO_SAMPLER_AUTO)
     s.sampler = (s.n_modes >= 2 && s.n_modes <= 4) ? HCAO_SAMPLER_JOINT : HCAO_SAMPLER_GIBBS;
-  else if (d->sampler == HCAO_SAMPLER_JOINT || d->sampler == HCAO_SAMPLER_GIBBS)
+  else if (d->sampler == HCAO_SAMPLER_JOINT || d->sampler == HCAO_SAMPLER_GIBBS || d->sampler == HCAO_SAMPLER_EXACT)
     s.sampler = d->sampler;
   else
     return fail(c, HCAO_EINVAL, "unknown sampler");
@@ -770,6 +774,54 @@ hcao_status hcao_add_reaction(hcao_ctx *c, const hcao_reaction_desc *d, int32_t 
   c->reactions.push_back(r);
   if (id) *id = (int32_t)c->reactions.size() - 1;
   return HCAO_OK;
+}
+
+// Exact sampler: beta of the proposal per bin of E' (energy above the zero
+// point). Bin b holds the smallest beta_j of the grid, found by bisection,
+// with G(beta_j) + q / beta_j <= E'_b: E'_b is the bin's midpoint and G the
+// proposal's mean energy over the modes' full level sets (bends
+// k Theta / expm1(beta k Theta), stretches the Boltzmann mean of
+// E_i - E_0 over all levels, ascending). Any beta gives the target exactly;
+// this one puts the acceptance near its maximum.
+static double exact_beta_grid(uint32_t j) { return std::ldexp(1.0 + (double)(j & 15u) / 16.0, (int)(j >> 4) + 40); }
+
+static double exact_mean_energy(const SpeciesTab &S, const std::vector<double> &lev, double beta) {
+  double g = 0.0;
+  for (uint32_t m = 0; m < S.n_modes; ++m) {
+    if (m < S.n_bend) {
+      g = g + S.kt[m] / std::expm1(beta * S.kt[m]);
+    } else {
+      const double *L = lev.data() + S.lev_off[m];
+      double num = 0.0, den = 0.0;
+      for (uint32_t i = 0; i <= S.idiss[m]; ++i) {
+        const double e = L[i] - L[0];
+        const double w = std::exp(-(beta * e));
+        num = num + e * w;
+        den = den + w;
+      }
+      g = g + num / den;
+    }
+  }
+  return g;
+}
+
+static void build_exact_table(const SpeciesTab &S, const std::vector<double> &lev, double q,
+                              std::vector<double> &out) {
+  for (uint32_t b = kExactBinLo; b <= kExactBinHi; ++b) {
+    const uint64_t bits = ((uint64_t)b << 48) | ((uint64_t)1 << 47);
+    double ec;
+    std::memcpy(&ec, &bits, sizeof(ec));
+    uint32_t lo = 0, hi = kExactNBeta - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      const double bm = exact_beta_grid(mid);
+      if (exact_mean_energy(S, lev, bm) + q / bm <= ec)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    out.push_back(exact_beta_grid(lo));
+  }
 }
 
 hcao_status hcao_finalize(hcao_ctx *c) {
@@ -850,8 +902,24 @@ hcao_status hcao_finalize(hcao_ctx *c) {
         }
       }
       T.pr[a][b].react = react;
-      T.pr[a][b].pad = 0;
     }
+  // exact sampler: one beta table per (species, LB exponent), shared by the
+  // pairs that use it
+  c->beta_host.clear();
+  c->has_exact = false;
+  for (uint32_t a = 0; a < T.n_species; ++a)
+    if (T.sp[a].sampler == HCAO_SAMPLER_EXACT && T.sp[a].n_modes > 0) c->has_exact = true;
+  for (uint32_t a = 0; a < T.n_species; ++a)
+    for (uint32_t b = 0; b < T.n_species; ++b) {
+      T.pr[a][b].beta_off = 0xFFFFFFFFu;
+      if (T.sp[a].sampler != HCAO_SAMPLER_EXACT || T.sp[a].n_modes == 0) continue;
+      for (uint32_t b2 = 0; b2 < b; ++b2)
+        if (T.pr[a][b2].q == T.pr[a][b].q) T.pr[a][b].beta_off = T.pr[a][b2].beta_off;
+      if (T.pr[a][b].beta_off != 0xFFFFFFFFu) continue;
+      T.pr[a][b].beta_off = (uint32_t)c->beta_host.size();
+      build_exact_table(T.sp[a], c->lev_host, T.pr[a][b].q, c->beta_host);
+    }
+  if (c->beta_host.empty()) c->beta_host.push_back(0.0);
   T.rec_nt = kRecNodes;
   T.rec_l0 = std::log(kRecTmin);
   T.rec_inv_step = (double)(kRecNodes - 1) / std::log(kRecTmax / kRecTmin);
@@ -895,6 +963,9 @@ hcao_status hcao_finalize(hcao_ctx *c) {
   HIP_TRY(c, c->d_tab.alloc(1));
   HIP_TRY(c, c->d_lev.alloc(c->lev_host.size()));
   HIP_TRY(c, c->d_rec.alloc(c->rec_host.size()));
+  HIP_TRY(c, c->d_beta.alloc(c->beta_host.size()));
+  HIP_TRY(c, hipMemcpyAsync(c->d_beta.p, c->beta_host.data(), c->beta_host.size() * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
   if (!c->rec_host.empty())
     HIP_TRY(c, hipMemcpyAsync(c->d_rec.p, c->rec_host.data(), c->rec_host.size() * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));
@@ -1017,6 +1088,7 @@ StepArgs step_args(hcao_ctx *c, double dt) {
   a.seed = c->cfg.seed;
   a.dt = dt;
   a.rec = c->d_rec.p;
+  a.beta = c->d_beta.p;
   a.grp = c->grp.p;
   a.grp_work = c->grp_work.p;
   a.work = c->work.p;
@@ -1037,7 +1109,7 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
     const uint32_t k = std::min(n_steps - done, c->steps_per_launch);
     a.step = (step_dev ? 0u : base) + done;
     a.n_steps = k;
-    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->n_groups, s));
+    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->has_exact, c->n_groups, s));
     done += k;
     ++n;
   }
@@ -1513,6 +1585,21 @@ hcao_status hcao_get_recombination_table(const hcao_ctx *c, uint32_t reaction, d
   return HCAO_OK;
 }
 
+hcao_status hcao_get_exact_beta(const hcao_ctx *c, uint32_t species, uint32_t partner, double e_J, double *beta) {
+  if (!c || !beta || !c->finalized || species >= c->species.size() || partner >= c->species.size() || !(e_J > 0.0))
+    return HCAO_EINVAL;
+  const PairTab &P = c->tab.pr[species][partner];
+  if (P.beta_off == 0xFFFFFFFFu) return HCAO_EINVAL;
+  uint64_t bits;
+  std::memcpy(&bits, &e_J, sizeof(bits));
+  uint32_t bin = (uint32_t)(bits >> 48);
+  bin = bin < kExactBinLo ? kExactBinLo : (bin > kExactBinHi ? kExactBinHi : bin);
+  double b = c->beta_host[P.beta_off + (bin - kExactBinLo)];
+  if (b * e_J < P.q) b = P.q / e_J;
+  *beta = b;
+  return HCAO_OK;
+}
+
 hcao_status hcao_set_timing(hcao_ctx *c, int enable) {
   if (!c) return HCAO_EINVAL;
   c->timing = enable != 0;
@@ -1628,6 +1715,7 @@ void hcao_destroy(hcao_ctx *c) {
   c->d_tab.release();
   c->d_lev.release();
   c->d_rec.release();
+  c->d_beta.release();
   c->err.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);

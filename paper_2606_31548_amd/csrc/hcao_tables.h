@@ -35,8 +35,8 @@ struct SpeciesTab {
 
 struct PairTab {
   double mr, hm, m_a, m_b, msum, wa, wb, csg, esg, q;
-  uint32_t react;  // some reaction lists this pair (as A, or as A + B / B + C), in either order
-  uint32_t pad;
+  uint32_t react;     // some reaction lists this pair (as A, or as A + B / B + C), in either order
+  uint32_t beta_off;  // exact sampler: offset of the beta table of species a with exponent q
 };
 
 // Recombination B + C (+M) -> A (+M) is stored with a = B, b = C, c = A,
@@ -50,6 +50,14 @@ struct ReactionTab {
   double steric, ea, dh, zsum;
   uint64_t rec_off;
 };
+
+// Exact sampler: inverse temperature of the proposal per bin of the energy
+// E' above the zero point; bin = (bit pattern of E') >> 48, clamped to
+// [kExactBinLo, kExactBinHi] (2^-90 .. 2^-49 J, 1/16 octave per bin)
+constexpr uint32_t kExactBinLo = 14928u;
+constexpr uint32_t kExactBinHi = 15583u;
+constexpr uint32_t kExactBins = kExactBinHi - kExactBinLo + 1;
+constexpr uint32_t kExactNBeta = 960u;  // beta grid (1 + (j mod 16) / 16) 2^(40 + j div 16)
 
 constexpr uint32_t kRecNodes = 1024;
 constexpr double kRecTmin = 100.0;
@@ -98,7 +106,8 @@ struct StepArgs {
   State st;
   State scratch;  // products of the step, at the cell's base + pair index
   CellArrays cells;
-  const double *rec;  // recombination factors
+  const double *rec;   // recombination factors
+  const double *beta;  // exact sampler's beta tables (PairTab::beta_off)
   const uint32_t *grp;
   const uint64_t *grp_work;
   uint32_t *work;

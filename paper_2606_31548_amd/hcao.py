@@ -107,6 +107,7 @@ def load_library():
     L.hcao_get_levels.argtypes = [_vp, _u32, _u32, _vp, _u32, ctypes.POINTER(_u32)]
     L.hcao_get_pair.argtypes = [_vp, _u32, _u32, _vp]
     L.hcao_get_recombination_table.argtypes = [_vp, _u32, _vp, _u32, ctypes.POINTER(_u32)]
+    L.hcao_get_exact_beta.argtypes = [_vp, _u32, _u32, _d, ctypes.POINTER(_d)]
     L.hcao_set_timing.argtypes = [_vp, ctypes.c_int]
     L.hcao_kernel_time.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]
     L.hcao_save.argtypes = [_vp, ctypes.c_char_p]
@@ -122,7 +123,7 @@ def load_library():
                  "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
                  "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore",
                  "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
-                 "hcao_read_cell_particles"):
+                 "hcao_read_cell_particles", "hcao_get_exact_beta"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -343,6 +344,13 @@ class Simulation:
         out = np.zeros(8, np.float64)
         self._chk("hcao_get_pair", self._L.hcao_get_pair(self._h, a, b, _p(out)))
         return dict(zip(("mr", "hm", "msum", "wa", "wb", "csg", "esg", "q"), out))
+
+    def exact_beta(self, species, partner, e_J):
+        """Inverse temperature of the EXACT sampler's proposal (host table)."""
+        b = _d()
+        self._chk("hcao_get_exact_beta", self._L.hcao_get_exact_beta(self._h, species, partner, float(e_J),
+                                                                      ctypes.byref(b)))
+        return b.value
 
     def recombination_table(self, reaction):
         out = np.zeros(self.n_species * 1024, np.float64)

@@ -26,7 +26,7 @@ K_BOLTZ = 1.380649e-23
 AMU = 1.66053906660e-27
 EV = 1.602176634e-19
 
-SAMPLER_AUTO, SAMPLER_JOINT, SAMPLER_GIBBS = 0, 1, 2
+SAMPLER_AUTO, SAMPLER_JOINT, SAMPLER_GIBBS, SAMPLER_EXACT = 0, 1, 2, 3
 RX_DISSOCIATION, RX_EXCHANGE, RX_RECOMBINATION = 0, 1, 2
 
 VOLUME = 4.64e-6

@@ -82,6 +82,25 @@ def test_mixed_energy_drift_over_1e4_steps(hc, case):
         assert (rc > 0).sum() >= 2
 
 
+def test_mixed_exact_sampler_energy_audit(hc):
+    """The exact sampler in the mixed form: the audit closes and the drift
+    stays far below 1e-6 of the thermal energy."""
+    wl = W.methane_chemistry(n_cells=16, per_cell=256, recombination=True)
+    for s in wl.species:
+        if s.n_modes:
+            s.sampler = W.SAMPLER_EXACT
+    g = _run(hc, wl, hc.MIXED, 0)
+    m0 = g.moments()
+    scale = _thermal(m0, g)
+    e0 = g.total_energy(m0, with_defect=False)
+    g.step(wl.dt, 2000)
+    g.sync()
+    m = g.moments()
+    assert abs(g.total_energy(m) - e0) / scale < 1e-11
+    assert abs(g.total_energy(m, with_defect=False) - e0) / scale < 1e-6
+    assert g.cell_state()[2][:, 3].sum() > 1000  # relaxations happened
+
+
 def test_fp64_energy_is_conserved_over_1e4_steps(hc):
     wl = W.methane_chemistry(n_cells=32, per_cell=256, recombination=True)
     g = _run(hc, wl, hc.FP64, 0)

@@ -134,6 +134,43 @@ def test_step_parity_joint_sampler_many_modes(orc, hc):
     _run_parity(orc, hc, wl, 20, [20])
 
 
+def _exact_workload(**kw):
+    wl = W.methane_chemistry(**kw)
+    for s in wl.species:
+        if s.n_modes:
+            s.sampler = W.SAMPLER_EXACT
+    return wl
+
+
+def test_exact_beta_tables_are_bitwise_equal(orc, hc):
+    """The exact sampler's beta per E' bin, built on each side from its own
+    code, for every bin and every (species, partner)."""
+    wl = _exact_workload(n_cells=2, per_cell=16, recombination=True)
+    o, g = _both(orc, hc, wl)
+    bins = np.arange(14928, 15584, dtype=np.uint64)
+    eps = ((bins << np.uint64(48)) | np.uint64(1 << 47)).view(np.float64)
+    eps = np.concatenate([eps, [1e-30, 1e-12]])  # below and above the table
+    for s, sp in enumerate(wl.species):
+        if not sp.n_modes:
+            continue
+        for t in range(len(wl.species)):
+            q = g.pair(s, t)["q"]
+            a = np.array([o.exact_beta(s, q, e) for e in eps])
+            b = np.array([g.exact_beta(s, t, e) for e in eps])
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), (s, t)
+
+
+def test_step_parity_exact_sampler(orc, hc):
+    """Every molecule (CH4, CH3, H2) relaxes, and every product takes its
+    levels, through the exact joint sampler: bitwise against the oracle,
+    with dissociation, exchange and recombination."""
+    wl = _exact_workload(n_cells=16, per_cell=256, recombination=True, t=12000.0)
+    o, g = _run_parity(orc, hc, wl, 40, [1, 19, 20])
+    ctr = o.counters().sum(0)
+    assert ctr[orc.CTR_RELAX] > 1000
+    assert (ctr[orc.CTR_REACTION0:orc.CTR_REACTION0 + 3] > 0).sum() >= 2
+
+
 def test_step_parity_ragged_cells(orc, hc):
     """Cells of 0, 1, 2, 3 ... particles next to cells of up to 2500."""
     wl = W.methane_argon(n_cells=40, per_cell=256, t_trans=30000.0)

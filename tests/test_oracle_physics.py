@@ -6,6 +6,7 @@ Larsen-Borgnakke level distribution for tiny level counts, Boltzmann
 populations in a heat bath, per-collision conservation, reaction thresholds
 and competition weights, and the adiabatic equilibrium of a closed reservoir.
 """
+import itertools
 import math
 
 import numpy as np
@@ -301,6 +302,102 @@ def test_gibbs_envelope_bounds_the_target(orc):
                 assert np.all(t <= (1.0 - c * i) * (1 + 1e-12)), (sp, m, ec)
 
 
+def _joint_target(levels, e_coll, q):
+    """Exact law of the joint target over all level vectors: P proportional
+    to (E_coll - sum E)^q where sum E < E_coll."""
+    probs = {}
+    for idx in itertools.product(*[range(len(L)) for L in levels]):
+        s = sum(L[i] for L, i in zip(levels, idx))
+        if s < e_coll:
+            probs[idx] = (e_coll - s) ** q
+    z = sum(probs.values())
+    return {k: v / z for k, v in probs.items()}
+
+
+@pytest.mark.parametrize("e_coll_ev", [0.62, 1.2, 2.0])
+def test_exact_sampler_matches_enumeration(orc, e_coll_ev):
+    """The exact sampler draws the joint target itself, independently of the
+    molecule's levels before the collision: chi^2 against enumeration from
+    two different starting states. The tiny species' first stretch has
+    growing spacings, so its proposal slope is the smallest (E_i - E_0)/i."""
+    q = 1.5 - 0.74
+    o = _build(orc, [_tiny_species(orc.SAMPLER_EXACT)], seed=13)
+    L = _mode_levels(o)
+    e_coll = e_coll_ev * EV
+    probs = _joint_target(L, e_coll, q)
+    n = 60000
+    for start in ((0, 0, 0), (1, 1, 1)):
+        st = np.tile(np.array(start, np.uint16), (n, 1))
+        e_tr = np.full(n, e_coll - sum(L[m][start[m]] for m in range(3)))
+        lv, e_out, trials = o.relax_batch(0, q, orc.SAMPLER_EXACT, e_tr, st)
+        samples = [tuple(int(x) for x in r) for r in lv]
+        if len(probs) > 1:
+            assert _chi2_states(samples, probs) > 1e-4, start
+        else:
+            assert set(samples) == set(probs)
+        evib = np.array([sum(L[m][i] for m, i in enumerate(smp)) for smp in samples])
+        np.testing.assert_allclose(e_out + evib, e_coll, rtol=1e-14)
+
+
+def test_exact_sampler_matches_enumeration_six_modes(orc):
+    """CH3 (three bends, three Morse stretches) at E' = 1 eV: chi^2 of the
+    full level vector against enumeration of the joint target, where the
+    printed joint proposal would need tens of trials."""
+    q = 1.5 - 0.74
+    o = _build(orc, W.methane_species(), seed=14)
+    zpe, nm, _ = o.species_info(W.CH3)
+    ep = 1.0 * EV
+    L = []
+    for m in range(nm):
+        lev = o.levels(W.CH3, m, 200)
+        L.append(lev[lev - lev[0] < ep])
+    probs = _joint_target(L, zpe + ep, q)
+    n = 80000
+    lv, e_out, trials = o.relax_batch(W.CH3, q, orc.SAMPLER_EXACT, np.full(n, ep), np.zeros((n, nm), np.uint16))
+    samples = [tuple(int(x) for x in r) for r in lv]
+    assert _chi2_states(samples, probs) > 1e-4
+
+
+def test_exact_beta_rule(orc):
+    """beta comes from the grid (1 + j/16) 2^k, is constant over each 1/16
+    octave of E', never below q / E', and solves mean proposal energy +
+    q / beta = E' to within one grid step at the bin's midpoint."""
+    q = 1.5 - 0.74
+    o = _build(orc, W.methane_species(), seed=15)
+    for sp in (W.CH4, W.CH3, W.H2):
+        s_obj = W.methane_species()[sp]
+        lev = [o.levels(sp, m, 200) for m in range(s_obj.n_modes)]
+        nb = len(s_obj.bend_theta_K)
+
+        def mean_e(beta):
+            g = 0.0
+            for m in range(s_obj.n_modes):
+                if m < nb:
+                    kt = KB * s_obj.bend_theta_K[m]
+                    g += kt / math.expm1(beta * kt)
+                else:
+                    e = lev[m] - lev[m][0]
+                    w = np.exp(-beta * e)
+                    g += float((e * w).sum() / w.sum())
+            return g
+
+        for ep_ev in (0.01, 0.1, 0.5, 1.0, 3.0, 8.0, 20.0):
+            ep = ep_ev * EV
+            beta = o.exact_beta(sp, q, ep)
+            assert beta * ep >= q * (1 - 1e-15)
+            assert o.exact_beta(sp, q, ep * (1 + 1e-9)) == beta
+            if beta * ep < q * 1.0001:
+                continue  # raised to q / E'
+            mant, ex = math.frexp(beta)
+            r = (2 * mant - 1) * 16
+            assert r == int(r), beta  # on the grid (1 + r/16) 2^k
+            prev = beta - math.ldexp(1.0 / 16, ex - 1 if r > 0 else ex - 2)
+            bits = int(np.float64(ep).view(np.uint64)) >> 48
+            mid = float(np.array([(bits << 48) | (1 << 47)], np.uint64).view(np.float64)[0])
+            assert mean_e(beta) + q / beta <= mid * (1 + 1e-12)
+            assert mean_e(prev) + q / prev > mid * (1 - 1e-12)
+
+
 # --------------------------------------------------------------------------
 # heat bath: Boltzmann populations
 # --------------------------------------------------------------------------
@@ -337,6 +434,11 @@ def test_heat_bath_joint_sampler_is_boltzmann(orc):
 def test_heat_bath_gibbs_sampler_is_boltzmann(orc):
     o = _build(orc, W.methane_species(), seed=22)
     assert _boltzmann_check(o, 0, orc.SAMPLER_GIBBS, 5000.0, 3000, 40) > 1e-4
+
+
+def test_heat_bath_exact_sampler_is_boltzmann(orc):
+    o = _build(orc, W.methane_species(), seed=24)
+    assert _boltzmann_check(o, 0, orc.SAMPLER_EXACT, 5000.0, 3000, 40) > 1e-4
 
 
 def test_heat_bath_gibbs_on_triatomic(orc):

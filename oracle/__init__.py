@@ -83,6 +83,7 @@ def lib():
         L.orc_wr_rho.argtypes = [vp, u32, d]; L.orc_wr_rho.restype = d
         L.orc_wr_probability.argtypes = [vp, u32, d, d, u32, d]; L.orc_wr_probability.restype = d
         L.orc_q_vib.argtypes = [vp, u32, d]; L.orc_q_vib.restype = d
+        L.orc_rec_exact_probability.argtypes = [vp, u32, d, d, d]; L.orc_rec_exact_probability.restype = d
         L.orc_rec_factor.argtypes = [vp, u32, u32, d]; L.orc_rec_factor.restype = d
         L.orc_rec_table.argtypes = [vp, u32, vp]; L.orc_rec_table.restype = ctypes.c_int
         for name in ("orc_create", "orc_add_species", "orc_add_reaction", "orc_finalize", "orc_load",
@@ -320,6 +321,9 @@ class Oracle:
 
     def wr_probability(self, species, de, omega, n_samp, t):
         return lib().orc_wr_probability(self._h, species, float(de), float(omega), int(n_samp), float(t))
+
+    def rec_exact_probability(self, species, de, omega, t):
+        return lib().orc_rec_exact_probability(self._h, species, float(de), float(omega), float(t))
 
     def q_vib(self, species, t):
         return lib().orc_q_vib(self._h, species, float(t))

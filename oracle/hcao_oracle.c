@@ -724,6 +724,62 @@ double orc_wr_probability(const orc_ctx *o, uint32_t species, double de, double 
 
 double orc_q_vib(const orc_ctx *o, uint32_t species, double t) { return q_vib(&o->sp[species], t); }
 
+/* Forward probability of Eq. recomb-correct, summed over every combination
+ * of vibrational levels of A (reading A7b): P(T) = sum_i Q(a, (D_e - S_i)/kT)
+ * exp(-S_i/kT) / sum_i exp(-S_i/kT), S_i the energy of combination i above
+ * the ground level (sum over modes of E_m(j) - E_m(0)), a = 5/2 - omega, Q the
+ * regularized upper incomplete gamma with Q = 1 for a non-positive argument.
+ * Bends are infinite harmonic ladders, stretches run over 0..i_diss.
+ * Combinations below D_e are enumerated one by one (depth-first over the
+ * modes in order); every combination at or above D_e has Q = 1, and those
+ * are summed in closed form where the enumeration first crosses D_e: at mode
+ * m with partial energy S_p, the levels j' >= j of m that cross, times all
+ * levels of the later modes, give exp(-S_p/kT) sum_{j'>=j} exp(-e_m(j')/kT)
+ * prod_{m'>m} Z_m'. No term is subtracted, so small P keep full precision. */
+static double rec_zmode(const species_t *s, uint32_t m, double beta) {
+  if (m < s->n_bend) return 1.0 / (1.0 - exp(-(beta * s->kt[m])));
+  double z = 0.0;
+  for (uint32_t i = 0; i <= s->idiss[m]; ++i) z = z + exp(-(beta * (s->lev[m][i] - s->lev[m][0])));
+  return z;
+}
+
+static double rec_exact_walk(const species_t *s, uint32_t m, double sp, double de, double a, double beta,
+                             const double *zrest) {
+  if (m == s->n_modes) return gamma_q(a, beta * (de - sp)) * exp(-(beta * sp));
+  double total = 0.0;
+  for (uint32_t j = 0;; ++j) {
+    if (m >= s->n_bend && j > s->idiss[m]) break; /* stretch ladder ends below D_e */
+    double e = mode_energy(s, m, j) - mode_energy(s, m, 0);
+    double sj = sp + e;
+    if (!(sj < de)) {
+      /* levels j.. of mode m cross D_e: closed form over them and the later modes */
+      double tail;
+      if (m < s->n_bend) {
+        tail = exp(-(beta * sj)) / (1.0 - exp(-(beta * s->kt[m])));
+      } else {
+        tail = 0.0;
+        for (uint32_t k = j; k <= s->idiss[m]; ++k)
+          tail = tail + exp(-(beta * (sp + (mode_energy(s, m, k) - mode_energy(s, m, 0)))));
+      }
+      total = total + tail * zrest[m + 1];
+      break;
+    }
+    total = total + rec_exact_walk(s, m + 1, sj, de, a, beta, zrest);
+  }
+  return total;
+}
+
+double orc_rec_exact_probability(const orc_ctx *o, uint32_t species, double de, double omega, double t) {
+  if (!o || species >= o->n_species || !(t > 0.0) || !(de > 0.0)) return -1.0;
+  const species_t *s = &o->sp[species];
+  double beta = 1.0 / (K_BOLTZ * t);
+  double zrest[ORC_MAX_MODES + 1];
+  zrest[s->n_modes] = 1.0;
+  for (uint32_t m = s->n_modes; m-- > 0;) zrest[m] = zrest[m + 1] * rec_zmode(s, m, beta);
+  double num = rec_exact_walk(s, 0, 0.0, de, 2.5 - omega, beta, zrest);
+  return num / zrest[0];
+}
+
 /* per-collision recombination probability factor at the cell temperature,
  * linear in log T between table nodes */
 static double rec_lookup(const orc_ctx *o, const reaction_t *R, uint32_t m, double t) {

@@ -99,6 +99,9 @@ double orc_gamma_q(double a, double x);
 double orc_wr_rho(const orc_ctx *o, uint32_t species, double e);
 double orc_wr_probability(const orc_ctx *o, uint32_t species, double de, double omega, uint32_t n_samp, double t);
 double orc_q_vib(const orc_ctx *o, uint32_t species, double t);
+/* Eq. recomb-correct: the forward probability summed over every level
+ * combination of the species (a = 5/2 - omega), at temperature t. */
+double orc_rec_exact_probability(const orc_ctx *o, uint32_t species, double de, double omega, double t);
 double orc_rec_factor(const orc_ctx *o, uint32_t reaction, uint32_t third, double t);
 int orc_rec_table(const orc_ctx *o, uint32_t reaction, double *out);
 int orc_collide3_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,

@@ -101,6 +101,41 @@ def test_wr_probability_tracks_exact_level_sum(orc):
         assert 0.5 < approx / exact < 2.0, (t, approx, exact)
 
 
+@pytest.mark.parametrize("t", [1500.0, 3000.0, 6000.0, 10000.0, 20000.0])
+def test_exact_recombination_sum_matches_box_enumeration(orc, t):
+    """Eq. recomb-correct by the oracle's depth-first walk (closed-form tails
+    above D_e) against a brute-force sum over a level box of the triatomic
+    (bend truncated at 900 levels, far above D_e), down to P ~ 1e-15."""
+    sp = W.triatomic_species()
+    o = _build(orc, sp)
+    lev = [o.levels(0, 0, 900), o.levels(0, 1), o.levels(0, 2)]
+    de = 5.5 * EV
+    a = 2.5 - 0.74
+    e = (lev[0][:, None, None] - lev[0][0]) + (lev[1][None, :, None] - lev[1][0]) + \
+        (lev[2][None, None, :] - lev[2][0])
+    w = np.exp(-e / (KB * t))
+    g = special.gammaincc(a, np.maximum(de - e, 0) / (KB * t))
+    box = float((g * w).sum() / w.sum())
+    got = o.rec_exact_probability(0, de, 0.74, t)
+    assert abs(got / box - 1) < 1e-12, (got, box)
+
+
+def test_exact_recombination_single_oscillator_closed_form(orc):
+    """One harmonic oscillator of spacing eps and a = 1 (Q(1, x) = e^-x): the
+    J levels below D contribute e^(-D/kT) each, the rest their Boltzmann
+    weight, so P = (1 - r) (J e^(-D/kT) + r^J / (1 - r)), r = e^(-eps/kT)."""
+    theta = 1800.0
+    o = _build(orc, [W.Species("osc", 20 * W.AMU, bend_theta_K=[theta])])
+    eps = KB * theta
+    for de_ev, t in ((0.9, 700.0), (2.0, 3000.0), (5.0, 12000.0), (3.1, 40000.0)):
+        de = de_ev * EV
+        j = math.ceil(de / eps)
+        r = math.exp(-eps / (KB * t))
+        want = (1 - r) * (j * math.exp(-de / (KB * t)) + r ** j / (1 - r))
+        got = o.rec_exact_probability(0, de, 1.5, t)
+        assert abs(got / want - 1) < 1e-12, (de_ev, t, got, want)
+
+
 def _recomb_setup(orc):
     sp = W.methane_species()
     rx = [W.methane_dissociation(), W.methane_exchange(), W.methyl_recombination()]

@@ -86,6 +86,31 @@ SAMPLER_DESC = {"auto": "joint for 2-4 modes, Gibbs sweep otherwise", "joint": "
                 "gibbs": "Gibbs sweep", "exact": "exact joint sampler (per-mode Boltzmann proposals)"}
 
 
+def recombination_exact(hcao, oracle_nodes=3):
+    """Eq. recomb-correct for CH4 (9 modes, D_e 4.5 eV) over the 1024-node
+    temperature table on the device, and the oracle's serial sum at a few of
+    the nodes for comparison (time per temperature, largest relative
+    difference)."""
+    import oracle
+    oracle.build(force=False)
+    wl = W.methane_chemistry(n_cells=2, per_cell=16, recombination=True)
+    g = hcao.from_workload(wl)
+    nodes = np.exp(np.log(100.0) + np.arange(1024) * np.log(5e4 / 100.0) / 1023)
+    g.recombination_exact(W.CH4, 4.5 * W.EV, 0.74, nodes[:4])  # warm-up
+    p, ms, nrec = g.recombination_exact(W.CH4, 4.5 * W.EV, 0.74, nodes)
+    o = oracle.from_workload(wl)
+    worst, t0 = 0.0, time.perf_counter()
+    for i in np.linspace(256, 1023, oracle_nodes).astype(int):
+        want = o.rec_exact_probability(W.CH4, 4.5 * W.EV, 0.74, nodes[i])
+        worst = max(worst, abs(p[i] / want - 1.0))
+    cpu_per_t = (time.perf_counter() - t0) / oracle_nodes
+    g.close()
+    return {"species": "CH4 (9 modes)", "temperatures": 1024, "records": int(nrec), "device_ms": ms,
+            "records_x_temperatures_per_s": nrec * 1024 / (ms * 1e-3),
+            "oracle_s_per_temperature": cpu_per_t, "oracle_s_for_table": cpu_per_t * 1024,
+            "max_rel_diff_vs_oracle": worst}
+
+
 def set_sampler(wl, sampler):
     for s in wl.species:
         if s.n_modes:
@@ -288,6 +313,8 @@ def main():
                          "the tuned one")
     ap.add_argument("--sampler", default="auto", choices=SAMPLERS,
                     help="relaxation sampler of every molecular species")
+    ap.add_argument("--recomb-exact", action="store_true",
+                    help="also time Eq. recomb-correct for CH4 on the device against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this size (counter calibration)")
@@ -355,6 +382,9 @@ def main():
         out["sequential_fp64"] = seq
         if "fp64" in res:
             out["batched_vs_sequential_fp64"] = res["fp64"]["collisions_per_s"] / seq["collisions_per_s"]
+    if args.recomb_exact:
+        print("# Eq. recomb-correct for CH4 on the device and in the oracle", file=sys.stderr, flush=True)
+        out["recombination_exact"] = recombination_exact(hcao)
     if not args.no_cpu_baseline:
         print("# timing the oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds, args.sampler)

@@ -102,6 +102,10 @@ typedef enum {
   HCAO_SAMPLER_EXACT = 3
 } hcao_sampler;
 typedef enum { HCAO_RX_DISSOCIATION = 0, HCAO_RX_EXCHANGE = 1, HCAO_RX_RECOMBINATION = 2 } hcao_rx_kind;
+/* Forward probability of a recombination: the Whitten-Rabinovich
+ * approximation, or the sum over every level combination (Eq. recomb-correct,
+ * evaluated on the device at finalize). */
+typedef enum { HCAO_REC_WR = 0, HCAO_REC_EXACT = 1 } hcao_rec_model;
 
 /* Context configuration.
  *   seed: key of every random stream.
@@ -171,8 +175,11 @@ typedef struct {
  *     in [0,1]; Ea_J the barrier. m_A + m_B must equal m_C + m_D.
  *   RECOMBINATION (Sec. "Recombination reactions"): reactant = {B, C}
  *     (distinct species), product[0] = A, stretch_mask names the bond of A
- *     whose D_e enters the forward probability; n_samp sample energies of
- *     the Whitten-Rabinovich approximation (0 = 1000). The pair k's third
+ *     whose D_e enters the forward probability; rec_model picks the forward
+ *     probability P: HCAO_REC_WR (the Whitten-Rabinovich approximation with
+ *     n_samp sample energies, 0 = 1000) or HCAO_REC_EXACT (Eq.
+ *     recomb-correct summed over every level combination of A on the device,
+ *     see hcao_recombination_exact). The pair k's third
  *     body is the particle at permutation index 2 N_cand + k (if any); the
  *     pair recombines with probability min(1, k_b n / <sigma g>_BC) at the
  *     cell's step-start translational temperature, k_b = k_f / K_eq with k_f
@@ -189,6 +196,7 @@ typedef struct {
   double steric, Ea_J;
   double gamma_rot;
   uint32_t n_samp;
+  hcao_rec_model rec_model;
 } hcao_reaction_desc;
 
 /* Moments of one cell or of all cells (hcao_read_moments).
@@ -327,6 +335,26 @@ hcao_status hcao_get_recombination_table(const hcao_ctx *ctx, uint32_t reaction,
  * the EXACT sampler, has no modes, or e_J is not positive. Host-side table
  * read; no device work. */
 hcao_status hcao_get_exact_beta(const hcao_ctx *ctx, uint32_t species, uint32_t partner, double e_J, double *beta);
+
+/* Forward recombination probability of Sec. "Recombination reactions",
+ * Eq. recomb-correct, for product species `species` with bond energy de_J
+ * and VHS omega (a = 5/2 - omega, 0.5 <= omega < 1.5), at n_t temperatures
+ * t_K[] (host, K) into p_out[] (host). P(T) = sum_i Q(a, (D_e - S_i)/kT)
+ * exp(-S_i/kT) / sum_i exp(-S_i/kT) over every combination i of the
+ * species' vibrational levels, S_i its energy above the ground level, Q the
+ * regularized upper incomplete gamma (1 for arguments <= 0); bends are
+ * infinite harmonic ladders, stretches run to their top bound level. The
+ * device enumerates every combination below D_e (one record each) and the
+ * points where the enumeration first crosses D_e (the combinations above it
+ * have Q = 1 and are summed in closed form there), then sums the records
+ * for each temperature in one workgroup. Sums are in a fixed order, so
+ * results repeat bitwise; they match a serial sum to rounding (~1e-13
+ * relative). elapsed_ms and n_records (may be NULL) receive the device
+ * time and the number of records. Allocates device memory for the records
+ * (16 bytes each); synchronous on the context's stream. HCAO_EUNSUPPORTED
+ * if the species' stretch ladders exceed 8192 levels in total. */
+hcao_status hcao_recombination_exact(hcao_ctx *ctx, uint32_t species, double de_J, double omega, uint32_t n_t,
+                                     const double *t_K, double *p_out, double *elapsed_ms, uint64_t *n_records);
 
 /* Kernel timing over the stream: when enabled, each hcao_step call records
  * HIP events on the context's stream around its step-kernel launches;

@@ -2017,6 +2017,186 @@ __global__ void k_iota(uint32_t *x, uint64_t n) {
   if (i < n) x[i] = (uint32_t)i;
 }
 
+
+// ---------------------------------------------------------------------------
+// Eq. recomb-correct: forward probability summed over every combination of
+// vibrational levels (set-up work, not part of the step)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double level_above_ground(const SpeciesTab &S, const double *lev, uint32_t m, uint32_t j) {
+  return mode_energy(S, lev, m, j) - mode_energy(S, lev, m, 0);
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_rec_enum(RecEnumArgs A) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= A.n_prefix) return;
+  const SpeciesTab &S = A.tab->sp[A.species];
+  const uint32_t nm = S.n_modes, np = A.n_prefix_modes;
+  uint32_t j[kMaxModes];
+  double st[kMaxModes + 1];
+  uint64_t x = tid;
+  for (uint32_t m = 0; m < np; ++m) {
+    j[m] = (uint32_t)(x % A.box[m]);
+    x /= A.box[m];
+  }
+  uint32_t n = 0;
+  const uint64_t o = WRITE ? A.offset[tid] : 0;
+  auto emit = [&](double e, uint32_t code) {
+    if (WRITE) {
+      A.rec_e[o + n] = e;
+      A.rec_code[o + n] = code;
+    }
+    ++n;
+  };
+  // the prefix: valid while below de; a crossing inside it is emitted once,
+  // by the prefix whose crossing level is the first one and whose later
+  // digits are 0
+  double s = 0.0;
+  bool walk = true;
+  for (uint32_t m = 0; m < np && walk; ++m) {
+    if (m >= S.n_bend && j[m] > S.idiss[m]) {
+      walk = false;
+      break;
+    }
+    const double s2 = s + level_above_ground(S, A.lev, m, j[m]);
+    if (!(s2 < A.de)) {
+      bool first = j[m] == 0 || s + level_above_ground(S, A.lev, m, j[m] - 1) < A.de;
+      for (uint32_t k = m + 1; k < np; ++k) first = first && j[k] == 0;
+      if (first) emit(s2, m | (j[m] << 8));
+      walk = false;
+      break;
+    }
+    s = s2;
+  }
+  if (walk) {
+    if (np == nm) {
+      emit(s, kRecLeaf);
+    } else {
+      uint32_t m = np;
+      j[m] = 0;
+      st[m] = s;
+      for (;;) {
+        bool back = false;
+        if (m >= S.n_bend && j[m] > S.idiss[m]) {
+          back = true;
+        } else {
+          const double s2 = st[m] + level_above_ground(S, A.lev, m, j[m]);
+          if (!(s2 < A.de)) {
+            emit(s2, m | (j[m] << 8));
+            back = true;
+          } else if (m + 1 == nm) {
+            emit(s2, kRecLeaf);
+            ++j[m];
+          } else {
+            st[m + 1] = s2;
+            j[m + 1] = 0;
+            ++m;
+          }
+        }
+        if (back) {
+          if (m == np) break;
+          --m;
+          ++j[m];
+        }
+      }
+    }
+  }
+  if (!WRITE) A.count[tid] = n;
+}
+
+// Regularized upper incomplete gamma Q(a, x) times exp(-y), x > 0 (series
+// for the lower function below x = a + 1, Lentz's continued fraction above;
+// Press et al., Numerical Recipes 6.2); the prefactor joins exp(-y) in one
+// exponent so that small terms do not underflow early.
+__device__ double gamma_q_scaled(double a, double x, double lga, double y) {
+  const double lpre = (a * log(x) - x) - lga;
+  if (x < a + 1.0) {
+    double ap = a, del = 1.0 / a, sum = del;
+    for (int i = 1; i <= 1000; ++i) {
+      ap += 1.0;
+      del *= x / ap;
+      sum += del;
+      if (fabs(del) < fabs(sum) * 1e-17) break;
+    }
+    return (1.0 - sum * exp(lpre)) * exp(-y);
+  }
+  const double tiny = 1e-300;
+  double b = (x + 1.0) - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i <= 1000; ++i) {
+    const double an = -(double)i * ((double)i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (fabs(del - 1.0) < 1e-17) break;
+  }
+  return exp(lpre - y) * h;
+}
+
+__global__ __launch_bounds__(256) void k_rec_sum(RecSumArgs A) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  double *tail = reinterpret_cast<double *>(smem);  // stretch levels: sum_{k >= j} exp(-beta (e_k - e_j))
+  __shared__ double s_z[kMaxModes + 1], s_bend[kMaxModes], s_red[256];
+  const SpeciesTab &S = A.tab->sp[A.species];
+  const uint32_t nm = S.n_modes, tid = threadIdx.x;
+  const double beta = 1.0 / (kBoltz * A.t[blockIdx.x]);
+  if (tid < nm) {
+    const uint32_t m = tid;
+    if (m < S.n_bend) {
+      const double z = 1.0 / (1.0 - exp(-(beta * S.kt[m])));
+      s_bend[m] = z;
+      s_z[m] = z;
+    } else {
+      // tail sums from the top level down; the partition sum is tail[0]
+      const uint32_t base = S.lev_off[m] - S.lev_off[S.n_bend];
+      const uint32_t top = S.idiss[m];
+      tail[base + top] = 1.0;
+      for (uint32_t k = top; k-- > 0;) {
+        const double step = level_above_ground(S, A.lev, m, k + 1) - level_above_ground(S, A.lev, m, k);
+        tail[base + k] = 1.0 + exp(-(beta * step)) * tail[base + k + 1];
+      }
+      s_z[m] = tail[base];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // s_z[m] becomes the product of the partition sums of modes m..nm-1
+    double z = 1.0;
+    s_z[nm] = 1.0;
+    for (uint32_t m = nm; m-- > 0;) {
+      z = z * s_z[m];
+      s_z[m] = z;
+    }
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (uint64_t i = tid; i < A.n_rec; i += 256) {
+    const double e = A.rec_e[i];
+    const uint32_t code = A.rec_code[i];
+    if (code == kRecLeaf) {
+      acc += gamma_q_scaled(A.a, beta * (A.de - e), A.lgamma_a, beta * e);
+    } else {
+      const uint32_t m = code & 0xFFu, jj = code >> 8;
+      const double rel = m < S.n_bend ? s_bend[m] : tail[(S.lev_off[m] - S.lev_off[S.n_bend]) + jj];
+      acc += (exp(-(beta * e)) * rel) * s_z[m + 1];
+    }
+  }
+  s_red[tid] = acc;
+  __syncthreads();
+  for (uint32_t w = 128; w > 0; w >>= 1) {
+    if (tid < w) s_red[tid] = s_red[tid] + s_red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    A.num[blockIdx.x] = s_red[0];
+    A.den[blockIdx.x] = s_z[0];
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2137,6 +2317,22 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
 }
 
 uint64_t sort_tiles(uint64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+hipError_t launch_rec_enum(const RecEnumArgs &a, bool write, hipStream_t s) {
+  if (a.n_prefix == 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.n_prefix + 255) / 256));
+  if (write)
+    hipLaunchKernelGGL(k_rec_enum<true>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_rec_enum<false>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_sum(const RecSumArgs &a, uint32_t n_t, size_t lds, hipStream_t s) {
+  if (n_t == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rec_sum, dim3(n_t), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
                         const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,

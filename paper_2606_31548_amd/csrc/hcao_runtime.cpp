@@ -34,6 +34,8 @@ hipError_t launch_load_check(const Tables *tab, const uint32_t *cell, const uint
                              const uint16_t *lvl, uint64_t n, uint32_t n_cells, uint32_t *count, uint32_t *err,
                              hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t s);
+hipError_t launch_rec_enum(const RecEnumArgs &a, bool write, hipStream_t s);
+hipError_t launch_rec_sum(const RecSumArgs &a, uint32_t n_t, size_t lds, hipStream_t s);
 hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32_t *idx_tmp, uint32_t *hist,
                        uint64_t *offs, uint64_t n, uint32_t key_bits, hipStream_t s, bool &result_in_tmp);
 uint64_t sort_tiles(uint64_t n);
@@ -570,8 +572,107 @@ double wr_forward(const SpeciesHost &A, double de, double omega, uint32_t n_samp
 }
 
 // k_b / <sigma g>_BC on the log-T grid, per third-body species (appended to out)
+// Eq. recomb-correct on the device for species sp of the device tables:
+// every level combination below de is enumerated (count pass, scan, write
+// pass), then one workgroup per temperature sums the records. p[i] receives
+// the probability at t[i]; ms and n_rec (may be null) the device time and
+// the number of records.
+hcao_status exact_rec_probability(hcao_ctx *c, uint32_t sp, double de, double omega, uint32_t n_t, const double *t,
+                                  double *p, double *ms, uint64_t *n_rec) {
+  const SpeciesTab &S = c->tab.sp[sp];
+  const uint32_t nm = S.n_modes;
+  if (nm == 0 || !(de > 0.0) || !(omega >= 0.5 && omega < 1.5)) return fail(c, HCAO_EINVAL, "bad exact recombination input");
+  RecEnumArgs ea{};
+  ea.tab = c->d_tab.p;
+  ea.lev = c->d_lev.p;
+  ea.species = sp;
+  ea.de = de;
+  // box of the prefix modes: the levels below de and the first one above
+  uint32_t box[kMaxModes];
+  size_t n_sl = 0;
+  for (uint32_t m = 0; m < nm; ++m) {
+    uint32_t below = 0;
+    if (m < S.n_bend) {
+      while (((double)below + 0.5) * S.kt[m] - 0.5 * S.kt[m] < de) ++below;
+      box[m] = below + 1;
+    } else {
+      const double *L = c->lev_host.data() + S.lev_off[m];
+      while (below <= S.idiss[m] && L[below] - L[0] < de) ++below;
+      box[m] = std::min(below + 1, S.idiss[m] + 1);
+      n_sl += S.idiss[m] + 1;
+    }
+  }
+  if (n_sl * sizeof(double) > kLdsBudget) return fail(c, HCAO_EUNSUPPORTED, "stretch ladders too long for the exact sum");
+  uint64_t n_prefix = 1;
+  uint32_t np = 0;
+  while (np < nm && n_prefix * box[np] <= (1ull << 22)) n_prefix *= box[np++];
+  if (np == 0) {
+    np = 1;
+    n_prefix = box[0];
+  }
+  ea.n_prefix_modes = np;
+  for (uint32_t m = 0; m < np; ++m) ea.box[m] = box[m];
+  ea.n_prefix = n_prefix;
+  DevBuf<uint32_t> cnt;
+  DevBuf<uint64_t> off;
+  DevBuf<double> rec_e, d_t, d_num, d_den;
+  DevBuf<uint32_t> rec_code;
+  HIP_TRY(c, cnt.alloc(n_prefix));
+  HIP_TRY(c, off.alloc(n_prefix));
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  HIP_TRY(c, hipEventRecord(e0, c->stream));
+  ea.count = cnt.p;
+  HIP_TRY(c, launch_rec_enum(ea, false, c->stream));
+  HIP_TRY(c, launch_scan_u32(cnt.p, off.p, n_prefix, c->stream));
+  uint64_t last_off = 0;
+  uint32_t last_cnt = 0;
+  HIP_TRY(c, hipMemcpyAsync(&last_off, off.p + (n_prefix - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&last_cnt, cnt.p + (n_prefix - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const uint64_t total = last_off + last_cnt;
+  HIP_TRY(c, rec_e.alloc(total));
+  HIP_TRY(c, rec_code.alloc(total));
+  ea.offset = off.p;
+  ea.rec_e = rec_e.p;
+  ea.rec_code = rec_code.p;
+  HIP_TRY(c, launch_rec_enum(ea, true, c->stream));
+  HIP_TRY(c, d_t.alloc(n_t));
+  HIP_TRY(c, d_num.alloc(n_t));
+  HIP_TRY(c, d_den.alloc(n_t));
+  HIP_TRY(c, hipMemcpyAsync(d_t.p, t, n_t * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  RecSumArgs sa{};
+  sa.tab = c->d_tab.p;
+  sa.lev = c->d_lev.p;
+  sa.species = sp;
+  sa.de = de;
+  sa.a = 2.5 - omega;
+  sa.lgamma_a = std::lgamma(sa.a);
+  sa.t = d_t.p;
+  sa.rec_e = rec_e.p;
+  sa.rec_code = rec_code.p;
+  sa.n_rec = total;
+  sa.num = d_num.p;
+  sa.den = d_den.p;
+  HIP_TRY(c, launch_rec_sum(sa, n_t, std::max<size_t>(n_sl, 1) * sizeof(double), c->stream));
+  HIP_TRY(c, hipEventRecord(e1, c->stream));
+  std::vector<double> num(n_t), den(n_t);
+  HIP_TRY(c, hipMemcpyAsync(num.data(), d_num.p, n_t * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(den.data(), d_den.p, n_t * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  float el = 0.0f;
+  HIP_TRY(c, hipEventElapsedTime(&el, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (uint32_t i = 0; i < n_t; ++i) p[i] = num[i] / den[i];
+  if (ms) *ms = el;
+  if (n_rec) *n_rec = total;
+  return HCAO_OK;
+}
+
 void build_recombination_table(const hcao_ctx *c, const hcao_reaction_desc &d, const Tables &T,
-                               std::vector<double> &out) {
+                               std::vector<double> &out, const std::vector<std::pair<double, std::vector<double>>> &exact) {
   const SpeciesHost &B = c->species[d.reactant[0]], &C = c->species[d.reactant[1]], &A = c->species[d.product[0]];
   uint32_t j = 0;
   while (!((d.stretch_mask >> j) & 1ull)) ++j;
@@ -597,7 +698,10 @@ void build_recombination_table(const hcao_ctx *c, const hcao_reaction_desc &d, c
       const double mred = (A.d.mass_kg * M.mass_kg) / (A.d.mass_kg + M.mass_kg);
       const double delta = ((uint32_t)d.product[0] == m) ? 2.0 : 1.0;
       if (w != p_w) {
-        p = wr_forward(A, de, w, n_samp, t);
+        p = -1.0;
+        for (const auto &ex : exact)
+          if (ex.first == w) p = ex.second[i];
+        if (p < 0.0) p = wr_forward(A, de, w, n_samp, t);
         p_w = w;
       }
       const double kf =
@@ -731,6 +835,7 @@ hcao_status hcao_add_reaction(hcao_ctx *c, const hcao_reaction_desc *d, int32_t 
   if (c->finalized) return fail(c, HCAO_ESTATE, "add_reaction after finalize");
   if (c->reactions.size() >= (size_t)kMaxReactions) return fail(c, HCAO_EINVAL, "too many reactions");
   if (d->gamma_rot != 0.0) return fail(c, HCAO_EUNSUPPORTED, "rotation coupling needs rotational modes");
+  if (d->rec_model != HCAO_REC_WR && d->rec_model != HCAO_REC_EXACT) return fail(c, HCAO_EINVAL, "unknown recombination model");
   const int ns = (int)c->species.size();
   auto ok = [&](int s) { return s >= 0 && s < ns; };
   ReactionHost r;
@@ -938,7 +1043,34 @@ hcao_status hcao_finalize(hcao_ctx *c) {
       R.dh = c->species[a].d.formation_J - (c->species[b].d.formation_J + c->species[cc].d.formation_J);
       R.rec_off = c->rec_host.size();
       T.has_recomb = 1;
-      build_recombination_table(c, h.d, T, c->rec_host);
+      // Eq. recomb-correct on the device, one probability curve per omega of
+      // the (A, third body) pairs
+      std::vector<std::pair<double, std::vector<double>>> exact;
+      if (h.d.rec_model == HCAO_REC_EXACT) {
+        HIP_TRY(c, c->d_tab.alloc(1));
+        HIP_TRY(c, c->d_lev.alloc(c->lev_host.size()));
+        HIP_TRY(c, hipMemcpyAsync(c->d_tab.p, &T, sizeof(Tables), hipMemcpyHostToDevice, c->stream));
+        if (!c->lev_host.empty())
+          HIP_TRY(c, hipMemcpyAsync(c->d_lev.p, c->lev_host.data(), c->lev_host.size() * sizeof(double),
+                                    hipMemcpyHostToDevice, c->stream));
+        const SpeciesHost &A = c->species[a];
+        uint32_t jb = 0;
+        while (!((h.d.stretch_mask >> jb) & 1ull)) ++jb;
+        std::vector<double> temps(kRecNodes);
+        for (uint32_t i = 0; i < kRecNodes; ++i) temps[i] = std::exp(T.rec_l0 + (double)i / T.rec_inv_step);
+        for (uint32_t m = 0; m < T.n_species; ++m) {
+          const double w = (A.d.omega + c->species[m].d.omega) * 0.5;
+          bool have = false;
+          for (const auto &ex : exact) have = have || ex.first == w;
+          if (have) continue;
+          std::vector<double> pr(kRecNodes);
+          const hcao_status st = exact_rec_probability(c, (uint32_t)a, A.de[jb], w, kRecNodes, temps.data(),
+                                                       pr.data(), nullptr, nullptr);
+          if (st) return st;
+          exact.emplace_back(w, pr);
+        }
+      }
+      build_recombination_table(c, h.d, T, c->rec_host, exact);
     } else if (h.d.kind == HCAO_RX_DISSOCIATION) {
       const int a = h.d.reactant[0], pc = h.d.product[0], pd = h.d.product[1];
       R.a = a;
@@ -1583,6 +1715,15 @@ hcao_status hcao_get_recombination_table(const hcao_ctx *c, uint32_t reaction, d
   for (uint32_t i = 0; i < n && i < max_n; ++i) out[i] = c->rec_host[R.rec_off + i];
   if (n_out) *n_out = n;
   return HCAO_OK;
+}
+
+hcao_status hcao_recombination_exact(hcao_ctx *c, uint32_t species, double de_J, double omega, uint32_t n_t,
+                                     const double *t_K, double *p_out, double *elapsed_ms, uint64_t *n_records) {
+  if (!c || !c->finalized || species >= c->species.size() || (n_t && (!t_K || !p_out))) return HCAO_EINVAL;
+  for (uint32_t i = 0; i < n_t; ++i)
+    if (!(t_K[i] > 0.0)) return fail(c, HCAO_EINVAL, "temperatures must be positive");
+  if (c->species[species].n_modes == 0) return fail(c, HCAO_EINVAL, "species has no vibrational modes");
+  return exact_rec_probability(c, species, de_J, omega, n_t, t_K, p_out, elapsed_ms, n_records);
 }
 
 hcao_status hcao_get_exact_beta(const hcao_ctx *c, uint32_t species, uint32_t partner, double e_J, double *beta) {

@@ -121,4 +121,43 @@ struct StepArgs {
   double dt;
 };
 
+// Forward recombination probability summed over every level combination of
+// a species (Eq. recomb-correct). Enumeration pass: thread i takes prefix i
+// of the levels of the first n_prefix_modes modes (mixed radix over box[])
+// and walks the remaining modes depth first, emitting one record per
+// combination below de (a leaf: energy above ground, code kRecLeaf) and one
+// per point where the walk first crosses de at mode m, level j (energy of
+// that partial combination, code m | j << 8). With offset == null it only
+// counts a thread's records into count[i].
+constexpr uint32_t kRecLeaf = 0xFFu;
+
+struct RecEnumArgs {
+  const Tables *tab;
+  const double *lev;
+  uint32_t species, n_prefix_modes;
+  uint32_t box[kMaxModes];
+  uint64_t n_prefix;
+  double de;
+  uint32_t *count;
+  const uint64_t *offset;
+  double *rec_e;
+  uint32_t *rec_code;
+};
+
+// Sum pass: block b evaluates temperature t[b]; leaves contribute
+// Q(a, (de - e)/kT) exp(-e/kT), crossings exp(-e/kT) times the Boltzmann sum
+// of the crossing mode's levels from j up (relative to level j) times the
+// partition sums of the later modes. num[b] / den[b] is the probability.
+struct RecSumArgs {
+  const Tables *tab;
+  const double *lev;
+  uint32_t species;
+  double de, a, lgamma_a;
+  const double *t;
+  const double *rec_e;
+  const uint32_t *rec_code;
+  uint64_t n_rec;
+  double *num, *den;
+};
+
 }  // namespace hcao

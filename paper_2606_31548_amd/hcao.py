@@ -47,7 +47,8 @@ class hcao_species_desc(ctypes.Structure):
 
 class hcao_reaction_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("reactant", _i32 * 2), ("product", _i32 * 2), ("stretch_mask", _u64),
-                ("alpha", _pd), ("steric", _d), ("Ea_J", _d), ("gamma_rot", _d), ("n_samp", _u32)]
+                ("alpha", _pd), ("steric", _d), ("Ea_J", _d), ("gamma_rot", _d), ("n_samp", _u32),
+                ("rec_model", ctypes.c_int)]
 
 
 class hcao_moments(ctypes.Structure):
@@ -108,6 +109,7 @@ def load_library():
     L.hcao_get_pair.argtypes = [_vp, _u32, _u32, _vp]
     L.hcao_get_recombination_table.argtypes = [_vp, _u32, _vp, _u32, ctypes.POINTER(_u32)]
     L.hcao_get_exact_beta.argtypes = [_vp, _u32, _u32, _d, ctypes.POINTER(_d)]
+    L.hcao_recombination_exact.argtypes = [_vp, _u32, _d, _d, _u32, _vp, _vp, ctypes.POINTER(_d), ctypes.POINTER(_u64)]
     L.hcao_set_timing.argtypes = [_vp, ctypes.c_int]
     L.hcao_kernel_time.argtypes = [_vp, ctypes.POINTER(_d), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]
     L.hcao_save.argtypes = [_vp, ctypes.c_char_p]
@@ -123,7 +125,7 @@ def load_library():
                  "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
                  "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore",
                  "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
-                 "hcao_read_cell_particles", "hcao_get_exact_beta"):
+                 "hcao_read_cell_particles", "hcao_get_exact_beta", "hcao_recombination_exact"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -219,7 +221,7 @@ class Simulation:
         al = None if rx.alpha is None else np.asarray(rx.alpha, np.float64)
         self._keep.append(al)
         d = hcao_reaction_desc(rx.kind, (_i32 * 2)(*rx.reactant), (_i32 * 2)(*rx.product), int(rx.stretch_mask),
-                               _dp(al), rx.steric, rx.Ea_J, 0.0, getattr(rx, "n_samp", 0))
+                               _dp(al), rx.steric, rx.Ea_J, 0.0, getattr(rx, "n_samp", 0), getattr(rx, "rec_model", 0))
         i = _i32()
         self._chk("hcao_add_reaction", self._L.hcao_add_reaction(self._h, ctypes.byref(d), ctypes.byref(i)))
         self.n_reactions += 1
@@ -351,6 +353,15 @@ class Simulation:
         self._chk("hcao_get_exact_beta", self._L.hcao_get_exact_beta(self._h, species, partner, float(e_J),
                                                                       ctypes.byref(b)))
         return b.value
+
+    def recombination_exact(self, species, de_J, omega, temps):
+        """Eq. recomb-correct on the device: (probabilities, device ms, records)."""
+        t = np.ascontiguousarray(temps, np.float64)
+        p = np.zeros_like(t)
+        ms, nrec = _d(), _u64()
+        self._chk("hcao_recombination_exact", self._L.hcao_recombination_exact(
+            self._h, species, float(de_J), float(omega), len(t), _p(t), _p(p), ctypes.byref(ms), ctypes.byref(nrec)))
+        return p, ms.value, nrec.value
 
     def recombination_table(self, reaction):
         out = np.zeros(self.n_species * 1024, np.float64)

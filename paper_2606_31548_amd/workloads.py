@@ -28,6 +28,7 @@ EV = 1.602176634e-19
 
 SAMPLER_AUTO, SAMPLER_JOINT, SAMPLER_GIBBS, SAMPLER_EXACT = 0, 1, 2, 3
 RX_DISSOCIATION, RX_EXCHANGE, RX_RECOMBINATION = 0, 1, 2
+REC_WR, REC_EXACT = 0, 1
 
 VOLUME = 4.64e-6
 DENSITY = 1e22
@@ -72,6 +73,7 @@ class Reaction:
     steric: float = 1.0
     Ea_J: float = 0.0
     n_samp: int = 1000
+    rec_model: int = REC_WR
 
 
 @dataclass

@@ -61,7 +61,12 @@ def lib():
         L.orc_add_species.argtypes = [vp, d, d, d, d, u32, vp, u32, vp, vp, vp, vp, vp, d, d, ctypes.c_int]
         L.orc_add_reaction.argtypes = [vp, ctypes.c_int, vp, vp, u64, vp, d, d, u32]
         L.orc_finalize.argtypes = [vp]
-        L.orc_load.argtypes = [vp, u64, vp, vp, vp, vp]
+        L.orc_load.argtypes = [vp, u64, vp, vp, vp, vp, vp]
+        L.orc_set_rotation.argtypes = [vp, u32, u32, d]; L.orc_set_rotation.restype = ctypes.c_int
+        L.orc_set_gamma_rot.argtypes = [vp, u32, d]; L.orc_set_gamma_rot.restype = ctypes.c_int
+        L.orc_read_rot.argtypes = [vp, u32, vp]; L.orc_read_rot.restype = ctypes.c_int
+        L.orc_rot_energy.argtypes = [vp, u32, vp]; L.orc_rot_energy.restype = ctypes.c_int
+        L.orc_collide_rot_batch.argtypes = [vp, u32] + [vp] * 13; L.orc_collide_rot_batch.restype = ctypes.c_int
         L.orc_init_thermal.argtypes = [vp, vp, vp, vp]
         L.orc_step.argtypes = [vp, d, u32]
         L.orc_max_modes.argtypes = [vp]; L.orc_max_modes.restype = u32
@@ -198,6 +203,8 @@ class Oracle:
             self._h, sp.mass_kg, sp.dref_m, sp.omega, sp.Tref_K, len(th), _p(th) if len(th) else None,
             len(we), _p(we) if len(we) else None, _p(xe) if len(xe) else None, _p(de) if len(de) else None,
             _p(nl), _p(lv), sp.formation_J, sp.p_vib, sp.sampler))
+        if getattr(sp, "zeta_rot", 0):
+            _chk("orc_set_rotation", lib().orc_set_rotation(self._h, self.n_species, int(sp.zeta_rot), float(sp.p_rot)))
         self.n_species += 1
         return self.n_species - 1
 
@@ -207,6 +214,8 @@ class Oracle:
         al = None if rx.alpha is None else np.asarray(rx.alpha, np.float64)
         _chk("orc_add_reaction", lib().orc_add_reaction(self._h, rx.kind, _p(r), _p(p), int(rx.stretch_mask),
                                                         _p(al), rx.steric, rx.Ea_J, int(getattr(rx, "n_samp", 0))))
+        if getattr(rx, "gamma_rot", 0.0):
+            _chk("orc_set_gamma_rot", lib().orc_set_gamma_rot(self._h, self.n_reactions, float(rx.gamma_rot)))
         self.n_reactions += 1
         return self.n_reactions - 1
 
@@ -214,12 +223,23 @@ class Oracle:
         _chk("orc_finalize", lib().orc_finalize(self._h))
         self.max_modes = lib().orc_max_modes(self._h)
 
-    def load(self, cell, species, vel, levels):
+    def load(self, cell, species, vel, levels, rot=None):
         cell = np.ascontiguousarray(cell, np.uint32)
         species = np.ascontiguousarray(species, np.uint8)
         vel = np.ascontiguousarray(vel, np.float64)
         levels = np.ascontiguousarray(levels, np.uint16)
-        _chk("orc_load", lib().orc_load(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels)))
+        rot = None if rot is None else np.ascontiguousarray(rot, np.float64)
+        _chk("orc_load", lib().orc_load(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels), _p(rot)))
+
+    def read_rot(self, cell):
+        out = np.zeros(self.count(cell), np.float64)
+        _chk("orc_read_rot", lib().orc_read_rot(self._h, cell, _p(out)))
+        return out
+
+    def rot_energy(self, cell):
+        out = np.zeros(self.n_species, np.float64)
+        _chk("orc_rot_energy", lib().orc_rot_energy(self._h, cell, _p(out)))
+        return out
 
     def init_thermal(self, counts, t_trans, t_vib):
         counts = np.ascontiguousarray(counts, np.uint32)
@@ -371,6 +391,25 @@ class Oracle:
         _chk("orc_collide_batch", lib().orc_collide_batch(self._h, n, _p(sp), _p(vel), _p(lvl), _p(sp_o), _p(vel_o),
                                                           _p(lvl_o), _p(rx), _p(bsp), _p(bvel), _p(blvl)))
         return sp_o, vel_o, lvl_o, rx, bsp, bvel, blvl
+
+    def collide_rot_batch(self, sp, vel, lvl, rot):
+        """collide_batch with rotational energies: returns also rot out and the
+        newborns' rotational energies."""
+        sp = np.ascontiguousarray(sp, np.uint8)
+        n = len(sp) // 2
+        vel = np.ascontiguousarray(vel, np.float64)
+        lvl = np.ascontiguousarray(lvl, np.uint16)
+        rot = np.ascontiguousarray(rot, np.float64)
+        sp_o, vel_o, lvl_o, rot_o = np.zeros_like(sp), np.zeros_like(vel), np.zeros_like(lvl), np.zeros_like(rot)
+        rx = np.zeros(n, np.int32)
+        bsp = np.zeros(n, np.uint8)
+        bvel = np.zeros((n, 3), np.float64)
+        blvl = np.zeros((n, self.max_modes), np.uint16)
+        brot = np.zeros(n, np.float64)
+        _chk("orc_collide_rot_batch", lib().orc_collide_rot_batch(
+            self._h, n, _p(sp), _p(vel), _p(lvl), _p(rot), _p(sp_o), _p(vel_o), _p(lvl_o), _p(rot_o), _p(rx),
+            _p(bsp), _p(bvel), _p(blvl), _p(brot)))
+        return sp_o, vel_o, lvl_o, rot_o, rx, bsp, bvel, blvl, brot
 
 
 def from_workload(wl, seed=None, capacity_per_cell=0):

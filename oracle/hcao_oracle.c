@@ -258,6 +258,8 @@ typedef struct {
   double zpe;
   double formation;
   double p_vib;
+  uint32_t zeta_rot;           /* rotational degrees of freedom: 0, 2 or 3 */
+  double p_rot;                /* rotational relaxation probability per collision */
   int sampler;                 /* resolved: JOINT, GIBBS or EXACT */
   int concave[ORC_MAX_MODES]; /* level spacings never increase (bends, Morse stretches) */
 } species_t;
@@ -279,6 +281,7 @@ typedef struct {
   double dh;   /* sum of formation energies of products minus reactants */
   double zsum; /* dissociation: ZPE_A + ZPE_B + ZPE_C */
   uint32_t n_samp;
+  double gamma_rot; /* degree of rotation coupling in the collision energy (Sec. Rotation coupling) */
   double *rec; /* recombination: [third-body species][REC_NT] k_b / <sigma g>_BC  [m^3] */
 } reaction_t;
 
@@ -287,6 +290,7 @@ typedef struct {
   double *vx, *vy, *vz;
   uint8_t *sp;
   uint16_t *lvl; /* n x max_modes, row major */
+  double *rot;   /* rotational energy [J] */
   double volume, weight, sgmax, rem;
   uint64_t ctr[ORC_N_CTR];
 } cell_t;
@@ -294,7 +298,7 @@ typedef struct {
 struct orc_ctx {
   uint64_t seed;
   uint32_t n_cells, cap_default, step, finalized, loaded;
-  uint32_t n_species, n_reactions, max_modes, has_recomb;
+  uint32_t n_species, n_reactions, max_modes, has_recomb, has_rot;
   double rec_l0, rec_inv_step; /* log(REC_TMIN), (REC_NT - 1) / log(REC_TMAX / REC_TMIN) */
   species_t sp[ORC_MAX_SPECIES];
   reaction_t rx[ORC_MAX_REACTIONS];
@@ -348,9 +352,11 @@ static void free_cell(cell_t *c) {
   free(c->vz);
   free(c->sp);
   free(c->lvl);
+  free(c->rot);
   c->vx = c->vy = c->vz = NULL;
   c->sp = NULL;
   c->lvl = NULL;
+  c->rot = NULL;
 }
 
 void orc_destroy(orc_ctx *o) {
@@ -476,6 +482,29 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
     return E_INVAL;
   if (s->n_modes > o->max_modes) o->max_modes = s->n_modes;
   o->n_species += 1;
+  return E_OK;
+}
+
+/* Rotational mode of a species (reading R-A): zeta rotational degrees of
+ * freedom (0 none, 2 linear, 3 nonlinear rotor), relaxed with probability
+ * p_rot per non-reactive collision. Before finalize. */
+int orc_set_rotation(orc_ctx *o, uint32_t species, uint32_t zeta, double p_rot) {
+  if (!o || o->finalized) return E_STATE;
+  if (species >= o->n_species || !(zeta == 0 || zeta == 2 || zeta == 3)) return E_INVAL;
+  if (!(p_rot >= 0.0) || !(p_rot <= 1.0)) return E_INVAL;
+  o->sp[species].zeta_rot = zeta;
+  o->sp[species].p_rot = p_rot;
+  if (zeta > 0) o->has_rot = 1;
+  return E_OK;
+}
+
+/* Degree of rotation coupling gamma in [0, 1] of a dissociation or exchange
+ * (Sec. Rotation coupling). Before finalize. */
+int orc_set_gamma_rot(orc_ctx *o, uint32_t reaction, double gamma) {
+  if (!o || o->finalized) return E_STATE;
+  if (reaction >= o->n_reactions || !(gamma >= 0.0) || !(gamma <= 1.0)) return E_INVAL;
+  if (o->rx[reaction].kind == ORC_RX_RECOMBINATION && gamma != 0.0) return E_INVAL;
+  o->rx[reaction].gamma_rot = gamma;
   return E_OK;
 }
 
@@ -819,7 +848,8 @@ static int alloc_cell(orc_ctx *o, cell_t *c, uint32_t cap) {
   c->vz = (double *)calloc(cap ? cap : 1, sizeof(double));
   c->sp = (uint8_t *)calloc(cap ? cap : 1, 1);
   c->lvl = (uint16_t *)calloc((size_t)(cap ? cap : 1) * mm, sizeof(uint16_t));
-  if (!c->vx || !c->vy || !c->vz || !c->sp || !c->lvl) return E_NOMEM;
+  c->rot = (double *)calloc(cap ? cap : 1, sizeof(double));
+  if (!c->vx || !c->vy || !c->vz || !c->sp || !c->lvl || !c->rot) return E_NOMEM;
   return E_OK;
 }
 
@@ -870,7 +900,7 @@ static int check_particle(const orc_ctx *o, uint32_t sp, const double *v, const 
 
 /* Stable placement of particles into their cells (a counting sort by cell). */
 int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *species, const double *vel,
-             const uint16_t *levels) {
+             const uint16_t *levels, const double *rot) {
   if (!o || !o->finalized) return E_STATE;
   uint32_t mm = o->max_modes;
   uint32_t *count = (uint32_t *)calloc(o->n_cells, sizeof(uint32_t));
@@ -881,6 +911,8 @@ int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *specie
       return E_INVAL;
     }
     int rc = check_particle(o, species[i], vel + 3 * i, levels + (size_t)i * mm);
+    if (!rc && rot && !(rot[i] >= 0.0 && isfinite(rot[i]) && (rot[i] == 0.0 || o->sp[species[i]].zeta_rot > 0)))
+      rc = E_INVAL;
     if (rc) {
       free(count);
       return rc;
@@ -908,6 +940,7 @@ int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *specie
     c->vy[j] = vel[3 * i + 1];
     c->vz[j] = vel[3 * i + 2];
     c->sp[j] = species[i];
+    c->rot[j] = rot ? rot[i] : 0.0;
     for (uint32_t m = 0; m < mm; ++m) c->lvl[(size_t)j * mm + m] = levels[(size_t)i * mm + m];
   }
   for (uint32_t c = 0; c < o->n_cells; ++c) init_sgmax(o, &o->cells[c]);
@@ -930,7 +963,10 @@ static void polar_normals(stream *st, double *n1, double *n2) {
   *n2 = y * f;
 }
 
-/* Thermal initial state. Velocities: Maxwellian at T_trans. Bends: the floor
+/* Thermal initial state. Rotational energy (species with a rotor, after the
+ * levels): Boltzmann at T_rot = T_trans, Gamma(zeta/2, k T): zeta = 2 takes
+ * -ln(1 - u), zeta = 3 adds half the square of one polar normal.
+ * Velocities: Maxwellian at T_trans. Bends: the floor
  * form of the initialization section (i = floor(-ln r T_vib / Theta), r in (0,1]).
  * Stretches: uniform proposal over 0..i_diss accepted with
  * exp(-(E_i - E_0)/(k T_vib)) (Eq. accept-quant; proposal range read as
@@ -986,6 +1022,16 @@ int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, 
               }
             }
           }
+        }
+        C->rot[slot] = 0.0;
+        if (S->zeta_rot > 0) {
+          double g = -orc_detlog(1.0 - uniform(&st));
+          if (S->zeta_rot == 3) {
+            double z1, z2;
+            polar_normals(&st, &z1, &z2);
+            g = g + 0.5 * (z1 * z1);
+          }
+          C->rot[slot] = (K_BOLTZ * t_trans[c]) * g;
         }
         slot += 1;
       }
@@ -1317,6 +1363,7 @@ typedef struct {
   double v[2][3];
   uint8_t sp[2];
   uint16_t lvl[2][ORC_MAX_MODES];
+  double rot[2];
   int dead[2];
   int has_m;   /* a third body is available for recombination */
   uint8_t sp_m;
@@ -1329,7 +1376,23 @@ typedef struct {
   uint8_t sp;
   double v[3];
   uint16_t lvl[ORC_MAX_MODES];
+  double rot;
 } newborn;
+
+/* Rotational Larsen-Borgnakke share (reading R-B): the fraction f of the
+ * pooled energy E_tr + E_rot that the rotor keeps has density proportional to
+ * f^(zeta/2 - 1) (1 - f)^q, q = 3/2 - omega the exponent of the vibrational
+ * sampler. zeta = 2: inversion, f = 1 - (1 - u)^(1/(q+1)). zeta = 3: rejection
+ * from the uniform, accepted with (f/f*)^(1/2) ((1 - f)/(1 - f*))^q, f* = 1/(1 + 2q)
+ * the mode. */
+static double rot_fraction(uint32_t zeta, double q, stream *st) {
+  if (zeta == 2) return 1.0 - orc_detpow(1.0 - uniform(st), 1.0 / (q + 1.0));
+  double fs = 1.0 / (1.0 + 2.0 * q);
+  for (;;) {
+    double f = uniform(st), u2 = uniform(st);
+    if (u2 < orc_detpow(f / fs, 0.5) * orc_detpow((1.0 - f) / (1.0 - fs), q)) return f;
+  }
+}
 
 typedef struct {
   int kind, rx, a_side, mode;
@@ -1375,6 +1438,9 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
     const pair_t *pam = &o->pr[R->c][ps->sp_m];
     double e_am = pam->hm * ((gx * gx + gy * gy) + gz * gz);
     double pool = (((e_am + e_tr) + evib[b]) + evib[c]) - R->dh;
+    /* rotation of B and C: kept by A's rotor, else pooled (reading R-D) */
+    double rsum = ps->rot[b] + ps->rot[c];
+    if (A->zeta_rot == 0) pool = pool + rsum;
     double et = pool - A->zpe;
     if (!(et > 0.0)) {
       if (ctr) ctr[ORC_CTR_SUPPRESSED] += 1;
@@ -1390,6 +1456,8 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
     memcpy(ps->v_m, vm, sizeof(vm));
     ps->sp[b] = (uint8_t)R->c;
     memcpy(ps->lvl[b], la, sizeof(la));
+    ps->rot[b] = A->zeta_rot > 0 ? rsum : 0.0;
+    ps->rot[c] = 0.0;
     ps->dead[c] = 1;
     if (ctr) {
       ctr[ORC_CTR_TRIALS] += t;
@@ -1412,10 +1480,12 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
       for (uint32_t j = 0; j < SA->n_stretch; ++j) {
         if (!((R->mask >> j) & 1ULL)) continue;
         uint32_t m = SA->n_bend + j;
-        /* Eq. Ecoll-diss: E_tr + E_vib,A - sum of ZPE over A, B, C + E_A,j(0) */
-        double ecoll = ((e_tr + evib[side]) - R->zsum) + SA->lev[m][0];
+        /* Eq. Ecoll-diss (with rotation coupling): E_tr + gamma E_rot,A + E_vib,A
+         * - sum of ZPE over A, B, C + E_A,j(0) */
+        double grot = R->gamma_rot * ps->rot[side];
+        double ecoll = (((e_tr + grot) + evib[side]) - R->zsum) + SA->lev[m][0];
         double eex = ecoll - SA->de[m];
-        double pool = (e_tr + evib[side]) - R->dh;
+        double pool = ((e_tr + grot) + evib[side]) - R->dh;
         double left = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
         if (eex > 0.0 && left > 0.0 && nch < MAX_CHANNELS) {
           ch[nch].kind = ORC_RX_DISSOCIATION;
@@ -1435,12 +1505,13 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
       if (R->kind != ORC_RX_EXCHANGE || R->a != A || R->b != B) continue;
       double us = uniform(st);
       const species_t *SA = &o->sp[A];
-      /* Eq. Ecoll-exch: E_tr + sum_j alpha_j E_vib,A,j */
-      double ecoll = e_tr;
+      /* Eq. Ecoll-exch (with rotation coupling): E_tr + gamma E_rot,A + sum_j alpha_j E_vib,A,j */
+      double grot = R->gamma_rot * ps->rot[side];
+      double ecoll = e_tr + grot;
       for (uint32_t m = 0; m < SA->n_modes; ++m)
         ecoll = ecoll + R->alpha[m] * mode_energy(SA, m, ps->lvl[side][m]);
       double eex = ecoll - R->ea;
-      double pool = ((e_tr + evib[side]) + evib[1 - side]) - R->dh;
+      double pool = (((e_tr + grot) + evib[side]) + evib[1 - side]) - R->dh;
       double left = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
       if (us < R->steric && eex > 0.0 && left > 0.0 && nch < MAX_CHANNELS) {
         ch[nch].kind = ORC_RX_EXCHANGE;
@@ -1477,8 +1548,15 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
     if (R->kind == ORC_RX_DISSOCIATION) {
       /* A + M -> B + C + M: B takes A's slot, C is new. */
       int spA = ps->sp[a], spM = ps->sp[b];
-      double pool = (e_tr + evib[a]) - R->dh;
+      double grot = R->gamma_rot * ps->rot[a];
+      double pool = ((e_tr + grot) + evib[a]) - R->dh;
       double et = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
+      /* the rotation not coupled in stays with B's rotor, else is pooled */
+      double keep = ps->rot[a] - grot;
+      if (o->sp[R->c].zeta_rot == 0) {
+        et = et + keep;
+        keep = 0.0;
+      }
       uint16_t lb[ORC_MAX_MODES] = {0}, lc[ORC_MAX_MODES] = {0};
       int capped = 0;
       uint64_t t = 0;
@@ -1512,9 +1590,11 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
       }
       ps->sp[a] = (uint8_t)R->c;
       memcpy(ps->lvl[a], lb, sizeof(lb));
+      ps->rot[a] = keep;
       nb->born = 1;
       nb->sp = (uint8_t)R->d;
       memcpy(nb->lvl, lc, sizeof(lc));
+      nb->rot = 0.0;
       if (ctr) {
         ctr[ORC_CTR_TRIALS] += t;
         ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
@@ -1524,8 +1604,19 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
     } else {
       /* A + B -> C + D: C takes A's slot, D takes B's slot. */
       int spA = ps->sp[a], spB = ps->sp[b];
-      double pool = ((e_tr + evib[a]) + evib[b]) - R->dh;
+      double grot = R->gamma_rot * ps->rot[a];
+      double pool = (((e_tr + grot) + evib[a]) + evib[b]) - R->dh;
       double et = (pool - o->sp[R->c].zpe) - o->sp[R->d].zpe;
+      /* A's uncoupled rotation goes to C's rotor, B's to D's; else pooled */
+      double keep_c = ps->rot[a] - grot, keep_d = ps->rot[b];
+      if (o->sp[R->c].zeta_rot == 0) {
+        et = et + keep_c;
+        keep_c = 0.0;
+      }
+      if (o->sp[R->d].zeta_rot == 0) {
+        et = et + keep_d;
+        keep_d = 0.0;
+      }
       uint16_t lc[ORC_MAX_MODES] = {0}, ld[ORC_MAX_MODES] = {0};
       double qcd = o->pr[R->c][R->d].q;
       int capped = 0;
@@ -1545,6 +1636,8 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
       ps->sp[b] = (uint8_t)R->d;
       memcpy(ps->lvl[a], lc, sizeof(lc));
       memcpy(ps->lvl[b], ld, sizeof(ld));
+      ps->rot[a] = keep_c;
+      ps->rot[b] = keep_d;
       if (ctr) {
         ctr[ORC_CTR_TRIALS] += t;
         ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
@@ -1568,6 +1661,17 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
       ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
     }
   }
+  /* rotational relaxation of each rotor in turn (reading R-B) */
+  for (int x = 0; x < 2; ++x) {
+    const species_t *S = &o->sp[ps->sp[x]];
+    if (S->zeta_rot == 0) continue;
+    double u = uniform(st);
+    if (!(u < S->p_rot)) continue;
+    double ec = e_tr + ps->rot[x];
+    double f = rot_fraction(S->zeta_rot, pp->q, st);
+    ps->rot[x] = f * ec;
+    e_tr = ec - ps->rot[x];
+  }
   double vcm[3], va[3], vb[3];
   com(pp, ps->v[0], ps->v[1], vcm);
   split(pp, vcm, e_tr, st, va, vb);
@@ -1588,6 +1692,7 @@ static void load_pair(const cell_t *C, uint32_t mm, uint32_t p, uint32_t q, pair
     ps->v[x][1] = C->vy[i];
     ps->v[x][2] = C->vz[i];
     ps->sp[x] = C->sp[i];
+    ps->rot[x] = C->rot[i];
     for (uint32_t m = 0; m < mm; ++m) ps->lvl[x][m] = C->lvl[(size_t)i * mm + m];
   }
 }
@@ -1601,6 +1706,7 @@ static void store_pair(cell_t *C, uint32_t mm, uint32_t p, uint32_t q, const pai
     C->vz[i] = ps->v[x][2];
     C->sp[i] = ps->dead[x] ? (uint8_t)255 : ps->sp[x];
     for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)i * mm + m] = ps->lvl[x][m];
+    C->rot[i] = ps->rot[x];
   }
 }
 
@@ -1705,6 +1811,7 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
       C->vy[alive] = C->vy[i];
       C->vz[alive] = C->vz[i];
       C->sp[alive] = C->sp[i];
+      C->rot[alive] = C->rot[i];
       for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)alive * mm + m] = C->lvl[(size_t)i * mm + m];
     }
     ++alive;
@@ -1723,6 +1830,7 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     C->vy[j] = nb[k].v[1];
     C->vz[j] = nb[k].v[2];
     C->sp[j] = nb[k].sp;
+    C->rot[j] = nb[k].rot;
     for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)j * mm + m] = nb[k].lvl[m];
   }
   free(nb);
@@ -1761,6 +1869,22 @@ int orc_read_cell(const orc_ctx *o, uint32_t cell, uint8_t *species, double *vel
     vel[3 * i + 2] = C->vz[i];
     for (uint32_t m = 0; m < mm; ++m) levels[(size_t)i * mm + m] = C->lvl[(size_t)i * mm + m];
   }
+  return E_OK;
+}
+
+int orc_read_rot(const orc_ctx *o, uint32_t cell, double *rot) {
+  if (!o || cell >= o->n_cells) return E_INVAL;
+  const cell_t *C = &o->cells[cell];
+  for (uint32_t i = 0; i < C->n; ++i) rot[i] = C->rot[i];
+  return E_OK;
+}
+
+/* rotational energy of the cell's particles summed per species [J] */
+int orc_rot_energy(const orc_ctx *o, uint32_t cell, double *per_species) {
+  if (!o || cell >= o->n_cells) return E_INVAL;
+  const cell_t *C = &o->cells[cell];
+  for (uint32_t s = 0; s < o->n_species; ++s) per_species[s] = 0.0;
+  for (uint32_t i = 0; i < C->n; ++i) per_species[C->sp[i]] += C->rot[i];
   return E_OK;
 }
 
@@ -1936,13 +2060,23 @@ int orc_relax_chain(orc_ctx *o, uint32_t species, double q, int sampler, uint32_
 static int collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
                          uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
                          uint8_t *born_sp, double *born_vel, uint16_t *born_lvl, const uint8_t *m_sp, double *m_vel,
-                         double t_cell, double n_cell);
+                         double t_cell, double n_cell, const double *rot, double *rot_out, double *born_rot);
 
 int orc_collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
                       uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
                       uint8_t *born_sp, double *born_vel, uint16_t *born_lvl) {
   return collide_batch(o, n, sp, vel, lvl, sp_out, vel_out, lvl_out, reaction_out, born_sp, born_vel, born_lvl, NULL,
-                       NULL, 0.0, 0.0);
+                       NULL, 0.0, 0.0, NULL, NULL, NULL);
+}
+
+/* as orc_collide_batch, with rotational energies rot[2n] in, rot_out[2n] and
+ * born_rot[n] out */
+int orc_collide_rot_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
+                          const double *rot, uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, double *rot_out,
+                          int32_t *reaction_out, uint8_t *born_sp, double *born_vel, uint16_t *born_lvl,
+                          double *born_rot) {
+  return collide_batch(o, n, sp, vel, lvl, sp_out, vel_out, lvl_out, reaction_out, born_sp, born_vel, born_lvl, NULL,
+                       NULL, 0.0, 0.0, rot, rot_out, born_rot);
 }
 
 /* as orc_collide_batch, with a third body per item (m_sp[n], m_vel[3n] in and
@@ -1953,13 +2087,13 @@ int orc_collide3_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *
                        uint8_t *born_sp, double *born_vel, uint16_t *born_lvl, const uint8_t *m_sp, double *m_vel,
                        double t_cell, double n_cell) {
   return collide_batch(o, n, sp, vel, lvl, sp_out, vel_out, lvl_out, reaction_out, born_sp, born_vel, born_lvl, m_sp,
-                       m_vel, t_cell, n_cell);
+                       m_vel, t_cell, n_cell, NULL, NULL, NULL);
 }
 
 static int collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
                          uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,
                          uint8_t *born_sp, double *born_vel, uint16_t *born_lvl, const uint8_t *m_sp, double *m_vel,
-                         double t_cell, double n_cell) {
+                         double t_cell, double n_cell, const double *rot, double *rot_out, double *born_rot) {
   if (!o || !o->finalized) return E_INVAL;
   uint32_t mm = o->max_modes;
   for (uint32_t i = 0; i < n; ++i) {
@@ -1970,6 +2104,7 @@ static int collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double
       ps.sp[x] = sp[2 * i + x];
       for (int k = 0; k < 3; ++k) ps.v[x][k] = vel[6 * i + 3 * x + k];
       for (uint32_t m = 0; m < mm; ++m) ps.lvl[x][m] = lvl[((size_t)2 * i + x) * mm + m];
+      ps.rot[x] = rot ? rot[2 * i + x] : 0.0;
     }
     if (m_sp) {
       ps.has_m = 1;
@@ -1991,7 +2126,9 @@ static int collide_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double
       sp_out[2 * i + x] = ps.dead[x] ? (uint8_t)255 : ps.sp[x];
       for (int k = 0; k < 3; ++k) vel_out[6 * i + 3 * x + k] = ps.v[x][k];
       for (uint32_t m = 0; m < mm; ++m) lvl_out[((size_t)2 * i + x) * mm + m] = ps.lvl[x][m];
+      if (rot_out) rot_out[2 * i + x] = ps.dead[x] ? 0.0 : ps.rot[x];
     }
+    if (born_rot) born_rot[i] = nb.born ? nb.rot : 0.0;
     born_sp[i] = nb.born ? nb.sp : 255;
     for (int k = 0; k < 3; ++k) born_vel[3 * i + k] = nb.born ? nb.v[k] : 0.0;
     for (uint32_t m = 0; m < mm; ++m) born_lvl[(size_t)i * mm + m] = nb.born ? nb.lvl[m] : 0;

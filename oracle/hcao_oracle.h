@@ -65,9 +65,14 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
                     const double *levels, double formation, double p_vib, int sampler);
 int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int32_t product[2],
                      uint64_t stretch_mask, const double *alpha, double steric, double ea, uint32_t n_samp);
+/* rotational mode of a species: zeta in {0, 2, 3}, relaxation probability p_rot */
+int orc_set_rotation(orc_ctx *o, uint32_t species, uint32_t zeta, double p_rot);
+/* rotation coupling gamma in [0, 1] of a dissociation or exchange */
+int orc_set_gamma_rot(orc_ctx *o, uint32_t reaction, double gamma);
 int orc_finalize(orc_ctx *o);
+/* rot[n] (may be NULL: all zero) holds rotational energies [J] */
 int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *species, const double *vel,
-             const uint16_t *levels);
+             const uint16_t *levels, const double *rot);
 int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, const double *t_vib);
 int orc_step(orc_ctx *o, double dt, uint32_t n_steps);
 
@@ -76,6 +81,12 @@ uint32_t orc_max_modes(const orc_ctx *o);
 uint64_t orc_count(const orc_ctx *o, uint32_t cell);
 uint32_t orc_step_index(const orc_ctx *o);
 int orc_read_cell(const orc_ctx *o, uint32_t cell, uint8_t *species, double *vel, uint16_t *levels);
+int orc_read_rot(const orc_ctx *o, uint32_t cell, double *rot);
+int orc_rot_energy(const orc_ctx *o, uint32_t cell, double *per_species);
+int orc_collide_rot_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
+                          const double *rot, uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, double *rot_out,
+                          int32_t *reaction_out, uint8_t *born_sp, double *born_vel, uint16_t *born_lvl,
+                          double *born_rot);
 int orc_read_cell_state(const orc_ctx *o, uint32_t cell, double *sgmax, double *rem, uint64_t *ctr);
 int orc_levels(const orc_ctx *o, uint32_t species, uint32_t mode, double *out, uint32_t max_n);
 int orc_species_info(const orc_ctx *o, uint32_t species, double *zpe, uint32_t *n_modes,

@@ -53,6 +53,8 @@ class Species:
     formation_J: float = 0.0
     p_vib: float = 1.0
     sampler: int = SAMPLER_AUTO
+    zeta_rot: int = 0      # rotational degrees of freedom (0, 2 or 3)
+    p_rot: float = 0.2     # rotational relaxation probability per collision
     coupling: float = 0.0
     dref_m: float = VHS["dref_m"]
     omega: float = VHS["omega"]
@@ -74,6 +76,7 @@ class Reaction:
     Ea_J: float = 0.0
     n_samp: int = 1000
     rec_model: int = REC_WR
+    gamma_rot: float = 0.0  # degree of rotation coupling (dissociation, exchange)
 
 
 @dataclass

@@ -150,7 +150,13 @@ typedef struct {
  *     temperature, whose acceptance does not collapse with many modes
  *     (about 3 trials for 9 modes); AUTO = JOINT for 2 to 4 modes, GIBBS
  *     otherwise (for one mode both have the same target, and the sweep's
- *     proposal accepts more often). */
+ *     proposal accepts more often);
+ *   zeta_rot: rotational degrees of freedom (0: no rotor, 2: linear, 3:
+ *     nonlinear); the rotational energy is continuous, relaxed in each
+ *     non-reactive collision (after the vibrational relaxation) with
+ *     probability p_rot by the Larsen-Borgnakke rule: the rotor keeps a
+ *     share f of E_tr + E_rot with density f^(zeta/2-1) (1-f)^(3/2-omega);
+ *     thermal initialization draws it from Gamma(zeta/2, k T_trans). */
 typedef struct {
   double mass_kg, dref_m, omega, Tref_K;
   uint32_t n_bend;
@@ -163,6 +169,8 @@ typedef struct {
   double coupling;
   double p_vib;
   hcao_sampler sampler;
+  uint32_t zeta_rot;
+  double p_rot;
 } hcao_species_desc;
 
 /* One reaction (Sec. "Polyatomic QK reaction modeling").
@@ -186,7 +194,12 @@ typedef struct {
  *     of the section's forward-rate expression (VHS means of A and the third
  *     body) and K_eq from translational and vibrational partition sums. B
  *     takes A's slot; C is removed. m_A must equal m_B + m_C.
- *   gamma_rot must be 0 (no rotational modes are modelled). */
+ *   gamma_rot (Sec. "Rotation coupling"): degree of coupling in [0, 1];
+ *     dissociation and exchange add gamma E_rot,A to the collision energies
+ *     of Eqs. Ecoll-diss and Ecoll-exch and to the reaction's energy pool;
+ *     the rest of A's rotation stays with the product in A's slot, B's with
+ *     the product in B's slot (a product without a rotor pools it). Must be
+ *     0 for a recombination, which hands B's and C's rotation to A. */
 typedef struct {
   hcao_rx_kind kind;
   int32_t reactant[2];
@@ -215,8 +228,10 @@ typedef struct {
   double T_trans_K;
   double T_vib_K[HCAO_MAX_SPECIES];
   double E_defect_J; /* mixed form: energy owed to the particles by fp32 rounding, not yet
-                        returned (0 in HCAO_FP64); E_kin + sum (E_vib + N_s ZPE_s) + E_formation
-                        + E_defect is conserved to fp64 rounding */
+                        returned (0 in HCAO_FP64); E_kin + sum (E_vib + N_s ZPE_s + E_rot)
+                        + E_formation + E_defect is conserved to fp64 rounding */
+  double E_rot_J[HCAO_MAX_SPECIES]; /* sum of rotational energy */
+  double T_rot_K[HCAO_MAX_SPECIES]; /* 2 E_rot / (zeta k N_s) (0 without a rotor) */
 } hcao_moments;
 
 const char *hcao_status_string(hcao_status s);
@@ -230,17 +245,20 @@ hcao_status hcao_finalize(hcao_ctx *ctx);
 
 /* Loads n particles from host arrays in any order: cell[n] (< n_cells),
  * species[n], vel[3n] (x,y,z per particle), levels[n * max_modes].
- * Particles are placed by a stable counting sort on the device, so each
- * cell keeps the given relative order. Resets the step counter to 0 and
- * sets each cell's (sigma g)_max to an upper bound over its initial pairs. */
+ * rot[n] (may be NULL: none) rotational energies [J], >= 0 and 0 for
+ * species without a rotor. Particles are placed by a stable counting sort
+ * on the device, so each cell keeps the given relative order. Resets the
+ * step counter to 0 and sets each cell's (sigma g)_max to an upper bound
+ * over its initial pairs. */
 hcao_status hcao_load_particles(hcao_ctx *ctx, uint64_t n, const uint32_t *cell, const uint8_t *species,
-                                const double *vel, const uint16_t *levels);
+                                const double *vel, const uint16_t *levels, const double *rot);
 
 /* Thermal initial state on the device: counts[n_cells * n_species] particles
  * per cell and species (species-major within a cell), Maxwellian velocities
  * at t_trans[c] and vibrational levels at t_vib[c] (the paper's
  * initialization: bends by the floor form, stretches by Eq. accept-quant
- * with a proposal over 0..i_diss). */
+ * with a proposal over 0..i_diss) and rotational energies of rotors from
+ * Gamma(zeta/2, k t_trans[c]). */
 hcao_status hcao_init_thermal(hcao_ctx *ctx, const uint32_t *counts, const double *t_trans,
                               const double *t_vib);
 
@@ -297,6 +315,9 @@ uint32_t hcao_step_index(const hcao_ctx *ctx);
  * survivors in their previous order, then products born in pair order).
  * species[total], vel[3 total], levels[total * max_modes]. */
 hcao_status hcao_read_particles(hcao_ctx *ctx, uint8_t *species, double *vel, uint16_t *levels);
+/* Rotational energies [J] of every live particle, rot[total], in the order
+ * of hcao_read_particles (all 0 when no species has a rotor). */
+hcao_status hcao_read_rotational_energy(hcao_ctx *ctx, double *rot);
 
 /* The live particles of one cell in canonical order (for sampled checks of
  * large runs): writes min(count, max_n) particles into species[max_n],

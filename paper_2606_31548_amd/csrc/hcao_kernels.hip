@@ -714,6 +714,31 @@ __device__ __forceinline__ void zero_levels(uint16_t *lv, uint32_t stride, uint3
 
 // One colliding pair held on chip: velocities and species in registers,
 // quantum numbers in per-lane LDS slots (mode m of side x at lv_x[m * ls]).
+// Rotational Larsen-Borgnakke share: the fraction f of E_tr + E_rot that the
+// rotor keeps has density proportional to f^(zeta/2 - 1) (1 - f)^q:
+// zeta = 2 by inversion, f = 1 - (1 - u)^(1/(q+1)); zeta = 3 by rejection
+// from the uniform against the density over its value at the mode
+// f* = 1/(1 + 2q).
+template <bool MIX>
+__device__ double rot_fraction(uint32_t zeta, double q, RngT<MIX> &rng) {
+  if constexpr (MIX) {
+    const float qf = (float)q;
+    if (zeta == 2) return (double)(1.0f - pow_f(1.0f - rng.uniform_f(), 1.0f / (qf + 1.0f)));
+    const float fs = 1.0f / (1.0f + 2.0f * qf);
+    for (;;) {
+      const float f = rng.uniform_f(), u2 = rng.uniform_f();
+      if (u2 < pow_f(f / fs, 0.5f) * pow_f((1.0f - f) / (1.0f - fs), qf)) return (double)f;
+    }
+  } else {
+    if (zeta == 2) return 1.0 - dpow(1.0 - rng.uniform(), 1.0 / (q + 1.0));
+    const double fs = 1.0 / (1.0 + 2.0 * q);
+    for (;;) {
+      const double f = rng.uniform(), u2 = rng.uniform();
+      if (u2 < dpow(f / fs, 0.5) * dpow((1.0 - f) / (1.0 - fs), q)) return f;
+    }
+  }
+}
+
 template <bool MIX>
 struct PairLocal {
   using R = Real<MIX>;
@@ -733,6 +758,7 @@ struct PairLocal {
   double fold_used;  // mixed form: energy owed to the cell that joined this pair
   int32_t rec_i;  // recombination table node of the cell temperature (-1: below, -2: above)
   double rec_f;
+  double r0, r1, rn;  // rotational energies of p, q and the product (rotors only)
 };
 
 __device__ __forceinline__ double vib_local(const Tab &T, uint32_t sp, const uint16_t *lv, uint32_t ls) {
@@ -757,11 +783,11 @@ struct ChannelScan {
   bool found;
 };
 
-template <bool MIX>
+template <bool MIX, bool EX>
 __device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32_t sp1, double ev0, double ev1,
                                               const uint16_t *lv0, const uint16_t *lv1, uint32_t ls, double e_tr,
-                                              RngT<MIX> &rng, uint64_t &steric_ok, int pass, double target,
-                                              ChannelScan &S) {
+                                              double rot0, double rot1, RngT<MIX> &rng, uint64_t &steric_ok,
+                                              int pass, double target, ChannelScan &S) {
   double cum = 0.0;
   uint32_t seen = 0, ex_i = 0;
   for (uint32_t kind = 0; kind < 2; ++kind) {
@@ -778,10 +804,11 @@ __device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32
           for (uint32_t j = 0; j < nst; ++j) {
             if (!((R.mask >> j) & 1ull)) continue;
             const uint32_t m = SA.n_bend + j;
-            // Eq. Ecoll-diss: E_tr + E_vib,A - sum ZPE(A, B, C) + E_A,j(0)
-            const double ecoll = ((e_tr + evA) - R.zsum) + T.lev[SA.lev_off[m]];
+            // Eq. Ecoll-diss: E_tr (+ gamma E_rot,A) + E_vib,A - sum ZPE(A, B, C) + E_A,j(0)
+            const double etg = EX ? e_tr + R.gamma_rot * (side ? rot1 : rot0) : e_tr;
+            const double ecoll = ((etg + evA) - R.zsum) + T.lev[SA.lev_off[m]];
             const double eex = ecoll - SA.de[m];
-            const double pool = (e_tr + evA) - R.dh;
+            const double pool = (etg + evA) - R.dh;
             const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
             if (eex > 0.0 && left > 0.0 && seen < (uint32_t)kMaxChannels) {
               const Channel ch{(int32_t)r, (int32_t)side, (int32_t)m};
@@ -809,12 +836,13 @@ __device__ __forceinline__ void scan_channels(const Tab &T, uint32_t sp0, uint32
             st_ok = ex_i < 64 ? ((steric_ok >> ex_i) & 1ull) != 0 : false;
           }
           ++ex_i;
-          // Eq. Ecoll-exch: E_tr + sum_j alpha_j E_vib,A,j
-          double ecoll = e_tr;
+          // Eq. Ecoll-exch: E_tr (+ gamma E_rot,A) + sum_j alpha_j E_vib,A,j
+          const double etg = EX ? e_tr + R.gamma_rot * (side ? rot1 : rot0) : e_tr;
+          double ecoll = etg;
           for (uint32_t m = 0; m < SA.n_modes; ++m)
             ecoll = ecoll + R.alpha[m] * mode_energy(SA, T.lev, m, lA[m * ls]);
           const double eex = ecoll - R.ea;
-          const double pool = ((e_tr + evA) + evB) - R.dh;
+          const double pool = ((etg + evA) + evB) - R.dh;
           const double left = (pool - T.sp[R.c].zpe) - T.sp[R.d].zpe;
           if (st_ok && eex > 0.0 && left > 0.0 && seen < (uint32_t)kMaxChannels) {
             const Channel ch{(int32_t)r, (int32_t)side, -1};
@@ -906,7 +934,13 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     const double gx = (double)c3.x - (double)P.v_m.x, gy = (double)c3.y - (double)P.v_m.y,
                  gz = (double)c3.z - (double)P.v_m.z;
     const double e_am = T.pair(R.c, P.sp_m).hm * ((gx * gx + gy * gy) + gz * gz);
-    const double pool = (((e_am + e_tr0) + (sb ? ev1 : ev0)) + (sb ? ev0 : ev1)) - R.dh;
+    double pool = (((e_am + e_tr0) + (sb ? ev1 : ev0)) + (sb ? ev0 : ev1)) - R.dh;
+    double rsum = 0.0;
+    if constexpr (EX) {
+      // B's and C's rotation: kept by A's rotor, else pooled
+      rsum = (sb ? P.r1 : P.r0) + (sb ? P.r0 : P.r1);
+      if (T.sp[R.c].zeta_rot == 0) pool = pool + rsum;
+    }
     const double e_left = pool - T.sp[R.c].zpe;
     if (!(e_left > 0.0)) {
       atomicAdd(&C.ctr[HCAO_CTR_SUPPRESSED], 1ull);
@@ -917,6 +951,11 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     side = sb;
     vbc = c3;
     et = e_left;
+    if constexpr (EX) {
+      const double ra = T.sp[R.c].zeta_rot > 0 ? rsum : 0.0;
+      P.r0 = sb ? 0.0 : ra;
+      P.r1 = sb ? ra : 0.0;
+    }
   }
 
   // --- dissociation and exchange channels, competition by excess energy ---
@@ -927,24 +966,55 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     S.total = 0.0;
     S.found = false;
     S.first = S.last = S.pick = Channel{-1, 0, 0};
-    scan_channels<MIX>(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 0, 0.0, S);
+    scan_channels<MIX, EX>(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, P.r0, P.r1, rng, steric_ok, 0, 0.0, S);
     if (S.nch > 0) {
       Channel pick = S.first;
       if (S.nch > 1) {
         const double target = (double)draw<MIX>(rng) * S.total;
-        scan_channels<MIX>(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, rng, steric_ok, 1, target, S);
+        scan_channels<MIX, EX>(T, sp0, sp1, ev0, ev1, P.lv0, P.lv1, ls, e_tr0, P.r0, P.r1, rng, steric_ok, 1, target,
+                               S);
         pick = S.found ? S.pick : S.last;
       }
       const ReactionTab &R = T.rx[pick.rx];
       rx = pick.rx;
       side = (uint32_t)pick.side;
       const double eva = side ? ev1 : ev0, evb = side ? ev0 : ev1;
+      const double ra = side ? P.r1 : P.r0, rb = side ? P.r0 : P.r1;
+      const double grot = EX ? R.gamma_rot * ra : 0.0;
+      const double etg = EX ? e_tr0 + grot : e_tr0;
       if (R.kind == HCAO_RX_DISSOCIATION) {
         kind = 1;
-        et = (((e_tr0 + eva) - R.dh) - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+        et = (((etg + eva) - R.dh) - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+        if constexpr (EX) {
+          // the uncoupled rotation stays with B's rotor, else is pooled
+          double keep = ra - grot;
+          if (T.sp[R.c].zeta_rot == 0) {
+            et = et + keep;
+            keep = 0.0;
+          }
+          if (side)
+            P.r1 = keep;
+          else
+            P.r0 = keep;
+          P.rn = 0.0;
+        }
       } else {
         kind = 2;
-        et = ((((e_tr0 + eva) + evb) - R.dh) - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+        et = ((((etg + eva) + evb) - R.dh) - T.sp[R.c].zpe) - T.sp[R.d].zpe;
+        if constexpr (EX) {
+          // A's uncoupled rotation goes to C's rotor, B's to D's; else pooled
+          double keep_c = ra - grot, keep_d = rb;
+          if (T.sp[R.c].zeta_rot == 0) {
+            et = et + keep_c;
+            keep_c = 0.0;
+          }
+          if (T.sp[R.d].zeta_rot == 0) {
+            et = et + keep_d;
+            keep_d = 0.0;
+          }
+          P.r0 = side ? keep_d : keep_c;
+          P.r1 = side ? keep_c : keep_d;
+        }
       }
     }
   }
@@ -1045,6 +1115,25 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   if (tr) atomicAdd(&C.ctr[HCAO_CTR_TRIALS], (unsigned long long)tr);
   if (nrel) atomicAdd(&C.ctr[HCAO_CTR_RELAX], (unsigned long long)nrel);
   if (ncap) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], (unsigned long long)ncap);
+
+  // --- rotational relaxation of each rotor in turn (non-reactive collisions) ---
+  if constexpr (EX) {
+    if (kind == 0) {
+      for (uint32_t x = 0; x < 2; ++x) {
+        const SpeciesTab &S = T.sp[x ? sp1 : sp0];
+        if (S.zeta_rot == 0) continue;
+        const double u = (double)draw<MIX>(rng);
+        if (!(u < S.p_rot)) continue;
+        const double ec = et + (x ? P.r1 : P.r0);
+        const double er = rot_fraction<MIX>(S.zeta_rot, PP.q, rng) * ec;
+        if (x)
+          P.r1 = er;
+        else
+          P.r0 = er;
+        et = ec - er;
+      }
+    }
+  }
 
   // --- scattering ---
   const V3<Rl> va0 = side ? P.v1 : P.v0, vb0 = side ? P.v0 : P.v1;
@@ -1474,6 +1563,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       P.lv0[m * BLOCK] = A.st.lvl[m * A.st.stride + gp];
       P.lv1[m * BLOCK] = A.st.lvl[m * A.st.stride + gq];
     }
+    P.r0 = P.r1 = P.rn = 0.0;
+    if constexpr (EX) {
+      if (A.st.rot) {
+        P.r0 = A.st.rot[gp];
+        P.r1 = A.st.rot[gq];
+      }
+    }
     P.has_m = false;
     uint64_t gm = 0;
     if (GT->has_recomb && 2 * H.ncand + k < H.n) {
@@ -1539,12 +1635,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       A.st.lvl[m * A.st.stride + gp] = P.lv0[m * BLOCK];
       A.st.lvl[m * A.st.stride + gq] = P.lv1[m * BLOCK];
     }
+    if constexpr (EX) {
+      if (A.st.rot) {
+        A.st.rot[gp] = P.dead0 ? 0.0 : P.r0;
+        A.st.rot[gq] = P.dead1 ? 0.0 : P.r1;
+      }
+    }
     if (P.m_moved) stv<MIX>(A.st, gm, P.v_m);
     if (P.born) {
       const uint64_t gb = H.base + k;
       stv<MIX>(A.scratch, gb, P.nb_v);
       A.scratch.sp[gb] = (uint8_t)P.nb_sp;
       for (uint32_t m = 0; m < mm; ++m) A.scratch.lvl[m * A.scratch.stride + gb] = P.lvn[m * BLOCK];
+      if constexpr (EX) {
+        if (A.scratch.rot) A.scratch.rot[gb] = P.rn;
+      }
       bflag[j] = 1;
     }
   }
@@ -1582,6 +1687,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           if (live) l = A.st.lvl[mo * A.st.stride + src];
           if (live) A.st.lvl[mo * A.st.stride + dst] = l;
         }
+        if constexpr (EX) {
+          if (A.st.rot) {
+            double rv = 0.0;
+            if (live) rv = A.st.rot[src];
+            if (live) A.st.rot[dst] = rv;
+          }
+        }
         kept += (uint32_t)__popcll(m);
       }
       alive = kept;
@@ -1600,6 +1712,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           A.st.sp[to] = A.scratch.sp[from];
           for (uint32_t mo = 0; mo < mm; ++mo)
             A.st.lvl[mo * A.st.stride + to] = A.scratch.lvl[mo * A.scratch.stride + from];
+          if constexpr (EX) {
+            if (A.st.rot) A.st.rot[to] = A.scratch.rot[from];
+          }
         }
         done += (uint32_t)__popcll(m);
       }
@@ -1727,6 +1842,21 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
       }
       A.st.lvl[m * A.st.stride + g] = (uint16_t)l;
     }
+    if (A.st.rot) {
+      // rotational energy of a rotor: Gamma(zeta/2, k T_trans), -ln(1 - u)
+      // plus, for zeta = 3, half the square of one polar normal
+      double e = 0.0;
+      if (S.zeta_rot > 0) {
+        double gm = -dlog(1.0 - rng.uniform());
+        if (S.zeta_rot == 3) {
+          double z1, z2;
+          polar_normals(rng, z1, z2);
+          gm = gm + 0.5 * (z1 * z1);
+        }
+        e = (kBoltz * tt) * gm;
+      }
+      A.st.rot[g] = e;
+    }
   }
 }
 
@@ -1794,12 +1924,12 @@ struct MomentArgs {
   State st;
   const uint64_t *off;
   const uint32_t *cnt;
-  double *out;  // [n_cells][6 + 2 S]
+  double *out;  // [n_cells][6 + 3 S]: sums, counts, E_vib above ZPE, E_rot per species
 };
 
 __global__ __launch_bounds__(256) void k_moments(MomentArgs A) {
   constexpr int kB = 256;
-  constexpr int kW = 6 + 2 * kMaxSpecies;
+  constexpr int kW = 6 + 3 * kMaxSpecies;
   __shared__ double s_red[kB];
   const uint32_t c = blockIdx.x;
   const Tables &T = *A.tab;
@@ -1824,18 +1954,21 @@ __global__ __launch_bounds__(256) void k_moments(MomentArgs A) {
     acc[5] += S.formation;
     double ev = 0.0;
     for (uint32_t q = 0; q < S.n_modes; ++q) ev = ev + mode_energy(S, A.lev, q, A.st.lvl[q * A.st.stride + g]);
+    const double er = A.st.rot ? A.st.rot[g] : 0.0;
 #pragma unroll
     for (int j = 0; j < kMaxSpecies; ++j) {
       if ((uint32_t)j == s) {
         acc[6 + j] += 1.0;
         acc[6 + kMaxSpecies + j] += ev - S.zpe;
+        acc[6 + 2 * kMaxSpecies + j] += er;
       }
     }
   }
-  double *out = A.out + (size_t)c * (6 + 2 * ns);
+  double *out = A.out + (size_t)c * (6 + 3 * ns);
 #pragma unroll
   for (int j = 0; j < kW; ++j) {
-    const bool used = j < 6 || (j >= 6 && j < 6 + (int)ns) || (j >= 6 + kMaxSpecies && j < 6 + kMaxSpecies + (int)ns);
+    const int blk = j < 6 ? -1 : (j - 6) / kMaxSpecies, sj = j < 6 ? 0 : (j - 6) % kMaxSpecies;
+    const bool used = j < 6 || sj < (int)ns;
     if (!used) continue;
     s_red[threadIdx.x] = acc[j];
     __syncthreads();
@@ -1844,7 +1977,7 @@ __global__ __launch_bounds__(256) void k_moments(MomentArgs A) {
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const int dst = j < 6 ? j : (j < 6 + kMaxSpecies ? j : j - kMaxSpecies + (int)ns);
+      const int dst = j < 6 ? j : 6 + blk * (int)ns + sj;
       out[dst] = s_red[0];
     }
     __syncthreads();
@@ -1991,6 +2124,7 @@ struct PlaceArgs {
   const uint8_t *sp;
   const double *vel;
   const uint16_t *lvl;
+  const double *rot;  // may be null
   State st;
   uint64_t n;
 };
@@ -2005,6 +2139,7 @@ __global__ __launch_bounds__(256) void k_load_place(PlaceArgs A) {
   store_vel(A.st, g, A.vel[3 * src], A.vel[3 * src + 1], A.vel[3 * src + 2]);
   A.st.sp[g] = A.sp[src];
   for (uint32_t m = 0; m < mm; ++m) A.st.lvl[m * A.st.stride + g] = A.lvl[src * mm + m];
+  if (A.st.rot) A.st.rot[g] = A.rot ? A.rot[src] : 0.0;
 }
 
 // advances the device step index after the launches of a graph replay
@@ -2336,8 +2471,8 @@ hipError_t launch_rec_sum(const RecSumArgs &a, uint32_t n_t, size_t lds, hipStre
 
 hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
                         const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,
-                        const uint16_t *lvl, const State &st, uint64_t n, hipStream_t s) {
-  PlaceArgs a{tab, sorted_cell, sorted_idx, packed_start, off, sp, vel, lvl, st, n};
+                        const uint16_t *lvl, const double *rot, const State &st, uint64_t n, hipStream_t s) {
+  PlaceArgs a{tab, sorted_cell, sorted_idx, packed_start, off, sp, vel, lvl, rot, st, n};
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_load_place, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -41,7 +41,7 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
 uint64_t sort_tiles(uint64_t n);
 hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
                         const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,
-                        const uint16_t *lvl, const State &st, uint64_t n, hipStream_t s);
+                        const uint16_t *lvl, const double *rot, const State &st, uint64_t n, hipStream_t s);
 }  // namespace hcao
 
 using namespace hcao;
@@ -123,6 +123,7 @@ struct hcao_ctx {
   DevBuf<float> fx, fy, fz, bfx, bfy, bfz;   // mixed form
   DevBuf<uint8_t> sp, bsp;
   DevBuf<uint16_t> lvl, blvl;
+  DevBuf<double> rot, brot;  // rotational energies (only when some species has a rotor)
   DevBuf<uint64_t> off;
   DevBuf<uint32_t> cnt, cap;
   DevBuf<double> d_volume, d_weight, sgmax, rem, defect;
@@ -236,6 +237,8 @@ void free_state(hcao_ctx *c) {
   c->bfz.release();
   c->bsp.release();
   c->blvl.release();
+  c->rot.release();
+  c->brot.release();
   c->off.release();
   c->cnt.release();
   c->cap.release();
@@ -260,10 +263,11 @@ uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
 }
 
 State state_of(hcao_ctx *c) {
-  return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->total_slots};
+  return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->rot.p, c->total_slots};
 }
 State scratch_of(hcao_ctx *c) {
-  return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->total_slots};
+  return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->brot.p,
+               c->total_slots};
 }
 CellArrays cells_of(hcao_ctx *c) {
   return CellArrays{c->off.p,   c->cnt.p, c->cap.p,    c->d_volume.p, c->d_weight.p,
@@ -416,6 +420,11 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   HIP_TRY(c, alloc_vel(c, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, tot));
   HIP_TRY(c, c->sp.alloc(tot));
   HIP_TRY(c, c->lvl.alloc(tot * mm));
+  if (c->tab.has_rot) {
+    HIP_TRY(c, c->rot.alloc(tot));
+    HIP_TRY(c, c->brot.alloc(tot));
+    HIP_TRY(c, hipMemsetAsync(c->rot.p, 0, tot * sizeof(double), c->stream));
+  }
   HIP_TRY(c, c->off.alloc(nc + 1));
   HIP_TRY(c, c->cnt.alloc(nc));
   HIP_TRY(c, c->cap.alloc(nc));
@@ -792,6 +801,9 @@ hcao_status hcao_add_species(hcao_ctx *c, const hcao_species_desc *d, int32_t *i
     return fail(c, HCAO_EINVAL, "bad mass or VHS parameters");
   if (d->n_bend + d->n_stretch > (uint32_t)kMaxModes) return fail(c, HCAO_EINVAL, "too many modes");
   if (!(d->p_vib >= 0.0) || !(d->p_vib <= 1.0)) return fail(c, HCAO_EINVAL, "p_vib outside [0,1]");
+  if (!(d->zeta_rot == 0 || d->zeta_rot == 2 || d->zeta_rot == 3))
+    return fail(c, HCAO_EINVAL, "zeta_rot must be 0, 2 or 3");
+  if (d->zeta_rot && (!(d->p_rot >= 0.0) || !(d->p_rot <= 1.0))) return fail(c, HCAO_EINVAL, "p_rot outside [0,1]");
   SpeciesHost s;
   s.d = *d;
   s.d.bend_theta_K = nullptr;
@@ -834,7 +846,9 @@ hcao_status hcao_add_reaction(hcao_ctx *c, const hcao_reaction_desc *d, int32_t 
   if (!c || !d) return HCAO_EINVAL;
   if (c->finalized) return fail(c, HCAO_ESTATE, "add_reaction after finalize");
   if (c->reactions.size() >= (size_t)kMaxReactions) return fail(c, HCAO_EINVAL, "too many reactions");
-  if (d->gamma_rot != 0.0) return fail(c, HCAO_EUNSUPPORTED, "rotation coupling needs rotational modes");
+  if (!(d->gamma_rot >= 0.0) || !(d->gamma_rot <= 1.0)) return fail(c, HCAO_EINVAL, "gamma_rot outside [0,1]");
+  if (d->kind == HCAO_RX_RECOMBINATION && d->gamma_rot != 0.0)
+    return fail(c, HCAO_EINVAL, "gamma_rot applies to dissociation and exchange");
   if (d->rec_model != HCAO_REC_WR && d->rec_model != HCAO_REC_EXACT) return fail(c, HCAO_EINVAL, "unknown recombination model");
   const int ns = (int)c->species.size();
   auto ok = [&](int s) { return s >= 0 && s < ns; };
@@ -946,6 +960,9 @@ hcao_status hcao_finalize(hcao_ctx *c) {
     S.zpe = h.zpe;
     S.formation = h.d.formation_J;
     S.p_vib = h.d.p_vib;
+    S.zeta_rot = h.d.zeta_rot;
+    S.p_rot = h.d.zeta_rot ? h.d.p_rot : 0.0;
+    if (S.zeta_rot) T.has_rot = 1;
     S.n_modes = h.n_modes;
     S.n_bend = h.d.n_bend;
     S.sampler = (uint32_t)h.sampler;
@@ -1034,6 +1051,7 @@ hcao_status hcao_finalize(hcao_ctx *c) {
     ReactionTab &R = T.rx[r];
     R.kind = (int32_t)h.d.kind;
     R.mask = h.d.stretch_mask;
+    R.gamma_rot = h.d.gamma_rot;
     if (h.d.kind == HCAO_RX_RECOMBINATION) {
       const int b = h.d.reactant[0], cc = h.d.reactant[1], a = h.d.product[0];
       R.a = b;
@@ -1112,13 +1130,25 @@ hcao_status hcao_finalize(hcao_ctx *c) {
 }
 
 hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, const uint8_t *species,
-                                const double *vel, const uint16_t *levels) {
+                                const double *vel, const uint16_t *levels, const double *rot) {
   if (!c) return HCAO_EINVAL;
   if (hcao_status s = check_sticky(c)) return s;
   if (!c->finalized) return fail(c, HCAO_ESTATE, "load before finalize");
   if (n && (!cell || !species || !vel || !levels)) return fail(c, HCAO_EINVAL, "null particle array");
   if (n > 0xFFFFFFFFull) return fail(c, HCAO_EINVAL, "too many particles");
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
+  if (rot) {
+    for (uint64_t i = 0; i < n; ++i) {
+      const bool rotor = species[i] < c->species.size() && c->species[species[i]].d.zeta_rot > 0;
+      if (!(rot[i] >= 0.0) || !std::isfinite(rot[i]) || (rot[i] != 0.0 && !rotor))
+        return fail(c, HCAO_EINVAL, "rotational energy must be finite, >= 0, and 0 without a rotor");
+    }
+  }
+  DevBuf<double> d_rot;
+  if (rot && c->tab.has_rot) {
+    HIP_TRY(c, d_rot.alloc(n));
+    if (n) HIP_TRY(c, hipMemcpyAsync(d_rot.p, rot, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
   DevBuf<uint32_t> d_cell, d_count, keys_tmp, idx, idx_tmp, hist;
   DevBuf<uint8_t> d_sp;
   DevBuf<double> d_vel;
@@ -1164,8 +1194,8 @@ hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, c
   HIP_TRY(c, launch_scan_u32(c->cnt.p, packed.p, nc, c->stream));
   const uint32_t *sk = in_tmp ? keys_tmp.p : d_cell.p;
   const uint32_t *si = in_tmp ? idx_tmp.p : idx.p;
-  HIP_TRY(c, launch_place(c->d_tab.p, sk, si, packed.p, c->off.p, d_sp.p, d_vel.p, d_lvl.p, state_of(c), n,
-                          c->stream));
+  HIP_TRY(c, launch_place(c->d_tab.p, sk, si, packed.p, c->off.p, d_sp.p, d_vel.p, d_lvl.p, d_rot.p, state_of(c),
+                          n, c->stream));
   HIP_TRY(c, launch_cell_init(c->d_tab.p, state_of(c), cells_of(c), nc, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   d_cell.release();
@@ -1241,7 +1271,7 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
     const uint32_t k = std::min(n_steps - done, c->steps_per_launch);
     a.step = (step_dev ? 0u : base) + done;
     a.n_steps = k;
-    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->has_exact, c->n_groups, s));
+    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->has_exact || c->tab.has_rot, c->n_groups, s));
     done += k;
     ++n;
   }
@@ -1368,7 +1398,7 @@ namespace {
 
 // Device copy of everything a step changes, for the autotuner's trials.
 struct Snapshot {
-  DevBuf<double> vx, vy, vz, sgmax, rem, defect;
+  DevBuf<double> vx, vy, vz, sgmax, rem, defect, rot;
   DevBuf<float> fx, fy, fz;
   DevBuf<uint8_t> sp;
   DevBuf<uint16_t> lvl;
@@ -1398,6 +1428,7 @@ hcao_status snapshot(hcao_ctx *c, Snapshot &S, bool take) {
   SNAP(fy);
   SNAP(fz);
   SNAP(sp);
+  SNAP(rot);
   SNAP(lvl);
   SNAP(cnt);
   SNAP(sgmax);
@@ -1601,6 +1632,22 @@ hcao_status hcao_read_particles(hcao_ctx *c, uint8_t *species, double *vel, uint
   return HCAO_OK;
 }
 
+hcao_status hcao_read_rotational_energy(hcao_ctx *c, double *rot) {
+  if (!c || !rot) return HCAO_EINVAL;
+  if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
+  const uint64_t tot = c->total_slots;
+  const uint32_t nc = c->cfg.n_cells;
+  std::vector<uint32_t> cnt(nc);
+  std::vector<double> r(c->rot.p ? tot : 0);
+  HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost, c->stream));
+  if (c->rot.p) HIP_TRY(c, hipMemcpyAsync(r.data(), c->rot.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  uint64_t j = 0;
+  for (uint32_t cell = 0; cell < nc; ++cell)
+    for (uint32_t i = 0; i < cnt[cell]; ++i, ++j) rot[j] = c->rot.p ? r[c->off_host[cell] + i] : 0.0;
+  return HCAO_OK;
+}
+
 hcao_status hcao_read_cell_state(hcao_ctx *c, double *sgmax, double *rem, uint64_t *counters) {
   if (!c) return HCAO_EINVAL;
   if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
@@ -1617,7 +1664,7 @@ hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments 
   if (!c) return HCAO_EINVAL;
   if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
   const uint32_t nc = c->cfg.n_cells, ns = (uint32_t)c->species.size();
-  const uint32_t w = 6 + 2 * ns;
+  const uint32_t w = 6 + 3 * ns;
   DevBuf<double> d_out;
   HIP_TRY(c, d_out.alloc((size_t)nc * w));
   HIP_TRY(c, launch_moments(c->d_tab.p, c->d_lev.p, state_of(c), c->off.p, c->cnt.p, d_out.p, nc, c->stream));
@@ -1641,6 +1688,9 @@ hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments 
       M.E_vib_J[s] = r[6 + ns + s];
       if (vol > 0.0) M.number_density[s] = (double)k * wgt / vol;
       M.T_vib_K[s] = k ? solve_tvib(c->species[s], r[6 + ns + s] / (double)k) : 0.0;
+      M.E_rot_J[s] = r[6 + 2 * ns + s];
+      const uint32_t z = c->species[s].d.zeta_rot;
+      M.T_rot_K[s] = (k && z) ? (2.0 * M.E_rot_J[s]) / ((double)z * kB * (double)k) : 0.0;
     }
     M.n_total = ntot;
     M.T_trans_K = ntot ? 2.0 * M.E_trans_J / (3.0 * kB * (double)ntot) : 0.0;
@@ -1777,10 +1827,14 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   HIP_TRY(c, hipMemcpy(sg.data(), c->sgmax.p, nc * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(rm.data(), c->rem.p, nc * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(ctr.data(), c->ctr.p, ctr.size() * 8, hipMemcpyDeviceToHost));
+  std::vector<double> rt(c->rot.p ? tot : 0);
+  if (c->rot.p) HIP_TRY(c, hipMemcpy(rt.data(), c->rot.p, tot * 8, hipMemcpyDeviceToHost));
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(c, HCAO_EINVAL, std::string("cannot open ") + path);
-  // velocities are stored as fp64 in both forms (exact for fp32 values)
-  const uint64_t hdr[7] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step, c->mixed ? 1ull : 0ull};
+  // velocities are stored as fp64 in both forms (exact for fp32 values);
+  // word 6: bit 0 mixed form, bit 1 rotational energies follow the levels
+  const uint64_t form = (c->mixed ? 1ull : 0ull) | (c->rot.p ? 2ull : 0ull);
+  const uint64_t hdr[7] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step, form};
   bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
   ok = ok && std::fwrite(c->cap_host.data(), 4, nc, f) == nc;
   ok = ok && std::fwrite(cnt.data(), 4, nc, f) == nc;
@@ -1793,6 +1847,7 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   ok = ok && std::fwrite(vz.data(), 8, tot, f) == tot;
   ok = ok && std::fwrite(sp.data(), 1, tot, f) == tot;
   ok = ok && std::fwrite(lv.data(), 2, lv.size(), f) == lv.size();
+  ok = ok && std::fwrite(rt.data(), 8, rt.size(), f) == rt.size();
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return fail(c, HCAO_EINVAL, "write failed");
   return HCAO_OK;
@@ -1807,7 +1862,7 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   uint64_t hdr[7];
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
   if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x48434130534156ull || hdr[1] != HCAO_ABI_VERSION ||
-      hdr[2] != nc || hdr[4] != mm || hdr[6] != (c->mixed ? 1ull : 0ull)) {
+      hdr[2] != nc || hdr[4] != mm || hdr[6] != ((c->mixed ? 1ull : 0ull) | (c->tab.has_rot ? 2ull : 0ull))) {
     std::fclose(f);
     return fail(c, HCAO_EINVAL, "checkpoint does not match this context");
   }
@@ -1828,6 +1883,8 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   ok = ok && std::fread(vz.data(), 8, tot, f) == tot;
   ok = ok && std::fread(sp.data(), 1, tot, f) == tot;
   ok = ok && std::fread(lv.data(), 2, lv.size(), f) == lv.size();
+  std::vector<double> rt(c->tab.has_rot ? tot : 0);
+  ok = ok && std::fread(rt.data(), 8, rt.size(), f) == rt.size();
   std::fclose(f);
   if (!ok) return fail(c, HCAO_EINVAL, "truncated checkpoint");
   uint64_t t2 = 0;
@@ -1841,6 +1898,7 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   HIP_TRY(c, hipMemcpy(c->sgmax.p, sg.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->rem.p, rm.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->ctr.p, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice));
+  if (c->rot.p) HIP_TRY(c, hipMemcpy(c->rot.p, rt.data(), tot * 8, hipMemcpyHostToDevice));
   c->step = (uint32_t)hdr[5];
   c->loaded = true;
   return HCAO_OK;

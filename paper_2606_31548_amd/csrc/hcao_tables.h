@@ -23,9 +23,10 @@ constexpr uint32_t kErrLevel = 4u;
 constexpr uint32_t kErrNonFinite = 8u;
 
 struct SpeciesTab {
-  double mass, zpe, formation, p_vib;
+  double mass, zpe, formation, p_vib, p_rot;
   uint32_t n_modes, n_bend, sampler;
   uint32_t concave;             // bit m: the level spacings of mode m never increase
+  uint32_t zeta_rot, pad_rot;   // rotational degrees of freedom (0, 2 or 3)
   double kt[kMaxModes];         // bends: k_B Theta
   double theta[kMaxModes];      // bends: Theta
   double de[kMaxModes];         // stretches: D_e
@@ -48,6 +49,7 @@ struct ReactionTab {
   uint64_t mask;
   double alpha[kMaxModes];
   double steric, ea, dh, zsum;
+  double gamma_rot;  // rotation coupling of dissociation / exchange
   uint64_t rec_off;
 };
 
@@ -65,7 +67,7 @@ constexpr double kRecTmax = 5.0e4;
 
 struct Tables {
   uint32_t n_species, n_reactions, max_modes, n_levels;
-  uint32_t has_recomb, rec_nt, pad0, pad1;
+  uint32_t has_recomb, rec_nt, has_rot, pad1;
   double rec_l0, rec_inv_step;  // log T of node 0; nodes per unit of log T
   SpeciesTab sp[kMaxSpecies];
   PairTab pr[kMaxSpecies][kMaxSpecies];
@@ -82,6 +84,7 @@ struct State {
   float *fx, *fy, *fz;
   uint8_t *sp;
   uint16_t *lvl;
+  double *rot;      // rotational energy [J]; null when no species has a rotor
   uint64_t stride;  // total slots (all cells)
 };
 

@@ -42,7 +42,7 @@ class hcao_species_desc(ctypes.Structure):
     _fields_ = [("mass_kg", _d), ("dref_m", _d), ("omega", _d), ("Tref_K", _d), ("n_bend", _u32),
                 ("bend_theta_K", _pd), ("n_stretch", _u32), ("omega_e_per_m", _pd), ("chi_e", _pd), ("De_J", _pd),
                 ("n_levels", ctypes.POINTER(_u32)), ("levels_J", _pd), ("formation_J", _d), ("coupling", _d),
-                ("p_vib", _d), ("sampler", ctypes.c_int)]
+                ("p_vib", _d), ("sampler", ctypes.c_int), ("zeta_rot", _u32), ("p_rot", _d)]
 
 
 class hcao_reaction_desc(ctypes.Structure):
@@ -54,7 +54,8 @@ class hcao_reaction_desc(ctypes.Structure):
 class hcao_moments(ctypes.Structure):
     _fields_ = [("n_total", _u64), ("n_species", _u64 * MAX_SPECIES), ("number_density", _d * MAX_SPECIES),
                 ("momentum", _d * 3), ("E_trans_J", _d), ("E_kin_J", _d), ("E_vib_J", _d * MAX_SPECIES),
-                ("E_formation_J", _d), ("T_trans_K", _d), ("T_vib_K", _d * MAX_SPECIES), ("E_defect_J", _d)]
+                ("E_formation_J", _d), ("T_trans_K", _d), ("T_vib_K", _d * MAX_SPECIES), ("E_defect_J", _d),
+                ("E_rot_J", _d * MAX_SPECIES), ("T_rot_K", _d * MAX_SPECIES)]
 
 
 class hcao_launch_shape(ctypes.Structure):
@@ -94,7 +95,8 @@ def load_library():
     L.hcao_add_species.argtypes = [_vp, ctypes.POINTER(hcao_species_desc), ctypes.POINTER(_i32)]
     L.hcao_add_reaction.argtypes = [_vp, ctypes.POINTER(hcao_reaction_desc), ctypes.POINTER(_i32)]
     L.hcao_finalize.argtypes = [_vp]
-    L.hcao_load_particles.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp]
+    L.hcao_load_particles.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp]
+    L.hcao_read_rotational_energy.argtypes = [_vp, _vp]
     L.hcao_init_thermal.argtypes = [_vp, _vp, _vp, _vp]
     L.hcao_step.argtypes = [_vp, _d, _u32]
     L.hcao_sync.argtypes = [_vp]
@@ -125,7 +127,8 @@ def load_library():
                  "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
                  "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore",
                  "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
-                 "hcao_read_cell_particles", "hcao_get_exact_beta", "hcao_recombination_exact"):
+                 "hcao_read_cell_particles", "hcao_get_exact_beta", "hcao_recombination_exact",
+                 "hcao_read_rotational_energy"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -210,7 +213,8 @@ class Simulation:
                               len(we), _dp(we) if len(we) else None, _dp(xe) if len(xe) else None,
                               _dp(de) if len(de) else None,
                               nl.ctypes.data_as(ctypes.POINTER(_u32)) if nl is not None else None, _dp(lv),
-                              sp.formation_J, getattr(sp, "coupling", 0.0), sp.p_vib, sp.sampler)
+                              sp.formation_J, getattr(sp, "coupling", 0.0), sp.p_vib, sp.sampler,
+                              int(getattr(sp, "zeta_rot", 0)), float(getattr(sp, "p_rot", 0.0)))
         i = _i32()
         self._chk("hcao_add_species", self._L.hcao_add_species(self._h, ctypes.byref(d), ctypes.byref(i)))
         self.n_species += 1
@@ -221,7 +225,8 @@ class Simulation:
         al = None if rx.alpha is None else np.asarray(rx.alpha, np.float64)
         self._keep.append(al)
         d = hcao_reaction_desc(rx.kind, (_i32 * 2)(*rx.reactant), (_i32 * 2)(*rx.product), int(rx.stretch_mask),
-                               _dp(al), rx.steric, rx.Ea_J, 0.0, getattr(rx, "n_samp", 0), getattr(rx, "rec_model", 0))
+                               _dp(al), rx.steric, rx.Ea_J, float(getattr(rx, "gamma_rot", 0.0)), getattr(rx, "n_samp", 0),
+                               getattr(rx, "rec_model", 0))
         i = _i32()
         self._chk("hcao_add_reaction", self._L.hcao_add_reaction(self._h, ctypes.byref(d), ctypes.byref(i)))
         self.n_reactions += 1
@@ -232,13 +237,22 @@ class Simulation:
         self.max_modes = self._L.hcao_max_modes(self._h)
 
     # -- particles --
-    def load_particles(self, cell, species, vel, levels):
+    def load_particles(self, cell, species, vel, levels, rot=None):
         cell = np.ascontiguousarray(cell, np.uint32)
         species = np.ascontiguousarray(species, np.uint8)
         vel = np.ascontiguousarray(vel, np.float64)
         levels = np.ascontiguousarray(levels, np.uint16)
+        rot = None if rot is None else np.ascontiguousarray(rot, np.float64)
         self._chk("hcao_load_particles",
-                  self._L.hcao_load_particles(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels)))
+                  self._L.hcao_load_particles(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels),
+                                              _p(rot)))
+
+    def read_rotational_energy(self):
+        """Rotational energies [J] of every particle, in read_particles order."""
+        _, tot = self.counts()
+        out = np.zeros(tot, np.float64)
+        self._chk("hcao_read_rotational_energy", self._L.hcao_read_rotational_energy(self._h, _p(out)))
+        return out
 
     def init_thermal(self, counts, t_trans, t_vib):
         counts = np.ascontiguousarray(counts, np.uint32)
@@ -321,13 +335,13 @@ class Simulation:
         return float(sum(self.levels(species, m, 1)[0] for m in range(self._n_modes[species])))
 
     def total_energy(self, m=None, with_defect: bool = True) -> float:
-        """Kinetic + vibrational (zero point included) + formation energy of
-        all particles [J], plus, by default, the energy the mixed form still
-        owes them."""
+        """Kinetic + vibrational (zero point included) + rotational + formation
+        energy of all particles [J], plus, by default, the energy the mixed
+        form still owes them."""
         m = self.moments() if m is None else m
         e = m.E_kin_J + m.E_formation_J
         for s in range(self.n_species):
-            e += m.E_vib_J[s] + m.n_species[s] * self.zero_point(s)
+            e += m.E_vib_J[s] + m.n_species[s] * self.zero_point(s) + m.E_rot_J[s]
         return e + (m.E_defect_J if with_defect else 0.0)
 
     def reaction_counts(self):

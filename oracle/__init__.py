@@ -61,7 +61,9 @@ def lib():
         L.orc_add_species.argtypes = [vp, d, d, d, d, u32, vp, u32, vp, vp, vp, vp, vp, d, d, ctypes.c_int]
         L.orc_add_reaction.argtypes = [vp, ctypes.c_int, vp, vp, u64, vp, d, d, u32]
         L.orc_finalize.argtypes = [vp]
-        L.orc_load.argtypes = [vp, u64, vp, vp, vp, vp, vp]
+        L.orc_load.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp]
+        L.orc_set_domain.argtypes = [vp, u32, u32, u32, d, d, d, u32]; L.orc_set_domain.restype = ctypes.c_int
+        L.orc_read_pos.argtypes = [vp, u32, vp]; L.orc_read_pos.restype = ctypes.c_int
         L.orc_set_rotation.argtypes = [vp, u32, u32, d]; L.orc_set_rotation.restype = ctypes.c_int
         L.orc_set_gamma_rot.argtypes = [vp, u32, d]; L.orc_set_gamma_rot.restype = ctypes.c_int
         L.orc_read_rot.argtypes = [vp, u32, vp]; L.orc_read_rot.restype = ctypes.c_int
@@ -223,13 +225,24 @@ class Oracle:
         _chk("orc_finalize", lib().orc_finalize(self._h))
         self.max_modes = lib().orc_max_modes(self._h)
 
-    def load(self, cell, species, vel, levels, rot=None):
+    def set_domain(self, nx, ny, nz, lx, ly, lz, periodic=0):
+        _chk("orc_set_domain", lib().orc_set_domain(self._h, nx, ny, nz, float(lx), float(ly), float(lz),
+                                                    int(periodic)))
+
+    def load(self, cell, species, vel, levels, rot=None, pos=None):
         cell = np.ascontiguousarray(cell, np.uint32)
         species = np.ascontiguousarray(species, np.uint8)
         vel = np.ascontiguousarray(vel, np.float64)
         levels = np.ascontiguousarray(levels, np.uint16)
         rot = None if rot is None else np.ascontiguousarray(rot, np.float64)
-        _chk("orc_load", lib().orc_load(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels), _p(rot)))
+        pos = None if pos is None else np.ascontiguousarray(pos, np.float64)
+        _chk("orc_load", lib().orc_load(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels), _p(rot),
+                                        _p(pos)))
+
+    def read_pos(self, cell):
+        out = np.zeros((self.count(cell), 3), np.float64)
+        _chk("orc_read_pos", lib().orc_read_pos(self._h, cell, _p(out)))
+        return out
 
     def read_rot(self, cell):
         out = np.zeros(self.count(cell), np.float64)
@@ -415,6 +428,8 @@ class Oracle:
 def from_workload(wl, seed=None, capacity_per_cell=0):
     """Builds an Oracle with the species and reactions of a workloads.Workload."""
     o = Oracle(wl.seed if seed is None else seed, wl.n_cells, wl.cell_volume, wl.cell_weight, capacity_per_cell)
+    if getattr(wl, "domain", None) is not None:
+        o.set_domain(*wl.domain)
     for sp in wl.species:
         o.add_species(sp)
     for rx in wl.reactions:

@@ -291,6 +291,7 @@ typedef struct {
   uint8_t *sp;
   uint16_t *lvl; /* n x max_modes, row major */
   double *rot;   /* rotational energy [J] */
+  double *px, *py, *pz; /* positions [m] (spatial mode) */
   double volume, weight, sgmax, rem;
   uint64_t ctr[ORC_N_CTR];
 } cell_t;
@@ -299,6 +300,8 @@ struct orc_ctx {
   uint64_t seed;
   uint32_t n_cells, cap_default, step, finalized, loaded;
   uint32_t n_species, n_reactions, max_modes, has_recomb, has_rot;
+  uint32_t spatial, nx, ny, nz, periodic; /* spatial mode: box of nx ny nz cells, periodic axes (bits) */
+  double len[3];
   double rec_l0, rec_inv_step; /* log(REC_TMIN), (REC_NT - 1) / log(REC_TMAX / REC_TMIN) */
   species_t sp[ORC_MAX_SPECIES];
   reaction_t rx[ORC_MAX_REACTIONS];
@@ -353,10 +356,14 @@ static void free_cell(cell_t *c) {
   free(c->sp);
   free(c->lvl);
   free(c->rot);
+  free(c->px);
+  free(c->py);
+  free(c->pz);
   c->vx = c->vy = c->vz = NULL;
   c->sp = NULL;
   c->lvl = NULL;
   c->rot = NULL;
+  c->px = c->py = c->pz = NULL;
 }
 
 void orc_destroy(orc_ctx *o) {
@@ -506,6 +513,69 @@ int orc_set_gamma_rot(orc_ctx *o, uint32_t reaction, double gamma) {
   if (o->rx[reaction].kind == ORC_RX_RECOMBINATION && gamma != 0.0) return E_INVAL;
   o->rx[reaction].gamma_rot = gamma;
   return E_OK;
+}
+
+/* Spatial mode (reading S-A): the cells tile the box [0, lx) x
+ * [0, ly) x [0, lz) as an nx x ny x nz grid, cell = ix + nx (iy + ny iz);
+ * bit k of periodic makes axis k periodic, else its walls reflect
+ * specularly. Every step then moves all particles ballistically, re-bins
+ * them by a stable counting sort on the new cell, and collides. Before
+ * finalize; every cell's volume must be the grid cell's. */
+int orc_set_domain(orc_ctx *o, uint32_t nx, uint32_t ny, uint32_t nz, double lx, double ly, double lz,
+                   uint32_t periodic) {
+  if (!o || o->finalized) return E_STATE;
+  if (nx == 0 || ny == 0 || nz == 0 || (uint64_t)nx * ny * nz != o->n_cells) return E_INVAL;
+  if (!(lx > 0.0) || !(ly > 0.0) || !(lz > 0.0) || periodic > 7u) return E_INVAL;
+  double vc = ((lx * ly) * lz) / (double)o->n_cells;
+  for (uint32_t c = 0; c < o->n_cells; ++c)
+    if (fabs(o->cells[c].volume - vc) > 1e-9 * vc) return E_INVAL;
+  o->spatial = 1;
+  o->nx = nx;
+  o->ny = ny;
+  o->nz = nz;
+  o->len[0] = lx;
+  o->len[1] = ly;
+  o->len[2] = lz;
+  o->periodic = periodic;
+  return E_OK;
+}
+
+/* grid index along axis k of coordinate x: floor(x / (L_k / n_k)), clamped */
+static uint32_t axis_index(const orc_ctx *o, int k, double x) {
+  uint32_t n = k == 0 ? o->nx : (k == 1 ? o->ny : o->nz);
+  double d = o->len[k] / (double)n;
+  double f = floor(x / d);
+  if (!(f >= 0.0)) return 0;
+  if (f >= (double)n) return n - 1;
+  return (uint32_t)f;
+}
+
+static uint32_t cell_of(const orc_ctx *o, double x, double y, double z) {
+  return axis_index(o, 0, x) + o->nx * (axis_index(o, 1, y) + o->ny * axis_index(o, 2, z));
+}
+
+/* ballistic move of one coordinate over dt with the axis' boundary:
+ * periodic wraps into [0, L); specular reflects (x < 0: -x, x > L: 2L - x,
+ * velocity reversed) until inside [0, L] */
+static void move_axis(double *x, double *v, double dt, double len, int periodic) {
+  double y = *x + *v * dt;
+  if (periodic) {
+    while (y < 0.0) y = y + len;
+    while (y >= len) y = y - len;
+  } else {
+    for (;;) {
+      if (y < 0.0) {
+        y = -y;
+        *v = -*v;
+      } else if (y > len) {
+        y = (len + len) - y;
+        *v = -*v;
+      } else {
+        break;
+      }
+    }
+  }
+  *x = y;
 }
 
 int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int32_t product[2],
@@ -850,6 +920,12 @@ static int alloc_cell(orc_ctx *o, cell_t *c, uint32_t cap) {
   c->lvl = (uint16_t *)calloc((size_t)(cap ? cap : 1) * mm, sizeof(uint16_t));
   c->rot = (double *)calloc(cap ? cap : 1, sizeof(double));
   if (!c->vx || !c->vy || !c->vz || !c->sp || !c->lvl || !c->rot) return E_NOMEM;
+  if (o->spatial) {
+    c->px = (double *)calloc(cap ? cap : 1, sizeof(double));
+    c->py = (double *)calloc(cap ? cap : 1, sizeof(double));
+    c->pz = (double *)calloc(cap ? cap : 1, sizeof(double));
+    if (!c->px || !c->py || !c->pz) return E_NOMEM;
+  }
   return E_OK;
 }
 
@@ -900,7 +976,7 @@ static int check_particle(const orc_ctx *o, uint32_t sp, const double *v, const 
 
 /* Stable placement of particles into their cells (a counting sort by cell). */
 int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *species, const double *vel,
-             const uint16_t *levels, const double *rot) {
+             const uint16_t *levels, const double *rot, const double *pos) {
   if (!o || !o->finalized) return E_STATE;
   uint32_t mm = o->max_modes;
   uint32_t *count = (uint32_t *)calloc(o->n_cells, sizeof(uint32_t));
@@ -913,6 +989,13 @@ int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *specie
     int rc = check_particle(o, species[i], vel + 3 * i, levels + (size_t)i * mm);
     if (!rc && rot && !(rot[i] >= 0.0 && isfinite(rot[i]) && (rot[i] == 0.0 || o->sp[species[i]].zeta_rot > 0)))
       rc = E_INVAL;
+    if (!rc && o->spatial) {
+      /* positions inside the box and in the particle's cell */
+      if (!pos) rc = E_INVAL;
+      for (int k = 0; !rc && k < 3; ++k)
+        if (!(pos[3 * i + k] >= 0.0) || !(pos[3 * i + k] <= o->len[k])) rc = E_INVAL;
+      if (!rc && cell_of(o, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]) != cell[i]) rc = E_INVAL;
+    }
     if (rc) {
       free(count);
       return rc;
@@ -941,6 +1024,11 @@ int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *specie
     c->vz[j] = vel[3 * i + 2];
     c->sp[j] = species[i];
     c->rot[j] = rot ? rot[i] : 0.0;
+    if (o->spatial) {
+      c->px[j] = pos[3 * i];
+      c->py[j] = pos[3 * i + 1];
+      c->pz[j] = pos[3 * i + 2];
+    }
     for (uint32_t m = 0; m < mm; ++m) c->lvl[(size_t)j * mm + m] = levels[(size_t)i * mm + m];
   }
   for (uint32_t c = 0; c < o->n_cells; ++c) init_sgmax(o, &o->cells[c]);
@@ -965,7 +1053,8 @@ static void polar_normals(stream *st, double *n1, double *n2) {
 
 /* Thermal initial state. Rotational energy (species with a rotor, after the
  * levels): Boltzmann at T_rot = T_trans, Gamma(zeta/2, k T): zeta = 2 takes
- * -ln(1 - u), zeta = 3 adds half the square of one polar normal.
+ * -ln(1 - u), zeta = 3 adds half the square of one polar normal. Position
+ * (spatial mode, last): uniform in the cell, one draw per axis.
  * Velocities: Maxwellian at T_trans. Bends: the floor
  * form of the initialization section (i = floor(-ln r T_vib / Theta), r in (0,1]).
  * Stretches: uniform proposal over 0..i_diss accepted with
@@ -1032,6 +1121,13 @@ int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, 
             g = g + 0.5 * (z1 * z1);
           }
           C->rot[slot] = (K_BOLTZ * t_trans[c]) * g;
+        }
+        if (o->spatial) {
+          /* uniform in the cell: x = (i_x + u) L_x / n_x per axis */
+          uint32_t ix = c % o->nx, iy = (c / o->nx) % o->ny, iz = c / (o->nx * o->ny);
+          C->px[slot] = ((double)ix + uniform(&st)) * (o->len[0] / (double)o->nx);
+          C->py[slot] = ((double)iy + uniform(&st)) * (o->len[1] / (double)o->ny);
+          C->pz[slot] = ((double)iz + uniform(&st)) * (o->len[2] / (double)o->nz);
         }
         slot += 1;
       }
@@ -1364,6 +1460,7 @@ typedef struct {
   uint8_t sp[2];
   uint16_t lvl[2][ORC_MAX_MODES];
   double rot[2];
+  double pos[2][3];
   int dead[2];
   int has_m;   /* a third body is available for recombination */
   uint8_t sp_m;
@@ -1377,6 +1474,7 @@ typedef struct {
   double v[3];
   uint16_t lvl[ORC_MAX_MODES];
   double rot;
+  double pos[3]; /* spatial mode: the dissociating molecule's position */
 } newborn;
 
 /* Rotational Larsen-Borgnakke share (reading R-B): the fraction f of the
@@ -1595,6 +1693,7 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
       nb->sp = (uint8_t)R->d;
       memcpy(nb->lvl, lc, sizeof(lc));
       nb->rot = 0.0;
+      for (int k = 0; k < 3; ++k) nb->pos[k] = ps->pos[a][k];
       if (ctr) {
         ctr[ORC_CTR_TRIALS] += t;
         ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
@@ -1693,6 +1792,11 @@ static void load_pair(const cell_t *C, uint32_t mm, uint32_t p, uint32_t q, pair
     ps->v[x][2] = C->vz[i];
     ps->sp[x] = C->sp[i];
     ps->rot[x] = C->rot[i];
+    if (C->px) {
+      ps->pos[x][0] = C->px[i];
+      ps->pos[x][1] = C->py[i];
+      ps->pos[x][2] = C->pz[i];
+    }
     for (uint32_t m = 0; m < mm; ++m) ps->lvl[x][m] = C->lvl[(size_t)i * mm + m];
   }
 }
@@ -1812,6 +1916,11 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
       C->vz[alive] = C->vz[i];
       C->sp[alive] = C->sp[i];
       C->rot[alive] = C->rot[i];
+      if (C->px) {
+        C->px[alive] = C->px[i];
+        C->py[alive] = C->py[i];
+        C->pz[alive] = C->pz[i];
+      }
       for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)alive * mm + m] = C->lvl[(size_t)i * mm + m];
     }
     ++alive;
@@ -1831,6 +1940,11 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     C->vz[j] = nb[k].v[2];
     C->sp[j] = nb[k].sp;
     C->rot[j] = nb[k].rot;
+    if (C->px) {
+      C->px[j] = nb[k].pos[0];
+      C->py[j] = nb[k].pos[1];
+      C->pz[j] = nb[k].pos[2];
+    }
     for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)j * mm + m] = nb[k].lvl[m];
   }
   free(nb);
@@ -1838,10 +1952,78 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
   return E_OK;
 }
 
+/* Spatial mode: every particle moves over dt (cells in order, particles in
+ * slot order), then all are re-binned by their new cell, keeping that
+ * order within each new cell (a stable counting sort). */
+static int move_and_rebin(orc_ctx *o, double dt) {
+  uint32_t mm = o->max_modes ? o->max_modes : 1;
+  uint32_t *newn = (uint32_t *)calloc(o->n_cells, sizeof(uint32_t));
+  if (!newn) return E_NOMEM;
+  for (uint32_t c = 0; c < o->n_cells; ++c) {
+    cell_t *C = &o->cells[c];
+    for (uint32_t i = 0; i < C->n; ++i) {
+      move_axis(&C->px[i], &C->vx[i], dt, o->len[0], (int)(o->periodic & 1u));
+      move_axis(&C->py[i], &C->vy[i], dt, o->len[1], (int)((o->periodic >> 1) & 1u));
+      move_axis(&C->pz[i], &C->vz[i], dt, o->len[2], (int)((o->periodic >> 2) & 1u));
+      newn[cell_of(o, C->px[i], C->py[i], C->pz[i])] += 1;
+    }
+  }
+  for (uint32_t c = 0; c < o->n_cells; ++c)
+    if (newn[c] > o->cells[c].cap) {
+      free(newn);
+      return E_CAPACITY;
+    }
+  cell_t *nc = (cell_t *)calloc(o->n_cells, sizeof(cell_t));
+  if (!nc) {
+    free(newn);
+    return E_NOMEM;
+  }
+  int rc = E_OK;
+  for (uint32_t c = 0; c < o->n_cells && !rc; ++c) {
+    rc = alloc_cell(o, &nc[c], o->cells[c].cap);
+    nc[c].volume = o->cells[c].volume;
+    nc[c].weight = o->cells[c].weight;
+    nc[c].sgmax = o->cells[c].sgmax;
+    nc[c].rem = o->cells[c].rem;
+    memcpy(nc[c].ctr, o->cells[c].ctr, sizeof(nc[c].ctr));
+  }
+  for (uint32_t c = 0; c < o->n_cells && !rc; ++c) {
+    cell_t *C = &o->cells[c];
+    for (uint32_t i = 0; i < C->n; ++i) {
+      cell_t *D = &nc[cell_of(o, C->px[i], C->py[i], C->pz[i])];
+      uint32_t j = D->n++;
+      D->vx[j] = C->vx[i];
+      D->vy[j] = C->vy[i];
+      D->vz[j] = C->vz[i];
+      D->sp[j] = C->sp[i];
+      D->rot[j] = C->rot[i];
+      D->px[j] = C->px[i];
+      D->py[j] = C->py[i];
+      D->pz[j] = C->pz[i];
+      for (uint32_t m = 0; m < mm; ++m) D->lvl[(size_t)j * mm + m] = C->lvl[(size_t)i * mm + m];
+    }
+  }
+  for (uint32_t c = 0; c < o->n_cells; ++c) {
+    if (!rc) {
+      free_cell(&o->cells[c]);
+      o->cells[c] = nc[c];
+    } else {
+      free_cell(&nc[c]);
+    }
+  }
+  free(nc);
+  free(newn);
+  return rc;
+}
+
 int orc_step(orc_ctx *o, double dt, uint32_t n_steps) {
   if (!o || !o->loaded) return E_STATE;
   if (!(dt > 0.0)) return E_INVAL;
   for (uint32_t s = 0; s < n_steps; ++s) {
+    if (o->spatial) {
+      int rc = move_and_rebin(o, dt);
+      if (rc) return rc;
+    }
     for (uint32_t c = 0; c < o->n_cells; ++c) {
       int rc = step_cell(o, c, dt);
       if (rc) return rc;
@@ -1868,6 +2050,17 @@ int orc_read_cell(const orc_ctx *o, uint32_t cell, uint8_t *species, double *vel
     vel[3 * i + 1] = C->vy[i];
     vel[3 * i + 2] = C->vz[i];
     for (uint32_t m = 0; m < mm; ++m) levels[(size_t)i * mm + m] = C->lvl[(size_t)i * mm + m];
+  }
+  return E_OK;
+}
+
+int orc_read_pos(const orc_ctx *o, uint32_t cell, double *pos) {
+  if (!o || cell >= o->n_cells || !o->spatial) return E_INVAL;
+  const cell_t *C = &o->cells[cell];
+  for (uint32_t i = 0; i < C->n; ++i) {
+    pos[3 * i] = C->px[i];
+    pos[3 * i + 1] = C->py[i];
+    pos[3 * i + 2] = C->pz[i];
   }
   return E_OK;
 }

@@ -70,9 +70,14 @@ int orc_set_rotation(orc_ctx *o, uint32_t species, uint32_t zeta, double p_rot);
 /* rotation coupling gamma in [0, 1] of a dissociation or exchange */
 int orc_set_gamma_rot(orc_ctx *o, uint32_t reaction, double gamma);
 int orc_finalize(orc_ctx *o);
-/* rot[n] (may be NULL: all zero) holds rotational energies [J] */
+/* rot[n] (may be NULL: all zero) holds rotational energies [J]; pos[3n]
+ * positions (spatial mode, required there; else ignored) */
 int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *species, const double *vel,
-             const uint16_t *levels, const double *rot);
+             const uint16_t *levels, const double *rot, const double *pos);
+/* spatial mode: box of nx x ny x nz cells, periodic axes as bits 0..2 */
+int orc_set_domain(orc_ctx *o, uint32_t nx, uint32_t ny, uint32_t nz, double lx, double ly, double lz,
+                   uint32_t periodic);
+int orc_read_pos(const orc_ctx *o, uint32_t cell, double *pos);
 int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, const double *t_vib);
 int orc_step(orc_ctx *o, double dt, uint32_t n_steps);
 

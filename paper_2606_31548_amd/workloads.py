@@ -94,6 +94,7 @@ class Workload:
     seed: int = 0
     capacity_per_cell: int = 0
     notes: str = ""
+    domain: Optional[tuple] = None  # spatial mode: (nx, ny, nz, lx, ly, lz, periodic axis bits)
 
     @property
     def n_cells(self) -> int:
@@ -226,6 +227,29 @@ def batched_reservoirs(n_res=4096, lo=1_000, hi=100_000, seed=0, steps=1000):
 # ---------------------------------------------------------------------------
 # seeded random particle states (for the host-array load path)
 # ---------------------------------------------------------------------------
+
+def spatial_box(nx=16, ny=16, nz=16, per_cell=256, cell_edge=1e-4, periodic=0, chemistry=False,
+                t_trans=20_000.0, t_vib=300.0, dt=1e-8, seed=0):
+    """A box of nx x ny x nz cubic cells of edge cell_edge [m] at density
+    1e22 m^-3 (F_N = n V_cell / per_cell), walls specular except on the
+    periodic axes (bits 0..2). Species and reactions of the methane/argon
+    workload (or, with chemistry=True, the CH4/CH3/H/H2 chemistry at
+    t_trans). A particle at 5 km/s crosses half a 0.1 mm cell per 1e-8 s
+    step, so the per-step re-binning moves a large share of particles."""
+    n_cells = nx * ny * nz
+    vol = cell_edge ** 3
+    if chemistry:
+        base = methane_chemistry(n_cells=n_cells, per_cell=per_cell, recombination=True, t=t_trans, dt=dt)
+    else:
+        base = methane_argon(n_cells=n_cells, per_cell=per_cell, t_trans=t_trans, t_vib=t_vib)
+        base.dt = dt
+    base.cell_volume = np.full(n_cells, vol)
+    base.cell_weight = np.full(n_cells, DENSITY * vol / per_cell)
+    base.domain = (nx, ny, nz, nx * cell_edge, ny * cell_edge, nz * cell_edge, periodic)
+    base.name = f"box-{nx}x{ny}x{nz}"
+    base.seed = seed
+    return base
+
 
 def random_state(wl: Workload, seed: int, max_level: int = 3, level_fraction: float = 0.5):
     """Particles in canonical cell order with Maxwellian velocities at each

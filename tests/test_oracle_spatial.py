@@ -1,0 +1,136 @@
+"""Spatial mode (movement and re-binning): pins of the oracle's
+ballistic move with periodic and specular walls against closed-form
+trajectories, of the stable counting-sort re-bin, of the uniform thermal
+placement, and of conservation in closed and periodic boxes."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2606_31548_amd import workloads as W
+
+KB, AMU = W.K_BOLTZ, W.AMU
+
+
+def _free_box(orc, periodic, nx=4, ny=3, nz=2, edge=1e-4, n=600, seed=5):
+    """Argon-like tracers that never collide (F_N tiny), one bend level
+    per particle as its identity."""
+    sp = [W.Species("tracer", 40 * AMU, bend_theta_K=[1000.0])]
+    n_cells = nx * ny * nz
+    o = orc.Oracle(seed, n_cells, edge ** 3, 1e-30, capacity_per_cell=n)
+    o.set_domain(nx, ny, nz, nx * edge, ny * edge, nz * edge, periodic)
+    o.add_species(sp[0])
+    o.finalize()
+    rng = np.random.default_rng(seed)
+    L = np.array([nx * edge, ny * edge, nz * edge])
+    pos = rng.random((n, 3)) * L
+    vel = rng.standard_normal((n, 3)) * 3000.0
+    d = L / np.array([nx, ny, nz])
+    ijk = np.minimum(np.floor(pos / d).astype(int), np.array([nx, ny, nz]) - 1)
+    cell = (ijk[:, 0] + nx * (ijk[:, 1] + ny * ijk[:, 2])).astype(np.uint32)
+    order = np.argsort(cell, kind="stable")
+    ids = np.arange(n, dtype=np.uint16)
+    o.load(cell[order], np.zeros(n, np.uint8), vel[order], ids[order][:, None], None, pos[order])
+    return o, L, d, pos[order], vel[order], ids[order], (nx, ny, nz)
+
+
+def _read(o, n_cells):
+    ids, pos, vel, cells = [], [], [], []
+    for c in range(n_cells):
+        s, v, lv = o.read_cell(c)
+        ids.append(lv[:, 0].astype(int))
+        vel.append(v)
+        pos.append(o.read_pos(c))
+        cells.append(np.full(len(s), c))
+    return (np.concatenate(ids), np.concatenate(pos), np.concatenate(vel), np.concatenate(cells))
+
+
+@pytest.mark.parametrize("periodic", [0b000, 0b111, 0b101])
+def test_free_flight_matches_closed_form(orc, periodic):
+    """No collisions: after k steps x = x0 + v t wrapped (periodic) or folded
+    (specular, x mod 2L mirrored into [0, L] with the velocity's sign flipped
+    once per fold) on each axis; every particle sits in the cell holding it;
+    within a cell the particles keep their previous order."""
+    o, L, d, p0, v0, ids, dims = _free_box(orc, periodic)
+    n_cells = int(np.prod(dims))
+    dt, k = 2e-8, 25
+    order_before = ids.copy()
+    for step in range(k):
+        prev_ids = _read(o, n_cells)[0]
+        o.step(dt, 1)
+        ids1, p1, v1, cells = _read(o, n_cells)
+        rank = {int(i): r for r, i in enumerate(prev_ids)}
+        for c in range(n_cells):
+            r = np.array([rank[int(i)] for i in ids1[cells == c]])
+            assert np.all(np.diff(r) > 0), "re-bin is not stable"
+    t = dt * k
+    idx = np.argsort(ids1)
+    p1, v1 = p1[idx], v1[idx]
+    for ax in range(3):
+        y = p0[np.argsort(ids), ax] + v0[np.argsort(ids), ax] * t
+        vv = v0[np.argsort(ids), ax]
+        if (periodic >> ax) & 1:
+            want = np.mod(y, L[ax])
+            want_v = vv
+        else:
+            r = np.mod(y, 2 * L[ax])
+            want = np.where(r <= L[ax], r, 2 * L[ax] - r)
+            flips = np.floor(y / L[ax]).astype(int)
+            want_v = np.where(flips % 2 == 0, vv, -vv)
+        np.testing.assert_allclose(p1[:, ax], want, rtol=0, atol=1e-9 * L[ax])
+        np.testing.assert_array_equal(v1[:, ax], want_v)
+    ijk = np.minimum(np.floor(p1 / d).astype(int), np.array(dims) - 1)
+    assert np.all((ijk[:, 0] + dims[0] * (ijk[:, 1] + dims[1] * ijk[:, 2]))[np.argsort(idx)] == cells)
+
+
+def test_thermal_init_places_particles_uniformly_in_their_cells(orc):
+    wl = W.spatial_box(nx=4, ny=4, nz=2, per_cell=400)
+    o = orc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    nx, ny, nz, lx, ly, lz, _ = wl.domain
+    d = np.array([lx / nx, ly / ny, lz / nz])
+    rel = []
+    for c in range(wl.n_cells):
+        p = o.read_pos(c)
+        ijk = np.array([c % nx, (c // nx) % ny, c // (nx * ny)])
+        u = p / d - ijk
+        assert np.all(u >= 0) and np.all(u < 1)
+        rel.append(u)
+    rel = np.concatenate(rel)
+    for ax in range(3):
+        assert stats.kstest(rel[:, ax], "uniform").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("periodic", [0b000, 0b111])
+def test_box_with_collisions_conserves(orc, periodic):
+    """Methane/argon in a box with movement, re-binning, collisions and
+    dissociation: particle energy (kinetic + vibrational + formation) is
+    conserved to rounding; a fully periodic box also conserves momentum;
+    particles move between cells."""
+    wl = W.spatial_box(nx=4, ny=4, nz=4, per_cell=128, periodic=periodic, t_trans=30000.0)
+    o = orc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+
+    def totals():
+        e, p, n = 0.0, np.zeros(3), 0
+        for c in range(wl.n_cells):
+            m = o.moments(c)
+            e += 0.5 * m.sum_mv2 + m.formation + m.evib.sum()
+            p += m.momentum
+            n += int(m.count.sum())
+        return e, p, n
+
+    e0, p0, n0 = totals()
+    counts0 = np.array([o.count(c) for c in range(wl.n_cells)])
+    o.step(wl.dt, 40)
+    e1, p1, n1 = totals()
+    counts1 = np.array([o.count(c) for c in range(wl.n_cells)])
+    ctr = o.counters().sum(0)
+    assert abs(e1 / e0 - 1) < 1e-12
+    assert n1 - n0 == int(ctr[orc.CTR_BIRTHS]) - int(ctr[orc.CTR_DEATHS])
+    assert ctr[orc.CTR_COLLISIONS] > 1000
+    assert np.any(counts1 != counts0)
+    if periodic == 0b111:
+        scale = np.abs(p0).max() + 1e-20 + math.sqrt(n0) * 40 * AMU * 3000.0
+        assert np.all(np.abs(p1 - p0) < 1e-9 * scale)

@@ -234,31 +234,53 @@ typedef struct {
   double T_rot_K[HCAO_MAX_SPECIES]; /* 2 E_rot / (zeta k N_s) (0 without a rotor) */
 } hcao_moments;
 
+/* Spatial mode (the steps either side of the collision step): the cells
+ * tile the box [0, lx) x [0, ly) x [0, lz) as an nx x ny x nz grid, cell =
+ * ix + nx (iy + ny iz); bit k of periodic makes axis k periodic, else its
+ * two walls reflect specularly. */
+typedef struct {
+  uint32_t nx, ny, nz, periodic;
+  double lx, ly, lz;
+} hcao_domain;
+
 const char *hcao_status_string(hcao_status s);
 const char *hcao_last_error(const hcao_ctx *ctx);
 
 hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out);
 hcao_status hcao_add_species(hcao_ctx *ctx, const hcao_species_desc *sp, int32_t *id);
 hcao_status hcao_add_reaction(hcao_ctx *ctx, const hcao_reaction_desc *rx, int32_t *id);
+/* Turns on the spatial mode (before finalize): particles carry positions
+ * [m]; every step moves each particle ballistically over dt (periodic axes
+ * wrap into [0, L), the others reflect: x < 0 -> -x, x > L -> 2L - x, the
+ * velocity component reversed, until inside), re-bins all particles by a
+ * stable counting sort on their new cell on the device (within a cell the
+ * previous cell-major order is kept), and then collides. n_cells must be
+ * nx ny nz and every cell volume the grid cell's. A cell that would exceed
+ * its slot capacity raises HCAO_ECAPACITY. hcao_step_graph and
+ * hcao_autotune are not available in this mode (HCAO_EUNSUPPORTED). */
+hcao_status hcao_set_domain(hcao_ctx *ctx, const hcao_domain *domain);
 /* Builds the level, pair and reaction tables and uploads them. */
 hcao_status hcao_finalize(hcao_ctx *ctx);
 
 /* Loads n particles from host arrays in any order: cell[n] (< n_cells),
  * species[n], vel[3n] (x,y,z per particle), levels[n * max_modes].
  * rot[n] (may be NULL: none) rotational energies [J], >= 0 and 0 for
- * species without a rotor. Particles are placed by a stable counting sort
+ * species without a rotor; pos[3n] positions [m] (spatial mode: required,
+ * inside the box and in the particle's cell; otherwise ignored). Particles
+ * are placed by a stable counting sort
  * on the device, so each cell keeps the given relative order. Resets the
  * step counter to 0 and sets each cell's (sigma g)_max to an upper bound
  * over its initial pairs. */
 hcao_status hcao_load_particles(hcao_ctx *ctx, uint64_t n, const uint32_t *cell, const uint8_t *species,
-                                const double *vel, const uint16_t *levels, const double *rot);
+                                const double *vel, const uint16_t *levels, const double *rot, const double *pos);
 
 /* Thermal initial state on the device: counts[n_cells * n_species] particles
  * per cell and species (species-major within a cell), Maxwellian velocities
  * at t_trans[c] and vibrational levels at t_vib[c] (the paper's
  * initialization: bends by the floor form, stretches by Eq. accept-quant
- * with a proposal over 0..i_diss) and rotational energies of rotors from
- * Gamma(zeta/2, k t_trans[c]). */
+ * with a proposal over 0..i_diss), rotational energies of rotors from
+ * Gamma(zeta/2, k t_trans[c]) and, in the spatial mode, positions uniform
+ * in the cell. */
 hcao_status hcao_init_thermal(hcao_ctx *ctx, const uint32_t *counts, const double *t_trans,
                               const double *t_vib);
 
@@ -318,6 +340,9 @@ hcao_status hcao_read_particles(hcao_ctx *ctx, uint8_t *species, double *vel, ui
 /* Rotational energies [J] of every live particle, rot[total], in the order
  * of hcao_read_particles (all 0 when no species has a rotor). */
 hcao_status hcao_read_rotational_energy(hcao_ctx *ctx, double *rot);
+/* Positions [m] of every live particle, pos[3 total], in the order of
+ * hcao_read_particles (spatial mode only, else HCAO_ESTATE). */
+hcao_status hcao_read_positions(hcao_ctx *ctx, double *pos);
 
 /* The live particles of one cell in canonical order (for sampled checks of
  * large runs): writes min(count, max_n) particles into species[max_n],

@@ -759,6 +759,7 @@ struct PairLocal {
   int32_t rec_i;  // recombination table node of the cell temperature (-1: below, -2: above)
   double rec_f;
   double r0, r1, rn;  // rotational energies of p, q and the product (rotors only)
+  uint32_t nb_from;   // side (0: p, 1: q) whose position the product takes
 };
 
 __device__ __forceinline__ double vib_local(const Tab &T, uint32_t sp, const uint16_t *lv, uint32_t ls) {
@@ -1183,6 +1184,7 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     P.born = true;
     P.nb_sp = (uint32_t)RX.d;
     P.nb_v = y2;
+    P.nb_from = side;
     atomicAdd(&C.ctr[HCAO_CTR_BIRTHS], 1ull);
   }
   if (kind == 3) {
@@ -1649,6 +1651,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       for (uint32_t m = 0; m < mm; ++m) A.scratch.lvl[m * A.scratch.stride + gb] = P.lvn[m * BLOCK];
       if constexpr (EX) {
         if (A.scratch.rot) A.scratch.rot[gb] = P.rn;
+        if (A.st.px) {
+          const uint64_t gs = P.nb_from ? gq : gp;
+          A.scratch.px[gb] = A.st.px[gs];
+          A.scratch.py[gb] = A.st.py[gs];
+          A.scratch.pz[gb] = A.st.pz[gs];
+        }
       }
       bflag[j] = 1;
     }
@@ -1693,6 +1701,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             if (live) rv = A.st.rot[src];
             if (live) A.st.rot[dst] = rv;
           }
+          if (A.st.px) {
+            double x = 0.0, y = 0.0, z = 0.0;
+            if (live) {
+              x = A.st.px[src];
+              y = A.st.py[src];
+              z = A.st.pz[src];
+            }
+            if (live) {
+              A.st.px[dst] = x;
+              A.st.py[dst] = y;
+              A.st.pz[dst] = z;
+            }
+          }
         }
         kept += (uint32_t)__popcll(m);
       }
@@ -1714,6 +1735,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             A.st.lvl[mo * A.st.stride + to] = A.scratch.lvl[mo * A.scratch.stride + from];
           if constexpr (EX) {
             if (A.st.rot) A.st.rot[to] = A.scratch.rot[from];
+            if (A.st.px) {
+              A.st.px[to] = A.scratch.px[from];
+              A.st.py[to] = A.scratch.py[from];
+              A.st.pz[to] = A.scratch.pz[from];
+            }
           }
         }
         done += (uint32_t)__popcll(m);
@@ -1791,6 +1817,8 @@ struct InitArgs {
   const double *t_trans, *t_vib;
   uint64_t seed;
   uint32_t n_cells;
+  uint32_t nx, ny, nz;  // spatial mode grid (positions drawn when st.px is set)
+  double len[3];
 };
 
 __global__ __launch_bounds__(256) void k_init(InitArgs A) {
@@ -1856,6 +1884,13 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
         e = (kBoltz * tt) * gm;
       }
       A.st.rot[g] = e;
+    }
+    if (A.st.px) {
+      // spatial mode: uniform in the cell, one draw per axis
+      const uint32_t ix = c % A.nx, iy = (c / A.nx) % A.ny, iz = c / (A.nx * A.ny);
+      A.st.px[g] = ((double)ix + rng.uniform()) * (A.len[0] / (double)A.nx);
+      A.st.py[g] = ((double)iy + rng.uniform()) * (A.len[1] / (double)A.ny);
+      A.st.pz[g] = ((double)iz + rng.uniform()) * (A.len[2] / (double)A.nz);
     }
   }
 }
@@ -2125,6 +2160,7 @@ struct PlaceArgs {
   const double *vel;
   const uint16_t *lvl;
   const double *rot;  // may be null
+  const double *pos;  // 3n, spatial mode
   State st;
   uint64_t n;
 };
@@ -2140,6 +2176,11 @@ __global__ __launch_bounds__(256) void k_load_place(PlaceArgs A) {
   A.st.sp[g] = A.sp[src];
   for (uint32_t m = 0; m < mm; ++m) A.st.lvl[m * A.st.stride + g] = A.lvl[src * mm + m];
   if (A.st.rot) A.st.rot[g] = A.rot ? A.rot[src] : 0.0;
+  if (A.st.px) {
+    A.st.px[g] = A.pos[3 * src];
+    A.st.py[g] = A.pos[3 * src + 1];
+    A.st.pz[g] = A.pos[3 * src + 2];
+  }
 }
 
 // advances the device step index after the launches of a graph replay
@@ -2332,6 +2373,98 @@ __global__ __launch_bounds__(256) void k_rec_sum(RecSumArgs A) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// spatial mode: ballistic move with periodic or specular walls, then a
+// re-bin by a stable radix sort on the new cell
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double move_axis(double x, double &v, double dt, double len, bool periodic) {
+  double y = x + v * dt;
+  if (periodic) {
+    while (y < 0.0) y = y + len;
+    while (y >= len) y = y - len;
+  } else {
+    for (;;) {
+      if (y < 0.0) {
+        y = -y;
+        v = -v;
+      } else if (y > len) {
+        y = (len + len) - y;
+        v = -v;
+      } else {
+        break;
+      }
+    }
+  }
+  return y;
+}
+
+__device__ __forceinline__ uint32_t axis_index(double x, double len, uint32_t n) {
+  const double f = floor(x / (len / (double)n));
+  if (!(f >= 0.0)) return 0;
+  if (f >= (double)n) return n - 1;
+  return (uint32_t)f;
+}
+
+__global__ __launch_bounds__(256) void k_move(MoveArgs A) {
+  const uint32_t c = blockIdx.x;
+  const uint64_t base = A.off[c];
+  const uint32_t n = A.cnt[c], cap = A.cap[c];
+  for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
+    const uint64_t g = base + i;
+    uint32_t key = A.n_cells;
+    if (i < n) {
+      const Vec3 v = load_vel(A.st, g);
+      double vx = v.x, vy = v.y, vz = v.z;
+      const double x = move_axis(A.st.px[g], vx, A.dt, A.len[0], (A.periodic & 1u) != 0);
+      const double y = move_axis(A.st.py[g], vy, A.dt, A.len[1], (A.periodic & 2u) != 0);
+      const double z = move_axis(A.st.pz[g], vz, A.dt, A.len[2], (A.periodic & 4u) != 0);
+      A.st.px[g] = x;
+      A.st.py[g] = y;
+      A.st.pz[g] = z;
+      store_vel(A.st, g, vx, vy, vz);
+      key = axis_index(x, A.len[0], A.nx) + A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
+    }
+    A.key[g] = key;
+    A.idx[g] = (uint32_t)g;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_count_keys(const uint32_t *key, uint64_t n, uint32_t n_cells, uint32_t *cnt) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t k = key[j];
+  if (k < n_cells) atomicAdd(&cnt[k], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_place_moved(PlaceMovedArgs A) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= A.n) return;
+  const uint32_t k = A.key[j];
+  if (k >= A.n_cells) return;
+  const uint64_t rank = j - A.packed[k];
+  if (rank >= A.cap[k]) {
+    atomicOr(A.err, kErrCapacity);
+    return;
+  }
+  const uint64_t src = A.idx[j], dst = A.off[k] + rank;
+  if (A.src.fx) {
+    A.dst.fx[dst] = A.src.fx[src];
+    A.dst.fy[dst] = A.src.fy[src];
+    A.dst.fz[dst] = A.src.fz[src];
+  } else {
+    A.dst.vx[dst] = A.src.vx[src];
+    A.dst.vy[dst] = A.src.vy[src];
+    A.dst.vz[dst] = A.src.vz[src];
+  }
+  A.dst.sp[dst] = A.src.sp[src];
+  for (uint32_t m = 0; m < A.mm; ++m) A.dst.lvl[m * A.dst.stride + dst] = A.src.lvl[m * A.src.stride + src];
+  if (A.src.rot) A.dst.rot[dst] = A.src.rot[src];
+  A.dst.px[dst] = A.src.px[src];
+  A.dst.py[dst] = A.src.py[src];
+  A.dst.pz[dst] = A.src.pz[src];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2392,8 +2525,8 @@ hipError_t set_step_lds_limit(size_t bytes) {
 
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
-                       hipStream_t s) {
-  InitArgs a{tab, lev, st, off, counts, tt, tv, seed, n_cells};
+                       const uint32_t grid[3], const double len[3], hipStream_t s) {
+  InitArgs a{tab, lev, st, off, counts, tt, tv, seed, n_cells, grid[0], grid[1], grid[2], {len[0], len[1], len[2]}};
   hipLaunchKernelGGL(k_init, dim3(n_cells), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -2453,6 +2586,24 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
 
 uint64_t sort_tiles(uint64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
+hipError_t launch_move(const MoveArgs &a, hipStream_t s) {
+  if (a.n_cells == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move, dim3(a.n_cells), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_keys(const uint32_t *key, uint64_t n, uint32_t n_cells, uint32_t *cnt, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, n, n_cells, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_place_moved(const PlaceMovedArgs &a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_place_moved, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_rec_enum(const RecEnumArgs &a, bool write, hipStream_t s) {
   if (a.n_prefix == 0) return hipSuccess;
   const dim3 grid((unsigned)((a.n_prefix + 255) / 256));
@@ -2471,8 +2622,9 @@ hipError_t launch_rec_sum(const RecSumArgs &a, uint32_t n_t, size_t lds, hipStre
 
 hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
                         const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,
-                        const uint16_t *lvl, const double *rot, const State &st, uint64_t n, hipStream_t s) {
-  PlaceArgs a{tab, sorted_cell, sorted_idx, packed_start, off, sp, vel, lvl, rot, st, n};
+                        const uint16_t *lvl, const double *rot, const double *pos, const State &st, uint64_t n,
+                        hipStream_t s) {
+  PlaceArgs a{tab, sorted_cell, sorted_idx, packed_start, off, sp, vel, lvl, rot, pos, st, n};
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_load_place, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -25,7 +25,10 @@ hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s);
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
-                       hipStream_t s);
+                       const uint32_t grid[3], const double len[3], hipStream_t s);
+hipError_t launch_move(const MoveArgs &a, hipStream_t s);
+hipError_t launch_count_keys(const uint32_t *key, uint64_t n, uint32_t n_cells, uint32_t *cnt, hipStream_t s);
+hipError_t launch_place_moved(const PlaceMovedArgs &a, hipStream_t s);
 hipError_t launch_cell_init(const Tables *tab, const State &st, const CellArrays &cells, uint32_t n_cells,
                             hipStream_t s);
 hipError_t launch_moments(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
@@ -41,7 +44,8 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
 uint64_t sort_tiles(uint64_t n);
 hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
                         const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,
-                        const uint16_t *lvl, const double *rot, const State &st, uint64_t n, hipStream_t s);
+                        const uint16_t *lvl, const double *rot, const double *pos, const State &st, uint64_t n,
+                        hipStream_t s);
 }  // namespace hcao
 
 using namespace hcao;
@@ -124,6 +128,13 @@ struct hcao_ctx {
   DevBuf<uint8_t> sp, bsp;
   DevBuf<uint16_t> lvl, blvl;
   DevBuf<double> rot, brot;  // rotational energies (only when some species has a rotor)
+  // spatial mode: positions, and the re-bin's sort buffers (all slots)
+  bool spatial = false;
+  uint32_t grid[3] = {1, 1, 1}, periodic = 0;
+  double len[3] = {0.0, 0.0, 0.0};
+  DevBuf<double> px, py, pz, bpx, bpy, bpz;
+  DevBuf<uint32_t> mv_key, mv_idx, mv_key_tmp, mv_idx_tmp, mv_hist, mv_cnt;
+  DevBuf<uint64_t> mv_offs, mv_packed;
   DevBuf<uint64_t> off;
   DevBuf<uint32_t> cnt, cap;
   DevBuf<double> d_volume, d_weight, sgmax, rem, defect;
@@ -239,6 +250,20 @@ void free_state(hcao_ctx *c) {
   c->blvl.release();
   c->rot.release();
   c->brot.release();
+  c->px.release();
+  c->py.release();
+  c->pz.release();
+  c->bpx.release();
+  c->bpy.release();
+  c->bpz.release();
+  c->mv_key.release();
+  c->mv_idx.release();
+  c->mv_key_tmp.release();
+  c->mv_idx_tmp.release();
+  c->mv_hist.release();
+  c->mv_cnt.release();
+  c->mv_offs.release();
+  c->mv_packed.release();
   c->off.release();
   c->cnt.release();
   c->cap.release();
@@ -263,11 +288,12 @@ uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
 }
 
 State state_of(hcao_ctx *c) {
-  return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->rot.p, c->total_slots};
+  return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->rot.p,
+               c->px.p, c->py.p, c->pz.p, c->total_slots};
 }
 State scratch_of(hcao_ctx *c) {
   return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->brot.p,
-               c->total_slots};
+               c->bpx.p, c->bpy.p, c->bpz.p, c->total_slots};
 }
 CellArrays cells_of(hcao_ctx *c) {
   return CellArrays{c->off.p,   c->cnt.p, c->cap.p,    c->d_volume.p, c->d_weight.p,
@@ -424,6 +450,22 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
     HIP_TRY(c, c->rot.alloc(tot));
     HIP_TRY(c, c->brot.alloc(tot));
     HIP_TRY(c, hipMemsetAsync(c->rot.p, 0, tot * sizeof(double), c->stream));
+  }
+  if (c->spatial) {
+    HIP_TRY(c, c->px.alloc(tot));
+    HIP_TRY(c, c->py.alloc(tot));
+    HIP_TRY(c, c->pz.alloc(tot));
+    HIP_TRY(c, c->bpx.alloc(tot));
+    HIP_TRY(c, c->bpy.alloc(tot));
+    HIP_TRY(c, c->bpz.alloc(tot));
+    HIP_TRY(c, c->mv_key.alloc(tot));
+    HIP_TRY(c, c->mv_idx.alloc(tot));
+    HIP_TRY(c, c->mv_key_tmp.alloc(tot));
+    HIP_TRY(c, c->mv_idx_tmp.alloc(tot));
+    HIP_TRY(c, c->mv_hist.alloc(256 * sort_tiles(tot)));
+    HIP_TRY(c, c->mv_offs.alloc(256 * sort_tiles(tot)));
+    HIP_TRY(c, c->mv_cnt.alloc(nc));
+    HIP_TRY(c, c->mv_packed.alloc(nc));
   }
   HIP_TRY(c, c->off.alloc(nc + 1));
   HIP_TRY(c, c->cnt.alloc(nc));
@@ -1130,7 +1172,7 @@ hcao_status hcao_finalize(hcao_ctx *c) {
 }
 
 hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, const uint8_t *species,
-                                const double *vel, const uint16_t *levels, const double *rot) {
+                                const double *vel, const uint16_t *levels, const double *rot, const double *pos) {
   if (!c) return HCAO_EINVAL;
   if (hcao_status s = check_sticky(c)) return s;
   if (!c->finalized) return fail(c, HCAO_ESTATE, "load before finalize");
@@ -1143,6 +1185,23 @@ hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, c
       if (!(rot[i] >= 0.0) || !std::isfinite(rot[i]) || (rot[i] != 0.0 && !rotor))
         return fail(c, HCAO_EINVAL, "rotational energy must be finite, >= 0, and 0 without a rotor");
     }
+  }
+  DevBuf<double> d_pos;
+  if (c->spatial) {
+    if (n && !pos) return fail(c, HCAO_EINVAL, "the spatial mode needs positions");
+    for (uint64_t i = 0; i < n; ++i) {
+      uint32_t ijk[3];
+      for (int k = 0; k < 3; ++k) {
+        const double x = pos[3 * i + k];
+        if (!(x >= 0.0) || !(x <= c->len[k])) return fail(c, HCAO_EINVAL, "position outside the box");
+        const double f = std::floor(x / (c->len[k] / (double)c->grid[k]));
+        ijk[k] = !(f >= 0.0) ? 0u : (f >= (double)c->grid[k] ? c->grid[k] - 1 : (uint32_t)f);
+      }
+      if (ijk[0] + c->grid[0] * (ijk[1] + c->grid[1] * ijk[2]) != cell[i])
+        return fail(c, HCAO_EINVAL, "position not in the particle's cell");
+    }
+    HIP_TRY(c, d_pos.alloc(3 * n));
+    if (n) HIP_TRY(c, hipMemcpyAsync(d_pos.p, pos, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
   }
   DevBuf<double> d_rot;
   if (rot && c->tab.has_rot) {
@@ -1194,8 +1253,8 @@ hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, c
   HIP_TRY(c, launch_scan_u32(c->cnt.p, packed.p, nc, c->stream));
   const uint32_t *sk = in_tmp ? keys_tmp.p : d_cell.p;
   const uint32_t *si = in_tmp ? idx_tmp.p : idx.p;
-  HIP_TRY(c, launch_place(c->d_tab.p, sk, si, packed.p, c->off.p, d_sp.p, d_vel.p, d_lvl.p, d_rot.p, state_of(c),
-                          n, c->stream));
+  HIP_TRY(c, launch_place(c->d_tab.p, sk, si, packed.p, c->off.p, d_sp.p, d_vel.p, d_lvl.p, d_rot.p, d_pos.p,
+                          state_of(c), n, c->stream));
   HIP_TRY(c, launch_cell_init(c->d_tab.p, state_of(c), cells_of(c), nc, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   d_cell.release();
@@ -1229,7 +1288,7 @@ hcao_status hcao_init_thermal(hcao_ctx *c, const uint32_t *counts, const double 
   HIP_TRY(c, hipMemcpyAsync(d_tt.p, t_trans, nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(d_tv.p, t_vib, nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_init(c->d_tab.p, c->d_lev.p, state_of(c), c->off.p, d_counts.p, d_tt.p, d_tv.p, c->cfg.seed, nc,
-                         c->stream));
+                         c->grid, c->len, c->stream));
   HIP_TRY(c, launch_cell_init(c->d_tab.p, state_of(c), cells_of(c), nc, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->step = 0;
@@ -1262,8 +1321,81 @@ StepArgs step_args(hcao_ctx *c, double dt) {
 // Issues the step-kernel launches of n_steps steps on stream s. With
 // step_dev, the launches read their base step index from the device and a
 // final kernel advances it; otherwise base is the first step's index.
+// spatial mode: move every particle over dt, then re-bin all of them by a
+// stable radix sort on the new cell into the staging buffers, which then
+// become the state (the old state becomes the products staging)
+hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
+  const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
+  const uint64_t tot = c->total_slots;
+  MoveArgs m{};
+  m.st = state_of(c);
+  m.off = c->off.p;
+  m.cnt = c->cnt.p;
+  m.cap = c->cap.p;
+  m.n_cells = nc;
+  m.nx = c->grid[0];
+  m.ny = c->grid[1];
+  m.nz = c->grid[2];
+  m.periodic = c->periodic;
+  for (int k = 0; k < 3; ++k) m.len[k] = c->len[k];
+  m.dt = dt;
+  m.key = c->mv_key.p;
+  m.idx = c->mv_idx.p;
+  HIP_TRY(c, launch_move(m, s));
+  uint32_t key_bits = 0;
+  while (key_bits < 32 && ((uint64_t)1 << key_bits) <= nc) ++key_bits;  // keys 0..nc (nc: empty slot)
+  key_bits = ((key_bits + 7) / 8) * 8;
+  bool in_tmp = false;
+  HIP_TRY(c, launch_sort(c->mv_key.p, c->mv_idx.p, c->mv_key_tmp.p, c->mv_idx_tmp.p, c->mv_hist.p, c->mv_offs.p, tot,
+                         key_bits, s, in_tmp));
+  const uint32_t *sk = in_tmp ? c->mv_key_tmp.p : c->mv_key.p;
+  const uint32_t *si = in_tmp ? c->mv_idx_tmp.p : c->mv_idx.p;
+  HIP_TRY(c, hipMemsetAsync(c->mv_cnt.p, 0, nc * sizeof(uint32_t), s));
+  HIP_TRY(c, launch_count_keys(sk, tot, nc, c->mv_cnt.p, s));
+  HIP_TRY(c, launch_scan_u32(c->mv_cnt.p, c->mv_packed.p, nc, s));
+  PlaceMovedArgs p{};
+  p.src = state_of(c);
+  p.dst = scratch_of(c);
+  p.key = sk;
+  p.idx = si;
+  p.packed = c->mv_packed.p;
+  p.off = c->off.p;
+  p.cap = c->cap.p;
+  p.n_cells = nc;
+  p.mm = mm;
+  p.n = tot;
+  p.err = c->err.p;
+  HIP_TRY(c, launch_place_moved(p, s));
+  HIP_TRY(c, hipMemcpyAsync(c->cnt.p, c->mv_cnt.p, nc * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  std::swap(c->vx, c->bvx);
+  std::swap(c->vy, c->bvy);
+  std::swap(c->vz, c->bvz);
+  std::swap(c->fx, c->bfx);
+  std::swap(c->fy, c->bfy);
+  std::swap(c->fz, c->bfz);
+  std::swap(c->sp, c->bsp);
+  std::swap(c->lvl, c->blvl);
+  std::swap(c->rot, c->brot);
+  std::swap(c->px, c->bpx);
+  std::swap(c->py, c->bpy);
+  std::swap(c->pz, c->bpz);
+  return HCAO_OK;
+}
+
 hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base, uint32_t *step_dev,
                         hipStream_t s, uint32_t *launches) {
+  if (c->spatial) {
+    // one collision launch per step, each after the move and re-bin
+    for (uint32_t d = 0; d < n_steps; ++d) {
+      if (hcao_status st = move_rebin(c, dt, s)) return st;
+      StepArgs a = step_args(c, dt);
+      a.step = base + d;
+      a.n_steps = 1;
+      HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, true, c->n_groups, s));
+    }
+    if (launches) *launches = n_steps;
+    return HCAO_OK;
+  }
   StepArgs a = step_args(c, dt);
   a.step_dev = step_dev;
   uint32_t n = 0;
@@ -1271,7 +1403,8 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
     const uint32_t k = std::min(n_steps - done, c->steps_per_launch);
     a.step = (step_dev ? 0u : base) + done;
     a.n_steps = k;
-    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->has_exact || c->tab.has_rot, c->n_groups, s));
+    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->has_exact || c->tab.has_rot || c->spatial,
+                           c->n_groups, s));
     done += k;
     ++n;
   }
@@ -1326,6 +1459,7 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
 
 hcao_status hcao_step_graph(hcao_ctx *c, double dt, uint32_t n_steps) {
   if (hcao_status s = check_step_args(c, dt)) return s;
+  if (c->spatial) return fail(c, HCAO_EUNSUPPORTED, "graph replay is not available in the spatial mode");
   if (n_steps == 0) return HCAO_OK;
   if (!c->graph_exec || c->graph_dt != dt || c->graph_n != n_steps || c->graph_gen != c->shape_gen) {
     drop_graph(c);
@@ -1467,6 +1601,7 @@ std::string tune_key(const hcao_ctx *c) {
 hcao_status hcao_autotune(hcao_ctx *c, double dt, uint32_t trial_steps, const char *cache_path,
                           hcao_launch_shape *chosen) {
   if (hcao_status s = check_step_args(c, dt)) return s;
+  if (c->spatial) return fail(c, HCAO_EUNSUPPORTED, "autotuning is not available in the spatial mode");
   if (trial_steps == 0) return fail(c, HCAO_EINVAL, "trial_steps must be > 0");
   if (!cache_path) cache_path = std::getenv("HCAO_AUTOTUNE_CACHE");
   const std::string key = tune_key(c);
@@ -1776,6 +1911,51 @@ hcao_status hcao_recombination_exact(hcao_ctx *c, uint32_t species, double de_J,
   return exact_rec_probability(c, species, de_J, omega, n_t, t_K, p_out, elapsed_ms, n_records);
 }
 
+hcao_status hcao_set_domain(hcao_ctx *c, const hcao_domain *d) {
+  if (!c || !d) return HCAO_EINVAL;
+  if (c->finalized) return fail(c, HCAO_ESTATE, "set_domain after finalize");
+  const uint32_t nc = c->cfg.n_cells;
+  if (d->nx == 0 || d->ny == 0 || d->nz == 0 || (uint64_t)d->nx * d->ny * d->nz != nc)
+    return fail(c, HCAO_EINVAL, "the grid must have n_cells cells");
+  if (!(d->lx > 0.0) || !(d->ly > 0.0) || !(d->lz > 0.0) || d->periodic > 7u)
+    return fail(c, HCAO_EINVAL, "bad box lengths or periodic bits");
+  const double vc = ((d->lx * d->ly) * d->lz) / (double)nc;
+  for (uint32_t i = 0; i < nc; ++i)
+    if (std::fabs(c->volume[i] - vc) > 1e-9 * vc) return fail(c, HCAO_EINVAL, "cell volume differs from the grid cell");
+  c->spatial = true;
+  c->grid[0] = d->nx;
+  c->grid[1] = d->ny;
+  c->grid[2] = d->nz;
+  c->periodic = d->periodic;
+  c->len[0] = d->lx;
+  c->len[1] = d->ly;
+  c->len[2] = d->lz;
+  return HCAO_OK;
+}
+
+hcao_status hcao_read_positions(hcao_ctx *c, double *pos) {
+  if (!c || !pos) return HCAO_EINVAL;
+  if (!c->loaded || !c->spatial) return fail(c, HCAO_ESTATE, "no positions (spatial mode only)");
+  const uint64_t tot = c->total_slots;
+  const uint32_t nc = c->cfg.n_cells;
+  std::vector<uint32_t> cnt(nc);
+  std::vector<double> x(tot), y(tot), z(tot);
+  HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(x.data(), c->px.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(y.data(), c->py.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(z.data(), c->pz.p, tot * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  uint64_t j = 0;
+  for (uint32_t cell = 0; cell < nc; ++cell)
+    for (uint32_t i = 0; i < cnt[cell]; ++i, ++j) {
+      const uint64_t g = c->off_host[cell] + i;
+      pos[3 * j] = x[g];
+      pos[3 * j + 1] = y[g];
+      pos[3 * j + 2] = z[g];
+    }
+  return HCAO_OK;
+}
+
 hcao_status hcao_get_exact_beta(const hcao_ctx *c, uint32_t species, uint32_t partner, double e_J, double *beta) {
   if (!c || !beta || !c->finalized || species >= c->species.size() || partner >= c->species.size() || !(e_J > 0.0))
     return HCAO_EINVAL;
@@ -1829,11 +2009,18 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   HIP_TRY(c, hipMemcpy(ctr.data(), c->ctr.p, ctr.size() * 8, hipMemcpyDeviceToHost));
   std::vector<double> rt(c->rot.p ? tot : 0);
   if (c->rot.p) HIP_TRY(c, hipMemcpy(rt.data(), c->rot.p, tot * 8, hipMemcpyDeviceToHost));
+  std::vector<double> pos(c->spatial ? 3 * tot : 0);
+  if (c->spatial) {
+    HIP_TRY(c, hipMemcpy(pos.data(), c->px.p, tot * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(pos.data() + tot, c->py.p, tot * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(pos.data() + 2 * tot, c->pz.p, tot * 8, hipMemcpyDeviceToHost));
+  }
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(c, HCAO_EINVAL, std::string("cannot open ") + path);
   // velocities are stored as fp64 in both forms (exact for fp32 values);
-  // word 6: bit 0 mixed form, bit 1 rotational energies follow the levels
-  const uint64_t form = (c->mixed ? 1ull : 0ull) | (c->rot.p ? 2ull : 0ull);
+  // word 6: bit 0 mixed form, bit 1 rotational energies follow the levels,
+  // bit 2 positions (x, y, z arrays) follow
+  const uint64_t form = (c->mixed ? 1ull : 0ull) | (c->rot.p ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull);
   const uint64_t hdr[7] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step, form};
   bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
   ok = ok && std::fwrite(c->cap_host.data(), 4, nc, f) == nc;
@@ -1848,6 +2035,7 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   ok = ok && std::fwrite(sp.data(), 1, tot, f) == tot;
   ok = ok && std::fwrite(lv.data(), 2, lv.size(), f) == lv.size();
   ok = ok && std::fwrite(rt.data(), 8, rt.size(), f) == rt.size();
+  ok = ok && std::fwrite(pos.data(), 8, pos.size(), f) == pos.size();
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return fail(c, HCAO_EINVAL, "write failed");
   return HCAO_OK;
@@ -1862,7 +2050,8 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   uint64_t hdr[7];
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
   if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x48434130534156ull || hdr[1] != HCAO_ABI_VERSION ||
-      hdr[2] != nc || hdr[4] != mm || hdr[6] != ((c->mixed ? 1ull : 0ull) | (c->tab.has_rot ? 2ull : 0ull))) {
+      hdr[2] != nc || hdr[4] != mm ||
+      hdr[6] != ((c->mixed ? 1ull : 0ull) | (c->tab.has_rot ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull))) {
     std::fclose(f);
     return fail(c, HCAO_EINVAL, "checkpoint does not match this context");
   }
@@ -1885,6 +2074,8 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   ok = ok && std::fread(lv.data(), 2, lv.size(), f) == lv.size();
   std::vector<double> rt(c->tab.has_rot ? tot : 0);
   ok = ok && std::fread(rt.data(), 8, rt.size(), f) == rt.size();
+  std::vector<double> pos(c->spatial ? 3 * tot : 0);
+  ok = ok && std::fread(pos.data(), 8, pos.size(), f) == pos.size();
   std::fclose(f);
   if (!ok) return fail(c, HCAO_EINVAL, "truncated checkpoint");
   uint64_t t2 = 0;
@@ -1899,6 +2090,11 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   HIP_TRY(c, hipMemcpy(c->rem.p, rm.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->ctr.p, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice));
   if (c->rot.p) HIP_TRY(c, hipMemcpy(c->rot.p, rt.data(), tot * 8, hipMemcpyHostToDevice));
+  if (c->spatial) {
+    HIP_TRY(c, hipMemcpy(c->px.p, pos.data(), tot * 8, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->py.p, pos.data() + tot, tot * 8, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->pz.p, pos.data() + 2 * tot, tot * 8, hipMemcpyHostToDevice));
+  }
   c->step = (uint32_t)hdr[5];
   c->loaded = true;
   return HCAO_OK;

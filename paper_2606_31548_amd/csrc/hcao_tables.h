@@ -85,6 +85,7 @@ struct State {
   uint8_t *sp;
   uint16_t *lvl;
   double *rot;      // rotational energy [J]; null when no species has a rotor
+  double *px, *py, *pz;  // positions [m]; null outside the spatial mode
   uint64_t stride;  // total slots (all cells)
 };
 
@@ -122,6 +123,31 @@ struct StepArgs {
   uint32_t step;             // index of the launch's first step (plus *step_dev when set)
   uint32_t n_steps;          // steps advanced by this launch
   double dt;
+};
+
+// Spatial mode. Move pass: block c moves the particles of cell c over dt
+// and writes key[slot] = new cell (n_cells for empty slots) and idx[slot] =
+// slot; a stable radix sort of (key, idx) follows. Place pass: sorted entry
+// j with key k < n_cells goes to slot off[k] + (j - packed[k]) of dst.
+struct MoveArgs {
+  State st;
+  const uint64_t *off;
+  const uint32_t *cnt, *cap;
+  uint32_t n_cells, nx, ny, nz, periodic;
+  double len[3];
+  double dt;
+  uint32_t *key, *idx;
+};
+
+struct PlaceMovedArgs {
+  State src, dst;
+  const uint32_t *key, *idx;  // sorted
+  const uint64_t *packed;     // exclusive scan of the new counts
+  const uint64_t *off;
+  const uint32_t *cap;
+  uint32_t n_cells, mm;
+  uint64_t n;                 // entries (all slots)
+  uint32_t *err;
 };
 
 // Forward recombination probability summed over every level combination of

@@ -58,6 +58,10 @@ class hcao_moments(ctypes.Structure):
                 ("E_rot_J", _d * MAX_SPECIES), ("T_rot_K", _d * MAX_SPECIES)]
 
 
+class hcao_domain(ctypes.Structure):
+    _fields_ = [("nx", _u32), ("ny", _u32), ("nz", _u32), ("periodic", _u32), ("lx", _d), ("ly", _d), ("lz", _d)]
+
+
 class hcao_launch_shape(ctypes.Structure):
     _fields_ = [("block", _u32), ("group_slots", _u32), ("steps_per_launch", _u32)]
 
@@ -95,7 +99,9 @@ def load_library():
     L.hcao_add_species.argtypes = [_vp, ctypes.POINTER(hcao_species_desc), ctypes.POINTER(_i32)]
     L.hcao_add_reaction.argtypes = [_vp, ctypes.POINTER(hcao_reaction_desc), ctypes.POINTER(_i32)]
     L.hcao_finalize.argtypes = [_vp]
-    L.hcao_load_particles.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp]
+    L.hcao_load_particles.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.hcao_set_domain.argtypes = [_vp, ctypes.POINTER(hcao_domain)]
+    L.hcao_read_positions.argtypes = [_vp, _vp]
     L.hcao_read_rotational_energy.argtypes = [_vp, _vp]
     L.hcao_init_thermal.argtypes = [_vp, _vp, _vp, _vp]
     L.hcao_step.argtypes = [_vp, _d, _u32]
@@ -128,7 +134,7 @@ def load_library():
                  "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore",
                  "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
                  "hcao_read_cell_particles", "hcao_get_exact_beta", "hcao_recombination_exact",
-                 "hcao_read_rotational_energy"):
+                 "hcao_read_rotational_energy", "hcao_set_domain", "hcao_read_positions"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -237,15 +243,28 @@ class Simulation:
         self.max_modes = self._L.hcao_max_modes(self._h)
 
     # -- particles --
-    def load_particles(self, cell, species, vel, levels, rot=None):
+    def set_domain(self, nx, ny, nz, lx, ly, lz, periodic=0):
+        """Spatial mode (before finalize): box of nx x ny x nz cells."""
+        d = hcao_domain(nx, ny, nz, periodic, lx, ly, lz)
+        self._chk("hcao_set_domain", self._L.hcao_set_domain(self._h, ctypes.byref(d)))
+
+    def load_particles(self, cell, species, vel, levels, rot=None, pos=None):
         cell = np.ascontiguousarray(cell, np.uint32)
         species = np.ascontiguousarray(species, np.uint8)
         vel = np.ascontiguousarray(vel, np.float64)
         levels = np.ascontiguousarray(levels, np.uint16)
         rot = None if rot is None else np.ascontiguousarray(rot, np.float64)
+        pos = None if pos is None else np.ascontiguousarray(pos, np.float64)
         self._chk("hcao_load_particles",
                   self._L.hcao_load_particles(self._h, len(cell), _p(cell), _p(species), _p(vel), _p(levels),
-                                              _p(rot)))
+                                              _p(rot), _p(pos)))
+
+    def read_positions(self):
+        """Positions [m] of every particle, in read_particles order (spatial mode)."""
+        _, tot = self.counts()
+        out = np.zeros((tot, 3), np.float64)
+        self._chk("hcao_read_positions", self._L.hcao_read_positions(self._h, _p(out)))
+        return out
 
     def read_rotational_energy(self):
         """Rotational energies [J] of every particle, in read_particles order."""
@@ -409,6 +428,8 @@ def from_workload(wl, seed: Optional[int] = None, capacity_per_cell: Optional[in
     cap = wl.capacity_per_cell if capacity_per_cell is None else capacity_per_cell
     s = Simulation(wl.seed if seed is None else seed, wl.n_cells, wl.cell_volume, wl.cell_weight, cap,
                    stream=stream, precision=precision)
+    if getattr(wl, "domain", None) is not None:
+        s.set_domain(*wl.domain)
     for sp in wl.species:
         s.add_species(sp)
     for rx in wl.reactions:

@@ -37,22 +37,28 @@ from paper_2606_31548_amd import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(wl_species, counts_by_species, n_cells, b_v=8):
+def algorithmic_bytes(wl_species, counts_by_species, n_cells, b_v=8, spatial=False):
     """Bytes one step must read and write: every live particle's velocity
-    (3 b_v), species byte and 2-byte quantum number per mode it has, read and
-    written once, plus 64 B of per-cell state."""
-    per = np.array([2 * (3 * b_v + 1 + 2 * s.n_modes) for s in wl_species], np.float64)
+    (3 b_v), species byte, 2-byte quantum number per mode it has and, for a
+    rotor, 8-byte rotational energy, read and written once, plus 64 B of
+    per-cell state. In the spatial mode each particle also carries a 24-byte
+    position and its whole state is read and written a second time by the
+    move and re-bin."""
+    per = np.array([2 * (3 * b_v + 1 + 2 * s.n_modes + (8 if getattr(s, "zeta_rot", 0) else 0) +
+                         (24 if spatial else 0)) for s in wl_species], np.float64)
+    if spatial:
+        per = 2 * per
     return float((counts_by_species * per).sum() + 64.0 * n_cells)
 
 
-WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "triatomic")
+WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "triatomic", "box-67m")
 
 # Launch shape (workgroup size, slot target per workgroup) that the
 # library's autotuner (hcao_autotune) picks for each workload on MI355X;
 # fixed here so that a profiled run holds only the timed launches.
 # --autotune re-runs the autotuner instead.
 TUNED_SHAPE = {"chemistry-67m": (128, 2048), "chemistry-16m": (128, 2048), "methane-argon": (64, 1024),
-               "batched": (256, 4096), "triatomic": (64, 1024)}
+               "batched": (256, 4096), "triatomic": (64, 1024), "box-67m": (128, 2048)}
 
 
 def make_workload(name):
@@ -73,6 +79,12 @@ def make_workload(name):
         desc = ("4096 independent reservoirs of the CH4-like/Ar-like 1:9 chemistry, particle counts log-uniform "
                 f"in [1000, 100000] ({int(wl.n_particles)} in total), T_trans uniform in [5000, 30000] K, "
                 "T_vib 300 K, CH4+M->CH3+H+M, dt 1e-8 s")
+    elif name == "box-67m":
+        wl = W.spatial_box(nx=64, ny=64, nz=64, per_cell=256, periodic=0b111, chemistry=True, t_trans=8000.0,
+                           dt=5e-9)
+        desc = ("spatial box of 64 x 64 x 64 cells of 0.1 mm (periodic), 256 particles per cell (67.1M), "
+                "CH4/CH3/H/H2 64 each, T 8000 K, dissociation + exchange + recombination, dt 5e-9 s; every step "
+                "moves, re-bins and collides")
     elif name == "triatomic":
         wl = W.triatomic_reservoir(10000)
         desc = "1 cell x 10000 particles, synthetic triatomic, T_trans 10000 K, T_vib 300 K, dissociation"
@@ -111,24 +123,42 @@ def recombination_exact(hcao, oracle_nodes=3):
             "max_rel_diff_vs_oracle": worst}
 
 
+def set_rotors(wl, gamma=0.5):
+    """Rotors on every molecule (zeta 3 for polyatomics, 2 for diatomics),
+    rotation coupled into dissociation and exchange with gamma."""
+    for s in wl.species:
+        if s.n_modes:
+            s.zeta_rot = 2 if s.n_modes == 1 else 3
+    for r in wl.reactions:
+        if r.kind != W.RX_RECOMBINATION:
+            r.gamma_rot = gamma
+
+
 def set_sampler(wl, sampler):
     for s in wl.species:
         if s.n_modes:
             s.sampler = SAMPLERS[sampler]
 
 
-def cpu_baseline(name, target_s=15.0, sampler="auto"):
+def cpu_baseline(name, target_s=15.0, sampler="auto", rotors=False):
     """The oracle as it stands (single thread) on a bounded sample of the
-    same workload: a subset of the cells, stepped from the same kind of
-    initial state, until about target_s seconds of CPU work are done."""
+    same workload: a subset of the cells (for the spatial box an 8 x 8 x 8
+    box of the same cells), stepped from the same kind of initial state,
+    until about target_s seconds of CPU work are done."""
     import oracle
     oracle.build(force=False)
     wl, _ = make_workload(name)
-    set_sampler(wl, sampler)
     n_cells = min(wl.n_cells, 512)
-    sub = W.Workload(wl.name, wl.species, wl.reactions, wl.counts[:n_cells].copy(), wl.t_trans[:n_cells].copy(),
-                     wl.t_vib[:n_cells].copy(), wl.cell_volume[:n_cells].copy(), wl.cell_weight[:n_cells].copy(),
-                     dt=wl.dt, seed=wl.seed)
+    if getattr(wl, "domain", None) is not None:
+        sub = W.spatial_box(nx=8, ny=8, nz=8, per_cell=256, periodic=wl.domain[6], chemistry=True,
+                            t_trans=float(wl.t_trans[0]), dt=wl.dt)
+    else:
+        sub = W.Workload(wl.name, wl.species, wl.reactions, wl.counts[:n_cells].copy(),
+                         wl.t_trans[:n_cells].copy(), wl.t_vib[:n_cells].copy(), wl.cell_volume[:n_cells].copy(),
+                         wl.cell_weight[:n_cells].copy(), dt=wl.dt, seed=wl.seed)
+    set_sampler(sub, sampler)
+    if rotors:
+        set_rotors(sub)
     o = oracle.from_workload(sub)
     o.init_thermal(sub.counts, sub.t_trans, sub.t_vib)
     o.step(sub.dt, 2)  # warm-up
@@ -140,9 +170,10 @@ def cpu_baseline(name, target_s=15.0, sampler="auto"):
         steps += 5
     dt = time.perf_counter() - t0
     coll = int(o.counters()[:, oracle.CTR_COLLISIONS].sum() - c0)
+    what = (f"an 8 x 8 x 8 box of the same cells (the workload has {wl.n_cells})"
+            if getattr(wl, "domain", None) is not None else f"{n_cells} of {wl.n_cells} cells of the same workload")
     return {"value": coll / dt, "unit": "collisions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cells} of {wl.n_cells} cells of the same workload, {steps} steps after 2 warm-up "
-                      f"steps, {dt:.1f} s, single thread"}
+            "sample": f"{what}, {steps} steps after 2 warm-up steps, {dt:.1f} s, single thread"}
 
 
 def kernel_digest():
@@ -184,8 +215,8 @@ def _energy(sim, m, n_modes):
     e = m.E_kin_J + m.E_formation_J
     th = m.E_kin_J
     for s in range(len(n_modes)):
-        e += m.E_vib_J[s] + m.n_species[s] * sim.zero_point(s)
-        th += m.E_vib_J[s]
+        e += m.E_vib_J[s] + m.n_species[s] * sim.zero_point(s) + m.E_rot_J[s]
+        th += m.E_vib_J[s] + m.E_rot_J[s]
     return e, th
 
 
@@ -238,8 +269,9 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
     # algorithmic bytes per launch: per step, every live particle's state read
     # and written once plus 64 B per cell; a launch advances kernel_steps/launches steps
     b_v = 4 if precision == hcao.MIXED else 8
-    b_step = 0.5 * (algorithmic_bytes(wl.species, per_species0, wl.n_cells, b_v) +
-                    algorithmic_bytes(wl.species, per_species1, wl.n_cells, b_v))
+    spatial = getattr(wl, "domain", None) is not None
+    b_step = 0.5 * (algorithmic_bytes(wl.species, per_species0, wl.n_cells, b_v, spatial) +
+                    algorithmic_bytes(wl.species, per_species1, wl.n_cells, b_v, spatial))
     steps_per_launch = kernel_steps / max(launches, 1)
     b_alg = b_step * steps_per_launch
     avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
@@ -313,6 +345,8 @@ def main():
                          "the tuned one")
     ap.add_argument("--sampler", default="auto", choices=SAMPLERS,
                     help="relaxation sampler of every molecular species")
+    ap.add_argument("--rotors", action="store_true",
+                    help="give every molecule a rotor and couple rotation into its reactions (gamma 0.5)")
     ap.add_argument("--recomb-exact", action="store_true",
                     help="also time Eq. recomb-correct for CH4 on the device against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -339,6 +373,9 @@ def main():
 
     wl, desc = make_workload(args.workload)
     set_sampler(wl, args.sampler)
+    if args.rotors:
+        set_rotors(wl)
+        desc += "; every molecule a rotor, rotation coupling 0.5"
     spl = max(1, args.steps_per_launch)
     steps = -(-args.steps // spl) * spl
     warmup = -(-args.warmup // spl) * spl
@@ -352,7 +389,7 @@ def main():
                          graph=batched, autotune=args.autotune or batched,
                          shape=None if args.library_shape else TUNED_SHAPE[args.workload])
         res[f]["roofline"]["traffic"] = (measured_traffic(args.workload, f, spl, res[f]["launch_shape"])
-                                         if args.sampler == "auto" else None)
+                                         if args.sampler == "auto" and not args.rotors else None)
     head = res[forms[0]]
     out = {
         "metric": "HCAO collisions/s on 1 MI355X; mixed FP32/FP64 vs FP64 at fixed energy error",
@@ -387,7 +424,7 @@ def main():
         out["recombination_exact"] = recombination_exact(hcao)
     if not args.no_cpu_baseline:
         print("# timing the oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds, args.sampler)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds, args.sampler, args.rotors)
     print(json.dumps(out), flush=True)
 
 

@@ -425,9 +425,10 @@ class Oracle:
         return sp_o, vel_o, lvl_o, rot_o, rx, bsp, bvel, blvl, brot
 
 
-def from_workload(wl, seed=None, capacity_per_cell=0):
+def from_workload(wl, seed=None, capacity_per_cell=None):
     """Builds an Oracle with the species and reactions of a workloads.Workload."""
-    o = Oracle(wl.seed if seed is None else seed, wl.n_cells, wl.cell_volume, wl.cell_weight, capacity_per_cell)
+    cap = getattr(wl, "capacity_per_cell", 0) if capacity_per_cell is None else capacity_per_cell
+    o = Oracle(wl.seed if seed is None else seed, wl.n_cells, wl.cell_volume, wl.cell_weight, cap)
     if getattr(wl, "domain", None) is not None:
         o.set_domain(*wl.domain)
     for sp in wl.species:

@@ -2043,28 +2043,62 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint32_t *keys, 
 }
 
 // single-workgroup exclusive scan of a u32 array into u64 offsets
-__global__ __launch_bounds__(1024) void k_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n) {
+// Multi-block exclusive scan of u32 into u64: each 1024-thread block scans
+// a chunk of kScanChunk entries (16 per thread) and leaves its total in
+// bsum; one block then scans the totals; a third pass adds each chunk's
+// offset. Integer sums, so the result does not depend on the split.
+constexpr int kScanPer = 16;
+constexpr uint64_t kScanChunk = 1024 * kScanPer;
+
+__global__ __launch_bounds__(1024) void k_scan_chunk(const uint32_t *in, uint64_t *out, uint64_t n, uint64_t *bsum) {
   __shared__ uint64_t s_part[1024];
-  const uint64_t per = (n + 1023) / 1024;
-  const uint64_t b = threadIdx.x * per, e = min(n, b + per);
-  uint64_t s = 0;
-  for (uint64_t i = b; i < e; ++i) s += in[i];
-  s_part[threadIdx.x] = s;
+  const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanPer;
+  uint64_t sum = 0;
+  for (int k = 0; k < kScanPer; ++k)
+    if (b0 + k < n) sum += in[b0 + k];
+  s_part[threadIdx.x] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t acc = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const uint64_t v = s_part[i];
-      s_part[i] = acc;
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint64_t v = (int)threadIdx.x >= d ? s_part[threadIdx.x - d] : 0;
+    __syncthreads();
+    s_part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint64_t acc = s_part[threadIdx.x] - sum;
+  for (int k = 0; k < kScanPer; ++k)
+    if (b0 + k < n) {
+      out[b0 + k] = acc;
+      acc += in[b0 + k];
+    }
+  if (threadIdx.x == 1023) bsum[blockIdx.x] = s_part[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint64_t *bsum, uint64_t nb) {
+  __shared__ uint64_t s_part[1024];
+  const uint64_t b0 = (uint64_t)threadIdx.x * kScanPer;
+  uint64_t sum = 0;
+  for (int k = 0; k < kScanPer; ++k)
+    if (b0 + k < nb) sum += bsum[b0 + k];
+  s_part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint64_t v = (int)threadIdx.x >= d ? s_part[threadIdx.x - d] : 0;
+    __syncthreads();
+    s_part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint64_t acc = s_part[threadIdx.x] - sum;
+  for (int k = 0; k < kScanPer; ++k)
+    if (b0 + k < nb) {
+      const uint64_t v = bsum[b0 + k];
+      bsum[b0 + k] = acc;
       acc += v;
     }
-  }
-  __syncthreads();
-  uint64_t acc = s_part[threadIdx.x];
-  for (uint64_t i = b; i < e; ++i) {
-    out[i] = acc;
-    acc += in[i];
-  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint64_t *out, uint64_t n, const uint64_t *bsum) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += bsum[i / kScanChunk];
 }
 
 __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *keys_in, const uint32_t *idx_in,
@@ -2430,11 +2464,32 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_count_keys(const uint32_t *key, uint64_t n, uint32_t n_cells, uint32_t *cnt) {
+// start of every key's run in the sorted keys: packed[c] = first j with
+// key[j] >= c, for c = 0..n_cells (the entry n_cells is the particle total,
+// empty slots carry the key n_cells); each run boundary fills the starts of
+// the keys it skips
+__global__ __launch_bounds__(256) void k_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells,
+                                                    uint64_t *packed) {
   const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const uint32_t k = key[j];
-  if (k < n_cells) atomicAdd(&cnt[k], 1u);
+  const uint32_t k = key[j] < n_cells ? key[j] : n_cells;
+  const uint32_t prev = j ? (key[j - 1] < n_cells ? key[j - 1] : n_cells) : 0u;
+  const uint32_t from = j ? prev + 1 : 0u;
+  if (j == 0 || k != prev)
+    for (uint32_t c = from; c <= k; ++c) packed[c] = j;
+  if (j == n - 1)
+    for (uint32_t c = k + 1; c <= n_cells; ++c) packed[c] = n;
+}
+
+// new per-cell counts from the run starts; a count beyond the cell's slot
+// capacity flags an error (the place pass drops what does not fit)
+__global__ __launch_bounds__(256) void k_run_counts(const uint64_t *packed, uint32_t n_cells, const uint32_t *cap,
+                                                    uint32_t *cnt, uint32_t *err) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const uint64_t k = packed[c + 1] - packed[c];
+  if (k > cap[c]) atomicOr(err, kErrCapacity);
+  cnt[c] = (uint32_t)(k > cap[c] ? cap[c] : k);
 }
 
 __global__ __launch_bounds__(256) void k_place_moved(PlaceMovedArgs A) {
@@ -2545,8 +2600,19 @@ hipError_t launch_moments(const Tables *tab, const double *lev, const State &st,
   return hipGetLastError();
 }
 
-hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, in, out, n);
+uint64_t scan_tmp_entries(uint64_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }
+
+// exclusive scan; tmp holds scan_tmp_entries(n) entries (at most
+// kScanChunk chunks, i.e. n <= 2^28)
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, uint64_t *tmp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (nb > kScanChunk) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_chunk, dim3((unsigned)nb), dim3(1024), 0, s, in, out, n, tmp);
+  if (nb > 1) {
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, tmp);
+  }
   return hipGetLastError();
 }
 
@@ -2563,7 +2629,8 @@ hipError_t launch_load_check(const Tables *tab, const uint32_t *cell, const uint
 // 256 * tiles u32 and offs of 256 * tiles u64. Result in keys/idx (ping-pong
 // handled here; returns which buffer holds the result).
 hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32_t *idx_tmp, uint32_t *hist,
-                       uint64_t *offs, uint64_t n, uint32_t key_bits, hipStream_t s, bool &result_in_tmp) {
+                       uint64_t *offs, uint64_t *scan_tmp, uint64_t n, uint32_t key_bits, hipStream_t s,
+                       bool &result_in_tmp) {
   result_in_tmp = false;
   if (n == 0) return hipSuccess;
   const uint32_t tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
@@ -2571,7 +2638,8 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
   uint32_t *kin = keys, *iin = idx, *kout = keys_tmp, *iout = idx_tmp;
   for (uint32_t shift = 0; shift < key_bits; shift += 8) {
     hipLaunchKernelGGL(k_sort_hist, dim3(tiles), dim3(kSortBlock), 0, s, kin, n, shift, hist, tiles);
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, hist, offs, (uint64_t)256 * tiles);
+    const hipError_t e = launch_scan_u32(hist, offs, (uint64_t)256 * tiles, scan_tmp, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sort_scatter, dim3(tiles), dim3(kSortBlock), 0, s, kin, iin, kout, iout, n, shift, offs,
                        tiles);
     uint32_t *tk = kin, *ti = iin;
@@ -2592,9 +2660,11 @@ hipError_t launch_move(const MoveArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_count_keys(const uint32_t *key, uint64_t n, uint32_t n_cells, uint32_t *cnt, hipStream_t s) {
+hipError_t launch_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells, uint64_t *packed,
+                             const uint32_t *cap, uint32_t *cnt, uint32_t *err, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, n, n_cells, cnt);
+  hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, n, n_cells, packed);
+  hipLaunchKernelGGL(k_run_counts, dim3((n_cells + 255) / 256), dim3(256), 0, s, packed, n_cells, cap, cnt, err);
   return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ hipError_t launch_init(const Tables *tab, const double *lev, const State &st, co
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
                        const uint32_t grid[3], const double len[3], hipStream_t s);
 hipError_t launch_move(const MoveArgs &a, hipStream_t s);
-hipError_t launch_count_keys(const uint32_t *key, uint64_t n, uint32_t n_cells, uint32_t *cnt, hipStream_t s);
+hipError_t launch_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells, uint64_t *packed,
+                             const uint32_t *cap, uint32_t *cnt, uint32_t *err, hipStream_t s);
 hipError_t launch_place_moved(const PlaceMovedArgs &a, hipStream_t s);
 hipError_t launch_cell_init(const Tables *tab, const State &st, const CellArrays &cells, uint32_t n_cells,
                             hipStream_t s);
@@ -36,11 +37,13 @@ hipError_t launch_moments(const Tables *tab, const double *lev, const State &st,
 hipError_t launch_load_check(const Tables *tab, const uint32_t *cell, const uint8_t *sp, const double *vel,
                              const uint16_t *lvl, uint64_t n, uint32_t n_cells, uint32_t *count, uint32_t *err,
                              hipStream_t s);
-hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, uint64_t *tmp, hipStream_t s);
+uint64_t scan_tmp_entries(uint64_t n);
 hipError_t launch_rec_enum(const RecEnumArgs &a, bool write, hipStream_t s);
 hipError_t launch_rec_sum(const RecSumArgs &a, uint32_t n_t, size_t lds, hipStream_t s);
 hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32_t *idx_tmp, uint32_t *hist,
-                       uint64_t *offs, uint64_t n, uint32_t key_bits, hipStream_t s, bool &result_in_tmp);
+                       uint64_t *offs, uint64_t *scan_tmp, uint64_t n, uint32_t key_bits, hipStream_t s,
+                       bool &result_in_tmp);
 uint64_t sort_tiles(uint64_t n);
 hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
                         const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,
@@ -133,8 +136,8 @@ struct hcao_ctx {
   uint32_t grid[3] = {1, 1, 1}, periodic = 0;
   double len[3] = {0.0, 0.0, 0.0};
   DevBuf<double> px, py, pz, bpx, bpy, bpz;
-  DevBuf<uint32_t> mv_key, mv_idx, mv_key_tmp, mv_idx_tmp, mv_hist, mv_cnt;
-  DevBuf<uint64_t> mv_offs, mv_packed;
+  DevBuf<uint32_t> mv_key, mv_idx, mv_key_tmp, mv_idx_tmp, mv_hist;
+  DevBuf<uint64_t> mv_offs, mv_packed, mv_stmp;
   DevBuf<uint64_t> off;
   DevBuf<uint32_t> cnt, cap;
   DevBuf<double> d_volume, d_weight, sgmax, rem, defect;
@@ -261,9 +264,9 @@ void free_state(hcao_ctx *c) {
   c->mv_key_tmp.release();
   c->mv_idx_tmp.release();
   c->mv_hist.release();
-  c->mv_cnt.release();
   c->mv_offs.release();
   c->mv_packed.release();
+  c->mv_stmp.release();
   c->off.release();
   c->cnt.release();
   c->cap.release();
@@ -464,8 +467,8 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
     HIP_TRY(c, c->mv_idx_tmp.alloc(tot));
     HIP_TRY(c, c->mv_hist.alloc(256 * sort_tiles(tot)));
     HIP_TRY(c, c->mv_offs.alloc(256 * sort_tiles(tot)));
-    HIP_TRY(c, c->mv_cnt.alloc(nc));
-    HIP_TRY(c, c->mv_packed.alloc(nc));
+    HIP_TRY(c, c->mv_packed.alloc(nc + 1));
+    HIP_TRY(c, c->mv_stmp.alloc(std::max(scan_tmp_entries(256 * sort_tiles(tot)), scan_tmp_entries(nc))));
   }
   HIP_TRY(c, c->off.alloc(nc + 1));
   HIP_TRY(c, c->cnt.alloc(nc));
@@ -676,7 +679,9 @@ hcao_status exact_rec_probability(hcao_ctx *c, uint32_t sp, double de, double om
   HIP_TRY(c, hipEventRecord(e0, c->stream));
   ea.count = cnt.p;
   HIP_TRY(c, launch_rec_enum(ea, false, c->stream));
-  HIP_TRY(c, launch_scan_u32(cnt.p, off.p, n_prefix, c->stream));
+  DevBuf<uint64_t> stmp;
+  HIP_TRY(c, stmp.alloc(scan_tmp_entries(n_prefix)));
+  HIP_TRY(c, launch_scan_u32(cnt.p, off.p, n_prefix, stmp.p, c->stream));
   uint64_t last_off = 0;
   uint32_t last_cnt = 0;
   HIP_TRY(c, hipMemcpyAsync(&last_off, off.p + (n_prefix - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
@@ -1249,8 +1254,11 @@ hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, c
   HIP_TRY(c, offs.alloc(256 * tiles));
   HIP_TRY(c, packed.alloc(nc));
   bool in_tmp = false;
-  HIP_TRY(c, launch_sort(d_cell.p, idx.p, keys_tmp.p, idx_tmp.p, hist.p, offs.p, n, key_bits, c->stream, in_tmp));
-  HIP_TRY(c, launch_scan_u32(c->cnt.p, packed.p, nc, c->stream));
+  DevBuf<uint64_t> stmp;
+  HIP_TRY(c, stmp.alloc(std::max(scan_tmp_entries(256 * tiles), scan_tmp_entries(nc))));
+  HIP_TRY(c, launch_sort(d_cell.p, idx.p, keys_tmp.p, idx_tmp.p, hist.p, offs.p, stmp.p, n, key_bits, c->stream,
+                         in_tmp));
+  HIP_TRY(c, launch_scan_u32(c->cnt.p, packed.p, nc, stmp.p, c->stream));
   const uint32_t *sk = in_tmp ? keys_tmp.p : d_cell.p;
   const uint32_t *si = in_tmp ? idx_tmp.p : idx.p;
   HIP_TRY(c, launch_place(c->d_tab.p, sk, si, packed.p, c->off.p, d_sp.p, d_vel.p, d_lvl.p, d_rot.p, d_pos.p,
@@ -1346,13 +1354,13 @@ hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
   while (key_bits < 32 && ((uint64_t)1 << key_bits) <= nc) ++key_bits;  // keys 0..nc (nc: empty slot)
   key_bits = ((key_bits + 7) / 8) * 8;
   bool in_tmp = false;
-  HIP_TRY(c, launch_sort(c->mv_key.p, c->mv_idx.p, c->mv_key_tmp.p, c->mv_idx_tmp.p, c->mv_hist.p, c->mv_offs.p, tot,
-                         key_bits, s, in_tmp));
+  HIP_TRY(c, launch_sort(c->mv_key.p, c->mv_idx.p, c->mv_key_tmp.p, c->mv_idx_tmp.p, c->mv_hist.p, c->mv_offs.p,
+                         c->mv_stmp.p, tot, key_bits, s, in_tmp));
   const uint32_t *sk = in_tmp ? c->mv_key_tmp.p : c->mv_key.p;
   const uint32_t *si = in_tmp ? c->mv_idx_tmp.p : c->mv_idx.p;
-  HIP_TRY(c, hipMemsetAsync(c->mv_cnt.p, 0, nc * sizeof(uint32_t), s));
-  HIP_TRY(c, launch_count_keys(sk, tot, nc, c->mv_cnt.p, s));
-  HIP_TRY(c, launch_scan_u32(c->mv_cnt.p, c->mv_packed.p, nc, s));
+  // the new per-cell counts go straight to the context's counts (the move
+  // pass has read the old ones)
+  HIP_TRY(c, launch_run_starts(sk, tot, nc, c->mv_packed.p, c->cap.p, c->cnt.p, c->err.p, s));
   PlaceMovedArgs p{};
   p.src = state_of(c);
   p.dst = scratch_of(c);
@@ -1366,7 +1374,6 @@ hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
   p.n = tot;
   p.err = c->err.p;
   HIP_TRY(c, launch_place_moved(p, s));
-  HIP_TRY(c, hipMemcpyAsync(c->cnt.p, c->mv_cnt.p, nc * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   std::swap(c->vx, c->bvx);
   std::swap(c->vy, c->bvy);
   std::swap(c->vz, c->bvz);

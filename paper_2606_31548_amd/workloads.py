@@ -235,7 +235,8 @@ def spatial_box(nx=16, ny=16, nz=16, per_cell=256, cell_edge=1e-4, periodic=0, c
     periodic axes (bits 0..2). Species and reactions of the methane/argon
     workload (or, with chemistry=True, the CH4/CH3/H/H2 chemistry at
     t_trans). A particle at 5 km/s crosses half a 0.1 mm cell per 1e-8 s
-    step, so the per-step re-binning moves a large share of particles."""
+    step, so the per-step re-binning moves a large share of particles.
+    Cells get room for twice their initial count."""
     n_cells = nx * ny * nz
     vol = cell_edge ** 3
     if chemistry:
@@ -246,6 +247,9 @@ def spatial_box(nx=16, ny=16, nz=16, per_cell=256, cell_edge=1e-4, periodic=0, c
     base.cell_volume = np.full(n_cells, vol)
     base.cell_weight = np.full(n_cells, DENSITY * vol / per_cell)
     base.domain = (nx, ny, nz, nx * cell_edge, ny * cell_edge, nz * cell_edge, periodic)
+    # cells exchange particles every step and the chemistry adds products:
+    # room for twice the initial count
+    base.capacity_per_cell = 2 * per_cell + 64
     base.name = f"box-{nx}x{ny}x{nz}"
     base.seed = seed
     return base

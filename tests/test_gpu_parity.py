@@ -68,8 +68,11 @@ def test_thermal_init_parity(orc, hc, case):
     _compare_state(o, g, "init")
 
 
-def test_load_is_a_stable_counting_sort(orc, hc):
-    wl = W.methane_chemistry(n_cells=300, per_cell=40, recombination=False)
+@pytest.mark.parametrize("n_cells,per_cell", [(300, 40), (3000, 120)])
+def test_load_is_a_stable_counting_sort(orc, hc, n_cells, per_cell):
+    """Shuffled particles placed by the device radix sort; the larger case
+    (360k particles) scans digit histograms over several scan chunks."""
+    wl = W.methane_chemistry(n_cells=n_cells, per_cell=per_cell, recombination=False)
     wl.counts[::7] = 0            # empty cells
     wl.counts[3] = [1, 0, 0, 0, 0]  # single particle
     wl.counts[5] = [300, 0, 200, 100, 60]  # ragged, larger than the rest

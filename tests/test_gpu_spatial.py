@@ -122,3 +122,19 @@ def test_spatial_mixed_form_conserves_energy(hc):
     pos = g.read_positions()
     nx, ny, nz, lx, ly, lz, _ = wl.domain
     assert np.all(pos >= 0) and np.all(pos <= np.array([lx, ly, lz]))
+
+
+def test_spatial_parity_with_multi_chunk_scans(orc, hc):
+    """A 16 x 16 x 8 box (2,048 cells, 540k slots): the re-bin's radix sort
+    scans digit histograms of several scan chunks."""
+    wl = W.spatial_box(nx=16, ny=16, nz=8, per_cell=100, periodic=0b101, t_trans=25000.0)
+    o = orc.from_workload(wl)
+    g = hc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    for n in (1, 3):
+        o.step(wl.dt, n)
+        g.step(wl.dt, n)
+        g.sync()
+        _compare_state(o, g, "multi-chunk box")
+        _compare_pos(o, g, "multi-chunk box")

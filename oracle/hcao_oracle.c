@@ -19,6 +19,10 @@
  *   exchange ........................ Sec. "Exchange reactions", Eq. Ecoll-exch
  *   competing reactions ............. Sec. "Competing reactions"
  *   product redistribution .......... Sec. "Polyatomic QK reaction modeling" (LB)
+ *   rotation coupling ............... Sec. "Rotation coupling" (gamma E_rot in both
+ *                                     collision energies; rotor model: readings R-A..R-D)
+ *   exact recombination sum ......... Sec. "Recombination reactions", Eq. recomb-correct
+ *   spatial mode .................... not in the paper (reading S-A: move, re-bin, collide)
  * Pieces the paper takes from elsewhere are written from their textbook
  * definitions: NTC candidate count and VHS cross-section (Bird), Marsaglia's
  * (1972) unit vector and polar normal method, Philox4x32-10 (Salmon et al.,

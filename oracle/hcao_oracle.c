@@ -20,9 +20,9 @@
  *   competing reactions ............. Sec. "Competing reactions"
  *   product redistribution .......... Sec. "Polyatomic QK reaction modeling" (LB)
  *   rotation coupling ............... Sec. "Rotation coupling" (gamma E_rot in both
- *                                     collision energies; rotor model: readings R-A..R-D)
+ *                                     collision energies; the rotor model is our own)
  *   exact recombination sum ......... Sec. "Recombination reactions", Eq. recomb-correct
- *   spatial mode .................... not in the paper (reading S-A: move, re-bin, collide)
+ *   spatial mode .................... not in the paper (move, re-bin, collide)
  * Pieces the paper takes from elsewhere are written from their textbook
  * definitions: NTC candidate count and VHS cross-section (Bird), Marsaglia's
  * (1972) unit vector and polar normal method, Philox4x32-10 (Salmon et al.,
@@ -496,7 +496,7 @@ int orc_add_species(orc_ctx *o, double mass, double dref, double omega, double t
   return E_OK;
 }
 
-/* Rotational mode of a species (reading R-A): zeta rotational degrees of
+/* Rotational mode of a species (the paper does not define one): zeta rotational degrees of
  * freedom (0 none, 2 linear, 3 nonlinear rotor), relaxed with probability
  * p_rot per non-reactive collision. Before finalize. */
 int orc_set_rotation(orc_ctx *o, uint32_t species, uint32_t zeta, double p_rot) {
@@ -519,7 +519,7 @@ int orc_set_gamma_rot(orc_ctx *o, uint32_t reaction, double gamma) {
   return E_OK;
 }
 
-/* Spatial mode (reading S-A): the cells tile the box [0, lx) x
+/* Spatial mode (not in the paper, whose cases are 0D reservoirs): the cells tile the box [0, lx) x
  * [0, ly) x [0, lz) as an nx x ny x nz grid, cell = ix + nx (iy + ny iz);
  * bit k of periodic makes axis k periodic, else its walls reflect
  * specularly. Every step then moves all particles ballistically, re-bins
@@ -828,7 +828,7 @@ double orc_wr_probability(const orc_ctx *o, uint32_t species, double de, double 
 double orc_q_vib(const orc_ctx *o, uint32_t species, double t) { return q_vib(&o->sp[species], t); }
 
 /* Forward probability of Eq. recomb-correct, summed over every combination
- * of vibrational levels of A (reading A7b): P(T) = sum_i Q(a, (D_e - S_i)/kT)
+ * of vibrational levels of A: P(T) = sum_i Q(a, (D_e - S_i)/kT)
  * exp(-S_i/kT) / sum_i exp(-S_i/kT), S_i the energy of combination i above
  * the ground level (sum over modes of E_m(j) - E_m(0)), a = 5/2 - omega, Q the
  * regularized upper incomplete gamma with Q = 1 for a non-positive argument.
@@ -1173,7 +1173,7 @@ static uint32_t propose(const species_t *s, uint32_t m, double e, double u) {
   return i;
 }
 
-/* Gibbs-sweep proposal for one mode (our sampler, reading A3): the target
+/* Gibbs-sweep proposal for one mode (our sampler): the target
  * over levels 0..top is proportional to t_i = ((E_c - E_i) / den)^q with
  * den = E_c - E_0. Since (1 - x)^q <= 1 - q x for q in (0, 1], and a
  * concave level sequence has E_i - E_0 >= i (E_top - E_0) / top, t_i is
@@ -1200,7 +1200,7 @@ static uint32_t propose_linear(uint32_t top, double c, double u) {
 
 uint32_t orc_gibbs_propose(uint32_t top, double c, double u) { return propose_linear(top, c, u); }
 
-/* Exact sampler of the joint target (our design, reading A3): the target of
+/* Exact sampler of the joint target (our design): the target of
  * the joint proposal, P(i) proportional to (E' - S(i))^q over S(i) < E' with
  * e_m(i) = E_m(i) - E_m(0), S = sum_m e_m(i_m) and E' = E_coll - ZPE, drawn by
  * rejection from a product of per-mode Boltzmann distributions at one inverse
@@ -1481,7 +1481,7 @@ typedef struct {
   double pos[3]; /* spatial mode: the dissociating molecule's position */
 } newborn;
 
-/* Rotational Larsen-Borgnakke share (reading R-B): the fraction f of the
+/* Rotational Larsen-Borgnakke share (our rotor model): the fraction f of the
  * pooled energy E_tr + E_rot that the rotor keeps has density proportional to
  * f^(zeta/2 - 1) (1 - f)^q, q = 3/2 - omega the exponent of the vibrational
  * sampler. zeta = 2: inversion, f = 1 - (1 - u)^(1/(q+1)). zeta = 3: rejection
@@ -1540,7 +1540,7 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
     const pair_t *pam = &o->pr[R->c][ps->sp_m];
     double e_am = pam->hm * ((gx * gx + gy * gy) + gz * gz);
     double pool = (((e_am + e_tr) + evib[b]) + evib[c]) - R->dh;
-    /* rotation of B and C: kept by A's rotor, else pooled (reading R-D) */
+    /* rotation of B and C: kept by A's rotor, else pooled */
     double rsum = ps->rot[b] + ps->rot[c];
     if (A->zeta_rot == 0) pool = pool + rsum;
     double et = pool - A->zpe;
@@ -1764,7 +1764,7 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
       ctr[ORC_CTR_CAPPED] += (uint64_t)capped;
     }
   }
-  /* rotational relaxation of each rotor in turn (reading R-B) */
+  /* rotational relaxation of each rotor in turn, after the vibrational one */
   for (int x = 0; x < 2; ++x) {
     const species_t *S = &o->sp[ps->sp[x]];
     if (S->zeta_rot == 0) continue;

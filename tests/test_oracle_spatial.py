@@ -1,4 +1,4 @@
-"""Spatial mode (movement and re-binning, SURVEY f4): pins of the oracle's
+"""Spatial mode (movement and re-binning): pins of the oracle's
 ballistic move with periodic and specular walls against closed-form
 trajectories, of the stable counting-sort re-bin, of the uniform thermal
 placement, and of conservation in closed and periodic boxes."""

@@ -138,3 +138,29 @@ def test_spatial_parity_with_multi_chunk_scans(orc, hc):
         g.sync()
         _compare_state(o, g, "multi-chunk box")
         _compare_pos(o, g, "multi-chunk box")
+
+
+def test_spatial_rebin_capacity_overflow_is_reported(orc, hc):
+    """Two cells of capacity 150: the 100 particles of cell 0 all fly into
+    cell 1, which already holds 100. The re-bin drops nothing silently: both
+    the oracle and the library report a capacity error."""
+    sp = [W.Species("Ar", 40 * W.AMU)]
+    edge = 1e-4
+    wl = W.Workload("overflow", sp, [], np.array([[100], [100]]), np.full(2, 300.0), np.full(2, 300.0),
+                    np.full(2, edge ** 3), np.full(2, 1e-30), dt=1e-8, capacity_per_cell=150,
+                    domain=(2, 1, 1, 2 * edge, edge, edge, 0))
+    rng = np.random.default_rng(9)
+    cell = np.repeat(np.arange(2, dtype=np.uint32), 100)
+    pos = np.stack([(cell + 0.25 + 0.5 * rng.random(200)) * edge, rng.random(200) * edge,
+                    rng.random(200) * edge], 1)
+    vel = np.zeros((200, 3))
+    vel[:100, 0] = 0.9 * edge / wl.dt  # crosses into cell 1 within one step, stays clear of the far wall
+    o = orc.from_workload(wl)
+    g = hc.from_workload(wl)
+    o.load(cell, np.zeros(200, np.uint8), vel, np.zeros((200, 1), np.uint16), None, pos)
+    g.load_particles(cell, np.zeros(200, np.uint8), vel, np.zeros((200, 1), np.uint16), None, pos)
+    with pytest.raises(orc.OracleError):
+        o.step(wl.dt, 1)
+    with pytest.raises(hc.HcaoError):
+        g.step(wl.dt, 1)
+        g.sync()

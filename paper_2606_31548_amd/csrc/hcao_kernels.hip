@@ -2042,7 +2042,6 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint32_t *keys, 
   hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = s_h[threadIdx.x];
 }
 
-// single-workgroup exclusive scan of a u32 array into u64 offsets
 // Multi-block exclusive scan of u32 into u64: each 1024-thread block scans
 // a chunk of kScanChunk entries (16 per thread) and leaves its total in
 // bsum; one block then scans the totals; a third pass adds each chunk's
@@ -2410,7 +2409,8 @@ __global__ __launch_bounds__(256) void k_rec_sum(RecSumArgs A) {
 
 // ---------------------------------------------------------------------------
 // spatial mode: ballistic move with periodic or specular walls, then a
-// re-bin by a stable radix sort on the new cell
+// stable re-bin by (new cell, old slot) that sorts only the particles that
+// left their cell
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double move_axis(double x, double &v, double dt, double len, bool periodic) {
   double y = x + v * dt;
@@ -2440,13 +2440,19 @@ __device__ __forceinline__ uint32_t axis_index(double x, double len, uint32_t n)
   return (uint32_t)f;
 }
 
+// one workgroup of four waves per cell; ranks in slot order come from
+// ballots within a wave and the per-wave totals in LDS
 __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
-  const uint32_t c = blockIdx.x;
+  __shared__ uint32_t s_wave[2][4];
+  const uint32_t c = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
   const uint64_t base = A.off[c];
-  const uint32_t n = A.cnt[c], cap = A.cap[c];
-  for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
+  const uint32_t n = A.cnt[c], top = A.cap[c] - 1u;
+  const uint64_t below_lane = (1ull << lane) - 1ull;
+  uint32_t run_s = 0, run_m = 0;
+  for (uint32_t i0 = 0; i0 < n; i0 += 256) {
+    const uint32_t i = i0 + tid;
     const uint64_t g = base + i;
-    uint32_t key = A.n_cells;
+    bool mover = false;
     if (i < n) {
       const Vec3 v = load_vel(A.st, g);
       double vx = v.x, vy = v.y, vz = v.z;
@@ -2457,17 +2463,60 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
       A.st.py[g] = y;
       A.st.pz[g] = z;
       store_vel(A.st, g, vx, vy, vz);
-      key = axis_index(x, A.len[0], A.nx) + A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
+      const uint32_t key =
+          axis_index(x, A.len[0], A.nx) + A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
+      A.key[g] = key;
+      mover = key != c;
     }
-    A.key[g] = key;
-    A.idx[g] = (uint32_t)g;
+    const uint64_t bm = __ballot(i < n && mover), bs = __ballot(i < n && !mover);
+    if (lane == 0) {
+      s_wave[0][wv] = (uint32_t)__popcll(bs);
+      s_wave[1][wv] = (uint32_t)__popcll(bm);
+    }
+    __syncthreads();
+    uint32_t pre_s = run_s, pre_m = run_m;
+    for (uint32_t w = 0; w < 4; ++w) {
+      const uint32_t ns = s_wave[0][w], nm = s_wave[1][w];
+      if (w < wv) {
+        pre_s += ns;
+        pre_m += nm;
+      }
+      run_s += ns;
+      run_m += nm;
+    }
+    // stayer ranks count up from the first slot, mover ranks down from the
+    // last: together they never pass n <= cap entries
+    if (i < n) {
+      if (mover)
+        A.list[base + top - (pre_m + (uint32_t)__popcll(bm & below_lane))] = i;
+      else
+        A.list[base + pre_s + (uint32_t)__popcll(bs & below_lane)] = i;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    A.n_stay[c] = run_s;
+    A.n_move[c] = run_m;
+  }
+}
+
+// movers of cell c into the list, in slot order
+__global__ __launch_bounds__(256) void k_list_movers(RebinArgs A) {
+  const uint32_t c = blockIdx.x;
+  const uint32_t nm = A.n_move[c];
+  if (nm == 0) return;
+  const uint64_t base = A.off[c], mb = A.mbase[c];
+  const uint64_t top = base + A.cap[c] - 1u;
+  for (uint32_t r = threadIdx.x; r < nm; r += blockDim.x) {
+    const uint64_t g = base + A.list[top - r];
+    A.mkey[mb + r] = A.key[g];
+    A.mslot[mb + r] = (uint32_t)g;
   }
 }
 
 // start of every key's run in the sorted keys: packed[c] = first j with
-// key[j] >= c, for c = 0..n_cells (the entry n_cells is the particle total,
-// empty slots carry the key n_cells); each run boundary fills the starts of
-// the keys it skips
+// key[j] >= c, for c = 0..n_cells (packed[n_cells] = n); each run boundary
+// fills the starts of the keys it skips
 __global__ __launch_bounds__(256) void k_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells,
                                                     uint64_t *packed) {
   const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2481,43 +2530,71 @@ __global__ __launch_bounds__(256) void k_run_starts(const uint32_t *key, uint64_
     for (uint32_t c = k + 1; c <= n_cells; ++c) packed[c] = n;
 }
 
-// new per-cell counts from the run starts; a count beyond the cell's slot
-// capacity flags an error (the place pass drops what does not fit)
-__global__ __launch_bounds__(256) void k_run_counts(const uint64_t *packed, uint32_t n_cells, const uint32_t *cap,
-                                                    uint32_t *cnt, uint32_t *err) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
-  const uint64_t k = packed[c + 1] - packed[c];
-  if (k > cap[c]) atomicOr(err, kErrCapacity);
-  cnt[c] = (uint32_t)(k > cap[c] ? cap[c] : k);
+__device__ __forceinline__ void copy_particle(const State &s, const State &d, uint64_t from, uint64_t to, uint32_t mm) {
+  if (s.fx) {
+    d.fx[to] = s.fx[from];
+    d.fy[to] = s.fy[from];
+    d.fz[to] = s.fz[from];
+  } else {
+    d.vx[to] = s.vx[from];
+    d.vy[to] = s.vy[from];
+    d.vz[to] = s.vz[from];
+  }
+  d.sp[to] = s.sp[from];
+  for (uint32_t m = 0; m < mm; ++m) d.lvl[m * d.stride + to] = s.lvl[m * s.stride + from];
+  if (s.rot) d.rot[to] = s.rot[from];
+  d.px[to] = s.px[from];
+  d.py[to] = s.py[from];
+  d.pz[to] = s.pz[from];
 }
 
-__global__ __launch_bounds__(256) void k_place_moved(PlaceMovedArgs A) {
-  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= A.n) return;
-  const uint32_t k = A.key[j];
+// one workgroup per new cell k fills its slots in order: the run of movers
+// into k (in slot order) splits at the first mover from a slot above off[k]
+// (found by bisection), k's stayers go between the two parts. A count beyond
+// the cell's capacity flags an error and the tail is dropped. Workgroups go
+// to the eight XCDs in turn, so the grid (a multiple of 8) gives each XCD one
+// contiguous range of cells: movers come from neighbouring cells, whose
+// lines are then in the same L2.
+__global__ __launch_bounds__(256) void k_rebin_place(RebinArgs A) {
+  __shared__ uint32_t s_below;
+  const uint32_t per_xcd = gridDim.x >> 3;
+  const uint32_t k = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
   if (k >= A.n_cells) return;
-  const uint64_t rank = j - A.packed[k];
-  if (rank >= A.cap[k]) {
-    atomicOr(A.err, kErrCapacity);
-    return;
+  const uint64_t base = A.off[k];
+  uint64_t lo = 0, hi = 0;
+  if (A.m) {
+    lo = A.packed[k];
+    hi = A.packed[k + 1];
   }
-  const uint64_t src = A.idx[j], dst = A.off[k] + rank;
-  if (A.src.fx) {
-    A.dst.fx[dst] = A.src.fx[src];
-    A.dst.fy[dst] = A.src.fy[src];
-    A.dst.fz[dst] = A.src.fz[src];
-  } else {
-    A.dst.vx[dst] = A.src.vx[src];
-    A.dst.vy[dst] = A.src.vy[src];
-    A.dst.vz[dst] = A.src.vz[src];
+  if (threadIdx.x == 0) {
+    uint64_t a = lo, b = hi;
+    while (a < b) {
+      const uint64_t mid = (a + b) >> 1;
+      if (A.mslot[A.sidx[mid]] < base)
+        a = mid + 1;
+      else
+        b = mid;
+    }
+    s_below = (uint32_t)(a - lo);
   }
-  A.dst.sp[dst] = A.src.sp[src];
-  for (uint32_t m = 0; m < A.mm; ++m) A.dst.lvl[m * A.dst.stride + dst] = A.src.lvl[m * A.src.stride + src];
-  if (A.src.rot) A.dst.rot[dst] = A.src.rot[src];
-  A.dst.px[dst] = A.src.px[src];
-  A.dst.py[dst] = A.src.py[src];
-  A.dst.pz[dst] = A.src.pz[src];
+  __syncthreads();
+  const uint32_t below = s_below, ns = A.n_stay[k], cap = A.cap[k];
+  const uint64_t want = (hi - lo) + ns;
+  const uint32_t total = (uint32_t)(want > cap ? cap : want);
+  if (threadIdx.x == 0) {
+    if (want > cap) atomicOr(A.err, kErrCapacity);
+    A.cnt[k] = total;
+  }
+  for (uint32_t p = threadIdx.x; p < total; p += blockDim.x) {
+    uint64_t from;
+    if (p < below)
+      from = A.mslot[A.sidx[lo + p]];
+    else if (p < below + ns)
+      from = base + A.list[base + (p - below)];
+    else
+      from = A.mslot[A.sidx[lo + p - ns]];
+    copy_particle(A.src, A.dst, from, base + p, A.mm);
+  }
 }
 
 }  // namespace
@@ -2656,21 +2733,30 @@ uint64_t sort_tiles(uint64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
 hipError_t launch_move(const MoveArgs &a, hipStream_t s) {
   if (a.n_cells == 0) return hipSuccess;
+  if (!a.off || !a.cnt || !a.cap || !a.key || !a.list || !a.n_stay || !a.n_move || !a.st.px || !a.st.py || !a.st.pz)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_move, dim3(a.n_cells), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells, uint64_t *packed,
-                             const uint32_t *cap, uint32_t *cnt, uint32_t *err, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, n, n_cells, packed);
-  hipLaunchKernelGGL(k_run_counts, dim3((n_cells + 255) / 256), dim3(256), 0, s, packed, n_cells, cap, cnt, err);
+hipError_t launch_list_movers(const RebinArgs &a, hipStream_t s) {
+  if (a.n_cells == 0 || a.m == 0) return hipSuccess;
+  if (!a.off || !a.cap || !a.key || !a.list || !a.n_move || !a.mbase || !a.mkey || !a.mslot)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_list_movers, dim3(a.n_cells), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_place_moved(const PlaceMovedArgs &a, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_place_moved, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+// run starts of the sorted movers, then the place pass
+hipError_t launch_rebin_place(const RebinArgs &a, hipStream_t s) {
+  if (a.n_cells == 0) return hipSuccess;
+  if (!a.off || !a.cap || !a.list || !a.n_stay || !a.packed || !a.cnt || !a.err ||
+      (a.m && (!a.skey || !a.sidx || !a.mslot)))
+    return hipErrorInvalidValue;
+  if (a.m)
+    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a.skey, a.m, a.n_cells,
+                       a.packed);
+  hipLaunchKernelGGL(k_rebin_place, dim3(((a.n_cells + 7u) / 8u) * 8u), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -27,9 +27,8 @@ hipError_t launch_init(const Tables *tab, const double *lev, const State &st, co
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
                        const uint32_t grid[3], const double len[3], hipStream_t s);
 hipError_t launch_move(const MoveArgs &a, hipStream_t s);
-hipError_t launch_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells, uint64_t *packed,
-                             const uint32_t *cap, uint32_t *cnt, uint32_t *err, hipStream_t s);
-hipError_t launch_place_moved(const PlaceMovedArgs &a, hipStream_t s);
+hipError_t launch_list_movers(const RebinArgs &a, hipStream_t s);
+hipError_t launch_rebin_place(const RebinArgs &a, hipStream_t s);
 hipError_t launch_cell_init(const Tables *tab, const State &st, const CellArrays &cells, uint32_t n_cells,
                             hipStream_t s);
 hipError_t launch_moments(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
@@ -136,8 +135,9 @@ struct hcao_ctx {
   uint32_t grid[3] = {1, 1, 1}, periodic = 0;
   double len[3] = {0.0, 0.0, 0.0};
   DevBuf<double> px, py, pz, bpx, bpy, bpz;
-  DevBuf<uint32_t> mv_key, mv_idx, mv_key_tmp, mv_idx_tmp, mv_hist;
-  DevBuf<uint64_t> mv_offs, mv_packed, mv_stmp;
+  DevBuf<uint32_t> mv_key, mv_list, mv_mkey, mv_mslot, mv_sidx, mv_sidx_tmp, mv_hist;
+  DevBuf<uint32_t> mv_nstay, mv_nmove;
+  DevBuf<uint64_t> mv_offs, mv_packed, mv_stmp, mv_mbase;
   DevBuf<uint64_t> off;
   DevBuf<uint32_t> cnt, cap;
   DevBuf<double> d_volume, d_weight, sgmax, rem, defect;
@@ -260,9 +260,14 @@ void free_state(hcao_ctx *c) {
   c->bpy.release();
   c->bpz.release();
   c->mv_key.release();
-  c->mv_idx.release();
-  c->mv_key_tmp.release();
-  c->mv_idx_tmp.release();
+  c->mv_list.release();
+  c->mv_mkey.release();
+  c->mv_mslot.release();
+  c->mv_sidx.release();
+  c->mv_sidx_tmp.release();
+  c->mv_nstay.release();
+  c->mv_nmove.release();
+  c->mv_mbase.release();
   c->mv_hist.release();
   c->mv_offs.release();
   c->mv_packed.release();
@@ -445,6 +450,8 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   }
   c->off_host[nc] = tot;
   c->total_slots = tot;
+  // the spatial re-bin keeps old slots as 32-bit indices
+  if (c->spatial && tot > 0xFFFFFFFFull) return fail(c, HCAO_EINVAL, "spatial mode holds at most 2^32 - 1 slots");
   const uint32_t mm = c->max_modes ? c->max_modes : 1;
   HIP_TRY(c, alloc_vel(c, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, tot));
   HIP_TRY(c, c->sp.alloc(tot));
@@ -462,13 +469,21 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
     HIP_TRY(c, c->bpy.alloc(tot));
     HIP_TRY(c, c->bpz.alloc(tot));
     HIP_TRY(c, c->mv_key.alloc(tot));
-    HIP_TRY(c, c->mv_idx.alloc(tot));
-    HIP_TRY(c, c->mv_key_tmp.alloc(tot));
-    HIP_TRY(c, c->mv_idx_tmp.alloc(tot));
+    HIP_TRY(c, c->mv_list.alloc(tot));
+    HIP_TRY(c, c->mv_mkey.alloc(tot));
+    HIP_TRY(c, c->mv_mslot.alloc(tot));
+    HIP_TRY(c, c->mv_sidx.alloc(tot));
+    HIP_TRY(c, c->mv_sidx_tmp.alloc(tot));
     HIP_TRY(c, c->mv_hist.alloc(256 * sort_tiles(tot)));
     HIP_TRY(c, c->mv_offs.alloc(256 * sort_tiles(tot)));
     HIP_TRY(c, c->mv_packed.alloc(nc + 1));
-    HIP_TRY(c, c->mv_stmp.alloc(std::max(scan_tmp_entries(256 * sort_tiles(tot)), scan_tmp_entries(nc))));
+    HIP_TRY(c, c->mv_nstay.alloc(nc));
+    HIP_TRY(c, c->mv_nmove.alloc(nc + 1));
+    HIP_TRY(c, c->mv_mbase.alloc(nc + 1));
+    // the entry past the last cell stays zero, so the scan's last output is
+    // the number of movers
+    HIP_TRY(c, hipMemsetAsync(c->mv_nmove.p, 0, (nc + 1) * sizeof(uint32_t), c->stream));
+    HIP_TRY(c, c->mv_stmp.alloc(std::max(scan_tmp_entries(256 * sort_tiles(tot)), scan_tmp_entries(nc + 1))));
   }
   HIP_TRY(c, c->off.alloc(nc + 1));
   HIP_TRY(c, c->cnt.alloc(nc));
@@ -1334,7 +1349,6 @@ StepArgs step_args(hcao_ctx *c, double dt) {
 // become the state (the old state becomes the products staging)
 hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
-  const uint64_t tot = c->total_slots;
   MoveArgs m{};
   m.st = state_of(c);
   m.off = c->off.p;
@@ -1348,32 +1362,45 @@ hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
   for (int k = 0; k < 3; ++k) m.len[k] = c->len[k];
   m.dt = dt;
   m.key = c->mv_key.p;
-  m.idx = c->mv_idx.p;
+  m.list = c->mv_list.p;
+  m.n_stay = c->mv_nstay.p;
+  m.n_move = c->mv_nmove.p;
   HIP_TRY(c, launch_move(m, s));
+  // the number of movers sizes the sort: one small read-back per step
+  HIP_TRY(c, launch_scan_u32(c->mv_nmove.p, c->mv_mbase.p, (uint64_t)nc + 1, c->mv_stmp.p, s));
+  uint64_t movers = 0;
+  HIP_TRY(c, hipMemcpyAsync(&movers, c->mv_mbase.p + nc, sizeof movers, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  RebinArgs r{};
+  r.src = state_of(c);
+  r.dst = scratch_of(c);
+  r.off = c->off.p;
+  r.cap = c->cap.p;
+  r.key = c->mv_key.p;
+  r.list = c->mv_list.p;
+  r.n_stay = c->mv_nstay.p;
+  r.n_move = c->mv_nmove.p;
+  r.mbase = c->mv_mbase.p;
+  r.mkey = c->mv_mkey.p;
+  r.mslot = c->mv_mslot.p;
+  r.packed = c->mv_packed.p;
+  r.cnt = c->cnt.p;
+  r.err = c->err.p;
+  r.m = movers;
+  r.n_cells = nc;
+  r.mm = mm;
+  HIP_TRY(c, launch_list_movers(r, s));
   uint32_t key_bits = 0;
-  while (key_bits < 32 && ((uint64_t)1 << key_bits) <= nc) ++key_bits;  // keys 0..nc (nc: empty slot)
+  while (key_bits < 32 && ((uint64_t)1 << key_bits) < nc) ++key_bits;  // keys 0..nc-1
   key_bits = ((key_bits + 7) / 8) * 8;
+  // the per-slot keys are dead after the list pass: they serve as the
+  // sort's second key buffer
   bool in_tmp = false;
-  HIP_TRY(c, launch_sort(c->mv_key.p, c->mv_idx.p, c->mv_key_tmp.p, c->mv_idx_tmp.p, c->mv_hist.p, c->mv_offs.p,
-                         c->mv_stmp.p, tot, key_bits, s, in_tmp));
-  const uint32_t *sk = in_tmp ? c->mv_key_tmp.p : c->mv_key.p;
-  const uint32_t *si = in_tmp ? c->mv_idx_tmp.p : c->mv_idx.p;
-  // the new per-cell counts go straight to the context's counts (the move
-  // pass has read the old ones)
-  HIP_TRY(c, launch_run_starts(sk, tot, nc, c->mv_packed.p, c->cap.p, c->cnt.p, c->err.p, s));
-  PlaceMovedArgs p{};
-  p.src = state_of(c);
-  p.dst = scratch_of(c);
-  p.key = sk;
-  p.idx = si;
-  p.packed = c->mv_packed.p;
-  p.off = c->off.p;
-  p.cap = c->cap.p;
-  p.n_cells = nc;
-  p.mm = mm;
-  p.n = tot;
-  p.err = c->err.p;
-  HIP_TRY(c, launch_place_moved(p, s));
+  HIP_TRY(c, launch_sort(c->mv_mkey.p, c->mv_sidx.p, c->mv_key.p, c->mv_sidx_tmp.p, c->mv_hist.p, c->mv_offs.p,
+                         c->mv_stmp.p, movers, key_bits, s, in_tmp));
+  r.skey = in_tmp ? c->mv_key.p : c->mv_mkey.p;
+  r.sidx = in_tmp ? c->mv_sidx_tmp.p : c->mv_sidx.p;
+  HIP_TRY(c, launch_rebin_place(r, s));
   std::swap(c->vx, c->bvx);
   std::swap(c->vy, c->bvy);
   std::swap(c->vz, c->bvz);

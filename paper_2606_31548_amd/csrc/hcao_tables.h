@@ -125,10 +125,11 @@ struct StepArgs {
   double dt;
 };
 
-// Spatial mode. Move pass: block c moves the particles of cell c over dt
-// and writes key[slot] = new cell (n_cells for empty slots) and idx[slot] =
-// slot; a stable radix sort of (key, idx) follows. Place pass: sorted entry
-// j with key k < n_cells goes to slot off[k] + (j - packed[k]) of dst.
+// Spatial mode, move pass: block c moves the particles of cell c over dt
+// and writes key[slot] = the new cell; its stayers (new cell = c) and its
+// movers are listed by cell-relative slot in list[], stayers in slot order
+// from the cell's first slot up, movers in slot order from its last slot
+// down; n_stay[c] and n_move[c] count them.
 struct MoveArgs {
   State st;
   const uint64_t *off;
@@ -136,18 +137,27 @@ struct MoveArgs {
   uint32_t n_cells, nx, ny, nz, periodic;
   double len[3];
   double dt;
-  uint32_t *key, *idx;
+  uint32_t *key, *list, *n_stay, *n_move;
 };
 
-struct PlaceMovedArgs {
+// Spatial mode, re-bin after the move pass. The new order of cell k is the
+// stable order by (new cell, old slot): movers from lower slots, then k's
+// stayers, then movers from higher slots. Only the movers are sorted: the
+// list pass writes them in slot order (position mbase[c] + rank), a stable
+// radix sort orders them by new cell and packed[k] is the start of k's run.
+// The place pass fills each cell's new slots in order.
+struct RebinArgs {
   State src, dst;
-  const uint32_t *key, *idx;  // sorted
-  const uint64_t *packed;     // exclusive scan of the new counts
   const uint64_t *off;
   const uint32_t *cap;
+  const uint32_t *key, *list, *n_stay, *n_move;  // from the move pass
+  const uint64_t *mbase;                         // exclusive scan of n_move
+  uint32_t *mkey, *mslot;                        // movers in slot order: new cell, old slot
+  const uint32_t *skey, *sidx;                   // sorted movers: new cell, position in the list
+  uint64_t *packed;                              // run starts in skey (n_cells + 1)
+  uint32_t *cnt, *err;
+  uint64_t m;                                    // number of movers
   uint32_t n_cells, mm;
-  uint64_t n;                 // entries (all slots)
-  uint32_t *err;
 };
 
 // Forward recombination probability summed over every level combination of

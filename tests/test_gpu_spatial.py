@@ -1,5 +1,6 @@
 """Spatial mode on the GPU: ballistic movement with periodic and specular
-walls, the per-step re-bin by a device radix sort, then the collision step,
+walls, the per-step stable re-bin (a device radix sort of the particles
+that left their cell), then the collision step,
 against the fp64 oracle bit for bit (positions, velocities, cell order,
 species, levels, counters)."""
 import numpy as np
@@ -164,3 +165,29 @@ def test_spatial_rebin_capacity_overflow_is_reported(orc, hc):
     with pytest.raises(hc.HcaoError):
         g.step(wl.dt, 1)
         g.sync()
+
+
+@pytest.mark.parametrize("shape,dt", [((3, 3, 2), 1e-13), ((1, 2, 5), None)])
+def test_spatial_rebin_without_movers_and_on_thin_axes(orc, hc, shape, dt):
+    """The re-bin sorts only the particles that leave their cell. A step
+    too short for anyone to leave takes the path with no movers; a periodic
+    box one and two cells thick wraps movers onto their own cell's
+    neighbours from both sides."""
+    nx, ny, nz = shape
+    wl = W.spatial_box(nx=nx, ny=ny, nz=nz, per_cell=150, periodic=0b111, t_trans=30000.0)
+    if dt is not None:
+        wl.dt = dt
+    o = orc.from_workload(wl)
+    g = hc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    before = np.array([o.count(c) for c in range(wl.n_cells)])
+    for n in (1, 6):
+        o.step(wl.dt, n)
+        g.step(wl.dt, n)
+        g.sync()
+        _compare_state(o, g, f"{shape}: {n} steps")
+        _compare_pos(o, g, f"{shape}: {n} steps")
+    after = np.array([o.count(c) for c in range(wl.n_cells)])
+    if dt is None:
+        assert np.any(before != after)

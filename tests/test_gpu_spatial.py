@@ -191,3 +191,27 @@ def test_spatial_rebin_without_movers_and_on_thin_axes(orc, hc, shape, dt):
     after = np.array([o.count(c) for c in range(wl.n_cells)])
     if dt is None:
         assert np.any(before != after)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_spatial_launch_shape_invariance(hc, monkeypatch, precision):
+    """Movement, re-bin and collisions give the same bits for every launch
+    shape (workgroup size, slots per workgroup), in both forms."""
+    wl = W.spatial_box(nx=8, ny=6, nz=5, per_cell=180, periodic=0b101, chemistry=True, t_trans=12000.0, dt=5e-9)
+    prec = hc.FP64 if precision == "fp64" else hc.MIXED
+    outs = []
+    for block, slots in (("64", "1"), ("128", "3072"), ("256", "4608")):
+        monkeypatch.setenv("HCAO_BLOCK", block)
+        monkeypatch.setenv("HCAO_GROUP_SLOTS", slots)
+        g = hc.from_workload(wl, precision=prec)
+        g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+        g.step(wl.dt, 15)
+        g.sync()
+        outs.append((g.read_particles(), g.read_positions(), g.cell_state()[2]))
+        g.close()
+    for parts, pos, ctr in outs[1:]:
+        for a, b in zip(outs[0][0], parts):
+            assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
+        assert np.array_equal(outs[0][1].view(np.uint64), pos.view(np.uint64))
+        assert np.array_equal(outs[0][2], ctr)
+    assert outs[0][2][:, 1].sum() > 0

@@ -64,6 +64,8 @@ def lib():
         L.orc_load.argtypes = [vp, u64, vp, vp, vp, vp, vp, vp]
         L.orc_set_domain.argtypes = [vp, u32, u32, u32, d, d, d, u32]; L.orc_set_domain.restype = ctypes.c_int
         L.orc_read_pos.argtypes = [vp, u32, vp]; L.orc_read_pos.restype = ctypes.c_int
+        L.orc_set_inflow.argtypes = [vp, u32, vp, d, d]; L.orc_set_inflow.restype = ctypes.c_int
+        L.orc_flux_counts.argtypes = [vp, vp]; L.orc_flux_counts.restype = ctypes.c_int
         L.orc_set_rotation.argtypes = [vp, u32, u32, d]; L.orc_set_rotation.restype = ctypes.c_int
         L.orc_set_gamma_rot.argtypes = [vp, u32, d]; L.orc_set_gamma_rot.restype = ctypes.c_int
         L.orc_read_rot.argtypes = [vp, u32, vp]; L.orc_read_rot.restype = ctypes.c_int
@@ -228,6 +230,15 @@ class Oracle:
     def set_domain(self, nx, ny, nz, lx, ly, lz, periodic=0):
         _chk("orc_set_domain", lib().orc_set_domain(self._h, nx, ny, nz, float(lx), float(ly), float(lz),
                                                     int(periodic)))
+
+    def set_inflow(self, open_faces, number_density, t_trans, t_vib):
+        n = np.ascontiguousarray(number_density, np.float64)
+        _chk("orc_set_inflow", lib().orc_set_inflow(self._h, int(open_faces), _p(n), float(t_trans), float(t_vib)))
+
+    def flux_counts(self):
+        out = np.zeros(2, np.uint64)
+        _chk("orc_flux_counts", lib().orc_flux_counts(self._h, _p(out)))
+        return int(out[0]), int(out[1])
 
     def load(self, cell, species, vel, levels, rot=None, pos=None):
         cell = np.ascontiguousarray(cell, np.uint32)
@@ -436,4 +447,6 @@ def from_workload(wl, seed=None, capacity_per_cell=None):
     for rx in wl.reactions:
         o.add_reaction(rx)
     o.finalize()
+    if getattr(wl, "inflow", None) is not None:
+        o.set_inflow(*wl.inflow)
     return o

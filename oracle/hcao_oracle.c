@@ -23,6 +23,9 @@
  *                                     collision energies; the rotor model is our own)
  *   exact recombination sum ......... Sec. "Recombination reactions", Eq. recomb-correct
  *   spatial mode .................... not in the paper (move, re-bin, collide)
+ *   open faces ...................... not in the paper (outflow, admission from a
+ *                                     resting Maxwellian reservoir; the admitted
+ *                                     molecules' levels by the initial-state sampler)
  * Pieces the paper takes from elsewhere are written from their textbook
  * definitions: NTC candidate count and VHS cross-section (Bird), Marsaglia's
  * (1972) unit vector and polar normal method, Philox4x32-10 (Salmon et al.,
@@ -306,12 +309,21 @@ struct orc_ctx {
   uint32_t n_species, n_reactions, max_modes, has_recomb, has_rot;
   uint32_t spatial, nx, ny, nz, periodic; /* spatial mode: box of nx ny nz cells, periodic axes (bits) */
   double len[3];
+  /* open faces (bit 2 axis + side) and their reservoir; per (face cell,
+   * species) remainder of the expected inflow; particles in and out */
+  uint32_t open_faces, n_face_cells;
+  double in_flux[ORC_MAX_SPECIES]; /* n_s sqrt(k T / (2 pi m_s)) [m^-2 s^-1] */
+  double in_t, in_tv;
+  double *in_rem;
+  uint64_t flux_in, flux_out;
   double rec_l0, rec_inv_step; /* log(REC_TMIN), (REC_NT - 1) / log(REC_TMAX / REC_TMIN) */
   species_t sp[ORC_MAX_SPECIES];
   reaction_t rx[ORC_MAX_REACTIONS];
   pair_t pr[ORC_MAX_SPECIES][ORC_MAX_SPECIES];
   cell_t *cells;
 };
+
+static void reset_inflow(orc_ctx *o);
 
 static double mode_energy(const species_t *s, uint32_t m, uint32_t i) {
   if (m < s->n_bend) return ((double)i + 0.5) * s->kt[m];
@@ -378,6 +390,7 @@ void orc_destroy(orc_ctx *o) {
   if (o->cells)
     for (uint32_t c = 0; c < o->n_cells; ++c) free_cell(&o->cells[c]);
   free(o->cells);
+  free(o->in_rem);
   free(o);
 }
 
@@ -559,9 +572,11 @@ static uint32_t cell_of(const orc_ctx *o, double x, double y, double z) {
 }
 
 /* ballistic move of one coordinate over dt with the axis' boundary:
- * periodic wraps into [0, L); specular reflects (x < 0: -x, x > L: 2L - x,
- * velocity reversed) until inside [0, L] */
-static void move_axis(double *x, double *v, double dt, double len, int periodic) {
+ * periodic wraps into [0, L); a specular face reflects (x < 0: -x, x > L:
+ * 2L - x, velocity reversed) until inside [0, L]; crossing an open face
+ * (x < 0 with the face at 0 open, x > L with the face at L open) ends the
+ * move: returns 1, the particle leaves the box */
+static int move_axis(double *x, double *v, double dt, double len, int periodic, int open_lo, int open_hi) {
   double y = *x + *v * dt;
   if (periodic) {
     while (y < 0.0) y = y + len;
@@ -569,9 +584,11 @@ static void move_axis(double *x, double *v, double dt, double len, int periodic)
   } else {
     for (;;) {
       if (y < 0.0) {
+        if (open_lo) return 1;
         y = -y;
         *v = -*v;
       } else if (y > len) {
+        if (open_hi) return 1;
         y = (len + len) - y;
         *v = -*v;
       } else {
@@ -580,6 +597,74 @@ static void move_axis(double *x, double *v, double dt, double len, int periodic)
     }
   }
   *x = y;
+  return 0;
+}
+
+/* move of one particle on all three axes; 1 if it leaves through an open face */
+static int move_particle(const orc_ctx *o, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                         double dt) {
+  const uint32_t f = o->open_faces;
+  if (move_axis(x, vx, dt, o->len[0], (int)(o->periodic & 1u), (int)(f & 1u), (int)((f >> 1) & 1u))) return 1;
+  if (move_axis(y, vy, dt, o->len[1], (int)((o->periodic >> 1) & 1u), (int)((f >> 2) & 1u), (int)((f >> 3) & 1u)))
+    return 1;
+  return move_axis(z, vz, dt, o->len[2], (int)((o->periodic >> 2) & 1u), (int)((f >> 4) & 1u), (int)((f >> 5) & 1u));
+}
+
+/* cells per axis */
+static uint32_t axis_cells(const orc_ctx *o, int k) { return k == 0 ? o->nx : (k == 1 ? o->ny : o->nz); }
+
+/* the two axes tangential to face f, in increasing order, and the number of
+ * face cells (face cell j = i_a + n_a i_b) */
+static void face_axes(const orc_ctx *o, uint32_t f, int *a, int *b, uint32_t *size) {
+  int k = (int)(f >> 1);
+  *a = k == 0 ? 1 : 0;
+  *b = k == 2 ? 1 : 2;
+  *size = axis_cells(o, *a) * axis_cells(o, *b);
+}
+
+/* Surface-flux boundaries (spatial mode; not in the paper, whose cases are
+ * 0D reservoirs). Face f = 2 k + side lies on axis k at coordinate 0 (side
+ * 0) or L_k (side 1); bit f of open makes it open. A particle whose move
+ * crosses an open face leaves the box. Every step, after the move, each
+ * open face admits from a resting Maxwellian reservoir of number densities
+ * n_s at t_trans (translation and rotation) and t_vib: face cell j of face f
+ * gets floor(x) particles of species s, x = ((F_s A) dt) / F_N + rem, with
+ * the one-sided flux F_s = n_s sqrt(k T / (2 pi m_s)), A the face cell's area,
+ * F_N the weight of the cell behind it and rem the fraction carried from the
+ * previous step. Axes with an open face must not be periodic. */
+int orc_set_inflow(orc_ctx *o, uint32_t open, const double *n_s, double t_trans, double t_vib) {
+  if (!o || !o->spatial || !o->finalized) return E_STATE;
+  if (open > 63u || !n_s || !(t_trans > 0.0) || !(t_vib > 0.0) || !isfinite(t_trans) || !isfinite(t_vib))
+    return E_INVAL;
+  for (int k = 0; k < 3; ++k)
+    if (((o->periodic >> k) & 1u) && ((open >> (2 * k)) & 3u)) return E_INVAL;
+  for (uint32_t s = 0; s < o->n_species; ++s)
+    if (!(n_s[s] >= 0.0) || !isfinite(n_s[s])) return E_INVAL;
+  uint32_t total = 0;
+  for (uint32_t f = 0; f < 6; ++f) {
+    int a, b;
+    uint32_t size;
+    face_axes(o, f, &a, &b, &size);
+    total += size;
+  }
+  double *rem = (double *)calloc((size_t)total * o->n_species, sizeof(double));
+  if (!rem) return E_NOMEM;
+  free(o->in_rem);
+  o->in_rem = rem;
+  o->n_face_cells = total;
+  o->open_faces = open;
+  o->in_t = t_trans;
+  o->in_tv = t_vib;
+  for (uint32_t s = 0; s < o->n_species; ++s)
+    o->in_flux[s] = n_s[s] * sqrt((K_BOLTZ * t_trans) / ((2.0 * PI_D) * o->sp[s].mass));
+  return E_OK;
+}
+
+int orc_flux_counts(const orc_ctx *o, uint64_t *out) {
+  if (!o || !out) return E_INVAL;
+  out[0] = o->flux_in;
+  out[1] = o->flux_out;
+  return E_OK;
 }
 
 int orc_add_reaction(orc_ctx *o, int kind, const int32_t reactant[2], const int32_t product[2],
@@ -1038,6 +1123,7 @@ int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *specie
   for (uint32_t c = 0; c < o->n_cells; ++c) init_sgmax(o, &o->cells[c]);
   o->step = 0;
   o->loaded = 1;
+  reset_inflow(o);
   return E_OK;
 }
 
@@ -1053,6 +1139,54 @@ static void polar_normals(stream *st, double *n1, double *n2) {
   double f = sqrt((-2.0 * orc_detlog(s)) / s);
   *n1 = x * f;
   *n2 = y * f;
+}
+
+/* Internal state of a molecule drawn at T_vib (levels) and T_rot (rotational
+ * energy), the thermal initial state's sampler: levels of every mode in
+ * order, then the rotational energy. */
+static void sample_internal(const species_t *S, stream *st, double t_vib, double t_rot, uint16_t *lv, uint32_t mm,
+                            double *rot) {
+  for (uint32_t m = 0; m < mm; ++m) lv[m] = 0;
+  for (uint32_t m = 0; m < S->n_modes; ++m) {
+    if (m < S->n_bend) {
+      double r = 1.0 - uniform(st);
+      double t = -orc_detlog(r);
+      double fi = floor(t * (t_vib / S->theta[m]));
+      if (fi > 65535.0) fi = 65535.0;
+      lv[m] = (uint16_t)fi;
+    } else {
+      uint32_t top = S->idiss[m];
+      double kt = K_BOLTZ * t_vib;
+      for (;;) {
+        double u = uniform(st);
+        uint32_t i = (uint32_t)floor(u * (double)(top + 1));
+        if (i > top) i = top;
+        double u2 = uniform(st);
+        double x = (S->lev[m][i] - S->lev[m][0]) / kt;
+        if (u2 < orc_detexp(-x)) {
+          lv[m] = (uint16_t)i;
+          break;
+        }
+      }
+    }
+  }
+  *rot = 0.0;
+  if (S->zeta_rot > 0) {
+    double g = -orc_detlog(1.0 - uniform(st));
+    if (S->zeta_rot == 3) {
+      double z1, z2;
+      polar_normals(st, &z1, &z2);
+      g = g + 0.5 * (z1 * z1);
+    }
+    *rot = (K_BOLTZ * t_rot) * g;
+  }
+}
+
+/* a new particle state starts the inflow remainders and the flux counts afresh */
+static void reset_inflow(orc_ctx *o) {
+  if (o->in_rem) memset(o->in_rem, 0, (size_t)o->n_face_cells * o->n_species * sizeof(double));
+  o->flux_in = 0;
+  o->flux_out = 0;
 }
 
 /* Thermal initial state. Rotational energy (species with a rotor, after the
@@ -1091,41 +1225,7 @@ int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, 
         C->vy[slot] = sigma * n2;
         C->vz[slot] = sigma * n3;
         C->sp[slot] = (uint8_t)s;
-        uint16_t *lv = C->lvl + (size_t)slot * mm;
-        for (uint32_t m = 0; m < mm; ++m) lv[m] = 0;
-        for (uint32_t m = 0; m < S->n_modes; ++m) {
-          if (m < S->n_bend) {
-            double r = 1.0 - uniform(&st);
-            double t = -orc_detlog(r);
-            double fi = floor(t * (t_vib[c] / S->theta[m]));
-            if (fi > 65535.0) fi = 65535.0;
-            lv[m] = (uint16_t)fi;
-          } else {
-            uint32_t top = S->idiss[m];
-            double kt = K_BOLTZ * t_vib[c];
-            for (;;) {
-              double u = uniform(&st);
-              uint32_t i = (uint32_t)floor(u * (double)(top + 1));
-              if (i > top) i = top;
-              double u2 = uniform(&st);
-              double x = (S->lev[m][i] - S->lev[m][0]) / kt;
-              if (u2 < orc_detexp(-x)) {
-                lv[m] = (uint16_t)i;
-                break;
-              }
-            }
-          }
-        }
-        C->rot[slot] = 0.0;
-        if (S->zeta_rot > 0) {
-          double g = -orc_detlog(1.0 - uniform(&st));
-          if (S->zeta_rot == 3) {
-            double z1, z2;
-            polar_normals(&st, &z1, &z2);
-            g = g + 0.5 * (z1 * z1);
-          }
-          C->rot[slot] = (K_BOLTZ * t_trans[c]) * g;
-        }
+        sample_internal(S, &st, t_vib[c], t_trans[c], C->lvl + (size_t)slot * mm, mm, &C->rot[slot]);
         if (o->spatial) {
           /* uniform in the cell: x = (i_x + u) L_x / n_x per axis */
           uint32_t ix = c % o->nx, iy = (c / o->nx) % o->ny, iz = c / (o->nx * o->ny);
@@ -1141,6 +1241,7 @@ int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, 
   }
   o->step = 0;
   o->loaded = 1;
+  reset_inflow(o);
   return E_OK;
 }
 
@@ -1956,33 +2057,150 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
   return E_OK;
 }
 
+/* an inserted particle, held until the re-bin */
+typedef struct {
+  double v[3], p[3], rot;
+  uint16_t lvl[ORC_MAX_MODES];
+  uint8_t sp;
+  uint32_t cell; /* UINT32_MAX: left again during its partial flight */
+} inflow_t;
+
+/* The particles the open faces admit this step (faces in order, face cells
+ * in order, species in order). Particle i of species s at face cell j of
+ * face f draws from the stream pair = (s << 24) | i, cell = n_cells + the
+ * face cell's index over all six faces, step = the step: the normal speed
+ * from the flux-weighted Maxwellian, v_n = sigma sqrt(-2 ln(1 - u)); the two
+ * tangential components, sigma times a polar normal pair; the fraction tau
+ * of the step it flies; its place on the face cell, uniform on each
+ * tangential axis; then levels at t_vib and rotational energy at t_trans as
+ * the thermal initial state draws them. It enters at the face and moves
+ * over tau dt with the box's boundaries. */
+static int make_inflow(orc_ctx *o, double dt, inflow_t **out, uint64_t *n_out) {
+  uint32_t mm = o->max_modes ? o->max_modes : 1;
+  uint64_t n = 0, cap = 0;
+  inflow_t *list = NULL;
+  uint32_t base = 0;
+  for (uint32_t f = 0; f < 6; ++f) {
+    int a, b;
+    uint32_t size;
+    face_axes(o, f, &a, &b, &size);
+    if (!((o->open_faces >> f) & 1u)) {
+      base += size;
+      continue;
+    }
+    int k = (int)(f >> 1), side = (int)(f & 1u);
+    uint32_t na = axis_cells(o, a), nb = axis_cells(o, b), nk = axis_cells(o, k);
+    double da = o->len[a] / (double)na, db = o->len[b] / (double)nb;
+    double area = da * db;
+    for (uint32_t j = 0; j < size; ++j) {
+      uint32_t idx[3];
+      idx[k] = side ? nk - 1 : 0;
+      idx[a] = j % na;
+      idx[b] = j / na;
+      uint32_t c = idx[0] + o->nx * (idx[1] + o->ny * idx[2]);
+      double weight = o->cells[c].weight;
+      for (uint32_t s = 0; s < o->n_species; ++s) {
+        double *rem = &o->in_rem[(size_t)(base + j) * o->n_species + s];
+        double x = ((o->in_flux[s] * area) * dt) / weight + *rem;
+        double fl = floor(x);
+        if (!(fl < 16777216.0)) {
+          free(list);
+          return E_INVAL;
+        }
+        uint32_t cnt = (uint32_t)fl;
+        *rem = x - fl;
+        const species_t *S = &o->sp[s];
+        double sigma = sqrt((K_BOLTZ * o->in_t) / S->mass);
+        for (uint32_t i = 0; i < cnt; ++i) {
+          if (n == cap) {
+            cap = cap ? 2 * cap : 1024;
+            inflow_t *nl = (inflow_t *)realloc(list, cap * sizeof(inflow_t));
+            if (!nl) {
+              free(list);
+              return E_NOMEM;
+            }
+            list = nl;
+          }
+          inflow_t *P = &list[n++];
+          stream st;
+          stream_open(&st, o->seed, (s << 24) | i, o->n_cells + base + j, o->step);
+          double vn = sigma * sqrt(-2.0 * orc_detlog(1.0 - uniform(&st)));
+          double n1, n2;
+          polar_normals(&st, &n1, &n2);
+          double tau = uniform(&st);
+          double ua = uniform(&st);
+          double ub = uniform(&st);
+          P->p[k] = side ? o->len[k] : 0.0;
+          P->v[k] = side ? -vn : vn;
+          P->p[a] = ((double)idx[a] + ua) * da;
+          P->p[b] = ((double)idx[b] + ub) * db;
+          P->v[a] = sigma * n1;
+          P->v[b] = sigma * n2;
+          P->sp = (uint8_t)s;
+          sample_internal(S, &st, o->in_tv, o->in_t, P->lvl, mm, &P->rot);
+          if (move_particle(o, &P->p[0], &P->p[1], &P->p[2], &P->v[0], &P->v[1], &P->v[2], tau * dt))
+            P->cell = UINT32_MAX;
+          else
+            P->cell = cell_of(o, P->p[0], P->p[1], P->p[2]);
+        }
+      }
+    }
+    base += size;
+  }
+  *out = list;
+  *n_out = n;
+  return E_OK;
+}
+
 /* Spatial mode: every particle moves over dt (cells in order, particles in
- * slot order), then all are re-binned by their new cell, keeping that
- * order within each new cell (a stable counting sort). */
+ * slot order; one that crosses an open face leaves), the open faces admit
+ * their particles, then all are re-binned by their new cell: within each
+ * new cell the particles already in the box keep their order and the
+ * admitted ones follow in the order they were made. */
 static int move_and_rebin(orc_ctx *o, double dt) {
   uint32_t mm = o->max_modes ? o->max_modes : 1;
   uint32_t *newn = (uint32_t *)calloc(o->n_cells, sizeof(uint32_t));
-  if (!newn) return E_NOMEM;
-  for (uint32_t c = 0; c < o->n_cells; ++c) {
-    cell_t *C = &o->cells[c];
-    for (uint32_t i = 0; i < C->n; ++i) {
-      move_axis(&C->px[i], &C->vx[i], dt, o->len[0], (int)(o->periodic & 1u));
-      move_axis(&C->py[i], &C->vy[i], dt, o->len[1], (int)((o->periodic >> 1) & 1u));
-      move_axis(&C->pz[i], &C->vz[i], dt, o->len[2], (int)((o->periodic >> 2) & 1u));
-      newn[cell_of(o, C->px[i], C->py[i], C->pz[i])] += 1;
-    }
-  }
-  for (uint32_t c = 0; c < o->n_cells; ++c)
-    if (newn[c] > o->cells[c].cap) {
-      free(newn);
-      return E_CAPACITY;
-    }
-  cell_t *nc = (cell_t *)calloc(o->n_cells, sizeof(cell_t));
-  if (!nc) {
+  uint32_t **dest = (uint32_t **)calloc(o->n_cells, sizeof(uint32_t *));
+  if (!newn || !dest) {
     free(newn);
+    free(dest);
     return E_NOMEM;
   }
   int rc = E_OK;
+  for (uint32_t c = 0; c < o->n_cells && !rc; ++c) {
+    cell_t *C = &o->cells[c];
+    dest[c] = (uint32_t *)malloc((C->n ? C->n : 1) * sizeof(uint32_t));
+    if (!dest[c]) {
+      rc = E_NOMEM;
+      break;
+    }
+    for (uint32_t i = 0; i < C->n; ++i) {
+      if (move_particle(o, &C->px[i], &C->py[i], &C->pz[i], &C->vx[i], &C->vy[i], &C->vz[i], dt)) {
+        dest[c][i] = UINT32_MAX;
+        o->flux_out += 1;
+      } else {
+        dest[c][i] = cell_of(o, C->px[i], C->py[i], C->pz[i]);
+        newn[dest[c][i]] += 1;
+      }
+    }
+  }
+  inflow_t *ins = NULL;
+  uint64_t n_ins = 0;
+  if (!rc && o->open_faces) rc = make_inflow(o, dt, &ins, &n_ins);
+  for (uint64_t i = 0; i < n_ins && !rc; ++i) {
+    o->flux_in += 1;
+    if (ins[i].cell == UINT32_MAX)
+      o->flux_out += 1;
+    else
+      newn[ins[i].cell] += 1;
+  }
+  for (uint32_t c = 0; c < o->n_cells && !rc; ++c)
+    if (newn[c] > o->cells[c].cap) rc = E_CAPACITY;
+  cell_t *nc = NULL;
+  if (!rc) {
+    nc = (cell_t *)calloc(o->n_cells, sizeof(cell_t));
+    if (!nc) rc = E_NOMEM;
+  }
   for (uint32_t c = 0; c < o->n_cells && !rc; ++c) {
     rc = alloc_cell(o, &nc[c], o->cells[c].cap);
     nc[c].volume = o->cells[c].volume;
@@ -1994,7 +2212,8 @@ static int move_and_rebin(orc_ctx *o, double dt) {
   for (uint32_t c = 0; c < o->n_cells && !rc; ++c) {
     cell_t *C = &o->cells[c];
     for (uint32_t i = 0; i < C->n; ++i) {
-      cell_t *D = &nc[cell_of(o, C->px[i], C->py[i], C->pz[i])];
+      if (dest[c][i] == UINT32_MAX) continue;
+      cell_t *D = &nc[dest[c][i]];
       uint32_t j = D->n++;
       D->vx[j] = C->vx[i];
       D->vy[j] = C->vy[i];
@@ -2007,15 +2226,35 @@ static int move_and_rebin(orc_ctx *o, double dt) {
       for (uint32_t m = 0; m < mm; ++m) D->lvl[(size_t)j * mm + m] = C->lvl[(size_t)i * mm + m];
     }
   }
-  for (uint32_t c = 0; c < o->n_cells; ++c) {
-    if (!rc) {
-      free_cell(&o->cells[c]);
-      o->cells[c] = nc[c];
-    } else {
-      free_cell(&nc[c]);
+  for (uint64_t i = 0; i < n_ins && !rc; ++i) {
+    const inflow_t *P = &ins[i];
+    if (P->cell == UINT32_MAX) continue;
+    cell_t *D = &nc[P->cell];
+    uint32_t j = D->n++;
+    D->vx[j] = P->v[0];
+    D->vy[j] = P->v[1];
+    D->vz[j] = P->v[2];
+    D->sp[j] = P->sp;
+    D->rot[j] = P->rot;
+    D->px[j] = P->p[0];
+    D->py[j] = P->p[1];
+    D->pz[j] = P->p[2];
+    for (uint32_t m = 0; m < mm; ++m) D->lvl[(size_t)j * mm + m] = P->lvl[m];
+  }
+  if (nc) {
+    for (uint32_t c = 0; c < o->n_cells; ++c) {
+      if (!rc) {
+        free_cell(&o->cells[c]);
+        o->cells[c] = nc[c];
+      } else {
+        free_cell(&nc[c]);
+      }
     }
   }
   free(nc);
+  for (uint32_t c = 0; c < o->n_cells; ++c) free(dest[c]);
+  free(dest);
+  free(ins);
   free(newn);
   return rc;
 }

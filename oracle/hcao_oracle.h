@@ -78,6 +78,12 @@ int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *specie
 int orc_set_domain(orc_ctx *o, uint32_t nx, uint32_t ny, uint32_t nz, double lx, double ly, double lz,
                    uint32_t periodic);
 int orc_read_pos(const orc_ctx *o, uint32_t cell, double *pos);
+/* spatial mode, after finalize: faces f = 2 axis + side (side 1 at L) open
+ * as bits of open, admitting from a resting reservoir of number densities
+ * n_s[n_species] [m^-3] at t_trans and t_vib */
+int orc_set_inflow(orc_ctx *o, uint32_t open, const double *n_s, double t_trans, double t_vib);
+/* out[0] particles admitted, out[1] particles that left, since the last load */
+int orc_flux_counts(const orc_ctx *o, uint64_t *out);
 int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, const double *t_vib);
 int orc_step(orc_ctx *o, double dt, uint32_t n_steps);
 

@@ -95,6 +95,9 @@ class Workload:
     capacity_per_cell: int = 0
     notes: str = ""
     domain: Optional[tuple] = None  # spatial mode: (nx, ny, nz, lx, ly, lz, periodic axis bits)
+    # spatial mode, open faces: (face bits 2 axis + side, reservoir number
+    # densities [n_species] m^-3, T_trans, T_vib)
+    inflow: Optional[tuple] = None
 
     @property
     def n_cells(self) -> int:
@@ -229,14 +232,17 @@ def batched_reservoirs(n_res=4096, lo=1_000, hi=100_000, seed=0, steps=1000):
 # ---------------------------------------------------------------------------
 
 def spatial_box(nx=16, ny=16, nz=16, per_cell=256, cell_edge=1e-4, periodic=0, chemistry=False,
-                t_trans=20_000.0, t_vib=300.0, dt=1e-8, seed=0):
+                t_trans=20_000.0, t_vib=300.0, dt=1e-8, seed=0, open_faces=0, empty=False):
     """A box of nx x ny x nz cubic cells of edge cell_edge [m] at density
     1e22 m^-3 (F_N = n V_cell / per_cell), walls specular except on the
     periodic axes (bits 0..2). Species and reactions of the methane/argon
     workload (or, with chemistry=True, the CH4/CH3/H/H2 chemistry at
     t_trans). A particle at 5 km/s crosses half a 0.1 mm cell per 1e-8 s
     step, so the per-step re-binning moves a large share of particles.
-    Cells get room for twice their initial count."""
+    Cells get room for twice their initial count. open_faces (bits 2 axis +
+    side, on non-periodic axes) opens faces to a reservoir of the initial
+    composition, density and temperatures; empty=True starts the box with
+    no particles (it then fills through its open faces)."""
     n_cells = nx * ny * nz
     vol = cell_edge ** 3
     if chemistry:
@@ -252,6 +258,11 @@ def spatial_box(nx=16, ny=16, nz=16, per_cell=256, cell_edge=1e-4, periodic=0, c
     base.capacity_per_cell = 2 * per_cell + 64
     base.name = f"box-{nx}x{ny}x{nz}"
     base.seed = seed
+    if open_faces:
+        frac = base.counts[0] / float(per_cell)
+        base.inflow = (open_faces, DENSITY * frac, float(base.t_trans[0]), float(base.t_vib[0]))
+    if empty:
+        base.counts = np.zeros_like(base.counts)
     return base
 
 

@@ -1,0 +1,219 @@
+"""Open faces of the spatial mode (surface-flux insertion and outflow):
+pins of the oracle against physics the inflow formula does not encode.
+
+  - an empty, collisionless box open on two faces to a resting reservoir
+    fills, by the particles' own ballistic motion in and out, to the
+    reservoir's density per species and to its temperature on every axis:
+    effusion out of a uniform gas carries n sqrt(kT / 2 pi m) per unit area,
+    so a wrong flux constant, a wrong mass dependence or a wrong normal-speed
+    law shows as a wrong steady state;
+  - the particles admitted in one short step: normal speeds follow the
+    flux-weighted Maxwellian (Rayleigh), tangential speeds the Maxwellian,
+    entry depth / (v_n dt) is uniform, places are uniform on the face cell,
+    bend levels Boltzmann at the reservoir's T_vib (KS and chi-square);
+  - outflow and reflection of single particles against closed forms;
+  - bookkeeping: count = initial + admitted - left, and admitted particles
+    follow a cell's earlier particles in the re-bin order.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2606_31548_amd import workloads as W
+
+KB, AMU = W.K_BOLTZ, W.AMU
+
+
+def _tracers(masses, dref=1e-14):
+    """Collisionless tracer species (a cross-section 10^-8 of a molecule's),
+    one bend each so the levels can be checked."""
+    return [W.Species(f"t{i}", m * AMU, bend_theta_K=[1500.0], dref_m=dref) for i, m in enumerate(masses)]
+
+
+def _box(orc, species, dims, edge, weight, open_faces, n_res, t, t_vib=2000.0, cap=4096, seed=3):
+    nx, ny, nz = dims
+    n_cells = nx * ny * nz
+    o = orc.Oracle(seed, n_cells, edge ** 3, weight, capacity_per_cell=cap)
+    o.set_domain(nx, ny, nz, nx * edge, ny * edge, nz * edge, 0)
+    for s in species:
+        o.add_species(s)
+    o.finalize()
+    o.set_inflow(open_faces, n_res, t, t_vib)
+    z = np.zeros(0)
+    o.load(z.astype(np.uint32), z.astype(np.uint8), np.zeros((0, 3)), np.zeros((0, 1), np.uint16), None,
+           np.zeros((0, 3)))
+    return o
+
+
+def _all(o, n_cells):
+    sp, vel, lvl, pos, cell = [], [], [], [], []
+    for c in range(n_cells):
+        s, v, lv = o.read_cell(c)
+        sp.append(s)
+        vel.append(v)
+        lvl.append(lv)
+        pos.append(o.read_pos(c))
+        cell.append(np.full(len(s), c))
+    return (np.concatenate(sp), np.concatenate(vel), np.concatenate(lvl), np.concatenate(pos),
+            np.concatenate(cell))
+
+
+def test_empty_box_fills_to_the_reservoir_state(orc):
+    """Two tracer species (4 and 40 amu) around a 4 x 4 x 4 box open on all
+    six faces, at 1000 K: without collisions every trajectory inside came in
+    through a face, so the filled box holds the reservoir's Maxwellian: n_s V
+    / F_N of each species, and the reservoir temperature on each axis."""
+    dims, edge, t = (4, 4, 4), 1e-4, 1000.0
+    n_res = np.array([3e21, 7e21])
+    vol = (dims[0] * edge) * (dims[1] * edge) * (dims[2] * edge)
+    weight = 4e7  # about 4,800 and 11,200 tracers at the reservoir density
+    o = _box(orc, _tracers([4.0, 40.0]), dims, edge, weight, 0b111111, n_res, t)
+    n_cells = int(np.prod(dims))
+    dt = 2e-8  # 40 amu at 1000 K (sigma 456 m/s) crosses the 0.4 mm box in ~45 steps
+    o.step(dt, 150)
+    counts = np.zeros(2)
+    ekin = np.zeros((2, 3))
+    samples = 0
+    for _ in range(40):
+        o.step(dt, 5)
+        sp, vel, _, _, _ = _all(o, n_cells)
+        for s in range(2):
+            v = vel[sp == s]
+            counts[s] += len(v)
+            ekin[s] += (v ** 2).sum(0)
+        samples += 1
+    want = n_res * vol / weight
+    got = counts / samples
+    np.testing.assert_allclose(got, want, rtol=0.04)
+    masses = np.array([4.0, 40.0]) * AMU
+    for s in range(2):
+        t_axis = masses[s] * ekin[s] / counts[s] / KB
+        np.testing.assert_allclose(t_axis, t, rtol=0.04)
+    n_in, n_out = o.flux_counts()
+    assert n_in - n_out == sum(o.count(c) for c in range(n_cells))
+
+
+def test_admitted_particles_follow_the_flux_distribution(orc):
+    """One 1e-9 s step into an empty box through the face at x = 0 (4 x 4
+    face cells): ~5,800 argon tracers that stay within 2 um of the face."""
+    dims, edge, t, t_vib = (3, 4, 4), 1e-4, 1000.0, 2000.0
+    species = _tracers([40.0])
+    o = _box(orc, species, dims, edge, 1e5, 0b000001, np.array([1e22]), t, t_vib=t_vib)
+    dt = 1e-9
+    o.step(dt, 1)
+    sp, vel, lvl, pos, cell = _all(o, int(np.prod(dims)))
+    n = len(sp)
+    area = edge * edge
+    flux = 1e22 * math.sqrt((KB * t) / ((2.0 * math.pi) * species[0].mass_kg))
+    x = ((flux * area) * dt) / 1e5
+    assert n == 16 * math.floor(x)
+    assert o.flux_counts() == (n, 0)
+    sigma = math.sqrt(KB * t / (40 * AMU))
+    vn = vel[:, 0]
+    assert np.all(vn >= 0)
+    assert stats.kstest(vn / sigma, "rayleigh").pvalue > 1e-3
+    for ax in (1, 2):
+        assert stats.kstest(vel[:, ax] / sigma, "norm").pvalue > 1e-3
+    depth = pos[:, 0] / (vn * dt)
+    assert stats.kstest(depth[vn > 0], "uniform").pvalue > 1e-3
+    for ax in (1, 2):
+        frac = pos[:, ax] / edge - np.floor(pos[:, ax] / edge)
+        assert stats.kstest(frac, "uniform").pvalue > 1e-3
+    # every face cell admitted the same number into the cell behind it; a
+    # tangential drift of < 1 um moves a few across face-cell edges
+    iy = np.floor(pos[:, 1] / edge).astype(int)
+    iz = np.floor(pos[:, 2] / edge).astype(int)
+    assert np.all(cell == 3 * (iy + 4 * iz))
+    assert np.all(np.abs(np.bincount(iy + 4 * iz, minlength=16) - math.floor(x)) <= 4)
+    # bend levels: geometric with ratio exp(-Theta / T_vib)
+    r = math.exp(-1500.0 / t_vib)
+    k = np.arange(6)
+    p = (1 - r) * r ** k
+    obs = np.bincount(np.minimum(lvl[:, 0], 5), minlength=6)
+    exp = np.append(p[:5], 1 - p[:5].sum()) * n
+    assert stats.chisquare(obs, exp).pvalue > 1e-3
+
+
+def test_outflow_and_reflection_against_closed_forms(orc):
+    """Face x = 0 open, x = L specular, other axes specular. A particle
+    heading for x = 0 leaves; one heading for x = L folds back; one that
+    folds at x = L and then reaches x = 0 in the same step leaves too."""
+    edge = 1e-4
+    sp = _tracers([40.0])
+    o = orc.Oracle(1, 3, edge ** 3, 1.0, capacity_per_cell=8)
+    o.set_domain(3, 1, 1, 3 * edge, edge, edge, 0)
+    o.add_species(sp[0])
+    o.finalize()
+    o.set_inflow(0b000001, np.array([0.0]), 300.0, 300.0)  # open, nothing comes in
+    L = 3 * edge
+    pos = np.array([[0.5 * edge, 0.5 * edge, 0.5 * edge],
+                    [2.5 * edge, 0.5 * edge, 0.5 * edge],
+                    [2.9 * edge, 0.5 * edge, 0.5 * edge]])
+    dt = 1e-7
+    vel = np.array([[-1000.0, 0.0, 0.0],       # 0.1 mm to the open face in 1e-7 s: leaves
+                    [1000.0, 0.0, 0.0],        # to L, folds back: 2L - (x + v dt)
+                    [4000.0, 0.0, 0.0]])       # folds at L, then 0.4 mm back: crosses x = 0
+    cell = np.array([0, 2, 2], np.uint32)
+    ids = np.array([[1], [2], [3]], np.uint16)
+    o.load(cell, np.zeros(3, np.uint8), vel, ids, None, pos)
+    o.step(dt, 1)
+    s, v, lv, p, c = _all(o, 3)
+    assert list(lv[:, 0]) == [2]
+    assert p[0, 0] == pytest.approx(2 * L - (2.5 * edge + 1000.0 * dt), rel=1e-12)
+    assert v[0, 0] == -1000.0
+    assert o.flux_counts() == (0, 2)
+
+
+def test_admitted_particles_come_after_a_cells_earlier_particles(orc):
+    """Collisionless tracers with identity levels (>= 1000) in a box open at
+    x = 0 and x = L: after a step every cell lists the tracers that were in
+    the box, in their previous order, before the admitted ones (levels drawn
+    at T_vib, all far below 1000)."""
+    dims, edge = (5, 2, 2), 1e-4
+    sp = _tracers([40.0])
+    n_cells = int(np.prod(dims))
+    o = orc.Oracle(7, n_cells, edge ** 3, 1e7, capacity_per_cell=2048)
+    o.set_domain(*dims, dims[0] * edge, dims[1] * edge, dims[2] * edge, 0)
+    o.add_species(sp[0])
+    o.finalize()
+    o.set_inflow(0b000011, np.array([5e21]), 1000.0, 1000.0)
+    rng = np.random.default_rng(2)
+    n = 1500
+    L = np.array(dims) * edge
+    pos = rng.random((n, 3)) * L
+    vel = rng.standard_normal((n, 3)) * 456.0
+    ijk = np.minimum(np.floor(pos / edge).astype(int), np.array(dims) - 1)
+    cell = (ijk[:, 0] + dims[0] * (ijk[:, 1] + dims[1] * ijk[:, 2])).astype(np.uint32)
+    order = np.argsort(cell, kind="stable")
+    ids = (1000 + np.arange(n)).astype(np.uint16)
+    o.load(cell[order], np.zeros(n, np.uint8), vel[order], ids[order][:, None], None, pos[order])
+    before = _all(o, n_cells)[2][:, 0]
+    rank = {int(i): r for r, i in enumerate(before)}
+    o.step(4e-8, 1)
+    _, _, lvl, _, c = _all(o, n_cells)
+    admitted = 0
+    for k in range(n_cells):
+        lv = lvl[c == k, 0].astype(int)
+        old = lv >= 1000
+        assert not np.any(np.diff(old.astype(int)) > 0), "an admitted particle precedes an earlier one"
+        r = [rank[i] for i in lv[old]]
+        assert np.all(np.diff(r) > 0)
+        admitted += int((~old).sum())
+    assert admitted > 100
+
+
+def test_admitted_particles_follow_earlier_ones_and_counts_balance(orc):
+    """A methane/argon box with collisions and chemistry, x faces open: the
+    particle count closes: initial + admitted - left + births - deaths."""
+    wl = W.spatial_box(nx=4, ny=3, nz=2, per_cell=120, open_faces=0b000011, t_trans=20000.0)
+    o = orc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    n0 = sum(o.count(c) for c in range(wl.n_cells))
+    o.step(wl.dt, 30)
+    n_in, n_out = o.flux_counts()
+    ctr = o.counters().sum(0)
+    n1 = sum(o.count(c) for c in range(wl.n_cells))
+    assert n_in > 100 and n_out > 100
+    assert n1 == n0 + n_in - n_out + int(ctr[orc.CTR_BIRTHS]) - int(ctr[orc.CTR_DEATHS])

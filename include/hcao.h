@@ -243,6 +243,31 @@ typedef struct {
   double lx, ly, lz;
 } hcao_domain;
 
+/* Open faces of the spatial mode (surface-flux boundaries; the paper's
+ * cases are 0D reservoirs). Face f = 2 axis + side lies on that axis at 0
+ * (side 0) or at L (side 1); bit f of open_faces opens it. A particle whose
+ * move crosses an open face leaves the box. Every step, after the move,
+ * face cell j of an open face (numbered over all six faces in face order,
+ * j = i_a + n_a i_b on the face's tangential axes a < b) admits, per species
+ * s, floor(x) particles with x = ((F_s A) dt) / F_N + rem, F_s = n_s sqrt(k
+ * T_trans / (2 pi m_s)) the one-sided flux of a resting Maxwellian
+ * reservoir, A the face cell's area, F_N the weight of the cell behind it,
+ * rem the fraction carried from the previous step. Admission i of species s
+ * draws from the stream (pair (s << 24) | i, cell n_cells + j, the step):
+ * normal speed sigma sqrt(-2 ln(1 - u)) inward (sigma^2 = k T_trans / m_s),
+ * the two tangential components sigma times a polar normal pair, the
+ * fraction tau of the step it flies, its place uniform on the face cell per
+ * tangential axis, then levels at T_vib and rotational energy at T_trans as
+ * hcao_init_thermal draws them; it enters at the face and moves over tau dt
+ * (and may leave again). Within a cell, admitted particles follow the
+ * particles already in the box, in the order they were made.
+ * number_density[n_species] in m^-3 (caller-owned, copied). */
+typedef struct {
+  uint32_t open_faces, pad;
+  const double *number_density;
+  double t_trans_K, t_vib_K;
+} hcao_inflow;
+
 const char *hcao_status_string(hcao_status s);
 const char *hcao_last_error(const hcao_ctx *ctx);
 
@@ -259,6 +284,18 @@ hcao_status hcao_add_reaction(hcao_ctx *ctx, const hcao_reaction_desc *rx, int32
  * its slot capacity raises HCAO_ECAPACITY. hcao_step_graph and
  * hcao_autotune are not available in this mode (HCAO_EUNSUPPORTED). */
 hcao_status hcao_set_domain(hcao_ctx *ctx, const hcao_domain *domain);
+/* Opens faces of the spatial mode to a reservoir (after finalize; before
+ * the particles are loaded or at any later point: the inflow remainders and
+ * flux counts start at zero here and at every load, init and restore).
+ * open_faces 0 closes them again. HCAO_ESTATE outside the spatial mode,
+ * HCAO_EINVAL for an open face on a periodic axis, a negative or
+ * non-finite density or a non-positive temperature. A checkpoint of a
+ * context with open faces restores only into a context with open faces. */
+hcao_status hcao_set_inflow(hcao_ctx *ctx, const hcao_inflow *inflow);
+/* out[0]: particles admitted through open faces, out[1]: particles that
+ * left through them (admissions that leave again during their first flight
+ * included), since the last load, init or restore; zeros without open faces. */
+hcao_status hcao_read_flux_counts(hcao_ctx *ctx, uint64_t out[2]);
 /* Builds the level, pair and reaction tables and uploads them. */
 hcao_status hcao_finalize(hcao_ctx *ctx);
 

@@ -1808,6 +1808,58 @@ __device__ __forceinline__ void polar_normals(Rng &rng, double &n1, double &n2) 
   n2 = y * f;
 }
 
+// Internal state of a new molecule at T_vib (levels) and T_rot (rotational
+// energy): bends by the floor form, stretches by the uniform proposal with
+// the Boltzmann acceptance, then (rotors only) Gamma(zeta/2, k T_rot):
+// -ln(1 - u) plus, for zeta = 3, half the square of one polar normal. Writes
+// the levels (mode-major, stride st.stride) and the rotational energy of
+// slot g. The thermal initial state and admission through open faces draw
+// the same way.
+__device__ __forceinline__ void sample_internal(const SpeciesTab &S, const double *lev, Rng &rng, double tv,
+                                                double trot, const State &st, uint64_t g, uint32_t mm) {
+  for (uint32_t m = 0; m < mm; ++m) {
+    uint32_t l = 0;
+    if (m < S.n_modes) {
+      if (m < S.n_bend) {
+        const double r = 1.0 - rng.uniform();
+        const double lg = -dlog(r);
+        double fi = floor(lg * (tv / S.theta[m]));
+        fi = fi > 65535.0 ? 65535.0 : fi;
+        l = (uint32_t)fi;
+      } else {
+        const uint32_t top = S.idiss[m];
+        const double *L = lev + S.lev_off[m];
+        const double kt = kBoltz * tv;
+        for (;;) {
+          const double u = rng.uniform();
+          uint32_t j = (uint32_t)floor(u * (double)(top + 1));
+          j = j > top ? top : j;
+          const double u2 = rng.uniform();
+          const double xx = (L[j] - L[0]) / kt;
+          if (u2 < dexp(-xx)) {
+            l = j;
+            break;
+          }
+        }
+      }
+    }
+    st.lvl[m * st.stride + g] = (uint16_t)l;
+  }
+  if (st.rot) {
+    double e = 0.0;
+    if (S.zeta_rot > 0) {
+      double gm = -dlog(1.0 - rng.uniform());
+      if (S.zeta_rot == 3) {
+        double z1, z2;
+        polar_normals(rng, z1, z2);
+        gm = gm + 0.5 * (z1 * z1);
+      }
+      e = (kBoltz * trot) * gm;
+    }
+    st.rot[g] = e;
+  }
+}
+
 struct InitArgs {
   const Tables *tab;
   const double *lev;
@@ -1842,49 +1894,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs A) {
     const uint64_t g = A.off[c] + i;
     store_vel(A.st, g, sigma * n1, sigma * n2, sigma * n3);
     A.st.sp[g] = (uint8_t)s;
-    for (uint32_t m = 0; m < mm; ++m) {
-      uint32_t l = 0;
-      if (m < S.n_modes) {
-        if (m < S.n_bend) {
-          const double r = 1.0 - rng.uniform();
-          const double lg = -dlog(r);
-          double fi = floor(lg * (tv / S.theta[m]));
-          fi = fi > 65535.0 ? 65535.0 : fi;
-          l = (uint32_t)fi;
-        } else {
-          const uint32_t top = S.idiss[m];
-          const double *L = A.lev + S.lev_off[m];
-          const double kt = kBoltz * tv;
-          for (;;) {
-            const double u = rng.uniform();
-            uint32_t j = (uint32_t)floor(u * (double)(top + 1));
-            j = j > top ? top : j;
-            const double u2 = rng.uniform();
-            const double xx = (L[j] - L[0]) / kt;
-            if (u2 < dexp(-xx)) {
-              l = j;
-              break;
-            }
-          }
-        }
-      }
-      A.st.lvl[m * A.st.stride + g] = (uint16_t)l;
-    }
-    if (A.st.rot) {
-      // rotational energy of a rotor: Gamma(zeta/2, k T_trans), -ln(1 - u)
-      // plus, for zeta = 3, half the square of one polar normal
-      double e = 0.0;
-      if (S.zeta_rot > 0) {
-        double gm = -dlog(1.0 - rng.uniform());
-        if (S.zeta_rot == 3) {
-          double z1, z2;
-          polar_normals(rng, z1, z2);
-          gm = gm + 0.5 * (z1 * z1);
-        }
-        e = (kBoltz * tt) * gm;
-      }
-      A.st.rot[g] = e;
-    }
+    sample_internal(S, A.lev, rng, tv, tt, A.st, g, mm);
     if (A.st.px) {
       // spatial mode: uniform in the cell, one draw per axis
       const uint32_t ix = c % A.nx, iy = (c / A.nx) % A.ny, iz = c / (A.nx * A.ny);
@@ -2412,7 +2422,11 @@ __global__ __launch_bounds__(256) void k_rec_sum(RecSumArgs A) {
 // stable re-bin by (new cell, old slot) that sorts only the particles that
 // left their cell
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double move_axis(double x, double &v, double dt, double len, bool periodic) {
+// one coordinate over dt: periodic axes wrap into [0, L); a specular face
+// reflects (x < 0: -x, x > L: 2L - x, velocity reversed) until inside
+// [0, L]; crossing an open face sets left and ends the move
+__device__ __forceinline__ double move_axis(double x, double &v, double dt, double len, bool periodic, bool open_lo,
+                                           bool open_hi, bool &left) {
   double y = x + v * dt;
   if (periodic) {
     while (y < 0.0) y = y + len;
@@ -2420,9 +2434,17 @@ __device__ __forceinline__ double move_axis(double x, double &v, double dt, doub
   } else {
     for (;;) {
       if (y < 0.0) {
+        if (open_lo) {
+          left = true;
+          break;
+        }
         y = -y;
         v = -v;
       } else if (y > len) {
+        if (open_hi) {
+          left = true;
+          break;
+        }
         y = (len + len) - y;
         v = -v;
       } else {
@@ -2431,6 +2453,19 @@ __device__ __forceinline__ double move_axis(double x, double &v, double dt, doub
     }
   }
   return y;
+}
+
+// a particle over dt on x, then y, then z; true if it leaves through an open
+// face (its coordinates are then of no use)
+__device__ __forceinline__ bool move_particle(double &x, double &y, double &z, double &vx, double &vy, double &vz,
+                                              double dt, const double len[3], uint32_t periodic, uint32_t open) {
+  bool left = false;
+  x = move_axis(x, vx, dt, len[0], (periodic & 1u) != 0, (open & 1u) != 0, (open & 2u) != 0, left);
+  if (left) return true;
+  y = move_axis(y, vy, dt, len[1], (periodic & 2u) != 0, (open & 4u) != 0, (open & 8u) != 0, left);
+  if (left) return true;
+  z = move_axis(z, vz, dt, len[2], (periodic & 4u) != 0, (open & 16u) != 0, (open & 32u) != 0, left);
+  return left;
 }
 
 __device__ __forceinline__ uint32_t axis_index(double x, double len, uint32_t n) {
@@ -2452,23 +2487,24 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
   for (uint32_t i0 = 0; i0 < n; i0 += 256) {
     const uint32_t i = i0 + tid;
     const uint64_t g = base + i;
-    bool mover = false;
+    bool mover = false, stayer = false;
     if (i < n) {
       const Vec3 v = load_vel(A.st, g);
       double vx = v.x, vy = v.y, vz = v.z;
-      const double x = move_axis(A.st.px[g], vx, A.dt, A.len[0], (A.periodic & 1u) != 0);
-      const double y = move_axis(A.st.py[g], vy, A.dt, A.len[1], (A.periodic & 2u) != 0);
-      const double z = move_axis(A.st.pz[g], vz, A.dt, A.len[2], (A.periodic & 4u) != 0);
-      A.st.px[g] = x;
-      A.st.py[g] = y;
-      A.st.pz[g] = z;
-      store_vel(A.st, g, vx, vy, vz);
-      const uint32_t key =
-          axis_index(x, A.len[0], A.nx) + A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
-      A.key[g] = key;
-      mover = key != c;
+      double x = A.st.px[g], y = A.st.py[g], z = A.st.pz[g];
+      if (!move_particle(x, y, z, vx, vy, vz, A.dt, A.len, A.periodic, A.open)) {
+        A.st.px[g] = x;
+        A.st.py[g] = y;
+        A.st.pz[g] = z;
+        store_vel(A.st, g, vx, vy, vz);
+        const uint32_t key = axis_index(x, A.len[0], A.nx) +
+                             A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
+        A.key[g] = key;
+        mover = key != c;
+        stayer = !mover;
+      }
     }
-    const uint64_t bm = __ballot(i < n && mover), bs = __ballot(i < n && !mover);
+    const uint64_t bm = __ballot(mover), bs = __ballot(stayer);
     if (lane == 0) {
       s_wave[0][wv] = (uint32_t)__popcll(bs);
       s_wave[1][wv] = (uint32_t)__popcll(bm);
@@ -2486,18 +2522,122 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
     }
     // stayer ranks count up from the first slot, mover ranks down from the
     // last: together they never pass n <= cap entries
-    if (i < n) {
-      if (mover)
-        A.list[base + top - (pre_m + (uint32_t)__popcll(bm & below_lane))] = i;
-      else
-        A.list[base + pre_s + (uint32_t)__popcll(bs & below_lane)] = i;
-    }
+    if (mover) A.list[base + top - (pre_m + (uint32_t)__popcll(bm & below_lane))] = i;
+    if (stayer) A.list[base + pre_s + (uint32_t)__popcll(bs & below_lane)] = i;
     __syncthreads();
   }
   if (tid == 0) {
     A.n_stay[c] = run_s;
     A.n_move[c] = run_m;
+    const uint32_t gone = n - run_s - run_m;
+    if (gone && A.flux) atomicAdd(&A.flux[1], (unsigned long long)gone);
   }
+}
+
+// geometry of face cell t / n_species: face f, its axis k and side, the two
+// tangential axes a < b, the face cell's indices and the cell behind it
+struct FaceCell {
+  uint32_t f, k, side, a, b, ia, ib, cell;
+  double da, db;
+};
+__device__ __forceinline__ FaceCell face_cell(const InflowArgs &A, uint32_t gfc) {
+  FaceCell F;
+  F.f = 0;
+  while (gfc >= A.face_base[F.f + 1]) ++F.f;
+  F.k = F.f >> 1;
+  F.side = F.f & 1u;
+  F.a = F.k == 0 ? 1u : 0u;
+  F.b = F.k == 2 ? 1u : 2u;
+  const uint32_t n3[3] = {A.nx, A.ny, A.nz};
+  const uint32_t na = n3[F.a], nb = n3[F.b];
+  const uint32_t j = gfc - A.face_base[F.f];
+  F.ia = j % na;
+  F.ib = j / na;
+  uint32_t idx[3];
+  idx[F.k] = F.side ? n3[F.k] - 1u : 0u;
+  idx[F.a] = F.ia;
+  idx[F.b] = F.ib;
+  F.cell = idx[0] + A.nx * (idx[1] + A.ny * idx[2]);
+  F.da = A.len[F.a] / (double)na;
+  F.db = A.len[F.b] / (double)nb;
+  return F;
+}
+
+__global__ __launch_bounds__(256) void k_inflow_count(InflowArgs A) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t ns = A.n_species;
+  if (t >= (uint64_t)A.face_base[6] * ns) return;
+  const uint32_t gfc = (uint32_t)(t / ns), s = (uint32_t)(t % ns);
+  const FaceCell F = face_cell(A, gfc);
+  uint32_t cnt = 0;
+  if ((A.open >> F.f) & 1u) {
+    const double area = F.da * F.db;
+    const double x = ((A.flux_s[s] * area) * A.dt) / A.weight[F.cell] + A.rem[t];
+    const double fl = floor(x);
+    if (fl < 16777216.0) {
+      cnt = (uint32_t)fl;
+      A.rem[t] = x - fl;
+    } else {
+      atomicOr(A.err, kErrCapacity);
+    }
+  }
+  A.count[t] = cnt;
+}
+
+// admission i of species s at a face cell: normal speed from the
+// flux-weighted Maxwellian, sigma sqrt(-2 ln(1 - u)); tangential speeds, a
+// polar normal pair times sigma; the flight fraction tau; the place on the
+// face cell, uniform per tangential axis; levels and rotation as the thermal
+// initial state draws them; then a move over tau dt
+__global__ __launch_bounds__(256) void k_inflow_make(InflowArgs A) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t ns = A.n_species;
+  if (t >= (uint64_t)A.face_base[6] * ns) return;
+  const uint32_t cnt = A.count[t];
+  if (cnt == 0) return;
+  const uint32_t gfc = (uint32_t)(t / ns), s = (uint32_t)(t % ns);
+  const FaceCell F = face_cell(A, gfc);
+  const SpeciesTab &S = A.tab->sp[s];
+  const uint32_t mm = A.tab->max_modes;
+  const double sigma = sqrt((kBoltz * A.t_trans) / S.mass);
+  const uint64_t j0 = A.ibase[t], m_real = A.mbase[A.n_cells];
+  uint32_t gone = 0;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const uint64_t j = j0 + i;
+    if (j >= A.cap_ins) {
+      atomicOr(A.err, kErrCapacity);
+      break;
+    }
+    Rng rng;
+    rng.open(A.seed, (s << 24) | i, A.n_cells + gfc, A.step);
+    const double vn = sigma * sqrt(-2.0 * dlog(1.0 - rng.uniform()));
+    double n1, n2;
+    polar_normals(rng, n1, n2);
+    const double tau = rng.uniform();
+    const double ua = rng.uniform();
+    const double ub = rng.uniform();
+    double p[3], v[3];
+    p[F.k] = F.side ? A.len[F.k] : 0.0;
+    v[F.k] = F.side ? -vn : vn;
+    p[F.a] = ((double)F.ia + ua) * F.da;
+    p[F.b] = ((double)F.ib + ub) * F.db;
+    v[F.a] = sigma * n1;
+    v[F.b] = sigma * n2;
+    A.ins.sp[j] = (uint8_t)s;
+    sample_internal(S, A.lev, rng, A.t_vib, A.t_trans, A.ins, j, mm);
+    const bool left = move_particle(p[0], p[1], p[2], v[0], v[1], v[2], tau * A.dt, A.len, A.periodic, A.open);
+    store_vel(A.ins, j, v[0], v[1], v[2]);
+    A.ins.px[j] = p[0];
+    A.ins.py[j] = p[1];
+    A.ins.pz[j] = p[2];
+    A.mkey[m_real + j] = left ? A.n_cells
+                              : axis_index(p[0], A.len[0], A.nx) +
+                                    A.nx * (axis_index(p[1], A.len[1], A.ny) + A.ny * axis_index(p[2], A.len[2], A.nz));
+    A.mslot[m_real + j] = (uint32_t)(A.tot + j);
+    gone += left ? 1u : 0u;
+  }
+  atomicAdd(&A.flux[0], (unsigned long long)cnt);
+  if (gone) atomicAdd(&A.flux[1], (unsigned long long)gone);
 }
 
 // movers of cell c into the list, in slot order
@@ -2550,7 +2690,9 @@ __device__ __forceinline__ void copy_particle(const State &s, const State &d, ui
 
 // one workgroup per new cell k fills its slots in order: the run of movers
 // into k (in slot order) splits at the first mover from a slot above off[k]
-// (found by bisection), k's stayers go between the two parts. A count beyond
+// (found by bisection), k's stayers go between the two parts; particles
+// admitted through open faces (virtual old slots from tot on) come last in
+// the run, in the order they were made. A count beyond
 // the cell's capacity flags an error and the tail is dropped. Workgroups go
 // to the eight XCDs in turn, so the grid (a multiple of 8) gives each XCD one
 // contiguous range of cells: movers come from neighbouring cells, whose
@@ -2593,7 +2735,10 @@ __global__ __launch_bounds__(256) void k_rebin_place(RebinArgs A) {
       from = base + A.list[base + (p - below)];
     else
       from = A.mslot[A.sidx[lo + p - ns]];
-    copy_particle(A.src, A.dst, from, base + p, A.mm);
+    if (from < A.tot)
+      copy_particle(A.src, A.dst, from, base + p, A.mm);
+    else
+      copy_particle(A.ins, A.dst, from - A.tot, base + p, A.mm);
   }
 }
 
@@ -2744,6 +2889,24 @@ hipError_t launch_list_movers(const RebinArgs &a, hipStream_t s) {
   if (!a.off || !a.cap || !a.key || !a.list || !a.n_move || !a.mbase || !a.mkey || !a.mslot)
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_list_movers, dim3(a.n_cells), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_inflow_count(const InflowArgs &a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.face_base[6] * a.n_species;
+  if (n == 0) return hipSuccess;
+  if (!a.tab || !a.weight || !a.rem || !a.count || !a.err) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_inflow_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_inflow_make(const InflowArgs &a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.face_base[6] * a.n_species;
+  if (n == 0) return hipSuccess;
+  if (!a.tab || !a.lev || !a.count || !a.ibase || !a.mbase || !a.mkey || !a.mslot || !a.flux || !a.err ||
+      !a.ins.sp || !a.ins.lvl || !a.ins.px || !a.ins.py || !a.ins.pz || (!a.ins.vx && !a.ins.fx))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_inflow_make, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ hipError_t launch_init(const Tables *tab, const double *lev, const State &st, co
                        const uint32_t grid[3], const double len[3], hipStream_t s);
 hipError_t launch_move(const MoveArgs &a, hipStream_t s);
 hipError_t launch_list_movers(const RebinArgs &a, hipStream_t s);
+hipError_t launch_inflow_count(const InflowArgs &a, hipStream_t s);
+hipError_t launch_inflow_make(const InflowArgs &a, hipStream_t s);
 hipError_t launch_rebin_place(const RebinArgs &a, hipStream_t s);
 hipError_t launch_cell_init(const Tables *tab, const State &st, const CellArrays &cells, uint32_t n_cells,
                             hipStream_t s);
@@ -136,8 +138,23 @@ struct hcao_ctx {
   double len[3] = {0.0, 0.0, 0.0};
   DevBuf<double> px, py, pz, bpx, bpy, bpz;
   DevBuf<uint32_t> mv_key, mv_list, mv_mkey, mv_mslot, mv_sidx, mv_sidx_tmp, mv_hist;
-  DevBuf<uint32_t> mv_nstay, mv_nmove;
+  DevBuf<uint32_t> mv_nstay, mv_nmove, mv_ktmp;
   DevBuf<uint64_t> mv_offs, mv_packed, mv_stmp, mv_mbase;
+  uint64_t list_cap = 0;  // entries of the mover list arrays (movers and admissions)
+  // open faces: the reservoir's one-sided flux per species, per (face cell,
+  // species) inflow remainders and counts, the admissions' staging state,
+  // and the counts of particles admitted and gone
+  uint32_t open_faces = 0, face_base[7] = {0, 0, 0, 0, 0, 0, 0};
+  double in_flux[kMaxSpecies] = {}, in_t = 0.0, in_tv = 0.0;
+  DevBuf<double> in_rem;
+  DevBuf<uint32_t> in_count;
+  DevBuf<uint64_t> in_base;
+  DevBuf<unsigned long long> flux;
+  uint64_t ins_cap = 0;
+  DevBuf<double> ivx, ivy, ivz, irot, ipx, ipy, ipz;
+  DevBuf<float> ifx, ify, ifz;
+  DevBuf<uint8_t> isp;
+  DevBuf<uint16_t> ilvl;
   DevBuf<uint64_t> off;
   DevBuf<uint32_t> cnt, cap;
   DevBuf<double> d_volume, d_weight, sgmax, rem, defect;
@@ -234,6 +251,22 @@ double host_mode_energy(const SpeciesHost &s, uint32_t m, uint32_t i) {
   return s.levels[m - nb][i];
 }
 
+void release_ins(hcao_ctx *c) {
+  c->ivx.release();
+  c->ivy.release();
+  c->ivz.release();
+  c->ifx.release();
+  c->ify.release();
+  c->ifz.release();
+  c->isp.release();
+  c->ilvl.release();
+  c->irot.release();
+  c->ipx.release();
+  c->ipy.release();
+  c->ipz.release();
+  c->ins_cap = 0;
+}
+
 void free_state(hcao_ctx *c) {
   c->vx.release();
   c->vy.release();
@@ -272,6 +305,9 @@ void free_state(hcao_ctx *c) {
   c->mv_offs.release();
   c->mv_packed.release();
   c->mv_stmp.release();
+  c->mv_ktmp.release();
+  c->list_cap = 0;
+  release_ins(c);
   c->off.release();
   c->cnt.release();
   c->cap.release();
@@ -293,6 +329,12 @@ void free_state(hcao_ctx *c) {
 uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
   if (c->cfg.capacity_per_cell) return c->cfg.capacity_per_cell;
   return n + n / 4 + 32;
+}
+
+// staging state of the admissions through open faces (stride ins_cap)
+State ins_state(hcao_ctx *c) {
+  return State{c->ivx.p, c->ivy.p, c->ivz.p, c->ifx.p, c->ify.p, c->ifz.p, c->isp.p, c->ilvl.p, c->irot.p,
+               c->ipx.p, c->ipy.p, c->ipz.p, c->ins_cap};
 }
 
 State state_of(hcao_ctx *c) {
@@ -434,6 +476,54 @@ hcao_status build_groups(hcao_ctx *c) {
 
 // Allocates the state for per-cell counts; sets capacities, offsets and
 // the split between cells served from LDS tiles and from HBM.
+// the mover list and its sort buffers for up to n entries (movers plus
+// admissions), and the scan scratch for every scan of the re-bin
+hipError_t grow_list(hcao_ctx *c, uint64_t n) {
+  hipError_t e;
+  if (n > c->list_cap) {
+    if ((e = c->mv_mkey.alloc(n)) != hipSuccess) return e;
+    if ((e = c->mv_mslot.alloc(n)) != hipSuccess) return e;
+    if ((e = c->mv_sidx.alloc(n)) != hipSuccess) return e;
+    if ((e = c->mv_sidx_tmp.alloc(n)) != hipSuccess) return e;
+    if ((e = c->mv_ktmp.alloc(n)) != hipSuccess) return e;
+    if ((e = c->mv_hist.alloc(256 * sort_tiles(n))) != hipSuccess) return e;
+    if ((e = c->mv_offs.alloc(256 * sort_tiles(n))) != hipSuccess) return e;
+    c->list_cap = n;
+  }
+  const uint64_t faces = (uint64_t)c->face_base[6] * c->species.size();
+  const size_t need = std::max({scan_tmp_entries(256 * sort_tiles(c->list_cap)),
+                                scan_tmp_entries((uint64_t)c->cfg.n_cells + 1), scan_tmp_entries(faces + 1)});
+  if (c->mv_stmp.n < need && (e = c->mv_stmp.alloc(need)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// a new particle state starts the inflow remainders and flux counts afresh
+hipError_t reset_inflow(hcao_ctx *c) {
+  hipError_t e;
+  if (!c->open_faces) return hipSuccess;
+  if ((e = hipMemsetAsync(c->in_rem.p, 0, c->in_rem.n * sizeof(double), c->stream)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(c->in_count.p, 0, c->in_count.n * sizeof(uint32_t), c->stream)) != hipSuccess) return e;
+  return hipMemsetAsync(c->flux.p, 0, 2 * sizeof(unsigned long long), c->stream);
+}
+
+// staging for n admissions (state arrays of the context's precision)
+hipError_t grow_ins(hcao_ctx *c, uint64_t n) {
+  if (n <= c->ins_cap) return hipSuccess;
+  const uint64_t cap = n + n / 4 + 1024;
+  const uint32_t mm = c->max_modes ? c->max_modes : 1;
+  release_ins(c);
+  hipError_t e;
+  if ((e = alloc_vel(c, c->ivx, c->ivy, c->ivz, c->ifx, c->ify, c->ifz, cap)) != hipSuccess) return e;
+  if ((e = c->isp.alloc(cap)) != hipSuccess) return e;
+  if ((e = c->ilvl.alloc(cap * mm)) != hipSuccess) return e;
+  if (c->tab.has_rot && (e = c->irot.alloc(cap)) != hipSuccess) return e;
+  if ((e = c->ipx.alloc(cap)) != hipSuccess) return e;
+  if ((e = c->ipy.alloc(cap)) != hipSuccess) return e;
+  if ((e = c->ipz.alloc(cap)) != hipSuccess) return e;
+  c->ins_cap = cap;
+  return hipSuccess;
+}
+
 hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
                         const std::vector<uint32_t> *caps = nullptr) {
   free_state(c);
@@ -470,12 +560,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
     HIP_TRY(c, c->bpz.alloc(tot));
     HIP_TRY(c, c->mv_key.alloc(tot));
     HIP_TRY(c, c->mv_list.alloc(tot));
-    HIP_TRY(c, c->mv_mkey.alloc(tot));
-    HIP_TRY(c, c->mv_mslot.alloc(tot));
-    HIP_TRY(c, c->mv_sidx.alloc(tot));
-    HIP_TRY(c, c->mv_sidx_tmp.alloc(tot));
-    HIP_TRY(c, c->mv_hist.alloc(256 * sort_tiles(tot)));
-    HIP_TRY(c, c->mv_offs.alloc(256 * sort_tiles(tot)));
+    HIP_TRY(c, grow_list(c, tot));
     HIP_TRY(c, c->mv_packed.alloc(nc + 1));
     HIP_TRY(c, c->mv_nstay.alloc(nc));
     HIP_TRY(c, c->mv_nmove.alloc(nc + 1));
@@ -483,7 +568,8 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
     // the entry past the last cell stays zero, so the scan's last output is
     // the number of movers
     HIP_TRY(c, hipMemsetAsync(c->mv_nmove.p, 0, (nc + 1) * sizeof(uint32_t), c->stream));
-    HIP_TRY(c, c->mv_stmp.alloc(std::max(scan_tmp_entries(256 * sort_tiles(tot)), scan_tmp_entries(nc + 1))));
+    release_ins(c);
+    HIP_TRY(c, reset_inflow(c));
   }
   HIP_TRY(c, c->off.alloc(nc + 1));
   HIP_TRY(c, c->cnt.alloc(nc));
@@ -1347,8 +1433,11 @@ StepArgs step_args(hcao_ctx *c, double dt) {
 // spatial mode: move every particle over dt, then re-bin all of them by a
 // stable radix sort on the new cell into the staging buffers, which then
 // become the state (the old state becomes the products staging)
-hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
+hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
+  const uint32_t ns = (uint32_t)c->species.size();
+  const uint64_t tot = c->total_slots, faces = (uint64_t)c->face_base[6] * ns;
+  HIP_TRY(c, grow_list(c, c->list_cap));  // scan scratch for open faces set after the load
   MoveArgs m{};
   m.st = state_of(c);
   m.off = c->off.p;
@@ -1359,21 +1448,65 @@ hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
   m.ny = c->grid[1];
   m.nz = c->grid[2];
   m.periodic = c->periodic;
+  m.open = c->open_faces;
   for (int k = 0; k < 3; ++k) m.len[k] = c->len[k];
   m.dt = dt;
   m.key = c->mv_key.p;
   m.list = c->mv_list.p;
   m.n_stay = c->mv_nstay.p;
   m.n_move = c->mv_nmove.p;
+  m.flux = c->open_faces ? c->flux.p : nullptr;
   HIP_TRY(c, launch_move(m, s));
-  // the number of movers sizes the sort: one small read-back per step
   HIP_TRY(c, launch_scan_u32(c->mv_nmove.p, c->mv_mbase.p, (uint64_t)nc + 1, c->mv_stmp.p, s));
-  uint64_t movers = 0;
+  InflowArgs in{};
+  if (c->open_faces) {
+    in.tab = c->d_tab.p;
+    in.lev = c->d_lev.p;
+    in.weight = c->d_weight.p;
+    in.rem = c->in_rem.p;
+    in.count = c->in_count.p;
+    in.ibase = c->in_base.p;
+    in.mbase = c->mv_mbase.p;
+    in.flux = c->flux.p;
+    in.err = c->err.p;
+    for (uint32_t k = 0; k < ns; ++k) in.flux_s[k] = c->in_flux[k];
+    for (int k = 0; k < 3; ++k) in.len[k] = c->len[k];
+    in.dt = dt;
+    in.t_trans = c->in_t;
+    in.t_vib = c->in_tv;
+    in.seed = c->cfg.seed;
+    in.tot = tot;
+    for (int k = 0; k < 7; ++k) in.face_base[k] = c->face_base[k];
+    in.nx = c->grid[0];
+    in.ny = c->grid[1];
+    in.nz = c->grid[2];
+    in.n_cells = nc;
+    in.periodic = c->periodic;
+    in.open = c->open_faces;
+    in.n_species = ns;
+    in.step = step;
+    HIP_TRY(c, launch_inflow_count(in, s));
+    // the entry past the last (face cell, species) stays zero: the scan's
+    // last output is the number of admissions
+    HIP_TRY(c, launch_scan_u32(c->in_count.p, c->in_base.p, faces + 1, c->mv_stmp.p, s));
+  }
+  // the numbers of movers and admissions size the sort: one small read-back
+  // per step
+  uint64_t movers = 0, n_ins = 0;
   HIP_TRY(c, hipMemcpyAsync(&movers, c->mv_mbase.p + nc, sizeof movers, hipMemcpyDeviceToHost, s));
+  if (c->open_faces) HIP_TRY(c, hipMemcpyAsync(&n_ins, c->in_base.p + faces, sizeof n_ins, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  if (n_ins) {
+    if (tot + n_ins + n_ins / 4 + 1024 > 0xFFFFFFFFull)
+      return fail(c, HCAO_ECAPACITY, "admissions of one step exceed the 32-bit slot range");
+    HIP_TRY(c, grow_ins(c, n_ins));
+  }
+  HIP_TRY(c, grow_list(c, movers + n_ins));
   RebinArgs r{};
   r.src = state_of(c);
   r.dst = scratch_of(c);
+  r.ins = ins_state(c);
+  r.tot = tot;
   r.off = c->off.p;
   r.cap = c->cap.p;
   r.key = c->mv_key.p;
@@ -1386,19 +1519,26 @@ hcao_status move_rebin(hcao_ctx *c, double dt, hipStream_t s) {
   r.packed = c->mv_packed.p;
   r.cnt = c->cnt.p;
   r.err = c->err.p;
-  r.m = movers;
+  r.m = movers + n_ins;
   r.n_cells = nc;
   r.mm = mm;
   HIP_TRY(c, launch_list_movers(r, s));
+  if (n_ins) {
+    in.ins = ins_state(c);
+    in.cap_ins = c->ins_cap;
+    in.mkey = c->mv_mkey.p;
+    in.mslot = c->mv_mslot.p;
+    HIP_TRY(c, launch_inflow_make(in, s));
+  }
+  // keys 0..nc-1, and nc for an admission that leaves again (it sorts last)
+  const uint64_t top_key = c->open_faces ? nc : nc - 1;
   uint32_t key_bits = 0;
-  while (key_bits < 32 && ((uint64_t)1 << key_bits) < nc) ++key_bits;  // keys 0..nc-1
+  while (key_bits < 32 && ((uint64_t)1 << key_bits) <= top_key) ++key_bits;
   key_bits = ((key_bits + 7) / 8) * 8;
-  // the per-slot keys are dead after the list pass: they serve as the
-  // sort's second key buffer
   bool in_tmp = false;
-  HIP_TRY(c, launch_sort(c->mv_mkey.p, c->mv_sidx.p, c->mv_key.p, c->mv_sidx_tmp.p, c->mv_hist.p, c->mv_offs.p,
-                         c->mv_stmp.p, movers, key_bits, s, in_tmp));
-  r.skey = in_tmp ? c->mv_key.p : c->mv_mkey.p;
+  HIP_TRY(c, launch_sort(c->mv_mkey.p, c->mv_sidx.p, c->mv_ktmp.p, c->mv_sidx_tmp.p, c->mv_hist.p, c->mv_offs.p,
+                         c->mv_stmp.p, movers + n_ins, key_bits, s, in_tmp));
+  r.skey = in_tmp ? c->mv_ktmp.p : c->mv_mkey.p;
   r.sidx = in_tmp ? c->mv_sidx_tmp.p : c->mv_sidx.p;
   HIP_TRY(c, launch_rebin_place(r, s));
   std::swap(c->vx, c->bvx);
@@ -1421,7 +1561,7 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
   if (c->spatial) {
     // one collision launch per step, each after the move and re-bin
     for (uint32_t d = 0; d < n_steps; ++d) {
-      if (hcao_status st = move_rebin(c, dt, s)) return st;
+      if (hcao_status st = move_rebin(c, dt, base + d, s)) return st;
       StepArgs a = step_args(c, dt);
       a.step = base + d;
       a.n_steps = 1;
@@ -1967,6 +2107,61 @@ hcao_status hcao_set_domain(hcao_ctx *c, const hcao_domain *d) {
   return HCAO_OK;
 }
 
+hcao_status hcao_set_inflow(hcao_ctx *c, const hcao_inflow *in) {
+  if (!c || !in) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  if (!c->spatial || !c->finalized) return fail(c, HCAO_ESTATE, "open faces need the spatial mode, after finalize");
+  const uint32_t ns = (uint32_t)c->species.size();
+  if (in->open_faces > 63u) return fail(c, HCAO_EINVAL, "open_faces has bits beyond the six faces");
+  for (int k = 0; k < 3; ++k)
+    if (((c->periodic >> k) & 1u) && ((in->open_faces >> (2 * k)) & 3u))
+      return fail(c, HCAO_EINVAL, "an open face on a periodic axis");
+  if (in->open_faces) {
+    if (!in->number_density) return fail(c, HCAO_EINVAL, "number densities missing");
+    if (!(in->t_trans_K > 0.0) || !(in->t_vib_K > 0.0) || !std::isfinite(in->t_trans_K) || !std::isfinite(in->t_vib_K))
+      return fail(c, HCAO_EINVAL, "bad reservoir temperature");
+    for (uint32_t k = 0; k < ns; ++k)
+      if (!(in->number_density[k] >= 0.0) || !std::isfinite(in->number_density[k]))
+        return fail(c, HCAO_EINVAL, "bad reservoir number density");
+  }
+  c->face_base[0] = 0;
+  for (uint32_t f = 0; f < 6; ++f) {
+    const uint32_t k = f >> 1, a = k == 0 ? 1u : 0u, b = k == 2 ? 1u : 2u;
+    c->face_base[f + 1] = c->face_base[f] + c->grid[a] * c->grid[b];
+  }
+  c->open_faces = in->open_faces;
+  c->in_rem.release();
+  c->in_count.release();
+  c->in_base.release();
+  c->flux.release();
+  if (!c->open_faces) return HCAO_OK;
+  c->in_t = in->t_trans_K;
+  c->in_tv = in->t_vib_K;
+  for (uint32_t k = 0; k < ns; ++k)
+    c->in_flux[k] = in->number_density[k] * std::sqrt((kB * c->in_t) / ((2.0 * kPi) * c->species[k].d.mass_kg));
+  const uint64_t faces = (uint64_t)c->face_base[6] * ns;
+  HIP_TRY(c, c->in_rem.alloc(faces));
+  HIP_TRY(c, c->in_count.alloc(faces + 1));
+  HIP_TRY(c, c->in_base.alloc(faces + 1));
+  HIP_TRY(c, c->flux.alloc(2));
+  HIP_TRY(c, reset_inflow(c));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return HCAO_OK;
+}
+
+hcao_status hcao_read_flux_counts(hcao_ctx *c, uint64_t *out) {
+  if (!c || !out) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+  out[0] = out[1] = 0;
+  if (!c->open_faces) return HCAO_OK;
+  unsigned long long v[2];
+  HIP_TRY(c, hipMemcpyAsync(v, c->flux.p, sizeof v, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  out[0] = v[0];
+  out[1] = v[1];
+  return HCAO_OK;
+}
+
 hcao_status hcao_read_positions(hcao_ctx *c, double *pos) {
   if (!c || !pos) return HCAO_EINVAL;
   if (!c->loaded || !c->spatial) return fail(c, HCAO_ESTATE, "no positions (spatial mode only)");
@@ -2051,10 +2246,18 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   }
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(c, HCAO_EINVAL, std::string("cannot open ") + path);
+  std::vector<double> irem(c->open_faces ? c->in_rem.n : 0);
+  unsigned long long fl[2] = {0, 0};
+  if (c->open_faces) {
+    HIP_TRY(c, hipMemcpy(irem.data(), c->in_rem.p, irem.size() * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(fl, c->flux.p, sizeof fl, hipMemcpyDeviceToHost));
+  }
   // velocities are stored as fp64 in both forms (exact for fp32 values);
   // word 6: bit 0 mixed form, bit 1 rotational energies follow the levels,
-  // bit 2 positions (x, y, z arrays) follow
-  const uint64_t form = (c->mixed ? 1ull : 0ull) | (c->rot.p ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull);
+  // bit 2 positions (x, y, z arrays) follow, bit 3 the open faces' inflow
+  // remainders and the two flux counts follow
+  const uint64_t form = (c->mixed ? 1ull : 0ull) | (c->rot.p ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull) |
+                        (c->open_faces ? 8ull : 0ull);
   const uint64_t hdr[7] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step, form};
   bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
   ok = ok && std::fwrite(c->cap_host.data(), 4, nc, f) == nc;
@@ -2070,6 +2273,8 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   ok = ok && std::fwrite(lv.data(), 2, lv.size(), f) == lv.size();
   ok = ok && std::fwrite(rt.data(), 8, rt.size(), f) == rt.size();
   ok = ok && std::fwrite(pos.data(), 8, pos.size(), f) == pos.size();
+  ok = ok && std::fwrite(irem.data(), 8, irem.size(), f) == irem.size();
+  if (c->open_faces) ok = ok && std::fwrite(fl, 8, 2, f) == 2;
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return fail(c, HCAO_EINVAL, "write failed");
   return HCAO_OK;
@@ -2085,7 +2290,8 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
   if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x48434130534156ull || hdr[1] != HCAO_ABI_VERSION ||
       hdr[2] != nc || hdr[4] != mm ||
-      hdr[6] != ((c->mixed ? 1ull : 0ull) | (c->tab.has_rot ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull))) {
+      hdr[6] != ((c->mixed ? 1ull : 0ull) | (c->tab.has_rot ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull) |
+                 (c->open_faces ? 8ull : 0ull))) {
     std::fclose(f);
     return fail(c, HCAO_EINVAL, "checkpoint does not match this context");
   }
@@ -2110,6 +2316,10 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   ok = ok && std::fread(rt.data(), 8, rt.size(), f) == rt.size();
   std::vector<double> pos(c->spatial ? 3 * tot : 0);
   ok = ok && std::fread(pos.data(), 8, pos.size(), f) == pos.size();
+  std::vector<double> irem(c->open_faces ? c->in_rem.n : 0);
+  unsigned long long fl[2] = {0, 0};
+  ok = ok && std::fread(irem.data(), 8, irem.size(), f) == irem.size();
+  if (c->open_faces) ok = ok && std::fread(fl, 8, 2, f) == 2;
   std::fclose(f);
   if (!ok) return fail(c, HCAO_EINVAL, "truncated checkpoint");
   uint64_t t2 = 0;
@@ -2129,6 +2339,11 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
     HIP_TRY(c, hipMemcpy(c->py.p, pos.data() + tot, tot * 8, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->pz.p, pos.data() + 2 * tot, tot * 8, hipMemcpyHostToDevice));
   }
+  if (c->open_faces) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(c->in_rem.p, irem.data(), irem.size() * 8, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->flux.p, fl, sizeof fl, hipMemcpyHostToDevice));
+  }
   c->step = (uint32_t)hdr[5];
   c->loaded = true;
   return HCAO_OK;
@@ -2146,6 +2361,10 @@ void hcao_destroy(hcao_ctx *c) {
   c->d_rec.release();
   c->d_beta.release();
   c->err.release();
+  c->in_rem.release();
+  c->in_count.release();
+  c->in_base.release();
+  c->flux.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;

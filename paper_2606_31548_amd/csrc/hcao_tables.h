@@ -129,15 +129,45 @@ struct StepArgs {
 // and writes key[slot] = the new cell; its stayers (new cell = c) and its
 // movers are listed by cell-relative slot in list[], stayers in slot order
 // from the cell's first slot up, movers in slot order from its last slot
-// down; n_stay[c] and n_move[c] count them.
+// down; n_stay[c] and n_move[c] count them. A particle that crosses an open
+// face (bit 2 axis + side of open) is in neither list; flux[1] counts them.
 struct MoveArgs {
   State st;
   const uint64_t *off;
   const uint32_t *cnt, *cap;
-  uint32_t n_cells, nx, ny, nz, periodic;
+  uint32_t n_cells, nx, ny, nz, periodic, open;
   double len[3];
   double dt;
   uint32_t *key, *list, *n_stay, *n_move;
+  unsigned long long *flux;  // [2]: admitted, left (null without open faces)
+};
+
+// Spatial mode, admission through open faces; one thread per (face cell,
+// species), face cells numbered over all six faces (face f = 2 axis + side
+// starts at face_base[f]). The count pass sets count[t] = floor(x) with x =
+// ((flux_s A) dt) / F_N + rem[t] and keeps the fraction in rem[t]; the make
+// pass writes admission j of the step (j = ibase[t] + i) to slot j of the
+// staging state ins and to the mover list at movers + j with the virtual
+// old slot tot + j and its new cell (n_cells if it leaves again during its
+// partial flight).
+struct InflowArgs {
+  const Tables *tab;
+  const double *lev;
+  State ins;
+  const double *weight;        // per cell F_N
+  double *rem;                 // [n_face_cells * n_species]
+  uint32_t *count;             // [n_face_cells * n_species]
+  const uint64_t *ibase;       // exclusive scan of count
+  const uint64_t *mbase;       // movers' scan: mbase[n_cells] = movers
+  uint32_t *mkey, *mslot;
+  unsigned long long *flux;    // [2]: admitted, left
+  uint32_t *err;
+  double flux_s[HCAO_MAX_SPECIES];  // n_s sqrt(k T / (2 pi m_s)) [m^-2 s^-1]
+  double len[3];
+  double dt, t_trans, t_vib;
+  uint64_t seed, tot, cap_ins;
+  uint32_t face_base[7];
+  uint32_t nx, ny, nz, n_cells, periodic, open, n_species, step;
 };
 
 // Spatial mode, re-bin after the move pass. The new order of cell k is the
@@ -148,6 +178,8 @@ struct MoveArgs {
 // The place pass fills each cell's new slots in order.
 struct RebinArgs {
   State src, dst;
+  State ins;                                     // admitted particles (virtual old slots tot + j)
+  uint64_t tot;
   const uint64_t *off;
   const uint32_t *cap;
   const uint32_t *key, *list, *n_stay, *n_move;  // from the move pass

@@ -62,6 +62,10 @@ class hcao_domain(ctypes.Structure):
     _fields_ = [("nx", _u32), ("ny", _u32), ("nz", _u32), ("periodic", _u32), ("lx", _d), ("ly", _d), ("lz", _d)]
 
 
+class hcao_inflow(ctypes.Structure):
+    _fields_ = [("open_faces", _u32), ("pad", _u32), ("number_density", _vp), ("t_trans_K", _d), ("t_vib_K", _d)]
+
+
 class hcao_launch_shape(ctypes.Structure):
     _fields_ = [("block", _u32), ("group_slots", _u32), ("steps_per_launch", _u32)]
 
@@ -101,6 +105,8 @@ def load_library():
     L.hcao_finalize.argtypes = [_vp]
     L.hcao_load_particles.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp]
     L.hcao_set_domain.argtypes = [_vp, ctypes.POINTER(hcao_domain)]
+    L.hcao_set_inflow.argtypes = [_vp, ctypes.POINTER(hcao_inflow)]
+    L.hcao_read_flux_counts.argtypes = [_vp, _vp]
     L.hcao_read_positions.argtypes = [_vp, _vp]
     L.hcao_read_rotational_energy.argtypes = [_vp, _vp]
     L.hcao_init_thermal.argtypes = [_vp, _vp, _vp, _vp]
@@ -134,7 +140,8 @@ def load_library():
                  "hcao_get_pair", "hcao_get_recombination_table", "hcao_set_timing", "hcao_kernel_time", "hcao_save", "hcao_restore",
                  "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
                  "hcao_read_cell_particles", "hcao_get_exact_beta", "hcao_recombination_exact",
-                 "hcao_read_rotational_energy", "hcao_set_domain", "hcao_read_positions"):
+                 "hcao_read_rotational_energy", "hcao_set_domain", "hcao_read_positions", "hcao_set_inflow",
+                 "hcao_read_flux_counts"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -247,6 +254,19 @@ class Simulation:
         """Spatial mode (before finalize): box of nx x ny x nz cells."""
         d = hcao_domain(nx, ny, nz, periodic, lx, ly, lz)
         self._chk("hcao_set_domain", self._L.hcao_set_domain(self._h, ctypes.byref(d)))
+
+    def set_inflow(self, open_faces, number_density, t_trans, t_vib):
+        """Spatial mode (after finalize): faces 2 axis + side open to a resting
+        reservoir of number densities [n_species] m^-3 at t_trans, t_vib."""
+        n = np.ascontiguousarray(number_density, np.float64)
+        d = hcao_inflow(int(open_faces), 0, n.ctypes.data, float(t_trans), float(t_vib))
+        self._chk("hcao_set_inflow", self._L.hcao_set_inflow(self._h, ctypes.byref(d)))
+
+    def flux_counts(self):
+        """(admitted, left) through open faces since the last load, init or restore."""
+        out = np.zeros(2, np.uint64)
+        self._chk("hcao_read_flux_counts", self._L.hcao_read_flux_counts(self._h, _p(out)))
+        return int(out[0]), int(out[1])
 
     def load_particles(self, cell, species, vel, levels, rot=None, pos=None):
         cell = np.ascontiguousarray(cell, np.uint32)
@@ -435,4 +455,6 @@ def from_workload(wl, seed: Optional[int] = None, capacity_per_cell: Optional[in
     for rx in wl.reactions:
         s.add_reaction(rx)
     s.finalize()
+    if getattr(wl, "inflow", None) is not None:
+        s.set_inflow(*wl.inflow)
     return s

@@ -1,0 +1,128 @@
+"""Open faces of the spatial mode on the GPU (outflow and surface-flux
+admission), against the fp64 oracle bit for bit: positions, velocities,
+cell order, species, levels, rotational energies, counters and the flux
+counts."""
+import numpy as np
+import pytest
+
+from paper_2606_31548_amd import workloads as W
+from test_gpu_parity import _compare_state
+from test_gpu_spatial import _compare_pos
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hc():
+    from paper_2606_31548_amd import hcao
+    hcao.load_library()
+    return hcao
+
+
+def _run_pair(orc, hc, wl, chunks, what):
+    o = orc.from_workload(wl)
+    g = hc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    _compare_state(o, g, f"{what}: init")
+    done = 0
+    for n in chunks:
+        o.step(wl.dt, n)
+        g.step(wl.dt, n)
+        g.sync()
+        done += n
+        _compare_state(o, g, f"{what}: {done} steps")
+        _compare_pos(o, g, f"{what}: {done} steps")
+        assert o.flux_counts() == g.flux_counts(), f"{what}: flux counts after {done} steps"
+    return o, g
+
+
+@pytest.mark.parametrize("open_faces,periodic", [(0b000011, 0b000), (0b000111, 0b100)])
+def test_open_faces_parity(orc, hc, open_faces, periodic):
+    """Methane/argon at 20,000 K in a 5 x 4 x 3 box: x faces open (and, in
+    the second case, the face y = 0 open with y = L specular and z
+    periodic); particles leave and enter every step; dissociation runs."""
+    wl = W.spatial_box(nx=5, ny=4, nz=3, per_cell=150, periodic=periodic, open_faces=open_faces,
+                       t_trans=20000.0)
+    o, g = _run_pair(orc, hc, wl, (1, 9, 20), f"open {open_faces:06b}")
+    n_in, n_out = g.flux_counts()
+    assert n_in > 500 and n_out > 500
+    assert o.counters().sum(0)[orc.CTR_REACTION0] > 0
+
+
+def test_open_faces_chemistry_with_rotors_parity(orc, hc):
+    """The CH4/CH3/H/H2 chemistry (recombination included) with rotors,
+    all six faces open: admitted molecules draw levels and rotational
+    energies as the initial state does."""
+    wl = W.spatial_box(nx=4, ny=3, nz=3, per_cell=150, chemistry=True, t_trans=12000.0, dt=5e-9,
+                       open_faces=0b111111)
+    for s in wl.species:
+        if s.name in ("CH4", "CH3", "H2"):
+            s.zeta_rot = 2 if s.name == "H2" else 3
+    for r in wl.reactions:
+        if r.kind != W.RX_RECOMBINATION:
+            r.gamma_rot = 0.5
+    o, g = _run_pair(orc, hc, wl, (2, 10), "chemistry, rotors, all faces open")
+    rot_o = np.concatenate([o.read_rot(c) for c in range(wl.n_cells)])
+    assert np.array_equal(rot_o.view(np.uint64), g.read_rotational_energy().view(np.uint64))
+
+
+def test_empty_box_fills_through_its_faces(orc, hc):
+    """A box that starts empty, open on all faces: every particle in it was
+    admitted on the device; the state matches the oracle's."""
+    wl = W.spatial_box(nx=4, ny=4, nz=2, per_cell=100, open_faces=0b111111, t_trans=20000.0, empty=True)
+    o, g = _run_pair(orc, hc, wl, (1, 14), "empty box")
+    assert g.counts()[1] > 1000
+
+
+def test_open_faces_checkpoint_and_launch_shapes(hc, tmp_path, monkeypatch):
+    """A checkpoint carries the inflow remainders and flux counts: a restored
+    context continues bit for bit. The mixed form with open faces gives the
+    same bits at every launch shape."""
+    wl = W.spatial_box(nx=4, ny=3, nz=3, per_cell=120, open_faces=0b000011, t_trans=20000.0)
+    a = hc.from_workload(wl)
+    a.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    a.step(wl.dt, 20)
+    b = hc.from_workload(wl)
+    b.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    b.step(wl.dt, 10)
+    b.save(tmp_path / "open.bin")
+    c = hc.from_workload(wl)
+    c.restore(tmp_path / "open.bin")
+    c.step(wl.dt, 10)
+    for x, y in zip(a.read_particles(), c.read_particles()):
+        assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
+    assert np.array_equal(a.read_positions().view(np.uint64), c.read_positions().view(np.uint64))
+    assert a.flux_counts() == c.flux_counts()
+    closed = W.spatial_box(nx=4, ny=3, nz=3, per_cell=120, t_trans=20000.0)
+    d = hc.from_workload(closed)
+    with pytest.raises(hc.HcaoError):
+        d.restore(tmp_path / "open.bin")
+    outs = []
+    for block, slots in (("64", "1"), ("256", "4096")):
+        monkeypatch.setenv("HCAO_BLOCK", block)
+        monkeypatch.setenv("HCAO_GROUP_SLOTS", slots)
+        g = hc.from_workload(wl, precision=hc.MIXED)
+        g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+        g.step(wl.dt, 12)
+        g.sync()
+        outs.append((g.read_particles(), g.read_positions(), g.flux_counts()))
+        g.close()
+    for x, y in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
+    assert np.array_equal(outs[0][1].view(np.uint64), outs[1][1].view(np.uint64))
+    assert outs[0][2] == outs[1][2]
+
+
+def test_open_face_refusals(hc):
+    wl = W.spatial_box(nx=3, ny=3, nz=3, per_cell=50, periodic=0b001)
+    g = hc.from_workload(wl)
+    n = np.full(len(wl.species), 1e21)
+    with pytest.raises(hc.HcaoError):
+        g.set_inflow(0b000001, n, 1000.0, 1000.0)  # x is periodic
+    with pytest.raises(hc.HcaoError):
+        g.set_inflow(0b000100, -n, 1000.0, 1000.0)
+    with pytest.raises(hc.HcaoError):
+        g.set_inflow(0b000100, n, 0.0, 1000.0)
+    g.set_inflow(0b000100, n, 1000.0, 1000.0)
+    assert g.flux_counts() == (0, 0)

@@ -2584,60 +2584,65 @@ __global__ __launch_bounds__(256) void k_inflow_count(InflowArgs A) {
   A.count[t] = cnt;
 }
 
-// admission i of species s at a face cell: normal speed from the
-// flux-weighted Maxwellian, sigma sqrt(-2 ln(1 - u)); tangential speeds, a
-// polar normal pair times sigma; the flight fraction tau; the place on the
-// face cell, uniform per tangential axis; levels and rotation as the thermal
-// initial state draws them; then a move over tau dt
+// admission j of the step: its (face cell, species) t is the last with
+// ibase[t] <= j (entries without admissions share the next one's base), i =
+// j - ibase[t]. Normal speed from the flux-weighted Maxwellian, sigma
+// sqrt(-2 ln(1 - u)); tangential speeds, a polar normal pair times sigma;
+// the flight fraction tau; the place on the face cell, uniform per
+// tangential axis; levels and rotation as the thermal initial state draws
+// them; then a move over tau dt
 __global__ __launch_bounds__(256) void k_inflow_make(InflowArgs A) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= A.n_ins) return;
+  if (j >= A.cap_ins) {
+    atomicOr(A.err, kErrCapacity);
+    return;
+  }
   const uint32_t ns = A.n_species;
-  if (t >= (uint64_t)A.face_base[6] * ns) return;
-  const uint32_t cnt = A.count[t];
-  if (cnt == 0) return;
+  uint64_t lo = 0, hi = (uint64_t)A.face_base[6] * ns - 1;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi + 1) >> 1;
+    if (A.ibase[mid] <= j)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const uint64_t t = lo;
+  const uint32_t i = (uint32_t)(j - A.ibase[t]);
   const uint32_t gfc = (uint32_t)(t / ns), s = (uint32_t)(t % ns);
   const FaceCell F = face_cell(A, gfc);
   const SpeciesTab &S = A.tab->sp[s];
   const uint32_t mm = A.tab->max_modes;
   const double sigma = sqrt((kBoltz * A.t_trans) / S.mass);
-  const uint64_t j0 = A.ibase[t], m_real = A.mbase[A.n_cells];
-  uint32_t gone = 0;
-  for (uint32_t i = 0; i < cnt; ++i) {
-    const uint64_t j = j0 + i;
-    if (j >= A.cap_ins) {
-      atomicOr(A.err, kErrCapacity);
-      break;
-    }
-    Rng rng;
-    rng.open(A.seed, (s << 24) | i, A.n_cells + gfc, A.step);
-    const double vn = sigma * sqrt(-2.0 * dlog(1.0 - rng.uniform()));
-    double n1, n2;
-    polar_normals(rng, n1, n2);
-    const double tau = rng.uniform();
-    const double ua = rng.uniform();
-    const double ub = rng.uniform();
-    double p[3], v[3];
-    p[F.k] = F.side ? A.len[F.k] : 0.0;
-    v[F.k] = F.side ? -vn : vn;
-    p[F.a] = ((double)F.ia + ua) * F.da;
-    p[F.b] = ((double)F.ib + ub) * F.db;
-    v[F.a] = sigma * n1;
-    v[F.b] = sigma * n2;
-    A.ins.sp[j] = (uint8_t)s;
-    sample_internal(S, A.lev, rng, A.t_vib, A.t_trans, A.ins, j, mm);
-    const bool left = move_particle(p[0], p[1], p[2], v[0], v[1], v[2], tau * A.dt, A.len, A.periodic, A.open);
-    store_vel(A.ins, j, v[0], v[1], v[2]);
-    A.ins.px[j] = p[0];
-    A.ins.py[j] = p[1];
-    A.ins.pz[j] = p[2];
-    A.mkey[m_real + j] = left ? A.n_cells
-                              : axis_index(p[0], A.len[0], A.nx) +
-                                    A.nx * (axis_index(p[1], A.len[1], A.ny) + A.ny * axis_index(p[2], A.len[2], A.nz));
-    A.mslot[m_real + j] = (uint32_t)(A.tot + j);
-    gone += left ? 1u : 0u;
-  }
-  atomicAdd(&A.flux[0], (unsigned long long)cnt);
-  if (gone) atomicAdd(&A.flux[1], (unsigned long long)gone);
+  Rng rng;
+  rng.open(A.seed, (s << 24) | i, A.n_cells + gfc, A.step);
+  const double vn = sigma * sqrt(-2.0 * dlog(1.0 - rng.uniform()));
+  double n1, n2;
+  polar_normals(rng, n1, n2);
+  const double tau = rng.uniform();
+  const double ua = rng.uniform();
+  const double ub = rng.uniform();
+  double p[3], v[3];
+  p[F.k] = F.side ? A.len[F.k] : 0.0;
+  v[F.k] = F.side ? -vn : vn;
+  p[F.a] = ((double)F.ia + ua) * F.da;
+  p[F.b] = ((double)F.ib + ub) * F.db;
+  v[F.a] = sigma * n1;
+  v[F.b] = sigma * n2;
+  A.ins.sp[j] = (uint8_t)s;
+  sample_internal(S, A.lev, rng, A.t_vib, A.t_trans, A.ins, j, mm);
+  const bool left = move_particle(p[0], p[1], p[2], v[0], v[1], v[2], tau * A.dt, A.len, A.periodic, A.open);
+  store_vel(A.ins, j, v[0], v[1], v[2]);
+  A.ins.px[j] = p[0];
+  A.ins.py[j] = p[1];
+  A.ins.pz[j] = p[2];
+  const uint64_t m_real = A.mbase[A.n_cells];
+  A.mkey[m_real + j] = left ? A.n_cells
+                            : axis_index(p[0], A.len[0], A.nx) +
+                                  A.nx * (axis_index(p[1], A.len[1], A.ny) + A.ny * axis_index(p[2], A.len[2], A.nz));
+  A.mslot[m_real + j] = (uint32_t)(A.tot + j);
+  if (i == 0) atomicAdd(&A.flux[0], (unsigned long long)A.count[t]);
+  if (left) atomicAdd(&A.flux[1], 1ull);
 }
 
 // movers of cell c into the list, in slot order
@@ -2901,8 +2906,8 @@ hipError_t launch_inflow_count(const InflowArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_inflow_make(const InflowArgs &a, hipStream_t s) {
-  const uint64_t n = (uint64_t)a.face_base[6] * a.n_species;
-  if (n == 0) return hipSuccess;
+  const uint64_t n = a.n_ins;
+  if (n == 0 || a.face_base[6] == 0 || a.n_species == 0) return hipSuccess;
   if (!a.tab || !a.lev || !a.count || !a.ibase || !a.mbase || !a.mkey || !a.mslot || !a.flux || !a.err ||
       !a.ins.sp || !a.ins.lvl || !a.ins.px || !a.ins.py || !a.ins.pz || (!a.ins.vx && !a.ins.fx))
     return hipErrorInvalidValue;

@@ -1526,6 +1526,7 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   if (n_ins) {
     in.ins = ins_state(c);
     in.cap_ins = c->ins_cap;
+    in.n_ins = n_ins;
     in.mkey = c->mv_mkey.p;
     in.mslot = c->mv_mslot.p;
     HIP_TRY(c, launch_inflow_make(in, s));

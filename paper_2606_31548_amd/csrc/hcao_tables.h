@@ -146,8 +146,8 @@ struct MoveArgs {
 // species), face cells numbered over all six faces (face f = 2 axis + side
 // starts at face_base[f]). The count pass sets count[t] = floor(x) with x =
 // ((flux_s A) dt) / F_N + rem[t] and keeps the fraction in rem[t]; the make
-// pass writes admission j of the step (j = ibase[t] + i) to slot j of the
-// staging state ins and to the mover list at movers + j with the virtual
+// pass (one thread per admission) writes admission j of the step (j =
+// ibase[t] + i) to slot j of the staging state ins and to the mover list at movers + j with the virtual
 // old slot tot + j and its new cell (n_cells if it leaves again during its
 // partial flight).
 struct InflowArgs {
@@ -166,6 +166,7 @@ struct InflowArgs {
   double len[3];
   double dt, t_trans, t_vib;
   uint64_t seed, tot, cap_ins;
+  uint64_t n_ins;              // admissions of the step (make pass)
   uint32_t face_base[7];
   uint32_t nx, ny, nz, n_cells, periodic, open, n_species, step;
 };

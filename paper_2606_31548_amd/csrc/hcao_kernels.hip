@@ -2423,10 +2423,10 @@ __global__ __launch_bounds__(256) void k_rec_sum(RecSumArgs A) {
 // left their cell
 // ---------------------------------------------------------------------------
 // one coordinate over dt: periodic axes wrap into [0, L); a specular face
-// reflects (x < 0: -x, x > L: 2L - x, velocity reversed) until inside
-// [0, L]; crossing an open face sets left and ends the move
+// reflects (x < 0: -x, x > L: 2L - x, velocity reversed; flip set) until
+// inside [0, L]; crossing an open face sets left and ends the move
 __device__ __forceinline__ double move_axis(double x, double &v, double dt, double len, bool periodic, bool open_lo,
-                                           bool open_hi, bool &left) {
+                                           bool open_hi, bool &left, bool &flip) {
   double y = x + v * dt;
   if (periodic) {
     while (y < 0.0) y = y + len;
@@ -2440,6 +2440,7 @@ __device__ __forceinline__ double move_axis(double x, double &v, double dt, doub
         }
         y = -y;
         v = -v;
+        flip = true;
       } else if (y > len) {
         if (open_hi) {
           left = true;
@@ -2447,6 +2448,7 @@ __device__ __forceinline__ double move_axis(double x, double &v, double dt, doub
         }
         y = (len + len) - y;
         v = -v;
+        flip = true;
       } else {
         break;
       }
@@ -2456,15 +2458,17 @@ __device__ __forceinline__ double move_axis(double x, double &v, double dt, doub
 }
 
 // a particle over dt on x, then y, then z; true if it leaves through an open
-// face (its coordinates are then of no use)
+// face (its coordinates are then of no use); flip tells whether a specular
+// face reversed a velocity component
 __device__ __forceinline__ bool move_particle(double &x, double &y, double &z, double &vx, double &vy, double &vz,
-                                              double dt, const double len[3], uint32_t periodic, uint32_t open) {
+                                              double dt, const double len[3], uint32_t periodic, uint32_t open,
+                                              bool &flip) {
   bool left = false;
-  x = move_axis(x, vx, dt, len[0], (periodic & 1u) != 0, (open & 1u) != 0, (open & 2u) != 0, left);
+  x = move_axis(x, vx, dt, len[0], (periodic & 1u) != 0, (open & 1u) != 0, (open & 2u) != 0, left, flip);
   if (left) return true;
-  y = move_axis(y, vy, dt, len[1], (periodic & 2u) != 0, (open & 4u) != 0, (open & 8u) != 0, left);
+  y = move_axis(y, vy, dt, len[1], (periodic & 2u) != 0, (open & 4u) != 0, (open & 8u) != 0, left, flip);
   if (left) return true;
-  z = move_axis(z, vz, dt, len[2], (periodic & 4u) != 0, (open & 16u) != 0, (open & 32u) != 0, left);
+  z = move_axis(z, vz, dt, len[2], (periodic & 4u) != 0, (open & 16u) != 0, (open & 32u) != 0, left, flip);
   return left;
 }
 
@@ -2492,11 +2496,12 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
       const Vec3 v = load_vel(A.st, g);
       double vx = v.x, vy = v.y, vz = v.z;
       double x = A.st.px[g], y = A.st.py[g], z = A.st.pz[g];
-      if (!move_particle(x, y, z, vx, vy, vz, A.dt, A.len, A.periodic, A.open)) {
+      bool flip = false;
+      if (!move_particle(x, y, z, vx, vy, vz, A.dt, A.len, A.periodic, A.open, flip)) {
         A.st.px[g] = x;
         A.st.py[g] = y;
         A.st.pz[g] = z;
-        store_vel(A.st, g, vx, vy, vz);
+        if (flip) store_vel(A.st, g, vx, vy, vz);  // only a reflection changes the velocity
         const uint32_t key = axis_index(x, A.len[0], A.nx) +
                              A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
         A.key[g] = key;
@@ -2631,7 +2636,9 @@ __global__ __launch_bounds__(256) void k_inflow_make(InflowArgs A) {
   v[F.b] = sigma * n2;
   A.ins.sp[j] = (uint8_t)s;
   sample_internal(S, A.lev, rng, A.t_vib, A.t_trans, A.ins, j, mm);
-  const bool left = move_particle(p[0], p[1], p[2], v[0], v[1], v[2], tau * A.dt, A.len, A.periodic, A.open);
+  bool flip = false;
+  const bool left =
+      move_particle(p[0], p[1], p[2], v[0], v[1], v[2], tau * A.dt, A.len, A.periodic, A.open, flip);
   store_vel(A.ins, j, v[0], v[1], v[2]);
   A.ins.px[j] = p[0];
   A.ins.py[j] = p[1];

@@ -314,6 +314,28 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
     return r
 
 
+def copy_peak(torch, mib=1024, repeats=10):
+    """HBM bandwidth that a plain device-to-device copy reaches (bytes read
+    plus bytes written per second, HIP events around `repeats` copies of
+    `mib` MiB): the practical ceiling beside the datasheet's 8 TB/s."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(repeats):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * n * 8 * repeats / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measure_sequential(hcao, torch, wl, steps):
     """The same reservoirs run one at a time: one context and one launch per
     reservoir and step (what the batched launch replaces)."""
@@ -406,6 +428,9 @@ def main():
                          shape=None if args.library_shape else TUNED_SHAPE[args.workload])
         res[f]["roofline"]["traffic"] = (measured_traffic(args.workload, f, spl, res[f]["launch_shape"])
                                          if args.sampler == "auto" and not args.rotors else None)
+    cp = copy_peak(torch)
+    for f in res:
+        res[f]["roofline"]["frac_of_copy"] = res[f]["roofline"]["achieved"] / cp
     head = res[forms[0]]
     out = {
         "metric": "HCAO collisions/s on 1 MI355X; mixed FP32/FP64 vs FP64 at fixed energy error",
@@ -425,6 +450,8 @@ def main():
         "particle_steps_per_s": head["particle_steps_per_s"],
         "energy_drift": head["energy_drift"],
         "roofline": head["roofline"],
+        # a 1 GiB device-to-device copy, bytes read plus written per second
+        "copy_peak_GBs": cp,
         "forms": res,
     }
     if "mixed" in res and "fp64" in res:

@@ -78,7 +78,7 @@ typedef enum {
   HCAO_ELEVEL = -6,      /* quantum number above the top bound level, or a
                             nonzero level in an unused mode slot */
   HCAO_ENONFINITE = -7,  /* non-finite velocity */
-  HCAO_EUNSUPPORTED = -8 /* feature not available in this build */
+  HCAO_EUNSUPPORTED = -8 /* feature not available in this mode of the library */
 } hcao_status;
 
 /* Arithmetic of the step.

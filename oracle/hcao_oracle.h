@@ -7,8 +7,9 @@
  * may load it. The product path never calls it, and it shares no source
  * with the GPU library: both are written independently from the paper
  * (Lauterbach, Tuttas, Pfeiffer, "A harmonically-coupled-anharmonic-
- * oscillator approach for polyatomic chemistry modeling in DSMC") and from
- * the determinism specification of the readings listed in the design notes.
+ * oscillator approach for polyatomic chemistry modeling in DSMC") and from a
+ * shared determinism specification (counter-based streams, draw order,
+ * deterministic log/exp) that fixes every random draw and rounding.
  *
  * Plain C API (ctypes friendly). Energies in J, SI units throughout.
  * Every call returns 0 on success and a negative code on error.

@@ -1,0 +1,91 @@
+"""The spatial workloads at their full size (64 x 64 x 64 cells of 0.1 mm,
+256 particles per cell, 67.1 M particles), in the launch configuration
+bench.py times (128 lanes, 3,072 slots per workgroup, one collision launch
+per step). Cells exchange particles every step, so the oracle cannot run a
+sample of them on its own; these runs are held to properties that hold at
+any size (the same workloads at small sizes are bitwise the oracle's in
+test_gpu_spatial and test_gpu_inflow):
+  - every particle lies in the cell that holds it;
+  - the periodic box conserves energy (the fp64 audit closes in both forms),
+    momentum, and C and H atoms;
+  - with open faces, the particle count closes: initial + admitted - left +
+    births - deaths."""
+import numpy as np
+import pytest
+
+from paper_2606_31548_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 10
+EDGE = 1e-4
+
+
+@pytest.fixture(scope="module")
+def hc():
+    from paper_2606_31548_amd import hcao
+    hcao.load_library()
+    return hcao
+
+
+def _box(open_faces=0):
+    return W.spatial_box(nx=64, ny=64, nz=64, per_cell=256, periodic=0b110 if open_faces else 0b111,
+                         chemistry=True, t_trans=8000.0, dt=5e-9, open_faces=open_faces)
+
+
+def _run(hc, wl, precision):
+    g = hc.from_workload(wl, precision=precision)
+    g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    g.set_launch_shape(128, 3072, 50)
+    return g
+
+
+def _in_their_cells(g, wl):
+    per, tot = g.counts()
+    pos = g.read_positions()
+    cell = np.repeat(np.arange(wl.n_cells, dtype=np.int64), per.astype(np.int64))
+    assert len(cell) == tot == len(pos)
+    n = np.array(wl.domain[:3], np.int64)
+    ijk = np.minimum(np.floor(pos / EDGE).astype(np.int64), n - 1)
+    assert np.all(pos >= 0.0) and np.all(pos <= n * EDGE)
+    assert np.array_equal(ijk[:, 0] + n[0] * (ijk[:, 1] + n[1] * ijk[:, 2]), cell)
+
+
+def _atoms(m):
+    n = np.array(m.n_species[:5], np.int64)  # CH4, Ar, CH3, H, H2
+    return n[0] + n[2], 4 * n[0] + 3 * n[2] + n[3] + 2 * n[4]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fullsize_periodic_box_invariants(hc, precision):
+    wl = _box()
+    print(f"64^3 periodic box, {precision}", flush=True)
+    g = _run(hc, wl, hc.FP64 if precision == "fp64" else hc.MIXED)
+    m0 = g.moments()
+    e0 = g.total_energy(m0)
+    scale = m0.E_kin_J + sum(m0.E_vib_J[s] for s in range(g.n_species))
+    p_scale = np.sqrt(2.0 * m0.E_kin_J * sum(m0.n_species[s] * wl.species[s].mass_kg
+                                              for s in range(len(wl.species))))
+    g.step(wl.dt, STEPS)
+    g.sync()
+    m1 = g.moments()
+    assert abs(g.total_energy(m1) - e0) / scale < 1e-11
+    assert np.all(np.abs(np.array(m1.momentum) - np.array(m0.momentum)) < 1e-9 * p_scale)
+    assert _atoms(m0) == _atoms(m1)
+    assert g.reaction_counts().sum() > 0
+    if precision == "fp64":
+        _in_their_cells(g, wl)
+
+
+def test_fullsize_inflow_channel_counts_close(hc):
+    wl = _box(open_faces=0b000011)
+    print("64^3 channel, x faces open, fp64", flush=True)
+    g = _run(hc, wl, hc.FP64)
+    n0 = g.counts()[1]
+    g.step(wl.dt, STEPS)
+    g.sync()
+    n_in, n_out = g.flux_counts()
+    ctr = g.cell_state()[2].sum(0)
+    assert n_in > 10000 and n_out > 10000
+    assert g.counts()[1] == n0 + n_in - n_out + int(ctr[hc.CTR_BIRTHS]) - int(ctr[hc.CTR_DEATHS])
+    _in_their_cells(g, wl)

@@ -65,12 +65,41 @@ def _sampled_parity(orc, hc, wl, seed):
         assert np.array_equal(ctr, gctr[c]), f"cell {c}: counters differ"
         collided += int(ctr[orc.CTR_COLLISIONS])
     assert collided > 0
-    return g
+    return g, o, cells
 
 
 def test_fullsize_precision_chemistry_sampled_cells(orc, hc):
     """262,144 cells x 256 (67.1 M particles), fp64 form."""
     _sampled_parity(orc, hc, W.methane_chemistry(n_cells=262144, per_cell=256, recombination=True), seed=1)
+
+
+def test_fullsize_exact_sampler_sampled_cells(orc, hc):
+    """262,144 cells x 256 with every molecule on the exact sampler of the
+    joint relaxation target (bench.py --sampler exact), fp64 form."""
+    wl = W.methane_chemistry(n_cells=262144, per_cell=256, recombination=True)
+    for sp in wl.species:
+        if sp.n_modes:
+            sp.sampler = W.SAMPLER_EXACT
+    _sampled_parity(orc, hc, wl, seed=4)
+
+
+def test_fullsize_rotors_sampled_cells(orc, hc):
+    """262,144 cells x 256 with every molecule a rotor and rotation coupled
+    into dissociation and exchange with 0.5 (bench.py --rotors), fp64 form;
+    rotational energies too."""
+    wl = W.methane_chemistry(n_cells=262144, per_cell=256, recombination=True)
+    for sp in wl.species:
+        if sp.n_modes:
+            sp.zeta_rot = 2 if sp.n_modes == 1 else 3
+    for r in wl.reactions:
+        if r.kind != W.RX_RECOMBINATION:
+            r.gamma_rot = 0.5
+    g, o, cells = _sampled_parity(orc, hc, wl, seed=5)
+    per, _ = g.counts()
+    start = np.concatenate([[0], np.cumsum(per.astype(np.int64))])
+    rot = g.read_rotational_energy()
+    for c in cells:
+        assert np.array_equal(o.read_rot(c).view(np.uint64), rot[start[c]:start[c + 1]].view(np.uint64)), f"cell {c}"
 
 
 def test_fullsize_methane_argon_sampled_cells(orc, hc):

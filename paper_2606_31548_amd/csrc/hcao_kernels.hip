@@ -1310,7 +1310,7 @@ __device__ __forceinline__ uint32_t group_cell(const CellHdr *hdr, uint32_t ncel
 // (the audit of its particles before and after); the cell's sum, reduced in
 // pair order, is owed to the cell and joins the translational energy of the
 // cell's pair 0 in the next step in which that pair collides.
-template <int BLOCK, bool MIX, bool EX>
+template <int BLOCK, bool MIX, int EX>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs A) {
   using R = Real<MIX>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -1566,7 +1566,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       P.lv1[m * BLOCK] = A.st.lvl[m * A.st.stride + gq];
     }
     P.r0 = P.r1 = P.rn = 0.0;
-    if constexpr (EX) {
+    if constexpr (EX >= 2) {
       if (A.st.rot) {
         P.r0 = A.st.rot[gp];
         P.r1 = A.st.rot[gq];
@@ -1608,7 +1608,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (P.has_m) mm3 = T.sp[P.sp_m].mass;  // joins the sums only if the third body takes part
     }
     const Vec3 vm_in = P.has_m ? Vec3{(double)P.v_m.x, (double)P.v_m.y, (double)P.v_m.z} : Vec3{0.0, 0.0, 0.0};
-    collide<MIX, EX>(C, P, g2, rng, A.rec, (MIX && k == 0) ? H.defect : 0.0);
+    collide<MIX, (EX >= 2)>(C, P, g2, rng, A.rec, (MIX && k == 0) ? H.defect : 0.0);
     if constexpr (MIX) {
       // Energy audit of the fp32 kinematics: the scattering intends the
       // kinetic energy of the total centre-of-mass motion plus the
@@ -1637,7 +1637,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       A.st.lvl[m * A.st.stride + gp] = P.lv0[m * BLOCK];
       A.st.lvl[m * A.st.stride + gq] = P.lv1[m * BLOCK];
     }
-    if constexpr (EX) {
+    if constexpr (EX >= 2) {
       if (A.st.rot) {
         A.st.rot[gp] = P.dead0 ? 0.0 : P.r0;
         A.st.rot[gq] = P.dead1 ? 0.0 : P.r1;
@@ -1649,7 +1649,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       stv<MIX>(A.scratch, gb, P.nb_v);
       A.scratch.sp[gb] = (uint8_t)P.nb_sp;
       for (uint32_t m = 0; m < mm; ++m) A.scratch.lvl[m * A.scratch.stride + gb] = P.lvn[m * BLOCK];
-      if constexpr (EX) {
+      if constexpr (EX >= 1) {
         if (A.scratch.rot) A.scratch.rot[gb] = P.rn;
         if (A.st.px) {
           const uint64_t gs = P.nb_from ? gq : gp;
@@ -1695,7 +1695,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           if (live) l = A.st.lvl[mo * A.st.stride + src];
           if (live) A.st.lvl[mo * A.st.stride + dst] = l;
         }
-        if constexpr (EX) {
+        if constexpr (EX >= 1) {
           if (A.st.rot) {
             double rv = 0.0;
             if (live) rv = A.st.rot[src];
@@ -1733,7 +1733,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           A.st.sp[to] = A.scratch.sp[from];
           for (uint32_t mo = 0; mo < mm; ++mo)
             A.st.lvl[mo * A.st.stride + to] = A.scratch.lvl[mo * A.scratch.stride + from];
-          if constexpr (EX) {
+          if constexpr (EX >= 1) {
             if (A.st.rot) A.st.rot[to] = A.scratch.rot[from];
             if (A.st.px) {
               A.st.px[to] = A.scratch.px[from];
@@ -2767,7 +2767,7 @@ size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block) {
   return (b + 15) & ~(size_t)15;
 }
 
-template <bool MIX, bool EX>
+template <bool MIX, int EX>
 static hipError_t launch_step_t(const StepArgs &a, size_t lds, int block, uint32_t n_groups, hipStream_t s) {
   switch (block) {
     case 64: hipLaunchKernelGGL((k_step<64, MIX, EX>), dim3(n_groups), dim3(64), lds, s, a); break;
@@ -2779,14 +2779,19 @@ static hipError_t launch_step_t(const StepArgs &a, size_t lds, int block, uint32
   return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, bool exact, uint32_t n_groups,
+// level 0: the collision step; 1: and positions (spatial mode); 2: and the
+// exact sampler and rotors (positions included)
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, int level, uint32_t n_groups,
                        hipStream_t s) {
   if (n_groups == 0) return hipSuccess;
-  if (exact)
-    return mixed ? launch_step_t<true, true>(a, lds, block, n_groups, s)
-                 : launch_step_t<false, true>(a, lds, block, n_groups, s);
-  return mixed ? launch_step_t<true, false>(a, lds, block, n_groups, s)
-               : launch_step_t<false, false>(a, lds, block, n_groups, s);
+  if (level >= 2)
+    return mixed ? launch_step_t<true, 2>(a, lds, block, n_groups, s)
+                 : launch_step_t<false, 2>(a, lds, block, n_groups, s);
+  if (level == 1)
+    return mixed ? launch_step_t<true, 1>(a, lds, block, n_groups, s)
+                 : launch_step_t<false, 1>(a, lds, block, n_groups, s);
+  return mixed ? launch_step_t<true, 0>(a, lds, block, n_groups, s)
+               : launch_step_t<false, 0>(a, lds, block, n_groups, s);
 }
 
 hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s) {

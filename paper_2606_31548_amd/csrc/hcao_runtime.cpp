@@ -19,7 +19,7 @@
 namespace hcao {
 // kernels (hcao_kernels.hip)
 size_t step_lds_bytes(const Tables &T, uint32_t max_cells, int block);
-hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, bool exact, uint32_t n_groups,
+hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, int level, uint32_t n_groups,
                        hipStream_t s);
 hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s);
@@ -1557,6 +1557,10 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   return HCAO_OK;
 }
 
+// which k_step instantiation a context needs: the exact sampler or rotors
+// (2), positions only (1), or neither (0)
+int step_level(const hcao_ctx *c) { return (c->has_exact || c->tab.has_rot) ? 2 : (c->spatial ? 1 : 0); }
+
 hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base, uint32_t *step_dev,
                         hipStream_t s, uint32_t *launches) {
   if (c->spatial) {
@@ -1566,7 +1570,7 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
       StepArgs a = step_args(c, dt);
       a.step = base + d;
       a.n_steps = 1;
-      HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, true, c->n_groups, s));
+      HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, step_level(c), c->n_groups, s));
     }
     if (launches) *launches = n_steps;
     return HCAO_OK;
@@ -1578,7 +1582,7 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
     const uint32_t k = std::min(n_steps - done, c->steps_per_launch);
     a.step = (step_dev ? 0u : base) + done;
     a.n_steps = k;
-    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, c->has_exact || c->tab.has_rot || c->spatial,
+    HIP_TRY(c, launch_step(a, c->step_lds, c->block, c->mixed, step_level(c),
                            c->n_groups, s));
     done += k;
     ++n;

@@ -126,3 +126,35 @@ def test_open_face_refusals(hc):
         g.set_inflow(0b000100, n, 0.0, 1000.0)
     g.set_inflow(0b000100, n, 1000.0, 1000.0)
     assert g.flux_counts() == (0, 0)
+
+
+def test_open_faces_with_the_exact_sampler_parity(orc, hc):
+    """Open faces with every molecule on the exact sampler: positions, the
+    exact sampler and admissions in one instantiation."""
+    wl = W.spatial_box(nx=4, ny=3, nz=2, per_cell=120, chemistry=True, t_trans=12000.0, dt=5e-9,
+                       open_faces=0b000011)
+    for s in wl.species:
+        if s.n_modes:
+            s.sampler = W.SAMPLER_EXACT
+    _run_pair(orc, hc, wl, (3, 9), "exact sampler, x faces open")
+
+
+def test_admissions_beyond_capacity_are_reported(orc, hc):
+    """A two-cell box of capacity 40 whose open face admits far more than a
+    cell holds in one step: the oracle and the library both report a
+    capacity error."""
+    sp = [W.Species("Ar", 40 * W.AMU)]
+    edge = 1e-4
+    wl = W.Workload("crowded", sp, [], np.array([[10], [10]]), np.full(2, 300.0), np.full(2, 300.0),
+                    np.full(2, edge ** 3), np.full(2, 1e6), dt=1e-8, capacity_per_cell=40,
+                    domain=(2, 1, 1, 2 * edge, edge, edge, 0),
+                    inflow=(0b000001, np.array([1e22]), 1000.0, 1000.0))
+    o = orc.from_workload(wl)
+    g = hc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    with pytest.raises(orc.OracleError):
+        o.step(wl.dt, 1)
+    with pytest.raises(hc.HcaoError):
+        g.step(wl.dt, 1)
+        g.sync()

@@ -217,3 +217,22 @@ def test_admitted_particles_follow_earlier_ones_and_counts_balance(orc):
     n1 = sum(o.count(c) for c in range(wl.n_cells))
     assert n_in > 100 and n_out > 100
     assert n1 == n0 + n_in - n_out + int(ctr[orc.CTR_BIRTHS]) - int(ctr[orc.CTR_DEATHS])
+
+
+def test_remainders_carry_the_fraction_of_every_step(orc):
+    """Each face cell admits floor(x) per step and carries x - floor(x): over
+    S steps it admits floor(S x) or one fewer (rounding of the carried sum),
+    never more, so a dropped or doubled remainder shows at once. Here x is
+    about 0.37 per face cell, so most steps admit nothing."""
+    dims, edge, t = (2, 3, 3), 1e-4, 1000.0
+    species = _tracers([40.0])
+    weight = 5e7
+    o = _box(orc, species, dims, edge, weight, 0b000001, np.array([1e21]), t)
+    dt, S = 1e-8, 400
+    flux = 1e21 * math.sqrt((KB * t) / ((2.0 * math.pi) * species[0].mass_kg))
+    x = ((flux * (edge * edge)) * dt) / weight
+    assert 0.2 < x < 0.5
+    o.step(dt, S)
+    n_in, _ = o.flux_counts()
+    faces = dims[1] * dims[2]
+    assert faces * (math.floor(S * x) - 1) <= n_in <= faces * math.floor(S * x)

@@ -346,7 +346,13 @@ hcao_status hcao_set_launch_shape(hcao_ctx *ctx, const hcao_launch_shape *shape)
 
 /* Autotuner of the launch shape: times trial_steps steps of every candidate
  * (block 64, 128, 256 x group_slots 256 .. 4096) from a device copy of the
- * current state, puts the state back, and keeps the fastest candidate
+ * current state advanced by max(trial_steps, 10) steps (so that the first
+ * steps' settling (sigma g)_max does not decide), puts the state back, and
+ * keeps the fastest candidate. Trials shorter than one launch
+ * (steps_per_launch) weigh a launch's start and tail more than the timed
+ * configuration does and can prefer larger workgroups (on the 67 M-particle
+ * chemistry: 5-step trials choose 4096 slots, 50-step trials 2048, the
+ * faster one over 50-step launches)
  * (steps_per_launch is left as it is). The particles, per-cell state,
  * counters and step index after the call are those before it. cache_path
  * (or, when NULL, the environment variable HCAO_AUTOTUNE_CACHE; no cache if

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -35,6 +36,7 @@ if ROOT not in sys.path:
 from paper_2606_31548_amd import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "k_step_traffic.txt")
 
 
 def algorithmic_bytes(wl_species, counts_by_species, n_cells, b_v=8, spatial=False):
@@ -152,11 +154,45 @@ def set_sampler(wl, sampler):
             s.sampler = SAMPLERS[sampler]
 
 
+def host_threads():
+    """Threads the host gives this process (affinity, capped by OMP_NUM_THREADS)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(name, target_s=15.0, sampler="auto", rotors=False):
-    """The oracle as it stands (single thread) on a bounded sample of the
-    same workload: a subset of the cells (for the spatial box an 8 x 8 x 8
-    box of the same cells), stepped from the same kind of initial state,
-    until about target_s seconds of CPU work are done."""
+    """The oracle as it stands on a bounded sample of the same workload, on
+    one thread and on all threads the host gives this process (threads over
+    cells; the oracle's result does not depend on the count). The headline
+    value is the all-threads leg."""
+    threads = host_threads()
+    one = _cpu_leg(name, 0.5 * target_s, sampler, rotors, 1)
+    many = _cpu_leg(name, 0.5 * target_s, sampler, rotors, threads) if threads > 1 else one
+    out = dict(many)
+    out["cpu_model"] = cpu_model()
+    out["single_thread"] = {k: one[k] for k in ("value", "cores", "sample")}
+    return out
+
+
+def _cpu_leg(name, target_s, sampler, rotors, threads):
+    """One leg: a subset of the cells (for the spatial box an 8 x 8 x 8 box
+    of the same cells), stepped from the same kind of initial state, until
+    about target_s seconds of wall time are done."""
     import oracle
     oracle.build(force=False)
     wl, _ = make_workload(name)
@@ -173,6 +209,7 @@ def cpu_baseline(name, target_s=15.0, sampler="auto", rotors=False):
     if rotors:
         set_rotors(sub)
     o = oracle.from_workload(sub)
+    o.set_threads(threads)
     o.init_thermal(sub.counts, sub.t_trans, sub.t_vib)
     o.step(sub.dt, 2)  # warm-up
     c0 = o.counters()[:, oracle.CTR_COLLISIONS].sum()
@@ -185,8 +222,9 @@ def cpu_baseline(name, target_s=15.0, sampler="auto", rotors=False):
     coll = int(o.counters()[:, oracle.CTR_COLLISIONS].sum() - c0)
     what = (f"an 8 x 8 x 8 box of the same cells (the workload has {wl.n_cells})"
             if getattr(wl, "domain", None) is not None else f"{n_cells} of {wl.n_cells} cells of the same workload")
-    return {"value": coll / dt, "unit": "collisions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}, {steps} steps after 2 warm-up steps, {dt:.1f} s, single thread"}
+    return {"value": coll / dt, "unit": "collisions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}, {steps} steps after 2 warm-up steps, {dt:.1f} s, "
+                      f"{threads} thread{'s' if threads > 1 else ''} over cells"}
 
 
 def kernel_digest():
@@ -200,12 +238,13 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, form, spl, shape):
-    """HBM bytes per k_step launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-    runs recorded in profiles/k_step_traffic.txt (lines 'traffic key=value
-    ...'), or None when no record matches this kernel, workload, form and
+def measured_traffic(workload, form, shape):
+    """HBM bytes per step of the k_step launches from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs recorded in profiles/k_step_traffic.txt
+    (lines 'traffic key=value ...', bytes per launch of steps_per_launch
+    steps), or None when no record matches this kernel, workload, form and
     launch shape."""
-    path = os.path.join(ROOT, "profiles", "k_step_traffic.txt")
+    path = TRAFFIC_PATH
     if not os.path.exists(path):
         return None
     digest = kernel_digest()
@@ -215,9 +254,9 @@ def measured_traffic(workload, form, spl, shape):
                 continue
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if (kv.get("digest") == digest and kv.get("workload") == workload and kv.get("form") == form
-                    and int(kv.get("steps_per_launch", -1)) == spl and int(kv.get("block", -1)) == shape["block"]
+                    and int(kv.get("block", -1)) == shape["block"]
                     and int(kv.get("group_slots", -1)) == shape["group_slots"]):
-                return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+                return (float(kv["fetch_bytes"]) + float(kv["write_bytes"])) / int(kv["steps_per_launch"])
     return None
 
 
@@ -233,12 +272,15 @@ def _energy(sim, m, n_modes):
     return e, th
 
 
-def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotune=False, shape=None):
+def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotune=False, shape=None,
+            phase_clocks=False):
     """Times `steps` steps of one form after `warmup` untimed ones, every
-    step-kernel launch advancing `spl` steps (so that every launch, warm-up
-    included, has the same size); returns throughput, the step kernel's
-    roofline figures and the energy drift. graph: steps through the captured
-    hipGraph form; autotune: picks the launch shape first."""
+    step-kernel launch advancing up to `spl` steps (the last launch of a
+    call takes the remainder); returns throughput, the step kernel's roofline
+    figures and the energy drift. graph: steps through the captured hipGraph
+    form (one graph of spl steps per replay, and a remainder graph);
+    autotune: picks the launch shape first; phase_clocks: per-phase clock
+    shares of the timed steps (instrumented library only)."""
     stream = torch.cuda.Stream()
     sim = hcao.from_workload(wl, stream=hcao.ctypes.c_void_p(stream.cuda_stream), precision=precision)
     sim.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
@@ -249,8 +291,17 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
     n_modes = [sp.n_modes for sp in wl.species]
     m_init = sim.moments()
     e_init, th_init = _energy(sim, m_init, n_modes)
-    advance = (lambda n: [sim.step_graph(wl.dt, spl) for _ in range(n // spl)]) if graph else \
-        (lambda n: sim.step(wl.dt, n))
+    # graph form: one captured graph of `chunk` steps, chunk dividing both
+    # step counts, so that it is captured in the warm-up and only replayed
+    # in the timed region
+    chunk = math.gcd(math.gcd(spl, steps), warmup) if warmup else math.gcd(spl, steps)
+
+    def advance(n):
+        if not graph:
+            sim.step(wl.dt, n)
+            return
+        for _ in range(n // chunk):
+            sim.step_graph(wl.dt, chunk)
     advance(warmup)
     sim.sync()
     if autotune:
@@ -263,6 +314,8 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
     _, _, ctr0 = sim.cell_state()
     tot0 = sim.moments()
     per_species0 = np.array(tot0.n_species[:len(wl.species)], np.float64)
+    if phase_clocks:
+        sim.phase_clocks(reset=True)
     sim.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -272,6 +325,7 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
     elapsed = time.perf_counter() - t0
     kernel_ms, launches, kernel_steps = sim.kernel_time()
     sim.set_timing(False)
+    clocks = sim.phase_clocks() if phase_clocks else None
     _, _, ctr1 = sim.cell_state()
     tot1 = sim.moments()
     flux1 = sim.flux_counts()
@@ -309,6 +363,8 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
         "launch_shape": dict(sim.launch_shape(), graph=graph, autotuned=autotune),
         # particles admitted through and gone out of open faces in the timed steps
         "flux": {"admitted": flux1[0] - flux0[0], "left": flux1[1] - flux0[1]} if open_faces else None,
+        "phase_clock_shares": ({k: v / max(sum(clocks.values()), 1) for k, v in clocks.items()}
+                               if clocks else None),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_step", "bytes_per_launch": b_alg, "steps_per_launch": steps_per_launch,
@@ -375,7 +431,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--steps-per-launch", type=int, default=50,
-                    help="steps per step-kernel launch; --steps and --warmup are rounded up to multiples of it")
+                    help="steps per step-kernel launch (the last launch of the warm-up or of the timed region "
+                         "takes the remainder)")
     ap.add_argument("--workload", default="chemistry-67m", choices=WORKLOADS)
     ap.add_argument("--precision", default="both", choices=("both", "mixed", "fp64"),
                     help="both: the mixed form is the headline value, the fp64 form is timed beside it")
@@ -392,6 +449,10 @@ def main():
     ap.add_argument("--recomb-exact", action="store_true",
                     help="also time Eq. recomb-correct for CH4 on the device against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--phase-clocks", action="store_true",
+                    help="report per-phase clock shares of the step kernel (needs the instrumented library: "
+                         "python paper_2606_31548_amd/build.py --phase-clocks, then HCAO_LIBRARY="
+                         "paper_2606_31548_amd/libhcao_clocks.so)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -419,19 +480,25 @@ def main():
         set_rotors(wl)
         desc += "; every molecule a rotor, rotation coupling 0.5"
     spl = max(1, args.steps_per_launch)
-    steps = -(-args.steps // spl) * spl
-    warmup = -(-args.warmup // spl) * spl
+    steps = args.steps
+    warmup = max(0, args.warmup)
+    if steps < 1:
+        print("bench.py needs --steps >= 1", file=sys.stderr)
+        sys.exit(2)
     forms = {"both": ("mixed", "fp64"), "mixed": ("mixed",), "fp64": ("fp64",)}[args.precision]
     batched = args.workload == "batched"
     res = {}
     for f in forms:
-        print(f"# timing the {f} form: {warmup} warm-up + {steps} steps, {spl} per launch", file=sys.stderr,
-              flush=True)
+        print(f"# timing the {f} form: {warmup} warm-up + {steps} steps, up to {spl} per launch",
+              file=sys.stderr, flush=True)
         res[f] = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, steps, warmup, spl,
                          graph=batched, autotune=args.autotune or batched,
-                         shape=None if args.library_shape else TUNED_SHAPE[args.workload])
-        res[f]["roofline"]["traffic"] = (measured_traffic(args.workload, f, spl, res[f]["launch_shape"])
-                                         if args.sampler == "auto" and not args.rotors else None)
+                         shape=None if args.library_shape else TUNED_SHAPE[args.workload],
+                         phase_clocks=args.phase_clocks)
+        per_step = (measured_traffic(args.workload, f, res[f]["launch_shape"])
+                    if args.sampler == "auto" and not args.rotors else None)
+        res[f]["roofline"]["traffic"] = (per_step * res[f]["roofline"]["steps_per_launch"]
+                                         if per_step is not None else None)
     cp = copy_peak(torch)
     for f in res:
         res[f]["roofline"]["frac_of_copy"] = res[f]["roofline"]["achieved"] / cp

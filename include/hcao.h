@@ -53,7 +53,7 @@ extern "C" {
 #define HCAO_MAX_MODES 16
 #define HCAO_MAX_REACTIONS 32
 #define HCAO_MAX_LEVELS 1024
-/* per-cell counters (hcao_read_counters): */
+/* per-cell counters (hcao_read_cell_state): */
 #define HCAO_CTR_CANDIDATES 0 /* NTC candidate pairs tested */
 #define HCAO_CTR_COLLISIONS 1 /* accepted pairs, reactive ones included */
 #define HCAO_CTR_TRIALS 2     /* relaxation sampler trials */
@@ -453,6 +453,19 @@ hcao_status hcao_recombination_exact(hcao_ctx *ctx, uint32_t species, double de_
  * replay counts its step-kernel launches). */
 hcao_status hcao_set_timing(hcao_ctx *ctx, int enable);
 hcao_status hcao_kernel_time(hcao_ctx *ctx, double *ms, uint64_t *launches, uint64_t *steps);
+
+/* Phase clocks of the step kernel, a debugging aid of instrumented builds
+ * (library compiled with HCAO_PHASE_CLOCKS; the default build returns
+ * HCAO_EUNSUPPORTED). Thread 0 of every step workgroup sums the shader
+ * clock cycles (clock64) spent in each phase of the step; out[0..n) (n <=
+ * HCAO_N_PHASES, host array) receives the sums over all workgroups since the
+ * last reset, in the order: launch loads, NTC counts and permutation keys,
+ * cell temperature, candidate acceptance, work-list sort, collisions,
+ * product placement, launch stores. The first call allocates the sums
+ * (zero); reset != 0 zeroes them after reading. Synchronous on the
+ * context's stream. */
+#define HCAO_N_PHASES 8
+hcao_status hcao_phase_clocks(hcao_ctx *ctx, uint64_t *out, uint32_t n, int reset);
 
 /* Checkpoint of the full state (particles, per-cell state, step index). */
 hcao_status hcao_save(hcao_ctx *ctx, const char *path);

@@ -16,7 +16,12 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hcao_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIBRARY names a separately compiled build of hcao_oracle.c (the
+# mutation tests load copies with planted mistakes); build() leaves it alone
+_ALT = os.environ.get("ORACLE_LIBRARY")
+_LIB = _ALT or os.path.join(_HERE, "liboracle.so")
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+          "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 SAMPLER_AUTO, SAMPLER_JOINT, SAMPLER_GIBBS, SAMPLER_EXACT = 0, 1, 2, 3
 RX_DISSOCIATION, RX_EXCHANGE, RX_RECOMBINATION = 0, 1, 2
@@ -26,14 +31,21 @@ MAX_REACTIONS = 32
 N_CTR = 8 + MAX_REACTIONS
 
 
+def compile_to(src: str, out: str) -> str:
+    """Compile an oracle source file with gcc (IEEE fp64: no contraction, no
+    fast-math) into the shared library out."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (IEEE fp64: no contraction, no fast-math)."""
+    """Compile the oracle (unless ORACLE_LIBRARY names another build)."""
+    if _ALT:
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-             "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+        compile_to(_SRC, _LIB)
     return _LIB
 
 
@@ -73,6 +85,7 @@ def lib():
         L.orc_collide_rot_batch.argtypes = [vp, u32] + [vp] * 13; L.orc_collide_rot_batch.restype = ctypes.c_int
         L.orc_init_thermal.argtypes = [vp, vp, vp, vp]
         L.orc_step.argtypes = [vp, d, u32]
+        L.orc_set_threads.argtypes = [vp, ctypes.c_int]; L.orc_set_threads.restype = ctypes.c_int
         L.orc_max_modes.argtypes = [vp]; L.orc_max_modes.restype = u32
         L.orc_count.argtypes = [vp, u32]; L.orc_count.restype = u64
         L.orc_step_index.argtypes = [vp]; L.orc_step_index.restype = u32
@@ -95,6 +108,13 @@ def lib():
         L.orc_rec_exact_probability.argtypes = [vp, u32, d, d, d]; L.orc_rec_exact_probability.restype = d
         L.orc_rec_factor.argtypes = [vp, u32, u32, d]; L.orc_rec_factor.restype = d
         L.orc_rec_table.argtypes = [vp, u32, vp]; L.orc_rec_table.restype = ctypes.c_int
+        L.orc_equilibrium_constant.argtypes = [vp, u32, d]; L.orc_equilibrium_constant.restype = d
+        L.orc_forward_rate.argtypes = [vp, u32, u32, d]; L.orc_forward_rate.restype = d
+        L.orc_forward_probability.argtypes = [vp, u32, u32, d]; L.orc_forward_probability.restype = d
+        L.orc_rec_node_temperature.argtypes = [vp, u32]; L.orc_rec_node_temperature.restype = d
+        L.orc_cell_temperature.argtypes = [vp, u32]; L.orc_cell_temperature.restype = d
+        L.orc_draw_unit_vectors.argtypes = [u64, u32, vp]; L.orc_draw_unit_vectors.restype = None
+        L.orc_draw_three_body_shares.argtypes = [u64, u32, vp]; L.orc_draw_three_body_shares.restype = None
         for name in ("orc_create", "orc_add_species", "orc_add_reaction", "orc_finalize", "orc_load",
                      "orc_init_thermal", "orc_step", "orc_read_cell", "orc_read_cell_state", "orc_levels",
                      "orc_species_info", "orc_pair_info", "orc_moments", "orc_tvib", "orc_relax_batch",
@@ -147,6 +167,18 @@ def gamma_q(a, x):
 
 def gibbs_propose(top, c, u):
     return lib().orc_gibbs_propose(int(top), float(c), float(u))
+
+
+def draw_unit_vectors(seed, n):
+    out = np.zeros((n, 3), np.float64)
+    lib().orc_draw_unit_vectors(int(seed), int(n), _p(out))
+    return out
+
+
+def draw_three_body_shares(seed, n):
+    out = np.zeros(n, np.float64)
+    lib().orc_draw_three_body_shares(int(seed), int(n), _p(out))
+    return out
 
 
 def feistel_index(n, keys, i):
@@ -274,6 +306,11 @@ class Oracle:
     def step(self, dt, n_steps=1):
         _chk("orc_step", lib().orc_step(self._h, float(dt), int(n_steps)))
 
+    def set_threads(self, n):
+        """OpenMP threads over cells in step() (cells are independent, so the
+        result does not depend on n)."""
+        _chk("orc_set_threads", lib().orc_set_threads(self._h, int(n)))
+
     @property
     def step_index(self):
         return lib().orc_step_index(self._h)
@@ -374,6 +411,21 @@ class Oracle:
 
     def rec_factor(self, reaction, third, t):
         return lib().orc_rec_factor(self._h, reaction, third, float(t))
+
+    def equilibrium_constant(self, reaction, t):
+        return lib().orc_equilibrium_constant(self._h, int(reaction), float(t))
+
+    def forward_rate(self, reaction, third, t):
+        return lib().orc_forward_rate(self._h, int(reaction), int(third), float(t))
+
+    def forward_probability(self, reaction, third, t):
+        return lib().orc_forward_probability(self._h, int(reaction), int(third), float(t))
+
+    def rec_node_temperature(self, i):
+        return lib().orc_rec_node_temperature(self._h, int(i))
+
+    def cell_temperature(self, cell):
+        return lib().orc_cell_temperature(self._h, int(cell))
 
     def rec_table(self, reaction):
         out = np.zeros(self.n_species * 1024, np.float64)

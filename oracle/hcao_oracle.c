@@ -321,6 +321,7 @@ struct orc_ctx {
   reaction_t rx[ORC_MAX_REACTIONS];
   pair_t pr[ORC_MAX_SPECIES][ORC_MAX_SPECIES];
   cell_t *cells;
+  int threads; /* OpenMP threads over cells in orc_step (0 or 1: serial) */
 };
 
 static void reset_inflow(orc_ctx *o);
@@ -831,12 +832,58 @@ static double wr_probability(const species_t *A, double de, double omega, uint32
   return den > 0.0 ? num / den : 0.0;
 }
 
-static int build_recombination(orc_ctx *o, reaction_t *R) {
+/* Equilibrium constant of A <-> B + C [m^-3] from partition functions per
+ * unit volume: translation (2 pi m k T / h^2)^(3/2) of each species and the
+ * vibrational sums from the ground state (no rotation is modelled), with the
+ * ground-to-ground energy change dE0 = (h_B + ZPE_B + h_C + ZPE_C) - (h_A +
+ * ZPE_A). Expression order: ((((2 pi k T / h^2)^(3/2) (m_B m_C / m_A)^(3/2))
+ * (Q_B Q_C / Q_A)) exp(-dE0 / kT)). */
+static double equilibrium_constant(const orc_ctx *o, const reaction_t *R, double t) {
   const species_t *B = &o->sp[R->a], *C = &o->sp[R->b], *A = &o->sp[R->c];
+  double de0 = ((B->formation + B->zpe) + (C->formation + C->zpe)) - (A->formation + A->zpe);
+  double ktr = (2.0 * PI_D * K_BOLTZ * t) / (H_PLANCK * H_PLANCK);
+  return pow(ktr, 1.5) * pow((B->mass * C->mass) / A->mass, 1.5) * ((q_vib(B, t) * q_vib(C, t)) / q_vib(A, t)) *
+         exp(-de0 / (K_BOLTZ * t));
+}
+
+/* Maxwellian mean of the VHS sigma g of a pair with mean diameter d,
+ * exponent w and reference temperature tr, reduced mass mred, at t:
+ * 2 d^2 sqrt(2 pi k tr / mred) (t / tr)^(1 - w). */
+static double mean_sigma_g(double d, double w, double tr, double mred, double t) {
+  return 2.0 * (d * d) * sqrt((2.0 * PI_D * K_BOLTZ * tr) / mred) * pow(t / tr, 1.0 - w);
+}
+
+/* dissociation energy of the recombining bond: D_e of A's first listed stretch */
+static double recombination_de(const orc_ctx *o, const reaction_t *R) {
+  const species_t *A = &o->sp[R->c];
   uint32_t j = 0;
   while (!((R->mask >> j) & 1ULL)) ++j;
-  double de = A->de[A->n_bend + j];
-  double de0 = ((B->formation + B->zpe) + (C->formation + C->zpe)) - (A->formation + A->zpe);
+  return A->de[A->n_bend + j];
+}
+
+/* Forward rate coefficient of A + M -> B + C + M [m^3/s]: the paper's
+ * forward probability P(T) (Whitten-Rabinovich; it depends on the third body
+ * only through the A-M VHS exponent) times the Maxwellian collision rate
+ * coefficient of A with M, halved for identical partners (M = A). The
+ * probability p is passed in so that the table builder evaluates it once
+ * per exponent. */
+static double forward_rate(const orc_ctx *o, const reaction_t *R, uint32_t m, double p, double t) {
+  const species_t *A = &o->sp[R->c], *M = &o->sp[m];
+  double w = (A->omega + M->omega) * 0.5, d = (A->dref + M->dref) * 0.5, tr = (A->tref + M->tref) * 0.5;
+  double mred = (A->mass * M->mass) / (A->mass + M->mass);
+  double delta = ((uint32_t)R->c == m) ? 2.0 : 1.0;
+  return p * ((2.0 * (d * d)) / delta) * sqrt((2.0 * PI_D * K_BOLTZ * tr) / mred) * pow(t / tr, 1.0 - w);
+}
+
+static double forward_probability(const orc_ctx *o, const reaction_t *R, uint32_t m, double t) {
+  const species_t *A = &o->sp[R->c], *M = &o->sp[m];
+  return wr_probability(A, recombination_de(o, R), (A->omega + M->omega) * 0.5, R->n_samp, t);
+}
+
+/* Table of the per-collision recombination factor k_b / <sigma g>_BC
+ * (k_b = k_f / K_eq) per third-body species on the log-spaced nodes. */
+static int build_recombination(orc_ctx *o, reaction_t *R) {
+  const species_t *B = &o->sp[R->a], *C = &o->sp[R->b], *A = &o->sp[R->c];
   const pair_t *pbc = &o->pr[R->a][R->b];
   double w_bc = 1.0 - pbc->esg;
   double d_bc = (B->dref + C->dref) * 0.5, t_bc = (B->tref + C->tref) * 0.5;
@@ -844,26 +891,46 @@ static int build_recombination(orc_ctx *o, reaction_t *R) {
   if (!R->rec) return E_NOMEM;
   for (uint32_t i = 0; i < REC_NT; ++i) {
     double t = exp(o->rec_l0 + (double)i / o->rec_inv_step);
-    double sg_bc = 2.0 * (d_bc * d_bc) * sqrt((2.0 * PI_D * K_BOLTZ * t_bc) / pbc->mr) * pow(t / t_bc, 1.0 - w_bc);
-    double ktr = (2.0 * PI_D * K_BOLTZ * t) / (H_PLANCK * H_PLANCK);
-    double keq = pow(ktr, 1.5) * pow((B->mass * C->mass) / A->mass, 1.5) * ((q_vib(B, t) * q_vib(C, t)) / q_vib(A, t)) *
-                 exp(-de0 / (K_BOLTZ * t));
-    double p_w = -1.0, p = 0.0; /* P depends on the third body only through omega */
+    double sg_bc = mean_sigma_g(d_bc, w_bc, t_bc, pbc->mr, t);
+    double keq = equilibrium_constant(o, R, t);
+    double p_w = -1.0, p = 0.0;
     for (uint32_t m = 0; m < o->n_species; ++m) {
-      const species_t *M = &o->sp[m];
-      double w = (A->omega + M->omega) * 0.5, d = (A->dref + M->dref) * 0.5, tr = (A->tref + M->tref) * 0.5;
-      double mred = (A->mass * M->mass) / (A->mass + M->mass);
-      double delta = ((uint32_t)R->c == m) ? 2.0 : 1.0;
+      double w = (A->omega + o->sp[m].omega) * 0.5;
       if (w != p_w) {
-        p = wr_probability(A, de, w, R->n_samp, t);
+        p = forward_probability(o, R, m, t);
         p_w = w;
       }
-      double kf = p * ((2.0 * (d * d)) / delta) * sqrt((2.0 * PI_D * K_BOLTZ * tr) / mred) * pow(t / tr, 1.0 - w);
-      double v = (kf / keq) / sg_bc;
+      double v = (forward_rate(o, R, m, p, t) / keq) / sg_bc;
       R->rec[(size_t)m * REC_NT + i] = (v == v && v >= 0.0) ? v : 0.0;
     }
   }
   return E_OK;
+}
+
+static const reaction_t *recombination_of(const orc_ctx *o, uint32_t reaction) {
+  if (!o || reaction >= o->n_reactions || o->rx[reaction].kind != ORC_RX_RECOMBINATION) return NULL;
+  return &o->rx[reaction];
+}
+
+double orc_equilibrium_constant(const orc_ctx *o, uint32_t reaction, double t) {
+  const reaction_t *R = recombination_of(o, reaction);
+  return R && t > 0.0 ? equilibrium_constant(o, R, t) : -1.0;
+}
+
+double orc_forward_rate(const orc_ctx *o, uint32_t reaction, uint32_t third, double t) {
+  const reaction_t *R = recombination_of(o, reaction);
+  if (!R || third >= o->n_species || !(t > 0.0)) return -1.0;
+  return forward_rate(o, R, third, forward_probability(o, R, third, t), t);
+}
+
+double orc_forward_probability(const orc_ctx *o, uint32_t reaction, uint32_t third, double t) {
+  const reaction_t *R = recombination_of(o, reaction);
+  if (!R || third >= o->n_species || !(t > 0.0)) return -1.0;
+  return forward_probability(o, R, third, t);
+}
+
+double orc_rec_node_temperature(const orc_ctx *o, uint32_t i) {
+  return exp(o->rec_l0 + (double)i / o->rec_inv_step);
 }
 
 int orc_finalize(orc_ctx *o) {
@@ -1540,6 +1607,36 @@ static void unit_vector(stream *st, double n[3]) {
   n[2] = 1.0 - 2.0 * s;
 }
 
+/* Dissociation into three bodies: share beta of the translational energy
+ * that goes to the B-C relative motion. Two relative motions of three
+ * translational degrees of freedom each give the density proportional to
+ * sqrt(beta (1 - beta)) on (0, 1), a Beta(3/2, 3/2) law; drawn by rejection
+ * from the uniform under its maximum 1/2. */
+static double three_body_share(stream *st) {
+  for (;;) {
+    double u1 = uniform(st), u2 = uniform(st);
+    if (u2 * 0.5 < sqrt(u1 * (1.0 - u1))) return u1;
+  }
+}
+
+/* n draws of the scattering direction and of the three-body share, draw i
+ * from the stream (seed; pair i, cell 0, step 0) */
+void orc_draw_unit_vectors(uint64_t seed, uint32_t n, double *out) {
+  for (uint32_t i = 0; i < n; ++i) {
+    stream st;
+    stream_open(&st, seed, i, 0, 0);
+    unit_vector(&st, out + 3 * (size_t)i);
+  }
+}
+
+void orc_draw_three_body_shares(uint64_t seed, uint32_t n, double *out) {
+  for (uint32_t i = 0; i < n; ++i) {
+    stream st;
+    stream_open(&st, seed, i, 0, 0);
+    out[i] = three_body_share(&st);
+  }
+}
+
 /* Places two bodies (pair table p) about the centre-of-mass velocity vcm
  * with relative speed sqrt(2 E / m_r) along a random direction. */
 static void split(const pair_t *p, const double vcm[3], double e, stream *st, double va[3], double vb[3]) {
@@ -1769,16 +1866,7 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
         t += relax(o, &o->sp[R->d], lc, &et, o->pr[R->d][spM].q, st, &c2);
         capped |= c2;
       }
-      /* share of the translational energy in the B-C relative motion:
-       * density proportional to sqrt(beta (1 - beta)), by rejection */
-      double beta;
-      for (;;) {
-        double u1 = uniform(st), u2 = uniform(st);
-        if (u2 * 0.5 < sqrt(u1 * (1.0 - u1))) {
-          beta = u1;
-          break;
-        }
-      }
+      double beta = three_body_share(st);
       double ebc = beta * et;
       double exm = et - ebc;
       const pair_t *pam = &o->pr[spA][spM];
@@ -1919,10 +2007,13 @@ static void store_pair(cell_t *C, uint32_t mm, uint32_t p, uint32_t q, const pai
   }
 }
 
-/* Translational temperature of a cell at step start. The sums of m, m v and
- * m |v|^2 run over blocks of 64 particles in slot order; each block is
- * reduced by a halving tree (element t takes element t + s for s = 32, 16,
- * ..., 1), and block results are added left to right. */
+/* Translational temperature of a cell at step start, T = (sum m |v|^2 -
+ * |sum m v|^2 / sum m) / (3 k N): the sum of m |v - u|^2 about the
+ * mass-weighted mean velocity u over 3 k N. Summation order (fixed, so that
+ * every implementation rounds alike): partial sum t (t = 0..63) takes the
+ * particles t, t + 64, t + 128, ... in slot order; the 64 partial sums are
+ * then combined by a halving tree (sum t adds sum t + s for s = 32, 16, ...,
+ * 1). */
 static double cell_temperature(const orc_ctx *o, const cell_t *C) {
   uint32_t n = C->n;
   if (n < 2) return 0.0;
@@ -1946,6 +2037,11 @@ static double cell_temperature(const orc_ctx *o, const cell_t *C) {
       for (int q = 0; q < 5; ++q) x[q][t] = x[q][t] + x[q][t + sft];
   double p2 = (x[1][0] * x[1][0] + x[2][0] * x[2][0]) + x[3][0] * x[3][0];
   return (x[4][0] - p2 / x[0][0]) / (3.0 * K_BOLTZ * (double)n);
+}
+
+double orc_cell_temperature(const orc_ctx *o, uint32_t cell) {
+  if (!o || cell >= o->n_cells) return -1.0;
+  return cell_temperature(o, &o->cells[cell]);
 }
 
 static int step_cell(orc_ctx *o, uint32_t c, double dt) {
@@ -2259,6 +2355,12 @@ static int move_and_rebin(orc_ctx *o, double dt) {
   return rc;
 }
 
+int orc_set_threads(orc_ctx *o, int n) {
+  if (!o || n < 0) return E_INVAL;
+  o->threads = n;
+  return E_OK;
+}
+
 int orc_step(orc_ctx *o, double dt, uint32_t n_steps) {
   if (!o || !o->loaded) return E_STATE;
   if (!(dt > 0.0)) return E_INVAL;
@@ -2267,10 +2369,18 @@ int orc_step(orc_ctx *o, double dt, uint32_t n_steps) {
       int rc = move_and_rebin(o, dt);
       if (rc) return rc;
     }
+    /* cells are independent (per-cell state, per-cell streams), so threads
+     * over cells give the same result as one thread */
+    int first = E_OK;
+#pragma omp parallel for schedule(static) num_threads(o->threads > 0 ? o->threads : 1)
     for (uint32_t c = 0; c < o->n_cells; ++c) {
       int rc = step_cell(o, c, dt);
-      if (rc) return rc;
+      if (rc) {
+#pragma omp critical
+        if (first == E_OK) first = rc;
+      }
     }
+    if (first != E_OK) return first;
     o->step += 1;
   }
   return E_OK;

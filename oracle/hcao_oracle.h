@@ -87,6 +87,8 @@ int orc_set_inflow(orc_ctx *o, uint32_t open, const double *n_s, double t_trans,
 int orc_flux_counts(const orc_ctx *o, uint64_t *out);
 int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, const double *t_vib);
 int orc_step(orc_ctx *o, double dt, uint32_t n_steps);
+/* threads over cells for orc_step (cells are independent: same result) */
+int orc_set_threads(orc_ctx *o, int n);
 
 /* ---- queries ---- */
 uint32_t orc_max_modes(const orc_ctx *o);
@@ -126,6 +128,21 @@ double orc_q_vib(const orc_ctx *o, uint32_t species, double t);
  * combination of the species (a = 5/2 - omega), at temperature t. */
 double orc_rec_exact_probability(const orc_ctx *o, uint32_t species, double de, double omega, double t);
 double orc_rec_factor(const orc_ctx *o, uint32_t reaction, uint32_t third, double t);
+/* pieces of the recombination factor k_f / K_eq / <sigma g>_BC of a
+ * recombination reaction (B + C + M -> A + M) at temperature t: the
+ * equilibrium constant of A <-> B + C [m^-3], the forward rate coefficient
+ * of A + M -> B + C + M [m^3/s] and its forward probability P; the
+ * temperature of table node i */
+double orc_equilibrium_constant(const orc_ctx *o, uint32_t reaction, double t);
+double orc_forward_rate(const orc_ctx *o, uint32_t reaction, uint32_t third, double t);
+double orc_forward_probability(const orc_ctx *o, uint32_t reaction, uint32_t third, double t);
+double orc_rec_node_temperature(const orc_ctx *o, uint32_t i);
+/* translational temperature of a cell as the step computes it */
+double orc_cell_temperature(const orc_ctx *o, uint32_t cell);
+/* draw i of n from the stream (seed; pair i, cell 0, step 0): scattering
+ * unit vectors (out[3 n]) and the three-body energy share (out[n]) */
+void orc_draw_unit_vectors(uint64_t seed, uint32_t n, double *out);
+void orc_draw_three_body_shares(uint64_t seed, uint32_t n, double *out);
 int orc_rec_table(const orc_ctx *o, uint32_t reaction, double *out);
 int orc_collide3_batch(orc_ctx *o, uint32_t n, const uint8_t *sp, const double *vel, const uint16_t *lvl,
                        uint8_t *sp_out, double *vel_out, uint16_t *lvl_out, int32_t *reaction_out,

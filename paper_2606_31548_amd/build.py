@@ -25,18 +25,27 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True) -> str:
+# instrumented build: per-phase clock sums of the step kernel (hcao_phase_clocks)
+LIB_CLOCKS = os.path.join(HERE, "libhcao_clocks.so")
+
+
+def build(verbose: bool = True, phase_clocks: bool = False) -> str:
+    """Compiles the library in-tree. phase_clocks: the instrumented variant
+    libhcao_clocks.so (load it with HCAO_LIBRARY=<path>)."""
     os.makedirs(BUILD, exist_ok=True)
-    k_obj = os.path.join(BUILD, "hcao_kernels.o")
-    r_obj = os.path.join(BUILD, "hcao_runtime.o")
-    _run([HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", os.path.join(CSRC, "hcao_kernels.hip"), "-o", k_obj])
-    _run([HIPCC, *COMMON, "-c", os.path.join(CSRC, "hcao_runtime.cpp"), "-o", r_obj])
-    tmp = LIB + ".tmp"
+    tag = "_clocks" if phase_clocks else ""
+    defs = ["-DHCAO_PHASE_CLOCKS"] if phase_clocks else []
+    lib = LIB_CLOCKS if phase_clocks else LIB
+    k_obj = os.path.join(BUILD, f"hcao_kernels{tag}.o")
+    r_obj = os.path.join(BUILD, f"hcao_runtime{tag}.o")
+    _run([HIPCC, "-x", "hip", *DEVICE, *COMMON, *defs, "-c", os.path.join(CSRC, "hcao_kernels.hip"), "-o", k_obj])
+    _run([HIPCC, *COMMON, *defs, "-c", os.path.join(CSRC, "hcao_runtime.cpp"), "-o", r_obj])
+    tmp = lib + ".tmp"
     _run([HIPCC, *DEVICE, "-shared", "-fPIC", "-o", tmp, k_obj, r_obj])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build()
+    build(phase_clocks="--phase-clocks" in sys.argv[1:])
     sys.exit(0)

@@ -24,6 +24,24 @@ namespace {
 constexpr double kBoltz = 1.380649e-23;
 constexpr uint8_t kDead = 255;  // species byte of a particle removed by recombination
 
+// Instrumented builds (HCAO_PHASE_CLOCKS) let thread 0 of every step
+// workgroup sum the shader clock spent between the barriers that end each
+// phase; the default build compiles the marks away.
+#ifdef HCAO_PHASE_CLOCKS
+#define HCAO_PHASE_MARK(k)               \
+  do {                                   \
+    if (tid == 0) {                      \
+      const uint64_t t_ = clock64();     \
+      clk_acc[k] += t_ - clk_t;          \
+      clk_t = t_;                        \
+    }                                    \
+  } while (0)
+#else
+#define HCAO_PHASE_MARK(k) \
+  do {                     \
+  } while (0)
+#endif
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 counter-based generator (Salmon et al., SC'11)
 // ---------------------------------------------------------------------------
@@ -1325,6 +1343,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   const uint32_t c0 = A.grp[2 * blockIdx.x], c1 = A.grp[2 * blockIdx.x + 1];
   const uint32_t ncell = c1 - c0;
   const uint64_t wbase = A.grp_work[2 * blockIdx.x];
+#ifdef HCAO_PHASE_CLOCKS
+  uint64_t clk_acc[kPhases] = {};
+  uint64_t clk_t = clock64();
+#endif
 
   // ---- LDS carve-up ----
   unsigned char *q = smem;
@@ -1377,6 +1399,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   uint8_t *bflag = A.bflag + wbase;
   double *wdef = MIX ? A.wdef + wbase : nullptr;
   __syncthreads();
+  HCAO_PHASE_MARK(kPhaseLoad);
 
   const uint32_t step0 = A.step_dev ? *A.step_dev + A.step : A.step;
   for (uint32_t si = 0; si < A.n_steps; ++si) {
@@ -1406,6 +1429,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     if (ncand > 0) make_perm(H.perm, n, A.seed, H.cell, step);
   }
   __syncthreads();
+  HCAO_PHASE_MARK(kPhaseNtc);
   if (GT->has_recomb) {
     // cell temperature and its recombination-table coordinate (one wave per cell)
     for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
@@ -1441,6 +1465,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     s_nwork = 0;
   }
   __syncthreads();
+  HCAO_PHASE_MARK(kPhaseTemperature);
   const uint32_t total = s_total;
 
   // ---- phase A: candidate pairs, VHS acceptance ----
@@ -1513,6 +1538,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     }
   }
   __syncthreads();
+  HCAO_PHASE_MARK(kPhaseAccept);
 
   // ---- counting sort of the work list by key ----
   const uint32_t nwork = s_nwork;
@@ -1543,6 +1569,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     work[3 * pos + 2] = work_in[4 * i + 2];
   }
   __syncthreads();
+  HCAO_PHASE_MARK(kPhaseSort);
 
   // ---- phase B: one accepted pair per lane ----
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
@@ -1662,6 +1689,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     }
   }
   __syncthreads();
+  HCAO_PHASE_MARK(kPhaseCollide);
 
   // ---- phase C: deaths, products in pair order, per-cell state ----
   // one wave per cell: ballots give each survivor its new slot and each
@@ -1773,6 +1801,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     }
   }
   __syncthreads();
+  HCAO_PHASE_MARK(kPhasePlace);
   }  // steps
 
   // ---- persistent cell state back to HBM ----
@@ -1790,6 +1819,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (MIX) A.cells.defect[c] = H.defect;
     }
   }
+#ifdef HCAO_PHASE_CLOCKS
+  HCAO_PHASE_MARK(kPhaseStore);
+  if (tid == 0 && A.clk)
+    for (int k = 0; k < kPhases; ++k) atomicAdd(&A.clk[k], (unsigned long long)clk_acc[k]);
+#endif
 }
 
 // ---------------------------------------------------------------------------

@@ -185,6 +185,7 @@ struct hcao_ctx {
   uint64_t graph_gen = ~0ull;
   DevBuf<uint32_t> d_step;      // step index read by graph replays
   int64_t d_step_value = -1;    // value d_step holds (-1: unknown)
+  DevBuf<unsigned long long> clk;  // per-phase clock sums of the step kernel (instrumented builds)
 };
 
 namespace {
@@ -1424,6 +1425,7 @@ StepArgs step_args(hcao_ctx *c, double dt) {
   a.work = c->work.p;
   a.bflag = c->bflag.p;
   a.wdef = c->wdef.p;
+  a.clk = c->clk.p;
   return a;
 }
 
@@ -2254,6 +2256,30 @@ hcao_status hcao_kernel_time(hcao_ctx *c, double *ms, uint64_t *launches, uint64
   if (launches) *launches = c->timed_launches;
   if (steps) *steps = c->timed_steps;
   return HCAO_OK;
+}
+
+hcao_status hcao_phase_clocks(hcao_ctx *c, uint64_t *out, uint32_t n, int reset) {
+  if (!c || (n && !out)) return HCAO_EINVAL;
+  if (hcao_status s = check_sticky(c)) return s;
+#ifdef HCAO_PHASE_CLOCKS
+  if (!c->finalized) return fail(c, HCAO_ESTATE, "phase clocks before finalize");
+  if (!c->clk.p) {
+    HIP_TRY(c, c->clk.alloc(kPhases));
+    HIP_TRY(c, hipMemsetAsync(c->clk.p, 0, kPhases * sizeof(unsigned long long), c->stream));
+  }
+  unsigned long long h[kPhases] = {};
+  HIP_TRY(c, hipMemcpyAsync(h, c->clk.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (uint32_t k = 0; k < n && k < (uint32_t)kPhases; ++k) out[k] = h[k];
+  if (reset) {
+    HIP_TRY(c, hipMemsetAsync(c->clk.p, 0, kPhases * sizeof(unsigned long long), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return HCAO_OK;
+#else
+  (void)reset;
+  return fail(c, HCAO_EUNSUPPORTED, "phase clocks need a library built with HCAO_PHASE_CLOCKS");
+#endif
 }
 
 hcao_status hcao_save(hcao_ctx *c, const char *path) {

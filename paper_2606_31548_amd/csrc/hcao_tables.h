@@ -99,6 +99,23 @@ struct CellArrays {
   unsigned long long *ctr;  // [n_cells][kNumCtr]
 };
 
+// Phases of the step kernel, for the clock sums of instrumented builds
+// (HCAO_PHASE_CLOCKS): table and cell loads of a launch, NTC counts and
+// permutation keys, cell temperature, candidate acceptance, work-list sort,
+// collisions, product placement, and the launch's final stores.
+enum StepPhase {
+  kPhaseLoad = 0,
+  kPhaseNtc,
+  kPhaseTemperature,
+  kPhaseAccept,
+  kPhaseSort,
+  kPhaseCollide,
+  kPhasePlace,
+  kPhaseStore,
+  kPhases
+};
+static_assert(kPhases == HCAO_N_PHASES, "phase list and ABI disagree");
+
 // Workgroup b processes the consecutive cells [grp[2b], grp[2b+1]); its work
 // list, product flags and pair energy defects are the entries
 // [grp_work[2b], grp_work[2b+1]) of work (seven words each: the pair as
@@ -118,6 +135,7 @@ struct StepArgs {
   uint8_t *bflag;
   double *wdef;  // mixed form: energy defect of each candidate pair, indexed like bflag
   uint32_t *err;
+  unsigned long long *clk;   // per-phase clock sums [kPhases] (instrumented builds) or null
   uint64_t seed;
   const uint32_t *step_dev;  // device step index (graph replays) or null
   uint32_t step;             // index of the launch's first step (plus *step_dev when set)

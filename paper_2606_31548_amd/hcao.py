@@ -13,7 +13,11 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhcao.so")
+# HCAO_LIBRARY selects another build of the library (the instrumented
+# libhcao_clocks.so of build.py --phase-clocks); default: libhcao.so
+LIB_PATH = os.environ.get("HCAO_LIBRARY") or os.path.join(HERE, "libhcao.so")
+N_PHASES = 8
+PHASES = ("load", "ntc", "temperature", "accept", "sort", "collide", "place", "store")
 
 ABI_VERSION = 1
 MAX_SPECIES = 16
@@ -134,6 +138,7 @@ def load_library():
     L.hcao_autotune.argtypes = [_vp, _d, _u32, ctypes.c_char_p, ctypes.POINTER(hcao_launch_shape)]
     L.hcao_step_graph.argtypes = [_vp, _d, _u32]
     L.hcao_read_cell_particles.argtypes = [_vp, _u32, _u32, _vp, _vp, _vp, ctypes.POINTER(_u32)]
+    L.hcao_phase_clocks.argtypes = [_vp, _vp, _u32, ctypes.c_int]
     for name in ("hcao_create", "hcao_add_species", "hcao_add_reaction", "hcao_finalize", "hcao_load_particles",
                  "hcao_init_thermal", "hcao_step", "hcao_sync", "hcao_get_counts", "hcao_read_particles",
                  "hcao_read_cell_state", "hcao_read_moments", "hcao_read_reaction_counts", "hcao_get_levels",
@@ -141,7 +146,7 @@ def load_library():
                  "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
                  "hcao_read_cell_particles", "hcao_get_exact_beta", "hcao_recombination_exact",
                  "hcao_read_rotational_energy", "hcao_set_domain", "hcao_read_positions", "hcao_set_inflow",
-                 "hcao_read_flux_counts"):
+                 "hcao_read_flux_counts", "hcao_phase_clocks"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -434,6 +439,13 @@ class Simulation:
         self._chk("hcao_kernel_time", self._L.hcao_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n),
                                                                 ctypes.byref(k)))
         return ms.value, n.value, k.value
+
+    def phase_clocks(self, reset: bool = False):
+        """Per-phase clock sums of the step kernel (instrumented builds only;
+        raises HcaoError HCAO_EUNSUPPORTED otherwise)."""
+        out = np.zeros(N_PHASES, np.uint64)
+        self._chk("hcao_phase_clocks", self._L.hcao_phase_clocks(self._h, _p(out), N_PHASES, int(reset)))
+        return dict(zip(PHASES, (int(x) for x in out)))
 
     def save(self, path):
         self._chk("hcao_save", self._L.hcao_save(self._h, str(path).encode()))

@@ -37,14 +37,18 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-def test_measured_traffic_is_tied_to_the_kernel_sources(monkeypatch):
+def test_measured_traffic_is_tied_to_the_kernel_sources(monkeypatch, tmp_path):
     shape = {"block": 128, "group_slots": 2048}
-    t = bench.measured_traffic("chemistry-67m", "mixed", 50, shape)
-    assert t is not None and t > 0
-    assert bench.measured_traffic("chemistry-67m", "mixed", 25, shape) is None
-    assert bench.measured_traffic("methane-argon", "mixed", 50, shape) is None
+    rec = tmp_path / "traffic.txt"
+    rec.write_text(f"# header\ntraffic digest={bench.kernel_digest()} workload=chemistry-67m form=mixed "
+                   "steps_per_launch=50 block=128 group_slots=2048 fetch_bytes=2e11 write_bytes=1e11\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PATH", str(rec))
+    assert bench.measured_traffic("chemistry-67m", "mixed", shape) == pytest.approx(3e11 / 50)
+    assert bench.measured_traffic("chemistry-67m", "fp64", shape) is None
+    assert bench.measured_traffic("methane-argon", "mixed", shape) is None
+    assert bench.measured_traffic("chemistry-67m", "mixed", {"block": 64, "group_slots": 2048}) is None
     monkeypatch.setattr(bench, "kernel_digest", lambda: "0" * 16)
-    assert bench.measured_traffic("chemistry-67m", "mixed", 50, shape) is None
+    assert bench.measured_traffic("chemistry-67m", "mixed", shape) is None
 
 
 @pytest.mark.parametrize("name", bench.WORKLOADS)
@@ -59,6 +63,25 @@ def test_every_workload_builds_and_has_a_tuned_shape(name):
 
 
 def test_cpu_baseline_reports_the_oracle_on_a_bounded_sample():
-    cb = bench.cpu_baseline("methane-argon", target_s=0.5)
-    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "collisions/s"
-    assert cb["value"] > 0 and "cells" in cb["sample"]
+    cb = bench.cpu_baseline("methane-argon", target_s=1.0)
+    assert cb["kind"] == "oracle" and cb["cores"] == bench.host_threads() and cb["unit"] == "collisions/s"
+    assert cb["value"] > 0 and "cells" in cb["sample"] and cb["cpu_model"]
+    assert cb["single_thread"]["cores"] == 1 and cb["single_thread"]["value"] > 0
+
+
+def test_oracle_threads_do_not_change_the_result():
+    import numpy as np
+    import oracle
+    from paper_2606_31548_amd import workloads as W
+    wl = W.methane_chemistry(n_cells=16, per_cell=64, recombination=True, t=12000.0)
+    outs = []
+    for threads in (1, 4):
+        o = oracle.from_workload(wl)
+        o.set_threads(threads)
+        o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+        o.step(wl.dt, 5)
+        outs.append((o.read_all(), o.counters()))
+    (a, ca), (b, cb) = outs
+    for x, y in zip(a, b):
+        assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8))
+    assert np.array_equal(ca, cb)

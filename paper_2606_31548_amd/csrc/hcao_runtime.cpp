@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "hcao.h"
+#include "hcao_host_tables.h"
 #include "hcao_tables.h"
 
 namespace hcao {
@@ -56,8 +57,6 @@ using namespace hcao;
 
 namespace {
 
-constexpr double kH = 6.62607015e-34;
-constexpr double kC = 299792458.0;
 constexpr double kB = 1.380649e-23;
 constexpr double kPi = 3.141592653589793;
 constexpr size_t kLdsBudget = 64 * 1024;  // LDS bytes per workgroup of the step kernel
@@ -212,38 +211,22 @@ hcao_status hip_fail(hcao_ctx *c, hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
   } while (0)
 
-// Morse levels E(i) = a (i + 1/2) - a x_e (i + 1/2)^2, a = h c w_e; kept while
-// below D_e and still increasing. D_e defaults to a / (4 x_e).
+// Level ladder of one stretch: explicit energies, or the Morse ladder of
+// (w_e, x_e) capped at D_e (D_e = h c w_e / (4 x_e) when not given).
 hcao_status build_stretch(hcao_ctx *c, double we, double xe, double de, uint32_t n_explicit, const double *expl,
                           std::vector<double> &out, double &de_out) {
-  out.clear();
-  if (n_explicit > 0) {
-    if (!(de > 0.0)) return fail(c, HCAO_EINVAL, "explicit level list needs D_e > 0");
-    for (uint32_t i = 0; i < n_explicit && i < (uint32_t)kMaxLevels; ++i) {
-      const double e = expl[i];
-      if (!(e < de)) break;
-      if (i > 0 && !(e > out.back())) return fail(c, HCAO_EINVAL, "level list must increase strictly");
-      out.push_back(e);
-    }
-  } else {
-    if (!(we > 0.0) || !(xe >= 0.0)) return fail(c, HCAO_EINVAL, "stretch needs omega_e > 0 and chi_e >= 0");
-    const double a = (kH * kC) * we;
-    const double ax = a * xe;
-    if (!(de > 0.0)) {
-      if (!(xe > 0.0)) return fail(c, HCAO_EINVAL, "D_e missing and chi_e = 0");
-      de = a / (4.0 * xe);
-    }
-    for (uint32_t i = 0; i < (uint32_t)kMaxLevels; ++i) {
-      const double v = (double)i + 0.5;
-      const double e = (a * v) - ((ax * v) * v);
-      if (!(e < de)) break;
-      if (i > 0 && !(e > out.back())) break;
-      out.push_back(e);
-    }
-  }
-  if (out.empty()) return fail(c, HCAO_EINVAL, "stretch has no bound level");
+  const char *why = n_explicit > 0 ? host::explicit_ladder(expl, n_explicit, de, out) : host::morse_ladder(we, xe, de, out);
+  if (why) return fail(c, HCAO_EINVAL, why);
   de_out = de;
   return HCAO_OK;
+}
+
+// the vibrational modes of a species for the host tables
+host::ModeSet modes_of(const SpeciesHost &s) {
+  host::ModeSet m;
+  m.theta = s.theta;
+  for (const std::vector<double> &L : s.levels) m.ladder.push_back(&L);
+  return m;
 }
 
 double host_mode_energy(const SpeciesHost &s, uint32_t m, uint32_t i) {
@@ -617,117 +600,6 @@ hcao_status read_err(hcao_ctx *c) {
   return HCAO_OK;
 }
 
-// mean vibrational energy above the zero point at temperature t (Boltzmann
-// sums over the bound stretch levels, harmonic closed form for bends)
-double mean_evib(const SpeciesHost &s, double t) {
-  double e = 0.0;
-  for (uint32_t b = 0; b < s.d.n_bend; ++b) {
-    const double th = s.theta[b];
-    e += kB * th / std::expm1(th / t);
-  }
-  for (const auto &L : s.levels) {
-    double num = 0.0, den = 0.0;
-    for (double x : L) {
-      const double d = x - L[0];
-      const double w = std::exp(-d / (kB * t));
-      num += d * w;
-      den += w;
-    }
-    e += num / den;
-  }
-  return e;
-}
-
-double solve_tvib(const SpeciesHost &s, double target) {
-  if (s.n_modes == 0 || !(target > 0.0)) return 0.0;
-  double lo = 0.0, hi = std::log(1.0e6);
-  if (mean_evib(s, std::exp(hi)) < target) return std::exp(hi);
-  for (int it = 0; it < 200 && hi - lo > 1e-15; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mean_evib(s, std::exp(mid)) < target)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return std::exp(0.5 * (lo + hi));
-}
-
-// ---------------------------------------------------------------------------
-// recombination: per-collision probability factors k_b / <sigma g>_BC
-// ---------------------------------------------------------------------------
-// regularized upper incomplete gamma Q(a, x), x > 0 (series below a + 1,
-// Lentz continued fraction above; Press et al., Numerical Recipes 6.2)
-double inc_gamma_q(double a, double x) {
-  if (!(x > 0.0)) return 1.0;
-  const double lpre = -x + a * std::log(x) - std::lgamma(a);
-  if (x < a + 1.0) {
-    double ap = a, del = 1.0 / a, sum = del;
-    for (int n = 1; n <= 1000; ++n) {
-      ap = ap + 1.0;
-      del = del * (x / ap);
-      sum = sum + del;
-      if (std::fabs(del) < std::fabs(sum) * 1e-17) break;
-    }
-    return 1.0 - sum * std::exp(lpre);
-  }
-  const double tiny = 1e-300;
-  double bb = x + 1.0 - a, cf = 1.0 / tiny, d = 1.0 / bb, h = d;
-  for (int i = 1; i <= 1000; ++i) {
-    const double an = -(double)i * ((double)i - a);
-    bb = bb + 2.0;
-    d = an * d + bb;
-    if (std::fabs(d) < tiny) d = tiny;
-    cf = bb + an / cf;
-    if (std::fabs(cf) < tiny) cf = tiny;
-    d = 1.0 / d;
-    const double del = d * cf;
-    h = h * del;
-    if (std::fabs(del - 1.0) < 1e-17) break;
-  }
-  return std::exp(lpre) * h;
-}
-
-// vibrational partition sum from the ground state
-double partition_vib(const SpeciesHost &s, double t) {
-  double qv = 1.0;
-  for (uint32_t b = 0; b < s.d.n_bend; ++b) qv = qv * (1.0 / (1.0 - std::exp(-s.theta[b] / t)));
-  for (const auto &L : s.levels) {
-    double z = 0.0;
-    for (size_t i = 0; i < L.size(); ++i) z = z + std::exp(-(L[i] - L[0]) / (kB * t));
-    qv = qv * z;
-  }
-  return qv;
-}
-
-// forward probability of the recombination section: Whitten-Rabinovich
-// density of states at n_samp evenly spaced energies up to D_e
-double wr_forward(const SpeciesHost &A, double de, double omega, uint32_t n_samp, double t) {
-  const uint32_t l = A.n_modes, nb = A.d.n_bend;
-  double nu_sum = 0.0, nu2_sum = 0.0;
-  for (uint32_t m = 0; m < l; ++m) {
-    const double nu = (m < nb) ? (kB * A.theta[m]) / kH : (A.levels[m - nb][1] - A.levels[m - nb][0]) / kH;
-    nu_sum = nu_sum + nu;
-    nu2_sum = nu2_sum + nu * nu;
-  }
-  const double ez = 0.5 * kH * nu_sum;
-  const double lm1 = (double)l - 1.0;
-  const double beta = (lm1 * lm1 * nu2_sum) / ((double)l * (nu_sum * nu_sum));
-  double num = 0.0, den = 0.0;
-  for (uint32_t i = 1; i <= n_samp; ++i) {
-    const double e = (double)(i - 1) * de / (double)(n_samp - 1);
-    const double r = e / ez;
-    const double omg =
-        (r >= 1.0) ? std::pow(10.0, -1.0506 * std::pow(r, 0.25)) : 1.0 / (5.0 * r + 2.73 * std::sqrt(r) + 3.51);
-    const double aw = 1.0 - beta * omg;
-    const double rho = std::pow(e + aw * ez, lm1);
-    const double w = rho * std::exp(-e / (kB * t));
-    num = num + inc_gamma_q(2.5 - omega, (de - e) / (kB * t)) * w;
-    den = den + w;
-  }
-  return den > 0.0 ? num / den : 0.0;
-}
-
-// k_b / <sigma g>_BC on the log-T grid, per third-body species (appended to out)
 // Eq. recomb-correct on the device for species sp of the device tables:
 // every level combination below de is enumerated (count pass, scan, write
 // pass), then one workgroup per temperature sums the records. p[i] receives
@@ -829,45 +701,47 @@ hcao_status exact_rec_probability(hcao_ctx *c, uint32_t sp, double de, double om
   return HCAO_OK;
 }
 
+// k_b / <sigma g>_BC of a recombination reaction on the log-T nodes, per
+// third-body species (appended to out); exact holds the device's Eq.
+// recomb-correct probabilities per (A, third body) exponent, if any
 void build_recombination_table(const hcao_ctx *c, const hcao_reaction_desc &d, const Tables &T,
                                std::vector<double> &out, const std::vector<std::pair<double, std::vector<double>>> &exact) {
   const SpeciesHost &B = c->species[d.reactant[0]], &C = c->species[d.reactant[1]], &A = c->species[d.product[0]];
-  uint32_t j = 0;
-  while (!((d.stretch_mask >> j) & 1ull)) ++j;
-  const double de = A.de[j];
-  const double de0 = ((B.d.formation_J + B.zpe) + (C.d.formation_J + C.zpe)) - (A.d.formation_J + A.zpe);
-  const PairTab &PBC = T.pr[d.reactant[0]][d.reactant[1]];
-  const double w_bc = 1.0 - PBC.esg;
-  const double d_bc = (B.d.dref_m + C.d.dref_m) * 0.5, t_bc = (B.d.Tref_K + C.d.Tref_K) * 0.5;
-  const uint32_t ns = T.n_species, n_samp = d.n_samp ? d.n_samp : 1000;
-  const size_t off = out.size();
-  out.resize(off + (size_t)ns * kRecNodes, 0.0);
-  for (uint32_t i = 0; i < kRecNodes; ++i) {
-    const double t = std::exp(T.rec_l0 + (double)i / T.rec_inv_step);
-    const double sg_bc = 2.0 * (d_bc * d_bc) * std::sqrt((2.0 * kPi * kB * t_bc) / PBC.mr) * std::pow(t / t_bc, 1.0 - w_bc);
-    const double ktr = (2.0 * kPi * kB * t) / (kH * kH);
-    const double keq = std::pow(ktr, 1.5) * std::pow((B.d.mass_kg * C.d.mass_kg) / A.d.mass_kg, 1.5) *
-                       ((partition_vib(B, t) * partition_vib(C, t)) / partition_vib(A, t)) * std::exp(-de0 / (kB * t));
-    double p_w = -1.0, p = 0.0;  // P depends on the third body only through omega
-    for (uint32_t m = 0; m < ns; ++m) {
-      const hcao_species_desc &M = c->species[m].d;
-      const double w = (A.d.omega + M.omega) * 0.5, dd = (A.d.dref_m + M.dref_m) * 0.5,
-                   tr = (A.d.Tref_K + M.Tref_K) * 0.5;
-      const double mred = (A.d.mass_kg * M.mass_kg) / (A.d.mass_kg + M.mass_kg);
-      const double delta = ((uint32_t)d.product[0] == m) ? 2.0 : 1.0;
-      if (w != p_w) {
-        p = -1.0;
-        for (const auto &ex : exact)
-          if (ex.first == w) p = ex.second[i];
-        if (p < 0.0) p = wr_forward(A, de, w, n_samp, t);
-        p_w = w;
-      }
-      const double kf =
-          p * ((2.0 * (dd * dd)) / delta) * std::sqrt((2.0 * kPi * kB * tr) / mred) * std::pow(t / tr, 1.0 - w);
-      const double v = (kf / keq) / sg_bc;
-      out[off + (size_t)m * kRecNodes + i] = (v == v && v >= 0.0) ? v : 0.0;
-    }
+  const host::ModeSet ma = modes_of(A), mb = modes_of(B), mc = modes_of(C);
+  host::Recombination r{};
+  r.a = &ma;
+  r.b = &mb;
+  r.c = &mc;
+  r.mass_a = A.d.mass_kg;
+  r.mass_b = B.d.mass_kg;
+  r.mass_c = C.d.mass_kg;
+  r.formation_a = A.d.formation_J;
+  r.formation_b = B.d.formation_J;
+  r.formation_c = C.d.formation_J;
+  r.zpe_a = A.zpe;
+  r.zpe_b = B.zpe;
+  r.zpe_c = C.zpe;
+  r.dref_a = A.d.dref_m;
+  r.omega_a = A.d.omega;
+  r.tref_a = A.d.Tref_K;
+  const PairTab &bc = T.pr[d.reactant[0]][d.reactant[1]];
+  r.bc_dref = (B.d.dref_m + C.d.dref_m) * 0.5;
+  r.bc_tref = (B.d.Tref_K + C.d.Tref_K) * 0.5;
+  r.bc_esg = bc.esg;
+  r.bc_mr = bc.mr;
+  uint32_t bond = 0;  // the first stretch the reaction names
+  while (!((d.stretch_mask >> bond) & 1ull)) ++bond;
+  r.de = A.de[bond];
+  r.n_samp = d.n_samp ? d.n_samp : 1000;
+  r.self = (uint32_t)d.product[0];
+  for (const SpeciesHost &M : c->species) {
+    r.m_dref.push_back(M.d.dref_m);
+    r.m_omega.push_back(M.d.omega);
+    r.m_tref.push_back(M.d.Tref_K);
+    r.m_mass.push_back(M.d.mass_kg);
   }
+  r.exact = &exact;
+  host::recombination_factors(r, T.rec_l0, T.rec_inv_step, kRecNodes, out);
 }
 
 }  // namespace
@@ -1044,54 +918,6 @@ hcao_status hcao_add_reaction(hcao_ctx *c, const hcao_reaction_desc *d, int32_t 
   return HCAO_OK;
 }
 
-// Exact sampler: beta of the proposal per bin of E' (energy above the zero
-// point). Bin b holds the smallest beta_j of the grid, found by bisection,
-// with G(beta_j) + q / beta_j <= E'_b: E'_b is the bin's midpoint and G the
-// proposal's mean energy over the modes' full level sets (bends
-// k Theta / expm1(beta k Theta), stretches the Boltzmann mean of
-// E_i - E_0 over all levels, ascending). Any beta gives the target exactly;
-// this one puts the acceptance near its maximum.
-static double exact_beta_grid(uint32_t j) { return std::ldexp(1.0 + (double)(j & 15u) / 16.0, (int)(j >> 4) + 40); }
-
-static double exact_mean_energy(const SpeciesTab &S, const std::vector<double> &lev, double beta) {
-  double g = 0.0;
-  for (uint32_t m = 0; m < S.n_modes; ++m) {
-    if (m < S.n_bend) {
-      g = g + S.kt[m] / std::expm1(beta * S.kt[m]);
-    } else {
-      const double *L = lev.data() + S.lev_off[m];
-      double num = 0.0, den = 0.0;
-      for (uint32_t i = 0; i <= S.idiss[m]; ++i) {
-        const double e = L[i] - L[0];
-        const double w = std::exp(-(beta * e));
-        num = num + e * w;
-        den = den + w;
-      }
-      g = g + num / den;
-    }
-  }
-  return g;
-}
-
-static void build_exact_table(const SpeciesTab &S, const std::vector<double> &lev, double q,
-                              std::vector<double> &out) {
-  for (uint32_t b = kExactBinLo; b <= kExactBinHi; ++b) {
-    const uint64_t bits = ((uint64_t)b << 48) | ((uint64_t)1 << 47);
-    double ec;
-    std::memcpy(&ec, &bits, sizeof(ec));
-    uint32_t lo = 0, hi = kExactNBeta - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      const double bm = exact_beta_grid(mid);
-      if (exact_mean_energy(S, lev, bm) + q / bm <= ec)
-        hi = mid;
-      else
-        lo = mid + 1;
-    }
-    out.push_back(exact_beta_grid(lo));
-  }
-}
-
 hcao_status hcao_finalize(hcao_ctx *c) {
   if (!c) return HCAO_EINVAL;
   if (c->finalized) return fail(c, HCAO_ESTATE, "finalize called twice");
@@ -1188,7 +1014,13 @@ hcao_status hcao_finalize(hcao_ctx *c) {
         if (T.pr[a][b2].q == T.pr[a][b].q) T.pr[a][b].beta_off = T.pr[a][b2].beta_off;
       if (T.pr[a][b].beta_off != 0xFFFFFFFFu) continue;
       T.pr[a][b].beta_off = (uint32_t)c->beta_host.size();
-      build_exact_table(T.sp[a], c->lev_host, T.pr[a][b].q, c->beta_host);
+      // exact sampler: beta per bin of E' (energy above the zero point), the
+      // smallest grid value whose proposal mean energy plus q / beta is at
+      // most the bin's midpoint (any beta samples the target exactly; this one
+      // puts the acceptance near its peak)
+      std::vector<double> kt(T.sp[a].kt, T.sp[a].kt + T.sp[a].n_bend);
+      host::exact_beta_bins(kt, modes_of(c->species[a]), T.pr[a][b].q, kExactBinLo, kExactBinHi, kExactNBeta,
+                            c->beta_host);
     }
   if (c->beta_host.empty()) c->beta_host.push_back(0.0);
   T.rec_nt = kRecNodes;
@@ -2037,7 +1869,7 @@ hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments 
       ntot += k;
       M.E_vib_J[s] = r[6 + ns + s];
       if (vol > 0.0) M.number_density[s] = (double)k * wgt / vol;
-      M.T_vib_K[s] = k ? solve_tvib(c->species[s], r[6 + ns + s] / (double)k) : 0.0;
+      M.T_vib_K[s] = k ? host::vibrational_temperature(modes_of(c->species[s]), r[6 + ns + s] / (double)k) : 0.0;
       M.E_rot_J[s] = r[6 + 2 * ns + s];
       const uint32_t z = c->species[s].d.zeta_rot;
       M.T_rot_K[s] = (k && z) ? (2.0 * M.E_rot_J[s]) / ((double)z * kB * (double)k) : 0.0;

@@ -368,6 +368,28 @@ hcao_status hcao_autotune(hcao_ctx *ctx, double dt, uint32_t trial_steps, const 
  * stream; later calls replay it. Results are bitwise those of hcao_step. */
 hcao_status hcao_step_graph(hcao_ctx *ctx, double dt, uint32_t n_steps);
 
+/* Allocation-free step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same n_steps steps as hcao_step, with bitwise the same
+ * result, but the step's work lists, pair flags, pair energy defects and
+ * products staging live in one fixed device array of
+ * HCAO_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, not in the context's buffers. The call allocates
+ * and frees nothing. Its need is about 30 + 3 b_v + 2 max_modes bytes per
+ * work entry (b_v = 8 fp64, 4 mixed; 8 more in the mixed form and 8 more
+ * with rotors; work entries = sum over cells of capacity / 2 + 1, e.g.
+ * 725,000 for 4,096 cells of 256 particles at the default capacity, 52 MB
+ * in fp64 for the methane species): a context that needs more
+ * gets HCAO_ECAPACITY with the figure in hcao_last_error and nothing runs.
+ * The spatial mode is refused (HCAO_EUNSUPPORTED): its re-bin needs buffers
+ * as large as the state. Every call on a GPU uses that GPU's one array, whose
+ * contents the next call overwrites (nothing in it needs to start at zero):
+ * calls that overlap on one GPU, from two streams or threads, race, and the
+ * caller must order them. Asynchronous on the context's stream, like
+ * hcao_step. */
+#define HCAO_STATIC_SCRATCH_BYTES (128u << 20)
+hcao_status hcao_step_static(hcao_ctx *ctx, double dt, uint32_t n_steps);
+
 /* Waits for the stream and returns the sticky device status. */
 hcao_status hcao_sync(hcao_ctx *ctx);
 

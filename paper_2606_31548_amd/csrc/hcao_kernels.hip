@@ -1672,17 +1672,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     }
     if (P.m_moved) stv<MIX>(A.st, gm, P.v_m);
     if (P.born) {
-      const uint64_t gb = H.base + k;
-      stv<MIX>(A.scratch, gb, P.nb_v);
-      A.scratch.sp[gb] = (uint8_t)P.nb_sp;
-      for (uint32_t m = 0; m < mm; ++m) A.scratch.lvl[m * A.scratch.stride + gb] = P.lvn[m * BLOCK];
+      const uint64_t gb = wbase + j;
+      stv<MIX>(A.born, gb, P.nb_v);
+      A.born.sp[gb] = (uint8_t)P.nb_sp;
+      for (uint32_t m = 0; m < mm; ++m) A.born.lvl[m * A.born.stride + gb] = P.lvn[m * BLOCK];
       if constexpr (EX >= 1) {
-        if (A.scratch.rot) A.scratch.rot[gb] = P.rn;
+        if (A.born.rot) A.born.rot[gb] = P.rn;
         if (A.st.px) {
           const uint64_t gs = P.nb_from ? gq : gp;
-          A.scratch.px[gb] = A.st.px[gs];
-          A.scratch.py[gb] = A.st.py[gs];
-          A.scratch.pz[gb] = A.st.pz[gs];
+          A.born.px[gb] = A.st.px[gs];
+          A.born.py[gb] = A.st.py[gs];
+          A.born.pz[gb] = A.st.pz[gs];
         }
       }
       bflag[j] = 1;
@@ -1756,17 +1756,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         const bool f = k < H.ncand && bflag[H.cstart + k] != 0;
         const unsigned long long m = __ballot(f);
         if (f) {
-          const uint64_t from = H.base + k, to = H.base + alive + done + (uint32_t)__popcll(m & lt);
-          stv<MIX>(A.st, to, ldv<MIX>(A.scratch, from));
-          A.st.sp[to] = A.scratch.sp[from];
+          const uint64_t from = wbase + H.cstart + k, to = H.base + alive + done + (uint32_t)__popcll(m & lt);
+          stv<MIX>(A.st, to, ldv<MIX>(A.born, from));
+          A.st.sp[to] = A.born.sp[from];
           for (uint32_t mo = 0; mo < mm; ++mo)
-            A.st.lvl[mo * A.st.stride + to] = A.scratch.lvl[mo * A.scratch.stride + from];
+            A.st.lvl[mo * A.st.stride + to] = A.born.lvl[mo * A.born.stride + from];
           if constexpr (EX >= 1) {
-            if (A.st.rot) A.st.rot[to] = A.scratch.rot[from];
+            if (A.st.rot) A.st.rot[to] = A.born.rot[from];
             if (A.st.px) {
-              A.st.px[to] = A.scratch.px[from];
-              A.st.py[to] = A.scratch.py[from];
-              A.st.pz[to] = A.scratch.pz[from];
+              A.st.px[to] = A.born.px[from];
+              A.st.py[to] = A.born.py[from];
+              A.st.pz[to] = A.born.pz[from];
             }
           }
         }
@@ -2827,6 +2827,15 @@ hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, int
   return mixed ? launch_step_t<true, 0>(a, lds, block, n_groups, s)
                : launch_step_t<false, 0>(a, lds, block, n_groups, s);
 }
+
+// Fixed device array for the allocation-free step (hcao_step_static): the
+// work lists, pair flags, pair energy defects and products staging of one
+// step call. Host code never passes the array's name to a kernel: it uses
+// the device address that static_scratch_address() returns for the current
+// device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_address(void **ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
 
 hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, step, n);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,7 @@ hipError_t launch_step(const StepArgs &a, size_t lds, int block, bool mixed, int
                        hipStream_t s);
 hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s);
+hipError_t static_scratch_address(void **ptr);
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,
                        const uint32_t *counts, const double *tt, const double *tv, uint64_t seed, uint32_t n_cells,
                        const uint32_t grid[3], const double len[3], hipStream_t s);
@@ -191,6 +193,29 @@ namespace {
 
 thread_local std::string g_create_error;  // failure text of the last hcao_create on this thread
 
+// Device address of the fixed scratch array of the allocation-free step, per
+// device: looked up once per device, with that device current, when the
+// first context is created on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+hipError_t lookup_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = static_scratch_address(&p);
+  if (e == hipSuccess) g_scratch_dev[device] = p;
+  return e;
+}
+
+void *static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 hcao_status fail(hcao_ctx *c, hcao_status s, const std::string &msg) {
   if (c) c->last_error = msg;
   return s;
@@ -325,7 +350,7 @@ State state_of(hcao_ctx *c) {
   return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->rot.p,
                c->px.p, c->py.p, c->pz.p, c->total_slots};
 }
-State scratch_of(hcao_ctx *c) {
+State staging_of(hcao_ctx *c) {
   return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->brot.p,
                c->bpx.p, c->bpy.p, c->bpz.p, c->total_slots};
 }
@@ -458,8 +483,6 @@ hcao_status build_groups(hcao_ctx *c) {
   return HCAO_OK;
 }
 
-// Allocates the state for per-cell counts; sets capacities, offsets and
-// the split between cells served from LDS tiles and from HBM.
 // the mover list and its sort buffers for up to n entries (movers plus
 // admissions), and the scan scratch for every scan of the re-bin
 hipError_t grow_list(hcao_ctx *c, uint64_t n) {
@@ -508,6 +531,8 @@ hipError_t grow_ins(hcao_ctx *c, uint64_t n) {
   return hipSuccess;
 }
 
+// Allocates the particle state and its products staging for per-cell counts
+// (capacities from caps, else the default headroom) and sets the offsets.
 hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
                         const std::vector<uint32_t> *caps = nullptr) {
   free_state(c);
@@ -801,6 +826,7 @@ hcao_status hcao_create(const hcao_config *cfg, hcao_ctx **out) {
   }
   const char *step = "hipSetDevice";
   hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = lookup_static_scratch(c->device), step = "hipGetSymbolAddress";
   if (e == hipSuccess) e = hipEventCreate(&c->ev0), step = "hipEventCreate";
   if (e == hipSuccess) e = hipEventCreate(&c->ev1), step = "hipEventCreate";
   if (e == hipSuccess) e = c->err.alloc(1), step = "hipMalloc";
@@ -1245,7 +1271,7 @@ StepArgs step_args(hcao_ctx *c, double dt) {
   a.tab = c->d_tab.p;
   a.lev = c->d_lev.p;
   a.st = state_of(c);
-  a.scratch = scratch_of(c);
+  a.born = staging_of(c);
   a.cells = cells_of(c);
   a.err = c->err.p;
   a.seed = c->cfg.seed;
@@ -1338,7 +1364,7 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   HIP_TRY(c, grow_list(c, movers + n_ins));
   RebinArgs r{};
   r.src = state_of(c);
-  r.dst = scratch_of(c);
+  r.dst = staging_of(c);
   r.ins = ins_state(c);
   r.tot = tot;
   r.off = c->off.p;
@@ -1395,8 +1421,50 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
 // (2), positions only (1), or neither (0)
 int step_level(const hcao_ctx *c) { return (c->has_exact || c->tab.has_rot) ? 2 : (c->spatial ? 1 : 0); }
 
+// Where one step call keeps its work lists, pair flags, pair energy defects
+// and products: the context's buffers, or the fixed device array.
+struct StepScratch {
+  uint32_t *work;
+  uint8_t *bflag;
+  double *wdef;
+  State born;
+};
+
+// Carves the allocation-free step's scratch out of the fixed array at base
+// (256-byte aligned pieces, products staged per work entry); returns the
+// bytes it needs.
+uint64_t static_layout(const hcao_ctx *c, unsigned char *base, StepScratch &out) {
+  const uint64_t w = c->work_entries;
+  const uint32_t mm = c->max_modes ? c->max_modes : 1;
+  uint64_t at = 0;
+  auto take = [&](uint64_t bytes) {
+    unsigned char *p = base + at;
+    at += (bytes + 255) & ~uint64_t(255);
+    return p;
+  };
+  out = StepScratch{};
+  out.work = reinterpret_cast<uint32_t *>(take(7 * w * sizeof(uint32_t)));
+  out.bflag = take(w);
+  if (c->mixed) out.wdef = reinterpret_cast<double *>(take(w * sizeof(double)));
+  State &b = out.born;
+  if (c->mixed) {
+    b.fx = reinterpret_cast<float *>(take(w * sizeof(float)));
+    b.fy = reinterpret_cast<float *>(take(w * sizeof(float)));
+    b.fz = reinterpret_cast<float *>(take(w * sizeof(float)));
+  } else {
+    b.vx = reinterpret_cast<double *>(take(w * sizeof(double)));
+    b.vy = reinterpret_cast<double *>(take(w * sizeof(double)));
+    b.vz = reinterpret_cast<double *>(take(w * sizeof(double)));
+  }
+  b.sp = take(w);
+  b.lvl = reinterpret_cast<uint16_t *>(take(w * mm * sizeof(uint16_t)));
+  if (c->tab.has_rot) b.rot = reinterpret_cast<double *>(take(w * sizeof(double)));
+  b.stride = w;
+  return at;
+}
+
 hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base, uint32_t *step_dev,
-                        hipStream_t s, uint32_t *launches) {
+                        hipStream_t s, uint32_t *launches, const StepScratch *sc = nullptr) {
   if (c->spatial) {
     // one collision launch per step, each after the move and re-bin
     for (uint32_t d = 0; d < n_steps; ++d) {
@@ -1410,6 +1478,12 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
     return HCAO_OK;
   }
   StepArgs a = step_args(c, dt);
+  if (sc) {
+    a.work = sc->work;
+    a.bflag = sc->bflag;
+    a.wdef = sc->wdef;
+    a.born = sc->born;
+  }
   a.step_dev = step_dev;
   uint32_t n = 0;
   for (uint32_t done = 0; done < n_steps;) {
@@ -1466,6 +1540,28 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
   if (hcao_status s = timing_begin(c)) return s;
   uint32_t launches = 0;
   if (hcao_status s = issue_steps(c, dt, n_steps, c->step, nullptr, c->stream, &launches)) return s;
+  c->step += n_steps;
+  return timing_end(c, launches, n_steps);
+}
+
+hcao_status hcao_step_static(hcao_ctx *c, double dt, uint32_t n_steps) {
+  if (hcao_status s = check_step_args(c, dt)) return s;
+  if (c->spatial)
+    return fail(c, HCAO_EUNSUPPORTED,
+                "the allocation-free step does not run the spatial mode (its re-bin needs buffers as large as the "
+                "state)");
+  unsigned char *base = static_cast<unsigned char *>(static_scratch(c->device));
+  if (!base) return fail(c, HCAO_ESTATE, "the fixed scratch array has no address on this device");
+  StepScratch sc;
+  const uint64_t need = static_layout(c, base, sc);
+  if (need > kStaticScratchBytes)
+    return fail(c, HCAO_ECAPACITY,
+                "the allocation-free step needs " + std::to_string(need) + " bytes of scratch for " +
+                    std::to_string(c->work_entries) + " work entries; the fixed device array holds " +
+                    std::to_string(kStaticScratchBytes));
+  if (hcao_status s = timing_begin(c)) return s;
+  uint32_t launches = 0;
+  if (hcao_status s = issue_steps(c, dt, n_steps, c->step, nullptr, c->stream, &launches, &sc)) return s;
   c->step += n_steps;
   return timing_end(c, launches, n_steps);
 }

@@ -61,6 +61,9 @@ constexpr uint32_t kExactBinHi = 15583u;
 constexpr uint32_t kExactBins = kExactBinHi - kExactBinLo + 1;
 constexpr uint32_t kExactNBeta = 960u;  // beta grid (1 + (j mod 16) / 16) 2^(40 + j div 16)
 
+// bytes of the fixed device array behind the allocation-free step
+constexpr uint64_t kStaticScratchBytes = HCAO_STATIC_SCRATCH_BYTES;
+
 constexpr uint32_t kRecNodes = 1024;
 constexpr double kRecTmin = 100.0;
 constexpr double kRecTmax = 5.0e4;
@@ -125,7 +128,7 @@ struct StepArgs {
   const Tables *tab;
   const double *lev;
   State st;
-  State scratch;  // products of the step, at the cell's base + pair index
+  State born;  // products of the step, at the workgroup's work base + candidate index
   CellArrays cells;
   const double *rec;   // recombination factors
   const double *beta;  // exact sampler's beta tables (PairTab::beta_off)

@@ -137,6 +137,7 @@ def load_library():
     L.hcao_set_launch_shape.argtypes = [_vp, ctypes.POINTER(hcao_launch_shape)]
     L.hcao_autotune.argtypes = [_vp, _d, _u32, ctypes.c_char_p, ctypes.POINTER(hcao_launch_shape)]
     L.hcao_step_graph.argtypes = [_vp, _d, _u32]
+    L.hcao_step_static.argtypes = [_vp, _d, _u32]
     L.hcao_read_cell_particles.argtypes = [_vp, _u32, _u32, _vp, _vp, _vp, ctypes.POINTER(_u32)]
     L.hcao_phase_clocks.argtypes = [_vp, _vp, _u32, ctypes.c_int]
     for name in ("hcao_create", "hcao_add_species", "hcao_add_reaction", "hcao_finalize", "hcao_load_particles",
@@ -146,7 +147,7 @@ def load_library():
                  "hcao_get_launch_shape", "hcao_set_launch_shape", "hcao_autotune", "hcao_step_graph",
                  "hcao_read_cell_particles", "hcao_get_exact_beta", "hcao_recombination_exact",
                  "hcao_read_rotational_energy", "hcao_set_domain", "hcao_read_positions", "hcao_set_inflow",
-                 "hcao_read_flux_counts", "hcao_phase_clocks"):
+                 "hcao_read_flux_counts", "hcao_phase_clocks", "hcao_step_static"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -306,6 +307,10 @@ class Simulation:
 
     def step(self, dt: float, n_steps: int = 1):
         self._chk("hcao_step", self._L.hcao_step(self._h, float(dt), int(n_steps)))
+
+    def step_static(self, dt: float, n_steps: int = 1):
+        """The allocation-free step (scratch in the library's fixed device array)."""
+        self._chk("hcao_step_static", self._L.hcao_step_static(self._h, float(dt), int(n_steps)))
 
     def step_graph(self, dt: float, n_steps: int = 1):
         """hcao_step through a captured hipGraph (captured on first use per (dt, n_steps))."""

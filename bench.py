@@ -363,8 +363,7 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
         "launch_shape": dict(sim.launch_shape(), graph=graph, autotuned=autotune),
         # particles admitted through and gone out of open faces in the timed steps
         "flux": {"admitted": flux1[0] - flux0[0], "left": flux1[1] - flux0[1]} if open_faces else None,
-        "phase_clock_shares": ({k: v / max(sum(clocks.values()), 1) for k, v in clocks.items()}
-                               if clocks else None),
+        "phase_clock_shares": phase_shares(clocks) if clocks else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_step", "bytes_per_launch": b_alg, "steps_per_launch": steps_per_launch,
@@ -372,6 +371,16 @@ def measure(hcao, torch, wl, precision, steps, warmup, spl, graph=False, autotun
     }
     sim.close()
     return r
+
+
+def phase_shares(clocks):
+    """Shares of the step kernel's phases (workgroup clocks) and, separately,
+    of the collision phase's parts (wave clocks)."""
+    step = {k: v for k, v in clocks.items() if not k.startswith("collide_")}
+    parts = {k: v for k, v in clocks.items() if k.startswith("collide_")}
+    out = {k: v / max(sum(step.values()), 1) for k, v in step.items()}
+    out.update({k: v / max(sum(parts.values()), 1) for k, v in parts.items()})
+    return out
 
 
 def copy_peak(torch, mib=1024, repeats=10):

@@ -376,8 +376,8 @@ hcao_status hcao_step_graph(hcao_ctx *ctx, double dt, uint32_t n_steps);
  * HCAO_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
  * until the process ends, not in the context's buffers. The call allocates
  * and frees nothing. Its need is about 30 + 3 b_v + 2 max_modes bytes per
- * work entry (b_v = 8 fp64, 4 mixed; 8 more in the mixed form and 8 more
- * with rotors; work entries = sum over cells of capacity / 2 + 1, e.g.
+ * work entry (b_v = 8 fp64, 4 mixed; 8 more in the mixed form, 8 more with
+ * rotors and 40 more with a recombination reaction; work entries = sum over cells of capacity / 2 + 1, e.g.
  * 725,000 for 4,096 cells of 256 particles at the default capacity, 52 MB
  * in fp64 for the methane species): a context that needs more
  * gets HCAO_ECAPACITY with the figure in hcao_last_error and nothing runs.
@@ -483,10 +483,13 @@ hcao_status hcao_kernel_time(hcao_ctx *ctx, double *ms, uint64_t *launches, uint
  * HCAO_N_PHASES, host array) receives the sums over all workgroups since the
  * last reset, in the order: launch loads, NTC counts and permutation keys,
  * cell temperature, candidate acceptance, work-list sort, collisions,
- * product placement, launch stores. The first call allocates the sums
+ * product placement, launch stores; then the collision phase per wave
+ * (summed over waves): gathering a pair's state, reaction decision,
+ * relaxation sampler, scattering and reaction application, write-back.
+ * The first call allocates the sums
  * (zero); reset != 0 zeroes them after reading. Synchronous on the
  * context's stream. */
-#define HCAO_N_PHASES 8
+#define HCAO_N_PHASES 13
 hcao_status hcao_phase_clocks(hcao_ctx *ctx, uint64_t *out, uint32_t n, int reset);
 
 /* Checkpoint of the full state (particles, per-cell state, step index). */

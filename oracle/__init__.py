@@ -113,6 +113,7 @@ def lib():
         L.orc_forward_probability.argtypes = [vp, u32, u32, d]; L.orc_forward_probability.restype = d
         L.orc_rec_node_temperature.argtypes = [vp, u32]; L.orc_rec_node_temperature.restype = d
         L.orc_cell_temperature.argtypes = [vp, u32]; L.orc_cell_temperature.restype = d
+        L.orc_cell_sums.argtypes = [vp, u32, ctypes.c_int, vp]; L.orc_cell_sums.restype = ctypes.c_int
         L.orc_draw_unit_vectors.argtypes = [u64, u32, vp]; L.orc_draw_unit_vectors.restype = None
         L.orc_draw_three_body_shares.argtypes = [u64, u32, vp]; L.orc_draw_three_body_shares.restype = None
         for name in ("orc_create", "orc_add_species", "orc_add_reaction", "orc_finalize", "orc_load",
@@ -426,6 +427,11 @@ class Oracle:
 
     def cell_temperature(self, cell):
         return lib().orc_cell_temperature(self._h, int(cell))
+
+    def cell_sums(self, cell, direct=False):
+        out = np.zeros(5, np.float64)
+        _chk("orc_cell_sums", lib().orc_cell_sums(self._h, int(cell), int(direct), _p(out)))
+        return out
 
     def rec_table(self, reaction):
         out = np.zeros(self.n_species * 1024, np.float64)

@@ -300,6 +300,9 @@ typedef struct {
   double *rot;   /* rotational energy [J] */
   double *px, *py, *pz; /* positions [m] (spatial mode) */
   double volume, weight, sgmax, rem;
+  /* recombination: running sums of m, m v_x, m v_y, m v_z, m |v|^2 over the
+   * cell's particles, from which the step takes the cell temperature */
+  double tsum[5];
   uint64_t ctr[ORC_N_CTR];
 } cell_t;
 
@@ -325,6 +328,7 @@ struct orc_ctx {
 };
 
 static void reset_inflow(orc_ctx *o);
+static void init_sums(const orc_ctx *o, cell_t *C);
 
 static double mode_energy(const species_t *s, uint32_t m, uint32_t i) {
   if (m < s->n_bend) return ((double)i + 0.5) * s->kt[m];
@@ -1187,7 +1191,10 @@ int orc_load(orc_ctx *o, uint64_t n, const uint32_t *cell, const uint8_t *specie
     }
     for (uint32_t m = 0; m < mm; ++m) c->lvl[(size_t)j * mm + m] = levels[(size_t)i * mm + m];
   }
-  for (uint32_t c = 0; c < o->n_cells; ++c) init_sgmax(o, &o->cells[c]);
+  for (uint32_t c = 0; c < o->n_cells; ++c) {
+    init_sgmax(o, &o->cells[c]);
+    init_sums(o, &o->cells[c]);
+  }
   o->step = 0;
   o->loaded = 1;
   reset_inflow(o);
@@ -1305,6 +1312,7 @@ int orc_init_thermal(orc_ctx *o, const uint32_t *counts, const double *t_trans, 
     }
     C->n = n;
     init_sgmax(o, C);
+    init_sums(o, C);
   }
   o->step = 0;
   o->loaded = 1;
@@ -1665,6 +1673,7 @@ typedef struct {
   double pos[2][3];
   int dead[2];
   int has_m;   /* a third body is available for recombination */
+  int m_moved; /* the third body took part (recombination) */
   uint8_t sp_m;
   double v_m[3];
   double t_cell, n_cell;
@@ -1754,6 +1763,7 @@ static int collide(const orc_ctx *o, pair_state *ps, double g2, stream *st, uint
     split(pam, vcm, et, st, va, vm);
     memcpy(ps->v[b], va, sizeof(va));
     memcpy(ps->v_m, vm, sizeof(vm));
+    ps->m_moved = 1;
     ps->sp[b] = (uint8_t)R->c;
     memcpy(ps->lvl[b], la, sizeof(la));
     ps->rot[b] = A->zeta_rot > 0 ? rsum : 0.0;
@@ -2007,18 +2017,13 @@ static void store_pair(cell_t *C, uint32_t mm, uint32_t p, uint32_t q, const pai
   }
 }
 
-/* Translational temperature of a cell at step start, T = (sum m |v|^2 -
- * |sum m v|^2 / sum m) / (3 k N): the sum of m |v - u|^2 about the
- * mass-weighted mean velocity u over 3 k N. Summation order (fixed, so that
- * every implementation rounds alike): partial sum t (t = 0..63) takes the
- * particles t, t + 64, t + 128, ... in slot order; the 64 partial sums are
- * then combined by a halving tree (sum t adds sum t + s for s = 32, 16, ...,
- * 1). */
-static double cell_temperature(const orc_ctx *o, const cell_t *C) {
+/* Sums of m, m v_x, m v_y, m v_z and m |v|^2 over a cell's particles (m the
+ * particle's mass). Summation order (fixed, so that every implementation
+ * rounds alike): partial sum t (t = 0..63) takes the particles t, t + 64,
+ * t + 128, ... in slot order; the 64 partial sums are then combined by a
+ * halving tree (sum t adds sum t + s for s = 32, 16, ..., 1). */
+static void cell_sums(const orc_ctx *o, const cell_t *C, double out[5]) {
   uint32_t n = C->n;
-  if (n < 2) return 0.0;
-  /* 64 partial sums: sum t takes particles t, t + 64, t + 128, ... in slot
-   * order; then a halving tree (sum t adds sum t + s for s = 32, ..., 1) */
   double x[5][64];
   for (int t = 0; t < 64; ++t) {
     for (int q = 0; q < 5; ++q) x[q][t] = 0.0;
@@ -2035,13 +2040,49 @@ static double cell_temperature(const orc_ctx *o, const cell_t *C) {
   for (int sft = 32; sft >= 1; sft >>= 1)
     for (int t = 0; t < sft; ++t)
       for (int q = 0; q < 5; ++q) x[q][t] = x[q][t] + x[q][t + sft];
-  double p2 = (x[1][0] * x[1][0] + x[2][0] * x[2][0]) + x[3][0] * x[3][0];
-  return (x[4][0] - p2 / x[0][0]) / (3.0 * K_BOLTZ * (double)n);
+  for (int q = 0; q < 5; ++q) out[q] = x[q][0];
+}
+
+/* The running sums start from the particles whenever a cell's particles are
+ * placed (load, thermal initial state, every re-bin of the spatial mode) and
+ * then follow each step's collisions (see step_cell). */
+static void init_sums(const orc_ctx *o, cell_t *C) {
+  if (o->has_recomb) cell_sums(o, C, C->tsum);
+}
+
+/* Translational temperature of a cell at step start from its running sums,
+ * T = (sum m |v|^2 - |sum m v|^2 / sum m) / (3 k N): the sum of m |v - u|^2
+ * about the mass-weighted mean velocity u over 3 k N (0 below two particles). */
+static double cell_temperature(const orc_ctx *o, const cell_t *C) {
+  (void)o;
+  uint32_t n = C->n;
+  if (n < 2) return 0.0;
+  const double *s = C->tsum;
+  double p2 = (s[1] * s[1] + s[2] * s[2]) + s[3] * s[3];
+  return (s[4] - p2 / s[0]) / (3.0 * K_BOLTZ * (double)n);
+}
+
+/* adds one particle's five terms (m, m v, m |v|^2) to acc, in that order */
+static void add_terms(double acc[5], double m, const double v[3]) {
+  acc[0] = acc[0] + m;
+  acc[1] = acc[1] + m * v[0];
+  acc[2] = acc[2] + m * v[1];
+  acc[3] = acc[3] + m * v[2];
+  acc[4] = acc[4] + m * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
 }
 
 double orc_cell_temperature(const orc_ctx *o, uint32_t cell) {
   if (!o || cell >= o->n_cells) return -1.0;
   return cell_temperature(o, &o->cells[cell]);
+}
+
+int orc_cell_sums(const orc_ctx *o, uint32_t cell, int direct, double *out5) {
+  if (!o || cell >= o->n_cells || !out5) return E_INVAL;
+  if (direct)
+    cell_sums(o, &o->cells[cell], out5);
+  else
+    memcpy(out5, o->cells[cell].tsum, 5 * sizeof(double));
+  return E_OK;
 }
 
 static int step_cell(orc_ctx *o, uint32_t c, double dt) {
@@ -2064,9 +2105,18 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     orc_philox4x32_10((uint32_t)o->seed, (uint32_t)(o->seed >> 32), ctr, keys + 4 * blk);
   }
   newborn *nb = NULL;
+  double *dsum = NULL;    /* recombination: each pair's change of the running sums */
+  uint8_t *moved = NULL;  /* the pair collided */
   if (ncand > 0) {
     nb = (newborn *)calloc(ncand, sizeof(newborn));
-    if (!nb) return E_NOMEM;
+    dsum = (double *)calloc((size_t)ncand * 5, sizeof(double));
+    moved = (uint8_t *)calloc(ncand, 1);
+    if (!nb || !dsum || !moved) {
+      free(nb);
+      free(dsum);
+      free(moved);
+      return E_NOMEM;
+    }
   }
   double t_cell = o->has_recomb ? cell_temperature(o, C) : 0.0;
   double n_cell = (double)n * C->weight / C->volume;
@@ -2087,6 +2137,7 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     C->ctr[ORC_CTR_COLLISIONS] += 1;
     pair_state ps;
     load_pair(C, mm, p, q, &ps);
+    ps.m_moved = 0;
     /* third body of pair k: the particle at permutation index 2 N_cand + k */
     uint32_t mslot = 0;
     if (2 * ncand + k < n) {
@@ -2099,7 +2150,26 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     }
     ps.t_cell = t_cell;
     ps.n_cell = n_cell;
+    double before[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, vm_before[3] = {ps.v_m[0], ps.v_m[1], ps.v_m[2]};
+    uint8_t sp_before[2] = {ps.sp[0], ps.sp[1]};
+    double v_before[2][3];
+    memcpy(v_before, ps.v, sizeof(v_before));
     collide(o, &ps, g2, &st, C->ctr, &nb[k]);
+    if (o->has_recomb) {
+      /* this pair's change of the running sums: its particles after the
+       * collision (p, q, the third body if it took part, the newborn) minus
+       * before (p, q, the third body if it took part) */
+      add_terms(before, o->sp[sp_before[0]].mass, v_before[0]);
+      add_terms(before, o->sp[sp_before[1]].mass, v_before[1]);
+      if (ps.m_moved) add_terms(before, o->sp[ps.sp_m].mass, vm_before);
+      double after[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      if (!ps.dead[0]) add_terms(after, o->sp[ps.sp[0]].mass, ps.v[0]);
+      if (!ps.dead[1]) add_terms(after, o->sp[ps.sp[1]].mass, ps.v[1]);
+      if (ps.m_moved) add_terms(after, o->sp[ps.sp_m].mass, ps.v_m);
+      if (nb[k].born) add_terms(after, o->sp[nb[k].sp].mass, nb[k].v);
+      for (int qq = 0; qq < 5; ++qq) dsum[(size_t)k * 5 + qq] = after[qq] - before[qq];
+      moved[k] = 1;
+    }
     store_pair(C, mm, p, q, &ps);
     if (ps.has_m) {
       C->vx[mslot] = ps.v_m[0];
@@ -2131,6 +2201,8 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
   for (uint32_t k = 0; k < ncand; ++k) births += (uint32_t)nb[k].born;
   if (alive + births > C->cap) {
     free(nb);
+    free(dsum);
+    free(moved);
     return E_CAPACITY;
   }
   for (uint32_t k = 0; k < ncand; ++k) {
@@ -2148,7 +2220,26 @@ static int step_cell(orc_ctx *o, uint32_t c, double dt) {
     }
     for (uint32_t m = 0; m < mm; ++m) C->lvl[(size_t)j * mm + m] = nb[k].lvl[m];
   }
+  if (o->has_recomb) {
+    /* running sums: the pairs' changes over chunks of 64 consecutive
+     * candidates (left to right), each chunk reduced by a halving tree; a
+     * candidate that did not collide contributes 0 */
+    double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint64_t k0 = 0; k0 < ncand; k0 += 64) {
+      double x[5][64];
+      for (int t = 0; t < 64; ++t)
+        for (int qq = 0; qq < 5; ++qq)
+          x[qq][t] = (k0 + t < ncand && moved[k0 + t]) ? dsum[(size_t)(k0 + t) * 5 + qq] : 0.0;
+      for (int sft = 32; sft >= 1; sft >>= 1)
+        for (int t = 0; t < sft; ++t)
+          for (int qq = 0; qq < 5; ++qq) x[qq][t] = x[qq][t] + x[qq][t + sft];
+      for (int qq = 0; qq < 5; ++qq) d[qq] = d[qq] + x[qq][0];
+    }
+    for (int qq = 0; qq < 5; ++qq) C->tsum[qq] = C->tsum[qq] + d[qq];
+  }
   free(nb);
+  free(dsum);
+  free(moved);
   if (sg_seen > C->sgmax) C->sgmax = sg_seen;
   return E_OK;
 }
@@ -2368,6 +2459,7 @@ int orc_step(orc_ctx *o, double dt, uint32_t n_steps) {
     if (o->spatial) {
       int rc = move_and_rebin(o, dt);
       if (rc) return rc;
+      for (uint32_t c = 0; c < o->n_cells; ++c) init_sums(o, &o->cells[c]);
     }
     /* cells are independent (per-cell state, per-cell streams), so threads
      * over cells give the same result as one thread */

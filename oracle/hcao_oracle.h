@@ -137,8 +137,12 @@ double orc_equilibrium_constant(const orc_ctx *o, uint32_t reaction, double t);
 double orc_forward_rate(const orc_ctx *o, uint32_t reaction, uint32_t third, double t);
 double orc_forward_probability(const orc_ctx *o, uint32_t reaction, uint32_t third, double t);
 double orc_rec_node_temperature(const orc_ctx *o, uint32_t i);
-/* translational temperature of a cell as the step computes it */
+/* translational temperature of a cell as the next step takes it (from the
+ * cell's running sums); the sums themselves (m, m v_x, m v_y, m v_z,
+ * m |v|^2): running (direct = 0) or summed afresh over the particles
+ * (direct = 1) */
 double orc_cell_temperature(const orc_ctx *o, uint32_t cell);
+int orc_cell_sums(const orc_ctx *o, uint32_t cell, int direct, double *out5);
 /* draw i of n from the stream (seed; pair i, cell 0, step 0): scattering
  * unit vectors (out[3 n]) and the three-body energy share (out[n]) */
 void orc_draw_unit_vectors(uint64_t seed, uint32_t n, double *out);

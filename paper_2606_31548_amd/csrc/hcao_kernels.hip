@@ -36,9 +36,20 @@ constexpr uint8_t kDead = 255;  // species byte of a particle removed by recombi
       clk_t = t_;                        \
     }                                    \
   } while (0)
+// per-wave marks inside the collision phase: every active lane reads the
+// (wave-uniform) clock, the leading active lane of the wave keeps the sums
+#define HCAO_WAVE_MARK(acc, k)           \
+  do {                                   \
+    const uint64_t t_ = clock64();       \
+    (acc)[(k) - kPhaseCollideGather] += t_ - (acc##_t); \
+    acc##_t = t_;                        \
+  } while (0)
 #else
 #define HCAO_PHASE_MARK(k) \
   do {                     \
+  } while (0)
+#define HCAO_WAVE_MARK(acc, k) \
+  do {                         \
   } while (0)
 #endif
 
@@ -778,6 +789,9 @@ struct PairLocal {
   double rec_f;
   double r0, r1, rn;  // rotational energies of p, q and the product (rotors only)
   uint32_t nb_from;   // side (0: p, 1: q) whose position the product takes
+#ifdef HCAO_PHASE_CLOCKS
+  uint64_t wclk[5], wclk_t;  // collision sub-phase clocks of instrumented builds
+#endif
 };
 
 __device__ __forceinline__ double vib_local(const Tab &T, uint32_t sp, const uint16_t *lv, uint32_t ls) {
@@ -1038,6 +1052,7 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
     }
   }
 
+  HCAO_WAVE_MARK(P.wclk, kPhaseCollideDecide);
   // --- queue the relaxations (at most two, in draw order) ---
   uint16_t *lvj0 = nullptr, *lvj1 = nullptr;
   uint32_t spj0 = 0, spj1 = 0;
@@ -1135,6 +1150,7 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   if (nrel) atomicAdd(&C.ctr[HCAO_CTR_RELAX], (unsigned long long)nrel);
   if (ncap) atomicAdd(&C.ctr[HCAO_CTR_CAPPED], (unsigned long long)ncap);
 
+  HCAO_WAVE_MARK(P.wclk, kPhaseCollideRelax);
   // --- rotational relaxation of each rotor in turn (non-reactive collisions) ---
   if constexpr (EX) {
     if (kind == 0) {
@@ -1235,13 +1251,14 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   return rx;
 }
 
-// Translational temperature of a cell by one wave: lane t sums particles
-// t, t + 64, t + 128, ... in slot order (loads of four blocks issued
-// together), then a halving tree (lane t takes lane t + s for s = 32, ...,
-// 1) combines the 64 partial sums.
+// Sums of m, m v_x, m v_y, m v_z and m |v|^2 over a cell's particles by one
+// wave: lane t sums particles t, t + 64, t + 128, ... in slot order (loads
+// of four blocks issued together), then a halving tree (lane t takes lane
+// t + s for s = 32, ..., 1) combines the 64 partial sums; lane 0 returns
+// them. The running sums of the cell temperature start from these.
 template <bool MIX>
-__device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint64_t base, uint32_t n, uint32_t lane) {
-  if (n < 2) return 0.0;
+__device__ void cell_sums(const State &st, const SpeciesTab *spt, uint64_t base, uint32_t n, uint32_t lane,
+                          double out[5]) {
   constexpr int U = 4;
   double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0;
   for (uint32_t b0 = 0; b0 < n; b0 += 64 * U) {
@@ -1278,8 +1295,22 @@ __device__ double cell_temperature(const State &st, const SpeciesTab *spt, uint6
     x3 = x3 + __shfl_down(x3, s);
     x4 = x4 + __shfl_down(x4, s);
   }
-  const double p2 = (x1 * x1 + x2 * x2) + x3 * x3;
-  return (x4 - p2 / x0) / (3.0 * kBoltz * (double)n);
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+  out[4] = x4;
+}
+
+// adds one particle's terms m, m v, m |v|^2 to acc (in that order)
+template <typename R>
+__device__ __forceinline__ void add_terms(double acc[5], double m, V3<R> v) {
+  const double x = v.x, y = v.y, z = v.z;
+  acc[0] = acc[0] + m;
+  acc[1] = acc[1] + m * x;
+  acc[2] = acc[2] + m * y;
+  acc[3] = acc[3] + m * z;
+  acc[4] = acc[4] + m * ((x * x + y * y) + z * z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1293,6 +1324,7 @@ struct CellHdr {
   double sgmax, rem, volume, weight;
   double rem_new, n_cell, rec_f;
   double defect;  // mixed form: energy the cell's particles lack
+  double tsum[5];  // recombination: running sums m, m v, m |v|^2 of the cell's particles
   int32_t rec_i, pad2;
   unsigned long long sgbits, excess;
   Perm perm;
@@ -1391,11 +1423,26 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     H.volume = A.cells.volume[c];
     H.weight = A.cells.weight[c];
     H.defect = MIX ? A.cells.defect[c] : 0.0;
+    if (A.cells.tsum)
+      for (int q = 0; q < 5; ++q) H.tsum[q] = A.cells.tsum[(size_t)q * A.cells.n_cells + c];
+  }
+  if constexpr (EX >= 1) {
+    // spatial mode: the particles were re-binned since the last step, so the
+    // running sums start afresh from them (one wave per cell)
+    if (A.cells.tsum && A.st.px) {
+      __syncthreads();
+      for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
+        double sums[5];
+        cell_sums<MIX>(A.st, GT->sp, hdr[g].base, hdr[g].n, lane, sums);
+        if (lane == 0)
+          for (int q = 0; q < 5; ++q) hdr[g].tsum[q] = sums[q];
+      }
+    }
   }
   const Tab T{l_sp, l_pr, l_rx, l_lev, A.beta, ns, nr, mm, GT->rec_nt};
   const uint32_t wcap = (uint32_t)(A.grp_work[2 * blockIdx.x + 1] - wbase);
-  uint32_t *work_in = A.work + 7 * wbase;           // accepted pairs as found: (j, p, q, key)
-  uint32_t *work = work_in + 4 * (size_t)wcap;      // the same sorted by key: (j, p, q)
+  uint32_t *work_in = A.work + (size_t)kWorkWords * wbase;  // accepted pairs as found
+  uint32_t *work = work_in + (size_t)kWorkFound * wcap;       // the same sorted by key
   uint8_t *bflag = A.bflag + wbase;
   double *wdef = MIX ? A.wdef + wbase : nullptr;
   __syncthreads();
@@ -1427,34 +1474,26 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     H.sgbits = 0ull;
     H.excess = excess;
     if (ncand > 0) make_perm(H.perm, n, A.seed, H.cell, step);
-  }
-  __syncthreads();
-  HCAO_PHASE_MARK(kPhaseNtc);
-  if (GT->has_recomb) {
-    // cell temperature and its recombination-table coordinate (one wave per cell)
-    for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
-      CellHdr &H = hdr[g];
-      const double t = cell_temperature<MIX>(A.st, l_sp, H.base, H.n, lane);
-      if (lane == 0) {
-        int32_t ri = -1;
-        double rf = 0.0;
-        if (t > 0.0) {
-          const double u = (dlog(t) - GT->rec_l0) * GT->rec_inv_step;
-          if (!(u > 0.0)) {
-            ri = -1;
-          } else if (!(u < (double)(GT->rec_nt - 1))) {
-            ri = -2;
-          } else {
-            const double fi = floor(u);
-            ri = (int32_t)fi;
-            rf = u - fi;
-          }
+    if (GT->has_recomb && n >= 2) {
+      // cell temperature from the running sums and its recombination-table coordinate
+      const double p2 = (H.tsum[1] * H.tsum[1] + H.tsum[2] * H.tsum[2]) + H.tsum[3] * H.tsum[3];
+      const double t = (H.tsum[4] - p2 / H.tsum[0]) / (3.0 * kBoltz * (double)n);
+      if (t > 0.0) {
+        const double u = (dlog(t) - GT->rec_l0) * GT->rec_inv_step;
+        if (!(u > 0.0)) {
+          H.rec_i = -1;
+        } else if (!(u < (double)(GT->rec_nt - 1))) {
+          H.rec_i = -2;
+        } else {
+          const double fi = floor(u);
+          H.rec_i = (int32_t)fi;
+          H.rec_f = u - fi;
         }
-        H.rec_i = ri;
-        H.rec_f = rf;
       }
     }
   }
+  __syncthreads();
+  HCAO_PHASE_MARK(kPhaseNtc);
   if (tid == 0) {
     uint32_t acc = 0;
     for (uint32_t g = 0; g < ncell; ++g) {
@@ -1476,7 +1515,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   for (uint32_t j0 = 0; j0 < total; j0 += BLOCK) {
     const uint32_t j = j0 + tid;
     bool acc = false;
-    uint32_t pj = 0, qj = 0, key = 0;
+    uint32_t pj = 0, qj = 0, key = 0, rw1 = 0, rw2 = 0, rw3 = 0;
     if (j < total) {
       const uint32_t g = group_cell(hdr, ncell, j);
       const CellHdr &H = hdr[g];
@@ -1495,6 +1534,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       RngT<MIX> rng;
       rng.open(A.seed, k, H.cell, step);
       const R ua = draw<MIX>(rng);
+      // the rest of the pair stream's first block, handed to the collision pass
+      rw1 = rng.w1;
+      rw2 = rng.w2;
+      rw3 = rng.w3;
       bflag[j] = 0;
       // VHS acceptance ua < sigma g / (sigma g)_max with sigma g = C (g^2)^(1-w).
       if constexpr (MIX) {
@@ -1530,11 +1573,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     if (lane == 0 && ma) wb = atomicAdd(&s_nwork, (uint32_t)__popcll(ma));
     wb = __shfl(wb, 0);
     if (acc) {
-      const uint32_t slot = wb + (uint32_t)__popcll(ma & lt);
-      work_in[4 * slot] = j;
-      work_in[4 * slot + 1] = pj;
-      work_in[4 * slot + 2] = qj;
-      work_in[4 * slot + 3] = key;
+      uint32_t *w = work_in + (size_t)kWorkFound * (wb + (uint32_t)__popcll(ma & lt));
+      w[0] = j;
+      w[1] = pj;
+      w[2] = qj;
+      w[3] = key;
+      w[4] = rw1;
+      w[5] = rw2;
+      w[6] = rw3;
     }
   }
   __syncthreads();
@@ -1544,7 +1590,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   const uint32_t nwork = s_nwork;
   for (uint32_t i = tid; i < 256; i += BLOCK) s_bin[i] = 0;
   __syncthreads();
-  for (uint32_t i = tid; i < nwork; i += BLOCK) atomicAdd(&s_bin[work_in[4 * i + 3]], 1u);
+  for (uint32_t i = tid; i < nwork; i += BLOCK) atomicAdd(&s_bin[work_in[kWorkFound * i + 3]], 1u);
   __syncthreads();
   if (tid < 64) {
     // exclusive scan of the 256 bins, four per lane
@@ -1563,22 +1609,34 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   }
   __syncthreads();
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
-    const uint32_t pos = atomicAdd(&s_bin[work_in[4 * i + 3]], 1u);
-    work[3 * pos] = work_in[4 * i];
-    work[3 * pos + 1] = work_in[4 * i + 1];
-    work[3 * pos + 2] = work_in[4 * i + 2];
+    const uint32_t *f = work_in + (size_t)kWorkFound * i;
+    uint32_t *w = work + (size_t)kWorkSorted * atomicAdd(&s_bin[f[3]], 1u);
+    w[0] = f[0];
+    w[1] = f[1];
+    w[2] = f[2];
+    w[3] = f[4];
+    w[4] = f[5];
+    w[5] = f[6];
   }
   __syncthreads();
   HCAO_PHASE_MARK(kPhaseSort);
 
   // ---- phase B: one accepted pair per lane ----
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
-    const uint32_t j = work[3 * i], p = work[3 * i + 1], qq = work[3 * i + 2];
+#ifdef HCAO_PHASE_CLOCKS
+    PairLocal<MIX> P;
+    for (int x = 0; x < 5; ++x) P.wclk[x] = 0;
+    P.wclk_t = clock64();
+    const bool lead = lane == (uint32_t)(__ffsll((long long)__ballot(1)) - 1);
+#else
+    PairLocal<MIX> P;
+#endif
+    const uint32_t *wi = work + (size_t)kWorkSorted * i;
+    const uint32_t j = wi[0], p = wi[1], qq = wi[2];
     const uint32_t g = group_cell(hdr, ncell, j);
     const CellHdr &H = hdr[g];
     const uint32_t k = j - H.cstart;
     const uint64_t gp = H.base + p, gq = H.base + qq;
-    PairLocal<MIX> P;
     P.v0 = ldv<MIX>(A.st, gp);
     P.v1 = ldv<MIX>(A.st, gq);
     P.sp0 = A.st.sp[gp];
@@ -1588,10 +1646,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     P.lv0 = plv + tid;
     P.lv1 = plv + (size_t)mm * BLOCK + tid;
     P.lvn = plv + (size_t)2 * mm * BLOCK + tid;
-    for (uint32_t m = 0; m < mm; ++m) {
-      P.lv0[m * BLOCK] = A.st.lvl[m * A.st.stride + gp];
-      P.lv1[m * BLOCK] = A.st.lvl[m * A.st.stride + gq];
-    }
+    // quantum numbers of the species' own modes (the others are 0 in the state
+    // and nothing reads them here)
+    const uint32_t nm0 = T.sp[P.sp0].n_modes, nm1 = T.sp[P.sp1].n_modes;
+    for (uint32_t m = 0; m < nm0; ++m) P.lv0[m * BLOCK] = A.st.lvl[m * A.st.stride + gp];
+    for (uint32_t m = 0; m < nm1; ++m) P.lv1[m * BLOCK] = A.st.lvl[m * A.st.stride + gq];
     P.r0 = P.r1 = P.rn = 0.0;
     if constexpr (EX >= 2) {
       if (A.st.rot) {
@@ -1601,7 +1660,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     }
     P.has_m = false;
     uint64_t gm = 0;
-    if (GT->has_recomb && 2 * H.ncand + k < H.n) {
+    if ((T.pair(P.sp0, P.sp1).react & kReactRecomb) && 2 * H.ncand + k < H.n) {
       // third body of pair k: the particle at permutation index 2 N_cand + k
       PermReg perm;
       perm.load(H.perm);
@@ -1619,7 +1678,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     const double g2 = (dx * dx + dy * dy) + dz * dz;
     RngT<MIX> rng;
     rng.open(A.seed, k, H.cell, step);
-    (void)draw<MIX>(rng);  // the acceptance draw of phase A
+    // resume after the acceptance draw of phase A: its block's other words
+    rng.block = 1;
+    rng.w1 = wi[3];
+    rng.w2 = wi[4];
+    rng.w3 = wi[5];
+    rng.used = MIX ? 1u : 2u;
     unsigned long long *ctr = l_ctr + (size_t)g * nctr;
     atomicAdd(&ctr[HCAO_CTR_COLLISIONS], 1ull);
     Ctx C{T, ctr, scr, tid, BLOCK};
@@ -1635,7 +1699,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (P.has_m) mm3 = T.sp[P.sp_m].mass;  // joins the sums only if the third body takes part
     }
     const Vec3 vm_in = P.has_m ? Vec3{(double)P.v_m.x, (double)P.v_m.y, (double)P.v_m.z} : Vec3{0.0, 0.0, 0.0};
+    // recombination: the pair's terms of its cell's running sums before the collision
+    const uint32_t sp_in0 = P.sp0, sp_in1 = P.sp1;
+    const V3<R> v_in0 = P.v0, v_in1 = P.v1;
+    HCAO_WAVE_MARK(P.wclk, kPhaseCollideGather);
     collide<MIX, (EX >= 2)>(C, P, g2, rng, A.rec, (MIX && k == 0) ? H.defect : 0.0);
+    HCAO_WAVE_MARK(P.wclk, kPhaseCollideScatter);
     if constexpr (MIX) {
       // Energy audit of the fp32 kinematics: the scattering intends the
       // kinetic energy of the total centre-of-mass motion plus the
@@ -1656,13 +1725,33 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (P.m_moved) ke_out = ke_out + kinetic(T.sp[P.sp_m].mass, P.v_m);
       wdef[j] = (ke_int - ke_out) - P.fold_used;
     }
+    if (A.tdelta) {
+      // the pair's change of its cell's running sums: its particles after
+      // (p, q, the recoiling third body, the product) minus before (p, q,
+      // the third body if it took part)
+      double before[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, after[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      add_terms(before, T.sp[sp_in0].mass, v_in0);
+      add_terms(before, T.sp[sp_in1].mass, v_in1);
+      if (P.m_moved) add_terms(before, T.sp[P.sp_m].mass, vm_in);
+      if (!P.dead0) add_terms(after, T.sp[P.sp0].mass, P.v0);
+      if (!P.dead1) add_terms(after, T.sp[P.sp1].mass, P.v1);
+      if (P.m_moved) add_terms(after, T.sp[P.sp_m].mass, P.v_m);
+      if (P.born) add_terms(after, T.sp[P.nb_sp].mass, P.nb_v);
+      for (int x = 0; x < 5; ++x) A.tdelta[(size_t)x * A.tdelta_stride + wbase + j] = after[x] - before[x];
+    }
     stv<MIX>(A.st, gp, P.v0);
     stv<MIX>(A.st, gq, P.v1);
     A.st.sp[gp] = P.dead0 ? (uint8_t)kDead : (uint8_t)P.sp0;
     A.st.sp[gq] = P.dead1 ? (uint8_t)kDead : (uint8_t)P.sp1;
-    for (uint32_t m = 0; m < mm; ++m) {
-      A.st.lvl[m * A.st.stride + gp] = P.lv0[m * BLOCK];
-      A.st.lvl[m * A.st.stride + gq] = P.lv1[m * BLOCK];
+    // the new species' modes, and zeros over the modes only the old species had
+    // (a removed particle's levels are not kept)
+    if (!P.dead0) {
+      const uint32_t nn = T.sp[P.sp0].n_modes, top = nn > nm0 ? nn : nm0;
+      for (uint32_t m = 0; m < top; ++m) A.st.lvl[m * A.st.stride + gp] = m < nn ? P.lv0[m * BLOCK] : (uint16_t)0;
+    }
+    if (!P.dead1) {
+      const uint32_t nn = T.sp[P.sp1].n_modes, top = nn > nm1 ? nn : nm1;
+      for (uint32_t m = 0; m < top; ++m) A.st.lvl[m * A.st.stride + gq] = m < nn ? P.lv1[m * BLOCK] : (uint16_t)0;
     }
     if constexpr (EX >= 2) {
       if (A.st.rot) {
@@ -1685,8 +1774,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           A.born.pz[gb] = A.st.pz[gs];
         }
       }
-      bflag[j] = 1;
     }
+    bflag[j] = (uint8_t)((P.born ? kFlagBorn : 0) | kFlagCollided);
+    HCAO_WAVE_MARK(P.wclk, kPhaseCollideWrite);
+#ifdef HCAO_PHASE_CLOCKS
+    if (lead && A.clk)
+      for (int x = 0; x < 5; ++x) atomicAdd(&A.clk[kPhaseCollideGather + x], (unsigned long long)P.wclk[x]);
+#endif
   }
   __syncthreads();
   HCAO_PHASE_MARK(kPhaseCollide);
@@ -1753,7 +1847,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       uint32_t done = 0;
       for (uint32_t k0 = 0; k0 < H.ncand; k0 += 64) {
         const uint32_t k = k0 + lane;
-        const bool f = k < H.ncand && bflag[H.cstart + k] != 0;
+        const bool f = k < H.ncand && (bflag[H.cstart + k] & kFlagBorn) != 0;
         const unsigned long long m = __ballot(f);
         if (f) {
           const uint64_t from = wbase + H.cstart + k, to = H.base + alive + done + (uint32_t)__popcll(m & lt);
@@ -1773,15 +1867,33 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         done += (uint32_t)__popcll(m);
       }
     }
-    double dsum = 0.0;
-    if constexpr (MIX) {
-      // energy defects of the cell's pairs, summed in pair order
+    // Per-pair records of the cell, over chunks of 64 consecutive candidates
+    // (left to right), each chunk reduced by a halving tree: the mixed
+    // form's energy defects, and the changes of the running sums (a
+    // candidate that did not collide contributes 0). A chunk's loads are all
+    // issued before any is used.
+    double dsum = 0.0, d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (MIX || A.tdelta) {
       for (uint32_t k0 = 0; k0 < H.ncand; k0 += 64) {
         const uint32_t k = k0 + lane;
-        double x = k < H.ncand ? wdef[H.cstart + k] : 0.0;
-        for (int s = 32; s >= 1; s >>= 1) x = x + __shfl_down(x, s);
-        dsum = dsum + x;
+        const bool in = k < H.ncand;
+        const uint64_t e = wbase + H.cstart + k;
+        double y[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        uint8_t fl = 0;
+        if (A.tdelta && in) {
+          fl = bflag[H.cstart + k];
+          for (int x = 0; x < 5; ++x) y[x] = A.tdelta[(size_t)x * A.tdelta_stride + e];
+        }
+        if (MIX && in) y[5] = wdef[H.cstart + k];
+        if (!(fl & kFlagCollided))
+          for (int x = 0; x < 5; ++x) y[x] = 0.0;
+        for (int s = 32; s >= 1; s >>= 1)
+          for (int x = 0; x < 6; ++x) y[x] = y[x] + __shfl_down(y[x], s);
+        for (int x = 0; x < 5; ++x) d[x] = d[x] + y[x];
+        dsum = dsum + y[5];
       }
+      if (A.tdelta && lane == 0)
+        for (int x = 0; x < 5; ++x) hdr[g].tsum[x] = H.tsum[x] + d[x];
     }
     unsigned long long *tot = l_tot + (size_t)g * nctr;
     for (uint32_t i = lane; i < nctr; i += 64) {
@@ -1817,6 +1929,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       A.cells.sgmax[c] = H.sgmax;
       A.cells.rem[c] = H.rem;
       if (MIX) A.cells.defect[c] = H.defect;
+      if (A.cells.tsum)
+        for (int q = 0; q < 5; ++q) A.cells.tsum[(size_t)q * A.cells.n_cells + c] = H.tsum[q];
     }
   }
 #ifdef HCAO_PHASE_CLOCKS
@@ -1970,6 +2084,16 @@ __global__ __launch_bounds__(256) void k_cell_init(CellInitArgs A) {
   }
   atomicMax(&s_v, (unsigned long long)__double_as_longlong(vmax2));
   atomicOr(&s_mask, mask);
+  if (A.cells.tsum && threadIdx.x < 64) {
+    // the running sums of the cell temperature start from the particles
+    double sums[5];
+    if (A.st.fx)
+      cell_sums<true>(A.st, A.tab->sp, base, n, threadIdx.x, sums);
+    else
+      cell_sums<false>(A.st, A.tab->sp, base, n, threadIdx.x, sums);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 5; ++q) A.cells.tsum[(size_t)q * A.cells.n_cells + c] = sums[q];
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const Tables &T = *A.tab;

@@ -159,6 +159,8 @@ struct hcao_ctx {
   DevBuf<uint64_t> off;
   DevBuf<uint32_t> cnt, cap;
   DevBuf<double> d_volume, d_weight, sgmax, rem, defect;
+  DevBuf<double> tsum;    // recombination: running sums of the cell temperature [5][n_cells]
+  DevBuf<double> tdelta;  // recombination: each work entry's change of the running sums [5][work_entries]
   DevBuf<unsigned long long> ctr;
   DevBuf<uint32_t> err;
   DevBuf<uint32_t> grp, work;
@@ -325,6 +327,7 @@ void free_state(hcao_ctx *c) {
   c->sgmax.release();
   c->rem.release();
   c->defect.release();
+  c->tsum.release();
   c->ctr.release();
   c->grp.release();
   c->grp_work.release();
@@ -355,8 +358,9 @@ State staging_of(hcao_ctx *c) {
                c->bpx.p, c->bpy.p, c->bpz.p, c->total_slots};
 }
 CellArrays cells_of(hcao_ctx *c) {
-  return CellArrays{c->off.p,   c->cnt.p, c->cap.p,    c->d_volume.p, c->d_weight.p,
-                    c->sgmax.p, c->rem.p, c->defect.p, c->ctr.p};
+  return CellArrays{c->off.p,    c->cnt.p, c->cap.p,    c->d_volume.p, c->d_weight.p,
+                    c->sgmax.p,  c->rem.p, c->defect.p, c->ctr.p,      c->tab.has_recomb ? c->tsum.p : nullptr,
+                    c->cfg.n_cells};
 }
 
 // velocity arrays of the context's precision (three, fp64 or fp32)
@@ -471,9 +475,10 @@ hcao_status build_groups(hcao_ctx *c) {
   HIP_TRY(c, c->grp.alloc(grp.size()));
   HIP_TRY(c, c->grp_work.alloc(gw.size()));
   if (c->work_entries != wsum) {
-    HIP_TRY(c, c->work.alloc(7 * wsum));  // (j, p, q, key) as found, then (j, p, q) sorted
+    HIP_TRY(c, c->work.alloc((uint64_t)kWorkWords * wsum));  // the pairs as found, then sorted
     HIP_TRY(c, c->bflag.alloc(wsum));
     if (c->mixed) HIP_TRY(c, c->wdef.alloc(wsum));
+    if (c->tab.has_recomb) HIP_TRY(c, c->tdelta.alloc(5 * wsum));
     c->work_entries = wsum;
   }
   HIP_TRY(c, hipMemcpyAsync(c->grp.p, grp.data(), grp.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -588,6 +593,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   HIP_TRY(c, c->sgmax.alloc(nc));
   HIP_TRY(c, c->rem.alloc(nc));
   HIP_TRY(c, c->defect.alloc(nc));
+  if (c->tab.has_recomb) HIP_TRY(c, c->tsum.alloc(5 * (size_t)nc));
   HIP_TRY(c, c->ctr.alloc((size_t)nc * kNumCtr));
   HIP_TRY(c, hipMemsetAsync(c->defect.p, 0, nc * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->lvl.p, 0, tot * mm * sizeof(uint16_t), c->stream));
@@ -1019,9 +1025,10 @@ hcao_status hcao_finalize(hcao_ctx *c) {
       for (const ReactionHost &h : c->reactions) {
         const int32_t ra = h.d.reactant[0], rb = h.d.reactant[1];
         if (h.d.kind == HCAO_RX_DISSOCIATION) {
-          if (ra == (int32_t)a || ra == (int32_t)b) react = 1;
+          if (ra == (int32_t)a || ra == (int32_t)b) react |= kReactAny;
         } else if ((ra == (int32_t)a && rb == (int32_t)b) || (ra == (int32_t)b && rb == (int32_t)a)) {
-          react = 1;
+          react |= kReactAny;
+          if (h.d.kind == HCAO_RX_RECOMBINATION) react |= kReactRecomb;
         }
       }
       T.pr[a][b].react = react;
@@ -1283,6 +1290,8 @@ StepArgs step_args(hcao_ctx *c, double dt) {
   a.work = c->work.p;
   a.bflag = c->bflag.p;
   a.wdef = c->wdef.p;
+  a.tdelta = c->tab.has_recomb ? c->tdelta.p : nullptr;
+  a.tdelta_stride = c->work_entries;
   a.clk = c->clk.p;
   return a;
 }
@@ -1427,6 +1436,7 @@ struct StepScratch {
   uint32_t *work;
   uint8_t *bflag;
   double *wdef;
+  double *tdelta;
   State born;
 };
 
@@ -1443,9 +1453,10 @@ uint64_t static_layout(const hcao_ctx *c, unsigned char *base, StepScratch &out)
     return p;
   };
   out = StepScratch{};
-  out.work = reinterpret_cast<uint32_t *>(take(7 * w * sizeof(uint32_t)));
+  out.work = reinterpret_cast<uint32_t *>(take((uint64_t)kWorkWords * w * sizeof(uint32_t)));
   out.bflag = take(w);
   if (c->mixed) out.wdef = reinterpret_cast<double *>(take(w * sizeof(double)));
+  if (c->tab.has_recomb) out.tdelta = reinterpret_cast<double *>(take(5 * w * sizeof(double)));
   State &b = out.born;
   if (c->mixed) {
     b.fx = reinterpret_cast<float *>(take(w * sizeof(float)));
@@ -1482,6 +1493,7 @@ hcao_status issue_steps(hcao_ctx *c, double dt, uint32_t n_steps, uint32_t base,
     a.work = sc->work;
     a.bflag = sc->bflag;
     a.wdef = sc->wdef;
+    a.tdelta = sc->tdelta;  // stride: work entries, as the context's own
     a.born = sc->born;
   }
   a.step_dev = step_dev;
@@ -1641,7 +1653,7 @@ namespace {
 
 // Device copy of everything a step changes, for the autotuner's trials.
 struct Snapshot {
-  DevBuf<double> vx, vy, vz, sgmax, rem, defect, rot;
+  DevBuf<double> vx, vy, vz, sgmax, rem, defect, rot, tsum;
   DevBuf<float> fx, fy, fz;
   DevBuf<uint8_t> sp;
   DevBuf<uint16_t> lvl;
@@ -1661,6 +1673,7 @@ struct Snapshot {
     rem.release();
     defect.release();
     rot.release();
+    tsum.release();
     fx.release();
     fy.release();
     fz.release();
@@ -1699,6 +1712,7 @@ hcao_status snapshot(hcao_ctx *c, Snapshot &S, bool take) {
   SNAP(sgmax);
   SNAP(rem);
   SNAP(defect);
+  SNAP(tsum);
   SNAP(ctr);
   SNAP(err);
 #undef SNAP
@@ -2216,7 +2230,7 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   if (hcao_status s = hcao_sync(c)) return s;
   const uint64_t tot = c->total_slots;
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
-  std::vector<double> vx, vy, vz, sg(nc), rm(nc), df(nc);
+  std::vector<double> vx, vy, vz, sg(nc), rm(nc), df(nc), ts(c->tsum.p ? 5 * (size_t)nc : 0);
   std::vector<uint8_t> sp(tot);
   std::vector<uint16_t> lv(tot * mm);
   std::vector<uint32_t> cnt(nc);
@@ -2229,6 +2243,7 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   HIP_TRY(c, hipMemcpy(sg.data(), c->sgmax.p, nc * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(rm.data(), c->rem.p, nc * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(ctr.data(), c->ctr.p, ctr.size() * 8, hipMemcpyDeviceToHost));
+  if (!ts.empty()) HIP_TRY(c, hipMemcpy(ts.data(), c->tsum.p, ts.size() * 8, hipMemcpyDeviceToHost));
   std::vector<double> rt(c->rot.p ? tot : 0);
   if (c->rot.p) HIP_TRY(c, hipMemcpy(rt.data(), c->rot.p, tot * 8, hipMemcpyDeviceToHost));
   std::vector<double> pos(c->spatial ? 3 * tot : 0);
@@ -2248,9 +2263,10 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   // velocities are stored as fp64 in both forms (exact for fp32 values);
   // word 6: bit 0 mixed form, bit 1 rotational energies follow the levels,
   // bit 2 positions (x, y, z arrays) follow, bit 3 the open faces' inflow
-  // remainders and the two flux counts follow
+  // remainders and the two flux counts follow, bit 4 the cells' running
+  // sums of the recombination temperature follow ([5][n_cells])
   const uint64_t form = (c->mixed ? 1ull : 0ull) | (c->rot.p ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull) |
-                        (c->open_faces ? 8ull : 0ull);
+                        (c->open_faces ? 8ull : 0ull) | (ts.empty() ? 0ull : 16ull);
   const uint64_t hdr[7] = {0x48434130534156ull, HCAO_ABI_VERSION, nc, tot, mm, c->step, form};
   bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1;
   ok = ok && std::fwrite(c->cap_host.data(), 4, nc, f) == nc;
@@ -2268,6 +2284,7 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   ok = ok && std::fwrite(pos.data(), 8, pos.size(), f) == pos.size();
   ok = ok && std::fwrite(irem.data(), 8, irem.size(), f) == irem.size();
   if (c->open_faces) ok = ok && std::fwrite(fl, 8, 2, f) == 2;
+  ok = ok && std::fwrite(ts.data(), 8, ts.size(), f) == ts.size();
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return fail(c, HCAO_EINVAL, "write failed");
   return HCAO_OK;
@@ -2284,7 +2301,7 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   if (std::fread(hdr, sizeof(hdr), 1, f) != 1 || hdr[0] != 0x48434130534156ull || hdr[1] != HCAO_ABI_VERSION ||
       hdr[2] != nc || hdr[4] != mm ||
       hdr[6] != ((c->mixed ? 1ull : 0ull) | (c->tab.has_rot ? 2ull : 0ull) | (c->spatial ? 4ull : 0ull) |
-                 (c->open_faces ? 8ull : 0ull))) {
+                 (c->open_faces ? 8ull : 0ull) | (c->tab.has_recomb ? 16ull : 0ull))) {
     std::fclose(f);
     return fail(c, HCAO_EINVAL, "checkpoint does not match this context");
   }
@@ -2313,6 +2330,8 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   unsigned long long fl[2] = {0, 0};
   ok = ok && std::fread(irem.data(), 8, irem.size(), f) == irem.size();
   if (c->open_faces) ok = ok && std::fread(fl, 8, 2, f) == 2;
+  std::vector<double> ts(c->tab.has_recomb ? 5 * (size_t)nc : 0);
+  ok = ok && std::fread(ts.data(), 8, ts.size(), f) == ts.size();
   std::fclose(f);
   if (!ok) return fail(c, HCAO_EINVAL, "truncated checkpoint");
   uint64_t t2 = 0;
@@ -2326,6 +2345,7 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   HIP_TRY(c, hipMemcpy(c->sgmax.p, sg.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->rem.p, rm.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->ctr.p, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice));
+  if (!ts.empty()) HIP_TRY(c, hipMemcpy(c->tsum.p, ts.data(), ts.size() * 8, hipMemcpyHostToDevice));
   if (c->rot.p) HIP_TRY(c, hipMemcpy(c->rot.p, rt.data(), tot * 8, hipMemcpyHostToDevice));
   if (c->spatial) {
     HIP_TRY(c, hipMemcpy(c->px.p, pos.data(), tot * 8, hipMemcpyHostToDevice));

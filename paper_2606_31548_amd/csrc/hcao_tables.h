@@ -34,9 +34,20 @@ struct SpeciesTab {
   uint32_t idiss[kMaxModes];    // stretches: top bound level
 };
 
+// PairTab::react bits
+constexpr uint32_t kReactAny = 1u;    // some reaction lists the pair (as A, or as A + B / B + C), in either order
+constexpr uint32_t kReactRecomb = 2u;  // a recombination lists it as B + C, in either order
+
+// Words per work-list entry: the pair as found (candidate j, p, q, sort key,
+// words 1-3 of the pair stream's first Philox block), then as sorted (j, p,
+// q, the three words).
+constexpr uint32_t kWorkFound = 7;
+constexpr uint32_t kWorkSorted = 6;
+constexpr uint32_t kWorkWords = kWorkFound + kWorkSorted;
+
 struct PairTab {
   double mr, hm, m_a, m_b, msum, wa, wb, csg, esg, q;
-  uint32_t react;     // some reaction lists this pair (as A, or as A + B / B + C), in either order
+  uint32_t react;     // kReact* bits
   uint32_t beta_off;  // exact sampler: offset of the beta table of species a with exponent q
 };
 
@@ -100,12 +111,18 @@ struct CellArrays {
   double *sgmax, *rem;
   double *defect;           // mixed form: energy the cell's particles lack [J]
   unsigned long long *ctr;  // [n_cells][kNumCtr]
+  double *tsum;             // recombination: [5][n_cells] running sums m, m v_x, m v_y, m v_z, m |v|^2 (else null)
+  uint32_t n_cells;
 };
 
 // Phases of the step kernel, for the clock sums of instrumented builds
 // (HCAO_PHASE_CLOCKS): table and cell loads of a launch, NTC counts and
 // permutation keys, cell temperature, candidate acceptance, work-list sort,
 // collisions, product placement, and the launch's final stores.
+// The collision phase is further split per wave (sums over waves, in the
+// leading active lane's clock): gathering a pair's state, the reaction
+// decision, the relaxation sampler, scattering and reaction application,
+// and the write-back.
 enum StepPhase {
   kPhaseLoad = 0,
   kPhaseNtc,
@@ -115,13 +132,22 @@ enum StepPhase {
   kPhaseCollide,
   kPhasePlace,
   kPhaseStore,
+  kPhaseCollideGather,
+  kPhaseCollideDecide,
+  kPhaseCollideRelax,
+  kPhaseCollideScatter,
+  kPhaseCollideWrite,
   kPhases
 };
 static_assert(kPhases == HCAO_N_PHASES, "phase list and ABI disagree");
 
+// bflag bits of a candidate pair
+constexpr uint8_t kFlagBorn = 1;      // it left a dissociation product in the products staging
+constexpr uint8_t kFlagCollided = 2;  // it collided (its running-sum change is in tdelta)
+
 // Workgroup b processes the consecutive cells [grp[2b], grp[2b+1]); its work
 // list, product flags and pair energy defects are the entries
-// [grp_work[2b], grp_work[2b+1]) of work (seven words each: the pair as
+// [grp_work[2b], grp_work[2b+1]) of work (kWorkWords words each: the pair as
 // found and as sorted) / bflag / wdef
 // (sum over its cells of cap/2 + 1 entries).
 struct StepArgs {
@@ -137,6 +163,8 @@ struct StepArgs {
   uint32_t *work;
   uint8_t *bflag;
   double *wdef;  // mixed form: energy defect of each candidate pair, indexed like bflag
+  double *tdelta;  // recombination: [5][tdelta_stride] each colliding pair's change of its cell's running sums
+  uint64_t tdelta_stride;
   uint32_t *err;
   unsigned long long *clk;   // per-phase clock sums [kPhases] (instrumented builds) or null
   uint64_t seed;

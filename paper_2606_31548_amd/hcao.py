@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # HCAO_LIBRARY selects another build of the library (the instrumented
 # libhcao_clocks.so of build.py --phase-clocks); default: libhcao.so
 LIB_PATH = os.environ.get("HCAO_LIBRARY") or os.path.join(HERE, "libhcao.so")
-N_PHASES = 8
-PHASES = ("load", "ntc", "temperature", "accept", "sort", "collide", "place", "store")
+N_PHASES = 13
+PHASES = ("load", "ntc", "temperature", "accept", "sort", "collide", "place", "store", "collide_gather",
+          "collide_decide", "collide_relax", "collide_scatter", "collide_write")
 
 ABI_VERSION = 1
 MAX_SPECIES = 16

@@ -59,9 +59,18 @@ MUTATIONS = [
      "for (uint32_t i = (uint32_t)t; i < n; i += 64) {", "for (uint32_t i = (uint32_t)t; i < (n & ~63u); i += 64) {",
      [PINS + "test_cell_temperature_closed_form"]),
     ("cell temperature about the origin instead of the mean velocity",
-     "return (x[4][0] - p2 / x[0][0]) / (3.0 * K_BOLTZ * (double)n);",
-     "return (x[4][0] - 0.0 * p2 / x[0][0]) / (3.0 * K_BOLTZ * (double)n);",
+     "return (s[4] - p2 / s[0]) / (3.0 * K_BOLTZ * (double)n);",
+     "return (s[4] - 0.0 * p2 / s[0]) / (3.0 * K_BOLTZ * (double)n);",
      [PINS + "test_cell_temperature_two_masses_and_galilean_boost"]),
+    ("running sums without the dissociation product",
+     "if (nb[k].born) add_terms(after, o->sp[nb[k].sp].mass, nb[k].v);", "",
+     [PINS + "test_running_sums_track_the_particles"]),
+    ("running sums without the recoiling third body",
+     "if (ps.m_moved) add_terms(after, o->sp[ps.sp_m].mass, ps.v_m);", "",
+     [PINS + "test_running_sums_track_the_particles"]),
+    ("running sums drop the last partial chunk of pairs",
+     "for (uint64_t k0 = 0; k0 < ncand; k0 += 64) {", "for (uint64_t k0 = 0; k0 + 64 <= ncand; k0 += 64) {",
+     [PINS + "test_running_sums_track_the_particles"]),
     ("Morse levels with a wrong anharmonic term",
      "double e = (a * v) - ((ax * v) * v);", "double e = (a * v) - ((ax * v) * (v + 1.0));",
      [PHYS + "test_morse_spacing_and_cap"]),

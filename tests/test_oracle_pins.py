@@ -297,3 +297,31 @@ def test_cell_temperature_two_masses_and_galilean_boost(orc):
     assert abs(t0 / want - 1) < 1e-12
     _, ob = _load_cell(orc, ids, vel + np.array([350.0, -220.0, 90.0]))
     assert abs(ob.cell_temperature(0) / t0 - 1) < 1e-10
+
+
+def test_running_sums_track_the_particles(orc):
+    """The cell temperature's running sums (reading A8: updated each step by
+    the colliding pairs' changes, products and recoiling third bodies
+    included) stay equal to the sums over the particles to rounding, through
+    steps with dissociation, exchange and recombination."""
+    # dense (1e26 m^-3) and moderately hot, so that dissociation and
+    # recombination both happen within a few steps
+    wl = W.methane_chemistry(n_cells=6, per_cell=256, recombination=True, t=4000.0)
+    wl.cell_weight = wl.cell_weight * 1e4
+    wl.dt = wl.dt * 1e-4
+    o = orc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    for c in range(wl.n_cells):
+        assert np.array_equal(o.cell_sums(c), o.cell_sums(c, direct=True))
+    o.step(wl.dt, 40)
+    ctr = o.counters()
+    assert ctr[:, orc.CTR_BIRTHS].sum() > 0 and ctr[:, orc.CTR_DEATHS].sum() > 0
+    for c in range(wl.n_cells):
+        run, direct = o.cell_sums(c), o.cell_sums(c, direct=True)
+        scale = math.sqrt(direct[0] * direct[4])  # |sum m v| <= sqrt(sum m * sum m |v|^2)
+        assert abs(run[0] / direct[0] - 1) < 1e-12
+        assert abs(run[4] / direct[4] - 1) < 1e-11
+        assert np.all(np.abs(run[1:4] - direct[1:4]) < 1e-11 * scale)
+        n = o.count(c)
+        t_direct = (direct[4] - (direct[1] ** 2 + direct[2] ** 2 + direct[3] ** 2) / direct[0]) / (3 * KB * n)
+        assert abs(o.cell_temperature(c) / t_direct - 1) < 1e-10

@@ -63,7 +63,7 @@ WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "tria
 # warm-up (from there it picks 128 / 2048 on the chemistry workload as
 # well; trials from the initial state, where (sigma g)_max is still
 # settling, preferred 128 / 4096, 5% (mixed) and 20% (fp64) slower).
-TUNED_SHAPE = {"chemistry-67m": (128, 2048), "chemistry-16m": (128, 2048), "methane-argon": (64, 1024),
+TUNED_SHAPE = {"chemistry-67m": (128, 3072), "chemistry-16m": (128, 3072), "methane-argon": (64, 1024),
                "batched": (256, 4096), "triatomic": (64, 1024), "box-67m": (128, 3072),
                "box-inflow-67m": (128, 3072)}
 
@@ -383,6 +383,72 @@ def phase_shares(clocks):
     return out
 
 
+def precision_report(hcao, torch, wl, steps=10000, spl=50):
+    """Both forms run `steps` untimed steps from the same thermal initial
+    state: energy drift of each (relative to the initial thermal energy),
+    and per observable the two forms' values with the statistical error of
+    each (cells are independent replicas of the reservoir, so the error of a
+    per-cell mean is the cells' spread over sqrt(cells); a total's is the
+    spread times sqrt(cells)), the relative error of mixed against fp64 and
+    their difference in units of the combined sigma. Observables: the
+    translational temperature and each molecular species' vibrational
+    temperature (per-cell means), particles per cell of each species, and
+    reactions per channel over the run."""
+    n_modes = [sp.n_modes for sp in wl.species]
+    forms = {}
+    for name, prec in (("mixed", hcao.MIXED), ("fp64", hcao.FP64)):
+        print(f"# precision report: {steps} steps of the {name} form", file=sys.stderr, flush=True)
+        sim = hcao.from_workload(wl, precision=prec)
+        sim.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+        sim.set_launch_shape(*TUNED_SHAPE.get(getattr(wl, "bench_name", ""), (128, 3072)), spl)
+        m0 = sim.moments()
+        e0, th0 = _energy(sim, m0, n_modes)
+        t0 = time.perf_counter()
+        sim.step(wl.dt, steps)
+        sim.sync()
+        wall = time.perf_counter() - t0
+        m1 = sim.moments()
+        e1, _ = _energy(sim, m1, n_modes)
+        per = sim.moments_per_cell()
+        ctr = sim.cell_state()[2]
+        nc = len(per)
+        obs = {}
+
+        def mean_of(x, name):
+            x = np.asarray(x, np.float64)
+            obs[name] = (float(x.mean()), float(x.std(ddof=1) / np.sqrt(len(x))))
+
+        mean_of(per["T_trans_K"], "T_trans_K")
+        for s, sp in enumerate(wl.species):
+            mean_of(per["n_species"][:, s], f"n_per_cell[{sp.name}]")
+            if sp.n_modes:
+                have = per["n_species"][:, s] > 0
+                if have.sum() > 1:
+                    mean_of(per["T_vib_K"][have, s], f"T_vib_K[{sp.name}]")
+        for r in range(len(wl.reactions)):
+            x = ctr[:, hcao.CTR_REACTION0 + r].astype(np.float64)
+            obs[f"reactions[{r}]"] = (float(x.sum()), float(x.std(ddof=1) * np.sqrt(nc)))
+        forms[name] = {"energy_drift": abs(e1 - e0) / th0, "energy_owed_rel": m1.E_defect_J / th0,
+                       "steps": steps, "wall_s": wall, "observables": obs}
+        sim.close()
+    comp = {}
+    for k, (vm, sm) in forms["mixed"]["observables"].items():
+        if k not in forms["fp64"]["observables"]:
+            continue
+        vf, sf = forms["fp64"]["observables"][k]
+        sig = float(np.hypot(sm, sf))
+        comp[k] = {"mixed": vm, "fp64": vf, "sigma_mixed": sm, "sigma_fp64": sf,
+                   "rel_err": (vm - vf) / vf if vf else None,
+                   "z": abs(vm - vf) / sig if sig > 0 else (0.0 if vm == vf else float("inf"))}
+    return {"steps": steps, "cells": wl.n_cells, "particles": int(wl.n_particles),
+            "energy_drift": {f: forms[f]["energy_drift"] for f in forms},
+            "energy_owed_rel_mixed": forms["mixed"]["energy_owed_rel"],
+            "wall_s": {f: forms[f]["wall_s"] for f in forms},
+            "mixed_vs_fp64": comp,
+            "max_z": max((c["z"] for c in comp.values()), default=0.0),
+            "mixed_drift_within_1e-6": forms["mixed"]["energy_drift"] <= 1e-6}
+
+
 def copy_peak(torch, mib=1024, repeats=10):
     """HBM bandwidth that a plain device-to-device copy reaches (bytes read
     plus bytes written per second, HIP events around `repeats` copies of
@@ -458,6 +524,9 @@ def main():
     ap.add_argument("--recomb-exact", action="store_true",
                     help="also time Eq. recomb-correct for CH4 on the device against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precision-steps", type=int, default=10000,
+                    help="steps of the untimed precision report (both forms from the same initial state: energy "
+                         "drift, temperatures, species and reaction counts of mixed against fp64); 0 skips it")
     ap.add_argument("--phase-clocks", action="store_true",
                     help="report per-phase clock shares of the step kernel (needs the instrumented library: "
                          "python paper_2606_31548_amd/build.py --phase-clocks, then HCAO_LIBRARY="
@@ -484,6 +553,7 @@ def main():
         return
 
     wl, desc = make_workload(args.workload)
+    wl.bench_name = args.workload
     set_sampler(wl, args.sampler)
     if args.rotors:
         set_rotors(wl)
@@ -542,6 +612,8 @@ def main():
         out["sequential_fp64"] = seq
         if "fp64" in res:
             out["batched_vs_sequential_fp64"] = res["fp64"]["collisions_per_s"] / seq["collisions_per_s"]
+    if args.precision_steps > 0 and args.workload in ("chemistry-67m", "chemistry-16m"):
+        out["precision_report"] = precision_report(hcao, torch, wl, args.precision_steps, spl)
     if args.recomb_exact:
         print("# Eq. recomb-correct for CH4 on the device and in the oracle", file=sys.stderr, flush=True)
         out["recombination_exact"] = recombination_exact(hcao)

@@ -9,6 +9,7 @@
 // forward probability times the Maxwellian A-M collision rate).
 #include "hcao_host_tables.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -139,6 +140,55 @@ double vibrational_temperature(const ModeSet &m, double e) {
     (mean_energy(m, std::exp(mid)) < e ? lo : hi) = mid;
   }
   return std::exp(0.5 * (lo + hi));
+}
+
+VibrationalThermometer::VibrationalThermometer(const ModeSet &m) : theta_(m.theta) {
+  for (const std::vector<double> *L : m.ladder) ladders_.push_back(*L);
+  constexpr int kGrid = 512;
+  const double top = std::log(1.0e6);
+  for (int i = 0; i < kGrid; ++i) {
+    const double lt = top * (double)i / (double)(kGrid - 1);
+    log_t_.push_back(lt);
+    mean_.push_back(mean(std::exp(lt)));
+  }
+}
+
+double VibrationalThermometer::mean(double t) const {
+  double e = 0.0;
+  for (double th : theta_) e += kBoltzmann * th / std::expm1(th / t);
+  for (const std::vector<double> &L : ladders_) e += ladder_mean(L, kBoltzmann * t, false);
+  return e;
+}
+
+double VibrationalThermometer::temperature(double e) const {
+  if (theta_.empty() && ladders_.empty()) return 0.0;
+  if (!(e > 0.0)) return 0.0;
+  if (!(e < mean_.back())) return std::exp(log_t_.back());
+  // first grid node whose mean energy reaches e
+  size_t hi = (size_t)(std::lower_bound(mean_.begin(), mean_.end(), e) - mean_.begin());
+  if (hi == 0) hi = 1;
+  double a = log_t_[hi - 1], b = log_t_[hi];
+  double fa = mean_[hi - 1] - e, fb = mean_[hi] - e;
+  if (fb == 0.0) return std::exp(b);
+  int side = 0;
+  for (int it = 0; it < 100 && b - a > 1e-15 * (1.0 + std::fabs(b)); ++it) {
+    const double x = (a * fb - b * fa) / (fb - fa);
+    const double fx = mean(std::exp(x)) - e;
+    if (fx == 0.0) return std::exp(x);
+    if ((fx < 0.0) == (fa < 0.0)) {
+      a = x;
+      fa = fx;
+      if (side == -1) fb *= 0.5;
+      side = -1;
+    } else {
+      b = x;
+      fb = fx;
+      if (side == 1) fa *= 0.5;
+      side = 1;
+    }
+    if (x == a && x == b) break;
+  }
+  return std::exp(std::fabs(fa) < std::fabs(fb) ? a : b);
 }
 
 double wr_probability(const ModeSet &m, double de, double omega, uint32_t n_samp, double t) {

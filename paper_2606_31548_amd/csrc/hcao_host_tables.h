@@ -43,6 +43,23 @@ double partition_function(const ModeSet &m, double t);
 double mean_energy(const ModeSet &m, double t);
 double vibrational_temperature(const ModeSet &m, double e);
 
+// The same inverse for many energies of one species: the mean energy on a
+// log-spaced temperature grid over [1 K, 1e6 K] brackets the root, then a
+// bracketed secant (Illinois) iteration on the exact mean energy in log T
+// refines it to rounding. Holds its own copy of the modes.
+class VibrationalThermometer {
+ public:
+  VibrationalThermometer() = default;
+  explicit VibrationalThermometer(const ModeSet &m);
+  double temperature(double e) const;
+
+ private:
+  double mean(double t) const;  // mean_energy over the copied modes
+  std::vector<double> theta_;
+  std::vector<std::vector<double>> ladders_;
+  std::vector<double> log_t_, mean_;
+};
+
 // Whitten-Rabinovich forward probability of the recombination section at
 // temperature t: D_e the bond energy, omega the (A, third body) VHS exponent,
 // n_samp energies on [0, D_e].

@@ -121,6 +121,14 @@ struct RngT {
     return (double)(next64() >> 11) * 0x1p-53;
   }
   __device__ __forceinline__ float uniform_f() { return (float)(next32() >> 8) * 0x1p-24f; }
+  // a 53-bit uniform in either form: the next two words (low first); the
+  // fp64 form's uniform() takes the same two words
+  __device__ __forceinline__ double uniform53() {
+    if (!MIX) return uniform();
+    const uint64_t lo = next32();
+    const uint64_t hi = next32();
+    return (double)(((hi << 32) | lo) >> 11) * 0x1p-53;
+  }
 };
 using Rng = RngT<false>;
 
@@ -946,7 +954,9 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
       sb = 1;
     else
       continue;
-    const double u = (double)draw<MIX>(rng);
+    // 53 bits in both forms: the per-collision probability can be far below
+    // the 2^-24 steps of the mixed form's single-word uniforms
+    const double u = rng.uniform53();
     if (!P.has_m) {
       atomicAdd(&C.ctr[HCAO_CTR_SUPPRESSED], 1ull);
       continue;

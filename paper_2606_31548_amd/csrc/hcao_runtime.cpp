@@ -117,6 +117,7 @@ struct hcao_ctx {
   hcao_status sticky = HCAO_OK;
   std::string last_error;
   std::vector<SpeciesHost> species;
+  std::vector<host::VibrationalThermometer> thermo;  // per species, built at finalize
   std::vector<ReactionHost> reactions;
   uint32_t max_modes = 0;
   Tables tab{};
@@ -995,6 +996,8 @@ hcao_status hcao_finalize(hcao_ctx *c) {
     }
   }
   T.n_levels = (uint32_t)c->lev_host.size();
+  c->thermo.clear();
+  for (const SpeciesHost &h : c->species) c->thermo.emplace_back(modes_of(h));
   // VHS pair constants: sigma g = C (g^2)^(1-w), C = pi d^2 (2 k T_ref / m_r)^(w-1/2) / Gamma(5/2-w),
   // mixed-pair d, w, T_ref as species means; LB exponent 3/2 - w
   for (uint32_t a = 0; a < T.n_species; ++a)
@@ -1979,7 +1982,7 @@ hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments 
       ntot += k;
       M.E_vib_J[s] = r[6 + ns + s];
       if (vol > 0.0) M.number_density[s] = (double)k * wgt / vol;
-      M.T_vib_K[s] = k ? host::vibrational_temperature(modes_of(c->species[s]), r[6 + ns + s] / (double)k) : 0.0;
+      M.T_vib_K[s] = k ? c->thermo[s].temperature(r[6 + ns + s] / (double)k) : 0.0;
       M.E_rot_J[s] = r[6 + 2 * ns + s];
       const uint32_t z = c->species[s].d.zeta_rot;
       M.T_rot_K[s] = (k && z) ? (2.0 * M.E_rot_J[s]) / ((double)z * kB * (double)k) : 0.0;

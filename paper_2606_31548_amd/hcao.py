@@ -380,6 +380,13 @@ class Simulation:
             self._h, ctypes.cast(arr, _vp) if per_cell else None, ctypes.byref(tot)))
         return (tot, list(arr)) if per_cell else tot
 
+    def moments_per_cell(self):
+        """Per-cell moments as a numpy structured array (fields of hcao_moments)."""
+        tot = hcao_moments()
+        arr = (hcao_moments * self.n_cells)()
+        self._chk("hcao_read_moments", self._L.hcao_read_moments(self._h, ctypes.cast(arr, _vp), ctypes.byref(tot)))
+        return np.ctypeslib.as_array(arr).copy()
+
     def zero_point(self, species) -> float:
         """Zero-point energy of a species [J]: the sum of its modes' ground levels."""
         return float(sum(self.levels(species, m, 1)[0] for m in range(self._n_modes[species])))

@@ -40,8 +40,8 @@ def build(verbose: bool = True, phase_clocks: bool = False) -> str:
     r_obj = os.path.join(BUILD, f"hcao_runtime{tag}.o")
     t_obj = os.path.join(BUILD, f"hcao_host_tables{tag}.o")
     _run([HIPCC, "-x", "hip", *DEVICE, *COMMON, *defs, "-c", os.path.join(CSRC, "hcao_kernels.hip"), "-o", k_obj])
-    _run([HIPCC, *COMMON, *defs, "-c", os.path.join(CSRC, "hcao_runtime.cpp"), "-o", r_obj])
-    _run([HIPCC, *COMMON, "-c", os.path.join(CSRC, "hcao_host_tables.cpp"), "-o", t_obj])
+    _run([HIPCC, *DEVICE, *COMMON, *defs, "-c", os.path.join(CSRC, "hcao_runtime.cpp"), "-o", r_obj])
+    _run([HIPCC, *DEVICE, *COMMON, "-c", os.path.join(CSRC, "hcao_host_tables.cpp"), "-o", t_obj])
     tmp = lib + ".tmp"
     _run([HIPCC, *DEVICE, "-shared", "-fPIC", "-o", tmp, k_obj, r_obj, t_obj])
     os.replace(tmp, lib)

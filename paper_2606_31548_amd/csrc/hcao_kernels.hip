@@ -121,6 +121,25 @@ struct RngT {
     return (double)(next64() >> 11) * 0x1p-53;
   }
   __device__ __forceinline__ float uniform_f() { return (float)(next32() >> 8) * 0x1p-24f; }
+  // passes over the next n uniforms of this form without using them (blocks
+  // wholly passed over are not computed)
+  __device__ __forceinline__ void skip(uint32_t n) {
+    if (n == 0) return;
+    const uint32_t words = MIX ? n : 2 * n;
+    // word index within the stream of the next word to be used
+    const uint32_t at = (used >= 4 ? 4 * block : 4 * (block - 1) + used) + words;
+    const uint32_t b = at / 4, w = at % 4;
+    if (w == 0) {
+      block = b;
+      used = 4;  // the next draw computes block b
+    } else if (b != block - 1 || used >= 4) {
+      block = b;
+      refill();  // computes block b, block = b + 1
+      used = w;
+    } else {
+      used = w;
+    }
+  }
   // a 53-bit uniform in either form: the next two words (low first); the
   // fp64 form's uniform() takes the same two words
   __device__ __forceinline__ double uniform53() {
@@ -282,6 +301,35 @@ __device__ __forceinline__ double dpow(double x, double y) {
 // 1.7e7 operands); a decision further than kFilter from est is the one the
 // fp64 power gives, and only the band in between evaluates dpow. The
 // result of every comparison is therefore that of the fp64 expression.
+// Quantum numbers of slot i, a row of s.lrow uint16 read and written as
+// dwords (two modes each). load_levels unpacks the first n modes to
+// dst[m * ds]; store_levels packs src[m * ss] for m < n and zeros for
+// n <= m < top (top >= n: modes only the old species had), in whole dwords
+// (a mode past top in the last dword is 0 in the state and stays 0).
+__device__ __forceinline__ void load_levels(const State &s, uint64_t i, uint32_t n, uint16_t *dst, uint32_t ds) {
+  const uint32_t *row = reinterpret_cast<const uint32_t *>(s.lvl + i * s.lrow);
+  for (uint32_t w = 0; 2 * w < n; ++w) {
+    const uint32_t x = row[w];
+    dst[2 * w * ds] = (uint16_t)(x & 0xFFFFu);
+    if (2 * w + 1 < n) dst[(2 * w + 1) * ds] = (uint16_t)(x >> 16);
+  }
+}
+__device__ __forceinline__ void store_levels(const State &s, uint64_t i, uint32_t n, uint32_t top, const uint16_t *src,
+                                             uint32_t ss) {
+  uint32_t *row = reinterpret_cast<uint32_t *>(s.lvl + i * s.lrow);
+  for (uint32_t w = 0; 2 * w < top; ++w) {
+    const uint32_t lo = 2 * w < n ? src[2 * w * ss] : 0u;
+    const uint32_t hi = 2 * w + 1 < n ? src[(2 * w + 1) * ss] : 0u;
+    row[w] = lo | (hi << 16);
+  }
+}
+// the whole row of slot from to slot to (dwords)
+__device__ __forceinline__ void copy_levels(const State &src, uint64_t from, const State &dst, uint64_t to) {
+  const uint32_t *a = reinterpret_cast<const uint32_t *>(src.lvl + from * src.lrow);
+  uint32_t *b = reinterpret_cast<uint32_t *>(dst.lvl + to * dst.lrow);
+  for (uint32_t w = 0; w < src.lrow / 2; ++w) b[w] = a[w];
+}
+
 constexpr double kFilter = 1e-4;
 
 __device__ __forceinline__ double pow_estimate(double x, double y) {
@@ -1002,7 +1050,23 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
   }
 
   // --- dissociation and exchange channels, competition by excess energy ---
+  // A pair none of whose channels can open skips the scan (its steric draws
+  // are passed over): the bounds are tested with a margin far above the
+  // rounding of the scan's own sums, so only pairs that certainly stay shut
+  // skip it and the result is the scan's.
+  bool may_open = false;
   if (kind == 0 && PP.react) {
+    const PairBound &B = PP.bound;
+    for (uint32_t sd = 0; sd < 2; ++sd) {
+      const double ev = sd ? ev1 : ev0;
+      const double et = EX ? e_tr0 + (sd ? P.r1 : P.r0) : e_tr0;
+      const double scale = 1e-9 * ((fabs(et) + ev) + fabs(B.dis_c[sd] < 0.0 ? 0.0 : B.dis_c[sd]) + 1e-30);
+      if ((et + ev) + B.dis_c[sd] > -scale - 1e-9 * fabs(B.dis_c[sd])) may_open = true;
+      if (B.ex_a[sd] >= 0.0 && (et + B.ex_a[sd] * ev) - B.ex_e[sd] > -scale - 1e-9 * B.ex_e[sd]) may_open = true;
+    }
+    if (!may_open) rng.skip(B.n_steric);
+  }
+  if (kind == 0 && PP.react && may_open) {
     uint64_t steric_ok = 0;
     ChannelScan S;
     S.nch = 0;
@@ -1659,8 +1723,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     // quantum numbers of the species' own modes (the others are 0 in the state
     // and nothing reads them here)
     const uint32_t nm0 = T.sp[P.sp0].n_modes, nm1 = T.sp[P.sp1].n_modes;
-    for (uint32_t m = 0; m < nm0; ++m) P.lv0[m * BLOCK] = A.st.lvl[m * A.st.stride + gp];
-    for (uint32_t m = 0; m < nm1; ++m) P.lv1[m * BLOCK] = A.st.lvl[m * A.st.stride + gq];
+    load_levels(A.st, gp, nm0, P.lv0, BLOCK);
+    load_levels(A.st, gq, nm1, P.lv1, BLOCK);
     P.r0 = P.r1 = P.rn = 0.0;
     if constexpr (EX >= 2) {
       if (A.st.rot) {
@@ -1756,12 +1820,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     // the new species' modes, and zeros over the modes only the old species had
     // (a removed particle's levels are not kept)
     if (!P.dead0) {
-      const uint32_t nn = T.sp[P.sp0].n_modes, top = nn > nm0 ? nn : nm0;
-      for (uint32_t m = 0; m < top; ++m) A.st.lvl[m * A.st.stride + gp] = m < nn ? P.lv0[m * BLOCK] : (uint16_t)0;
+      const uint32_t nn = T.sp[P.sp0].n_modes;
+      store_levels(A.st, gp, nn, nn > nm0 ? nn : nm0, P.lv0, BLOCK);
     }
     if (!P.dead1) {
-      const uint32_t nn = T.sp[P.sp1].n_modes, top = nn > nm1 ? nn : nm1;
-      for (uint32_t m = 0; m < top; ++m) A.st.lvl[m * A.st.stride + gq] = m < nn ? P.lv1[m * BLOCK] : (uint16_t)0;
+      const uint32_t nn = T.sp[P.sp1].n_modes;
+      store_levels(A.st, gq, nn, nn > nm1 ? nn : nm1, P.lv1, BLOCK);
     }
     if constexpr (EX >= 2) {
       if (A.st.rot) {
@@ -1774,7 +1838,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       const uint64_t gb = wbase + j;
       stv<MIX>(A.born, gb, P.nb_v);
       A.born.sp[gb] = (uint8_t)P.nb_sp;
-      for (uint32_t m = 0; m < mm; ++m) A.born.lvl[m * A.born.stride + gb] = P.lvn[m * BLOCK];
+      store_levels(A.born, gb, mm, A.born.lrow, P.lvn, BLOCK);
       if constexpr (EX >= 1) {
         if (A.born.rot) A.born.rot[gb] = P.rn;
         if (A.st.px) {
@@ -1822,11 +1886,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           stv<MIX>(A.st, dst, v);
           A.st.sp[dst] = spv;
         }
-        for (uint32_t mo = 0; mo < mm; ++mo) {
-          uint16_t l = 0;
-          if (live) l = A.st.lvl[mo * A.st.stride + src];
-          if (live) A.st.lvl[mo * A.st.stride + dst] = l;
-        }
+        if (live) copy_levels(A.st, src, A.st, dst);
         if constexpr (EX >= 1) {
           if (A.st.rot) {
             double rv = 0.0;
@@ -1863,8 +1923,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           const uint64_t from = wbase + H.cstart + k, to = H.base + alive + done + (uint32_t)__popcll(m & lt);
           stv<MIX>(A.st, to, ldv<MIX>(A.born, from));
           A.st.sp[to] = A.born.sp[from];
-          for (uint32_t mo = 0; mo < mm; ++mo)
-            A.st.lvl[mo * A.st.stride + to] = A.born.lvl[mo * A.born.stride + from];
+          copy_levels(A.born, from, A.st, to);
           if constexpr (EX >= 1) {
             if (A.st.rot) A.st.rot[to] = A.born.rot[from];
             if (A.st.px) {
@@ -1970,7 +2029,7 @@ __device__ __forceinline__ void polar_normals(Rng &rng, double &n1, double &n2) 
 // energy): bends by the floor form, stretches by the uniform proposal with
 // the Boltzmann acceptance, then (rotors only) Gamma(zeta/2, k T_rot):
 // -ln(1 - u) plus, for zeta = 3, half the square of one polar normal. Writes
-// the levels (mode-major, stride st.stride) and the rotational energy of
+// the level row and the rotational energy of
 // slot g. The thermal initial state and admission through open faces draw
 // the same way.
 __device__ __forceinline__ void sample_internal(const SpeciesTab &S, const double *lev, Rng &rng, double tv,
@@ -2001,8 +2060,9 @@ __device__ __forceinline__ void sample_internal(const SpeciesTab &S, const doubl
         }
       }
     }
-    st.lvl[m * st.stride + g] = (uint16_t)l;
+    st.lvl[g * st.lrow + m] = (uint16_t)l;
   }
+  for (uint32_t m = mm; m < st.lrow; ++m) st.lvl[g * st.lrow + m] = 0;
   if (st.rot) {
     double e = 0.0;
     if (S.zeta_rot > 0) {
@@ -2166,7 +2226,7 @@ __global__ __launch_bounds__(256) void k_moments(MomentArgs A) {
     acc[4] += m;
     acc[5] += S.formation;
     double ev = 0.0;
-    for (uint32_t q = 0; q < S.n_modes; ++q) ev = ev + mode_energy(S, A.lev, q, A.st.lvl[q * A.st.stride + g]);
+    for (uint32_t q = 0; q < S.n_modes; ++q) ev = ev + mode_energy(S, A.lev, q, A.st.lvl[g * A.st.lrow + q]);
     const double er = A.st.rot ? A.st.rot[g] : 0.0;
 #pragma unroll
     for (int j = 0; j < kMaxSpecies; ++j) {
@@ -2385,7 +2445,7 @@ __global__ __launch_bounds__(256) void k_load_place(PlaceArgs A) {
   const uint32_t mm = A.tab->max_modes;
   store_vel(A.st, g, A.vel[3 * src], A.vel[3 * src + 1], A.vel[3 * src + 2]);
   A.st.sp[g] = A.sp[src];
-  for (uint32_t m = 0; m < mm; ++m) A.st.lvl[m * A.st.stride + g] = A.lvl[src * mm + m];
+  for (uint32_t m = 0; m < A.st.lrow; ++m) A.st.lvl[g * A.st.lrow + m] = m < mm ? A.lvl[src * mm + m] : (uint16_t)0;
   if (A.st.rot) A.st.rot[g] = A.rot ? A.rot[src] : 0.0;
   if (A.st.px) {
     A.st.px[g] = A.pos[3 * src];
@@ -2861,7 +2921,7 @@ __device__ __forceinline__ void copy_particle(const State &s, const State &d, ui
     d.vz[to] = s.vz[from];
   }
   d.sp[to] = s.sp[from];
-  for (uint32_t m = 0; m < mm; ++m) d.lvl[m * d.stride + to] = s.lvl[m * s.stride + from];
+  copy_levels(s, from, d, to);
   if (s.rot) d.rot[to] = s.rot[from];
   d.px[to] = s.px[from];
   d.py[to] = s.py[from];
@@ -2976,22 +3036,28 @@ hipError_t launch_advance(uint32_t *step, uint32_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t set_step_lds_limit(size_t bytes) {
+// the dynamic LDS limit of every k_step instantiation the launcher can pick
+// (block sizes 64..512, both precisions, levels 0..2)
+template <bool MIX, int EX>
+static hipError_t set_lds_limit_level(int bytes) {
   hipError_t e = hipSuccess;
-  const void *fns[] = {
-      (const void *)k_step<64, false, false>, (const void *)k_step<128, false, false>,
-      (const void *)k_step<256, false, false>, (const void *)k_step<512, false, false>,
-      (const void *)k_step<64, true, false>, (const void *)k_step<128, true, false>,
-      (const void *)k_step<256, true, false>, (const void *)k_step<512, true, false>,
-      (const void *)k_step<64, false, true>, (const void *)k_step<128, false, true>,
-      (const void *)k_step<256, false, true>, (const void *)k_step<512, false, true>,
-      (const void *)k_step<64, true, true>, (const void *)k_step<128, true, true>,
-      (const void *)k_step<256, true, true>, (const void *)k_step<512, true, true>};
+  const void *fns[] = {(const void *)k_step<64, MIX, EX>, (const void *)k_step<128, MIX, EX>,
+                       (const void *)k_step<256, MIX, EX>, (const void *)k_step<512, MIX, EX>};
   for (const void *f : fns) {
-    hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (r != hipSuccess) e = r;
   }
   return e;
+}
+
+hipError_t set_step_lds_limit(size_t bytes) {
+  const int b = (int)bytes;
+  const hipError_t r[] = {set_lds_limit_level<false, 0>(b), set_lds_limit_level<true, 0>(b),
+                          set_lds_limit_level<false, 1>(b), set_lds_limit_level<true, 1>(b),
+                          set_lds_limit_level<false, 2>(b), set_lds_limit_level<true, 2>(b)};
+  for (hipError_t e : r)
+    if (e != hipSuccess) return e;
+  return hipSuccess;
 }
 
 hipError_t launch_init(const Tables *tab, const double *lev, const State &st, const uint64_t *off,

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -347,16 +348,16 @@ uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
 // staging state of the admissions through open faces (stride ins_cap)
 State ins_state(hcao_ctx *c) {
   return State{c->ivx.p, c->ivy.p, c->ivz.p, c->ifx.p, c->ify.p, c->ifz.p, c->isp.p, c->ilvl.p, c->irot.p,
-               c->ipx.p, c->ipy.p, c->ipz.p, c->ins_cap};
+               c->ipx.p, c->ipy.p, c->ipz.p, level_row(c->max_modes)};
 }
 
 State state_of(hcao_ctx *c) {
   return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->rot.p,
-               c->px.p, c->py.p, c->pz.p, c->total_slots};
+               c->px.p, c->py.p, c->pz.p, level_row(c->max_modes)};
 }
 State staging_of(hcao_ctx *c) {
   return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->brot.p,
-               c->bpx.p, c->bpy.p, c->bpz.p, c->total_slots};
+               c->bpx.p, c->bpy.p, c->bpz.p, level_row(c->max_modes)};
 }
 CellArrays cells_of(hcao_ctx *c) {
   return CellArrays{c->off.p,    c->cnt.p, c->cap.p,    c->d_volume.p, c->d_weight.p,
@@ -528,7 +529,7 @@ hipError_t grow_ins(hcao_ctx *c, uint64_t n) {
   hipError_t e;
   if ((e = alloc_vel(c, c->ivx, c->ivy, c->ivz, c->ifx, c->ify, c->ifz, cap)) != hipSuccess) return e;
   if ((e = c->isp.alloc(cap)) != hipSuccess) return e;
-  if ((e = c->ilvl.alloc(cap * mm)) != hipSuccess) return e;
+  if ((e = c->ilvl.alloc(cap * level_row(mm))) != hipSuccess) return e;
   if (c->tab.has_rot && (e = c->irot.alloc(cap)) != hipSuccess) return e;
   if ((e = c->ipx.alloc(cap)) != hipSuccess) return e;
   if ((e = c->ipy.alloc(cap)) != hipSuccess) return e;
@@ -560,7 +561,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   const uint32_t mm = c->max_modes ? c->max_modes : 1;
   HIP_TRY(c, alloc_vel(c, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz, tot));
   HIP_TRY(c, c->sp.alloc(tot));
-  HIP_TRY(c, c->lvl.alloc(tot * mm));
+  HIP_TRY(c, c->lvl.alloc(tot * level_row(mm)));
   if (c->tab.has_rot) {
     HIP_TRY(c, c->rot.alloc(tot));
     HIP_TRY(c, c->brot.alloc(tot));
@@ -597,7 +598,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   if (c->tab.has_recomb) HIP_TRY(c, c->tsum.alloc(5 * (size_t)nc));
   HIP_TRY(c, c->ctr.alloc((size_t)nc * kNumCtr));
   HIP_TRY(c, hipMemsetAsync(c->defect.p, 0, nc * sizeof(double), c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->lvl.p, 0, tot * mm * sizeof(uint16_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->lvl.p, 0, tot * level_row(mm) * sizeof(uint16_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->ctr.p, 0, (size_t)nc * kNumCtr * sizeof(unsigned long long), c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->off.p, c->off_host.data(), (nc + 1) * sizeof(uint64_t), hipMemcpyHostToDevice,
                             c->stream));
@@ -610,7 +611,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
   // products staging (indexed like the state)
   HIP_TRY(c, alloc_vel(c, c->bvx, c->bvy, c->bvz, c->bfx, c->bfy, c->bfz, tot));
   HIP_TRY(c, c->bsp.alloc(tot));
-  HIP_TRY(c, c->blvl.alloc(tot * mm));
+  HIP_TRY(c, c->blvl.alloc(tot * level_row(mm)));
   if (hcao_status st = build_groups(c)) return st;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return HCAO_OK;
@@ -1035,6 +1036,32 @@ hcao_status hcao_finalize(hcao_ctx *c) {
         }
       }
       T.pr[a][b].react = react;
+      // channel bounds for the scan's skip test (scan order: dissociation of
+      // a then b, exchange with a then b as A)
+      PairBound &pb = T.pr[a][b].bound;
+      pb.n_steric = 0;
+      for (uint32_t side = 0; side < 2; ++side) {
+        const uint32_t sa = side ? b : a, sb = side ? a : b;
+        pb.dis_c[side] = -std::numeric_limits<double>::infinity();
+        pb.ex_a[side] = -1.0;
+        pb.ex_e[side] = std::numeric_limits<double>::infinity();
+        const SpeciesHost &A = c->species[sa];
+        for (const ReactionHost &h : c->reactions) {
+          if (h.d.kind == HCAO_RX_DISSOCIATION && (uint32_t)h.d.reactant[0] == sa) {
+            const double zsum = (A.zpe + c->species[h.d.product[0]].zpe) + c->species[h.d.product[1]].zpe;
+            for (uint32_t j = 0; j < A.d.n_stretch; ++j)
+              if ((h.d.stretch_mask >> j) & 1ull)
+                pb.dis_c[side] = std::max(pb.dis_c[side], (A.levels[j][0] - A.de[j]) - zsum);
+          } else if (h.d.kind == HCAO_RX_EXCHANGE && (uint32_t)h.d.reactant[0] == sa &&
+                     (uint32_t)h.d.reactant[1] == sb) {
+            ++pb.n_steric;
+            double amax = 0.0;
+            for (double x : h.alpha) amax = std::max(amax, x);
+            pb.ex_a[side] = std::max(pb.ex_a[side], amax);
+            pb.ex_e[side] = std::min(pb.ex_e[side], h.d.Ea_J);
+          }
+        }
+      }
     }
   // exact sampler: one beta table per (species, LB exponent), shared by the
   // pairs that use it
@@ -1471,9 +1498,9 @@ uint64_t static_layout(const hcao_ctx *c, unsigned char *base, StepScratch &out)
     b.vz = reinterpret_cast<double *>(take(w * sizeof(double)));
   }
   b.sp = take(w);
-  b.lvl = reinterpret_cast<uint16_t *>(take(w * mm * sizeof(uint16_t)));
+  b.lrow = level_row(mm);
+  b.lvl = reinterpret_cast<uint16_t *>(take(w * b.lrow * sizeof(uint16_t)));
   if (c->tab.has_rot) b.rot = reinterpret_cast<double *>(take(w * sizeof(double)));
-  b.stride = w;
   return at;
 }
 
@@ -1775,48 +1802,56 @@ hcao_status hcao_autotune(hcao_ctx *c, double dt, uint32_t trial_steps, const ch
   if (!found) {
     Snapshot S, W;
     if (hcao_status s = snapshot(c, S, true)) return s;
+    const hcao_launch_shape orig{(uint32_t)c->block, c->group_slots, spl >= (1u << 30) ? 0u : spl};
+    const bool was_timing = c->timing;
+    double best_ms = 0.0;
     // candidates are timed from a copy advanced past the first steps, whose
     // (sigma g)_max still settles from its initial bound and would favour
-    // other shapes; the state before the call is put back at the end
-    const uint32_t warm = trial_steps > 10u ? trial_steps : 10u;
-    {
+    // other shapes
+    auto trials = [&]() -> hcao_status {
+      const uint32_t warm = trial_steps > 10u ? trial_steps : 10u;
       uint32_t launches = 0;
       if (hcao_status st = issue_steps(c, dt, warm, c->step, nullptr, c->stream, &launches)) return st;
       HIP_TRY(c, hipStreamSynchronize(c->stream));
       if (hcao_status e = read_err(c)) return e;
-    }
-    if (hcao_status s = snapshot(c, W, true)) return s;
-    const uint32_t blocks[] = {64, 128, 256};
-    const uint32_t slots[] = {256, 512, 1024, 2048, 4096};
-    const bool was_timing = c->timing;
-    double best_ms = 0.0;
-    for (uint32_t b : blocks) {
-      for (uint32_t g : slots) {
-        if (g < b) continue;
-        hcao_launch_shape t{b, g, spl >= (1u << 30) ? 0u : spl};
-        if (hcao_set_launch_shape(c, &t) != HCAO_OK) {
-          c->sticky = HCAO_OK;  // a shape whose LDS does not fit is skipped
-          continue;
+      if (hcao_status s = snapshot(c, W, true)) return s;
+      const uint32_t blocks[] = {64, 128, 256};
+      const uint32_t slots[] = {256, 512, 1024, 2048, 3072, 4096, 6144};
+      for (uint32_t b : blocks) {
+        for (uint32_t g : slots) {
+          if (g < b) continue;
+          hcao_launch_shape t{b, g, orig.steps_per_launch};
+          const hcao_status ss = hcao_set_launch_shape(c, &t);
+          if (ss == HCAO_EUNSUPPORTED) continue;  // its LDS does not fit: skipped
+          if (ss != HCAO_OK) return ss;
+          HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+          if (hcao_status st = issue_steps(c, dt, trial_steps, c->step + warm, nullptr, c->stream, &launches))
+            return st;
+          HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+          HIP_TRY(c, hipEventSynchronize(c->ev1));
+          float ms = 0.f;
+          HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+          if (hcao_status e = read_err(c)) return e;
+          if (!found || ms < best_ms) {
+            best_ms = ms;
+            best = t;
+            found = true;
+          }
+          if (hcao_status s = snapshot(c, W, false)) return s;
         }
-        HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
-        uint32_t launches = 0;
-        hcao_status st = issue_steps(c, dt, trial_steps, c->step + warm, nullptr, c->stream, &launches);
-        if (st) return st;
-        HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
-        HIP_TRY(c, hipEventSynchronize(c->ev1));
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        if (hcao_status e = read_err(c)) return e;
-        if (!found || ms < best_ms) {
-          best_ms = ms;
-          best = t;
-          found = true;
-        }
-        if (hcao_status s = snapshot(c, W, false)) return s;
       }
-    }
-    if (hcao_status s = snapshot(c, S, false)) return s;
+      return HCAO_OK;
+    };
+    const hcao_status tried = trials();
+    // every way out puts back the state before the call; a failed search also
+    // its launch shape (a device error stays sticky)
     c->timing = was_timing;
+    const hcao_status back = snapshot(c, S, false);
+    if (tried != HCAO_OK) {
+      if (c->sticky == HCAO_OK) (void)hcao_set_launch_shape(c, &orig);
+      return tried;
+    }
+    if (back != HCAO_OK) return back;
     if (cache_path) {
       if (FILE *f = std::fopen(cache_path, "a")) {
         std::fprintf(f, "%s block=%u group_slots=%u ms_per_step=%.6g\n", key.c_str(), best.block, best.group_slots,
@@ -1862,7 +1897,7 @@ hcao_status hcao_read_cell_particles(hcao_ctx *c, uint32_t cell, uint32_t max_n,
   if (!c || (max_n && (!species || !vel || !levels))) return HCAO_EINVAL;
   if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
   if (cell >= c->cfg.n_cells) return fail(c, HCAO_EINVAL, "cell index out of range");
-  const uint64_t tot = c->total_slots, b = c->off_host[cell];
+  const uint64_t b = c->off_host[cell];
   const uint32_t mm = c->max_modes ? c->max_modes : 1;
   uint32_t n = 0;
   HIP_TRY(c, hipMemcpyAsync(&n, c->cnt.p + cell, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
@@ -1871,7 +1906,8 @@ hcao_status hcao_read_cell_particles(hcao_ctx *c, uint32_t cell, uint32_t max_n,
   const uint32_t k = std::min(n, max_n);
   if (k == 0) return HCAO_OK;
   std::vector<double> v(3 * (size_t)k);
-  std::vector<uint16_t> lv((size_t)k * mm);
+  const uint32_t lr = level_row(c->max_modes);
+  std::vector<uint16_t> lv((size_t)k * lr);
   if (c->mixed) {
     std::vector<float> f(3 * (size_t)k);
     HIP_TRY(c, hipMemcpyAsync(f.data(), c->fx.p + b, k * 4, hipMemcpyDeviceToHost, c->stream));
@@ -1885,15 +1921,13 @@ hcao_status hcao_read_cell_particles(hcao_ctx *c, uint32_t cell, uint32_t max_n,
     HIP_TRY(c, hipMemcpyAsync(v.data() + 2 * (size_t)k, c->vz.p + b, k * 8, hipMemcpyDeviceToHost, c->stream));
   }
   HIP_TRY(c, hipMemcpyAsync(species, c->sp.p + b, k, hipMemcpyDeviceToHost, c->stream));
-  for (uint32_t m = 0; m < mm; ++m)
-    HIP_TRY(c, hipMemcpyAsync(lv.data() + (size_t)m * k, c->lvl.p + (size_t)m * tot + b, k * 2, hipMemcpyDeviceToHost,
-                              c->stream));
+  HIP_TRY(c, hipMemcpyAsync(lv.data(), c->lvl.p + b * lr, (size_t)k * lr * 2, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (uint32_t i = 0; i < k; ++i) {
     vel[3 * i] = v[i];
     vel[3 * i + 1] = v[k + i];
     vel[3 * i + 2] = v[2 * (size_t)k + i];
-    for (uint32_t m = 0; m < mm; ++m) levels[(size_t)i * mm + m] = lv[(size_t)m * k + i];
+    for (uint32_t m = 0; m < mm; ++m) levels[(size_t)i * mm + m] = lv[(size_t)i * lr + m];
   }
   return HCAO_OK;
 }
@@ -1905,11 +1939,12 @@ hcao_status hcao_read_particles(hcao_ctx *c, uint8_t *species, double *vel, uint
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
   std::vector<double> vx(tot), vy(tot), vz(tot);
   std::vector<uint8_t> sp(tot);
-  std::vector<uint16_t> lv(tot * mm);
+  const uint32_t lr = level_row(c->max_modes);
+  std::vector<uint16_t> lv(tot * lr);
   std::vector<uint32_t> cnt(nc);
   if (hcao_status s = download_vel(c, vx, vy, vz)) return s;
   HIP_TRY(c, hipMemcpyAsync(sp.data(), c->sp.p, tot, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(lv.data(), c->lvl.p, tot * mm * 2, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(lv.data(), c->lvl.p, tot * lr * 2, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   uint64_t j = 0;
@@ -1921,7 +1956,7 @@ hcao_status hcao_read_particles(hcao_ctx *c, uint8_t *species, double *vel, uint
       vel[3 * j] = vx[g];
       vel[3 * j + 1] = vy[g];
       vel[3 * j + 2] = vz[g];
-      for (uint32_t m = 0; m < mm; ++m) levels[j * mm + m] = lv[m * tot + g];
+      for (uint32_t m = 0; m < mm; ++m) levels[j * mm + m] = lv[g * lr + m];
     }
   }
   return HCAO_OK;
@@ -2241,7 +2276,14 @@ hcao_status hcao_save(hcao_ctx *c, const char *path) {
   if (hcao_status s = download_vel(c, vx, vy, vz)) return s;
   HIP_TRY(c, hipMemcpy(df.data(), c->defect.p, nc * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(sp.data(), c->sp.p, tot, hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(lv.data(), c->lvl.p, tot * mm * 2, hipMemcpyDeviceToHost));
+  {
+    // the file holds n x max_modes rows; the device rows are level_row long
+    const uint32_t lr = level_row(c->max_modes);
+    std::vector<uint16_t> rows(tot * lr);
+    HIP_TRY(c, hipMemcpy(rows.data(), c->lvl.p, tot * lr * 2, hipMemcpyDeviceToHost));
+    for (uint64_t g = 0; g < tot; ++g)
+      for (uint32_t m = 0; m < mm; ++m) lv[g * mm + m] = rows[g * lr + m];
+  }
   HIP_TRY(c, hipMemcpy(cnt.data(), c->cnt.p, nc * 4, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(sg.data(), c->sgmax.p, nc * 8, hipMemcpyDeviceToHost));
   HIP_TRY(c, hipMemcpy(rm.data(), c->rem.p, nc * 8, hipMemcpyDeviceToHost));
@@ -2344,7 +2386,13 @@ hcao_status hcao_restore(hcao_ctx *c, const char *path) {
   if (hcao_status s = upload_vel(c, vx, vy, vz)) return s;
   HIP_TRY(c, hipMemcpy(c->defect.p, df.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->sp.p, sp.data(), tot, hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->lvl.p, lv.data(), tot * mm * 2, hipMemcpyHostToDevice));
+  {
+    const uint32_t lr = level_row(c->max_modes);
+    std::vector<uint16_t> rows(tot * lr, 0);
+    for (uint64_t g = 0; g < tot; ++g)
+      for (uint32_t m = 0; m < mm; ++m) rows[g * lr + m] = lv[g * mm + m];
+    HIP_TRY(c, hipMemcpy(c->lvl.p, rows.data(), tot * lr * 2, hipMemcpyHostToDevice));
+  }
   HIP_TRY(c, hipMemcpy(c->sgmax.p, sg.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->rem.p, rm.data(), nc * 8, hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->ctr.p, ctr.data(), ctr.size() * 8, hipMemcpyHostToDevice));

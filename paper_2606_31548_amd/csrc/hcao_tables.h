@@ -45,10 +45,24 @@ constexpr uint32_t kWorkFound = 7;
 constexpr uint32_t kWorkSorted = 6;
 constexpr uint32_t kWorkWords = kWorkFound + kWorkSorted;
 
+// Bounds of the pair's dissociation and exchange channels, per side (0: a is
+// A, 1: b is A), for the test that lets a pair skip the channel scan when no
+// channel can open: a dissociation channel's excess energy is at most
+// (E_tr + E_rot,A) + E_vib,A + dis_c[side], an exchange channel's at most
+// (E_tr + E_rot,A) + ex_a[side] E_vib,A - ex_e[side] (its alpha-weighted
+// energy is at most alpha_max E_vib,A); -inf / ex_a < 0 mark no channel.
+// n_steric: the scan's steric draws, one per exchange reaction matched on
+// either side, whether or not anything opens.
+struct PairBound {
+  double dis_c[2], ex_a[2], ex_e[2];
+  uint32_t n_steric, pad;
+};
+
 struct PairTab {
   double mr, hm, m_a, m_b, msum, wa, wb, csg, esg, q;
   uint32_t react;     // kReact* bits
   uint32_t beta_off;  // exact sampler: offset of the beta table of species a with exponent q
+  PairBound bound;
 };
 
 // Recombination B + C (+M) -> A (+M) is stored with a = B, b = C, c = A,
@@ -89,10 +103,12 @@ struct Tables {
 };
 
 // Particle state in HBM: structure of arrays, cell-major segments with
-// per-cell slot capacity. Slot i of cell c lives at index off[c] + i;
-// level of mode m at lvl[m * stride + index]. Velocities are fp64 (vx, vy,
-// vz) in the fp64 form and fp32 (fx, fy, fz) in the mixed form; the other
-// set is null.
+// per-cell slot capacity. Slot i of cell c lives at index off[c] + i. The
+// quantum numbers of a slot are one row of lrow uint16 (lrow = max_modes
+// rounded up to even, so rows are dword aligned): mode m at lvl[index *
+// lrow + m], modes the species does not have (and the padding) 0.
+// Velocities are fp64 (vx, vy, vz) in the fp64 form and fp32 (fx, fy, fz)
+// in the mixed form; the other set is null.
 struct State {
   double *vx, *vy, *vz;
   float *fx, *fy, *fz;
@@ -100,8 +116,11 @@ struct State {
   uint16_t *lvl;
   double *rot;      // rotational energy [J]; null when no species has a rotor
   double *px, *py, *pz;  // positions [m]; null outside the spatial mode
-  uint64_t stride;  // total slots (all cells)
+  uint32_t lrow;    // uint16 per level row (even)
 };
+
+// level row length for max_modes modes: even, at least 2
+inline uint32_t level_row(uint32_t max_modes) { return max_modes < 2 ? 2u : (max_modes + 1u) & ~1u; }
 
 struct CellArrays {
   const uint64_t *off;

@@ -500,6 +500,31 @@ def measure_sequential(hcao, torch, wl, steps):
             "launches_per_step": wl.n_cells}
 
 
+def batched_leg(hcao, torch, steps):
+    """The batched-reservoir workload beside the headline: its mixed and fp64
+    forms through the captured graph at the tuned launch shape (steps timed
+    after as many warm-up steps), their energy drift, and the same reservoirs
+    stepped one launch per reservoir (fp64, two steps)."""
+    wl, desc = make_workload("batched")
+    wl.bench_name = "batched"
+    spl = math.gcd(steps, 50)
+    out = {"workload": desc, "cells": wl.n_cells, "particles": int(wl.n_particles), "steps": steps,
+           "warmup": steps, "launch_shape": {"block": TUNED_SHAPE["batched"][0],
+                                             "group_slots": TUNED_SHAPE["batched"][1], "steps_per_launch": spl}}
+    for f in ("mixed", "fp64"):
+        print(f"# batched reservoirs, {f} form: {steps} warm-up + {steps} steps", file=sys.stderr, flush=True)
+        r = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, steps, steps, spl, graph=True,
+                    shape=TUNED_SHAPE["batched"])
+        out[f] = {k: r[k] for k in ("collisions_per_s", "particle_steps_per_s", "ms_per_step", "energy_drift",
+                                    "T_trans_K", "reactions")}
+    out["mixed_vs_fp64"] = out["mixed"]["collisions_per_s"] / out["fp64"]["collisions_per_s"]
+    print("# batched reservoirs, one launch per reservoir (fp64)", file=sys.stderr, flush=True)
+    seq = measure_sequential(hcao, torch, wl, 2)
+    out["sequential_fp64"] = seq
+    out["batched_vs_sequential_fp64"] = out["fp64"]["collisions_per_s"] / seq["collisions_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -524,6 +549,9 @@ def main():
     ap.add_argument("--recomb-exact", action="store_true",
                     help="also time Eq. recomb-correct for CH4 on the device against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batched-steps", type=int, default=50,
+                    help="chemistry workloads: steps of the batched-reservoir leg (mixed and fp64, captured "
+                         "graph, after as many warm-up steps) reported beside the headline; 0 skips it")
     ap.add_argument("--precision-steps", type=int, default=10000,
                     help="steps of the untimed precision report (both forms from the same initial state: energy "
                          "drift, temperatures, species and reaction counts of mixed against fp64); 0 skips it")
@@ -612,6 +640,8 @@ def main():
         out["sequential_fp64"] = seq
         if "fp64" in res:
             out["batched_vs_sequential_fp64"] = res["fp64"]["collisions_per_s"] / seq["collisions_per_s"]
+    if args.batched_steps > 0 and args.workload in ("chemistry-67m", "chemistry-16m"):
+        out["batched"] = batched_leg(hcao, torch, args.batched_steps)
     if args.precision_steps > 0 and args.workload in ("chemistry-67m", "chemistry-16m"):
         out["precision_report"] = precision_report(hcao, torch, wl, args.precision_steps, spl)
     if args.recomb_exact:

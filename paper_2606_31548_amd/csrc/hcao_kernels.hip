@@ -1615,7 +1615,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       bflag[j] = 0;
       // VHS acceptance ua < sigma g / (sigma g)_max with sigma g = C (g^2)^(1-w).
       if constexpr (MIX) {
-        wdef[j] = 0.0;
         const float sg = (g2 > 0.0f) ? (float)PP.csg * pow_f(g2, (float)PP.esg) : 0.0f;
         const unsigned long long sb = (unsigned long long)__double_as_longlong((double)sg);
         if ((double)sg > H.sgmax && sb > hdr[g].sgbits) atomicMax(&hdr[g].sgbits, sb);
@@ -1861,10 +1860,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 
   // ---- phase C: deaths, products in pair order, per-cell state ----
   // one wave per cell: ballots give each survivor its new slot and each
-  // product its rank in pair order
+  // product its rank in pair order. In the mixed form the per-pair records
+  // of a cell's first 64 candidates are loaded while the wave still works
+  // on its previous cell, so that their latency overlaps it (the fp64 form
+  // has no registers to spare for it).
+  const bool records = MIX || A.tdelta != nullptr;
+  constexpr bool kPrefetch = MIX;
+  auto chunk_load = [&](uint32_t g, uint32_t k0, double (&y)[6], uint8_t &fl) {
+    const CellHdr &H = hdr[g];
+    const uint32_t k = k0 + lane;
+    const bool in = k < H.ncand;
+    const uint64_t e = wbase + H.cstart + k;
+    for (int x = 0; x < 6; ++x) y[x] = 0.0;
+    fl = 0;
+    if (MIX && in) fl = bflag[H.cstart + k];  // the mixed form's defect records need it too
+    if (A.tdelta && in) {
+      if (!MIX) fl = bflag[H.cstart + k];
+      for (int x = 0; x < 5; ++x) y[x] = A.tdelta[(size_t)x * A.tdelta_stride + e];
+    }
+    if (MIX && in) y[5] = wdef[H.cstart + k];
+  };
+  double ny[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  uint8_t nfl = 0;
+  if (kPrefetch && records && wave < ncell) chunk_load(wave, 0, ny, nfl);
   for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
     const CellHdr &H = hdr[g];
     const unsigned long long *in = l_ctr + (size_t)g * nctr;
+    double cy[6];
+    for (int x = 0; x < 6; ++x) cy[x] = ny[x];
+    const uint8_t cfl = nfl;
+    if (kPrefetch && records && g + BLOCK / 64 < ncell) chunk_load(g + BLOCK / 64, 0, ny, nfl);
     uint32_t alive = H.n;
     if (in[HCAO_CTR_DEATHS] != 0ull) {
       // stable in-place compaction: a chunk's survivors move to lower slots
@@ -1942,20 +1967,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     // candidate that did not collide contributes 0). A chunk's loads are all
     // issued before any is used.
     double dsum = 0.0, d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (MIX || A.tdelta) {
+    if (records) {
       for (uint32_t k0 = 0; k0 < H.ncand; k0 += 64) {
-        const uint32_t k = k0 + lane;
-        const bool in = k < H.ncand;
-        const uint64_t e = wbase + H.cstart + k;
-        double y[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        uint8_t fl = 0;
-        if (A.tdelta && in) {
-          fl = bflag[H.cstart + k];
-          for (int x = 0; x < 5; ++x) y[x] = A.tdelta[(size_t)x * A.tdelta_stride + e];
+        double y[6];
+        uint8_t fl;
+        if (kPrefetch && k0 == 0) {
+          for (int x = 0; x < 6; ++x) y[x] = cy[x];
+          fl = cfl;
+        } else {
+          chunk_load(g, k0, y, fl);
         }
-        if (MIX && in) y[5] = wdef[H.cstart + k];
+        // (a record that phase B did not write is ignored)
         if (!(fl & kFlagCollided))
-          for (int x = 0; x < 5; ++x) y[x] = 0.0;
+          for (int x = 0; x < (MIX ? 6 : 5); ++x) y[x] = 0.0;
         for (int s = 32; s >= 1; s >>= 1)
           for (int x = 0; x < 6; ++x) y[x] = y[x] + __shfl_down(y[x], s);
         for (int x = 0; x < 5; ++x) d[x] = d[x] + y[x];

@@ -1438,10 +1438,13 @@ template <int BLOCK, bool MIX, int EX>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_step(StepArgs A) {
   using R = Real<MIX>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ uint32_t s_nwork, s_total;
+  __shared__ uint32_t s_nwork, s_total, s_next;
   __shared__ uint32_t s_bin[256];
   const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & 63u, wave = tid >> 6;
+  // the wave index is the same on every lane of a wave: held in a scalar
+  // register, so that per-wave loops (one wave per cell) and what they
+  // address stay scalar
+  const uint32_t lane = tid & 63u, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const unsigned long long lt = lane ? ((1ull << lane) - 1ull) : 0ull;
   const Tables *GT = A.tab;
   const uint32_t ns = GT->n_species, nr = GT->n_reactions, mm = GT->max_modes, nl = GT->n_levels;
@@ -1576,6 +1579,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     }
     s_total = acc;
     s_nwork = 0;
+    s_next = 0;
   }
   __syncthreads();
   HCAO_PHASE_MARK(kPhaseTemperature);
@@ -1695,7 +1699,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   HCAO_PHASE_MARK(kPhaseSort);
 
   // ---- phase B: one accepted pair per lane ----
-  for (uint32_t i = tid; i < nwork; i += BLOCK) {
+  // Waves take 64 consecutive pairs of the sorted list at a time from a
+  // shared counter, so that a wave that drew light pairs takes the next
+  // block instead of waiting at the barrier for one that drew heavy ones.
+  for (;;) {
+    uint32_t c0 = 0;
+    if (lane == 0) c0 = atomicAdd(&s_next, 64u);
+    c0 = __builtin_amdgcn_readfirstlane(c0);  // every lane is active here: lane 0's value
+    if (c0 >= nwork) break;
+    const uint32_t i = c0 + lane;
+    if (i < nwork) {
 #ifdef HCAO_PHASE_CLOCKS
     PairLocal<MIX> P;
     for (int x = 0; x < 5; ++x) P.wclk[x] = 0;
@@ -1854,6 +1867,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     if (lead && A.clk)
       for (int x = 0; x < 5; ++x) atomicAdd(&A.clk[kPhaseCollideGather + x], (unsigned long long)P.wclk[x]);
 #endif
+    }
   }
   __syncthreads();
   HCAO_PHASE_MARK(kPhaseCollide);

@@ -78,7 +78,11 @@ typedef enum {
   HCAO_ELEVEL = -6,      /* quantum number above the top bound level, or a
                             nonzero level in an unused mode slot */
   HCAO_ENONFINITE = -7,  /* non-finite velocity */
-  HCAO_EUNSUPPORTED = -8 /* feature not available in this mode of the library */
+  HCAO_EUNSUPPORTED = -8, /* feature not available in this mode of the library */
+  HCAO_EBOUNDS = -9       /* bounds-checked build (libhcao_checked.so) only: a
+                             kernel formed a particle-slot or per-pair record
+                             index outside its array; the access was redirected
+                             to index 0, so the call's results are void. Sticky. */
 } hcao_status;
 
 /* Arithmetic of the step.

@@ -179,6 +179,20 @@ struct V3 {
 using Vec3 = V3<double>;
 
 // velocity of slot i in the state's own precision
+#ifdef HCAO_CHECKED
+// Bounds-checked builds: an index outside [0, n) raises kErrBounds and is
+// replaced by 0, so that no access leaves its array (the call then reports
+// HCAO_EBOUNDS and its results are void).
+__device__ __forceinline__ uint64_t checked_index(uint64_t i, uint64_t n, uint32_t *err) {
+  if (i < n) return i;
+  atomicOr(err, kErrBounds);
+  return 0;
+}
+#define HCAO_IDX(i, n, err) checked_index((i), (n), (err))
+#else
+#define HCAO_IDX(i, n, err) (i)
+#endif
+
 template <bool MIX>
 __device__ __forceinline__ V3<Real<MIX>> ldv(const State &s, uint64_t i) {
   if constexpr (MIX)
@@ -1603,7 +1617,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       const uint32_t p = perm(2 * k), qq = perm(2 * k + 1);
       pj = p;
       qj = qq;
-      const uint64_t gp = H.base + p, gq = H.base + qq;
+      const uint64_t gp = HCAO_IDX(H.base + p, A.st.n_slots, A.err), gq = HCAO_IDX(H.base + qq, A.st.n_slots, A.err);
       const V3<R> vp = ldv<MIX>(A.st, gp), vq = ldv<MIX>(A.st, gq);
       const R dx = vp.x - vq.x, dy = vp.y - vq.y, dz = vp.z - vq.z;
       const R g2 = (dx * dx + dy * dy) + dz * dz;
@@ -1616,7 +1630,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       rw1 = rng.w1;
       rw2 = rng.w2;
       rw3 = rng.w3;
-      bflag[j] = 0;
+      bflag[HCAO_IDX(j, wcap, A.err)] = 0;
       // VHS acceptance ua < sigma g / (sigma g)_max with sigma g = C (g^2)^(1-w).
       if constexpr (MIX) {
         const float sg = (g2 > 0.0f) ? (float)PP.csg * pow_f(g2, (float)PP.esg) : 0.0f;
@@ -1650,7 +1664,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     if (lane == 0 && ma) wb = atomicAdd(&s_nwork, (uint32_t)__popcll(ma));
     wb = __shfl(wb, 0);
     if (acc) {
-      uint32_t *w = work_in + (size_t)kWorkFound * (wb + (uint32_t)__popcll(ma & lt));
+      uint32_t *w = work_in + (size_t)kWorkFound * HCAO_IDX(wb + (uint32_t)__popcll(ma & lt), wcap, A.err);
       w[0] = j;
       w[1] = pj;
       w[2] = qj;
@@ -1687,7 +1701,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   __syncthreads();
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
     const uint32_t *f = work_in + (size_t)kWorkFound * i;
-    uint32_t *w = work + (size_t)kWorkSorted * atomicAdd(&s_bin[f[3]], 1u);
+    uint32_t *w = work + (size_t)kWorkSorted * HCAO_IDX(atomicAdd(&s_bin[f[3]], 1u), wcap, A.err);
     w[0] = f[0];
     w[1] = f[1];
     w[2] = f[2];
@@ -1722,7 +1736,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     const uint32_t g = group_cell(hdr, ncell, j);
     const CellHdr &H = hdr[g];
     const uint32_t k = j - H.cstart;
-    const uint64_t gp = H.base + p, gq = H.base + qq;
+    const uint64_t gp = HCAO_IDX(H.base + p, A.st.n_slots, A.err), gq = HCAO_IDX(H.base + qq, A.st.n_slots, A.err);
     P.v0 = ldv<MIX>(A.st, gp);
     P.v1 = ldv<MIX>(A.st, gq);
     P.sp0 = A.st.sp[gp];
@@ -1750,7 +1764,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       // third body of pair k: the particle at permutation index 2 N_cand + k
       PermReg perm;
       perm.load(H.perm);
-      gm = H.base + perm(2 * H.ncand + k);
+      gm = HCAO_IDX(H.base + perm(2 * H.ncand + k), A.st.n_slots, A.err);
       P.has_m = true;
       P.sp_m = A.st.sp[gm];
       P.v_m = ldv<MIX>(A.st, gm);
@@ -1809,7 +1823,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (!P.dead1) ke_out = ke_out + kinetic(T.sp[P.sp1].mass, P.v1);
       if (P.born) ke_out = ke_out + kinetic(T.sp[P.nb_sp].mass, P.nb_v);
       if (P.m_moved) ke_out = ke_out + kinetic(T.sp[P.sp_m].mass, P.v_m);
-      wdef[j] = (ke_int - ke_out) - P.fold_used;
+      wdef[HCAO_IDX(j, wcap, A.err)] = (ke_int - ke_out) - P.fold_used;
     }
     if (A.tdelta) {
       // the pair's change of its cell's running sums: its particles after
@@ -1823,7 +1837,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (!P.dead1) add_terms(after, T.sp[P.sp1].mass, P.v1);
       if (P.m_moved) add_terms(after, T.sp[P.sp_m].mass, P.v_m);
       if (P.born) add_terms(after, T.sp[P.nb_sp].mass, P.nb_v);
-      for (int x = 0; x < 5; ++x) A.tdelta[(size_t)x * A.tdelta_stride + wbase + j] = after[x] - before[x];
+      const uint64_t e = HCAO_IDX(wbase + j, A.tdelta_stride, A.err);
+      for (int x = 0; x < 5; ++x) A.tdelta[(size_t)x * A.tdelta_stride + e] = after[x] - before[x];
     }
     stv<MIX>(A.st, gp, P.v0);
     stv<MIX>(A.st, gq, P.v1);
@@ -1847,7 +1862,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     }
     if (P.m_moved) stv<MIX>(A.st, gm, P.v_m);
     if (P.born) {
-      const uint64_t gb = wbase + j;
+      const uint64_t gb = HCAO_IDX(wbase + j, A.born.n_slots, A.err);
       stv<MIX>(A.born, gb, P.nb_v);
       A.born.sp[gb] = (uint8_t)P.nb_sp;
       store_levels(A.born, gb, mm, A.born.lrow, P.lvn, BLOCK);
@@ -1861,7 +1876,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         }
       }
     }
-    bflag[j] = (uint8_t)((P.born ? kFlagBorn : 0) | kFlagCollided);
+    bflag[HCAO_IDX(j, wcap, A.err)] = (uint8_t)((P.born ? kFlagBorn : 0) | kFlagCollided);
     HCAO_WAVE_MARK(P.wclk, kPhaseCollideWrite);
 #ifdef HCAO_PHASE_CLOCKS
     if (lead && A.clk)
@@ -1887,12 +1902,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     const uint64_t e = wbase + H.cstart + k;
     for (int x = 0; x < 6; ++x) y[x] = 0.0;
     fl = 0;
-    if (MIX && in) fl = bflag[H.cstart + k];  // the mixed form's defect records need it too
+    const uint32_t r = (uint32_t)HCAO_IDX(H.cstart + k, in ? wcap : ~0ull, A.err);
+    if (MIX && in) fl = bflag[r];  // the mixed form's defect records need it too
     if (A.tdelta && in) {
-      if (!MIX) fl = bflag[H.cstart + k];
+      if (!MIX) fl = bflag[r];
       for (int x = 0; x < 5; ++x) y[x] = A.tdelta[(size_t)x * A.tdelta_stride + e];
     }
-    if (MIX && in) y[5] = wdef[H.cstart + k];
+    if (MIX && in) y[5] = wdef[r];
   };
   double ny[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   uint8_t nfl = 0;
@@ -1911,10 +1927,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       uint32_t kept = 0;
       for (uint32_t i0 = 0; i0 < H.n; i0 += 64) {
         const uint32_t i = i0 + lane;
-        const uint64_t src = H.base + i;
+        const uint64_t src = HCAO_IDX(H.base + i, A.st.n_slots, A.err);
         const bool live = i < H.n && A.st.sp[src] != kDead;
         const unsigned long long m = __ballot(live);
-        const uint64_t dst = H.base + kept + (uint32_t)__popcll(m & lt);
+        const uint64_t dst = HCAO_IDX(H.base + kept + (uint32_t)__popcll(m & lt), A.st.n_slots, A.err);
         V3<R> v{R(0), R(0), R(0)};
         uint8_t spv = 0;
         if (live) {
@@ -1959,7 +1975,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         const bool f = k < H.ncand && (bflag[H.cstart + k] & kFlagBorn) != 0;
         const unsigned long long m = __ballot(f);
         if (f) {
-          const uint64_t from = wbase + H.cstart + k, to = H.base + alive + done + (uint32_t)__popcll(m & lt);
+          const uint64_t from = HCAO_IDX(wbase + H.cstart + k, A.born.n_slots, A.err),
+                         to = HCAO_IDX(H.base + alive + done + (uint32_t)__popcll(m & lt), A.st.n_slots, A.err);
           stv<MIX>(A.st, to, ldv<MIX>(A.born, from));
           A.st.sp[to] = A.born.sp[from];
           copy_levels(A.born, from, A.st, to);
@@ -3013,10 +3030,11 @@ __global__ __launch_bounds__(256) void k_rebin_place(RebinArgs A) {
       from = base + A.list[base + (p - below)];
     else
       from = A.mslot[A.sidx[lo + p - ns]];
+    const uint64_t to = HCAO_IDX(base + p, A.dst.n_slots, A.err);
     if (from < A.tot)
-      copy_particle(A.src, A.dst, from, base + p, A.mm);
+      copy_particle(A.src, A.dst, HCAO_IDX(from, A.src.n_slots, A.err), to, A.mm);
     else
-      copy_particle(A.ins, A.dst, from - A.tot, base + p, A.mm);
+      copy_particle(A.ins, A.dst, HCAO_IDX(from - A.tot, A.ins.n_slots, A.err), to, A.mm);
   }
 }
 

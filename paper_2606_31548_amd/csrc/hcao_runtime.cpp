@@ -4,6 +4,7 @@
 // device buffers of the structure-of-arrays particle state, and issues the
 // gfx950 kernels of hcao_kernels.hip on the context's stream.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -18,6 +19,18 @@
 #include "hcao.h"
 #include "hcao_host_tables.h"
 #include "hcao_tables.h"
+
+namespace {
+// A roctx range over one host-side phase of the library (the step, the
+// spatial move and re-bin, loads, moments, tuning), shown by rocprofv3
+// --marker-trace beside the kernels it launched.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
+}  // namespace
 
 namespace hcao {
 // kernels (hcao_kernels.hip)
@@ -347,17 +360,23 @@ uint32_t default_cap(const hcao_ctx *c, uint32_t n) {
 
 // staging state of the admissions through open faces (stride ins_cap)
 State ins_state(hcao_ctx *c) {
-  return State{c->ivx.p, c->ivy.p, c->ivz.p, c->ifx.p, c->ify.p, c->ifz.p, c->isp.p, c->ilvl.p, c->irot.p,
-               c->ipx.p, c->ipy.p, c->ipz.p, level_row(c->max_modes)};
+  State s{c->ivx.p, c->ivy.p, c->ivz.p, c->ifx.p, c->ify.p, c->ifz.p, c->isp.p, c->ilvl.p, c->irot.p,
+          c->ipx.p, c->ipy.p, c->ipz.p, level_row(c->max_modes)};
+  set_slots(s, c->ins_cap);
+  return s;
 }
 
 State state_of(hcao_ctx *c) {
-  return State{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->rot.p,
-               c->px.p, c->py.p, c->pz.p, level_row(c->max_modes)};
+  State s{c->vx.p, c->vy.p, c->vz.p, c->fx.p, c->fy.p, c->fz.p, c->sp.p, c->lvl.p, c->rot.p,
+          c->px.p, c->py.p, c->pz.p, level_row(c->max_modes)};
+  set_slots(s, c->total_slots);
+  return s;
 }
 State staging_of(hcao_ctx *c) {
-  return State{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->brot.p,
-               c->bpx.p, c->bpy.p, c->bpz.p, level_row(c->max_modes)};
+  State s{c->bvx.p, c->bvy.p, c->bvz.p, c->bfx.p, c->bfy.p, c->bfz.p, c->bsp.p, c->blvl.p, c->brot.p,
+          c->bpx.p, c->bpy.p, c->bpz.p, level_row(c->max_modes)};
+  set_slots(s, c->total_slots);
+  return s;
 }
 CellArrays cells_of(hcao_ctx *c) {
   return CellArrays{c->off.p,    c->cnt.p, c->cap.p,    c->d_volume.p, c->d_weight.p,
@@ -626,6 +645,10 @@ hcao_status read_err(hcao_ctx *c) {
   uint32_t e = 0;
   HIP_TRY(c, hipMemcpyAsync(&e, c->err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (e & kErrBounds) {
+    c->sticky = HCAO_EBOUNDS;
+    return fail(c, HCAO_EBOUNDS, "a kernel index left its array (bounds-checked build)");
+  }
   if (e & kErrCapacity) {
     c->sticky = HCAO_ECAPACITY;
     return fail(c, HCAO_ECAPACITY, "a cell exceeded its slot capacity");
@@ -795,6 +818,7 @@ const char *hcao_status_string(hcao_status s) {
     case HCAO_ELEVEL: return "invalid quantum number";
     case HCAO_ENONFINITE: return "non-finite velocity";
     case HCAO_EUNSUPPORTED: return "unsupported feature";
+    case HCAO_EBOUNDS: return "index outside its array (bounds-checked build)";
   }
   return "unknown status";
 }
@@ -1175,6 +1199,7 @@ hcao_status hcao_finalize(hcao_ctx *c) {
 
 hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, const uint8_t *species,
                                 const double *vel, const uint16_t *levels, const double *rot, const double *pos) {
+  Range range("hcao_load_particles");
   if (!c) return HCAO_EINVAL;
   if (hcao_status s = check_sticky(c)) return s;
   if (!c->finalized) return fail(c, HCAO_ESTATE, "load before finalize");
@@ -1269,6 +1294,7 @@ hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, c
 }
 
 hcao_status hcao_init_thermal(hcao_ctx *c, const uint32_t *counts, const double *t_trans, const double *t_vib) {
+  Range range("hcao_init_thermal");
   if (!c || !counts || !t_trans || !t_vib) return HCAO_EINVAL;
   if (hcao_status s = check_sticky(c)) return s;
   if (!c->finalized) return fail(c, HCAO_ESTATE, "init before finalize");
@@ -1333,6 +1359,7 @@ StepArgs step_args(hcao_ctx *c, double dt) {
 // stable radix sort on the new cell into the staging buffers, which then
 // become the state (the old state becomes the products staging)
 hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
+  Range range("hcao_move_rebin");
   const uint32_t nc = c->cfg.n_cells, mm = c->max_modes ? c->max_modes : 1;
   const uint32_t ns = (uint32_t)c->species.size();
   const uint64_t tot = c->total_slots, faces = (uint64_t)c->face_base[6] * ns;
@@ -1498,6 +1525,7 @@ uint64_t static_layout(const hcao_ctx *c, unsigned char *base, StepScratch &out)
     b.vz = reinterpret_cast<double *>(take(w * sizeof(double)));
   }
   b.sp = take(w);
+  set_slots(b, w);
   b.lrow = level_row(mm);
   b.lvl = reinterpret_cast<uint16_t *>(take(w * b.lrow * sizeof(uint16_t)));
   if (c->tab.has_rot) b.rot = reinterpret_cast<double *>(take(w * sizeof(double)));
@@ -1578,6 +1606,7 @@ void drop_graph(hcao_ctx *c) {
 }  // namespace
 
 hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
+  Range range("hcao_step");
   if (hcao_status s = check_step_args(c, dt)) return s;
   if (hcao_status s = timing_begin(c)) return s;
   uint32_t launches = 0;
@@ -1587,6 +1616,7 @@ hcao_status hcao_step(hcao_ctx *c, double dt, uint32_t n_steps) {
 }
 
 hcao_status hcao_step_static(hcao_ctx *c, double dt, uint32_t n_steps) {
+  Range range("hcao_step_static");
   if (hcao_status s = check_step_args(c, dt)) return s;
   if (c->spatial)
     return fail(c, HCAO_EUNSUPPORTED,
@@ -1609,6 +1639,7 @@ hcao_status hcao_step_static(hcao_ctx *c, double dt, uint32_t n_steps) {
 }
 
 hcao_status hcao_step_graph(hcao_ctx *c, double dt, uint32_t n_steps) {
+  Range range("hcao_step_graph");
   if (hcao_status s = check_step_args(c, dt)) return s;
   if (c->spatial) return fail(c, HCAO_EUNSUPPORTED, "graph replay is not available in the spatial mode");
   if (n_steps == 0) return HCAO_OK;
@@ -1775,6 +1806,7 @@ std::string tune_key(const hcao_ctx *c) {
 
 hcao_status hcao_autotune(hcao_ctx *c, double dt, uint32_t trial_steps, const char *cache_path,
                           hcao_launch_shape *chosen) {
+  Range range("hcao_autotune");
   if (hcao_status s = check_step_args(c, dt)) return s;
   if (c->spatial) return fail(c, HCAO_EUNSUPPORTED, "autotuning is not available in the spatial mode");
   if (trial_steps == 0) return fail(c, HCAO_EINVAL, "trial_steps must be > 0");
@@ -1991,6 +2023,7 @@ hcao_status hcao_read_cell_state(hcao_ctx *c, double *sgmax, double *rem, uint64
 }
 
 hcao_status hcao_read_moments(hcao_ctx *c, hcao_moments *per_cell, hcao_moments *total) {
+  Range range("hcao_read_moments");
   if (!c) return HCAO_EINVAL;
   if (!c->loaded) return fail(c, HCAO_ESTATE, "no particles");
   const uint32_t nc = c->cfg.n_cells, ns = (uint32_t)c->species.size();
@@ -2099,6 +2132,7 @@ hcao_status hcao_get_recombination_table(const hcao_ctx *c, uint32_t reaction, d
 
 hcao_status hcao_recombination_exact(hcao_ctx *c, uint32_t species, double de_J, double omega, uint32_t n_t,
                                      const double *t_K, double *p_out, double *elapsed_ms, uint64_t *n_records) {
+  Range range("hcao_recombination_exact");
   if (!c || !c->finalized || species >= c->species.size() || (n_t && (!t_K || !p_out))) return HCAO_EINVAL;
   for (uint32_t i = 0; i < n_t; ++i)
     if (!(t_K[i] > 0.0)) return fail(c, HCAO_EINVAL, "temperatures must be positive");

@@ -21,6 +21,7 @@ constexpr uint32_t kErrCapacity = 1u;
 constexpr uint32_t kErrInvalid = 2u;
 constexpr uint32_t kErrLevel = 4u;
 constexpr uint32_t kErrNonFinite = 8u;
+constexpr uint32_t kErrBounds = 16u;  // bounds-checked builds: an index outside its array
 
 struct SpeciesTab {
   double mass, zpe, formation, p_vib, p_rot;
@@ -117,7 +118,20 @@ struct State {
   double *rot;      // rotational energy [J]; null when no species has a rotor
   double *px, *py, *pz;  // positions [m]; null outside the spatial mode
   uint32_t lrow;    // uint16 per level row (even)
+#ifdef HCAO_CHECKED
+  uint64_t n_slots;  // slots the arrays hold: the bounds-checked build tests slot indices against it
+#endif
 };
+
+// records how many slots the arrays of s hold (bounds-checked builds only)
+inline void set_slots(State &s, uint64_t n) {
+#ifdef HCAO_CHECKED
+  s.n_slots = n;
+#else
+  (void)s;
+  (void)n;
+#endif
+}
 
 // level row length for max_modes modes: even, at least 2
 inline uint32_t level_row(uint32_t max_modes) { return max_modes < 2 ? 2u : (max_modes + 1u) & ~1u; }

@@ -30,7 +30,8 @@ CTR_REACTION0 = 8
 FP64, MIXED = 0, 1
 
 STATUS = {0: "HCAO_OK", -1: "HCAO_EINVAL", -2: "HCAO_ESTATE", -3: "HCAO_ENOMEM", -4: "HCAO_EDEVICE",
-          -5: "HCAO_ECAPACITY", -6: "HCAO_ELEVEL", -7: "HCAO_ENONFINITE", -8: "HCAO_EUNSUPPORTED"}
+          -5: "HCAO_ECAPACITY", -6: "HCAO_ELEVEL", -7: "HCAO_ENONFINITE", -8: "HCAO_EUNSUPPORTED",
+          -9: "HCAO_EBOUNDS"}
 
 _d, _u32, _u64, _i32 = ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
 _vp = ctypes.c_void_p

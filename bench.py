@@ -66,6 +66,10 @@ WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "tria
 TUNED_SHAPE = {"chemistry-67m": (128, 3072), "chemistry-16m": (128, 3072), "methane-argon": (64, 1024),
                "batched": (256, 4096), "triatomic": (64, 1024), "box-67m": (128, 3072),
                "box-inflow-67m": (128, 3072)}
+# the batched leg of the default run, per form: 512-lane workgroups suit the
+# fp64 form's large reservoirs (4.8 against 5.0 ms per step) and not the
+# mixed form's (6.8 against 4.5)
+BATCHED_LEG_SHAPE = {"mixed": (256, 4096), "fp64": (512, 8192)}
 
 
 def make_workload(name):
@@ -509,14 +513,15 @@ def batched_leg(hcao, torch, steps):
     wl.bench_name = "batched"
     spl = math.gcd(steps, 50)
     out = {"workload": desc, "cells": wl.n_cells, "particles": int(wl.n_particles), "steps": steps,
-           "warmup": steps, "launch_shape": {"block": TUNED_SHAPE["batched"][0],
-                                             "group_slots": TUNED_SHAPE["batched"][1], "steps_per_launch": spl}}
+           "warmup": steps}
     for f in ("mixed", "fp64"):
         print(f"# batched reservoirs, {f} form: {steps} warm-up + {steps} steps", file=sys.stderr, flush=True)
+        shape = BATCHED_LEG_SHAPE[f]
         r = measure(hcao, torch, wl, hcao.MIXED if f == "mixed" else hcao.FP64, steps, steps, spl, graph=True,
-                    shape=TUNED_SHAPE["batched"])
+                    shape=shape)
         out[f] = {k: r[k] for k in ("collisions_per_s", "particle_steps_per_s", "ms_per_step", "energy_drift",
                                     "T_trans_K", "reactions")}
+        out[f]["launch_shape"] = {"block": shape[0], "group_slots": shape[1], "steps_per_launch": spl}
     out["mixed_vs_fp64"] = out["mixed"]["collisions_per_s"] / out["fp64"]["collisions_per_s"]
     print("# batched reservoirs, one launch per reservoir (fp64)", file=sys.stderr, flush=True)
     seq = measure_sequential(hcao, torch, wl, 2)

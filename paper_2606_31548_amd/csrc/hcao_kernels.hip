@@ -344,6 +344,43 @@ __device__ __forceinline__ void copy_levels(const State &src, uint64_t from, con
   for (uint32_t w = 0; w < src.lrow / 2; ++w) b[w] = a[w];
 }
 
+// The value lane + S holds, delivered to the lanes that a halving tree
+// reads at level S (lane < S); other lanes receive arbitrary values. VALU
+// cross-lane moves of gfx950 instead of LDS-routed shuffles: the 32- and
+// 16-lane swaps for S = 32 and 16, DPP row shifts for S = 8 .. 1.
+template <int S>
+__device__ __forceinline__ uint32_t lane_down(uint32_t v) {
+  if constexpr (S == 32)
+    return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+  else if constexpr (S == 16)
+    return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x100 + S, 0xF, 0xF, false);
+}
+template <int S>
+__device__ __forceinline__ double tree_down(double v) {
+  const uint32_t lo = lane_down<S>((uint32_t)__double2loint(v));
+  const uint32_t hi = lane_down<S>((uint32_t)__double2hiint(v));
+  return __hiloint2double((int)hi, (int)lo);
+}
+// Halving tree over the 64 lanes of a wave (lane t adds lane t + s, s = 32
+// .. 1): lane 0 ends with the sum, in that order; every lane must be active.
+template <int N>
+__device__ __forceinline__ void tree_sum(double (&y)[N]) {
+#pragma unroll
+  for (int x = 0; x < N; ++x) y[x] = y[x] + tree_down<32>(y[x]);
+#pragma unroll
+  for (int x = 0; x < N; ++x) y[x] = y[x] + tree_down<16>(y[x]);
+#pragma unroll
+  for (int x = 0; x < N; ++x) y[x] = y[x] + tree_down<8>(y[x]);
+#pragma unroll
+  for (int x = 0; x < N; ++x) y[x] = y[x] + tree_down<4>(y[x]);
+#pragma unroll
+  for (int x = 0; x < N; ++x) y[x] = y[x] + tree_down<2>(y[x]);
+#pragma unroll
+  for (int x = 0; x < N; ++x) y[x] = y[x] + tree_down<1>(y[x]);
+}
+
 constexpr double kFilter = 1e-4;
 
 __device__ __forceinline__ double pow_estimate(double x, double y) {
@@ -2011,8 +2048,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         // (a record that phase B did not write is ignored)
         if (!(fl & kFlagCollided))
           for (int x = 0; x < (MIX ? 6 : 5); ++x) y[x] = 0.0;
-        for (int s = 32; s >= 1; s >>= 1)
-          for (int x = 0; x < 6; ++x) y[x] = y[x] + __shfl_down(y[x], s);
+        tree_sum(y);  // only lane 0's sums are used below
         for (int x = 0; x < 5; ++x) d[x] = d[x] + y[x];
         dsum = dsum + y[5];
       }

@@ -1380,7 +1380,8 @@ __device__ int collide(const Ctx &C, PairLocal<MIX> &P, double g2, RngT<MIX> &rn
 // wave: lane t sums particles t, t + 64, t + 128, ... in slot order (loads
 // of four blocks issued together), then a halving tree (lane t takes lane
 // t + s for s = 32, ..., 1) combines the 64 partial sums; lane 0 returns
-// them. The running sums of the cell temperature start from these.
+// them (every lane of the wave takes part). The running sums of the cell
+// temperature start from these.
 template <bool MIX>
 __device__ void cell_sums(const State &st, const SpeciesTab *spt, uint64_t base, uint32_t n, uint32_t lane,
                           double out[5]) {
@@ -1413,18 +1414,9 @@ __device__ void cell_sums(const State &st, const SpeciesTab *spt, uint64_t base,
       }
     }
   }
-  for (int s = 32; s >= 1; s >>= 1) {
-    x0 = x0 + __shfl_down(x0, s);
-    x1 = x1 + __shfl_down(x1, s);
-    x2 = x2 + __shfl_down(x2, s);
-    x3 = x3 + __shfl_down(x3, s);
-    x4 = x4 + __shfl_down(x4, s);
-  }
-  out[0] = x0;
-  out[1] = x1;
-  out[2] = x2;
-  out[3] = x3;
-  out[4] = x4;
+  double x[5] = {x0, x1, x2, x3, x4};
+  tree_sum(x);
+  for (int q = 0; q < 5; ++q) out[q] = x[q];
 }
 
 // adds one particle's terms m, m v, m |v|^2 to acc (in that order)
@@ -1699,7 +1691,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     const unsigned long long ma = __ballot(acc);
     uint32_t wb = 0;
     if (lane == 0 && ma) wb = atomicAdd(&s_nwork, (uint32_t)__popcll(ma));
-    wb = __shfl(wb, 0);
+    wb = __builtin_amdgcn_readfirstlane(wb);  // every lane is active here: lane 0's value
     if (acc) {
       uint32_t *w = work_in + (size_t)kWorkFound * HCAO_IDX(wb + (uint32_t)__popcll(ma & lt), wcap, A.err);
       w[0] = j;

@@ -1574,6 +1574,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 
   // ---- phase 0: candidate counts and permutation keys of the step ----
   for (uint32_t i = tid; i < nctr * ncell; i += BLOCK) l_ctr[i] = 0ull;
+  for (uint32_t i = tid; i < 256; i += BLOCK) s_bin[i] = 0;  // the work-list sort's bins, counted in phase A
   for (uint32_t g = tid; g < ncell; g += BLOCK) {
     CellHdr &H = hdr[g];
     const uint32_t n = H.n;
@@ -1687,6 +1688,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       const uint32_t na = T.sp[a].n_modes < 15 ? T.sp[a].n_modes : 15;
       const uint32_t nb = T.sp[b].n_modes < 15 ? T.sp[b].n_modes : 15;
       key = 255u - (na * 16u + nb);
+      if (acc) atomicAdd(&s_bin[key], 1u);
     }
     const unsigned long long ma = __ballot(acc);
     uint32_t wb = 0;
@@ -1707,11 +1709,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   HCAO_PHASE_MARK(kPhaseAccept);
 
   // ---- counting sort of the work list by key ----
+  // (the bins were counted as phase A appended the pairs)
   const uint32_t nwork = s_nwork;
-  for (uint32_t i = tid; i < 256; i += BLOCK) s_bin[i] = 0;
-  __syncthreads();
-  for (uint32_t i = tid; i < nwork; i += BLOCK) atomicAdd(&s_bin[work_in[kWorkFound * i + 3]], 1u);
-  __syncthreads();
   if (tid < 64) {
     // exclusive scan of the 256 bins, four per lane
     const uint32_t b0 = s_bin[4 * lane], b1 = s_bin[4 * lane + 1], b2 = s_bin[4 * lane + 2], b3 = s_bin[4 * lane + 3];

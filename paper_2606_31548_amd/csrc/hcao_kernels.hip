@@ -2978,11 +2978,15 @@ __global__ __launch_bounds__(256) void k_list_movers(RebinArgs A) {
 
 // start of every key's run in the sorted keys: packed[c] = first j with
 // key[j] >= c, for c = 0..n_cells (packed[n_cells] = n); each run boundary
-// fills the starts of the keys it skips
-__global__ __launch_bounds__(256) void k_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells,
-                                                    uint64_t *packed) {
+// fills the starts of the keys it skips. With inv, also the inverse of the
+// sort's permutation: inv[idx[j]] = j
+__global__ __launch_bounds__(256) void k_run_starts(const uint32_t *key, const uint32_t *idx, uint64_t n,
+                                                    uint32_t n_cells, uint64_t *packed, uint32_t *inv,
+                                                    uint32_t *err) {
   const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  (void)err;
+  if (inv) inv[HCAO_IDX(idx[j], n, err)] = (uint32_t)j;
   const uint32_t k = key[j] < n_cells ? key[j] : n_cells;
   const uint32_t prev = j ? (key[j - 1] < n_cells ? key[j - 1] : n_cells) : 0u;
   const uint32_t from = j ? prev + 1 : 0u;
@@ -3010,19 +3014,13 @@ __device__ __forceinline__ void copy_particle(const State &s, const State &d, ui
   d.pz[to] = s.pz[from];
 }
 
-// one workgroup per new cell k fills its slots in order: the run of movers
-// into k (in slot order) splits at the first mover from a slot above off[k]
-// (found by bisection), k's stayers go between the two parts; particles
-// admitted through open faces (virtual old slots from tot on) come last in
-// the run, in the order they were made. A count beyond
-// the cell's capacity flags an error and the tail is dropped. Workgroups go
-// to the eight XCDs in turn, so the grid (a multiple of 8) gives each XCD one
-// contiguous range of cells: movers come from neighbouring cells, whose
-// lines are then in the same L2.
-__global__ __launch_bounds__(256) void k_rebin_place(RebinArgs A) {
-  __shared__ uint32_t s_below;
-  const uint32_t per_xcd = gridDim.x >> 3;
-  const uint32_t k = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+// per new cell k: the split of its run of sorted list entries at the first
+// entry from a slot above off[k] (by bisection: the run is in slot order),
+// its count (capped at its capacity, which raises the capacity error; the
+// place pass stores it) and where its particles go (RebinDest). One thread
+// per cell.
+__global__ __launch_bounds__(256) void k_rebin_cells(RebinArgs A) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= A.n_cells) return;
   const uint64_t base = A.off[k];
   uint64_t lo = 0, hi = 0;
@@ -3030,39 +3028,224 @@ __global__ __launch_bounds__(256) void k_rebin_place(RebinArgs A) {
     lo = A.packed[k];
     hi = A.packed[k + 1];
   }
-  if (threadIdx.x == 0) {
-    uint64_t a = lo, b = hi;
-    while (a < b) {
-      const uint64_t mid = (a + b) >> 1;
-      if (A.mslot[A.sidx[mid]] < base)
-        a = mid + 1;
-      else
-        b = mid;
-    }
-    s_below = (uint32_t)(a - lo);
+  uint64_t a = lo, b = hi;
+  while (a < b) {
+    const uint64_t mid = (a + b) >> 1;
+    if (A.mslot[A.sidx[mid]] < base)
+      a = mid + 1;
+    else
+      b = mid;
   }
-  __syncthreads();
-  const uint32_t below = s_below, ns = A.n_stay[k], cap = A.cap[k];
+  const uint32_t ns = A.n_stay[k], cap = A.cap[k];
   const uint64_t want = (hi - lo) + ns;
   const uint32_t total = (uint32_t)(want > cap ? cap : want);
-  if (threadIdx.x == 0) {
-    if (want > cap) atomicOr(A.err, kErrCapacity);
-    A.cnt[k] = total;
+  if (want > cap) atomicOr(A.err, kErrCapacity);
+  RebinDest d;
+  d.first = base - lo;
+  d.split = a;
+  d.end = base + total;
+  d.below = (uint32_t)(a - lo);
+  d.ns = ns;
+  A.dest[k] = d;
+}
+
+// The order in which the place pass visits the old cells: tiles of kTileX x
+// kTileY x kTileZ cells (clipped to the grid), the tiles x fastest, then y,
+// then z, and the cells of a tile x fastest. A cell's neighbours in every
+// direction are then visited close together in time, so that the lines the
+// movers between them share are written while they are still in L2 (in
+// plain cell order the neighbours across z are nx ny cells apart).
+constexpr uint32_t kTileX = 8, kTileY = 8, kTileZ = 4;
+struct TileOrder {
+  uint32_t bx, by, bz, tx, ty, tz;  // tile edges, tiles per axis
+};
+__host__ __device__ __forceinline__ TileOrder tile_order(uint32_t nx, uint32_t ny, uint32_t nz) {
+  TileOrder o;
+  o.bx = nx < kTileX ? nx : kTileX;
+  o.by = ny < kTileY ? ny : kTileY;
+  o.bz = nz < kTileZ ? nz : kTileZ;
+  o.tx = (nx + o.bx - 1) / o.bx;
+  o.ty = (ny + o.by - 1) / o.by;
+  o.tz = (nz + o.bz - 1) / o.bz;
+  return o;
+}
+// the cell of rank r in that order, or ~0u for a rank in the padding of a
+// partial tile
+__device__ __forceinline__ uint32_t tile_order_cell(uint32_t r, const RebinArgs &A) {
+  const TileOrder o = tile_order(A.nx, A.ny, A.nz);
+  const uint32_t per = o.bx * o.by * o.bz;
+  const uint32_t t = r / per, w = r - t * per;
+  const uint32_t x = (t % o.tx) * o.bx + w % o.bx;
+  const uint32_t y = ((t / o.tx) % o.ty) * o.by + (w / o.bx) % o.by;
+  const uint32_t z = (t / (o.tx * o.ty)) * o.bz + w / (o.bx * o.by);
+  if (x >= A.nx || y >= A.ny || z >= A.nz) return ~0u;
+  return x + A.nx * (y + A.ny * z);
+}
+
+// Cells of up to kStageSlots old slots are staged through LDS by the place
+// pass; an output entry of kNoSlot is dropped (capacity overflow).
+constexpr uint32_t kStageSlots = 384;
+constexpr uint64_t kNoSlot = ~0ull;
+
+// new slot of list entry m (kNoSlot when it is dropped: an admission that
+// left again, or a slot past its new cell's capacity)
+__device__ __forceinline__ uint64_t entry_slot(const RebinArgs &A, uint64_t m) {
+  const uint64_t pos = HCAO_IDX(A.inv[m], A.m, A.err);
+  const uint32_t k = A.skey[pos];
+  if (k >= A.n_cells) return kNoSlot;
+  const RebinDest d = A.dest[k];
+  const uint64_t to = d.first + pos + (pos >= d.split ? d.ns : 0u);
+  return to < d.end ? to : kNoSlot;
+}
+
+// The place pass, pushed from the old cells: one workgroup per old cell j
+// writes each of its particles to its slot in the new cell. The order in
+// every new cell is that of a stable sort of all particles by new cell:
+// movers from slots below off[k], k's stayers, the other movers, the
+// admissions (k_rebin_admit). The movers from j into one new cell hold
+// consecutive sorted positions, hence consecutive new slots; the workgroup
+// ranks its movers by new slot, so that its writes form runs. A cell of up
+// to kStageSlots old slots is read whole, in slot order, into registers
+// (issued first, so that the loads overlap the ranking) and then LDS, and
+// written from there in output order; level rows (4 to 32 bytes each) are
+// copied row by row in that order. Larger cells copy each particle
+// directly. The old count is read before the new one is written (only this
+// workgroup touches cnt[j]). Workgroups go to the eight XCDs in turn, so
+// the grid (a multiple of 8) gives each XCD one contiguous range of the
+// tile order: movers go to neighbouring cells, whose lines are then in the
+// same L2.
+__global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
+  constexpr uint32_t kPer = (kStageSlots + 255u) / 256u;  // staged slots per thread
+  __shared__ uint64_t s_pos[3][kStageSlots];  // mover new slots while ranking
+  __shared__ uint64_t s_vel[3][kStageSlots];  // bits of a double, or of a float
+  __shared__ uint64_t s_rot[kStageSlots];
+  __shared__ uint64_t s_to[kStageSlots];
+  __shared__ uint16_t s_src[kStageSlots], s_msrc[kStageSlots];
+  __shared__ uint8_t s_sp[kStageSlots];
+  const uint32_t per_xcd = gridDim.x >> 3;
+  const uint32_t j = tile_order_cell((blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3), A);
+  if (j >= A.n_cells) return;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t base = A.off[j], mb = A.mbase[j];
+  const uint32_t ns = A.n_stay[j], nm = (uint32_t)(A.mbase[j + 1] - mb), n_old = A.cnt[j];
+  const RebinDest own = A.dest[j];
+  const uint32_t n_out = ns + nm;
+  const State &S = A.src, &D = A.dst;
+  if (n_old > kStageSlots) {
+    for (uint32_t t = tid; t < n_out; t += blockDim.x) {
+      uint64_t from, to;
+      if (t < ns) {
+        from = base + A.list[base + t];
+        to = base + own.below + t;
+        if (to >= own.end) continue;
+      } else {
+        const uint64_t m = HCAO_IDX(mb + (t - ns), A.m, A.err);
+        from = A.mslot[m];
+        to = entry_slot(A, m);
+        if (to == kNoSlot) continue;
+      }
+      copy_particle(S, D, HCAO_IDX(from, S.n_slots, A.err), HCAO_IDX(to, D.n_slots, A.err), A.mm);
+    }
+  } else {
+    const bool f32 = S.fx != nullptr, rot = S.rot != nullptr;
+    uint64_t rp[kPer][3], rv[kPer][3], rr[kPer];
+    uint8_t rs[kPer];
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint32_t i = tid + 256u * q;
+      if (i < n_old) {
+        const uint64_t g = base + i;
+        rp[q][0] = reinterpret_cast<const uint64_t *>(S.px)[g];
+        rp[q][1] = reinterpret_cast<const uint64_t *>(S.py)[g];
+        rp[q][2] = reinterpret_cast<const uint64_t *>(S.pz)[g];
+        if (f32) {
+          rv[q][0] = reinterpret_cast<const uint32_t *>(S.fx)[g];
+          rv[q][1] = reinterpret_cast<const uint32_t *>(S.fy)[g];
+          rv[q][2] = reinterpret_cast<const uint32_t *>(S.fz)[g];
+        } else {
+          rv[q][0] = reinterpret_cast<const uint64_t *>(S.vx)[g];
+          rv[q][1] = reinterpret_cast<const uint64_t *>(S.vy)[g];
+          rv[q][2] = reinterpret_cast<const uint64_t *>(S.vz)[g];
+        }
+        rr[q] = rot ? reinterpret_cast<const uint64_t *>(S.rot)[g] : 0u;
+        rs[q] = S.sp[g];
+      }
+    }
+    // output entries: the stayers in slot order, then the movers ranked by
+    // new slot (dropped movers, kNoSlot, last)
+    for (uint32_t t = tid; t < ns; t += blockDim.x) {
+      const uint64_t to = base + own.below + t;
+      s_src[t] = (uint16_t)A.list[base + t];
+      s_to[t] = to < own.end ? HCAO_IDX(to, D.n_slots, A.err) : kNoSlot;
+    }
+    uint64_t *s_mto = s_pos[0];
+    for (uint32_t r = tid; r < nm; r += blockDim.x) {
+      const uint64_t m = HCAO_IDX(mb + r, A.m, A.err);
+      const uint64_t to = entry_slot(A, m);
+      s_mto[r] = to == kNoSlot ? kNoSlot : HCAO_IDX(to, D.n_slots, A.err);
+      s_msrc[r] = (uint16_t)(A.mslot[m] - base);
+    }
+    __syncthreads();
+    for (uint32_t r = tid; r < nm; r += blockDim.x) {
+      const uint64_t me = s_mto[r];
+      uint32_t rank = 0;
+      for (uint32_t u = 0; u < nm; ++u) {
+        const uint64_t o = s_mto[u];
+        rank += (o < me || (o == me && u < r)) ? 1u : 0u;
+      }
+      s_src[ns + rank] = s_msrc[r];
+      s_to[ns + rank] = me;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint32_t i = tid + 256u * q;
+      if (i < n_old) {
+        for (int a = 0; a < 3; ++a) {
+          s_pos[a][i] = rp[q][a];
+          s_vel[a][i] = rv[q][a];
+        }
+        s_rot[i] = rr[q];
+        s_sp[i] = rs[q];
+      }
+    }
+    __syncthreads();
+    for (uint32_t w = tid; w < n_out; w += blockDim.x) {
+      const uint64_t to = s_to[w];
+      if (to == kNoSlot) continue;
+      const uint32_t i = s_src[w];
+      reinterpret_cast<uint64_t *>(D.px)[to] = s_pos[0][i];
+      reinterpret_cast<uint64_t *>(D.py)[to] = s_pos[1][i];
+      reinterpret_cast<uint64_t *>(D.pz)[to] = s_pos[2][i];
+      if (f32) {
+        reinterpret_cast<uint32_t *>(D.fx)[to] = (uint32_t)s_vel[0][i];
+        reinterpret_cast<uint32_t *>(D.fy)[to] = (uint32_t)s_vel[1][i];
+        reinterpret_cast<uint32_t *>(D.fz)[to] = (uint32_t)s_vel[2][i];
+      } else {
+        reinterpret_cast<uint64_t *>(D.vx)[to] = s_vel[0][i];
+        reinterpret_cast<uint64_t *>(D.vy)[to] = s_vel[1][i];
+        reinterpret_cast<uint64_t *>(D.vz)[to] = s_vel[2][i];
+      }
+      if (rot) reinterpret_cast<uint64_t *>(D.rot)[to] = s_rot[i];
+      D.sp[to] = s_sp[i];
+      copy_levels(S, base + i, D, to);
+    }
   }
-  for (uint32_t p = threadIdx.x; p < total; p += blockDim.x) {
-    uint64_t from;
-    if (p < below)
-      from = A.mslot[A.sidx[lo + p]];
-    else if (p < below + ns)
-      from = base + A.list[base + (p - below)];
-    else
-      from = A.mslot[A.sidx[lo + p - ns]];
-    const uint64_t to = HCAO_IDX(base + p, A.dst.n_slots, A.err);
-    if (from < A.tot)
-      copy_particle(A.src, A.dst, HCAO_IDX(from, A.src.n_slots, A.err), to, A.mm);
-    else
-      copy_particle(A.ins, A.dst, HCAO_IDX(from - A.tot, A.ins.n_slots, A.err), to, A.mm);
-  }
+  __syncthreads();  // every wave has read the old count
+  if (tid == 0) A.cnt[j] = (uint32_t)(own.end - base);
+}
+
+// the admissions of the step (list entries m_real .. m - 1, staged in ins in
+// the order made): one thread each; one that left again (key n_cells) is
+// dropped
+__global__ __launch_bounds__(256) void k_rebin_admit(RebinArgs A) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t m = A.m_real + i;
+  if (m >= A.m) return;
+  const uint64_t to = entry_slot(A, m);
+  if (to == kNoSlot) return;
+  copy_particle(A.ins, A.dst, HCAO_IDX(A.mslot[m] - A.tot, A.ins.n_slots, A.err), HCAO_IDX(to, A.dst.n_slots, A.err),
+                A.mm);
 }
 
 }  // namespace
@@ -3253,16 +3436,25 @@ hipError_t launch_inflow_make(const InflowArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// run starts of the sorted movers, then the place pass
+// run starts of the sorted list and its inverse permutation, the new cells'
+// counts and destinations, then the place pass from the old cells and the
+// admissions
 hipError_t launch_rebin_place(const RebinArgs &a, hipStream_t s) {
   if (a.n_cells == 0) return hipSuccess;
-  if (!a.off || !a.cap || !a.list || !a.n_stay || !a.packed || !a.cnt || !a.err ||
-      (a.m && (!a.skey || !a.sidx || !a.mslot)))
+  if (!a.off || !a.cap || !a.list || !a.n_stay || !a.mbase || !a.packed || !a.dest || !a.cnt || !a.err ||
+      a.m_real > a.m || (a.m && (!a.skey || !a.sidx || !a.mslot || !a.inv)) ||
+      (uint64_t)a.nx * a.ny * a.nz != a.n_cells)
     return hipErrorInvalidValue;
+  const TileOrder o = tile_order(a.nx, a.ny, a.nz);
+  const uint64_t ranks = (uint64_t)o.tx * o.ty * o.tz * o.bx * o.by * o.bz;
+  if (ranks > 0xFFFFFFFFull - 7u) return hipErrorInvalidValue;
   if (a.m)
-    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a.skey, a.m, a.n_cells,
-                       a.packed);
-  hipLaunchKernelGGL(k_rebin_place, dim3(((a.n_cells + 7u) / 8u) * 8u), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a.skey, a.sidx, a.m,
+                       a.n_cells, a.packed, a.inv, a.err);
+  hipLaunchKernelGGL(k_rebin_cells, dim3((a.n_cells + 255u) / 256u), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_rebin_push, dim3((unsigned)(((ranks + 7u) / 8u) * 8u)), dim3(256), 0, s, a);
+  if (a.m > a.m_real)
+    hipLaunchKernelGGL(k_rebin_admit, dim3((unsigned)((a.m - a.m_real + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -156,6 +156,7 @@ struct hcao_ctx {
   DevBuf<uint32_t> mv_key, mv_list, mv_mkey, mv_mslot, mv_sidx, mv_sidx_tmp, mv_hist;
   DevBuf<uint32_t> mv_nstay, mv_nmove, mv_ktmp;
   DevBuf<uint64_t> mv_offs, mv_packed, mv_stmp, mv_mbase;
+  DevBuf<RebinDest> mv_dest;  // per new cell: where the place pass puts its particles
   uint64_t list_cap = 0;  // entries of the mover list arrays (movers and admissions)
   // open faces: the reservoir's one-sided flux per species, per (face cell,
   // species) inflow remainders and counts, the admissions' staging state,
@@ -330,6 +331,7 @@ void free_state(hcao_ctx *c) {
   c->mv_hist.release();
   c->mv_offs.release();
   c->mv_packed.release();
+  c->mv_dest.release();
   c->mv_stmp.release();
   c->mv_ktmp.release();
   c->list_cap = 0;
@@ -597,6 +599,7 @@ hcao_status alloc_state(hcao_ctx *c, const std::vector<uint32_t> &counts,
     HIP_TRY(c, c->mv_list.alloc(tot));
     HIP_TRY(c, grow_list(c, tot));
     HIP_TRY(c, c->mv_packed.alloc(nc + 1));
+    HIP_TRY(c, c->mv_dest.alloc(nc));
     HIP_TRY(c, c->mv_nstay.alloc(nc));
     HIP_TRY(c, c->mv_nmove.alloc(nc + 1));
     HIP_TRY(c, c->mv_mbase.alloc(nc + 1));
@@ -1443,11 +1446,16 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   r.mkey = c->mv_mkey.p;
   r.mslot = c->mv_mslot.p;
   r.packed = c->mv_packed.p;
+  r.dest = c->mv_dest.p;
   r.cnt = c->cnt.p;
   r.err = c->err.p;
   r.m = movers + n_ins;
+  r.m_real = movers;
   r.n_cells = nc;
   r.mm = mm;
+  r.nx = c->grid[0];
+  r.ny = c->grid[1];
+  r.nz = c->grid[2];
   HIP_TRY(c, launch_list_movers(r, s));
   if (n_ins) {
     in.ins = ins_state(c);
@@ -1467,6 +1475,7 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
                          c->mv_stmp.p, movers + n_ins, key_bits, s, in_tmp));
   r.skey = in_tmp ? c->mv_ktmp.p : c->mv_mkey.p;
   r.sidx = in_tmp ? c->mv_sidx_tmp.p : c->mv_sidx.p;
+  r.inv = in_tmp ? c->mv_sidx.p : c->mv_sidx_tmp.p;  // the sort's other index buffer is free now
   HIP_TRY(c, launch_rebin_place(r, s));
   std::swap(c->vx, c->bvx);
   std::swap(c->vy, c->bvy);

@@ -259,6 +259,17 @@ struct InflowArgs {
 // list pass writes them in slot order (position mbase[c] + rank), a stable
 // radix sort orders them by new cell and packed[k] is the start of k's run.
 // The place pass fills each cell's new slots in order.
+// Where the re-bin puts new cell k's particles: a list entry at sorted
+// position pos (its run in the sorted keys starts at lo) goes to slot
+// first + pos, plus ns (the cell's stayers, which fill the gap) when pos >=
+// split = lo + below; stayer r goes to off[k] + below + r; a slot at or past
+// end (off[k] + the capped count) is dropped. first = off[k] - lo, modulo
+// 2^64.
+struct alignas(16) RebinDest {
+  uint64_t first, split, end;
+  uint32_t below, ns;
+};
+
 struct RebinArgs {
   State src, dst;
   State ins;                                     // admitted particles (virtual old slots tot + j)
@@ -270,9 +281,13 @@ struct RebinArgs {
   uint32_t *mkey, *mslot;                        // movers in slot order: new cell, old slot
   const uint32_t *skey, *sidx;                   // sorted movers: new cell, position in the list
   uint64_t *packed;                              // run starts in skey (n_cells + 1)
+  uint32_t *inv;                                 // sorted position of each list entry
+  RebinDest *dest;                               // per new cell (n_cells)
   uint32_t *cnt, *err;
-  uint64_t m;                                    // number of movers
+  uint64_t m;                                    // number of list entries (movers, then admissions)
+  uint64_t m_real;                               // movers out of real slots (the admissions follow)
   uint32_t n_cells, mm;
+  uint32_t nx, ny, nz;                           // cell grid (n_cells = nx ny nz)
 };
 
 // Forward recombination probability summed over every level combination of

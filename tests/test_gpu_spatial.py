@@ -167,6 +167,28 @@ def test_spatial_rebin_capacity_overflow_is_reported(orc, hc):
         g.sync()
 
 
+def test_spatial_rebin_large_and_small_cells_parity(orc, hc):
+    """Cells of 750 particles beside cells of 150 in a periodic box: the
+    place pass stages a cell's fields through LDS only up to 512 old slots,
+    so movers flow between cells that take the staged path and cells that
+    copy directly."""
+    wl = W.spatial_box(nx=3, ny=2, nz=2, per_cell=150, periodic=0b111, t_trans=30000.0)
+    wl.counts = wl.counts.copy()
+    wl.counts[::2] *= 5
+    wl.capacity_per_cell = 2048
+    o = orc.from_workload(wl)
+    g = hc.from_workload(wl)
+    o.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    g.init_thermal(wl.counts, wl.t_trans, wl.t_vib)
+    assert max(o.count(c) for c in range(wl.n_cells)) > 512 > min(o.count(c) for c in range(wl.n_cells))
+    for n in (1, 5):
+        o.step(wl.dt, n)
+        g.step(wl.dt, n)
+        g.sync()
+        _compare_state(o, g, f"large and small cells: {n} steps")
+        _compare_pos(o, g, f"large and small cells: {n} steps")
+
+
 @pytest.mark.parametrize("shape,dt", [((3, 3, 2), 1e-13), ((1, 2, 5), None)])
 def test_spatial_rebin_without_movers_and_on_thin_axes(orc, hc, shape, dt):
     """The re-bin sorts only the particles that leave their cell. A step

@@ -3049,39 +3049,6 @@ __global__ __launch_bounds__(256) void k_rebin_cells(RebinArgs A) {
   A.dest[k] = d;
 }
 
-// The order in which the place pass visits the old cells: tiles of kTileX x
-// kTileY x kTileZ cells (clipped to the grid), the tiles x fastest, then y,
-// then z, and the cells of a tile x fastest. A cell's neighbours in every
-// direction are then visited close together in time, so that the lines the
-// movers between them share are written while they are still in L2 (in
-// plain cell order the neighbours across z are nx ny cells apart).
-constexpr uint32_t kTileX = 8, kTileY = 8, kTileZ = 4;
-struct TileOrder {
-  uint32_t bx, by, bz, tx, ty, tz;  // tile edges, tiles per axis
-};
-__host__ __device__ __forceinline__ TileOrder tile_order(uint32_t nx, uint32_t ny, uint32_t nz) {
-  TileOrder o;
-  o.bx = nx < kTileX ? nx : kTileX;
-  o.by = ny < kTileY ? ny : kTileY;
-  o.bz = nz < kTileZ ? nz : kTileZ;
-  o.tx = (nx + o.bx - 1) / o.bx;
-  o.ty = (ny + o.by - 1) / o.by;
-  o.tz = (nz + o.bz - 1) / o.bz;
-  return o;
-}
-// the cell of rank r in that order, or ~0u for a rank in the padding of a
-// partial tile
-__device__ __forceinline__ uint32_t tile_order_cell(uint32_t r, const RebinArgs &A) {
-  const TileOrder o = tile_order(A.nx, A.ny, A.nz);
-  const uint32_t per = o.bx * o.by * o.bz;
-  const uint32_t t = r / per, w = r - t * per;
-  const uint32_t x = (t % o.tx) * o.bx + w % o.bx;
-  const uint32_t y = ((t / o.tx) % o.ty) * o.by + (w / o.bx) % o.by;
-  const uint32_t z = (t / (o.tx * o.ty)) * o.bz + w / (o.bx * o.by);
-  if (x >= A.nx || y >= A.ny || z >= A.nz) return ~0u;
-  return x + A.nx * (y + A.ny * z);
-}
-
 // Cells of up to kStageSlots old slots are staged through LDS by the place
 // pass; an output entry of kNoSlot is dropped (capacity overflow).
 constexpr uint32_t kStageSlots = 384;
@@ -3111,9 +3078,8 @@ __device__ __forceinline__ uint64_t entry_slot(const RebinArgs &A, uint64_t m) {
 // copied row by row in that order. Larger cells copy each particle
 // directly. The old count is read before the new one is written (only this
 // workgroup touches cnt[j]). Workgroups go to the eight XCDs in turn, so
-// the grid (a multiple of 8) gives each XCD one contiguous range of the
-// tile order: movers go to neighbouring cells, whose lines are then in the
-// same L2.
+// the grid (a multiple of 8) gives each XCD one contiguous range of cells:
+// movers go to neighbouring cells, whose lines are then in the same L2.
 __global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
   constexpr uint32_t kPer = (kStageSlots + 255u) / 256u;  // staged slots per thread
   __shared__ uint64_t s_pos[3][kStageSlots];  // mover new slots while ranking
@@ -3123,7 +3089,7 @@ __global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
   __shared__ uint16_t s_src[kStageSlots], s_msrc[kStageSlots];
   __shared__ uint8_t s_sp[kStageSlots];
   const uint32_t per_xcd = gridDim.x >> 3;
-  const uint32_t j = tile_order_cell((blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3), A);
+  const uint32_t j = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
   if (j >= A.n_cells) return;
   const uint32_t tid = threadIdx.x;
   const uint64_t base = A.off[j], mb = A.mbase[j];
@@ -3442,17 +3408,13 @@ hipError_t launch_inflow_make(const InflowArgs &a, hipStream_t s) {
 hipError_t launch_rebin_place(const RebinArgs &a, hipStream_t s) {
   if (a.n_cells == 0) return hipSuccess;
   if (!a.off || !a.cap || !a.list || !a.n_stay || !a.mbase || !a.packed || !a.dest || !a.cnt || !a.err ||
-      a.m_real > a.m || (a.m && (!a.skey || !a.sidx || !a.mslot || !a.inv)) ||
-      (uint64_t)a.nx * a.ny * a.nz != a.n_cells)
+      a.m_real > a.m || (a.m && (!a.skey || !a.sidx || !a.mslot || !a.inv)))
     return hipErrorInvalidValue;
-  const TileOrder o = tile_order(a.nx, a.ny, a.nz);
-  const uint64_t ranks = (uint64_t)o.tx * o.ty * o.tz * o.bx * o.by * o.bz;
-  if (ranks > 0xFFFFFFFFull - 7u) return hipErrorInvalidValue;
   if (a.m)
     hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a.skey, a.sidx, a.m,
                        a.n_cells, a.packed, a.inv, a.err);
   hipLaunchKernelGGL(k_rebin_cells, dim3((a.n_cells + 255u) / 256u), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_rebin_push, dim3((unsigned)(((ranks + 7u) / 8u) * 8u)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_rebin_push, dim3(((a.n_cells + 7u) / 8u) * 8u), dim3(256), 0, s, a);
   if (a.m > a.m_real)
     hipLaunchKernelGGL(k_rebin_admit, dim3((unsigned)((a.m - a.m_real + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();

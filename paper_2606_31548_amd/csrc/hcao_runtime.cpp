@@ -1453,9 +1453,6 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   r.m_real = movers;
   r.n_cells = nc;
   r.mm = mm;
-  r.nx = c->grid[0];
-  r.ny = c->grid[1];
-  r.nz = c->grid[2];
   HIP_TRY(c, launch_list_movers(r, s));
   if (n_ins) {
     in.ins = ins_state(c);

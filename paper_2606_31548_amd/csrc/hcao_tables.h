@@ -287,7 +287,6 @@ struct RebinArgs {
   uint64_t m;                                    // number of list entries (movers, then admissions)
   uint64_t m_real;                               // movers out of real slots (the admissions follow)
   uint32_t n_cells, mm;
-  uint32_t nx, ny, nz;                           // cell grid (n_cells = nx ny nz)
 };
 
 // Forward recombination probability summed over every level combination of

@@ -2978,15 +2978,11 @@ __global__ __launch_bounds__(256) void k_list_movers(RebinArgs A) {
 
 // start of every key's run in the sorted keys: packed[c] = first j with
 // key[j] >= c, for c = 0..n_cells (packed[n_cells] = n); each run boundary
-// fills the starts of the keys it skips. With inv, also the inverse of the
-// sort's permutation: inv[idx[j]] = j
-__global__ __launch_bounds__(256) void k_run_starts(const uint32_t *key, const uint32_t *idx, uint64_t n,
-                                                    uint32_t n_cells, uint64_t *packed, uint32_t *inv,
-                                                    uint32_t *err) {
+// fills the starts of the keys it skips
+__global__ __launch_bounds__(256) void k_run_starts(const uint32_t *key, uint64_t n, uint32_t n_cells,
+                                                    uint64_t *packed) {
   const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  (void)err;
-  if (inv) inv[HCAO_IDX(idx[j], n, err)] = (uint32_t)j;
   const uint32_t k = key[j] < n_cells ? key[j] : n_cells;
   const uint32_t prev = j ? (key[j - 1] < n_cells ? key[j - 1] : n_cells) : 0u;
   const uint32_t from = j ? prev + 1 : 0u;
@@ -3054,15 +3050,29 @@ __global__ __launch_bounds__(256) void k_rebin_cells(RebinArgs A) {
 constexpr uint32_t kStageSlots = 384;
 constexpr uint64_t kNoSlot = ~0ull;
 
-// new slot of list entry m (kNoSlot when it is dropped: an admission that
-// left again, or a slot past its new cell's capacity)
+// New slot of every list entry (by its sorted position j: its new cell's
+// destination record gives it), ~0u when the entry is dropped (an
+// admission that left again, or a slot past its new cell's capacity).
+// Slots of the spatial mode fit 32 bits below ~0u. One thread per sorted
+// entry; the writes scatter by list index, so that the place pass reads
+// its movers' slots in list order.
+constexpr uint32_t kNoSlot32 = 0xFFFFFFFFu;
+__global__ __launch_bounds__(256) void k_rebin_slots(RebinArgs A) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= A.m) return;
+  const uint32_t k = A.skey[j];
+  uint32_t slot = kNoSlot32;
+  if (k < A.n_cells) {
+    const RebinDest d = A.dest[k];
+    const uint64_t to = d.first + j + (j >= d.split ? d.ns : 0u);
+    if (to < d.end) slot = (uint32_t)to;
+  }
+  A.slot[HCAO_IDX(A.sidx[j], A.m, A.err)] = slot;
+}
+
 __device__ __forceinline__ uint64_t entry_slot(const RebinArgs &A, uint64_t m) {
-  const uint64_t pos = HCAO_IDX(A.inv[m], A.m, A.err);
-  const uint32_t k = A.skey[pos];
-  if (k >= A.n_cells) return kNoSlot;
-  const RebinDest d = A.dest[k];
-  const uint64_t to = d.first + pos + (pos >= d.split ? d.ns : 0u);
-  return to < d.end ? to : kNoSlot;
+  const uint32_t v = A.slot[m];
+  return v == kNoSlot32 ? kNoSlot : (uint64_t)v;
 }
 
 // The place pass, pushed from the old cells: one workgroup per old cell j
@@ -3402,18 +3412,19 @@ hipError_t launch_inflow_make(const InflowArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// run starts of the sorted list and its inverse permutation, the new cells'
-// counts and destinations, then the place pass from the old cells and the
-// admissions
+// run starts of the sorted list, the new cells' counts and destinations,
+// every list entry's new slot, then the place pass from the old cells and
+// the admissions
 hipError_t launch_rebin_place(const RebinArgs &a, hipStream_t s) {
   if (a.n_cells == 0) return hipSuccess;
   if (!a.off || !a.cap || !a.list || !a.n_stay || !a.mbase || !a.packed || !a.dest || !a.cnt || !a.err ||
-      a.m_real > a.m || (a.m && (!a.skey || !a.sidx || !a.mslot || !a.inv)))
+      a.m_real > a.m || (a.m && (!a.skey || !a.sidx || !a.mslot || !a.slot)))
     return hipErrorInvalidValue;
   if (a.m)
-    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a.skey, a.sidx, a.m,
-                       a.n_cells, a.packed, a.inv, a.err);
+    hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a.skey, a.m, a.n_cells,
+                       a.packed);
   hipLaunchKernelGGL(k_rebin_cells, dim3((a.n_cells + 255u) / 256u), dim3(256), 0, s, a);
+  if (a.m) hipLaunchKernelGGL(k_rebin_slots, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_rebin_push, dim3(((a.n_cells + 7u) / 8u) * 8u), dim3(256), 0, s, a);
   if (a.m > a.m_real)
     hipLaunchKernelGGL(k_rebin_admit, dim3((unsigned)((a.m - a.m_real + 255) / 256)), dim3(256), 0, s, a);

@@ -1472,7 +1472,7 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
                          c->mv_stmp.p, movers + n_ins, key_bits, s, in_tmp));
   r.skey = in_tmp ? c->mv_ktmp.p : c->mv_mkey.p;
   r.sidx = in_tmp ? c->mv_sidx_tmp.p : c->mv_sidx.p;
-  r.inv = in_tmp ? c->mv_sidx.p : c->mv_sidx_tmp.p;  // the sort's other index buffer is free now
+  r.slot = in_tmp ? c->mv_sidx.p : c->mv_sidx_tmp.p;  // the sort's other index buffer is free now
   HIP_TRY(c, launch_rebin_place(r, s));
   std::swap(c->vx, c->bvx);
   std::swap(c->vy, c->bvy);

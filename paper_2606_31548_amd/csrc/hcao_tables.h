@@ -281,7 +281,7 @@ struct RebinArgs {
   uint32_t *mkey, *mslot;                        // movers in slot order: new cell, old slot
   const uint32_t *skey, *sidx;                   // sorted movers: new cell, position in the list
   uint64_t *packed;                              // run starts in skey (n_cells + 1)
-  uint32_t *inv;                                 // sorted position of each list entry
+  uint32_t *slot;                                // new slot of each list entry (~0u: dropped)
   RebinDest *dest;                               // per new cell (n_cells)
   uint32_t *cnt, *err;
   uint64_t m;                                    // number of list entries (movers, then admissions)

@@ -2,7 +2,8 @@
 HCAO_LIBRARY variable the caller sets) through the paths whose indices it
 checks, each held bit for bit to the oracle: the 0D chemistry with births
 and deaths, the exact sampler with rotors, uneven batched reservoirs, the
-spatial mode with open faces, and the mixed form's step. Any index outside
+spatial mode with open faces and with cells on both sides of the re-bin's
+staging limit, and the mixed form's step. Any index outside
 its array makes a call fail with HCAO_EBOUNDS. Prints one line per case and
 "checked ok" at the end; exits non-zero on the first failure.
 
@@ -75,6 +76,13 @@ def main():
     wl = W.spatial_box(nx=4, ny=3, nz=3, per_cell=150, chemistry=True, t_trans=12000.0, dt=5e-9,
                        open_faces=0b000011)
     pair(wl, (2, 10), "spatial chemistry with open faces", positions=True)
+
+    # cells above the re-bin's LDS staging limit beside cells below it
+    wl = W.spatial_box(nx=3, ny=2, nz=2, per_cell=150, periodic=0b111, t_trans=30000.0)
+    wl.counts = wl.counts.copy()
+    wl.counts[::2] *= 5
+    wl.capacity_per_cell = 2048
+    pair(wl, (1, 4), "spatial cells above and below the staging limit", positions=True)
 
     wl = W.methane_chemistry(n_cells=24, per_cell=256, recombination=True, t=12000.0)
     pair(wl, (20,), "mixed form", precision=hcao.MIXED)

@@ -1562,7 +1562,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   const Tab T{l_sp, l_pr, l_rx, l_lev, A.beta, ns, nr, mm, GT->rec_nt};
   const uint32_t wcap = (uint32_t)(A.grp_work[2 * blockIdx.x + 1] - wbase);
   uint32_t *work_in = A.work + (size_t)kWorkWords * wbase;  // accepted pairs as found
-  uint32_t *work = work_in + (size_t)kWorkFound * wcap;       // the same sorted by key
+  uint32_t *work = work_in + (size_t)kWorkFound * wcap;       // their indices sorted by key
   uint8_t *bflag = A.bflag + wbase;
   double *wdef = MIX ? A.wdef + wbase : nullptr;
   __syncthreads();
@@ -1729,13 +1729,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   __syncthreads();
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
     const uint32_t *f = work_in + (size_t)kWorkFound * i;
-    uint32_t *w = work + (size_t)kWorkSorted * HCAO_IDX(atomicAdd(&s_bin[f[3]], 1u), wcap, A.err);
-    w[0] = f[0];
-    w[1] = f[1];
-    w[2] = f[2];
-    w[3] = f[4];
-    w[4] = f[5];
-    w[5] = f[6];
+    work[HCAO_IDX(atomicAdd(&s_bin[f[3]], 1u), wcap, A.err)] = i;  // the entry itself stays where it was found
   }
   __syncthreads();
   HCAO_PHASE_MARK(kPhaseSort);
@@ -1759,7 +1753,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 #else
     PairLocal<MIX> P;
 #endif
-    const uint32_t *wi = work + (size_t)kWorkSorted * i;
+    const uint32_t *wi = work_in + (size_t)kWorkFound * work[i];
     const uint32_t j = wi[0], p = wi[1], qq = wi[2];
     const uint32_t g = group_cell(hdr, ncell, j);
     const CellHdr &H = hdr[g];
@@ -1808,9 +1802,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     rng.open(A.seed, k, H.cell, step);
     // resume after the acceptance draw of phase A: its block's other words
     rng.block = 1;
-    rng.w1 = wi[3];
-    rng.w2 = wi[4];
-    rng.w3 = wi[5];
+    rng.w1 = wi[4];
+    rng.w2 = wi[5];
+    rng.w3 = wi[6];
     rng.used = MIX ? 1u : 2u;
     unsigned long long *ctr = l_ctr + (size_t)g * nctr;
     atomicAdd(&ctr[HCAO_CTR_COLLISIONS], 1ull);

@@ -40,10 +40,10 @@ constexpr uint32_t kReactAny = 1u;    // some reaction lists the pair (as A, or 
 constexpr uint32_t kReactRecomb = 2u;  // a recombination lists it as B + C, in either order
 
 // Words per work-list entry: the pair as found (candidate j, p, q, sort key,
-// words 1-3 of the pair stream's first Philox block), then as sorted (j, p,
-// q, the three words).
+// words 1-3 of the pair stream's first Philox block), then the sorted list
+// (the index of an entry as found).
 constexpr uint32_t kWorkFound = 7;
-constexpr uint32_t kWorkSorted = 6;
+constexpr uint32_t kWorkSorted = 1;
 constexpr uint32_t kWorkWords = kWorkFound + kWorkSorted;
 
 // Bounds of the pair's dissociation and exchange channels, per side (0: a is
@@ -181,7 +181,7 @@ constexpr uint8_t kFlagCollided = 2;  // it collided (its running-sum change is 
 // Workgroup b processes the consecutive cells [grp[2b], grp[2b+1]); its work
 // list, product flags and pair energy defects are the entries
 // [grp_work[2b], grp_work[2b+1]) of work (kWorkWords words each: the pair as
-// found and as sorted) / bflag / wdef
+// found and its place in the sorted list) / bflag / wdef
 // (sum over its cells of cap/2 + 1 entries).
 struct StepArgs {
   const Tables *tab;

@@ -80,7 +80,8 @@ def main():
     # cells above the re-bin's LDS staging limit beside cells below it
     wl = W.spatial_box(nx=3, ny=2, nz=2, per_cell=150, periodic=0b111, t_trans=30000.0)
     wl.counts = wl.counts.copy()
-    wl.counts[::2] *= 5
+    wl.counts[::3] *= 5
+    wl.counts[1::3] *= 2
     wl.capacity_per_cell = 2048
     pair(wl, (1, 4), "spatial cells above and below the staging limit", positions=True)
 

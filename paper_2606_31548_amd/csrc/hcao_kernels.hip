@@ -2426,12 +2426,22 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *key
   __syncthreads();
   const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
   const unsigned long long lt = lane ? ((1ull << lane) - 1ull) : 0ull;
+  // the tile's keys and indices are loaded at once, before the ranking
+  // rounds (whose barriers would otherwise wait on each round's loads)
+  uint32_t kr[kSortItems], ir[kSortItems];
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const uint64_t i = t0 + (uint64_t)it * kSortBlock + tid;
+    kr[it] = i < n ? keys_in[i] : 0u;
+    ir[it] = i < n ? idx_in[i] : 0u;
+  }
+#pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     for (int w = 0; w < kWaves; ++w) s_wave[w][tid] = 0;
     __syncthreads();
     const uint64_t i = t0 + (uint64_t)it * kSortBlock + tid;
     const bool valid = i < n;
-    const uint32_t key = valid ? keys_in[i] : 0u;
+    const uint32_t key = kr[it];
     const uint32_t d = (key >> shift) & 0xffu;
     unsigned long long same = __ballot(valid);
 #pragma unroll
@@ -2447,7 +2457,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *key
     if (valid) {
       const uint64_t pos = offs[(uint64_t)d * n_tiles + blockIdx.x] + before + rank;
       keys_out[pos] = key;
-      idx_out[pos] = idx_in[i];
+      idx_out[pos] = ir[it];
     }
     __syncthreads();
     uint32_t add = 0;

@@ -1548,12 +1548,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   }
   if constexpr (EX >= 1) {
     // spatial mode: the particles were re-binned since the last step, so the
-    // running sums start afresh from them (one wave per cell)
+    // running sums start afresh from them (one wave per cell; masses from
+    // the species table in LDS)
     if (A.cells.tsum && A.st.px) {
       __syncthreads();
       for (uint32_t g = wave; g < ncell; g += BLOCK / 64) {
         double sums[5];
-        cell_sums<MIX>(A.st, GT->sp, hdr[g].base, hdr[g].n, lane, sums);
+        cell_sums<MIX>(A.st, l_sp, hdr[g].base, hdr[g].n, lane, sums);
         if (lane == 0)
           for (int q = 0; q < 5; ++q) hdr[g].tsum[q] = sums[q];
       }

@@ -1638,9 +1638,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   for (uint32_t j0 = 0; j0 < total; j0 += BLOCK) {
     const uint32_t j = j0 + tid;
     bool acc = false;
-    uint32_t pj = 0, qj = 0, key = 0, rw1 = 0, rw2 = 0, rw3 = 0;
+    uint32_t pj = 0, qj = 0, key = 0, rw1 = 0, rw2 = 0, rw3 = 0, g_acc = 0;
     if (j < total) {
       const uint32_t g = group_cell(hdr, ncell, j);
+      g_acc = g;
       const CellHdr &H = hdr[g];
       const uint32_t k = j - H.cstart;
       PermReg perm;
@@ -1700,7 +1701,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       w[0] = j;
       w[1] = pj;
       w[2] = qj;
-      w[3] = key;
+      w[3] = key | (g_acc << 8);
       w[4] = rw1;
       w[5] = rw2;
       w[6] = rw3;
@@ -1730,7 +1731,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   __syncthreads();
   for (uint32_t i = tid; i < nwork; i += BLOCK) {
     const uint32_t *f = work_in + (size_t)kWorkFound * i;
-    work[HCAO_IDX(atomicAdd(&s_bin[f[3]], 1u), wcap, A.err)] = i;  // the entry itself stays where it was found
+    work[HCAO_IDX(atomicAdd(&s_bin[f[3] & 0xFFu], 1u), wcap, A.err)] = i;  // the entry itself stays where it was found
   }
   __syncthreads();
   HCAO_PHASE_MARK(kPhaseSort);
@@ -1756,7 +1757,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 #endif
     const uint32_t *wi = work_in + (size_t)kWorkFound * work[i];
     const uint32_t j = wi[0], p = wi[1], qq = wi[2];
-    const uint32_t g = group_cell(hdr, ncell, j);
+    const uint32_t g = wi[3] >> 8;
     const CellHdr &H = hdr[g];
     const uint32_t k = j - H.cstart;
     const uint64_t gp = HCAO_IDX(H.base + p, A.st.n_slots, A.err), gq = HCAO_IDX(H.base + qq, A.st.n_slots, A.err);

@@ -39,7 +39,8 @@ struct SpeciesTab {
 constexpr uint32_t kReactAny = 1u;    // some reaction lists the pair (as A, or as A + B / B + C), in either order
 constexpr uint32_t kReactRecomb = 2u;  // a recombination lists it as B + C, in either order
 
-// Words per work-list entry: the pair as found (candidate j, p, q, sort key,
+// Words per work-list entry: the pair as found (candidate j, p, q, the sort
+// key in bits 0-7 with the index of the pair's cell in its group from bit 8,
 // words 1-3 of the pair stream's first Philox block), then the sorted list
 // (the index of an entry as found).
 constexpr uint32_t kWorkFound = 7;

@@ -59,11 +59,12 @@ WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "tria
 # Launch shape (workgroup size, slot target per workgroup) per workload,
 # the fastest over the timed steps in sweeps of block 64/128/256 and slot
 # targets on MI355X; fixed here so that a profiled run holds only the timed
-# launches. --autotune runs the library's autotuner instead, after the
-# warm-up (from there it picks 128 / 2048 on the chemistry workload as
-# well; trials from the initial state, where (sigma g)_max is still
-# settling, preferred 128 / 4096, 5% (mixed) and 20% (fp64) slower).
-TUNED_SHAPE = {"chemistry-67m": (128, 3072), "chemistry-16m": (128, 3072), "methane-argon": (64, 1024),
+# launches. A slot target counts cell capacities: on the chemistry
+# workloads (352 slots per cell) 2560 gives workgroups of seven cells, 3%
+# (mixed) and 4% (fp64) faster than eight (2816 to 3072) and 2% faster than
+# six; the spatial box (576 per cell) does best with five (3072).
+# --autotune runs the library's autotuner instead, after the warm-up.
+TUNED_SHAPE = {"chemistry-67m": (128, 2560), "chemistry-16m": (128, 2560), "methane-argon": (64, 1024),
                "batched": (256, 4096), "triatomic": (64, 1024), "box-67m": (128, 3072),
                "box-inflow-67m": (128, 3072)}
 # the batched leg of the default run, per form: 512-lane workgroups suit the

@@ -349,7 +349,7 @@ hcao_status hcao_get_launch_shape(const hcao_ctx *ctx, hcao_launch_shape *shape)
 hcao_status hcao_set_launch_shape(hcao_ctx *ctx, const hcao_launch_shape *shape);
 
 /* Autotuner of the launch shape: times trial_steps steps of every candidate
- * (block 64, 128, 256 x group_slots 256 .. 4096) from a device copy of the
+ * (block 64, 128, 256 x group_slots 256 .. 6144) from a device copy of the
  * current state advanced by max(trial_steps, 10) steps (so that the first
  * steps' settling (sigma g)_max does not decide), puts the state back, and
  * keeps the fastest candidate. Trials shorter than one launch

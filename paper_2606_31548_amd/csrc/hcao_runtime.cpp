@@ -1854,7 +1854,7 @@ hcao_status hcao_autotune(hcao_ctx *c, double dt, uint32_t trial_steps, const ch
       if (hcao_status e = read_err(c)) return e;
       if (hcao_status s = snapshot(c, W, true)) return s;
       const uint32_t blocks[] = {64, 128, 256};
-      const uint32_t slots[] = {256, 512, 1024, 2048, 3072, 4096, 6144};
+      const uint32_t slots[] = {256, 512, 1024, 1536, 2048, 2560, 3072, 3584, 4096, 6144};
       for (uint32_t b : blocks) {
         for (uint32_t g : slots) {
           if (g < b) continue;

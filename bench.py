@@ -62,11 +62,12 @@ WORKLOADS = ("chemistry-67m", "chemistry-16m", "methane-argon", "batched", "tria
 # launches. A slot target counts cell capacities: on the chemistry
 # workloads (352 slots per cell) 2560 gives workgroups of seven cells, 3%
 # (mixed) and 4% (fp64) faster than eight (2816 to 3072) and 2% faster than
-# six; the spatial box (576 per cell) does best with five (3072).
+# six; the spatial box (576 per cell) does best with six (3456), 2% faster
+# than five or eight.
 # --autotune runs the library's autotuner instead, after the warm-up.
 TUNED_SHAPE = {"chemistry-67m": (128, 2560), "chemistry-16m": (128, 2560), "methane-argon": (64, 1024),
-               "batched": (256, 4096), "triatomic": (64, 1024), "box-67m": (128, 3072),
-               "box-inflow-67m": (128, 3072)}
+               "batched": (256, 4096), "triatomic": (64, 1024), "box-67m": (128, 3456),
+               "box-inflow-67m": (128, 3456)}
 # the batched leg of the default run, per form: 512-lane workgroups suit the
 # fp64 form's large reservoirs (4.8 against 5.0 ms per step) and not the
 # mixed form's (6.8 against 4.5)

@@ -3098,8 +3098,13 @@ __device__ __forceinline__ uint64_t entry_slot(const RebinArgs &A, uint64_t m) {
 // movers go to neighbouring cells, whose lines are then in the same L2.
 __global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
   constexpr uint32_t kPer = (kStageSlots + 255u) / 256u;  // staged slots per thread
-  __shared__ uint64_t s_pos[3][kStageSlots];  // mover new slots while ranking
-  __shared__ uint64_t s_vel[3][kStageSlots];  // bits of a double, or of a float
+  constexpr uint32_t kPerL = (kStageSlots * (kMaxModes / 2) + 255u) / 256u;  // staged level dwords per thread
+  // positions (rows 0-2) and velocities (rows 3-5: bits of a double, or of
+  // a float); mover new slots while ranking, level rows after the fields
+  __shared__ uint64_t s_pv[6][kStageSlots];
+  static_assert(kStageSlots * (kMaxModes / 2) * 4 <= sizeof(s_pv), "level rows must fit the staging rows");
+  uint64_t(*s_pos)[kStageSlots] = s_pv;
+  uint64_t(*s_vel)[kStageSlots] = s_pv + 3;
   __shared__ uint64_t s_rot[kStageSlots];
   __shared__ uint64_t s_to[kStageSlots];
   __shared__ uint16_t s_src[kStageSlots], s_msrc[kStageSlots];
@@ -3152,6 +3157,16 @@ __global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
         rr[q] = rot ? reinterpret_cast<const uint64_t *>(S.rot)[g] : 0u;
         rs[q] = S.sp[g];
       }
+    }
+    // the cell's level rows as one run of n_old * L dwords, loaded in order
+    // (lane t takes dwords t, t + 256, ...)
+    const uint32_t L = S.lrow / 2u, n_lv = n_old * L;
+    const uint32_t *lsrc = reinterpret_cast<const uint32_t *>(S.lvl) + base * L;
+    uint32_t rl[kPerL];
+#pragma unroll
+    for (uint32_t q = 0; q < kPerL; ++q) {
+      const uint32_t f = tid + 256u * q;
+      rl[q] = f < n_lv ? lsrc[f] : 0u;
     }
     // output entries: the stayers in slot order, then the movers ranked by
     // new slot (dropped movers, kNoSlot, last)
@@ -3210,7 +3225,26 @@ __global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
       }
       if (rot) reinterpret_cast<uint64_t *>(D.rot)[to] = s_rot[i];
       D.sp[to] = s_sp[i];
-      copy_levels(S, base + i, D, to);
+    }
+    // level rows through LDS (over the staged positions and velocities, read
+    // for the last time above), written dword by dword in output order, so
+    // that reads and writes of a wave are runs of consecutive dwords:
+    // output dword f is dword f mod L of entry f / L (exact as f * ceil(2^16
+    // / L) >> 16 for f <= 3072, L <= 8)
+    __syncthreads();
+    uint32_t *s_lv = reinterpret_cast<uint32_t *>(&s_pv[0][0]);
+#pragma unroll
+    for (uint32_t q = 0; q < kPerL; ++q) {
+      const uint32_t f = tid + 256u * q;
+      if (f < n_lv) s_lv[f] = rl[q];
+    }
+    __syncthreads();
+    uint32_t *ldst = reinterpret_cast<uint32_t *>(D.lvl);
+    const uint32_t inv = (65536u + L - 1u) / L;
+    for (uint32_t f = tid; f < n_out * L; f += blockDim.x) {
+      const uint32_t w = (f * inv) >> 16, d = f - w * L;
+      const uint64_t to = s_to[w];
+      if (to != kNoSlot) ldst[to * L + d] = s_lv[(uint32_t)s_src[w] * L + d];
     }
   }
   __syncthreads();  // every wave has read the old count

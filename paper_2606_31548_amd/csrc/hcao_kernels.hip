@@ -2808,6 +2808,7 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
     const uint32_t i = i0 + tid;
     const uint64_t g = base + i;
     bool mover = false, stayer = false;
+    uint32_t key = 0;
     if (i < n) {
       const Vec3 v = load_vel(A.st, g);
       double vx = v.x, vy = v.y, vz = v.z;
@@ -2818,9 +2819,8 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
         A.st.py[g] = y;
         A.st.pz[g] = z;
         if (flip) store_vel(A.st, g, vx, vy, vz);  // only a reflection changes the velocity
-        const uint32_t key = axis_index(x, A.len[0], A.nx) +
-                             A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
-        A.key[g] = key;
+        key = axis_index(x, A.len[0], A.nx) +
+              A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
         mover = key != c;
         stayer = !mover;
       }
@@ -2843,7 +2843,11 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
     }
     // stayer ranks count up from the first slot, mover ranks down from the
     // last: together they never pass n <= cap entries
-    if (mover) A.list[base + top - (pre_m + (uint32_t)__popcll(bm & below_lane))] = i;
+    if (mover) {
+      const uint64_t at = base + top - (pre_m + (uint32_t)__popcll(bm & below_lane));
+      A.list[at] = i;
+      A.key[at] = key;
+    }
     if (stayer) A.list[base + pre_s + (uint32_t)__popcll(bs & below_lane)] = i;
     __syncthreads();
   }
@@ -2976,9 +2980,8 @@ __global__ __launch_bounds__(256) void k_list_movers(RebinArgs A) {
   const uint64_t base = A.off[c], mb = A.mbase[c];
   const uint64_t top = base + A.cap[c] - 1u;
   for (uint32_t r = threadIdx.x; r < nm; r += blockDim.x) {
-    const uint64_t g = base + A.list[top - r];
-    A.mkey[mb + r] = A.key[g];
-    A.mslot[mb + r] = (uint32_t)g;
+    A.mkey[mb + r] = A.key[top - r];
+    A.mslot[mb + r] = (uint32_t)(base + A.list[top - r]);
   }
 }
 

@@ -208,11 +208,11 @@ struct StepArgs {
   double dt;
 };
 
-// Spatial mode, move pass: block c moves the particles of cell c over dt
-// and writes key[slot] = the new cell; its stayers (new cell = c) and its
-// movers are listed by cell-relative slot in list[], stayers in slot order
-// from the cell's first slot up, movers in slot order from its last slot
-// down; n_stay[c] and n_move[c] count them. A particle that crosses an open
+// Spatial mode, move pass: block c moves the particles of cell c over dt;
+// its stayers (new cell = c) and its movers are listed by cell-relative slot
+// in list[], stayers in slot order from the cell's first slot up, movers in
+// slot order from its last slot down, each mover's new cell in key[] at the
+// same place as its list entry; n_stay[c] and n_move[c] count them. A particle that crosses an open
 // face (bit 2 axis + side of open) is in neither list; flux[1] counts them.
 struct MoveArgs {
   State st;

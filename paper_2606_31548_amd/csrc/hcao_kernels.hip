@@ -3093,9 +3093,9 @@ __device__ __forceinline__ uint64_t entry_slot(const RebinArgs &A, uint64_t m) {
 // ranks its movers by new slot, so that its writes form runs. A cell of up
 // to kStageSlots old slots is read whole, in slot order, into registers
 // (issued first, so that the loads overlap the ranking) and then LDS, and
-// written from there in output order; level rows (4 to 32 bytes each) are
-// copied row by row in that order. Larger cells copy each particle
-// directly. The old count is read before the new one is written (only this
+// written from there in output order; its level rows (4 to 32 bytes each)
+// follow as one run of dwords, read in order and written dword by dword in
+// output order. Larger cells copy each particle directly. The old count is read before the new one is written (only this
 // workgroup touches cnt[j]). Workgroups go to the eight XCDs in turn, so
 // the grid (a multiple of 8) gives each XCD one contiguous range of cells:
 // movers go to neighbouring cells, whose lines are then in the same L2.

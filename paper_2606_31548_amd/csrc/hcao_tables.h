@@ -259,7 +259,9 @@ struct InflowArgs {
 // stayers, then movers from higher slots. Only the movers are sorted: the
 // list pass writes them in slot order (position mbase[c] + rank), a stable
 // radix sort orders them by new cell and packed[k] is the start of k's run.
-// The place pass fills each cell's new slots in order.
+// The place pass then writes every particle of each old cell to its new
+// slot.
+//
 // Where the re-bin puts new cell k's particles: a list entry at sorted
 // position pos (its run in the sorted keys starts at lo) goes to slot
 // first + pos, plus ns (the cell's stayers, which fill the gap) when pos >=
@@ -277,7 +279,7 @@ struct RebinArgs {
   uint64_t tot;
   const uint64_t *off;
   const uint32_t *cap;
-  const uint32_t *key, *list, *n_stay, *n_move;  // from the move pass
+  const uint32_t *key, *list, *n_stay, *n_move;  // from the move pass (key: movers' new cells, beside list)
   const uint64_t *mbase;                         // exclusive scan of n_move
   uint32_t *mkey, *mslot;                        // movers in slot order: new cell, old slot
   const uint32_t *skey, *sidx;                   // sorted movers: new cell, position in the list

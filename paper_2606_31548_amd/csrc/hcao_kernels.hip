@@ -2343,19 +2343,22 @@ __global__ __launch_bounds__(256) void k_moments(MomentArgs A) {
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
+constexpr uint32_t kSortMaxBits = 10;  // digit width of a pass: up to 10 bits (1024 bins)
+constexpr uint32_t kSortMaxBins = 1u << kSortMaxBits;
 
 __global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint32_t *keys, uint64_t n, uint32_t shift,
-                                                          uint32_t *hist, uint32_t n_tiles) {
-  __shared__ uint32_t s_h[256];
-  s_h[threadIdx.x] = 0;
+                                                          uint32_t bits, uint32_t *hist, uint32_t n_tiles) {
+  __shared__ uint32_t s_h[kSortMaxBins];
+  const uint32_t bins = 1u << bits, mask = bins - 1u;
+  for (uint32_t b = threadIdx.x; b < bins; b += kSortBlock) s_h[b] = 0;
   __syncthreads();
   const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
   for (int it = 0; it < kSortItems; ++it) {
     const uint64_t i = t0 + (uint64_t)it * kSortBlock + threadIdx.x;
-    if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 0xffu], 1u);
+    if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & mask], 1u);
   }
   __syncthreads();
-  hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = s_h[threadIdx.x];
+  for (uint32_t b = threadIdx.x; b < bins; b += kSortBlock) hist[(uint64_t)b * n_tiles + blockIdx.x] = s_h[b];
 }
 
 // Multi-block exclusive scan of u32 into u64: each 1024-thread block scans
@@ -2418,13 +2421,14 @@ __global__ __launch_bounds__(256) void k_scan_add(uint64_t *out, uint64_t n, con
 
 __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *keys_in, const uint32_t *idx_in,
                                                              uint32_t *keys_out, uint32_t *idx_out, uint64_t n,
-                                                             uint32_t shift, const uint64_t *offs,
+                                                             uint32_t shift, uint32_t bits, const uint64_t *offs,
                                                              uint32_t n_tiles) {
   constexpr int kWaves = kSortBlock / 64;
-  __shared__ uint32_t s_run[256];
-  __shared__ uint32_t s_wave[kWaves][256];
+  __shared__ uint32_t s_run[kSortMaxBins];
+  __shared__ uint32_t s_wave[kWaves][kSortMaxBins];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-  s_run[tid] = 0;
+  const uint32_t bins = 1u << bits, mask = bins - 1u;
+  for (uint32_t b = tid; b < bins; b += kSortBlock) s_run[b] = 0;
   __syncthreads();
   const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
   const unsigned long long lt = lane ? ((1ull << lane) - 1ull) : 0ull;
@@ -2439,17 +2443,20 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *key
   }
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
-    for (int w = 0; w < kWaves; ++w) s_wave[w][tid] = 0;
+    for (int w = 0; w < kWaves; ++w)
+      for (uint32_t b = tid; b < bins; b += kSortBlock) s_wave[w][b] = 0;
     __syncthreads();
     const uint64_t i = t0 + (uint64_t)it * kSortBlock + tid;
     const bool valid = i < n;
     const uint32_t key = kr[it];
-    const uint32_t d = (key >> shift) & 0xffu;
+    const uint32_t d = (key >> shift) & mask;
     unsigned long long same = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const unsigned long long bb = __ballot(((d >> bit) & 1u) != 0u);
-      same &= ((d >> bit) & 1u) ? bb : ~bb;
+    for (uint32_t bit = 0; bit < kSortMaxBits; ++bit) {
+      if (bit < bits) {  // the same on every lane
+        const unsigned long long bb = __ballot(((d >> bit) & 1u) != 0u);
+        same &= ((d >> bit) & 1u) ? bb : ~bb;
+      }
     }
     const uint32_t rank = (uint32_t)__popcll(same & lt);
     if (valid && rank == 0) s_wave[wave][d] = (uint32_t)__popcll(same);
@@ -2462,9 +2469,11 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *key
       idx_out[pos] = ir[it];
     }
     __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < kWaves; ++w) add += s_wave[w][tid];
-    s_run[tid] += add;
+    for (uint32_t b = tid; b < bins; b += kSortBlock) {
+      uint32_t add = 0;
+      for (int w = 0; w < kWaves; ++w) add += s_wave[w][b];
+      s_run[b] += add;
+    }
     __syncthreads();
   }
 }
@@ -3392,9 +3401,12 @@ hipError_t launch_load_check(const Tables *tab, const uint32_t *cell, const uint
   return hipGetLastError();
 }
 
-// Stable sort of (key, index) by key; buffers of n entries each, hist of
-// 256 * tiles u32 and offs of 256 * tiles u64. Result in keys/idx (ping-pong
-// handled here; returns which buffer holds the result).
+// Stable sort of (key, index) by the low key_bits bits of the key; buffers
+// of n entries each, hist and offs of sort_hist_entries(n) entries (u32,
+// u64). The passes take digits of equal width up to 10 bits: one pass up to
+// 10 bits, two up to 20 (e.g. 9 + 9 for 18), three up to 30. Result in
+// keys/idx or the tmp buffers (ping-pong handled here; returns which buffer
+// holds the result).
 hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32_t *idx_tmp, uint32_t *hist,
                        uint64_t *offs, uint64_t *scan_tmp, uint64_t n, uint32_t key_bits, hipStream_t s,
                        bool &result_in_tmp) {
@@ -3403,12 +3415,15 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
   const uint32_t tiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
   hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, idx, n);
   uint32_t *kin = keys, *iin = idx, *kout = keys_tmp, *iout = idx_tmp;
-  for (uint32_t shift = 0; shift < key_bits; shift += 8) {
-    hipLaunchKernelGGL(k_sort_hist, dim3(tiles), dim3(kSortBlock), 0, s, kin, n, shift, hist, tiles);
-    const hipError_t e = launch_scan_u32(hist, offs, (uint64_t)256 * tiles, scan_tmp, s);
+  if (key_bits > 32) return hipErrorInvalidValue;
+  const uint32_t passes = (key_bits + kSortMaxBits - 1) / kSortMaxBits;
+  const uint32_t bits = passes ? (key_bits + passes - 1) / passes : 0;
+  for (uint32_t shift = 0; shift < key_bits; shift += bits) {
+    hipLaunchKernelGGL(k_sort_hist, dim3(tiles), dim3(kSortBlock), 0, s, kin, n, shift, bits, hist, tiles);
+    const hipError_t e = launch_scan_u32(hist, offs, (uint64_t)(1u << bits) * tiles, scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_scatter, dim3(tiles), dim3(kSortBlock), 0, s, kin, iin, kout, iout, n, shift, offs,
-                       tiles);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(tiles), dim3(kSortBlock), 0, s, kin, iin, kout, iout, n, shift, bits,
+                       offs, tiles);
     uint32_t *tk = kin, *ti = iin;
     kin = kout;
     iin = iout;
@@ -3420,6 +3435,7 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
 }
 
 uint64_t sort_tiles(uint64_t n) { return (n + kSortTile - 1) / kSortTile; }
+uint64_t sort_hist_entries(uint64_t n) { return (uint64_t)kSortMaxBins * sort_tiles(n); }
 
 hipError_t launch_move(const MoveArgs &a, hipStream_t s) {
   if (a.n_cells == 0) return hipSuccess;

@@ -63,6 +63,7 @@ hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32
                        uint64_t *offs, uint64_t *scan_tmp, uint64_t n, uint32_t key_bits, hipStream_t s,
                        bool &result_in_tmp);
 uint64_t sort_tiles(uint64_t n);
+uint64_t sort_hist_entries(uint64_t n);
 hipError_t launch_place(const Tables *tab, const uint32_t *sorted_cell, const uint32_t *sorted_idx,
                         const uint64_t *packed_start, const uint64_t *off, const uint8_t *sp, const double *vel,
                         const uint16_t *lvl, const double *rot, const double *pos, const State &st, uint64_t n,
@@ -521,12 +522,12 @@ hipError_t grow_list(hcao_ctx *c, uint64_t n) {
     if ((e = c->mv_sidx.alloc(n)) != hipSuccess) return e;
     if ((e = c->mv_sidx_tmp.alloc(n)) != hipSuccess) return e;
     if ((e = c->mv_ktmp.alloc(n)) != hipSuccess) return e;
-    if ((e = c->mv_hist.alloc(256 * sort_tiles(n))) != hipSuccess) return e;
-    if ((e = c->mv_offs.alloc(256 * sort_tiles(n))) != hipSuccess) return e;
+    if ((e = c->mv_hist.alloc(sort_hist_entries(n))) != hipSuccess) return e;
+    if ((e = c->mv_offs.alloc(sort_hist_entries(n))) != hipSuccess) return e;
     c->list_cap = n;
   }
   const uint64_t faces = (uint64_t)c->face_base[6] * c->species.size();
-  const size_t need = std::max({scan_tmp_entries(256 * sort_tiles(c->list_cap)),
+  const size_t need = std::max({scan_tmp_entries(sort_hist_entries(c->list_cap)),
                                 scan_tmp_entries((uint64_t)c->cfg.n_cells + 1), scan_tmp_entries(faces + 1)});
   if (c->mv_stmp.n < need && (e = c->mv_stmp.alloc(need)) != hipSuccess) return e;
   return hipSuccess;
@@ -1270,17 +1271,15 @@ hcao_status hcao_load_particles(hcao_ctx *c, uint64_t n, const uint32_t *cell, c
   // stable counting sort by cell, then placement into the padded layout
   uint32_t key_bits = 0;
   while (key_bits < 32 && ((uint64_t)1 << key_bits) < nc) ++key_bits;
-  key_bits = ((key_bits + 7) / 8) * 8;
-  const uint64_t tiles = sort_tiles(n);
   HIP_TRY(c, keys_tmp.alloc(n));
   HIP_TRY(c, idx.alloc(n));
   HIP_TRY(c, idx_tmp.alloc(n));
-  HIP_TRY(c, hist.alloc(256 * tiles));
-  HIP_TRY(c, offs.alloc(256 * tiles));
+  HIP_TRY(c, hist.alloc(sort_hist_entries(n)));
+  HIP_TRY(c, offs.alloc(sort_hist_entries(n)));
   HIP_TRY(c, packed.alloc(nc));
   bool in_tmp = false;
   DevBuf<uint64_t> stmp;
-  HIP_TRY(c, stmp.alloc(std::max(scan_tmp_entries(256 * tiles), scan_tmp_entries(nc))));
+  HIP_TRY(c, stmp.alloc(std::max(scan_tmp_entries(sort_hist_entries(n)), scan_tmp_entries(nc))));
   HIP_TRY(c, launch_sort(d_cell.p, idx.p, keys_tmp.p, idx_tmp.p, hist.p, offs.p, stmp.p, n, key_bits, c->stream,
                          in_tmp));
   HIP_TRY(c, launch_scan_u32(c->cnt.p, packed.p, nc, stmp.p, c->stream));
@@ -1466,7 +1465,6 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   const uint64_t top_key = c->open_faces ? nc : nc - 1;
   uint32_t key_bits = 0;
   while (key_bits < 32 && ((uint64_t)1 << key_bits) <= top_key) ++key_bits;
-  key_bits = ((key_bits + 7) / 8) * 8;
   bool in_tmp = false;
   HIP_TRY(c, launch_sort(c->mv_mkey.p, c->mv_sidx.p, c->mv_ktmp.p, c->mv_sidx_tmp.p, c->mv_hist.p, c->mv_offs.p,
                          c->mv_stmp.p, movers + n_ins, key_bits, s, in_tmp));

@@ -2343,7 +2343,7 @@ __global__ __launch_bounds__(256) void k_moments(MomentArgs A) {
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortBlock * kSortItems;
-constexpr uint32_t kSortMaxBits = 10;  // digit width of a pass: up to 10 bits (1024 bins)
+constexpr uint32_t kSortMaxBits = 9;  // digit width of a pass: up to 9 bits (512 bins)
 constexpr uint32_t kSortMaxBins = 1u << kSortMaxBits;
 
 __global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint32_t *keys, uint64_t n, uint32_t shift,
@@ -3403,8 +3403,9 @@ hipError_t launch_load_check(const Tables *tab, const uint32_t *cell, const uint
 
 // Stable sort of (key, index) by the low key_bits bits of the key; buffers
 // of n entries each, hist and offs of sort_hist_entries(n) entries (u32,
-// u64). The passes take digits of equal width up to 10 bits: one pass up to
-// 10 bits, two up to 20 (e.g. 9 + 9 for 18), three up to 30. Result in
+// u64). The passes take digits of equal width up to 9 bits: one pass up to
+// 9 bits, two up to 18, three up to 27 (19 bits: three of 7; two of 10 cost
+// more in their larger histogram scans). Result in
 // keys/idx or the tmp buffers (ping-pong handled here; returns which buffer
 // holds the result).
 hipError_t launch_sort(uint32_t *keys, uint32_t *idx, uint32_t *keys_tmp, uint32_t *idx_tmp, uint32_t *hist,

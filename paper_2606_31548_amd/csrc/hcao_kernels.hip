@@ -2823,11 +2823,9 @@ __global__ __launch_bounds__(256) void k_move(MoveArgs A) {
       double vx = v.x, vy = v.y, vz = v.z;
       double x = A.st.px[g], y = A.st.py[g], z = A.st.pz[g];
       bool flip = false;
+      // the moved state is not stored: the place pass moves the particle
+      // again as it copies it (the same arithmetic, so the same bits)
       if (!move_particle(x, y, z, vx, vy, vz, A.dt, A.len, A.periodic, A.open, flip)) {
-        A.st.px[g] = x;
-        A.st.py[g] = y;
-        A.st.pz[g] = z;
-        if (flip) store_vel(A.st, g, vx, vy, vz);  // only a reflection changes the velocity
         key = axis_index(x, A.len[0], A.nx) +
               A.nx * (axis_index(y, A.len[1], A.ny) + A.ny * axis_index(z, A.len[2], A.nz));
         mover = key != c;
@@ -3093,8 +3091,27 @@ __device__ __forceinline__ uint64_t entry_slot(const RebinArgs &A, uint64_t m) {
   return v == kNoSlot32 ? kNoSlot : (uint64_t)v;
 }
 
+// one particle to its new slot with the step's move applied (the same
+// arithmetic as the move pass)
+__device__ __forceinline__ void copy_moved(const RebinArgs &A, uint64_t from, uint64_t to) {
+  const State &s = A.src, &d = A.dst;
+  const Vec3 v = load_vel(s, from);
+  double vx = v.x, vy = v.y, vz = v.z;
+  double x = s.px[from], y = s.py[from], z = s.pz[from];
+  bool flip = false;
+  move_particle(x, y, z, vx, vy, vz, A.dt, A.len, A.periodic, A.open, flip);
+  store_vel(d, to, vx, vy, vz);
+  d.sp[to] = s.sp[from];
+  copy_levels(s, from, d, to);
+  if (s.rot) d.rot[to] = s.rot[from];
+  d.px[to] = x;
+  d.py[to] = y;
+  d.pz[to] = z;
+}
+
 // The place pass, pushed from the old cells: one workgroup per old cell j
-// writes each of its particles to its slot in the new cell. The order in
+// writes each of its particles, moved over the step, to its slot in the
+// new cell. The order in
 // every new cell is that of a stable sort of all particles by new cell:
 // movers from slots below off[k], k's stayers, the other movers, the
 // admissions (k_rebin_admit). The movers from j into one new cell hold
@@ -3143,7 +3160,7 @@ __global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
         to = entry_slot(A, m);
         if (to == kNoSlot) continue;
       }
-      copy_particle(S, D, HCAO_IDX(from, S.n_slots, A.err), HCAO_IDX(to, D.n_slots, A.err), A.mm);
+      copy_moved(A, HCAO_IDX(from, S.n_slots, A.err), HCAO_IDX(to, D.n_slots, A.err));
     }
   } else {
     const bool f32 = S.fx != nullptr, rot = S.rot != nullptr;
@@ -3168,6 +3185,41 @@ __global__ __launch_bounds__(256) void k_rebin_push(RebinArgs A) {
         }
         rr[q] = rot ? reinterpret_cast<const uint64_t *>(S.rot)[g] : 0u;
         rs[q] = S.sp[g];
+      }
+    }
+    // the step's move (positions, and velocities a specular face reversed);
+    // a particle that left through an open face is in no list
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      if (tid + 256u * q < n_old) {
+        double x = __longlong_as_double((long long)rp[q][0]), y = __longlong_as_double((long long)rp[q][1]),
+               z = __longlong_as_double((long long)rp[q][2]);
+        double vx, vy, vz;
+        if (f32) {
+          vx = (double)__uint_as_float((uint32_t)rv[q][0]);
+          vy = (double)__uint_as_float((uint32_t)rv[q][1]);
+          vz = (double)__uint_as_float((uint32_t)rv[q][2]);
+        } else {
+          vx = __longlong_as_double((long long)rv[q][0]);
+          vy = __longlong_as_double((long long)rv[q][1]);
+          vz = __longlong_as_double((long long)rv[q][2]);
+        }
+        bool flip = false;
+        move_particle(x, y, z, vx, vy, vz, A.dt, A.len, A.periodic, A.open, flip);
+        rp[q][0] = (uint64_t)__double_as_longlong(x);
+        rp[q][1] = (uint64_t)__double_as_longlong(y);
+        rp[q][2] = (uint64_t)__double_as_longlong(z);
+        if (flip) {
+          if (f32) {
+            rv[q][0] = __float_as_uint((float)vx);
+            rv[q][1] = __float_as_uint((float)vy);
+            rv[q][2] = __float_as_uint((float)vz);
+          } else {
+            rv[q][0] = (uint64_t)__double_as_longlong(vx);
+            rv[q][1] = (uint64_t)__double_as_longlong(vy);
+            rv[q][2] = (uint64_t)__double_as_longlong(vz);
+          }
+        }
       }
     }
     // the cell's level rows as one run of n_old * L dwords, loaded in order

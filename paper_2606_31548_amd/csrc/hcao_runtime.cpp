@@ -1452,6 +1452,10 @@ hcao_status move_rebin(hcao_ctx *c, double dt, uint32_t step, hipStream_t s) {
   r.m_real = movers;
   r.n_cells = nc;
   r.mm = mm;
+  r.dt = dt;
+  for (int k = 0; k < 3; ++k) r.len[k] = c->len[k];
+  r.periodic = c->periodic;
+  r.open = c->open_faces;
   HIP_TRY(c, launch_list_movers(r, s));
   if (n_ins) {
     in.ins = ins_state(c);

@@ -208,8 +208,10 @@ struct StepArgs {
   double dt;
 };
 
-// Spatial mode, move pass: block c moves the particles of cell c over dt;
-// its stayers (new cell = c) and its movers are listed by cell-relative slot
+// Spatial mode, move pass: block c moves the particles of cell c over dt
+// to find their new cells (the state is left as it is: the place pass
+// applies the same move as it copies each particle to its new slot); its
+// stayers (new cell = c) and its movers are listed by cell-relative slot
 // in list[], stayers in slot order from the cell's first slot up, movers in
 // slot order from its last slot down, each mover's new cell in key[] at the
 // same place as its list entry; n_stay[c] and n_move[c] count them. A particle that crosses an open
@@ -290,6 +292,8 @@ struct RebinArgs {
   uint64_t m;                                    // number of list entries (movers, then admissions)
   uint64_t m_real;                               // movers out of real slots (the admissions follow)
   uint32_t n_cells, mm;
+  double dt, len[3];                             // the step's move, applied by the place pass
+  uint32_t periodic, open;
 };
 
 // Forward recombination probability summed over every level combination of

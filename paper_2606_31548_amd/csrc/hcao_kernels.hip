@@ -2980,13 +2980,14 @@ __global__ __launch_bounds__(256) void k_inflow_make(InflowArgs A) {
 }
 
 // movers of cell c into the list, in slot order
+// (one wave per cell, four cells per workgroup)
 __global__ __launch_bounds__(256) void k_list_movers(RebinArgs A) {
-  const uint32_t c = blockIdx.x;
+  const uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (c >= A.n_cells) return;
   const uint32_t nm = A.n_move[c];
-  if (nm == 0) return;
   const uint64_t base = A.off[c], mb = A.mbase[c];
   const uint64_t top = base + A.cap[c] - 1u;
-  for (uint32_t r = threadIdx.x; r < nm; r += blockDim.x) {
+  for (uint32_t r = threadIdx.x & 63u; r < nm; r += 64u) {
     A.mkey[mb + r] = A.key[top - r];
     A.mslot[mb + r] = (uint32_t)(base + A.list[top - r]);
   }
@@ -3502,7 +3503,7 @@ hipError_t launch_list_movers(const RebinArgs &a, hipStream_t s) {
   if (a.n_cells == 0 || a.m == 0) return hipSuccess;
   if (!a.off || !a.cap || !a.key || !a.list || !a.n_move || !a.mbase || !a.mkey || !a.mslot)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_list_movers, dim3(a.n_cells), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_list_movers, dim3((a.n_cells + 3u) / 4u), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
